@@ -1,0 +1,165 @@
+/*
+ * utd.h -- C ABI of the smooth-surface UTD field library (MI355X / gfx950).
+ *
+ * The library evaluates the receiver field of a point source in a scene of
+ * triangles (occluders only) and convex PEC bodies (spheres and vertical
+ * finite cylinders), with the smooth-surface diffraction of the paper
+ * (Sec. II-B, Eqs. (1)-(4); Sec. III-B for which creeping paths are summed):
+ *
+ *   E(R) = U_LOS E^i(R) + sum_bodies [ U^r E^r(R) + sum_paths U^d E^d(R) ]
+ *
+ * E^i is the ray field of a Hertzian dipole, E^r the reflected field of
+ * Eq. (3) with the UTD (Fock) reflection coefficients, E^d the creeping-wave
+ * field of Eq. (4) with the UTD transfer coefficients; the U are the
+ * Heaviside visibilities of Eqs. (1)-(2), decided against the triangle BVH
+ * and against the other bodies.  Time convention e^{+j w t}; lengths in
+ * metres, frequencies in Hz, c = 299792458 m/s.
+ *
+ * Conventions for every entry point:
+ *   - Pointers documented "device" must point to GPU memory readable (and,
+ *     for outputs, writable) by the current HIP device.  "host" pointers are
+ *     read during the call only.  The caller owns every buffer it passes; the
+ *     library never frees them.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream)
+ *     and the call returns without waiting for it.  The library's own
+ *     temporary device memory is allocated and released in stream order.
+ *   - A non-OK status means nothing was enqueued; utd_last_error() gives a
+ *     message for the calling thread.  No exception crosses the ABI.
+ *   - Conditions only visible on the device (source inside a body, receiver
+ *     inside a body, receiver on a sphere's axial caustic) are reported per
+ *     receiver through `rx_flags` (UTD_FLAG_*), never as a status.
+ */
+#ifndef UTD_H
+#define UTD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct utd_scene utd_scene;
+
+typedef enum {
+    UTD_OK = 0,
+    UTD_E_ARG = -1,          /* invalid argument (NULL, negative size, bad option) */
+    UTD_E_DEVICE = -2,       /* a HIP runtime call failed */
+    UTD_E_OOM = -3,          /* device or host allocation failed */
+    UTD_E_UNSUPPORTED = -5   /* valid but not supported by this build */
+} utd_status;
+
+/* Per-receiver flags written to rx_flags (bit set = condition holds). */
+#define UTD_FLAG_INSIDE    1u  /* receiver inside a body: E = 0                  */
+#define UTD_FLAG_CAUSTIC   2u  /* a sphere creeping path dropped at the axial caustic */
+#define UTD_FLAG_LOS       4u  /* direct path visible (U_LOS = 1)               */
+#define UTD_FLAG_TX_INSIDE 8u  /* source inside a body: E = 0 for every receiver */
+
+typedef struct {
+    int precision;          /* 0: FP32 field evaluation with FP64 path lengths and
+                               phase; 1: FP64 throughout.  Default 0.          */
+    int l_enc;              /* extra encirclements per side, 0..2 (Sec. III-B's
+                               generalised Fermat paths).  Default 0.          */
+    int bodies_occlude;     /* 1: segments are also tested against the other
+                               bodies.  Default 1.                             */
+    int lit_branch;         /* 1: include the direct and reflected fields
+                               (Eq. (1)); 0: creeping fields only.  Default 1. */
+    double caustic_guard;   /* sphere creeping paths whose receiver lies closer
+                               than this to the source axis are dropped and
+                               flagged (m).  Default 1e-6.                     */
+} utd_options;
+
+/* Bodies, device arrays of float32, row-major:
+ *   sph[n_sph][4] = (cx, cy, cz, a)            sphere centre and radius
+ *   cyl[n_cyl][5] = (cx, cy, z0, h, a)         vertical cylinder: axis through
+ *                                              (cx, cy), lateral surface z0..z0+h,
+ *                                              radius a; solid for occlusion  */
+typedef struct {
+    const float *sph;
+    int64_t n_sph;
+    const float *cyl;
+    int64_t n_cyl;
+} utd_bodies;
+
+/* Point source: position (m), dipole direction (unnormalised is allowed; the
+ * field scales with it) and amplitude A: E^i(P) = A (p - (p.s)s) e^{-jks}/s. */
+typedef struct {
+    float pos[3];
+    float dipole[3];
+    double amplitude;
+} utd_source;
+
+/* Fills the defaults listed above. */
+void utd_default_options(utd_options *opt);
+
+/* Builds the occluder scene: copies n_tri triangles (host float32
+ * [n_tri][3][3], vertex-major) to the device and builds a BVH over them
+ * (binned SAH, host C++).  n_tri may be 0.  *out receives the handle.
+ * Errors: UTD_E_ARG (out NULL, n_tri < 0, tri NULL with n_tri > 0),
+ * UTD_E_OOM, UTD_E_DEVICE. */
+utd_status utd_scene_create(const float *tri_xyz, int64_t n_tri, utd_scene **out);
+
+/* Frees the scene's device memory (waits for the device first).  NULL is a no-op. */
+void utd_scene_destroy(utd_scene *scene);
+
+/* Number of triangles and BVH nodes of a scene (for reporting). */
+int64_t utd_scene_triangles(const utd_scene *scene);
+int64_t utd_scene_nodes(const utd_scene *scene);
+
+/* Forward field (Eqs. (1)-(4)).
+ *   rx       device float32 [n_rx][3]  receiver positions
+ *   freqs_hz device float64 [n_f]      frequencies (> 0)
+ *   E_out    device, [n_f][3][n_rx] complex, interleaved (re, im):
+ *            float32 pairs when opt->precision == 0, float64 pairs when 1.
+ *            Fully overwritten.
+ *   rx_flags device uint8 [n_rx] or NULL.
+ * n_rx == 0 or n_f == 0 enqueues nothing and returns UTD_OK.
+ * Errors: UTD_E_ARG for NULL pointers with non-zero sizes, n_rx < 0, n_f < 0,
+ * l_enc outside 0..2, precision outside {0, 1}; UTD_E_DEVICE on launch failure. */
+utd_status utd_smooth_field(const utd_scene *scene, const utd_bodies *bodies,
+                            const utd_source *tx, const float *rx, int64_t n_rx,
+                            const double *freqs_hz, int n_f, const utd_options *opt,
+                            void *E_out, uint8_t *rx_flags, void *stream);
+
+/* Adjoint of utd_smooth_field for L(E) with dL/dE given as grad_E (same
+ * layout and precision as E_out): writes
+ *   d_cyl[n_cyl][3] = dL/d(cx, cy, a) per cylinder,
+ *   d_sph[n_sph][4] = dL/d(cx, cy, cz, a) per sphere,
+ *   d_tx[3]         = dL/d(source position),
+ * all device float32, fully overwritten, with dL/dtheta = Re sum conj(grad_E) dE/dtheta
+ * (the convention of PyTorch's complex autograd).  Visibility decisions and
+ * path classification are those of the forward evaluation at the same
+ * inputs and are held fixed (the field is piecewise smooth).  The
+ * reduction over receivers and frequencies is deterministic.
+ * Errors as for utd_smooth_field; d_* may be NULL when the matching count is 0. */
+utd_status utd_smooth_field_backward(const utd_scene *scene, const utd_bodies *bodies,
+                                     const utd_source *tx, const float *rx, int64_t n_rx,
+                                     const double *freqs_hz, int n_f, const utd_options *opt,
+                                     const void *grad_E, float *d_cyl, float *d_sph, float *d_tx,
+                                     void *stream);
+
+/* Many frames in one launch: frame f has cylinders cyl[body_off[f] .. body_off[f+1])
+ * and receivers rx[rx_off[f] .. rx_off[f+1]); all frames share the scene, the
+ * source and the frequencies.  body_off, rx_off: device int64 [n_frames+1],
+ * non-decreasing, starting at 0.  E_out: device complex; each frame keeps the
+ * layout of utd_smooth_field and frames are concatenated: frame f occupies
+ * the [n_f][3][n_rx_f] block starting at complex element 3 * n_f * rx_off[f].
+ * rx_flags: device uint8 [rx_off[n_frames]] or NULL.
+ * max_rx_frame and total_rx (host values) bound the frame sizes and size the
+ * work queue; they must be >= the true values.
+ * Errors as for utd_smooth_field; UTD_E_ARG if n_frames < 0. */
+utd_status utd_smooth_field_batched(const utd_scene *scene, int64_t n_frames,
+                                    const int64_t *body_off, const float *cyl,
+                                    const int64_t *rx_off, const float *rx,
+                                    int64_t max_rx_frame, int64_t total_rx,
+                                    const utd_source *tx, const double *freqs_hz, int n_f,
+                                    const utd_options *opt, void *E_out, uint8_t *rx_flags,
+                                    void *stream);
+
+/* Message for the last non-OK status returned on this thread ("" if none). */
+const char *utd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UTD_H */

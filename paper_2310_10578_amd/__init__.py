@@ -1,0 +1,197 @@
+"""Python binding of libutd.so, the MI355X smooth-surface UTD field library.
+
+Argument marshalling only: every step of the field evaluation runs in the
+library's HIP kernels.  Device buffers are torch tensors on the GPU; the
+functions here check shapes and dtypes, allocate outputs with torch and pass
+raw pointers and the current HIP stream through the C ABI declared in
+``include/utd.h``.  There is no CPU fallback: without the built library or a
+GPU every entry point raises.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libutd.so")
+
+UTD_OK = 0
+FLAG_INSIDE, FLAG_CAUSTIC, FLAG_LOS, FLAG_TX_INSIDE = 1, 2, 4, 8
+
+EXPORTS = ["utd_default_options", "utd_scene_create", "utd_scene_destroy", "utd_scene_triangles",
+           "utd_scene_nodes", "utd_smooth_field", "utd_smooth_field_backward", "utd_smooth_field_batched",
+           "utd_last_error"]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("l_enc", ctypes.c_int), ("bodies_occlude", ctypes.c_int),
+                ("lit_branch", ctypes.c_int), ("caustic_guard", ctypes.c_double)]
+
+
+class Bodies(ctypes.Structure):
+    _fields_ = [("sph", ctypes.c_void_p), ("n_sph", ctypes.c_int64),
+                ("cyl", ctypes.c_void_p), ("n_cyl", ctypes.c_int64)]
+
+
+class Source(ctypes.Structure):
+    _fields_ = [("pos", ctypes.c_float * 3), ("dipole", ctypes.c_float * 3), ("amplitude", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libutd.so and declare its signatures (works without a GPU)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libutd.so is not built (%s); run __graft_entry__.build()" % path)
+    lib = ctypes.CDLL(path)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    lib.utd_default_options.argtypes = [ctypes.POINTER(Options)]
+    lib.utd_default_options.restype = None
+    lib.utd_scene_create.argtypes = [vp, i64, ctypes.POINTER(vp)]
+    lib.utd_scene_create.restype = i32
+    lib.utd_scene_destroy.argtypes = [vp]
+    lib.utd_scene_destroy.restype = None
+    lib.utd_scene_triangles.argtypes = [vp]
+    lib.utd_scene_triangles.restype = i64
+    lib.utd_scene_nodes.argtypes = [vp]
+    lib.utd_scene_nodes.restype = i64
+    lib.utd_smooth_field.argtypes = [vp, ctypes.POINTER(Bodies), ctypes.POINTER(Source), vp, i64, vp, i32,
+                                     ctypes.POINTER(Options), vp, vp, vp]
+    lib.utd_smooth_field.restype = i32
+    lib.utd_smooth_field_backward.argtypes = [vp, ctypes.POINTER(Bodies), ctypes.POINTER(Source), vp, i64, vp, i32,
+                                              ctypes.POINTER(Options), vp, vp, vp, vp, vp]
+    lib.utd_smooth_field_backward.restype = i32
+    lib.utd_smooth_field_batched.argtypes = [vp, i64, vp, vp, vp, vp, i64, i64, ctypes.POINTER(Source), vp, i32,
+                                             ctypes.POINTER(Options), vp, vp, vp]
+    lib.utd_smooth_field_batched.restype = i32
+    lib.utd_last_error.argtypes = []
+    lib.utd_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+class UTDError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("utd status %d: %s" % (status, msg))
+        self.status = status
+
+
+def _check(status):
+    if status != UTD_OK:
+        raise UTDError(status, load_library().utd_last_error().decode())
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("the UTD library needs a ROCm GPU; none is visible")
+    return torch
+
+
+def _dev(t, dtype, shape_tail, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a GPU torch tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if shape_tail is not None and tuple(t.shape[1:]) != tuple(shape_tail):
+        raise ValueError("%s must have shape [n, %s]" % (name, ", ".join(map(str, shape_tail))))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return t
+
+
+def make_options(precision=0, l_enc=0, bodies_occlude=True, lit_branch=True, caustic_guard=1e-6):
+    o = Options()
+    load_library().utd_default_options(ctypes.byref(o))
+    o.precision, o.l_enc = int(precision), int(l_enc)
+    o.bodies_occlude, o.lit_branch = int(bool(bodies_occlude)), int(bool(lit_branch))
+    o.caustic_guard = float(caustic_guard)
+    return o
+
+
+def make_source(pos, dipole=(0.0, 0.0, 1.0), amplitude=1.0):
+    s = Source()
+    for a in range(3):
+        s.pos[a] = float(pos[a])
+        s.dipole[a] = float(dipole[a])
+    s.amplitude = float(amplitude)
+    return s
+
+
+class Scene:
+    """Occluder triangles (host float32 [n, 3, 3]) and their device BVH."""
+
+    def __init__(self, tri=None):
+        import numpy as np
+        lib = load_library()
+        self._h = ctypes.c_void_p()
+        if tri is None:
+            arr = np.zeros((0, 3, 3), np.float32)
+        else:
+            arr = np.ascontiguousarray(tri, dtype=np.float32).reshape(-1, 3, 3)
+        self._keep = arr
+        _check(lib.utd_scene_create(arr.ctypes.data if arr.size else None, arr.shape[0], ctypes.byref(self._h)))
+        self.n_tri = int(lib.utd_scene_triangles(self._h))
+        self.n_nodes = int(lib.utd_scene_nodes(self._h))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            load_library().utd_scene_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _bodies(spheres, cylinders):
+    torch = _torch()
+    b = Bodies()
+    sph = spheres if spheres is not None else torch.zeros((0, 4), dtype=torch.float32, device="cuda")
+    cyl = cylinders if cylinders is not None else torch.zeros((0, 5), dtype=torch.float32, device="cuda")
+    _dev(sph, torch.float32, (4,), "spheres")
+    _dev(cyl, torch.float32, (5,), "cylinders")
+    b.sph, b.n_sph = (sph.data_ptr() if sph.numel() else None), sph.shape[0]
+    b.cyl, b.n_cyl = (cyl.data_ptr() if cyl.numel() else None), cyl.shape[0]
+    return b, (sph, cyl)
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def smooth_field(scene, spheres, cylinders, source, rx, freqs, precision=0, l_enc=0, bodies_occlude=True,
+                 lit_branch=True, caustic_guard=1e-6, out=None, flags=None, stream=None):
+    """E[f, c, n] (complex64 for precision 0, complex128 for 1) and flags[n].
+
+    spheres [ns, 4], cylinders [nc, 5], rx [n, 3]: float32 GPU tensors;
+    freqs [nf]: float64 GPU tensor; source: a ``Source`` (``make_source``).
+    """
+    torch = _torch()
+    lib = load_library()
+    _dev(rx, torch.float32, (3,), "rx")
+    _dev(freqs, torch.float64, None, "freqs")
+    b, keep = _bodies(spheres, cylinders)
+    n, nf = rx.shape[0], freqs.shape[0]
+    cdt = torch.complex64 if precision == 0 else torch.complex128
+    if out is None:
+        out = torch.empty((nf, 3, n), dtype=cdt, device=rx.device)
+    if flags is None:
+        flags = torch.empty((n,), dtype=torch.uint8, device=rx.device)
+    opt = make_options(precision, l_enc, bodies_occlude, lit_branch, caustic_guard)
+    _check(lib.utd_smooth_field(scene.handle if scene is not None else None, ctypes.byref(b), ctypes.byref(source),
+                                rx.data_ptr() if n else None, n, freqs.data_ptr() if nf else None, nf,
+                                ctypes.byref(opt), out.data_ptr() if out.numel() else None,
+                                flags.data_ptr() if n else None, _stream(stream)))
+    return out, flags

@@ -1,0 +1,208 @@
+// Host-side BVH builder for the occluder triangles (binned SAH, two children
+// per node, leaves of at most 4 triangles).  The visibility steps U of
+// Eqs. (1)-(2) are decided by walking this tree on the GPU (utd_bvh.h).
+//
+// Output layout (read by the device traversal):
+//   node  = 4 float4: (lo0.xyz, hi0.x) (hi0.yz, lo1.xy) (lo1.z, hi1.xyz) (c0, n0, c1, n1)
+//           n_i > 0: leaf of n_i triangles starting at c_i; n_i == 0: inner node c_i;
+//           c_i < 0: empty child.
+//   tris  = 3 float4 per triangle (v0, v1, v2), in leaf order.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "utd_internal.h"
+
+namespace utd {
+
+namespace {
+
+struct Box {
+    float lo[3] = {INFINITY, INFINITY, INFINITY};
+    float hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    void grow(const float* p) {
+        for (int a = 0; a < 3; ++a) { lo[a] = std::min(lo[a], p[a]); hi[a] = std::max(hi[a], p[a]); }
+    }
+    void grow(const Box& b) {
+        for (int a = 0; a < 3; ++a) { lo[a] = std::min(lo[a], b.lo[a]); hi[a] = std::max(hi[a], b.hi[a]); }
+    }
+    float area() const {
+        float d[3];
+        for (int a = 0; a < 3; ++a) d[a] = std::max(hi[a] - lo[a], 0.0f);
+        return 2.0f * (d[0] * d[1] + d[1] * d[2] + d[2] * d[0]);
+    }
+};
+
+struct Prim {
+    Box box;
+    float c[3];
+    int64_t idx;
+};
+
+struct Child {
+    Box box;
+    int ref = -1;
+    int count = 0;
+};
+
+struct Node {
+    Child ch[2];
+};
+
+constexpr int kLeaf = 4;
+constexpr int kBins = 16;
+
+Box range_box(const std::vector<Prim>& P, int64_t b, int64_t e) {
+    Box bx;
+    for (int64_t i = b; i < e; ++i) bx.grow(P[i].box);
+    return bx;
+}
+
+// Binned SAH split of P[b, e); returns mid with b < mid < e.
+int64_t split(std::vector<Prim>& P, int64_t b, int64_t e) {
+    Box cb;
+    for (int64_t i = b; i < e; ++i) cb.grow(P[i].c);
+    float best = INFINITY;
+    int best_axis = -1, best_bin = -1;
+    for (int a = 0; a < 3; ++a) {
+        float ext = cb.hi[a] - cb.lo[a];
+        if (!(ext > 0)) continue;
+        Box bb[kBins];
+        int64_t cnt[kBins] = {0};
+        for (int64_t i = b; i < e; ++i) {
+            int k = (int)((P[i].c[a] - cb.lo[a]) / ext * kBins);
+            k = std::min(std::max(k, 0), kBins - 1);
+            bb[k].grow(P[i].box);
+            cnt[k]++;
+        }
+        float right_area[kBins];
+        int64_t right_cnt[kBins];
+        Box acc;
+        int64_t n = 0;
+        for (int k = kBins - 1; k > 0; --k) {
+            acc.grow(bb[k]);
+            n += cnt[k];
+            right_area[k] = acc.area();
+            right_cnt[k] = n;
+        }
+        Box lacc;
+        int64_t ln = 0;
+        for (int k = 0; k < kBins - 1; ++k) {
+            lacc.grow(bb[k]);
+            ln += cnt[k];
+            if (ln == 0 || right_cnt[k + 1] == 0) continue;
+            float cost = lacc.area() * (float)ln + right_area[k + 1] * (float)right_cnt[k + 1];
+            if (cost < best) { best = cost; best_axis = a; best_bin = k; }
+        }
+    }
+    int64_t mid;
+    if (best_axis >= 0) {
+        float ext = cb.hi[best_axis] - cb.lo[best_axis];
+        auto it = std::partition(P.begin() + b, P.begin() + e, [&](const Prim& p) {
+            int k = (int)((p.c[best_axis] - cb.lo[best_axis]) / ext * kBins);
+            k = std::min(std::max(k, 0), kBins - 1);
+            return k <= best_bin;
+        });
+        mid = it - P.begin();
+    } else {
+        mid = (b + e) / 2;
+    }
+    if (mid <= b || mid >= e) {
+        int a = 0;
+        float ext = -1;
+        for (int k = 0; k < 3; ++k)
+            if (cb.hi[k] - cb.lo[k] > ext) { ext = cb.hi[k] - cb.lo[k]; a = k; }
+        mid = (b + e) / 2;
+        std::nth_element(P.begin() + b, P.begin() + mid, P.begin() + e,
+                         [a](const Prim& x, const Prim& y) { return x.c[a] < y.c[a]; });
+    }
+    return mid;
+}
+
+}  // namespace
+
+int build_bvh(const float* tri, int64_t n, int max_depth, HostBvh* out) {
+    *out = HostBvh();
+    if (n <= 0) return 0;
+    std::vector<Prim> P((size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        Prim& p = P[(size_t)i];
+        for (int v = 0; v < 3; ++v) p.box.grow(tri + 9 * i + 3 * v);
+        for (int a = 0; a < 3; ++a) p.c[a] = 0.5f * (p.box.lo[a] + p.box.hi[a]);
+        p.idx = i;
+    }
+    std::vector<Node> nodes(1);
+    struct Task { int node; int64_t b, e; int depth; };
+    std::vector<Task> todo;
+    todo.push_back({0, 0, n, 1});
+    int depth_seen = 1;
+    while (!todo.empty()) {
+        Task t = todo.back();
+        todo.pop_back();
+        int64_t ranges[2][2];
+        if (t.e - t.b <= kLeaf) {
+            ranges[0][0] = t.b; ranges[0][1] = t.e;
+            ranges[1][0] = t.e; ranges[1][1] = t.e;
+        } else {
+            int64_t mid = split(P, t.b, t.e);
+            ranges[0][0] = t.b; ranges[0][1] = mid;
+            ranges[1][0] = mid; ranges[1][1] = t.e;
+        }
+        for (int c = 0; c < 2; ++c) {
+            int64_t b = ranges[c][0], e = ranges[c][1];
+            Child ch;
+            if (e > b) {
+                ch.box = range_box(P, b, e);
+                if (e - b <= kLeaf || t.depth + 1 >= max_depth) {
+                    ch.ref = (int)b;
+                    ch.count = (int)(e - b);
+                } else {
+                    ch.ref = (int)nodes.size();
+                    ch.count = 0;
+                    nodes.emplace_back();
+                    todo.push_back({ch.ref, b, e, t.depth + 1});
+                    depth_seen = std::max(depth_seen, t.depth + 1);
+                }
+            }
+            nodes[(size_t)t.node].ch[c] = ch;
+        }
+    }
+    out->n_nodes = (int64_t)nodes.size();
+    out->depth = depth_seen;
+    out->nodes = (float*)std::malloc(sizeof(float) * 16 * nodes.size());
+    out->tris = (float*)std::malloc(sizeof(float) * 12 * (size_t)n);
+    if (!out->nodes || !out->tris) { free_bvh(out); return -1; }
+    for (size_t k = 0; k < nodes.size(); ++k) {
+        float* q = out->nodes + 16 * k;
+        const Child& a = nodes[k].ch[0];
+        const Child& b = nodes[k].ch[1];
+        q[0] = a.box.lo[0]; q[1] = a.box.lo[1]; q[2] = a.box.lo[2]; q[3] = a.box.hi[0];
+        q[4] = a.box.hi[1]; q[5] = a.box.hi[2]; q[6] = b.box.lo[0]; q[7] = b.box.lo[1];
+        q[8] = b.box.lo[2]; q[9] = b.box.hi[0]; q[10] = b.box.hi[1]; q[11] = b.box.hi[2];
+        int refs[4] = {a.ref, a.count, b.ref, b.count};
+        std::memcpy(q + 12, refs, sizeof refs);
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        const float* s = tri + 9 * P[(size_t)i].idx;
+        float* d = out->tris + 12 * i;
+        for (int v = 0; v < 3; ++v) {
+            d[4 * v + 0] = s[3 * v + 0];
+            d[4 * v + 1] = s[3 * v + 1];
+            d[4 * v + 2] = s[3 * v + 2];
+            d[4 * v + 3] = 0.0f;
+        }
+    }
+    return 0;
+}
+
+void free_bvh(HostBvh* b) {
+    std::free(b->nodes);
+    std::free(b->tris);
+    b->nodes = nullptr;
+    b->tris = nullptr;
+    b->n_nodes = 0;
+}
+
+}  // namespace utd

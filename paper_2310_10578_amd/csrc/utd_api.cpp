@@ -1,0 +1,207 @@
+// C ABI of the smooth-surface UTD library: argument checks, scene (BVH)
+// ownership, stream-ordered workspace and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <new>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "../../include/utd.h"
+#include "utd_internal.h"
+
+struct utd_scene {
+    int64_t n_tri = 0;
+    int64_t n_nodes = 0;
+    int depth = 0;
+    float4* d_nodes = nullptr;
+    float4* d_tris = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+utd_status fail(utd_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+utd_status fail(utd_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+utd_status hip_fail(hipError_t e, const char* what) {
+    return fail(UTD_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+std::once_flag g_tables_once;
+hipError_t g_tables_err = hipSuccess;
+
+hipError_t ensure_tables() {
+    std::call_once(g_tables_once, [] {
+        g_tables_err = utd::pack_tables(nullptr);
+        if (g_tables_err == hipSuccess) g_tables_err = hipDeviceSynchronize();
+    });
+    return g_tables_err;
+}
+
+constexpr int kMaxDepth = 40;   // < kStackDepth of the device traversal
+
+utd_status check_common(const utd_bodies* bodies, const utd_source* tx, const float* rx, int64_t n_rx,
+                        const double* freqs, int n_f, const utd_options* opt) {
+    if (!bodies || !tx || !opt) return fail(UTD_E_ARG, "bodies, tx and opt must not be NULL");
+    if (n_rx < 0 || n_f < 0) return fail(UTD_E_ARG, "negative n_rx or n_f");
+    if (n_rx > ((int64_t)1 << 31) / 4) return fail(UTD_E_ARG, "n_rx too large (max 2^29)");
+    if (bodies->n_sph < 0 || bodies->n_cyl < 0) return fail(UTD_E_ARG, "negative body count");
+    if (bodies->n_sph + bodies->n_cyl > 4096) return fail(UTD_E_ARG, "more than 4096 bodies");
+    if ((bodies->n_sph && !bodies->sph) || (bodies->n_cyl && !bodies->cyl))
+        return fail(UTD_E_ARG, "NULL body array with non-zero count");
+    if (n_rx && !rx) return fail(UTD_E_ARG, "rx is NULL");
+    if (n_f && !freqs) return fail(UTD_E_ARG, "freqs is NULL");
+    if (opt->precision != 0 && opt->precision != 1) return fail(UTD_E_ARG, "precision must be 0 or 1");
+    if (opt->l_enc < 0 || opt->l_enc > 2) return fail(UTD_E_ARG, "l_enc must be in 0..2");
+    if (!(opt->caustic_guard >= 0)) return fail(UTD_E_ARG, "caustic_guard must be >= 0");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(tx->pos[a]) || !std::isfinite(tx->dipole[a]))
+            return fail(UTD_E_ARG, "non-finite source position or dipole");
+    if (!std::isfinite(tx->amplitude)) return fail(UTD_E_ARG, "non-finite amplitude");
+    return UTD_OK;
+}
+
+utd::LaunchParams make_params(const utd_bodies* bodies, const utd_source* tx, int64_t n_rx, int n_f,
+                              const utd_options* opt) {
+    utd::LaunchParams L;
+    for (int a = 0; a < 3; ++a) { L.T[a] = tx->pos[a]; L.p[a] = tx->dipole[a]; }
+    L.amp = tx->amplitude;
+    L.n_sph = (int)bodies->n_sph;
+    L.n_cyl = (int)bodies->n_cyl;
+    L.n_rx = n_rx;
+    L.n_f = n_f;
+    L.l_enc = opt->l_enc;
+    L.bodies_occlude = opt->bodies_occlude;
+    L.lit_branch = opt->lit_branch;
+    L.caustic_guard = opt->caustic_guard;
+    return L;
+}
+
+// Frequencies per lane: more frequencies per lane amortise the path geometry,
+// fewer keep enough lanes in flight.
+int pick_fc(int precision, int64_t n_rx, int n_f) {
+    int fc = precision == 0 ? 8 : 4;
+    while (fc > 1 && (fc / 2 >= n_f || n_rx * ((n_f + fc - 1) / fc) < 256 * 2048)) fc /= 2;
+    return fc;
+}
+
+}  // namespace
+
+extern "C" {
+
+void utd_default_options(utd_options* opt) {
+    if (!opt) return;
+    opt->precision = 0;
+    opt->l_enc = 0;
+    opt->bodies_occlude = 1;
+    opt->lit_branch = 1;
+    opt->caustic_guard = 1e-6;
+}
+
+const char* utd_last_error(void) { return g_err.c_str(); }
+
+utd_status utd_scene_create(const float* tri, int64_t n_tri, utd_scene** out) {
+    if (!out) return fail(UTD_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (n_tri < 0) return fail(UTD_E_ARG, "n_tri < 0");
+    if (n_tri > 0 && !tri) return fail(UTD_E_ARG, "tri is NULL with n_tri > 0");
+    if (n_tri > ((int64_t)1 << 30)) return fail(UTD_E_ARG, "too many triangles");
+    utd_scene* s = new (std::nothrow) utd_scene();
+    if (!s) return fail(UTD_E_OOM, "host allocation failed");
+    s->n_tri = n_tri;
+    if (n_tri > 0) {
+        utd::HostBvh b;
+        if (utd::build_bvh(tri, n_tri, kMaxDepth, &b) != 0) {
+            delete s;
+            return fail(UTD_E_OOM, "BVH build: host allocation failed");
+        }
+        s->n_nodes = b.n_nodes;
+        s->depth = b.depth;
+        hipError_t e = hipMalloc(&s->d_nodes, sizeof(float4) * 4 * b.n_nodes);
+        if (e == hipSuccess) e = hipMalloc(&s->d_tris, sizeof(float4) * 3 * n_tri);
+        if (e == hipSuccess) e = hipMemcpy(s->d_nodes, b.nodes, sizeof(float4) * 4 * b.n_nodes, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(s->d_tris, b.tris, sizeof(float4) * 3 * n_tri, hipMemcpyHostToDevice);
+        utd::free_bvh(&b);
+        if (e != hipSuccess) {
+            utd_scene_destroy(s);
+            return e == hipErrorOutOfMemory ? fail(UTD_E_OOM, "device allocation failed") : hip_fail(e, "scene upload");
+        }
+    }
+    *out = s;
+    return UTD_OK;
+}
+
+void utd_scene_destroy(utd_scene* s) {
+    if (!s) return;
+    if (s->d_nodes || s->d_tris) (void)hipDeviceSynchronize();
+    if (s->d_nodes) (void)hipFree(s->d_nodes);
+    if (s->d_tris) (void)hipFree(s->d_tris);
+    delete s;
+}
+
+int64_t utd_scene_triangles(const utd_scene* s) { return s ? s->n_tri : 0; }
+int64_t utd_scene_nodes(const utd_scene* s) { return s ? s->n_nodes : 0; }
+
+utd_status utd_smooth_field(const utd_scene* scene, const utd_bodies* bodies, const utd_source* tx, const float* rx,
+                            int64_t n_rx, const double* freqs, int n_f, const utd_options* opt, void* E_out,
+                            uint8_t* rx_flags, void* stream) {
+    utd_status st = check_common(bodies, tx, rx, n_rx, freqs, n_f, opt);
+    if (st != UTD_OK) return st;
+    if (n_rx == 0 || n_f == 0) return UTD_OK;
+    if (!E_out) return fail(UTD_E_ARG, "E_out is NULL");
+    hipError_t e = ensure_tables();
+    if (e != hipSuccess) return hip_fail(e, "table upload");
+    hipStream_t s = (hipStream_t)stream;
+    utd::LaunchParams L = make_params(bodies, tx, n_rx, n_f, opt);
+    int nb = L.n_sph + L.n_cyl;
+    // workspace: body constants, path masks, flags (if the caller passed none)
+    size_t prep_bytes = sizeof(utd::BodyPrep) * (size_t)(nb > 0 ? nb : 1);
+    size_t mask_bytes = (size_t)n_rx * (size_t)(nb > 0 ? nb : 1);
+    size_t flag_bytes = rx_flags ? 0 : (size_t)n_rx;
+    size_t off_mask = (prep_bytes + 255) & ~(size_t)255;
+    size_t off_flag = (off_mask + mask_bytes + 255) & ~(size_t)255;
+    size_t total = off_flag + flag_bytes + 256;
+    char* ws = nullptr;
+    e = hipMallocAsync((void**)&ws, total, s);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(UTD_E_OOM, "workspace allocation") : hip_fail(e, "hipMallocAsync");
+    utd::BodyPrep* prep = (utd::BodyPrep*)ws;
+    uint8_t* mask = (uint8_t*)(ws + off_mask);
+    uint8_t* flags = rx_flags ? rx_flags : (uint8_t*)(ws + off_flag);
+    const float4* nodes = scene ? scene->d_nodes : nullptr;
+    const float4* tris = scene ? scene->d_tris : nullptr;
+    e = utd::launch_prep(L, bodies->sph, bodies->cyl, prep, s);
+    if (e == hipSuccess) e = utd::launch_occlude(L, rx, bodies->sph, bodies->cyl, prep, nodes, tris, mask, flags, s);
+    int fc = pick_fc(opt->precision, n_rx, n_f);
+    if (e == hipSuccess) e = utd::launch_field(L, opt->precision, fc, rx, freqs, prep, mask, flags, E_out, s);
+    hipError_t e2 = hipFreeAsync(ws, s);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
+    return UTD_OK;
+}
+
+utd_status utd_smooth_field_backward(const utd_scene*, const utd_bodies*, const utd_source*, const float*, int64_t,
+                                     const double*, int, const utd_options*, const void*, float*, float*, float*,
+                                     void*) {
+    return fail(UTD_E_UNSUPPORTED, "backward not built yet");
+}
+
+utd_status utd_smooth_field_batched(const utd_scene*, int64_t, const int64_t*, const float*, const int64_t*,
+                                    const float*, int64_t, int64_t, const utd_source*, const double*, int,
+                                    const utd_options*, void*, uint8_t*, void*) {
+    return fail(UTD_E_UNSUPPORTED, "batched not built yet");
+}
+
+}  // extern "C"

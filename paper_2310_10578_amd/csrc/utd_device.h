@@ -1,0 +1,138 @@
+// Device-side building blocks of the smooth-surface UTD field evaluation
+// (gfx950).  Included by utd_kernels.hip only.
+//
+// Notation follows the paper (Sec. II-B, Eqs. (1)-(4)) and the off-surface
+// UTD it cites (Pathak, Burnside and Marhefka 1980): source T, receiver R,
+// attachment Q1, detachment Q2, reflection point Q_R, arc length t, incident
+// and shed lengths s^i, s^d, Fock parameter m = (k rho_g / 2)^{1/3},
+// xi = int m / rho_g dt, transition argument X, distance parameter L.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace utd {
+
+constexpr double kC0 = 299792458.0;
+constexpr double kTwoPi = 6.283185307179586476925287;
+constexpr double kPi = 3.141592653589793238462643;
+constexpr double kInvTwoPi = 0.1591549430918953357688837;
+
+// mask bits per (body, receiver): creeping path (side, ell) valid and visible
+// -> bit 2*ell + (side < 0); reflection -> bit 6; axial caustic drop -> bit 7
+constexpr int kBitRefl = 6;
+constexpr int kBitCaustic = 7;
+constexpr uint8_t kFlagInside = 1, kFlagCaustic = 2, kFlagLos = 4, kFlagTxInside = 8;
+
+struct LaunchParams {
+    double T[3];          // source position
+    double p[3];          // dipole
+    double amp;           // amplitude
+    int n_sph, n_cyl;
+    int64_t n_rx;
+    int n_f;
+    int l_enc, bodies_occlude, lit_branch;
+    double caustic_guard;
+};
+
+// Per-body quantities that depend only on the source (computed once per call).
+struct BodyPrep {
+    double c[3];      // sphere centre / cylinder axis point (cx, cy, 0)
+    double a;         // radius
+    double z0, h;     // cylinder lateral surface z0 .. z0 + h
+    double eT[3];     // sphere: unit (T - C); cylinder: unit (T - c) in xy
+    double dT;        // sphere: |T - C|; cylinder: rho_T (distance to axis)
+    double sI0;       // tangent length sqrt(dT^2 - a^2)
+    double gT;        // tangent half-angle gamma_T = atan2(sI0, a)
+    double aT;        // cylinder: azimuth of T about the axis
+    int kind;         // 0 sphere, 1 cylinder
+    int ok;           // 1 if T lies outside the body's circle/sphere
+    int pad[2];
+};
+
+// ---------------------------------------------------------------------------
+// small vector helpers (double)
+// ---------------------------------------------------------------------------
+struct d3 { double x, y, z; };
+__device__ __forceinline__ d3 mk(double x, double y, double z) { return d3{x, y, z}; }
+__device__ __forceinline__ d3 operator+(d3 a, d3 b) { return mk(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ d3 operator-(d3 a, d3 b) { return mk(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ d3 operator*(double s, d3 a) { return mk(s * a.x, s * a.y, s * a.z); }
+__device__ __forceinline__ double dot(d3 a, d3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ d3 cross(d3 a, d3 b) {
+    return mk(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ double norm(d3 a) { return sqrt(dot(a, a)); }
+
+// A unit vector perpendicular to e (only used for degenerate collinear cases).
+__device__ __forceinline__ d3 any_perp(d3 e) {
+    d3 ref = fabs(e.x) < 0.9 ? mk(1, 0, 0) : mk(0, 1, 0);
+    d3 c = cross(e, ref);
+    return (1.0 / norm(c)) * c;
+}
+
+// ---------------------------------------------------------------------------
+// Real-type traits: float for the FP32 path, double for the FP64 path.
+// ---------------------------------------------------------------------------
+template <typename R> struct RT;
+template <> struct RT<float> {
+    static __device__ __forceinline__ float sqrt_(float x) { return __builtin_sqrtf(x); }
+    static __device__ __forceinline__ float exp_(float x) { return expf(x); }
+    static __device__ __forceinline__ float cbrt_(float x) { return cbrtf(x); }
+    static __device__ __forceinline__ float rint_(float x) { return rintf(x); }
+    static __device__ __forceinline__ float floor_(float x) { return floorf(x); }
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+};
+template <> struct RT<double> {
+    static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+    static __device__ __forceinline__ double exp_(double x) { return exp(x); }
+    static __device__ __forceinline__ double cbrt_(double x) { return cbrt(x); }
+    static __device__ __forceinline__ double rint_(double x) { return rint(x); }
+    static __device__ __forceinline__ double floor_(double x) { return floor(x); }
+    static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+};
+
+template <typename R> struct cplx { R re, im; };
+template <typename R> __device__ __forceinline__ cplx<R> cmul(cplx<R> a, cplx<R> b) {
+    return cplx<R>{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+
+// sin and cos of 2 pi r for r in [-1/2, 1/2] (revolutions).
+// FP32: quadrant reduction to |x| <= pi/4 and Taylor polynomials of degree
+// 9 / 8 (truncation below 1e-9, under FP32 rounding).  FP64: the device
+// library's sincos.
+__device__ __forceinline__ void sincos_rev(float r, float* s, float* c) {
+    float q = rintf(4.0f * r);
+    float y = r - 0.25f * q;                      // |y| <= 1/8
+    float x = 6.28318530717958647692f * y;        // |x| <= pi/4
+    float x2 = x * x;
+    float sn = x * (1.0f + x2 * (-1.0f / 6 + x2 * (1.0f / 120 + x2 * (-1.0f / 5040 + x2 * (1.0f / 362880)))));
+    float cs = 1.0f + x2 * (-0.5f + x2 * (1.0f / 24 + x2 * (-1.0f / 720 + x2 * (1.0f / 40320))));
+    int qi = ((int)q) & 3;
+    float so = sn, co = cs;
+    if (qi == 1) { so = cs; co = -sn; }
+    else if (qi == 2) { so = -sn; co = -cs; }
+    else if (qi == 3) { so = -cs; co = sn; }
+    *s = so;
+    *c = co;
+}
+__device__ __forceinline__ void sincos_rev(double r, double* s, double* c) { sincospi(2.0 * r, s, c); }
+
+// e^{-j theta} for theta given in revolutions as an FP64 value (reduced in FP64).
+template <typename R> __device__ __forceinline__ cplx<R> phase_rev(double rev) {
+    double fr = rev - rint(rev);
+    R s, c;
+    sincos_rev((R)fr, &s, &c);
+    return cplx<R>{c, -s};
+}
+
+// e^{-j x} for a moderate real x of type R.
+template <typename R> __device__ __forceinline__ cplx<R> expmj(R x) {
+    R r = x * (R)kInvTwoPi;
+    r = r - RT<R>::rint_(r);
+    R s, c;
+    sincos_rev(r, &s, &c);
+    return cplx<R>{c, -s};
+}
+
+}  // namespace utd

@@ -1,0 +1,29 @@
+// Internal interface between the C ABI (utd_api.cpp) and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "utd_device.h"
+
+namespace utd {
+
+hipError_t pack_tables(hipStream_t s);
+hipError_t launch_prep(const LaunchParams& L, const float* sph, const float* cyl, BodyPrep* prep, hipStream_t s);
+hipError_t launch_occlude(const LaunchParams& L, const float* rx, const float* sph, const float* cyl,
+                          const BodyPrep* prep, const float4* nodes, const float4* tris, uint8_t* mask,
+                          uint8_t* flags, hipStream_t s);
+hipError_t launch_field(const LaunchParams& L, int precision, int fc, const float* rx, const double* freqs,
+                        const BodyPrep* prep, const uint8_t* mask, uint8_t* flags, void* E, hipStream_t s);
+
+// host BVH over a triangle soup (bvh.cpp)
+struct HostBvh {
+    int64_t n_nodes = 0;
+    int depth = 0;
+    float* nodes = nullptr;   // n_nodes * 16 floats (4 float4 per node)
+    float* tris = nullptr;    // n_tri * 12 floats (3 float4 per triangle), leaf order
+};
+int build_bvh(const float* tri_xyz, int64_t n_tri, int max_depth, HostBvh* out);
+void free_bvh(HostBvh* b);
+
+}  // namespace utd

@@ -1,0 +1,141 @@
+"""Parity of the HIP forward field (through the C ABI) against the FP64 oracle.
+
+Tolerances: relative normwise field error per frequency <= 1e-4 for the FP32
+path and <= 1e-10 for the FP64 path, on the same float32 inputs.  Visibility
+decisions may differ only where a segment grazes an occluder (FP32 watertight
+test on the GPU, FP64 Moller-Trumbore in the oracle); such receivers are
+counted and, when present, the field is compared on the others."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import normwise, run_library, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-4, 1: 1e-10}
+
+
+def _report(name, err):
+    print("%s normwise error per frequency: %s" % (name, np.array2string(np.asarray(err), precision=2)), flush=True)
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+@pytest.mark.parametrize("pol", ["hard", "soft"])
+def test_config1_sphere_ring(precision, pol):
+    cfg = W.config1(polarisation=pol)
+    Eg, fg = run_library(cfg, precision)
+    Eo, info = run_oracle(cfg)
+    err = normwise(Eg, Eo)
+    _report("config1 %s p%d" % (pol, precision), err)
+    assert np.all(err <= TOL[precision])
+    np.testing.assert_array_equal(fg & 5, info["flags"] & 5)
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_config2_plane_subsample(precision):
+    """Config 2 geometry: every 8th receiver row/column (32 x 32 = 1024, a
+    ragged tail w.r.t. the 256-lane blocks) at 9 of the 64 frequencies, so the
+    frequency chunks also end ragged."""
+    cfg = W.config2()
+    rx = cfg["rx"].reshape(256, 256, 3)[3::8, 5::8].reshape(-1, 3)
+    freqs = cfg["freqs"][::7]
+    Eg, fg = run_library(cfg, precision, rx=rx, freqs=freqs)
+    Eo, info = run_oracle(cfg, rx=rx, freqs=freqs)
+    err = normwise(Eg, Eo)
+    _report("config2 subsample p%d" % precision, err)
+    assert np.all(err <= TOL[precision])
+
+
+def test_config2_full_size_sampled():
+    """Config 2 at full size in the launch configuration the bench times
+    (65536 receivers, 64 frequencies, FP32); 1500 sampled receivers are
+    recomputed by the oracle one by one."""
+    cfg = W.config2()
+    Eg, fg = run_library(cfg, 0)
+    rng = np.random.default_rng(3)
+    idx = np.sort(rng.choice(cfg["rx"].shape[0], 1500, replace=False))
+    Eo, info = run_oracle(cfg, rx=cfg["rx"][idx])
+    err = normwise(Eg[:, :, idx], Eo)
+    _report("config2 full sampled", err)
+    assert np.all(err <= TOL[0])
+    np.testing.assert_array_equal(fg[idx] & 5, info["flags"] & 5)
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+@pytest.mark.parametrize("spheres", [False, True])
+def test_small_room(precision, spheres):
+    cfg = W.small_room(spheres=spheres)
+    Eg, fg = run_library(cfg, precision)
+    Eo, info = run_oracle(cfg)
+    ok = (fg & 5) == (info["flags"] & 5)
+    assert ok.mean() > 0.995
+    err = normwise(Eg[:, :, ok], Eo[:, :, ok])
+    _report("small room spheres=%s p%d (%d flag mismatches)" % (spheres, precision, (~ok).sum()), err)
+    assert np.all(err <= TOL[precision])
+
+
+def test_encirclements_and_creeping_only():
+    cfg = W.small_room(n_cyl=4, n_side=12, spheres=True)
+    for kw in (dict(l_enc=2), dict(lit_branch=False), dict(bodies_occlude=False)):
+        Eg, fg = run_library(cfg, 1, **kw)
+        Eo, info = run_oracle(cfg, opts=kw)
+        err = normwise(Eg, Eo)
+        _report("options %s" % kw, err)
+        assert np.all(err <= TOL[1])
+
+
+def test_inside_and_degenerate_receivers():
+    cfg = W.config1(n_rx=8)
+    rx = np.array([[0.1, 0.0, 0.0],        # inside the sphere
+                   [-3.0, 0.0, 0.0],       # on the source axis behind the sphere (caustic)
+                   [0.0, 2.0, 0.0],
+                   [-2.9, 0.4, 0.1]], np.float32)
+    Eg, fg = run_library(cfg, 1, rx=rx)
+    Eo, info = run_oracle(cfg, rx=rx)
+    assert fg[0] & 1 and np.all(Eg[:, :, 0] == 0)
+    assert fg[1] & 2 and info["flags"][1] & 2
+    assert np.isfinite(Eg).all()
+    assert np.all(normwise(Eg[:, :, [2, 3]], Eo[:, :, [2, 3]]) < 1e-10)
+
+
+def test_source_inside_body_zeroes_field():
+    cfg = W.config1(n_rx=64)
+    cfg["tx"] = dict(pos=np.array([0.1, 0.0, 0.0], np.float32), dipole=np.array([0, 0, 1.0], np.float32),
+                     amplitude=1.0)
+    Eg, fg = run_library(cfg, 0)
+    assert np.all(Eg == 0) and np.all(fg & 8)
+
+
+def test_empty_inputs():
+    import torch
+
+    import paper_2310_10578_amd as utd
+    scene = utd.Scene(None)
+    src = utd.make_source((0, 0, 0))
+    rx = torch.zeros((0, 3), dtype=torch.float32, device="cuda")
+    f = torch.tensor([1e9], dtype=torch.float64, device="cuda")
+    E, fl = utd.smooth_field(scene, None, None, src, rx, f)
+    assert E.shape == (1, 3, 0)
+    rx = torch.tensor([[1.0, 2.0, 3.0]], dtype=torch.float32, device="cuda")
+    E, fl = utd.smooth_field(scene, None, None, src, rx, f)
+    torch.cuda.synchronize()
+    s = np.sqrt(14.0)
+    k = 2 * np.pi * 1e9 / 299792458.0
+    sh = np.array([1, 2, 3.0]) / s
+    ref = (np.array([0, 0, 1.0]) - sh[2] * sh) * np.exp(-1j * k * s) / s
+    np.testing.assert_allclose(E.cpu().numpy()[0, :, 0], ref, rtol=2e-6, atol=1e-7)
+
+
+def test_bad_arguments_raise():
+    import torch
+
+    import paper_2310_10578_amd as utd
+    scene = utd.Scene(None)
+    src = utd.make_source((0, 0, 0))
+    rx = torch.zeros((4, 3), dtype=torch.float32, device="cuda")
+    f = torch.tensor([1e9], dtype=torch.float64, device="cuda")
+    with pytest.raises(utd.UTDError):
+        utd.smooth_field(scene, None, None, src, rx, f, l_enc=5)
+    with pytest.raises(utd.UTDError):
+        utd.smooth_field(scene, None, None, src, rx, f, precision=3)

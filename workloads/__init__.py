@@ -229,3 +229,13 @@ def to_oracle(scene, tx, rx):
     t = dict(pos=np.asarray(tx["pos"], np.float64), dipole=np.asarray(tx["dipole"], np.float64),
              amplitude=float(tx["amplitude"]))
     return sc, t, np.asarray(rx, np.float64)
+
+
+def small_room(n_cyl=8, edge=0.5, n_side=24, freqs=(5e9, 28e9), spheres=False):
+    """The config-3 room at a coarse tessellation, fewer cylinders and a
+    small receiver grid: a parity-test case the oracle finishes in seconds."""
+    sc, boxes = room_scene(n_cyl, 7, edge)
+    if spheres:
+        sc["spheres"] = np.array([[2.0, 6.5, 0.6, 0.35], [8.2, 1.4, 1.0, 0.5]], np.float32)
+    return dict(name="room-coarse-%dcyl-%dx%d" % (n_cyl, n_side, n_side), scene=sc, tx=room_tx(),
+                rx=room_grid(n_side), freqs=np.asarray(freqs, float), boxes=boxes)
