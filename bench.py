@@ -1,0 +1,174 @@
+"""Throughput of the smooth-surface UTD field evaluation on one MI355X.
+
+A step is one call of utd_smooth_field over the whole workload: per-body
+constants, path classification and visibility (BVH + body tests), and the
+coherent field of Eqs. (1)-(4) for every (receiver, body, frequency).
+Default workload: PEC sphere a = 1 m, source at 4 m, 256 x 256 receivers on
+the plane x = -3 m, 64 frequencies in 1-6 GHz, FP32 field with FP64 phase.
+Inputs are resident in HBM before the timed region.
+
+Prints one JSON line (rank 0).  ``--gpus`` above 1 is refused: this build
+runs on one GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# FP32 operations per (path, frequency) of the field kernel, counted from its
+# formula set (utd_fock.h / add_path): argument scaling 6, sqrt 1, transition
+# function 39 (locate 6, degree-6 complex Horner 24, combine 9), regime lookup
+# 65 (locate 6, degree-6 soft+hard complex Horner 48, combine 11), phase 30
+# (range reduction and degree-9/8 sin/cos polynomials), coefficient scaling 18,
+# accumulation into 3 complex components 24.  Direct field per (receiver,
+# frequency): 36 (phase 30 + 6 FMA).
+FLOPS_PER_PATH_FREQ = 6 + 1 + 39 + 65 + 30 + 18 + 24
+FLOPS_LOS = 36
+PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (published, packed-FP32 rate)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config5", "config1"])
+    ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--cpu-sample", type=int, default=1536, help="receivers in the oracle sample")
+    return ap.parse_args()
+
+
+def workload(name):
+    import workloads as W
+    if name == "config2":
+        return W.config2()
+    if name == "config3":
+        return W.config3()
+    if name == "config5":
+        return W.config5()
+    return W.config1()
+
+
+def cpu_baseline(cfg, n_sample):
+    """The FP64 oracle on a bounded receiver sample, all frequencies, in a
+    pool of worker processes (one receiver chunk each)."""
+    import multiprocessing as mp
+
+    import workloads as W
+    rng = np.random.default_rng(11)
+    idx = np.sort(rng.choice(cfg["rx"].shape[0], n_sample, replace=False))
+    sc, tx, rx = W.to_oracle(cfg["scene"], cfg["tx"], cfg["rx"][idx])
+    cores = max(1, min(os.cpu_count() or 1, 16))
+    chunks = np.array_split(np.arange(n_sample), cores)
+    args = [(sc, tx, rx[c], cfg["freqs"]) for c in chunks if c.size]
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(len(args)) as pool:
+        pool.map(_oracle_chunk, args)
+    dt = time.perf_counter() - t0
+    nb = len(sc["spheres"]) + len(sc["cylinders"])
+    evals = n_sample * max(nb, 1) * len(cfg["freqs"])
+    return dict(value=evals / dt, unit="evals/s", cores=len(args), kind="oracle",
+                sample="%d receivers x %d bodies x %d frequencies of the workload, %.1f s wall"
+                       % (n_sample, nb, len(cfg["freqs"]), dt))
+
+
+def _oracle_chunk(a):
+    os.environ["OMP_NUM_THREADS"] = "1"
+    from oracle import field
+    sc, tx, rx, freqs = a
+    return field.field(sc, tx, rx, freqs).shape
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU (this build has no multi-GPU path); got --gpus %d" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2310_10578_amd as utd
+    cfg = workload(args.workload)
+    dev = "cuda:0"
+    sc = cfg["scene"]
+    scene = utd.Scene(sc.get("tri"))
+    sph = torch.from_numpy(np.ascontiguousarray(sc["spheres"], np.float32)).to(dev)
+    cyl = torch.from_numpy(np.ascontiguousarray(sc["cylinders"], np.float32)).to(dev)
+    rx = torch.from_numpy(cfg["rx"]).to(dev)
+    freqs = torch.tensor(cfg["freqs"], dtype=torch.float64, device=dev)
+    src = utd.make_source(cfg["tx"]["pos"], cfg["tx"]["dipole"], cfg["tx"]["amplitude"])
+    n_rx, n_f = rx.shape[0], freqs.shape[0]
+    n_body = sph.shape[0] + cyl.shape[0]
+    out = torch.empty((n_f, 3, n_rx), dtype=torch.complex64, device=dev)
+    flags = torch.empty((n_rx,), dtype=torch.uint8, device=dev)
+
+    def step():
+        utd.smooth_field(scene, sph, cyl, src, rx, freqs, precision=0, out=out, flags=flags)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    utd.profile_enable(True)
+    utd.profile_read()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = e0.elapsed_time(e1)
+    prof = utd.profile_read()
+    utd.profile_enable(False)
+
+    # algorithmic work of the field kernel: the paths it evaluates, from the
+    # library's path census of the same inputs (outside the timed region)
+    census = utd.path_census(scene, sph, cyl, src, rx)
+    n_paths, los = census["paths"], census["los"]
+    flops = (n_paths * FLOPS_PER_PATH_FREQ + los * FLOPS_LOS) * n_f
+    field_ms, field_n = prof["field"]
+    field_avg_s = field_ms / max(field_n, 1) / 1e3
+    achieved = flops / field_avg_s / 1e12
+    ms_step = ms_total / args.steps
+    evals = n_rx * max(n_body, 1) * n_f
+    res = {
+        "metric": "diffracted (rx*body*freq) evals/sec",
+        "value": evals / (ms_step / 1e3),
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "receivers": n_rx, "bodies": n_body, "frequencies": n_f,
+                   "triangles": scene.n_tri, "evals_per_step": evals, "parallelism": "single-gpu"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": "k_field<float>", "kernel_ms": field_avg_s * 1e3,
+                     "flops_per_launch": flops, "paths": n_paths, "los_receivers": los},
+        "kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]},
+        "wall_s": wall,
+    }
+    if args.cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(cfg, min(args.cpu_sample, n_rx))
+    print(json.dumps(res))
+
+
+
+
+if __name__ == "__main__":
+    main()

@@ -155,6 +155,35 @@ utd_status utd_smooth_field_batched(const utd_scene *scene, int64_t n_frames,
                                     const utd_options *opt, void *E_out, uint8_t *rx_flags,
                                     void *stream);
 
+/* Path census (reporting): runs the classification and visibility stage of
+ * utd_smooth_field for the same inputs and writes, to the host array
+ * counts[10], the number of (receiver, body) pairs with each mask bit set --
+ * counts[2*ell + s] creeping paths on side s (0: towards the receiver,
+ * 1: far side) with ell encirclements, counts[6] reflections, counts[7]
+ * caustic drops -- then counts[8] receivers with a visible direct path and
+ * counts[9] receivers inside a body.  Waits for the stream.
+ * Errors as for utd_smooth_field; UTD_E_ARG if counts is NULL. */
+utd_status utd_path_census(const utd_scene *scene, const utd_bodies *bodies, const utd_source *tx,
+                           const float *rx, int64_t n_rx, const utd_options *opt, int64_t *counts,
+                           void *stream);
+
+/* Per-kernel timing for measurement.  utd_profile_enable(1) makes every
+ * later call record a HIP event pair around each kernel it launches, on the
+ * stream it launches on; utd_profile_read waits for those events, writes the
+ * summed durations in milliseconds and launch counts into ms[k] and count[k]
+ * (k = UTD_K_*; arrays of UTD_K_COUNT entries, host) and clears the record.
+ * utd_profile_enable(0) stops recording.  Not for concurrent use from
+ * several host threads.  Errors: UTD_E_ARG for NULL outputs, UTD_E_DEVICE. */
+#define UTD_K_PREP 0
+#define UTD_K_OCCLUDE 1
+#define UTD_K_FIELD 2
+#define UTD_K_BACKWARD 3
+#define UTD_K_REDUCE 4
+#define UTD_K_BATCHED 5
+#define UTD_K_COUNT 6
+void utd_profile_enable(int on);
+utd_status utd_profile_read(double *ms, int64_t *count);
+
 /* Message for the last non-OK status returned on this thread ("" if none). */
 const char *utd_last_error(void);
 

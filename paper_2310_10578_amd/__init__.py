@@ -18,7 +18,8 @@ FLAG_INSIDE, FLAG_CAUSTIC, FLAG_LOS, FLAG_TX_INSIDE = 1, 2, 4, 8
 
 EXPORTS = ["utd_default_options", "utd_scene_create", "utd_scene_destroy", "utd_scene_triangles",
            "utd_scene_nodes", "utd_smooth_field", "utd_smooth_field_backward", "utd_smooth_field_batched",
-           "utd_last_error"]
+           "utd_path_census", "utd_profile_enable", "utd_profile_read", "utd_last_error"]
+KERNELS = ["prep", "occlude", "field", "backward", "reduce", "batched"]
 
 
 class Options(ctypes.Structure):
@@ -66,6 +67,13 @@ def load_library(path=LIB_PATH):
     lib.utd_smooth_field_batched.argtypes = [vp, i64, vp, vp, vp, vp, i64, i64, ctypes.POINTER(Source), vp, i32,
                                              ctypes.POINTER(Options), vp, vp, vp]
     lib.utd_smooth_field_batched.restype = i32
+    lib.utd_path_census.argtypes = [vp, ctypes.POINTER(Bodies), ctypes.POINTER(Source), vp, i64,
+                                    ctypes.POINTER(Options), vp, vp]
+    lib.utd_path_census.restype = i32
+    lib.utd_profile_enable.argtypes = [i32]
+    lib.utd_profile_enable.restype = None
+    lib.utd_profile_read.argtypes = [vp, vp]
+    lib.utd_profile_read.restype = i32
     lib.utd_last_error.argtypes = []
     lib.utd_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -195,3 +203,35 @@ def smooth_field(scene, spheres, cylinders, source, rx, freqs, precision=0, l_en
                                 ctypes.byref(opt), out.data_ptr() if out.numel() else None,
                                 flags.data_ptr() if n else None, _stream(stream)))
     return out, flags
+
+
+def profile_enable(on=True):
+    """Record HIP event pairs around every kernel launch (measurement only)."""
+    load_library().utd_profile_enable(int(bool(on)))
+
+
+def profile_read():
+    """{kernel: (total_ms, launches)} since the last read; waits for the events."""
+    lib = load_library()
+    ms = (ctypes.c_double * len(KERNELS))()
+    cnt = (ctypes.c_int64 * len(KERNELS))()
+    _check(lib.utd_profile_read(ctypes.cast(ms, ctypes.c_void_p), ctypes.cast(cnt, ctypes.c_void_p)))
+    return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNELS)}
+
+
+def path_census(scene, spheres, cylinders, source, rx, l_enc=0, bodies_occlude=True, lit_branch=True,
+                caustic_guard=1e-6, stream=None):
+    """Counts of evaluated paths: dict with creeping (per side/ell), reflections,
+    caustic drops, line-of-sight receivers and receivers inside bodies."""
+    torch = _torch()
+    lib = load_library()
+    _dev(rx, torch.float32, (3,), "rx")
+    b, keep = _bodies(spheres, cylinders)
+    opt = make_options(0, l_enc, bodies_occlude, lit_branch, caustic_guard)
+    counts = (ctypes.c_int64 * 10)()
+    _check(lib.utd_path_census(scene.handle if scene is not None else None, ctypes.byref(b), ctypes.byref(source),
+                               rx.data_ptr() if rx.shape[0] else None, rx.shape[0], ctypes.byref(opt),
+                               ctypes.cast(counts, ctypes.c_void_p), _stream(stream)))
+    c = list(counts)
+    return dict(creeping=sum(c[:6]), creeping_by_bit=c[:6], reflections=c[6], caustic=c[7], los=c[8], inside=c[9],
+                paths=sum(c[:7]))

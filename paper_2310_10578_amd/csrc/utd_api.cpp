@@ -9,6 +9,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/utd.h"
 #include "utd_internal.h"
@@ -53,6 +54,30 @@ hipError_t ensure_tables() {
 
 constexpr int kMaxDepth = 40;   // < kStackDepth of the device traversal
 
+// --- optional per-kernel event timing (utd_profile_*) ---
+struct ProfRec {
+    int kernel;
+    hipEvent_t a, b;
+};
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+
+struct ProfScope {
+    int kernel;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(int k, hipStream_t st) : kernel(k), s(st) {
+        if (!g_prof_on) return;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { a = b = nullptr; return; }
+        (void)hipEventRecord(a, s);
+    }
+    ~ProfScope() {
+        if (!a) return;
+        (void)hipEventRecord(b, s);
+        g_prof.push_back({kernel, a, b});
+    }
+};
+
 utd_status check_common(const utd_bodies* bodies, const utd_source* tx, const float* rx, int64_t n_rx,
                         const double* freqs, int n_f, const utd_options* opt) {
     if (!bodies || !tx || !opt) return fail(UTD_E_ARG, "bodies, tx and opt must not be NULL");
@@ -92,8 +117,42 @@ utd::LaunchParams make_params(const utd_bodies* bodies, const utd_source* tx, in
 
 // Frequencies per lane: more frequencies per lane amortise the path geometry,
 // fewer keep enough lanes in flight.
+// Stream-ordered scratch of one call: body constants, frequency constants,
+// path masks, reflection angles, flags (when the caller passed none) and
+// counters.
+struct Workspace {
+    char* base = nullptr;
+    utd::BodyPrep* prep = nullptr;
+    utd::FreqConst* fc = nullptr;
+    uint8_t* mask = nullptr;
+    void* rec = nullptr;
+    uint8_t* flags = nullptr;
+    unsigned long long* counters = nullptr;
+    hipError_t alloc(int nb, int64_t n_rx, int n_f, int l_enc, int precision, bool need_flags, hipStream_t s) {
+        auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+        size_t nbb = (size_t)(nb > 0 ? nb : 1);
+        size_t o_prep = 0;
+        size_t o_fc = up(o_prep + sizeof(utd::BodyPrep) * nbb);
+        size_t o_mask = up(o_fc + sizeof(utd::FreqConst) * (size_t)(n_f > 0 ? n_f : 1));
+        size_t o_rec = up(o_mask + (size_t)n_rx * nbb);
+        size_t rec_bytes = utd::path_record_bytes(precision) * (size_t)(2 * (l_enc + 1)) * (size_t)n_rx * nbb;
+        size_t o_flag = up(o_rec + rec_bytes);
+        size_t o_cnt = up(o_flag + (need_flags ? (size_t)n_rx : 0));
+        size_t total = o_cnt + 16 * sizeof(unsigned long long);
+        hipError_t e = hipMallocAsync((void**)&base, total, s);
+        if (e != hipSuccess) return e;
+        prep = (utd::BodyPrep*)(base + o_prep);
+        fc = (utd::FreqConst*)(base + o_fc);
+        mask = (uint8_t*)(base + o_mask);
+        rec = (void*)(base + o_rec);
+        flags = need_flags ? (uint8_t*)(base + o_flag) : nullptr;
+        counters = (unsigned long long*)(base + o_cnt);
+        return hipSuccess;
+    }
+};
+
 int pick_fc(int precision, int64_t n_rx, int n_f) {
-    int fc = precision == 0 ? 8 : 4;
+    int fc = precision == 0 ? 4 : 2;
     while (fc > 1 && (fc / 2 >= n_f || n_rx * ((n_f + fc - 1) / fc) < 256 * 2048)) fc /= 2;
     return fc;
 }
@@ -112,6 +171,26 @@ void utd_default_options(utd_options* opt) {
 }
 
 const char* utd_last_error(void) { return g_err.c_str(); }
+
+void utd_profile_enable(int on) { g_prof_on = on != 0; }
+
+utd_status utd_profile_read(double* ms, int64_t* count) {
+    if (!ms || !count) return fail(UTD_E_ARG, "NULL output");
+    for (int k = 0; k < UTD_K_COUNT; ++k) { ms[k] = 0; count[k] = 0; }
+    utd_status st = UTD_OK;
+    for (auto& r : g_prof) {
+        float t = 0;
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, r.a, r.b);
+        if (e != hipSuccess && st == UTD_OK) st = hip_fail(e, "profile events");
+        ms[r.kernel] += t;
+        count[r.kernel] += 1;
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    g_prof.clear();
+    return st;
+}
 
 utd_status utd_scene_create(const float* tri, int64_t n_tri, utd_scene** out) {
     if (!out) return fail(UTD_E_ARG, "out is NULL");
@@ -167,28 +246,63 @@ utd_status utd_smooth_field(const utd_scene* scene, const utd_bodies* bodies, co
     hipStream_t s = (hipStream_t)stream;
     utd::LaunchParams L = make_params(bodies, tx, n_rx, n_f, opt);
     int nb = L.n_sph + L.n_cyl;
-    // workspace: body constants, path masks, flags (if the caller passed none)
-    size_t prep_bytes = sizeof(utd::BodyPrep) * (size_t)(nb > 0 ? nb : 1);
-    size_t mask_bytes = (size_t)n_rx * (size_t)(nb > 0 ? nb : 1);
-    size_t flag_bytes = rx_flags ? 0 : (size_t)n_rx;
-    size_t off_mask = (prep_bytes + 255) & ~(size_t)255;
-    size_t off_flag = (off_mask + mask_bytes + 255) & ~(size_t)255;
-    size_t total = off_flag + flag_bytes + 256;
-    char* ws = nullptr;
-    e = hipMallocAsync((void**)&ws, total, s);
+    Workspace w;
+    e = w.alloc(nb, n_rx, n_f, opt->l_enc, opt->precision, rx_flags == nullptr, s);
     if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(UTD_E_OOM, "workspace allocation") : hip_fail(e, "hipMallocAsync");
-    utd::BodyPrep* prep = (utd::BodyPrep*)ws;
-    uint8_t* mask = (uint8_t*)(ws + off_mask);
-    uint8_t* flags = rx_flags ? rx_flags : (uint8_t*)(ws + off_flag);
+    uint8_t* flags = rx_flags ? rx_flags : w.flags;
     const float4* nodes = scene ? scene->d_nodes : nullptr;
     const float4* tris = scene ? scene->d_tris : nullptr;
-    e = utd::launch_prep(L, bodies->sph, bodies->cyl, prep, s);
-    if (e == hipSuccess) e = utd::launch_occlude(L, rx, bodies->sph, bodies->cyl, prep, nodes, tris, mask, flags, s);
+    {
+        ProfScope ps(UTD_K_PREP, s);
+        e = utd::launch_prep(L, bodies->sph, bodies->cyl, freqs, w.prep, w.fc, s);
+    }
+    if (e == hipSuccess) {
+        ProfScope ps(UTD_K_OCCLUDE, s);
+        e = utd::launch_paths(L, opt->precision, rx, bodies->sph, bodies->cyl, w.prep, nodes, tris, w.mask, w.rec,
+                              flags, s);
+    }
     int fc = pick_fc(opt->precision, n_rx, n_f);
-    if (e == hipSuccess) e = utd::launch_field(L, opt->precision, fc, rx, freqs, prep, mask, flags, E_out, s);
+    if (e == hipSuccess) {
+        ProfScope ps(UTD_K_FIELD, s);
+        e = utd::launch_field(L, opt->precision, fc, rx, w.fc, w.mask, w.rec, flags, E_out, s);
+    }
+    char* ws = w.base;
     hipError_t e2 = hipFreeAsync(ws, s);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
+    return UTD_OK;
+}
+
+utd_status utd_path_census(const utd_scene* scene, const utd_bodies* bodies, const utd_source* tx, const float* rx,
+                           int64_t n_rx, const utd_options* opt, int64_t* counts, void* stream) {
+    double fdummy = 1e9;
+    utd_status st = check_common(bodies, tx, rx, n_rx, &fdummy, 1, opt);
+    if (st != UTD_OK) return st;
+    if (!counts) return fail(UTD_E_ARG, "counts is NULL");
+    for (int k = 0; k < 10; ++k) counts[k] = 0;
+    if (n_rx == 0) return UTD_OK;
+    hipError_t e = ensure_tables();
+    if (e != hipSuccess) return hip_fail(e, "table upload");
+    hipStream_t s = (hipStream_t)stream;
+    utd::LaunchParams L = make_params(bodies, tx, n_rx, 0, opt);
+    int nb = L.n_sph + L.n_cyl;
+    Workspace w;
+    e = w.alloc(nb, n_rx, 0, opt->l_enc, 0, true, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMallocAsync");
+    char* ws = w.base;
+    unsigned long long host[10] = {0};
+    e = hipMemsetAsync(w.counters, 0, 16 * sizeof(unsigned long long), s);
+    if (e == hipSuccess) e = utd::launch_prep(L, bodies->sph, bodies->cyl, nullptr, w.prep, w.fc, s);
+    if (e == hipSuccess)
+        e = utd::launch_paths(L, 0, rx, bodies->sph, bodies->cyl, w.prep, scene ? scene->d_nodes : nullptr,
+                              scene ? scene->d_tris : nullptr, w.mask, w.rec, w.flags, s);
+    if (e == hipSuccess) e = utd::launch_census(nb > 0 ? (int64_t)nb * n_rx : 0, w.mask, n_rx, w.flags, w.counters, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(host, w.counters, sizeof host, hipMemcpyDeviceToHost, s);
+    hipError_t e2 = hipFreeAsync(ws, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "path census");
+    if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
+    for (int k = 0; k < 10; ++k) counts[k] = (int64_t)host[k];
     return UTD_OK;
 }
 

@@ -50,6 +50,15 @@ struct BodyPrep {
     int pad[2];
 };
 
+// Per-frequency constants (computed once per call): phase revolutions per
+// metre f/c, wavenumber k and k^{1/3}, k^{1/6}, k^{-1/6} in both precisions.
+struct FreqConst {
+    double rev_per_m;
+    double kd, k13d, k16d, km16d;
+    float kf, k13f, k16f, km16f;
+    double pad;
+};
+
 // ---------------------------------------------------------------------------
 // small vector helpers (double)
 // ---------------------------------------------------------------------------

@@ -102,110 +102,86 @@ __device__ __forceinline__ int locate(R x, R lo, R inv_w, int n, R* s) {
     return i;
 }
 
-// Transition function: F(X), F(X)/sqrt(X) and 1 - F(X), u = sqrt(X).
-template <typename R>
-__device__ __forceinline__ void transition(const Tabs<R>& tb, R X, R u, cplx<R>* F, cplx<R>* G, cplx<R>* omF) {
-    using D = TabDims<R>;
-    R v[2], s;
-    if (u <= (R)FT_FA_HI) {
-        int i = locate<R>(u, (R)0, (R)D::NFA / (R)FT_FA_HI, D::NFA, &s);
-        horner2<R>(tb.tf + i * 2 * (D::DEG + 1), s, v);       // A(u)
-        *G = cplx<R>{-2 * v[1], 2 * v[0]};                     // 2j A
-        *F = cplx<R>{-2 * u * v[1], 2 * u * v[0]};             // 2j u A
-        *omF = cplx<R>{(R)1 - F->re, -F->im};
-    } else {
-        R iv = RT<R>::rcp(X);
-        int i = locate<R>(iv, (R)0, (R)D::NFH * (R)(FT_FA_HI * FT_FA_HI), D::NFH, &s);
-        horner2<R>(tb.tf + (D::NFA + i) * 2 * (D::DEG + 1), s, v);   // H(v) = (F - 1) X
-        *omF = cplx<R>{-iv * v[0], -iv * v[1]};
-        *F = cplx<R>{(R)1 - omF->re, -omF->im};
-        R iu = RT<R>::rcp(u);
-        *G = cplx<R>{F->re * iu, F->im * iu};
-    }
-}
-
 // B-type kernels K_s, K_h of one path at one frequency.
 //   creeping (refl = false): K = B_p(xi, X)
 //   reflection (refl = true): K = Rbar_p = -e^{-j xi^3/12} B_p(xi, X)
 // q = sqrt(X)/|xi| = sqrt(k L / 2)/m is passed explicitly (finite at xi = 0).
+// Written without data-dependent branches: the regime and the transition
+// range only select the segment, the local variable and a few operands, so a
+// wavefront whose lanes sit in different regimes stays converged.
 template <typename R>
 __device__ __forceinline__ void fock_kernel(const Tabs<R>& tb, R xi, R X, R q, bool refl,
                                             cplx<R>* Ks, cplx<R>* Kh) {
     using D = TabDims<R>;
     const R e4 = (R)kRs2;                     // e^{-j pi/4} = e4 (1 - j)
+    const R c2 = (R)kInv2SqrtPi;
+
+    // --- transition function: A(u) for u <= FA_HI, H(1/X) beyond -----------
     R u = RT<R>::sqrt_(X);
-    cplx<R> F, G, omF;
-    transition<R>(tb, X, u, &F, &G, &omF);
+    bool big = u > (R)FT_FA_HI;
+    R iX = RT<R>::rcp(big ? X : (R)1);
+    R targ = big ? iX : u;
+    R invw = big ? (R)(D::NFH * FT_FA_HI * FT_FA_HI) : (R)(D::NFA / FT_FA_HI);
+    int nseg = big ? D::NFH : D::NFA;
+    R st;
+    int tseg = (big ? D::NFA : 0) + locate<R>(targ, (R)0, invw, nseg, &st);
+    R v[2];
+    horner2<R>(tb.tf + tseg * 2 * (D::DEG + 1), st, v);
+    // small u: G = F/sqrt(X) = 2j A, F = u G; large u: 1 - F = -H/X, G = F/u
+    R iu = RT<R>::rcp(big ? u : (R)1);
+    R omr = -iX * v[0], omi = -iX * v[1];
+    cplx<R> G, omF;
+    G.re = big ? ((R)1 - omr) * iu : (R)-2 * v[1];
+    G.im = big ? -omi * iu : (R)2 * v[0];
+    omF.re = big ? omr : (R)1 - u * G.re;
+    omF.im = big ? omi : -u * G.im;
 
-    // regime: segment and local variable in the concatenated regime table
-    int seg;
+    // --- regime table ------------------------------------------------------
+    int regime = xi >= (R)FT_PT_HI ? 0 : (xi >= (R)FT_PT_LO ? 1 : 2);
+    R ixi = RT<R>::rcp(xi != (R)0 ? xi : (R)1);
+    R r3 = (R)FT_PT_LO * ixi;
+    R arg = regime == 0 ? (xi < (R)FT_DS_HI ? xi : (R)FT_DS_HI) : (regime == 1 ? xi : r3 * r3 * r3);
+    R rlo = regime == 0 ? (R)FT_PT_HI : (regime == 1 ? (R)FT_PT_LO : (R)0);
+    R rinv = regime == 0 ? (R)(D::NDS / (FT_DS_HI - FT_PT_HI))
+                         : (regime == 1 ? (R)(D::NPT / (FT_PT_HI - FT_PT_LO)) : (R)D::NCL);
+    int rn = regime == 0 ? D::NDS : (regime == 1 ? D::NPT : D::NCL);
+    int rbase = regime == 0 ? D::NPT : (regime == 1 ? 0 : D::NPT + D::NDS);
     R s;
-    int regime;
-    if (xi >= (R)FT_PT_HI) {
-        regime = 0;
-        R x = xi < (R)FT_DS_HI ? xi : (R)FT_DS_HI;
-        seg = D::NPT + locate<R>(x, (R)FT_PT_HI, (R)D::NDS / (R)(FT_DS_HI - FT_PT_HI), D::NDS, &s);
-    } else if (xi >= (R)FT_PT_LO) {
-        regime = 1;
-        seg = locate<R>(xi, (R)FT_PT_LO, (R)D::NPT / (R)(FT_PT_HI - FT_PT_LO), D::NPT, &s);
-    } else {
-        regime = 2;
-        R r = (R)FT_PT_LO * RT<R>::rcp(xi);
-        R t = r * r * r;
-        seg = D::NPT + D::NDS + locate<R>(t, (R)0, (R)D::NCL, D::NCL, &s);
+    int seg = rbase + locate<R>(arg, rlo, rinv, rn, &s);
+    R w4[4];
+    horner4<R>(tb.reg + seg * 4 * (D::DEG + 1), s, w4);
+    cplx<R> ps{w4[0], w4[1]}, ph{w4[2], w4[3]};
+    if (regime == 0 && xi > (R)FT_DS_HI) {
+        // past the table only the first creeping mode survives:
+        // scale the end value by e^{z1 (xi - DS_HI)} (rare)
+        R dx = xi - (R)FT_DS_HI;
+        R es = RT<R>::exp_((R)FT_Z1S_RE * dx), eh = RT<R>::exp_((R)FT_Z1H_RE * dx);
+        cplx<R> rs = expmj<R>(-(R)FT_Z1S_IM * dx), rh = expmj<R>(-(R)FT_Z1H_IM * dx);
+        ps = cmul(ps, cplx<R>{es * rs.re, es * rs.im});
+        ph = cmul(ph, cplx<R>{eh * rh.re, eh * rh.im});
     }
-    R v[4];
-    horner4<R>(tb.reg + seg * 4 * (D::DEG + 1), s, v);
-    cplx<R> ps{v[0], v[1]}, ph{v[2], v[3]};
 
-    if (regime == 0) {
-        // p* + e^{-j pi/4} (1 - F) / (2 sqrt(pi) xi); beyond DS_HI only the
-        // first mode survives and the last segment's value stands in for it
-        R f = (R)kInv2SqrtPi * e4 * RT<R>::rcp(xi);
-        cplx<R> c0{f * (omF.re + omF.im), f * (omF.im - omF.re)};
-        *Ks = cplx<R>{ps.re + c0.re, ps.im + c0.im};
-        *Kh = cplx<R>{ph.re + c0.re, ph.im + c0.im};
-        if (xi > (R)FT_DS_HI) {
-            // scale by the first-mode decay e^{z1 (xi - DS_HI)}
-            R dx = xi - (R)FT_DS_HI;
-            R es = RT<R>::exp_((R)FT_Z1S_RE * dx), eh = RT<R>::exp_((R)FT_Z1H_RE * dx);
-            cplx<R> rs = expmj<R>(-(R)FT_Z1S_IM * dx), rh = expmj<R>(-(R)FT_Z1H_IM * dx);
-            cplx<R> ks = cmul(ps, cplx<R>{es * rs.re, es * rs.im});
-            cplx<R> kh = cmul(ph, cplx<R>{eh * rh.re, eh * rh.im});
-            *Ks = cplx<R>{ks.re + c0.re, ks.im + c0.im};
-            *Kh = cplx<R>{kh.re + c0.re, kh.im + c0.im};
-        }
-        if (refl) {
-            cplx<R> e = expmj<R>(xi * xi * xi * (R)(1.0 / 12));
-            cplx<R> a = cmul(e, *Ks), b = cmul(e, *Kh);
-            *Ks = cplx<R>{-a.re, -a.im};
-            *Kh = cplx<R>{-b.re, -b.im};
-        }
-    } else if (regime == 1) {
-        // Ptilde - sgn e^{-j pi/4} q F/sqrt(X) / (2 sqrt(pi))
-        R sg = refl ? (xi > (R)0 ? (R)1 : (R)-1) : (xi < (R)0 ? (R)-1 : (R)1);
-        R f = sg * q * (R)kInv2SqrtPi * e4;
-        cplx<R> c0{f * (G.re + G.im), f * (G.im - G.re)};
-        cplx<R> bs{ps.re - c0.re, ps.im - c0.im}, bh{ph.re - c0.re, ph.im - c0.im};
-        if (refl) {
-            cplx<R> e = expmj<R>(xi * xi * xi * (R)(1.0 / 12));
-            cplx<R> a = cmul(e, bs), b = cmul(e, bh);
-            *Ks = cplx<R>{-a.re, -a.im};
-            *Kh = cplx<R>{-b.re, -b.im};
-        } else {
-            *Ks = bs;
-            *Kh = bh;
-        }
-    } else {
-        // -c sqrt(-xi)/2 - e^{-j xi^3/12} e^{-j pi/4} (1 - F)/(2 sqrt(pi) xi)
-        R h = (R)0.5 * RT<R>::sqrt_(-xi);
-        R f = (R)kInv2SqrtPi * e4 * RT<R>::rcp(xi);
-        cplx<R> c0{f * (omF.re + omF.im), f * (omF.im - omF.re)};
-        cplx<R> e = expmj<R>(xi * xi * xi * (R)(1.0 / 12));
-        cplx<R> corr = cmul(e, c0);
-        *Ks = cplx<R>{-ps.re * h - corr.re, -ps.im * h - corr.im};
-        *Kh = cplx<R>{-ph.re * h - corr.re, -ph.im * h - corr.im};
-    }
+    // --- combine ------------------------------------------------------------
+    // CW = e^{-j pi/4} coef W:  regime 1: coef = -sgn q/(2 sqrt pi), W = G
+    //                          regimes 0, 2: coef = 1/(2 sqrt(pi) xi), W = 1 - F
+    R sg = refl ? (xi > (R)0 ? (R)1 : (R)-1) : (xi < (R)0 ? (R)-1 : (R)1);
+    R coef = regime == 1 ? -sg * q * c2 : c2 * ixi;
+    cplx<R> W = regime == 1 ? G : omF;
+    R f = coef * e4;
+    cplx<R> CW{f * (W.re + W.im), f * (W.im - W.re)};
+    // creeping: K = P + CW
+    // reflection / deep lit: K = -(alpha P + e CW), e = e^{-j xi^3/12},
+    //   alpha = e (regimes 0, 1) or sqrt(-xi)/2 (regime 2, P = c)
+    cplx<R> e = expmj<R>(xi * xi * xi * (R)(1.0 / 12));
+    bool lit = refl || regime == 2;
+    R h = (R)0.5 * RT<R>::sqrt_(regime == 2 ? -xi : (R)0);
+    cplx<R> alpha = regime == 2 ? cplx<R>{h, (R)0} : e;
+    cplx<R> eCW = cmul(e, CW);
+    cplx<R> as = cmul(alpha, ps), ah = cmul(alpha, ph);
+    Ks->re = lit ? -(as.re + eCW.re) : ps.re + CW.re;
+    Ks->im = lit ? -(as.im + eCW.im) : ps.im + CW.im;
+    Kh->re = lit ? -(ah.re + eCW.re) : ph.re + CW.re;
+    Kh->im = lit ? -(ah.im + eCW.im) : ph.im + CW.im;
 }
 
 }  // namespace utd

@@ -1,13 +1,18 @@
 // Ray geometry of the smooth-surface UTD paths on spheres and vertical
-// cylinders (device code).  Lengths, angles and the reflection-point root
-// solve are carried in FP64; the frequency-independent path constants handed
-// to the frequency loop are rounded to the field precision R.
+// cylinders (device code).
 //
 // Creeping path (Eq. (4), Sec. III-B): tangent from the source T to the
 // attachment point Q1, surface geodesic Q1 -> Q2 of length t, tangent from
-// the detachment point Q2 to the receiver R.
-// Reflection (Eq. (3)): the specular point Q_R on the arc seen from both T
-// and R.
+// the detachment point Q2 to the receiver R.  Reflection (Eq. (3)): the
+// specular point Q_R on the arc seen from both T and R.
+//
+// Precision: everything that enters the phase k (s^i + t + s^d) -- distances,
+// tangent lengths and the arc angle phi -- is FP64.  Angles come from one
+// FP64 atan2 per (receiver, body): the arcs of the two sides add up to a
+// known total, and the cosines/sines of the detachment angles are algebraic
+// in the distances.  Frames, spreading and Fock arguments are computed in
+// the field precision R.  The reflection point is solved once (FP64
+// safeguarded Newton) by the visibility pass and its angle is reused.
 #pragma once
 
 #include "utd_device.h"
@@ -15,9 +20,9 @@
 namespace utd {
 
 // Everything the frequency loop needs about one path.  The per-frequency
-// coefficient is  K_p(xi, X) with xi = mhat k^{1/3} phi_e, X = k Lh phi_e^2,
+// coefficient is K_p(xi, X) with xi = mhat k^{1/3} phi_e, X = k Lh phi_e^2,
 // q = k^{1/6} qhat, and the contribution is
-//   e^{-j 2pi rev} k^{-1/6} (a_s K_s v_s + a_h K_h v_h),  rev = k s_tot / 2pi + rev0.
+//   e^{-j 2pi rev} k^{-1/6} (a_s K_s v_s + a_h K_h v_h),  rev = (f/c) s_tot + rev0.
 template <typename R> struct PathEval {
     double s_tot;     // total path length s^i + t + s^d (or s^i + s^r)
     double rev0;      // extra phase in revolutions (caustics: -N_c/4)
@@ -77,44 +82,76 @@ __device__ __forceinline__ bool inside_body(const BodyPrep& b, d3 P) {
     return x * x + y * y <= b.a * b.a && P.z >= b.z0 && P.z <= b.z0 + b.h;
 }
 
-// Receiver-side quantities of one body, shared by its paths.
+// Receiver-side quantities of one body, shared by all of its paths.
+//   sphere:   R at polar angle theta_R about e_T in the T-C-R plane, e_perp the
+//             in-plane unit normal to e_T towards R; cos/sin of the two
+//             detachment polar angles th2_+ = theta_R - gR, th2_- = 2pi - theta_R - gR.
+//   cylinder: everything in projection; u2_+ / u2_- the unit directions of the
+//             detachment points (R's tangent points) from the axis.
+// phi_p is the arc of side + (phi_m = arc_sum - phi_p) with ell = 0.
 struct RxGeo {
-    // sphere: along = e_T.(R-C), wn = |perp|, e_perp; cylinder: xy offsets
-    double dR, sD0, gR;      // distance (to centre / axis), tangent length, half-angle
-    double thR;              // sphere: polar angle of R about e_T
-    double dphi_plus;        // cylinder: CCW angle from T to R about the axis
-    double along, wn;
-    d3 eperp;
-    int ok;                  // receiver outside the body's sphere / circle
+    double dR, sD0;       // distance to centre / axis, tangent length
+    double phi_p, phi_m;  // arcs of the two sides
+    double wn;            // sphere: distance of R from the source axis
+    double along;         // sphere: component of R - C along e_T
+    double c2p, s2p, c2m, s2m;   // sphere: cos/sin of th2_+/-; cylinder: u2_+/- (x, y)
+    d3 eperp;             // sphere only
+    int ok;               // R outside the body's sphere / circle
 };
 
 __device__ __forceinline__ RxGeo rx_geo(const BodyPrep& b, d3 R) {
     RxGeo g;
+    double a = b.a;
+    double cgT = a / b.dT, sgT = b.sI0 / b.dT;
     if (b.kind == 0) {
         d3 C = mk(b.c[0], b.c[1], b.c[2]);
         d3 eT = mk(b.eT[0], b.eT[1], b.eT[2]);
         d3 v = R - C;
-        g.dR = norm(v);
-        g.along = dot(v, eT);
-        d3 w = v - g.along * eT;
+        double d2 = dot(v, v);
+        double along = dot(v, eT);
+        g.along = along;
+        d3 w = v - along * eT;
         g.wn = norm(w);
         g.eperp = g.wn > 1e-300 ? (1.0 / g.wn) * w : any_perp(eT);
-        g.thR = atan2(g.wn, g.along);
-        g.dphi_plus = 0;
+        g.dR = sqrt(d2);
+        g.ok = g.dR > a;
+        g.sD0 = g.ok ? sqrt((g.dR - a) * (g.dR + a)) : 0.0;
+        double id2 = 1.0 / d2;
+        // th2_+ = theta_R - gR ; th2_- = 2 pi - theta_R - gR
+        g.c2p = (along * a + g.wn * g.sD0) * id2;
+        g.s2p = (g.wn * a - along * g.sD0) * id2;
+        g.c2m = (along * a - g.wn * g.sD0) * id2;
+        g.s2m = -(g.wn * a + along * g.sD0) * id2;
+        // phi_+ = th2_+ - gT in (-pi, pi)
+        double cp = g.c2p * cgT + g.s2p * sgT;
+        double sp = g.s2p * cgT - g.c2p * sgT;
+        g.phi_p = atan2(sp, cp);
+        double gR = atan2(g.sD0, a);
+        g.phi_m = (kTwoPi - 2.0 * b.gT - 2.0 * gR) - g.phi_p;
     } else {
         double x = R.x - b.c[0], y = R.y - b.c[1];
-        g.dR = sqrt(x * x + y * y);
-        double aR = atan2(y, x);
-        double d = aR - b.aT;
-        d = d - kTwoPi * floor(d * kInvTwoPi);
-        if (d >= kTwoPi) d -= kTwoPi;
-        g.dphi_plus = d;
-        g.thR = 0; g.along = 0; g.wn = 0;
+        double r2 = x * x + y * y;
+        g.dR = sqrt(r2);
+        g.ok = g.dR > a;
+        g.sD0 = g.ok ? sqrt((g.dR - a) * (g.dR + a)) : 0.0;
+        g.wn = 0;
+        g.along = 0;
         g.eperp = mk(0, 0, 0);
+        double ir = 1.0 / r2;
+        // R's tangent points: u_R rotated by -gR (side +) and +gR (side -)
+        double cg = a, sg = g.sD0;     // times 1/dR each, folded into ir
+        g.c2p = (x * cg + y * sg) * ir;
+        g.s2p = (y * cg - x * sg) * ir;
+        g.c2m = (x * cg - y * sg) * ir;
+        g.s2m = (y * cg + x * sg) * ir;
+        // T's tangent point of side +: u_T rotated by +gT
+        double u1x = b.eT[0] * cgT - b.eT[1] * sgT, u1y = b.eT[1] * cgT + b.eT[0] * sgT;
+        double p = atan2(u1x * g.s2p - u1y * g.c2p, u1x * g.c2p + u1y * g.s2p);
+        double gR = atan2(g.sD0, a);
+        double G = b.gT + gR;
+        g.phi_p = p >= -G ? p : p + kTwoPi;
+        g.phi_m = (kTwoPi - 2.0 * G) - g.phi_p;
     }
-    g.ok = g.dR > b.a;
-    g.sD0 = g.ok ? sqrt((g.dR - b.a) * (g.dR + b.a)) : 0.0;
-    g.gR = atan2(g.sD0, b.a);
     return g;
 }
 
@@ -123,58 +160,61 @@ __device__ __forceinline__ RxGeo rx_geo(const BodyPrep& b, d3 R) {
 // ---------------------------------------------------------------------------
 
 // Sphere, side sgn = +1 (towards R) or -1 (far side), ell extra turns.
-// Geodesic: great circle in the T-C-R plane, arc phi = theta_R - gT - gR
-// (side +) or 2 pi - theta_R - gT - gR (side -), plus 2 pi ell; exists when
-// phi >= 0.  Spreading modulus sqrt(a sin gT / (s^d |rho_perp|)) with
-// |rho_perp| = |R - axis| = wn; one +pi/2 per caustic: floor(theta2/pi)
-// surface poles plus one axis crossing when sgn differs from sign(sin theta2).
+// Geodesic: great circle in the T-C-R plane; exists when phi >= 0.
+// Spreading modulus sqrt(a sin gT / (s^d |rho_perp|)) with |rho_perp| = wn,
+// the distance of R from the source axis; one +pi/2 per caustic:
+// floor(theta2/pi) surface poles plus one axis crossing when sgn differs from
+// the sign of sin(theta2).
 template <typename R>
 __device__ __forceinline__ bool sphere_creep(const BodyPrep& b, const RxGeo& g, d3 Rp, const LaunchParams& L,
                                              int sgn, int ell, bool* caustic, PathEval<R>* pe, PathPts* pts) {
-    double phi = (sgn > 0 ? g.thR : kTwoPi - g.thR) - b.gT - g.gR + kTwoPi * ell;
+    double phi = (sgn > 0 ? g.phi_p : g.phi_m) + kTwoPi * ell;
     *caustic = false;
     if (!(b.ok && g.ok) || phi < 0) return false;
     if (g.wn < L.caustic_guard) { *caustic = true; return false; }
     double a = b.a;
-    d3 C = mk(b.c[0], b.c[1], b.c[2]);
+    double cg = a / b.dT, sg = b.sI0 / b.dT;
+    double c2 = sgn > 0 ? g.c2p : g.c2m, s2 = sgn > 0 ? g.s2p : g.s2m;
     d3 eT = mk(b.eT[0], b.eT[1], b.eT[2]);
     d3 ep = (double)sgn * g.eperp;
-    double cg = a / b.dT, sg = b.sI0 / b.dT;
-    double th2 = b.gT + phi;
-    double s2, c2;
-    sincos(th2, &s2, &c2);
-    d3 n1 = cg * eT + sg * ep;
-    d3 t1 = (-sg) * eT + cg * ep;
-    d3 n2 = c2 * eT + s2 * ep;
-    d3 bb = cross(t1, n1);
     if (pts) {
+        d3 C = mk(b.c[0], b.c[1], b.c[2]);
         pts->P0 = mk(L.T[0], L.T[1], L.T[2]);
-        pts->P1 = C + a * n1;
-        pts->P2 = C + a * n2;
+        pts->P1 = C + a * (cg * eT + sg * ep);
+        pts->P2 = C + a * (c2 * eT + s2 * ep);
         pts->P3 = Rp;
     }
     if (pe) {
-        double np = floor(th2 * (1.0 / kPi));
-        int npi = (int)np;
+        double th2 = b.gT + phi;
+        int npi = (int)floor(th2 * (1.0 / kPi));
         bool s2pos = (npi & 1) == 0;
         int Nc = npi + ((sgn > 0) != s2pos ? 1 : 0);
         double sI = b.sI0, sD = g.sD0;
-        double Smod = sqrt(a * sg / (sD * g.wn));
-        double mhat = cbrt(0.5 * a);
-        double Ld = sI * sD / (sI + sD);
-        d3 p = mk(L.p[0], L.p[1], L.p[2]);
-        double A = L.amp * Smod / sI;
-        double P0 = -1.4142135623730951 * mhat;
         pe->s_tot = sI + a * phi + sD;
         pe->rev0 = -0.25 * Nc;
+        // frames in precision R: n1 = cg eT + sg ep, t1 = -sg eT + cg ep,
+        // b = t1 x n1 = -(eT x ep), n2 = c2 eT + s2 ep
+        R eTx = (R)eT.x, eTy = (R)eT.y, eTz = (R)eT.z;
+        R epx = (R)ep.x, epy = (R)ep.y, epz = (R)ep.z;
+        R bx = -(eTy * epz - eTz * epy), by = -(eTz * epx - eTx * epz), bz = -(eTx * epy - eTy * epx);
+        R cgR = (R)cg, sgR = (R)sg, c2R = (R)c2, s2R = (R)s2;
+        R n1x = cgR * eTx + sgR * epx, n1y = cgR * eTy + sgR * epy, n1z = cgR * eTz + sgR * epz;
+        R px = (R)L.p[0], py = (R)L.p[1], pz = (R)L.p[2];
+        R sIR = (R)sI, sDR = (R)sD, aR = (R)a;
+        R Ld = sIR * sDR / (sIR + sDR);
+        R mhat = RT<R>::cbrt_((R)0.5 * aR);
+        R Smod = RT<R>::sqrt_(aR * sgR / (sDR * (R)g.wn));
+        R A = (R)L.amp * Smod / sIR * ((R)-1.4142135623730951 * mhat);
         pe->phi_e = (R)phi;
-        pe->mhat = (R)mhat;
-        pe->Lh = (R)(0.5 * Ld);
-        pe->qhat = (R)(sqrt(0.5 * Ld) / mhat);
-        pe->a_s = (R)(A * dot(p, bb) * P0);
-        pe->a_h = (R)(A * dot(p, n1) * P0);
-        pe->vs[0] = (R)bb.x; pe->vs[1] = (R)bb.y; pe->vs[2] = (R)bb.z;
-        pe->vh[0] = (R)n2.x; pe->vh[1] = (R)n2.y; pe->vh[2] = (R)n2.z;
+        pe->mhat = mhat;
+        pe->Lh = (R)0.5 * Ld;
+        pe->qhat = RT<R>::sqrt_((R)0.5 * Ld) / mhat;
+        pe->a_s = A * (px * bx + py * by + pz * bz);
+        pe->a_h = A * (px * n1x + py * n1y + pz * n1z);
+        pe->vs[0] = bx; pe->vs[1] = by; pe->vs[2] = bz;
+        pe->vh[0] = c2R * eTx + s2R * epx;
+        pe->vh[1] = c2R * eTy + s2R * epy;
+        pe->vh[2] = c2R * eTz + s2R * epz;
         pe->refl = 0;
     }
     return true;
@@ -188,22 +228,19 @@ template <typename R>
 __device__ __forceinline__ bool cyl_creep(const BodyPrep& b, const RxGeo& g, d3 Rp, const LaunchParams& L,
                                           int sgn, int ell, PathEval<R>* pe, PathPts* pts) {
     if (!(b.ok && g.ok)) return false;
-    double dphi = sgn > 0 ? g.dphi_plus : kTwoPi - g.dphi_plus;
-    double phi = dphi - b.gT - g.gR + kTwoPi * ell;
+    double phi = (sgn > 0 ? g.phi_p : g.phi_m) + kTwoPi * ell;
     if (phi < 0) return false;
     double a = b.a;
     double dT = b.sI0, dR = g.sD0;
     double L2 = dT + a * phi + dR;
     double dz = Rp.z - L.T[2];
-    double Stot = sqrt(L2 * L2 + dz * dz);
     double zQ1 = L.T[2] + dz * dT / L2;
     double zQ2 = L.T[2] + dz * (dT + a * phi) / L2;
     if (zQ1 < b.z0 || zQ1 > b.z0 + b.h || zQ2 < b.z0 || zQ2 > b.z0 + b.h) return false;
-    double al1 = b.aT + sgn * b.gT;
-    double al2 = al1 + sgn * phi;
-    double s1, c1, s2, c2;
-    sincos(al1, &s1, &c1);
-    sincos(al2, &s2, &c2);
+    double cgT = a / b.dT, sgT = b.sI0 / b.dT;
+    // attachment direction: u_T rotated by sgn*gT; detachment: u2 of this side
+    double c1 = b.eT[0] * cgT - sgn * b.eT[1] * sgT, s1 = b.eT[1] * cgT + sgn * b.eT[0] * sgT;
+    double c2 = sgn > 0 ? g.c2p : g.c2m, s2 = sgn > 0 ? g.s2p : g.s2m;
     if (pts) {
         pts->P0 = mk(L.T[0], L.T[1], L.T[2]);
         pts->P1 = mk(b.c[0] + a * c1, b.c[1] + a * s1, zQ1);
@@ -211,30 +248,32 @@ __device__ __forceinline__ bool cyl_creep(const BodyPrep& b, const RxGeo& g, d3 
         pts->P3 = Rp;
     }
     if (pe) {
-        double cosd = L2 / Stot, sind = dz / Stot;
-        double sI = dT / cosd, t = a * phi / cosd, sD = dR / cosd;
-        d3 n1 = mk(c1, s1, 0), n2 = mk(c2, s2, 0);
-        d3 t1 = mk(-sgn * cosd * s1, sgn * cosd * c1, sind);
-        d3 t2 = mk(-sgn * cosd * s2, sgn * cosd * c2, sind);
-        d3 b1 = cross(t1, n1), b2 = cross(t2, n2);
-        double rho_g = a / (cosd * cosd);
-        double mhat = cbrt(0.5 * rho_g);
-        double Ld = sI * sD / (sI + sD);
-        double Smod = sqrt(sI / (sD * Stot));
-        d3 p = mk(L.p[0], L.p[1], L.p[2]);
-        double A = L.amp * Smod / sI;
-        double P0 = -1.4142135623730951 * mhat;
+        double Stot = sqrt(L2 * L2 + dz * dz);
         pe->s_tot = Stot;
         pe->rev0 = 0.0;
-        pe->phi_e = (R)(phi * cosd);
-        pe->mhat = (R)mhat;
-        pe->Lh = (R)(0.5 * Ld);
-        pe->qhat = (R)(sqrt(0.5 * Ld) / mhat);
-        pe->a_s = (R)(A * dot(p, b1) * P0);
-        pe->a_h = (R)(A * dot(p, n1) * P0);
-        pe->vs[0] = (R)b2.x; pe->vs[1] = (R)b2.y; pe->vs[2] = (R)b2.z;
-        pe->vh[0] = (R)n2.x; pe->vh[1] = (R)n2.y; pe->vh[2] = (R)n2.z;
+        R cosd = (R)(L2 / Stot), sind = (R)(dz / Stot);
+        R idc = (R)1 / cosd;
+        R sI = (R)dT * idc, t = (R)(a * phi) * idc, sD = (R)dR * idc;
+        R c1R = (R)c1, s1R = (R)s1, c2R = (R)c2, s2R = (R)s2;
+        R sg = (R)sgn;
+        // t_i = cosd * sgn (-s_i, c_i, 0) + sind z;  b_i = t_i x n_i, n_i = (c_i, s_i, 0)
+        R b1x = -sind * s1R, b1y = sind * c1R, b1z = -cosd * sg;
+        R b2x = -sind * s2R, b2y = sind * c2R, b2z = b1z;
+        R rho_g = (R)a * idc * idc;
+        R mhat = RT<R>::cbrt_((R)0.5 * rho_g);
+        R Ld = sI * sD / (sI + sD);
+        R Smod = RT<R>::sqrt_(sI / (sD * (R)Stot));
+        R px = (R)L.p[0], py = (R)L.p[1], pz = (R)L.p[2];
+        R A = (R)L.amp * Smod / sI * ((R)-1.4142135623730951 * mhat);
         (void)t;
+        pe->phi_e = (R)phi * cosd;
+        pe->mhat = mhat;
+        pe->Lh = (R)0.5 * Ld;
+        pe->qhat = RT<R>::sqrt_((R)0.5 * Ld) / mhat;
+        pe->a_s = A * (px * b1x + py * b1y + pz * b1z);
+        pe->a_h = A * (px * c1R + py * s1R);
+        pe->vs[0] = b2x; pe->vs[1] = b2y; pe->vs[2] = b2z;
+        pe->vh[0] = c2R; pe->vh[1] = s2R; pe->vh[2] = (R)0;
         pe->refl = 0;
     }
     return true;
@@ -277,80 +316,30 @@ __device__ __forceinline__ double alhazen(double a, double p1x, double p1y, doub
     return th;
 }
 
-// Shared reflection bookkeeping; caustic distances written as
-// 1/rho_1 = 1/s^i + f1/cos(th_i), 1/rho_2 = 1/s^i + f2 cos(th_i)
-// (sphere: f1 = f2 = 2/a; cylinder: f1 = 2 cos^2(beta)/a, f2 = 0).
-template <typename R>
-__device__ __forceinline__ void refl_common(d3 T, d3 Q, d3 n, d3 Rp, double rho_g, double f1, double f2,
-                                            const LaunchParams& L, PathEval<R>* pe) {
-    d3 vi = Q - T, vr = Rp - Q;
-    double sI = norm(vi), sR = norm(vr);
-    d3 si = (1.0 / sI) * vi, sr = (1.0 / sR) * vr;
-    double ci = -dot(si, n);
-    ci = ci < 0 ? 0 : (ci > 1 ? 1 : ci);
-    double r1c = 1.0 / (ci / sI + f1);
-    double rho1 = r1c * ci;
-    double rho2 = 1.0 / (1.0 / sI + f2 * ci);
-    d3 cr = cross(si, n);
-    double crn = norm(cr);
-    d3 eperp = crn > 1e-12 ? (1.0 / crn) * cr : any_perp(n);
-    d3 epi = cross(eperp, si), epr = cross(eperp, sr);
-    double mhat = cbrt(0.5 * rho_g);
-    double Lr = sI * sR / (sI + sR);
-    double P0 = 2.0 * sqrt(r1c / (2.0 * mhat)) * sqrt(rho2 / ((rho1 + sR) * (rho2 + sR)));
-    d3 p = mk(L.p[0], L.p[1], L.p[2]);
-    double A = L.amp / sI * P0;
-    pe->s_tot = sI + sR;
-    pe->rev0 = 0.0;
-    pe->phi_e = (R)(-2.0 * ci);
-    pe->mhat = (R)mhat;
-    pe->Lh = (R)(0.5 * Lr);
-    pe->qhat = (R)(sqrt(0.5 * Lr) / mhat);
-    pe->a_s = (R)(A * dot(p, eperp));
-    pe->a_h = (R)(A * dot(p, epi));
-    pe->vs[0] = (R)eperp.x; pe->vs[1] = (R)eperp.y; pe->vs[2] = (R)eperp.z;
-    pe->vh[0] = (R)epr.x; pe->vh[1] = (R)epr.y; pe->vh[2] = (R)epr.z;
-    pe->refl = 1;
-}
-
-// Sphere: lit when theta_R < gT + gR; solve in the T-C-R plane.
-template <typename R>
-__device__ __forceinline__ bool sphere_refl(const BodyPrep& b, const RxGeo& g, d3 Rp, const LaunchParams& L,
-                                            PathEval<R>* pe, PathPts* pts) {
+// Reflection point for a lit receiver: the angle parameter (sphere: polar
+// angle in the T-C-R plane; cylinder: azimuth) or a negative status if the
+// receiver is not lit by this body or the point is off the lateral surface.
+__device__ __forceinline__ bool refl_angle(const BodyPrep& b, const RxGeo& g, d3 Rp, const LaunchParams& L,
+                                           double* th_out) {
     if (!(b.ok && g.ok)) return false;
-    if (!(g.thR - b.gT - g.gR < 0)) return false;
-    double th = alhazen(b.a, b.dT, 0.0, g.along, g.wn, g.thR - g.gR, b.gT);
-    double s, c;
-    sincos(th, &s, &c);
-    d3 C = mk(b.c[0], b.c[1], b.c[2]);
-    d3 eT = mk(b.eT[0], b.eT[1], b.eT[2]);
-    d3 n = c * eT + s * g.eperp;
-    d3 Q = C + b.a * n;
-    d3 T = mk(L.T[0], L.T[1], L.T[2]);
-    if (pts) { pts->P0 = T; pts->P1 = Q; pts->P2 = Q; pts->P3 = Rp; }
-    if (pe) refl_common<R>(T, Q, n, Rp, b.a, 2.0 / b.a, 2.0 / b.a, L, pe);
-    return true;
-}
-
-// Cylinder: lit on the side whose arc is negative; 2-D Alhazen in projection,
-// reflection height by proportional split of dz; rho_g = a / cos^2(delta_R).
-template <typename R>
-__device__ __forceinline__ bool cyl_refl(const BodyPrep& b, const RxGeo& g, d3 Rp, const LaunchParams& L,
-                                         PathEval<R>* pe, PathPts* pts) {
-    if (!(b.ok && g.ok)) return false;
-    double php = g.dphi_plus - b.gT - g.gR;
-    double phm = (kTwoPi - g.dphi_plus) - b.gT - g.gR;
+    double a = b.a;
+    if (b.kind == 0) {
+        if (!(g.phi_p < 0)) return false;
+        // T at (dT, 0), R at (along, wn) in the plane basis; the arc seen
+        // from both runs from R's tangent point (thR - gR = phi_+ + gT) to T's (gT)
+        *th_out = alhazen(a, b.dT, 0.0, g.along, g.wn, g.phi_p + b.gT, b.gT);
+        return true;
+    }
     double lo, hi;
-    if (php < 0) {
-        lo = b.aT + g.dphi_plus - g.gR;
+    if (g.phi_p < 0) {
+        lo = b.aT + g.phi_p + b.gT;      // = aT + dphi_+ - gR
         hi = b.aT + b.gT;
-    } else if (phm < 0) {
+    } else if (g.phi_m < 0) {
         lo = b.aT - b.gT;
-        hi = b.aT - (kTwoPi - g.dphi_plus) + g.gR;
+        hi = b.aT - g.phi_m - b.gT;      // = aT - dphi_- + gR
     } else {
         return false;
     }
-    double a = b.a;
     double tx = L.T[0] - b.c[0], ty = L.T[1] - b.c[1];
     double rx = Rp.x - b.c[0], ry = Rp.y - b.c[1];
     double al = alhazen(a, tx, ty, rx, ry, lo, hi);
@@ -359,28 +348,100 @@ __device__ __forceinline__ bool cyl_refl(const BodyPrep& b, const RxGeo& g, d3 R
     double qx = a * c, qy = a * s;
     double lt = sqrt((qx - tx) * (qx - tx) + (qy - ty) * (qy - ty));
     double lr = sqrt((qx - rx) * (qx - rx) + (qy - ry) * (qy - ry));
-    double dz = Rp.z - L.T[2];
-    double zQ = L.T[2] + dz * lt / (lt + lr);
+    double zQ = L.T[2] + (Rp.z - L.T[2]) * lt / (lt + lr);
     if (zQ < b.z0 || zQ > b.z0 + b.h) return false;
-    d3 T = mk(L.T[0], L.T[1], L.T[2]);
-    d3 Q = mk(b.c[0] + qx, b.c[1] + qy, zQ);
-    d3 n = mk(c, s, 0);
-    if (pts) { pts->P0 = T; pts->P1 = Q; pts->P2 = Q; pts->P3 = Rp; }
-    if (pe) {
-        d3 vi = Q - T;
-        double sI = norm(vi);
-        d3 si = (1.0 / sI) * vi;
-        d3 circ = mk(-s, c, 0);
-        double sn = dot(si, n);
-        d3 tang = si - sn * n;
-        double tn2 = dot(tang, tang);
-        double tc = dot(tang, circ);
-        double cos2d = tn2 > 0 ? tc * tc / tn2 : 1.0;
-        if (cos2d < 1e-12) cos2d = 1e-12;
-        double cos2b = 1.0 - si.z * si.z;
-        refl_common<R>(T, Q, n, Rp, a / cos2d, 2.0 * cos2b / a, 0.0, L, pe);
-    }
+    *th_out = al;
     return true;
+}
+
+// Reflection point and its normal from the stored angle.
+__device__ __forceinline__ void refl_point(const BodyPrep& b, const RxGeo& g, d3 Rp, const LaunchParams& L,
+                                           double th, d3* Q, d3* n) {
+    double s, c;
+    sincos(th, &s, &c);
+    if (b.kind == 0) {
+        d3 eT = mk(b.eT[0], b.eT[1], b.eT[2]);
+        *n = c * eT + s * g.eperp;
+        *Q = mk(b.c[0], b.c[1], b.c[2]) + b.a * (*n);
+    } else {
+        double a = b.a;
+        double tx = L.T[0] - b.c[0], ty = L.T[1] - b.c[1];
+        double rx = Rp.x - b.c[0], ry = Rp.y - b.c[1];
+        double qx = a * c, qy = a * s;
+        double lt = sqrt((qx - tx) * (qx - tx) + (qy - ty) * (qy - ty));
+        double lr = sqrt((qx - rx) * (qx - rx) + (qy - ry) * (qy - ry));
+        double zQ = L.T[2] + (Rp.z - L.T[2]) * lt / (lt + lr);
+        *Q = mk(b.c[0] + qx, b.c[1] + qy, zQ);
+        *n = mk(c, s, 0);
+    }
+}
+
+// Reflected-field constants.  Caustic distances written as
+// 1/rho_1 = 1/s^i + f1/cos(th_i), 1/rho_2 = 1/s^i + f2 cos(th_i)
+// (sphere: f1 = f2 = 2/a, rho_g = a; cylinder: f1 = 2 cos^2(beta)/a, f2 = 0,
+// rho_g = a / cos^2(delta_R)).
+template <typename R>
+__device__ __forceinline__ void refl_eval(const BodyPrep& b, d3 Q, d3 n, d3 Rp, const LaunchParams& L,
+                                          PathEval<R>* pe) {
+    d3 T = mk(L.T[0], L.T[1], L.T[2]);
+    d3 vi = Q - T, vr = Rp - Q;
+    double sI = norm(vi), sR = norm(vr);
+    pe->s_tot = sI + sR;
+    pe->rev0 = 0.0;
+    R isI = (R)(1.0 / sI), isR = (R)(1.0 / sR);
+    R six = (R)vi.x * isI, siy = (R)vi.y * isI, siz = (R)vi.z * isI;
+    R srx = (R)vr.x * isR, sry = (R)vr.y * isR, srz = (R)vr.z * isR;
+    R nx = (R)n.x, ny = (R)n.y, nz = (R)n.z;
+    R ci = -(six * nx + siy * ny + siz * nz);
+    ci = ci < (R)0 ? (R)0 : (ci > (R)1 ? (R)1 : ci);
+    R a = (R)b.a;
+    R rho_g, f1, f2;
+    if (b.kind == 0) {
+        rho_g = a;
+        f1 = (R)2 / a;
+        f2 = f1;
+    } else {
+        // circumferential unit (-n_y, n_x, 0); trace of the incidence plane
+        R sn = six * nx + siy * ny + siz * nz;
+        R tgx = six - sn * nx, tgy = siy - sn * ny, tgz = siz - sn * nz;
+        R tn2 = tgx * tgx + tgy * tgy + tgz * tgz;
+        R tc = -tgx * ny + tgy * nx;
+        R cos2d = tn2 > (R)0 ? tc * tc / tn2 : (R)1;
+        cos2d = cos2d < (R)1e-12 ? (R)1e-12 : cos2d;
+        rho_g = a / cos2d;
+        f1 = (R)2 * ((R)1 - siz * siz) / a;
+        f2 = (R)0;
+    }
+    R sIR = (R)sI, sRR = (R)sR;
+    R r1c = (R)1 / (ci / sIR + f1);
+    R rho1 = r1c * ci;
+    R rho2 = (R)1 / ((R)1 / sIR + f2 * ci);
+    // e_perp = s_i x n / |.|, e_par^i = e_perp x s_i, e_par^r = e_perp x s_r
+    R cx = siy * nz - siz * ny, cy = siz * nx - six * nz, cz = six * ny - siy * nx;
+    R cn = RT<R>::sqrt_(cx * cx + cy * cy + cz * cz);
+    if (cn > (R)1e-6) {
+        R ic = (R)1 / cn;
+        cx *= ic; cy *= ic; cz *= ic;
+    } else {
+        d3 ap = any_perp(n);
+        cx = (R)ap.x; cy = (R)ap.y; cz = (R)ap.z;
+    }
+    R pix = cy * siz - cz * siy, piy = cz * six - cx * siz, piz = cx * siy - cy * six;
+    R prx = cy * srz - cz * sry, pry = cz * srx - cx * srz, prz = cx * sry - cy * srx;
+    R mhat = RT<R>::cbrt_((R)0.5 * rho_g);
+    R Lr = sIR * sRR / (sIR + sRR);
+    R P0 = (R)2 * RT<R>::sqrt_(r1c / ((R)2 * mhat)) * RT<R>::sqrt_(rho2 / ((rho1 + sRR) * (rho2 + sRR)));
+    R px = (R)L.p[0], py = (R)L.p[1], pz = (R)L.p[2];
+    R A = (R)L.amp * isI * P0;
+    pe->phi_e = (R)-2 * ci;
+    pe->mhat = mhat;
+    pe->Lh = (R)0.5 * Lr;
+    pe->qhat = RT<R>::sqrt_((R)0.5 * Lr) / mhat;
+    pe->a_s = A * (px * cx + py * cy + pz * cz);
+    pe->a_h = A * (px * pix + py * piy + pz * piz);
+    pe->vs[0] = cx; pe->vs[1] = cy; pe->vs[2] = cz;
+    pe->vh[0] = prx; pe->vh[1] = pry; pe->vh[2] = prz;
+    pe->refl = 1;
 }
 
 }  // namespace utd

@@ -9,12 +9,17 @@
 namespace utd {
 
 hipError_t pack_tables(hipStream_t s);
-hipError_t launch_prep(const LaunchParams& L, const float* sph, const float* cyl, BodyPrep* prep, hipStream_t s);
-hipError_t launch_occlude(const LaunchParams& L, const float* rx, const float* sph, const float* cyl,
-                          const BodyPrep* prep, const float4* nodes, const float4* tris, uint8_t* mask,
-                          uint8_t* flags, hipStream_t s);
-hipError_t launch_field(const LaunchParams& L, int precision, int fc, const float* rx, const double* freqs,
-                        const BodyPrep* prep, const uint8_t* mask, uint8_t* flags, void* E, hipStream_t s);
+hipError_t launch_prep(const LaunchParams& L, const float* sph, const float* cyl, const double* freqs,
+                       BodyPrep* prep, FreqConst* fc, hipStream_t s);
+hipError_t launch_paths(const LaunchParams& L, int precision, const float* rx, const float* sph, const float* cyl,
+                        const BodyPrep* prep, const float4* nodes, const float4* tris, uint8_t* mask, void* rec,
+                        uint8_t* flags, hipStream_t s);
+size_t path_record_bytes(int precision);
+hipError_t launch_field(const LaunchParams& L, int precision, int fc, const float* rx, const FreqConst* fcs,
+                        const uint8_t* mask, const void* rec, uint8_t* flags, void* E, hipStream_t s);
+
+hipError_t launch_census(int64_t n_mask, const uint8_t* mask, int64_t n_rx, const uint8_t* flags,
+                         unsigned long long* counts, hipStream_t s);
 
 // host BVH over a triangle soup (bvh.cpp)
 struct HostBvh {

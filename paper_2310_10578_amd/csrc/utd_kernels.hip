@@ -1,16 +1,16 @@
 // HIP kernels of the smooth-surface UTD field evaluation (gfx950).
 //
 //   k_prep     per body, source-dependent constants (FP64)
-//   k_occlude  per (receiver, body) path validity + visibility bits, and per
-//              receiver inside / line-of-sight flags  (the U of Eqs. (1)-(2))
+//   k_paths    per (receiver, body) path validity + visibility bits (the U of
+//              Eqs. (1)-(2)) and the frequency-independent constants of every
+//              valid path; per receiver inside / line-of-sight flags
 //   k_field    per (receiver, frequency chunk) coherent field of Eqs. (1)-(4)
 //
-// One lane owns one receiver and a chunk of FC frequencies; it walks the
-// bodies in order (uniform across the wavefront, so body data comes through
-// scalar loads), rebuilds the frequency-independent path constants once per
-// path and then runs the Fock-coefficient evaluation for each frequency of the
-// chunk, accumulating E in registers.  The Fock tables sit in LDS (FP32) or
-// global memory (FP64).
+// In k_field one lane owns one receiver and a chunk of FC frequencies; it
+// walks the bodies in order, reads each valid path's record once and runs the
+// Fock-coefficient evaluation for every frequency of the chunk, accumulating E
+// in registers.  Frequency constants are uniform across the workgroup (scalar
+// loads).  The Fock tables sit in LDS (FP32) or global memory (FP64).
 #define FT_QUAL __device__ const
 #include "utd_internal.h"
 #include "utd_bvh.h"
@@ -23,10 +23,20 @@ namespace utd {
 // body constants
 // ---------------------------------------------------------------------------
 __global__ void k_prep(LaunchParams L, const float* __restrict__ sph, const float* __restrict__ cyl,
-                       BodyPrep* __restrict__ out) {
+                       const double* __restrict__ freqs, BodyPrep* __restrict__ out, FreqConst* __restrict__ fc) {
     int nb = L.n_sph + L.n_cyl;
-    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += gridDim.x * blockDim.x)
-        out[b] = body_prep(L.T, sph, L.n_sph, cyl, b);
+    int tid = blockIdx.x * blockDim.x + threadIdx.x, nt = gridDim.x * blockDim.x;
+    for (int b = tid; b < nb; b += nt) out[b] = body_prep(L.T, sph, L.n_sph, cyl, b);
+    if (freqs)
+        for (int f = tid; f < L.n_f; f += nt) {
+            double k = kTwoPi * freqs[f] / kC0;
+            double k13 = cbrt(k), k16 = sqrt(k13);
+            FreqConst c;
+            c.rev_per_m = freqs[f] / kC0;
+            c.kd = k; c.k13d = k13; c.k16d = k16; c.km16d = 1.0 / k16;
+            c.kf = (float)k; c.k13f = (float)k13; c.k16f = (float)k16; c.km16f = (float)(1.0 / k16);
+            fc[f] = c;
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -49,40 +59,96 @@ __device__ __forceinline__ bool seg_blocked(d3 P0, d3 P1, const LaunchParams& L,
     return bvh_anyhit(nodes, tris, r, stack, stride);
 }
 
-// grid: x over receivers (blockDim 256), y over slot = 0 (receiver flags) or
-// 1 + body.  mask[body][rx] gets the path bits, flags[rx] the slot-0 bits.
-__global__ void __launch_bounds__(256) k_occlude(LaunchParams L, const float* __restrict__ rx,
-                                                 const float* __restrict__ sph, const float* __restrict__ cyl,
-                                                 const BodyPrep* __restrict__ prep, const float4* __restrict__ nodes,
-                                                 const float4* __restrict__ tris, uint8_t* __restrict__ mask,
-                                                 uint8_t* __restrict__ flags) {
+// Path records: the frequency-independent constants of one valid path,
+// written by the visibility pass and read by the field kernel.  Slot-major
+// layout rec[(body * S + slot) * n_rx + rx] keeps both passes coalesced;
+// S = 2 (l_enc + 1) bounds the valid paths of a (receiver, body) pair (one
+// side of a lit receiver carries the reflection instead of a creeping path).
+template <typename R> struct PathRec;
+template <> struct PathRec<float> {          // 64 bytes
+    double s_tot;
+    float rev0;
+    uint32_t refl;
+    float4 q0, q1, q2;                        // (phi_e, mhat, Lh, qhat) (a_s, a_h, vs0, vs1) (vs2, vh0, vh1, vh2)
+};
+template <> struct PathRec<double> {         // 128 bytes
+    double s_tot, rev0;
+    uint64_t refl, pad;
+    double v[12];
+};
+
+__device__ __forceinline__ void pack(const PathEval<float>& p, PathRec<float>* r) {
+    PathRec<float> o;
+    o.s_tot = p.s_tot;
+    o.rev0 = (float)p.rev0;
+    o.refl = (uint32_t)p.refl;
+    o.q0 = make_float4(p.phi_e, p.mhat, p.Lh, p.qhat);
+    o.q1 = make_float4(p.a_s, p.a_h, p.vs[0], p.vs[1]);
+    o.q2 = make_float4(p.vs[2], p.vh[0], p.vh[1], p.vh[2]);
+    *r = o;
+}
+__device__ __forceinline__ void unpack(const PathRec<float>& o, PathEval<float>* p) {
+    p->s_tot = o.s_tot;
+    p->rev0 = o.rev0;
+    p->refl = (int)o.refl;
+    p->phi_e = o.q0.x; p->mhat = o.q0.y; p->Lh = o.q0.z; p->qhat = o.q0.w;
+    p->a_s = o.q1.x; p->a_h = o.q1.y; p->vs[0] = o.q1.z; p->vs[1] = o.q1.w;
+    p->vs[2] = o.q2.x; p->vh[0] = o.q2.y; p->vh[1] = o.q2.z; p->vh[2] = o.q2.w;
+}
+__device__ __forceinline__ void pack(const PathEval<double>& p, PathRec<double>* r) {
+    PathRec<double> o;
+    o.s_tot = p.s_tot; o.rev0 = p.rev0; o.refl = (uint64_t)p.refl; o.pad = 0;
+    double v[12] = {p.phi_e, p.mhat, p.Lh, p.qhat, p.a_s, p.a_h, p.vs[0], p.vs[1], p.vs[2], p.vh[0], p.vh[1], p.vh[2]};
+    for (int k = 0; k < 12; ++k) o.v[k] = v[k];
+    *r = o;
+}
+__device__ __forceinline__ void unpack(const PathRec<double>& o, PathEval<double>* p) {
+    p->s_tot = o.s_tot; p->rev0 = o.rev0; p->refl = (int)o.refl;
+    p->phi_e = o.v[0]; p->mhat = o.v[1]; p->Lh = o.v[2]; p->qhat = o.v[3];
+    p->a_s = o.v[4]; p->a_h = o.v[5];
+    p->vs[0] = o.v[6]; p->vs[1] = o.v[7]; p->vs[2] = o.v[8];
+    p->vh[0] = o.v[9]; p->vh[1] = o.v[10]; p->vh[2] = o.v[11];
+}
+
+// Visibility and path constants.  grid: x over receivers (blockDim 256),
+// y over slot = 0 (receiver flags) or 1 + body.  mask[body][rx] gets the path
+// bits, flags[rx] the slot-0 bits, rec the constants of each valid path in
+// set-bit order.
+template <typename R>
+__global__ void __launch_bounds__(256) k_paths(LaunchParams L, const float* __restrict__ rx,
+                                               const float* __restrict__ sph, const float* __restrict__ cyl,
+                                               const BodyPrep* __restrict__ prep, const float4* __restrict__ nodes,
+                                               const float4* __restrict__ tris, uint8_t* __restrict__ mask,
+                                               PathRec<R>* __restrict__ rec, uint8_t* __restrict__ flags) {
     __shared__ int stack[kStackDepth * 256];
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int slot = blockIdx.y;
     if (i >= L.n_rx) return;
     int* stk = stack + threadIdx.x;
     const int stride = 256;
-    d3 R = mk(rx[3 * i], rx[3 * i + 1], rx[3 * i + 2]);
+    d3 R3 = mk(rx[3 * i], rx[3 * i + 1], rx[3 * i + 2]);
     d3 T = mk(L.T[0], L.T[1], L.T[2]);
     int nb = L.n_sph + L.n_cyl;
     if (slot == 0) {
         uint8_t f = 0;
         bool inside = false, tx_inside = false;
         for (int b = 0; b < nb; ++b) {
-            inside |= inside_body(prep[b], R);
+            inside |= inside_body(prep[b], R3);
             tx_inside |= inside_body(prep[b], T);
         }
         if (tx_inside) f |= kFlagTxInside;
         if (inside) f |= kFlagInside;
-        if (!inside && !tx_inside && !seg_blocked(T, R, L, sph, cyl, -1, true, nodes, tris, stk, stride))
+        if (!inside && !tx_inside && !seg_blocked(T, R3, L, sph, cyl, -1, true, nodes, tris, stk, stride))
             f |= kFlagLos;
         flags[i] = f;
         return;
     }
     int b = slot - 1;
-    const BodyPrep& P = prep[b];
-    RxGeo g = rx_geo(P, R);
+    const BodyPrep P = prep[b];
+    RxGeo g = rx_geo(P, R3);
     uint8_t m = 0;
+    int nrec = 0;
+    const int S = 2 * (L.l_enc + 1);
     bool bo = L.bodies_occlude != 0;
     for (int ell = 0; ell <= L.l_enc; ++ell) {
         for (int side = 0; side < 2; ++side) {
@@ -90,23 +156,36 @@ __global__ void __launch_bounds__(256) k_occlude(LaunchParams L, const float* __
             PathPts pts;
             bool ok, caus = false;
             if (P.kind == 0)
-                ok = sphere_creep<float>(P, g, R, L, sgn, ell, &caus, (PathEval<float>*)nullptr, &pts);
+                ok = sphere_creep<R>(P, g, R3, L, sgn, ell, &caus, (PathEval<R>*)nullptr, &pts);
             else
-                ok = cyl_creep<float>(P, g, R, L, sgn, ell, (PathEval<float>*)nullptr, &pts);
+                ok = cyl_creep<R>(P, g, R3, L, sgn, ell, (PathEval<R>*)nullptr, &pts);
             if (caus) m |= (uint8_t)(1u << kBitCaustic);
             if (!ok) continue;
             if (seg_blocked(pts.P0, pts.P1, L, sph, cyl, b, bo, nodes, tris, stk, stride)) continue;
             if (seg_blocked(pts.P2, pts.P3, L, sph, cyl, b, bo, nodes, tris, stk, stride)) continue;
             m |= (uint8_t)(1u << (2 * ell + side));
+            PathEval<R> pe;
+            bool cz;
+            if (P.kind == 0)
+                sphere_creep<R>(P, g, R3, L, sgn, ell, &cz, &pe, nullptr);
+            else
+                cyl_creep<R>(P, g, R3, L, sgn, ell, &pe, nullptr);
+            if (nrec < S) pack(pe, &rec[((int64_t)b * S + nrec) * L.n_rx + i]);
+            ++nrec;
         }
     }
-    if (L.lit_branch) {
-        PathPts pts;
-        bool ok = P.kind == 0 ? sphere_refl<float>(P, g, R, L, nullptr, &pts)
-                              : cyl_refl<float>(P, g, R, L, nullptr, &pts);
-        if (ok && !seg_blocked(pts.P0, pts.P1, L, sph, cyl, b, bo, nodes, tris, stk, stride) &&
-            !seg_blocked(pts.P2, pts.P3, L, sph, cyl, b, bo, nodes, tris, stk, stride))
+    double th = 0.0;
+    if (L.lit_branch && refl_angle(P, g, R3, L, &th)) {
+        d3 Q, n;
+        refl_point(P, g, R3, L, th, &Q, &n);
+        if (!seg_blocked(T, Q, L, sph, cyl, b, bo, nodes, tris, stk, stride) &&
+            !seg_blocked(Q, R3, L, sph, cyl, b, bo, nodes, tris, stk, stride)) {
             m |= (uint8_t)(1u << kBitRefl);
+            PathEval<R> pe;
+            refl_eval<R>(P, Q, n, R3, L, &pe);
+            if (nrec < S) pack(pe, &rec[((int64_t)b * S + nrec) * L.n_rx + i]);
+            ++nrec;
+        }
     }
     mask[(int64_t)b * L.n_rx + i] = m;
 }
@@ -114,24 +193,19 @@ __global__ void __launch_bounds__(256) k_occlude(LaunchParams L, const float* __
 // ---------------------------------------------------------------------------
 // field
 // ---------------------------------------------------------------------------
-template <typename R> struct FreqC {
-    double rev_per_m;   // f / c  (revolutions of phase per metre)
-    R kf, k13, k16, km16;
+template <typename R> struct FreqC;
+template <> struct FreqC<float> {
+    double rev_per_m;
+    float kf, k13, k16, km16;
+    __device__ __forceinline__ FreqC(const FreqConst& c)
+        : rev_per_m(c.rev_per_m), kf(c.kf), k13(c.k13f), k16(c.k16f), km16(c.km16f) {}
 };
-
-template <typename R>
-__device__ __forceinline__ FreqC<R> freq_consts(double f) {
-    FreqC<R> c;
-    double k = kTwoPi * f / kC0;
-    c.rev_per_m = f / kC0;
-    c.kf = (R)k;
-    double k13 = cbrt(k);
-    c.k13 = (R)k13;
-    double k16 = sqrt(k13);
-    c.k16 = (R)k16;
-    c.km16 = (R)(1.0 / k16);
-    return c;
-}
+template <> struct FreqC<double> {
+    double rev_per_m;
+    double kf, k13, k16, km16;
+    __device__ __forceinline__ FreqC(const FreqConst& c)
+        : rev_per_m(c.rev_per_m), kf(c.kd), k13(c.k13d), k16(c.k16d), km16(c.km16d) {}
+};
 
 template <typename R>
 __device__ __forceinline__ void add_path(const PathEval<R>& pe, const Tabs<R>& tb, const FreqC<R>& fc, R* E) {
@@ -208,16 +282,17 @@ template <> struct TableStage<double> {
 
 template <typename R, int FC>
 __global__ void __launch_bounds__(256) k_field(LaunchParams L, const float* __restrict__ rx,
-                                               const double* __restrict__ freqs, const BodyPrep* __restrict__ prep,
-                                               const uint8_t* __restrict__ mask, uint8_t* __restrict__ flags,
+                                               const FreqConst* __restrict__ fcs, const uint8_t* __restrict__ mask,
+                                               const PathRec<R>* __restrict__ rec, uint8_t* __restrict__ flags,
                                                R* __restrict__ E_out) {
     __shared__ R s_reg[TableStage<R>::NREG];
     __shared__ R s_tf[TableStage<R>::NTF];
     Tabs<R> tb = TableStage<R>::stage(s_reg, s_tf);
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= L.n_rx) return;
-    int f0 = blockIdx.y * FC;
-    int nfc = L.n_f - f0 < FC ? L.n_f - f0 : FC;
+    const int f0 = blockIdx.y * FC;
+    const int nfc = L.n_f - f0 < FC ? L.n_f - f0 : FC;
+    const int S = 2 * (L.l_enc + 1);
     R E[FC][6];
 #pragma unroll
     for (int j = 0; j < FC; ++j)
@@ -225,26 +300,25 @@ __global__ void __launch_bounds__(256) k_field(LaunchParams L, const float* __re
         for (int c = 0; c < 6; ++c) E[j][c] = (R)0;
     uint8_t fl = flags[i];
     if (!(fl & (kFlagInside | kFlagTxInside))) {
-        FreqC<R> fcs[FC];
-#pragma unroll
-        for (int j = 0; j < FC; ++j) fcs[j] = freq_consts<R>(freqs[f0 + (j < nfc ? j : 0)]);
-        d3 Rp = mk(rx[3 * i], rx[3 * i + 1], rx[3 * i + 2]);
         // direct field, Eq. (1): A (p - (p.s)s) e^{-jks}/s
         if ((fl & kFlagLos) && L.lit_branch) {
-            d3 v = Rp - mk(L.T[0], L.T[1], L.T[2]);
-            double s = norm(v);
-            d3 sh = (1.0 / s) * v;
-            d3 p = mk(L.p[0], L.p[1], L.p[2]);
-            d3 pp = p - dot(p, sh) * sh;
-            double A = L.amp / s;
-            R e3[3] = {(R)(A * pp.x), (R)(A * pp.y), (R)(A * pp.z)};
+            d3 v = mk(rx[3 * i] - L.T[0], rx[3 * i + 1] - L.T[1], rx[3 * i + 2] - L.T[2]);
+            double sd = norm(v);
+            R isd = (R)(1.0 / sd);
+            R shx = (R)v.x * isd, shy = (R)v.y * isd, shz = (R)v.z * isd;
+            R px = (R)L.p[0], py = (R)L.p[1], pz = (R)L.p[2];
+            R pd = px * shx + py * shy + pz * shz;
+            R A = (R)L.amp * isd;
+            R e3[3] = {A * (px - pd * shx), A * (py - pd * shy), A * (pz - pd * shz)};
 #pragma unroll
             for (int j = 0; j < FC; ++j) {
-                cplx<R> ph = phase_rev<R>(fcs[j].rev_per_m * s);
+                if (j < nfc) {
+                    cplx<R> ph = phase_rev<R>(fcs[f0 + j].rev_per_m * sd);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    E[j][2 * c] += e3[c] * ph.re;
-                    E[j][2 * c + 1] += e3[c] * ph.im;
+                    for (int c = 0; c < 3; ++c) {
+                        E[j][2 * c] += e3[c] * ph.re;
+                        E[j][2 * c + 1] += e3[c] * ph.im;
+                    }
                 }
             }
         }
@@ -253,39 +327,59 @@ __global__ void __launch_bounds__(256) k_field(LaunchParams L, const float* __re
         for (int b = 0; b < nb; ++b) {
             uint8_t m = mask[(int64_t)b * L.n_rx + i];
             caus |= m;
-            if (!(m & 0x7f)) continue;
-            const BodyPrep P = prep[b];
-            RxGeo g = rx_geo(P, Rp);
-            for (int bit = 0; bit < 7; ++bit) {
-                if (!(m & (1u << bit))) continue;
+            int n = __builtin_popcount(m & 0x7fu);
+            n = n < S ? n : S;
+            for (int k = 0; k < n; ++k) {
                 PathEval<R> pe;
-                bool ok;
-                if (bit == kBitRefl) {
-                    ok = P.kind == 0 ? sphere_refl<R>(P, g, Rp, L, &pe, nullptr) : cyl_refl<R>(P, g, Rp, L, &pe, nullptr);
-                } else {
-                    int ell = bit >> 1, sgn = (bit & 1) ? -1 : 1;
-                    bool cz;
-                    ok = P.kind == 0 ? sphere_creep<R>(P, g, Rp, L, sgn, ell, &cz, &pe, nullptr)
-                                     : cyl_creep<R>(P, g, Rp, L, sgn, ell, &pe, nullptr);
-                }
-                if (!ok) continue;
+                unpack(rec[((int64_t)b * S + k) * L.n_rx + i], &pe);
 #pragma unroll
-                for (int j = 0; j < FC; ++j)
-                    if (j < nfc) add_path<R>(pe, tb, fcs[j], E[j]);
+                for (int j = 0; j < FC; ++j) {
+                    if (j < nfc) {
+                        FreqC<R> fc(fcs[f0 + j]);
+                        add_path<R>(pe, tb, fc, E[j]);
+                    }
+                }
             }
         }
         if (blockIdx.y == 0 && (caus & (1u << kBitCaustic))) flags[i] = fl | kFlagCaustic;
     }
 #pragma unroll
     for (int j = 0; j < FC; ++j) {
-        if (j >= nfc) break;
+        if (j < nfc) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            int64_t o = ((int64_t)(f0 + j) * 3 + c) * L.n_rx + i;
-            E_out[2 * o] = E[j][2 * c];
-            E_out[2 * o + 1] = E[j][2 * c + 1];
+            for (int c = 0; c < 3; ++c) {
+                int64_t o = ((int64_t)(f0 + j) * 3 + c) * L.n_rx + i;
+                E_out[2 * o] = E[j][2 * c];
+                E_out[2 * o + 1] = E[j][2 * c + 1];
+            }
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// path census: per-bit counts of the masks (integer atomics, deterministic)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_census(int64_t n_mask, const uint8_t* __restrict__ mask, int64_t n_rx,
+                                                const uint8_t* __restrict__ flags,
+                                                unsigned long long* __restrict__ counts) {
+    __shared__ unsigned int part[10];
+    if (threadIdx.x < 10) part[threadIdx.x] = 0;
+    __syncthreads();
+    unsigned int loc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_mask; i += (int64_t)gridDim.x * blockDim.x) {
+        uint8_t m = mask[i];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) loc[b] += (m >> b) & 1u;
+    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_rx; i += (int64_t)gridDim.x * blockDim.x) {
+        uint8_t f = flags[i];
+        loc[8] += (f & kFlagLos) ? 1u : 0u;
+        loc[9] += (f & kFlagInside) ? 1u : 0u;
+    }
+#pragma unroll
+    for (int b = 0; b < 10; ++b) atomicAdd(&part[b], loc[b]);
+    __syncthreads();
+    if (threadIdx.x < 10) atomicAdd(&counts[threadIdx.x], (unsigned long long)part[threadIdx.x]);
 }
 
 // ---------------------------------------------------------------------------
@@ -296,46 +390,63 @@ hipError_t pack_tables(hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_prep(const LaunchParams& L, const float* sph, const float* cyl, BodyPrep* prep, hipStream_t s) {
-    int nb = L.n_sph + L.n_cyl;
-    if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_prep, dim3((nb + 63) / 64), dim3(64), 0, s, L, sph, cyl, prep);
+hipError_t launch_census(int64_t n_mask, const uint8_t* mask, int64_t n_rx, const uint8_t* flags,
+                         unsigned long long* counts, hipStream_t s) {
+    hipLaunchKernelGGL(k_census, dim3(512), dim3(256), 0, s, n_mask, mask, n_rx, flags, counts);
     return hipGetLastError();
 }
 
-hipError_t launch_occlude(const LaunchParams& L, const float* rx, const float* sph, const float* cyl,
-                          const BodyPrep* prep, const float4* nodes, const float4* tris, uint8_t* mask,
-                          uint8_t* flags, hipStream_t s) {
+hipError_t launch_prep(const LaunchParams& L, const float* sph, const float* cyl, const double* freqs,
+                       BodyPrep* prep, FreqConst* fc, hipStream_t s) {
+    int nb = L.n_sph + L.n_cyl;
+    int n = nb > L.n_f ? nb : L.n_f;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_prep, dim3((n + 63) / 64), dim3(64), 0, s, L, sph, cyl, freqs, prep, fc);
+    return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t launch_paths_t(const LaunchParams& L, const float* rx, const float* sph, const float* cyl,
+                                 const BodyPrep* prep, const float4* nodes, const float4* tris, uint8_t* mask,
+                                 void* rec, uint8_t* flags, hipStream_t s) {
     int nb = L.n_sph + L.n_cyl;
     dim3 grid((unsigned)((L.n_rx + 255) / 256), (unsigned)(nb + 1));
-    hipLaunchKernelGGL(k_occlude, grid, dim3(256), 0, s, L, rx, sph, cyl, prep, nodes, tris, mask, flags);
+    hipLaunchKernelGGL((k_paths<R>), grid, dim3(256), 0, s, L, rx, sph, cyl, prep, nodes, tris, mask,
+                       (PathRec<R>*)rec, flags);
     return hipGetLastError();
 }
+
+hipError_t launch_paths(const LaunchParams& L, int precision, const float* rx, const float* sph, const float* cyl,
+                        const BodyPrep* prep, const float4* nodes, const float4* tris, uint8_t* mask, void* rec,
+                        uint8_t* flags, hipStream_t s) {
+    return precision == 0 ? launch_paths_t<float>(L, rx, sph, cyl, prep, nodes, tris, mask, rec, flags, s)
+                          : launch_paths_t<double>(L, rx, sph, cyl, prep, nodes, tris, mask, rec, flags, s);
+}
+
+size_t path_record_bytes(int precision) { return precision == 0 ? sizeof(PathRec<float>) : sizeof(PathRec<double>); }
 
 template <typename R, int FC>
-static hipError_t launch_field_fc(const LaunchParams& L, const float* rx, const double* freqs, const BodyPrep* prep,
-                                  const uint8_t* mask, uint8_t* flags, R* E, hipStream_t s) {
+static hipError_t launch_field_fc(const LaunchParams& L, const float* rx, const FreqConst* fcs, const uint8_t* mask,
+                                  const void* rec, uint8_t* flags, R* E, hipStream_t s) {
     dim3 grid((unsigned)((L.n_rx + 255) / 256), (unsigned)((L.n_f + FC - 1) / FC));
-    hipLaunchKernelGGL((k_field<R, FC>), grid, dim3(256), 0, s, L, rx, freqs, prep, mask, flags, E);
+    hipLaunchKernelGGL((k_field<R, FC>), grid, dim3(256), 0, s, L, rx, fcs, mask, (const PathRec<R>*)rec, flags, E);
     return hipGetLastError();
 }
 
-hipError_t launch_field(const LaunchParams& L, int precision, int fc, const float* rx, const double* freqs,
-                        const BodyPrep* prep, const uint8_t* mask, uint8_t* flags, void* E, hipStream_t s) {
+hipError_t launch_field(const LaunchParams& L, int precision, int fc, const float* rx, const FreqConst* fcs,
+                        const uint8_t* mask, const void* rec, uint8_t* flags, void* E, hipStream_t s) {
     if (precision == 0) {
         float* e = (float*)E;
         switch (fc) {
-            case 1: return launch_field_fc<float, 1>(L, rx, freqs, prep, mask, flags, e, s);
-            case 2: return launch_field_fc<float, 2>(L, rx, freqs, prep, mask, flags, e, s);
-            case 4: return launch_field_fc<float, 4>(L, rx, freqs, prep, mask, flags, e, s);
-            default: return launch_field_fc<float, 8>(L, rx, freqs, prep, mask, flags, e, s);
+            case 1: return launch_field_fc<float, 1>(L, rx, fcs, mask, rec, flags, e, s);
+            case 2: return launch_field_fc<float, 2>(L, rx, fcs, mask, rec, flags, e, s);
+            default: return launch_field_fc<float, 4>(L, rx, fcs, mask, rec, flags, e, s);
         }
     }
     double* e = (double*)E;
     switch (fc) {
-        case 1: return launch_field_fc<double, 1>(L, rx, freqs, prep, mask, flags, e, s);
-        case 2: return launch_field_fc<double, 2>(L, rx, freqs, prep, mask, flags, e, s);
-        default: return launch_field_fc<double, 4>(L, rx, freqs, prep, mask, flags, e, s);
+        case 1: return launch_field_fc<double, 1>(L, rx, fcs, mask, rec, flags, e, s);
+        default: return launch_field_fc<double, 2>(L, rx, fcs, mask, rec, flags, e, s);
     }
 }
 
