@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config5", "config1"])
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=1536, help="receivers in the oracle sample")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run one device copy of this size (HBM counter calibration under a profiler)")
     return ap.parse_args()
 
 
@@ -111,6 +113,13 @@ def main():
     def step():
         utd.smooth_field(scene, sph, cyl, src, rx, freqs, precision=0, out=out, flags=flags)
 
+    if args.copy_calibration_mib:
+        a = torch.empty(args.copy_calibration_mib << 18, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()

@@ -109,17 +109,27 @@ __device__ __forceinline__ int locate(R x, R lo, R inv_w, int n, R* s) {
 // Written without data-dependent branches: the regime and the transition
 // range only select the segment, the local variable and a few operands, so a
 // wavefront whose lanes sit in different regimes stays converged.
+template <typename R> struct FockArgs {
+    R xi;    // Fock parameter
+    R u;     // sqrt(X), X the transition-function argument
+    R q;     // sqrt(X)/|xi|
+    R ixi;   // 1/xi (0 when xi == 0)
+    R h;     // sqrt(-xi)/2 (deep lit; 0 otherwise)
+};
+
 template <typename R>
-__device__ __forceinline__ void fock_kernel(const Tabs<R>& tb, R xi, R X, R q, bool refl,
+__device__ __forceinline__ void fock_kernel(const Tabs<R>& tb, const FockArgs<R>& A, bool refl, bool any_refl,
                                             cplx<R>* Ks, cplx<R>* Kh) {
     using D = TabDims<R>;
     const R e4 = (R)kRs2;                     // e^{-j pi/4} = e4 (1 - j)
     const R c2 = (R)kInv2SqrtPi;
+    const R xi = A.xi, u = A.u, q = A.q, ixi = A.ixi;
+    const R X = u * u;
 
     // --- transition function: A(u) for u <= FA_HI, H(1/X) beyond -----------
-    R u = RT<R>::sqrt_(X);
     bool big = u > (R)FT_FA_HI;
-    R iX = RT<R>::rcp(big ? X : (R)1);
+    R iu = RT<R>::rcp(big ? u : (R)1);
+    R iX = iu * iu;
     R targ = big ? iX : u;
     R invw = big ? (R)(D::NFH * FT_FA_HI * FT_FA_HI) : (R)(D::NFA / FT_FA_HI);
     int nseg = big ? D::NFH : D::NFA;
@@ -128,7 +138,6 @@ __device__ __forceinline__ void fock_kernel(const Tabs<R>& tb, R xi, R X, R q, b
     R v[2];
     horner2<R>(tb.tf + tseg * 2 * (D::DEG + 1), st, v);
     // small u: G = F/sqrt(X) = 2j A, F = u G; large u: 1 - F = -H/X, G = F/u
-    R iu = RT<R>::rcp(big ? u : (R)1);
     R omr = -iX * v[0], omi = -iX * v[1];
     cplx<R> G, omF;
     G.re = big ? ((R)1 - omr) * iu : (R)-2 * v[1];
@@ -138,7 +147,6 @@ __device__ __forceinline__ void fock_kernel(const Tabs<R>& tb, R xi, R X, R q, b
 
     // --- regime table ------------------------------------------------------
     int regime = xi >= (R)FT_PT_HI ? 0 : (xi >= (R)FT_PT_LO ? 1 : 2);
-    R ixi = RT<R>::rcp(xi != (R)0 ? xi : (R)1);
     R r3 = (R)FT_PT_LO * ixi;
     R arg = regime == 0 ? (xi < (R)FT_DS_HI ? xi : (R)FT_DS_HI) : (regime == 1 ? xi : r3 * r3 * r3);
     R rlo = regime == 0 ? (R)FT_PT_HI : (regime == 1 ? (R)FT_PT_LO : (R)0);
@@ -172,10 +180,10 @@ __device__ __forceinline__ void fock_kernel(const Tabs<R>& tb, R xi, R X, R q, b
     // creeping: K = P + CW
     // reflection / deep lit: K = -(alpha P + e CW), e = e^{-j xi^3/12},
     //   alpha = e (regimes 0, 1) or sqrt(-xi)/2 (regime 2, P = c)
-    cplx<R> e = expmj<R>(xi * xi * xi * (R)(1.0 / 12));
     bool lit = refl || regime == 2;
-    R h = (R)0.5 * RT<R>::sqrt_(regime == 2 ? -xi : (R)0);
-    cplx<R> alpha = regime == 2 ? cplx<R>{h, (R)0} : e;
+    cplx<R> e{(R)1, (R)0};
+    if (any_refl) e = expmj<R>(xi * xi * xi * (R)(1.0 / 12));
+    cplx<R> alpha = regime == 2 ? cplx<R>{A.h, (R)0} : e;
     cplx<R> eCW = cmul(e, CW);
     cplx<R> as = cmul(alpha, ps), ah = cmul(alpha, ph);
     Ks->re = lit ? -(as.re + eCW.re) : ps.re + CW.re;

@@ -19,18 +19,32 @@
 
 namespace utd {
 
-// Everything the frequency loop needs about one path.  The per-frequency
-// coefficient is K_p(xi, X) with xi = mhat k^{1/3} phi_e, X = k Lh phi_e^2,
-// q = k^{1/6} qhat, and the contribution is
-//   e^{-j 2pi rev} k^{-1/6} (a_s K_s v_s + a_h K_h v_h),  rev = (f/c) s_tot + rev0.
+// Everything the frequency loop needs about one path.  With m = mhat k^{1/3},
+// xi = m phi_e (phi_e = t/rho_g, or -2 cos th_i for a reflection) and
+// X = k L phi_e^2 / 2, the per-frequency Fock arguments are
+//   xi = k^{1/3} xh,  sqrt(X) = k^{1/2} uh,  q = k^{1/6} qhat,
+//   1/xi = k^{-1/3} ixh,  sqrt(-xi) = k^{1/6} sxh,
+// and the contribution is
+//   e^{-j 2pi rev} k^{-1/6} (a_s K_s v_s + a_h K_h v_h),  rev = (f/c) s_tot - nc/4.
 template <typename R> struct PathEval {
     double s_tot;     // total path length s^i + t + s^d (or s^i + s^r)
-    double rev0;      // extra phase in revolutions (caustics: -N_c/4)
-    R phi_e, mhat, Lh, qhat;
+    int nc;           // caustics passed (each +pi/2)
+    int refl;
+    R xh, uh, qhat, ixh, sxh;
     R a_s, a_h;       // incident projections x spreading x prefactor
     R vs[3], vh[3];   // output polarisation vectors at R
-    int refl;
 };
+
+// Fill the Fock-argument constants from mhat, phi_e and L (= L^d or L^r).
+template <typename R>
+__device__ __forceinline__ void set_fock_consts(PathEval<R>* pe, R mhat, R phi_e, R Ld) {
+    R xh = mhat * phi_e;
+    pe->xh = xh;
+    pe->uh = RT<R>::sqrt_((R)0.5 * Ld) * (phi_e < (R)0 ? -phi_e : phi_e);
+    pe->qhat = RT<R>::sqrt_((R)0.5 * Ld) / mhat;
+    pe->ixh = xh != (R)0 ? (R)1 / xh : (R)0;
+    pe->sxh = RT<R>::sqrt_(xh < (R)0 ? -xh : (R)0);
+}
 
 // Points of a path (for the visibility tests).
 struct PathPts {
@@ -191,7 +205,7 @@ __device__ __forceinline__ bool sphere_creep(const BodyPrep& b, const RxGeo& g, 
         int Nc = npi + ((sgn > 0) != s2pos ? 1 : 0);
         double sI = b.sI0, sD = g.sD0;
         pe->s_tot = sI + a * phi + sD;
-        pe->rev0 = -0.25 * Nc;
+        pe->nc = Nc;
         // frames in precision R: n1 = cg eT + sg ep, t1 = -sg eT + cg ep,
         // b = t1 x n1 = -(eT x ep), n2 = c2 eT + s2 ep
         R eTx = (R)eT.x, eTy = (R)eT.y, eTz = (R)eT.z;
@@ -205,10 +219,7 @@ __device__ __forceinline__ bool sphere_creep(const BodyPrep& b, const RxGeo& g, 
         R mhat = RT<R>::cbrt_((R)0.5 * aR);
         R Smod = RT<R>::sqrt_(aR * sgR / (sDR * (R)g.wn));
         R A = (R)L.amp * Smod / sIR * ((R)-1.4142135623730951 * mhat);
-        pe->phi_e = (R)phi;
-        pe->mhat = mhat;
-        pe->Lh = (R)0.5 * Ld;
-        pe->qhat = RT<R>::sqrt_((R)0.5 * Ld) / mhat;
+        set_fock_consts<R>(pe, mhat, (R)phi, Ld);
         pe->a_s = A * (px * bx + py * by + pz * bz);
         pe->a_h = A * (px * n1x + py * n1y + pz * n1z);
         pe->vs[0] = bx; pe->vs[1] = by; pe->vs[2] = bz;
@@ -250,7 +261,7 @@ __device__ __forceinline__ bool cyl_creep(const BodyPrep& b, const RxGeo& g, d3 
     if (pe) {
         double Stot = sqrt(L2 * L2 + dz * dz);
         pe->s_tot = Stot;
-        pe->rev0 = 0.0;
+        pe->nc = 0;
         R cosd = (R)(L2 / Stot), sind = (R)(dz / Stot);
         R idc = (R)1 / cosd;
         R sI = (R)dT * idc, t = (R)(a * phi) * idc, sD = (R)dR * idc;
@@ -266,10 +277,7 @@ __device__ __forceinline__ bool cyl_creep(const BodyPrep& b, const RxGeo& g, d3 
         R px = (R)L.p[0], py = (R)L.p[1], pz = (R)L.p[2];
         R A = (R)L.amp * Smod / sI * ((R)-1.4142135623730951 * mhat);
         (void)t;
-        pe->phi_e = (R)phi * cosd;
-        pe->mhat = mhat;
-        pe->Lh = (R)0.5 * Ld;
-        pe->qhat = RT<R>::sqrt_((R)0.5 * Ld) / mhat;
+        set_fock_consts<R>(pe, mhat, (R)phi * cosd, Ld);
         pe->a_s = A * (px * b1x + py * b1y + pz * b1z);
         pe->a_h = A * (px * c1R + py * s1R);
         pe->vs[0] = b2x; pe->vs[1] = b2y; pe->vs[2] = b2z;
@@ -387,7 +395,7 @@ __device__ __forceinline__ void refl_eval(const BodyPrep& b, d3 Q, d3 n, d3 Rp, 
     d3 vi = Q - T, vr = Rp - Q;
     double sI = norm(vi), sR = norm(vr);
     pe->s_tot = sI + sR;
-    pe->rev0 = 0.0;
+    pe->nc = 0;
     R isI = (R)(1.0 / sI), isR = (R)(1.0 / sR);
     R six = (R)vi.x * isI, siy = (R)vi.y * isI, siz = (R)vi.z * isI;
     R srx = (R)vr.x * isR, sry = (R)vr.y * isR, srz = (R)vr.z * isR;
@@ -433,10 +441,7 @@ __device__ __forceinline__ void refl_eval(const BodyPrep& b, d3 Q, d3 n, d3 Rp, 
     R P0 = (R)2 * RT<R>::sqrt_(r1c / ((R)2 * mhat)) * RT<R>::sqrt_(rho2 / ((rho1 + sRR) * (rho2 + sRR)));
     R px = (R)L.p[0], py = (R)L.p[1], pz = (R)L.p[2];
     R A = (R)L.amp * isI * P0;
-    pe->phi_e = (R)-2 * ci;
-    pe->mhat = mhat;
-    pe->Lh = (R)0.5 * Lr;
-    pe->qhat = RT<R>::sqrt_((R)0.5 * Lr) / mhat;
+    set_fock_consts<R>(pe, mhat, (R)-2 * ci, Lr);
     pe->a_s = A * (px * cx + py * cy + pz * cz);
     pe->a_h = A * (px * pix + py * piy + pz * piz);
     pe->vs[0] = cx; pe->vs[1] = cy; pe->vs[2] = cz;

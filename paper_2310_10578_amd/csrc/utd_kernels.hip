@@ -33,8 +33,9 @@ __global__ void k_prep(LaunchParams L, const float* __restrict__ sph, const floa
             double k13 = cbrt(k), k16 = sqrt(k13);
             FreqConst c;
             c.rev_per_m = freqs[f] / kC0;
-            c.kd = k; c.k13d = k13; c.k16d = k16; c.km16d = 1.0 / k16;
+            c.kd = k; c.k13d = k13; c.k16d = k16; c.km16d = 1.0 / k16; c.skd = sqrt(k); c.ik13d = 1.0 / k13;
             c.kf = (float)k; c.k13f = (float)k13; c.k16f = (float)k16; c.km16f = (float)(1.0 / k16);
+            c.skf = (float)sqrt(k); c.ik13f = (float)(1.0 / k13);
             fc[f] = c;
         }
 }
@@ -67,47 +68,53 @@ __device__ __forceinline__ bool seg_blocked(d3 P0, d3 P1, const LaunchParams& L,
 template <typename R> struct PathRec;
 template <> struct PathRec<float> {          // 64 bytes
     double s_tot;
-    float rev0;
-    uint32_t refl;
-    float4 q0, q1, q2;                        // (phi_e, mhat, Lh, qhat) (a_s, a_h, vs0, vs1) (vs2, vh0, vh1, vh2)
+    int16_t nc;                               // caustic quarter turns
+    int16_t refl;
+    float xh, uh, qhat;                       // see PathEval
+    float4 q0;                                // (ixh, sxh, a_s, a_h)
+    float4 q1;                                // (vs0, vs1, vs2, vh0)
+    float2 q2;                                // (vh1, vh2)
 };
-template <> struct PathRec<double> {         // 128 bytes
-    double s_tot, rev0;
-    uint64_t refl, pad;
-    double v[12];
+template <> struct PathRec<double> {         // 136 bytes
+    double s_tot;
+    int32_t nc, refl;
+    double v[15];
 };
 
 __device__ __forceinline__ void pack(const PathEval<float>& p, PathRec<float>* r) {
     PathRec<float> o;
     o.s_tot = p.s_tot;
-    o.rev0 = (float)p.rev0;
-    o.refl = (uint32_t)p.refl;
-    o.q0 = make_float4(p.phi_e, p.mhat, p.Lh, p.qhat);
-    o.q1 = make_float4(p.a_s, p.a_h, p.vs[0], p.vs[1]);
-    o.q2 = make_float4(p.vs[2], p.vh[0], p.vh[1], p.vh[2]);
+    o.nc = (int16_t)p.nc;
+    o.refl = (int16_t)p.refl;
+    o.xh = p.xh; o.uh = p.uh; o.qhat = p.qhat;
+    o.q0 = make_float4(p.ixh, p.sxh, p.a_s, p.a_h);
+    o.q1 = make_float4(p.vs[0], p.vs[1], p.vs[2], p.vh[0]);
+    o.q2 = make_float2(p.vh[1], p.vh[2]);
     *r = o;
 }
 __device__ __forceinline__ void unpack(const PathRec<float>& o, PathEval<float>* p) {
     p->s_tot = o.s_tot;
-    p->rev0 = o.rev0;
-    p->refl = (int)o.refl;
-    p->phi_e = o.q0.x; p->mhat = o.q0.y; p->Lh = o.q0.z; p->qhat = o.q0.w;
-    p->a_s = o.q1.x; p->a_h = o.q1.y; p->vs[0] = o.q1.z; p->vs[1] = o.q1.w;
-    p->vs[2] = o.q2.x; p->vh[0] = o.q2.y; p->vh[1] = o.q2.z; p->vh[2] = o.q2.w;
+    p->nc = o.nc;
+    p->refl = o.refl;
+    p->xh = o.xh; p->uh = o.uh; p->qhat = o.qhat;
+    p->ixh = o.q0.x; p->sxh = o.q0.y; p->a_s = o.q0.z; p->a_h = o.q0.w;
+    p->vs[0] = o.q1.x; p->vs[1] = o.q1.y; p->vs[2] = o.q1.z; p->vh[0] = o.q1.w;
+    p->vh[1] = o.q2.x; p->vh[2] = o.q2.y;
 }
 __device__ __forceinline__ void pack(const PathEval<double>& p, PathRec<double>* r) {
     PathRec<double> o;
-    o.s_tot = p.s_tot; o.rev0 = p.rev0; o.refl = (uint64_t)p.refl; o.pad = 0;
-    double v[12] = {p.phi_e, p.mhat, p.Lh, p.qhat, p.a_s, p.a_h, p.vs[0], p.vs[1], p.vs[2], p.vh[0], p.vh[1], p.vh[2]};
-    for (int k = 0; k < 12; ++k) o.v[k] = v[k];
+    o.s_tot = p.s_tot; o.nc = p.nc; o.refl = p.refl;
+    double v[15] = {p.xh, p.uh, p.qhat, p.ixh, p.sxh, p.a_s, p.a_h, p.vs[0], p.vs[1], p.vs[2],
+                    p.vh[0], p.vh[1], p.vh[2], 0.0, 0.0};
+    for (int k = 0; k < 15; ++k) o.v[k] = v[k];
     *r = o;
 }
 __device__ __forceinline__ void unpack(const PathRec<double>& o, PathEval<double>* p) {
-    p->s_tot = o.s_tot; p->rev0 = o.rev0; p->refl = (int)o.refl;
-    p->phi_e = o.v[0]; p->mhat = o.v[1]; p->Lh = o.v[2]; p->qhat = o.v[3];
-    p->a_s = o.v[4]; p->a_h = o.v[5];
-    p->vs[0] = o.v[6]; p->vs[1] = o.v[7]; p->vs[2] = o.v[8];
-    p->vh[0] = o.v[9]; p->vh[1] = o.v[10]; p->vh[2] = o.v[11];
+    p->s_tot = o.s_tot; p->nc = o.nc; p->refl = o.refl;
+    p->xh = o.v[0]; p->uh = o.v[1]; p->qhat = o.v[2]; p->ixh = o.v[3]; p->sxh = o.v[4];
+    p->a_s = o.v[5]; p->a_h = o.v[6];
+    p->vs[0] = o.v[7]; p->vs[1] = o.v[8]; p->vs[2] = o.v[9];
+    p->vh[0] = o.v[10]; p->vh[1] = o.v[11]; p->vh[2] = o.v[12];
 }
 
 // Visibility and path constants.  grid: x over receivers (blockDim 256),
@@ -196,25 +203,34 @@ __global__ void __launch_bounds__(256) k_paths(LaunchParams L, const float* __re
 template <typename R> struct FreqC;
 template <> struct FreqC<float> {
     double rev_per_m;
-    float kf, k13, k16, km16;
+    float kf, k13, k16, km16, sk, ik13;
     __device__ __forceinline__ FreqC(const FreqConst& c)
-        : rev_per_m(c.rev_per_m), kf(c.kf), k13(c.k13f), k16(c.k16f), km16(c.km16f) {}
+        : rev_per_m(c.rev_per_m), kf(c.kf), k13(c.k13f), k16(c.k16f), km16(c.km16f), sk(c.skf), ik13(c.ik13f) {}
 };
 template <> struct FreqC<double> {
     double rev_per_m;
-    double kf, k13, k16, km16;
+    double kf, k13, k16, km16, sk, ik13;
     __device__ __forceinline__ FreqC(const FreqConst& c)
-        : rev_per_m(c.rev_per_m), kf(c.kd), k13(c.k13d), k16(c.k16d), km16(c.km16d) {}
+        : rev_per_m(c.rev_per_m), kf(c.kd), k13(c.k13d), k16(c.k16d), km16(c.km16d), sk(c.skd), ik13(c.ik13d) {}
 };
 
+// One path at one frequency: the Fock arguments scale with powers of k
+// (xi ~ k^{1/3}, sqrt(X) ~ k^{1/2}, q ~ k^{1/6}), so they are products of the
+// path's constants and the frequency's.  any_refl tells whether any lane of
+// the wavefront holds a reflection (the e^{-j xi^3/12} factor is skipped
+// otherwise).
 template <typename R>
-__device__ __forceinline__ void add_path(const PathEval<R>& pe, const Tabs<R>& tb, const FreqC<R>& fc, R* E) {
-    R xi = pe.mhat * fc.k13 * pe.phi_e;
-    R X = fc.kf * pe.Lh * pe.phi_e * pe.phi_e;
-    R q = fc.k16 * pe.qhat;
+__device__ __forceinline__ void add_path(const PathEval<R>& pe, const Tabs<R>& tb, const FreqC<R>& fc,
+                                         bool any_refl, R* E) {
+    FockArgs<R> a;
+    a.xi = fc.k13 * pe.xh;
+    a.u = fc.sk * pe.uh;
+    a.q = fc.k16 * pe.qhat;
+    a.ixi = fc.ik13 * pe.ixh;
+    a.h = (R)0.5 * fc.k16 * pe.sxh;
     cplx<R> Ks, Kh;
-    fock_kernel<R>(tb, xi, X, q, pe.refl != 0, &Ks, &Kh);
-    cplx<R> ph = phase_rev<R>(fc.rev_per_m * pe.s_tot + pe.rev0);
+    fock_kernel<R>(tb, a, pe.refl != 0, any_refl, &Ks, &Kh);
+    cplx<R> ph = phase_rev<R>(fc.rev_per_m * pe.s_tot - 0.25 * pe.nc);
     R as = pe.a_s * fc.km16, ah = pe.a_h * fc.km16;
     cplx<R> cs = cmul(Ks, ph), ch = cmul(Kh, ph);
     cs.re *= as; cs.im *= as;
@@ -332,11 +348,12 @@ __global__ void __launch_bounds__(256) k_field(LaunchParams L, const float* __re
             for (int k = 0; k < n; ++k) {
                 PathEval<R> pe;
                 unpack(rec[((int64_t)b * S + k) * L.n_rx + i], &pe);
+                bool any_refl = __any(pe.refl != 0);
 #pragma unroll
                 for (int j = 0; j < FC; ++j) {
                     if (j < nfc) {
                         FreqC<R> fc(fcs[f0 + j]);
-                        add_path<R>(pe, tb, fc, E[j]);
+                        add_path<R>(pe, tb, fc, any_refl, E[j]);
                     }
                 }
             }
