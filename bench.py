@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config5", "config1"])
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=1536, help="receivers in the oracle sample")
+    ap.add_argument("--adjoint", type=int, default=1,
+                    help="also time forward + backward on the adjoint workload (room, 64 cylinders, 128^2 rx, 16 f)")
+    ap.add_argument("--adjoint-steps", type=int, default=3)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device copy of this size (HBM counter calibration under a profiler)")
     return ap.parse_args()
@@ -85,6 +88,58 @@ def _oracle_chunk(a):
     from oracle import field
     sc, tx, rx, freqs = a
     return field.field(sc, tx, rx, freqs).shape
+
+
+def _timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def adjoint_bench(steps):
+    """Forward and backward (loss = sum |E|^2, so dL/dE = 2E) on the adjoint
+    workload, FP32, inputs resident; the backward recomputes classification
+    and visibility itself (it takes no state from the forward call)."""
+    import torch
+
+    import paper_2310_10578_amd as utd
+    import workloads as W
+    cfg = W.config5()
+    dev = "cuda:0"
+    sc = cfg["scene"]
+    scene = utd.Scene(sc.get("tri"))
+    sph = torch.from_numpy(np.ascontiguousarray(sc["spheres"], np.float32)).to(dev)
+    cyl = torch.from_numpy(np.ascontiguousarray(sc["cylinders"], np.float32)).to(dev)
+    rx = torch.from_numpy(cfg["rx"]).to(dev)
+    freqs = torch.tensor(cfg["freqs"], dtype=torch.float64, device=dev)
+    src = utd.make_source(cfg["tx"]["pos"], cfg["tx"]["dipole"], cfg["tx"]["amplitude"])
+    n_rx, n_f, n_body = rx.shape[0], freqs.shape[0], sph.shape[0] + cyl.shape[0]
+    out = torch.empty((n_f, 3, n_rx), dtype=torch.complex64, device=dev)
+    flags = torch.empty((n_rx,), dtype=torch.uint8, device=dev)
+    utd.smooth_field(scene, sph, cyl, src, rx, freqs, out=out, flags=flags)
+    gE = 2 * out
+    fwd = _timed(lambda: utd.smooth_field(scene, sph, cyl, src, rx, freqs, out=out, flags=flags), steps, 1)
+    utd.profile_enable(True)
+    utd.profile_read()
+    bwd = _timed(lambda: utd.smooth_field_backward(scene, sph, cyl, src, rx, freqs, gE), steps, 1)
+    prof = utd.profile_read()
+    utd.profile_enable(False)
+    evals = n_rx * n_body * n_f
+    scene.close()
+    return {"workload": cfg["name"], "evals_per_step": evals, "fwd_ms": fwd, "bwd_ms": bwd,
+            "bwd_over_fwd": bwd / fwd, "fwd_evals_per_s": evals / (fwd / 1e3),
+            "bwd_evals_per_s": evals / (bwd / 1e3), "gradients": 3 + 3 * n_body,
+            "bwd_kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]}}
 
 
 def main():
@@ -172,6 +227,8 @@ def main():
         "kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]},
         "wall_s": wall,
     }
+    if args.adjoint:
+        res["adjoint"] = adjoint_bench(args.adjoint_steps)
     if args.cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(cfg, min(args.cpu_sample, n_rx))
     print(json.dumps(res))

@@ -120,21 +120,30 @@ utd_status utd_smooth_field(const utd_scene *scene, const utd_bodies *bodies,
                             const double *freqs_hz, int n_f, const utd_options *opt,
                             void *E_out, uint8_t *rx_flags, void *stream);
 
-/* Adjoint of utd_smooth_field for L(E) with dL/dE given as grad_E (same
- * layout and precision as E_out): writes
+/* Adjoint of utd_smooth_field (gradients for optimisation over the scene,
+ * Sec. I / Sec. II-B: the field of Eqs. (1)-(4) is differentiable in the
+ * body parameters and the source position wherever the visibility of every
+ * path is unchanged).  For a real loss L(E) with grad_E = dL/dRe(E) + j dL/dIm(E)
+ * (same layout and precision as E_out) writes
  *   d_cyl[n_cyl][3] = dL/d(cx, cy, a) per cylinder,
  *   d_sph[n_sph][4] = dL/d(cx, cy, cz, a) per sphere,
  *   d_tx[3]         = dL/d(source position),
- * all device float32, fully overwritten, with dL/dtheta = Re sum conj(grad_E) dE/dtheta
- * (the convention of PyTorch's complex autograd).  Visibility decisions and
- * path classification are those of the forward evaluation at the same
- * inputs and are held fixed (the field is piecewise smooth).  The
- * reduction over receivers and frequencies is deterministic.
- * Errors as for utd_smooth_field; d_* may be NULL when the matching count is 0. */
+ * i.e. dL/dtheta = Re sum conj(grad_E) dE/dtheta (PyTorch's convention for
+ * complex autograd).  All three are device arrays of float32 when
+ * opt->precision == 0 and float64 when 1, fully overwritten (zeros when
+ * n_rx == 0 or n_f == 0).  Cylinder heights (z0, h) only move visibility
+ * boundaries and get no gradient.  Path classification and visibility are
+ * those of the forward evaluation at the same inputs and are held fixed;
+ * receivers inside a body or with the source inside one contribute nothing.
+ * The reduction over receivers and frequencies runs in FP64 in a fixed order
+ * (bitwise reproducible).  Allocates stream-ordered workspace like
+ * utd_smooth_field.
+ * Errors as for utd_smooth_field; UTD_E_ARG if d_tx is NULL, d_cyl / d_sph is
+ * NULL with a non-zero count, or grad_E is NULL with n_rx, n_f > 0. */
 utd_status utd_smooth_field_backward(const utd_scene *scene, const utd_bodies *bodies,
                                      const utd_source *tx, const float *rx, int64_t n_rx,
                                      const double *freqs_hz, int n_f, const utd_options *opt,
-                                     const void *grad_E, float *d_cyl, float *d_sph, float *d_tx,
+                                     const void *grad_E, void *d_cyl, void *d_sph, void *d_tx,
                                      void *stream);
 
 /* Many frames in one launch: frame f has cylinders cyl[body_off[f] .. body_off[f+1])

@@ -71,13 +71,16 @@ def source_inside(scene, T):
     return bool(inside_mask(scene, np.asarray(T, dtype=float)[None, :])[0])
 
 
-def classify(scene, T, R, opts=None):
-    """All frequency-independent path data and the visibility decisions."""
+def classify(scene, T, R, opts=None, visibility=True):
+    """All frequency-independent path data and the visibility decisions
+    (``visibility=False`` skips the occlusion tests: every geometrically
+    valid path counts as visible and the line of sight as blocked; used when
+    the decisions are taken from an earlier call)."""
     with np.errstate(divide="ignore", invalid="ignore"):
-        return _classify(scene, T, R, opts)
+        return _classify(scene, T, R, opts, visibility)
 
 
-def _classify(scene, T, R, opts):
+def _classify(scene, T, R, opts, visibility=True):
     o = _opts(opts)
     sc = _scene(scene)
     T = np.asarray(T, dtype=float)
@@ -86,7 +89,10 @@ def _classify(scene, T, R, opts):
     inside = inside_mask(sc, R)
     flags = np.where(inside, FLAG_INSIDE, 0).astype(np.uint8)
     Tb = np.broadcast_to(T, R.shape)
-    los = ~occlusion.segments_blocked(sc, Tb, R, skip=None, bodies=True) & ~inside
+    if visibility:
+        los = ~occlusion.segments_blocked(sc, Tb, R, skip=None, bodies=True) & ~inside
+    else:
+        los = np.zeros(n, dtype=bool)
     flags |= np.where(los, FLAG_LOS, 0).astype(np.uint8)
     paths = []
     bodies = [("s", i, b) for i, b in enumerate(sc["spheres"])] + [("c", i, b) for i, b in enumerate(sc["cylinders"])]
@@ -112,7 +118,7 @@ def _classify(scene, T, R, opts):
                 segs = [(Tb, rec["Q1"]), (rec["Q2"], R)]
             else:
                 segs = [(Tb, rec["Q"]), (rec["Q"], R)]
-            for p0, p1 in segs:
+            for p0, p1 in (segs if visibility else ()):
                 idx = np.nonzero(valid)[0]
                 if idx.size:
                     blk = occlusion.segments_blocked(sc, p0[idx], p1[idx], skip=(kind, i),
@@ -146,7 +152,7 @@ def field(scene, tx, rx, freqs, opts=None, mode="em", frozen=None, return_info=F
     amp = float(tx.get("amplitude", 1.0))
     R = np.asarray(rx, dtype=float).reshape(-1, 3)
     freqs = np.atleast_1d(np.asarray(freqs, dtype=float))
-    info = classify(sc, T, R, o)
+    info = classify(sc, T, R, o, visibility=frozen is None)
     if frozen is not None:
         info["los"] = frozen["los"]
         info["inside"] = frozen["inside"]

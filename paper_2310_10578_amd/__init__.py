@@ -205,6 +205,74 @@ def smooth_field(scene, spheres, cylinders, source, rx, freqs, precision=0, l_en
     return out, flags
 
 
+def smooth_field_backward(scene, spheres, cylinders, source, rx, freqs, grad_E, precision=0, l_enc=0,
+                          bodies_occlude=True, lit_branch=True, caustic_guard=1e-6, stream=None):
+    """Gradients of L with dL/dE = grad_E ([nf, 3, n], complex64 for precision 0,
+    complex128 for 1): returns (d_sph [ns, 4], d_cyl [nc, 3], d_tx [3]) on the GPU,
+    float32 or float64 by precision.  d_cyl columns are (cx, cy, a)."""
+    torch = _torch()
+    lib = load_library()
+    _dev(rx, torch.float32, (3,), "rx")
+    _dev(freqs, torch.float64, None, "freqs")
+    b, keep = _bodies(spheres, cylinders)
+    n, nf = rx.shape[0], freqs.shape[0]
+    cdt = torch.complex64 if precision == 0 else torch.complex128
+    rdt = torch.float32 if precision == 0 else torch.float64
+    _dev(grad_E, cdt, (3, n), "grad_E")
+    if grad_E.shape[0] != nf:
+        raise ValueError("grad_E must have shape [n_f, 3, n_rx]")
+    d_sph = torch.empty((b.n_sph, 4), dtype=rdt, device=rx.device)
+    d_cyl = torch.empty((b.n_cyl, 3), dtype=rdt, device=rx.device)
+    d_tx = torch.empty((3,), dtype=rdt, device=rx.device)
+    opt = make_options(precision, l_enc, bodies_occlude, lit_branch, caustic_guard)
+    _check(lib.utd_smooth_field_backward(
+        scene.handle if scene is not None else None, ctypes.byref(b), ctypes.byref(source),
+        rx.data_ptr() if n else None, n, freqs.data_ptr() if nf else None, nf, ctypes.byref(opt),
+        grad_E.data_ptr() if grad_E.numel() else None, d_cyl.data_ptr() if d_cyl.numel() else None,
+        d_sph.data_ptr() if d_sph.numel() else None, d_tx.data_ptr(), _stream(stream)))
+    return d_sph, d_cyl, d_tx
+
+
+def _autograd_function():
+    torch = _torch()
+
+    class _SmoothField(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, spheres, cylinders, tx_pos, rx, freqs, scene, dipole, amplitude, kw):
+            src = make_source([float(v) for v in tx_pos.detach().cpu().tolist()], dipole, amplitude)
+            sph, cyl = spheres.detach().contiguous(), cylinders.detach().contiguous()
+            E, _ = smooth_field(scene, sph, cyl, src, rx, freqs, **kw)
+            ctx.save_for_backward(sph, cyl, rx, freqs)
+            ctx.scene, ctx.src, ctx.kw, ctx.tx_meta = scene, src, kw, (tx_pos.dtype, tx_pos.device)
+            return E
+
+        @staticmethod
+        def backward(ctx, gE):
+            sph, cyl, rx, freqs = ctx.saved_tensors
+            d_sph, d_cyl3, d_tx = smooth_field_backward(ctx.scene, sph, cyl, ctx.src, rx, freqs,
+                                                        gE.resolve_conj().resolve_neg().contiguous(),
+                                                        **ctx.kw)
+            d_cyl = torch.zeros(cyl.shape, dtype=d_cyl3.dtype, device=cyl.device)
+            d_cyl[:, 0:2] = d_cyl3[:, 0:2]
+            d_cyl[:, 4] = d_cyl3[:, 2]
+            dt, dev = ctx.tx_meta
+            return (d_sph.to(sph.dtype), d_cyl.to(cyl.dtype), d_tx.to(dtype=dt, device=dev),
+                    None, None, None, None, None, None)
+
+    return _SmoothField
+
+
+def field(scene, spheres, cylinders, tx_pos, rx, freqs, dipole=(0.0, 0.0, 1.0), amplitude=1.0, precision=0,
+          l_enc=0, bodies_occlude=True, lit_branch=True, caustic_guard=1e-6):
+    """Differentiable forward field: E[f, c, n] as ``smooth_field``, with
+    PyTorch autograd through ``utd_smooth_field_backward`` for ``spheres``,
+    ``cylinders`` (columns cx, cy, a; heights get zero) and ``tx_pos`` (a
+    3-vector tensor, CPU or GPU)."""
+    kw = dict(precision=precision, l_enc=l_enc, bodies_occlude=bodies_occlude, lit_branch=lit_branch,
+              caustic_guard=caustic_guard)
+    return _autograd_function().apply(spheres, cylinders, tx_pos, rx, freqs, scene, dipole, amplitude, kw)
+
+
 def profile_enable(on=True):
     """Record HIP event pairs around every kernel launch (measurement only)."""
     load_library().utd_profile_enable(int(bool(on)))

@@ -1,0 +1,353 @@
+// Adjoint of the field evaluation: gradients of a real loss
+// L = Re sum_{f,c,n} conj(g_{f,c,n}) E_{f,c,n} with respect to the source
+// position and the body parameters, with the path classification and the
+// visibility of the forward evaluation held fixed.  Included by
+// utd_kernels.hip after the forward kernels (it reuses their path records,
+// table staging and frequency constants).
+//
+// Per (receiver, body) lane and per valid path:
+//   1. record adjoint (reverse mode over the frequency loop): lambda_r =
+//      dL/dr for every frequency-independent record scalar r (path length,
+//      Fock constants xh / uh / qhat, amplitudes, polarisation vectors),
+//      summed over all frequencies.  The partial derivatives of the Fock
+//      coefficients come from the table polynomials evaluated on dual numbers
+//      (three directions: xh, uh, qhat).
+//   2. geometry tangents (forward mode): the path geometry re-evaluated on
+//      dual numbers once per parameter (3 source coordinates, then the
+//      body's centre and radius) gives dr/dtheta; dL/dtheta += sum_r lambda_r dr/dtheta.
+// The reflection point enters through one Newton step of its stationarity
+// condition taken on duals (implicit differentiation).  The direct ray's
+// gradient (source only) uses the same two steps.
+//
+// Reduction: each lane holds 7 FP64 sums (3 source + up to 4 body); a fixed
+// shuffle tree and a fixed LDS order reduce them per block, a second kernel
+// sums the blocks of each (body slot) in a fixed order and a third sums the
+// source partials over slots: the result does not depend on scheduling.
+#pragma once
+
+namespace utd {
+
+constexpr int kAdjComp = 8;   // per-block record: 3 source + 4 body + pad
+
+template <typename R> struct RecAdj {
+    double s;                  // path length (the phase term dominates)
+    R xh, uh, qhat, a_s, a_h;
+    R vs[3], vh[3];
+};
+
+// Step 1: lambda for one path from the frequencies' gradients.
+template <typename R>
+__device__ __forceinline__ void record_adjoint(const PathEval<R>& pe, const Tabs<R>& tb,
+                                               const FreqConst* __restrict__ fcs, int n_f,
+                                               const R* __restrict__ gE, int64_t n_rx, int64_t i, RecAdj<R>* out) {
+    using D = Dual<R>;
+    RecAdj<R> l;
+    l.s = 0.0;
+    l.xh = l.uh = l.qhat = l.a_s = l.a_h = (R)0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) l.vs[c] = l.vh[c] = (R)0;
+    const bool refl = pe.refl != 0;
+    for (int f = 0; f < n_f; ++f) {
+        FreqC<R> fc(fcs[f]);
+        cplx<R> g[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            int64_t o = ((int64_t)f * 3 + c) * n_rx + i;
+            g[c] = cplx<R>{gE[2 * o], gE[2 * o + 1]};
+        }
+        // Fock arguments and their derivatives along xh (xi, 1/xi and
+        // sqrt(-xi)/2 move together), uh and qhat
+        R xi = fc.k13 * pe.xh, u = fc.sk * pe.uh, q = fc.k16 * pe.qhat;
+        R ixi = fc.ik13 * pe.ixh, h = (R)0.5 * fc.k16 * pe.sxh;
+        R dixi = -fc.ik13 * pe.ixh * pe.ixh;
+        R dh = pe.sxh > (R)0 ? (R)-0.25 * fc.k16 / pe.sxh : (R)0;
+        cplx<R> Ks, Kh, dKs[3], dKh[3];
+#pragma unroll
+        for (int dir = 0; dir < 3; ++dir) {
+            FockArgs<D> a;
+            a.xi = D(xi, dir == 0 ? fc.k13 : (R)0);
+            a.u = D(u, dir == 1 ? fc.sk : (R)0);
+            a.q = D(q, dir == 2 ? fc.k16 : (R)0);
+            a.ixi = D(ixi, dir == 0 ? dixi : (R)0);
+            a.h = D(h, dir == 0 ? dh : (R)0);
+            cplx<D> ks, kh;
+            fock_kernel<D>(tb, a, refl, refl, &ks, &kh);
+            if (dir == 0) {
+                Ks = cplx<R>{ks.re.v, ks.im.v};
+                Kh = cplx<R>{kh.re.v, kh.im.v};
+            }
+            dKs[dir] = cplx<R>{ks.re.d, ks.im.d};
+            dKh[dir] = cplx<R>{kh.re.d, kh.im.d};
+        }
+        cplx<R> ph = phase_rev<R>(fc.rev_per_m * pe.s_tot - 0.25 * pe.nc);
+        cplx<R> P{ph.re * fc.km16, ph.im * fc.km16};
+        // gs = sum_c conj(g_c) vs_c, gh = sum_c conj(g_c) vh_c
+        cplx<R> gs{(R)0, (R)0}, gh{(R)0, (R)0};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            gs.re += g[c].re * pe.vs[c]; gs.im -= g[c].im * pe.vs[c];
+            gh.re += g[c].re * pe.vh[c]; gh.im -= g[c].im * pe.vh[c];
+        }
+        cplx<R> Zs = cmul(P, gs), Zh = cmul(P, gh);
+        // L_f = Re(a_s K_s Zs + a_h K_h Zh)
+        cplx<R> KZs = cmul(Ks, Zs), KZh = cmul(Kh, Zh);
+        l.a_s += KZs.re;
+        l.a_h += KZh.re;
+        l.s += kTwoPi * fc.rev_per_m * (double)(pe.a_s * KZs.im + pe.a_h * KZh.im);
+        R dx[3];
+#pragma unroll
+        for (int dir = 0; dir < 3; ++dir)
+            dx[dir] = pe.a_s * (dKs[dir].re * Zs.re - dKs[dir].im * Zs.im) +
+                      pe.a_h * (dKh[dir].re * Zh.re - dKh[dir].im * Zh.im);
+        l.xh += dx[0];
+        l.uh += dx[1];
+        l.qhat += dx[2];
+        cplx<R> Ws = cmul(P, Ks), Wh = cmul(P, Kh);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            l.vs[c] += pe.a_s * (Ws.re * g[c].re + Ws.im * g[c].im);
+            l.vh[c] += pe.a_h * (Wh.re * g[c].re + Wh.im * g[c].im);
+        }
+    }
+    *out = l;
+}
+
+// Step 2: sum_r lambda_r dr/dtheta for one tangent.
+template <typename R, typename RD, typename GD>
+__device__ __forceinline__ double contract(const RecAdj<R>& l, const PathEvalT<RD, GD>& p) {
+    R r = l.xh * p.xh.d + l.uh * p.uh.d + l.qhat * p.qhat.d + l.a_s * p.a_s.d + l.a_h * p.a_h.d;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) r += l.vs[c] * p.vs[c].d + l.vh[c] * p.vh[c].d;
+    return l.s * p.s_tot.d + (double)r;
+}
+
+// Direct ray T -> R: E_c = (amp / s) (p - (p.s) s)_c e^{-j 2 pi (f/c) s}.
+template <typename R>
+__device__ __forceinline__ void los_adjoint(const LaunchParams& L, d3 R3, const FreqConst* __restrict__ fcs,
+                                            const R* __restrict__ gE, int64_t i, double acc[kAdjComp]) {
+    using GD = Dual<double>;
+    using RD = Dual<R>;
+    d3 v0 = mk(R3.x - L.T[0], R3.y - L.T[1], R3.z - L.T[2]);
+    double sd0 = norm(v0);
+    // amplitude vector in R (as the forward kernel)
+    R isd = (R)(1.0 / sd0);
+    R shx = (R)v0.x * isd, shy = (R)v0.y * isd, shz = (R)v0.z * isd;
+    R px = (R)L.p[0], py = (R)L.p[1], pz = (R)L.p[2];
+    R pd = px * shx + py * shy + pz * shz;
+    R A = (R)L.amp * isd;
+    R e3[3] = {A * (px - pd * shx), A * (py - pd * shy), A * (pz - pd * shz)};
+    // lambda of the path length (phase) and of the amplitude vector
+    double lsd = 0.0;
+    R le[3] = {(R)0, (R)0, (R)0};
+    for (int f = 0; f < L.n_f; ++f) {
+        double rev = fcs[f].rev_per_m;
+        cplx<R> ph = phase_rev<R>(rev * sd0);
+        R im = (R)0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            int64_t o = ((int64_t)f * 3 + c) * L.n_rx + i;
+            R gr = gE[2 * o], gi = gE[2 * o + 1];
+            le[c] += gr * ph.re + gi * ph.im;
+            im += e3[c] * (gr * ph.im - gi * ph.re);
+        }
+        lsd += kTwoPi * rev * (double)im;
+    }
+#pragma unroll 1
+    for (int dir = 0; dir < 3; ++dir) {
+        V3<GD> v{GD(R3.x - L.T[0], dir == 0 ? -1.0 : 0.0), GD(R3.y - L.T[1], dir == 1 ? -1.0 : 0.0),
+                 GD(R3.z - L.T[2], dir == 2 ? -1.0 : 0.0)};
+        GD sd = gnorm(v);
+        RD is = (RD)(GD(1.0) / sd);
+        RD sx = (RD)v.x * is, sy = (RD)v.y * is, sz = (RD)v.z * is;
+        RD pdd = px * sx + py * sy + pz * sz;
+        RD Ad = (RD)L.amp * is;
+        RD ex = Ad * (px - pdd * sx), ey = Ad * (py - pdd * sy), ez = Ad * (pz - pdd * sz);
+        acc[dir] += lsd * sd.d + (double)(le[0] * ex.d + le[1] * ey.d + le[2] * ez.d);
+    }
+}
+
+// All valid paths of one (receiver, body) pair.
+template <typename R>
+__device__ __forceinline__ void body_adjoint(const LaunchParams& L, d3 R3, int b, const float* __restrict__ sph,
+                                             const float* __restrict__ cyl, const BodyPrep& P0,
+                                             const FreqConst* __restrict__ fcs, uint8_t m,
+                                             const PathRec<R>* __restrict__ rec, const Tabs<R>& tb,
+                                             const R* __restrict__ gE, int64_t i, double acc[kAdjComp]) {
+    using GD = Dual<double>;
+    using RD = Dual<R>;
+    const int S = 2 * (L.l_enc + 1);
+    const bool is_sph = b < L.n_sph;
+    double bp[4];
+    double z0 = 0.0, hh = 0.0;
+    if (is_sph) {
+        const float* s = sph + 4 * b;
+        bp[0] = s[0]; bp[1] = s[1]; bp[2] = s[2]; bp[3] = s[3];
+    } else {
+        const float* c = cyl + 5 * (b - L.n_sph);
+        bp[0] = c[0]; bp[1] = c[1]; bp[2] = c[4]; bp[3] = 0.0;
+        z0 = c[2]; hh = c[3];
+    }
+    const int ndir = is_sph ? 7 : 6;
+    d3 T0 = mk(L.T[0], L.T[1], L.T[2]);
+    V3<GD> Rg{GD(R3.x), GD(R3.y), GD(R3.z)};
+    int k = 0;
+    for (int bit = 0; bit <= kBitRefl; ++bit) {
+        if (!((m >> bit) & 1u)) continue;
+        if (bit < kBitRefl && bit >= 2 * (L.l_enc + 1)) continue;
+        if (k >= S) break;
+        PathEval<R> pe;
+        unpack(rec[((int64_t)b * S + k) * L.n_rx + i], &pe);
+        ++k;
+        RecAdj<R> lam;
+        record_adjoint<R>(pe, tb, fcs, L.n_f, gE, L.n_rx, i, &lam);
+        const bool refl = bit == kBitRefl;
+        const int ell = bit >> 1, sgn = (bit & 1) ? -1 : 1;
+        double th = 0.0;
+        if (refl) {
+            RxGeo g0 = rx_geo<double>(P0, R3);
+            if (!refl_angle(P0, g0, R3, T0, &th)) continue;
+        }
+#pragma unroll 1
+        for (int dir = 0; dir < ndir; ++dir) {
+            V3<GD> T{GD(T0.x, dir == 0 ? 1.0 : 0.0), GD(T0.y, dir == 1 ? 1.0 : 0.0), GD(T0.z, dir == 2 ? 1.0 : 0.0)};
+            GD p0(bp[0], dir == 3 ? 1.0 : 0.0), p1(bp[1], dir == 4 ? 1.0 : 0.0), p2(bp[2], dir == 5 ? 1.0 : 0.0);
+            BodyPrepT<GD> P = is_sph ? prep_sphere<GD>(T, V3<GD>{p0, p1, p2}, GD(bp[3], dir == 6 ? 1.0 : 0.0))
+                                     : prep_cylinder<GD>(T, p0, p1, z0, hh, p2);
+            RxGeoT<GD> g = rx_geo<GD>(P, Rg);
+            PathEvalT<RD, GD> pd;
+            bool ok = true;
+            if (refl) {
+                GD thd = refl_angle_g<GD>(P, g, Rg, T, th);
+                V3<GD> Q, n;
+                refl_point<GD>(P, g, Rg, T, thd, &Q, &n);
+                refl_eval<RD, GD>(P, Q, n, Rg, T, L, &pd);
+            } else if (is_sph) {
+                bool cz;
+                ok = sphere_creep<RD, GD>(P, g, Rg, T, L, sgn, ell, &cz, &pd, nullptr);
+            } else {
+                ok = cyl_creep<RD, GD>(P, g, Rg, T, L, sgn, ell, &pd, nullptr);
+            }
+            if (ok) acc[dir] += contract(lam, pd);
+        }
+    }
+}
+
+// grid: x over receivers (256 per block), y over slot = 0 (direct ray) or
+// 1 + body.  partial[(slot * gridDim.x + block) * kAdjComp + d].
+template <typename R>
+__global__ void __launch_bounds__(256) k_adjoint(LaunchParams L, const float* __restrict__ rx,
+                                                 const float* __restrict__ sph, const float* __restrict__ cyl,
+                                                 const BodyPrep* __restrict__ prep, const FreqConst* __restrict__ fcs,
+                                                 const uint8_t* __restrict__ mask, const PathRec<R>* __restrict__ rec,
+                                                 const uint8_t* __restrict__ flags, const R* __restrict__ gE,
+                                                 double* __restrict__ partial) {
+    __shared__ R s_reg[TableStage<R>::NREG];
+    __shared__ R s_tf[TableStage<R>::NTF];
+    __shared__ double s_red[4][kAdjComp];
+    Tabs<R> tb = TableStage<R>::stage(s_reg, s_tf);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int slot = blockIdx.y;
+    double acc[kAdjComp];
+#pragma unroll
+    for (int d = 0; d < kAdjComp; ++d) acc[d] = 0.0;
+    if (i < L.n_rx) {
+        uint8_t fl = flags[i];
+        if (!(fl & (kFlagInside | kFlagTxInside))) {
+            d3 R3 = mk(rx[3 * i], rx[3 * i + 1], rx[3 * i + 2]);
+            if (slot == 0) {
+                if ((fl & kFlagLos) && L.lit_branch) los_adjoint<R>(L, R3, fcs, gE, i, acc);
+            } else {
+                int b = slot - 1;
+                uint8_t m = mask[(int64_t)b * L.n_rx + i];
+                if (m & 0x7fu) body_adjoint<R>(L, R3, b, sph, cyl, prep[b], fcs, m, rec, tb, gE, i, acc);
+            }
+        }
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int d = 0; d < kAdjComp; ++d) {
+        double v = acc[d];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) s_red[wid][d] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kAdjComp) {
+        int d = threadIdx.x;
+        double t = (s_red[0][d] + s_red[1][d]) + (s_red[2][d] + s_red[3][d]);
+        partial[((int64_t)slot * gridDim.x + blockIdx.x) * kAdjComp + d] = t;
+    }
+}
+
+// Sum of the block partials of one slot (block per slot), fixed order.
+template <typename R>
+__global__ void __launch_bounds__(256) k_adjoint_reduce(const double* __restrict__ partial, int64_t nblk, int n_sph,
+                                                        R* __restrict__ d_sph, R* __restrict__ d_cyl,
+                                                        double* __restrict__ txpart) {
+    __shared__ double red[256];
+    const int slot = blockIdx.x;
+    for (int d = 0; d < 7; ++d) {
+        double s = 0.0;
+        for (int64_t j = threadIdx.x; j < nblk; j += 256) s += partial[((int64_t)slot * nblk + j) * kAdjComp + d];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            double t = red[0];
+            if (d < 3) {
+                txpart[slot * 3 + d] = t;
+            } else if (slot > 0) {
+                int b = slot - 1;
+                if (b < n_sph) d_sph[b * 4 + (d - 3)] = (R)t;
+                else if (d < 6) d_cyl[(b - n_sph) * 3 + (d - 3)] = (R)t;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <typename R>
+__global__ void k_adjoint_tx(const double* __restrict__ txpart, int nslot, R* __restrict__ d_tx) {
+    int d = threadIdx.x;
+    if (d < 3) {
+        double s = 0.0;
+        for (int k = 0; k < nslot; ++k) s += txpart[k * 3 + d];
+        d_tx[d] = (R)s;
+    }
+}
+
+template <typename R>
+static hipError_t launch_adjoint_t(const LaunchParams& L, const float* rx, const float* sph, const float* cyl,
+                                   const BodyPrep* prep, const FreqConst* fcs, const uint8_t* mask, const void* rec,
+                                   const uint8_t* flags, const void* gE, int64_t nblk, double* partial,
+                                   double* txpart, void* d_sph, void* d_cyl, void* d_tx, hipStream_t s) {
+    int nb = L.n_sph + L.n_cyl;
+    if (nblk > 0) {
+        dim3 grid((unsigned)nblk, (unsigned)(nb + 1));
+        hipLaunchKernelGGL((k_adjoint<R>), grid, dim3(256), 0, s, L, rx, sph, cyl, prep, fcs, mask,
+                           (const PathRec<R>*)rec, flags, (const R*)gE, partial);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_adjoint_reduce<R>), dim3(nb + 1), dim3(256), 0, s, partial, nblk, L.n_sph, (R*)d_sph,
+                       (R*)d_cyl, txpart);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_adjoint_tx<R>), dim3(1), dim3(64), 0, s, txpart, nb + 1, (R*)d_tx);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint(const LaunchParams& L, int precision, const float* rx, const float* sph, const float* cyl,
+                          const BodyPrep* prep, const FreqConst* fcs, const uint8_t* mask, const void* rec,
+                          const uint8_t* flags, const void* gE, int64_t nblk, double* partial, double* txpart,
+                          void* d_sph, void* d_cyl, void* d_tx, hipStream_t s) {
+    return precision == 0 ? launch_adjoint_t<float>(L, rx, sph, cyl, prep, fcs, mask, rec, flags, gE, nblk, partial,
+                                                    txpart, d_sph, d_cyl, d_tx, s)
+                          : launch_adjoint_t<double>(L, rx, sph, cyl, prep, fcs, mask, rec, flags, gE, nblk, partial,
+                                                     txpart, d_sph, d_cyl, d_tx, s);
+}
+
+}  // namespace utd

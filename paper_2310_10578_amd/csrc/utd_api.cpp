@@ -128,7 +128,9 @@ struct Workspace {
     void* rec = nullptr;
     uint8_t* flags = nullptr;
     unsigned long long* counters = nullptr;
-    hipError_t alloc(int nb, int64_t n_rx, int n_f, int l_enc, int precision, bool need_flags, hipStream_t s) {
+    char* extra = nullptr;
+    hipError_t alloc(int nb, int64_t n_rx, int n_f, int l_enc, int precision, bool need_flags, hipStream_t s,
+                     size_t extra_bytes = 0) {
         auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
         size_t nbb = (size_t)(nb > 0 ? nb : 1);
         size_t o_prep = 0;
@@ -138,7 +140,8 @@ struct Workspace {
         size_t rec_bytes = utd::path_record_bytes(precision) * (size_t)(2 * (l_enc + 1)) * (size_t)n_rx * nbb;
         size_t o_flag = up(o_rec + rec_bytes);
         size_t o_cnt = up(o_flag + (need_flags ? (size_t)n_rx : 0));
-        size_t total = o_cnt + 16 * sizeof(unsigned long long);
+        size_t o_extra = up(o_cnt + 16 * sizeof(unsigned long long));
+        size_t total = o_extra + extra_bytes;
         hipError_t e = hipMallocAsync((void**)&base, total, s);
         if (e != hipSuccess) return e;
         prep = (utd::BodyPrep*)(base + o_prep);
@@ -147,6 +150,7 @@ struct Workspace {
         rec = (void*)(base + o_rec);
         flags = need_flags ? (uint8_t*)(base + o_flag) : nullptr;
         counters = (unsigned long long*)(base + o_cnt);
+        extra = extra_bytes ? base + o_extra : nullptr;
         return hipSuccess;
     }
 };
@@ -306,10 +310,51 @@ utd_status utd_path_census(const utd_scene* scene, const utd_bodies* bodies, con
     return UTD_OK;
 }
 
-utd_status utd_smooth_field_backward(const utd_scene*, const utd_bodies*, const utd_source*, const float*, int64_t,
-                                     const double*, int, const utd_options*, const void*, float*, float*, float*,
-                                     void*) {
-    return fail(UTD_E_UNSUPPORTED, "backward not built yet");
+utd_status utd_smooth_field_backward(const utd_scene* scene, const utd_bodies* bodies, const utd_source* tx,
+                                     const float* rx, int64_t n_rx, const double* freqs, int n_f,
+                                     const utd_options* opt, const void* grad_E, void* d_cyl, void* d_sph, void* d_tx,
+                                     void* stream) {
+    utd_status st = check_common(bodies, tx, rx, n_rx, freqs, n_f, opt);
+    if (st != UTD_OK) return st;
+    if (!d_tx) return fail(UTD_E_ARG, "d_tx is NULL");
+    if (bodies->n_cyl && !d_cyl) return fail(UTD_E_ARG, "d_cyl is NULL with n_cyl > 0");
+    if (bodies->n_sph && !d_sph) return fail(UTD_E_ARG, "d_sph is NULL with n_sph > 0");
+    const bool work = n_rx > 0 && n_f > 0;
+    if (work && !grad_E) return fail(UTD_E_ARG, "grad_E is NULL");
+    hipError_t e = ensure_tables();
+    if (e != hipSuccess) return hip_fail(e, "table upload");
+    hipStream_t s = (hipStream_t)stream;
+    utd::LaunchParams L = make_params(bodies, tx, n_rx, n_f, opt);
+    int nb = L.n_sph + L.n_cyl;
+    int64_t nblk = work ? (n_rx + 255) / 256 : 0;
+    size_t n_part = (size_t)(nb + 1) * (size_t)nblk * 8;
+    size_t extra = sizeof(double) * (n_part + (size_t)(nb + 1) * 3) + 256;
+    Workspace w;
+    e = w.alloc(nb, work ? n_rx : 0, n_f, opt->l_enc, opt->precision, true, s, extra);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(UTD_E_OOM, "workspace allocation") : hip_fail(e, "hipMallocAsync");
+    double* partial = (double*)w.extra;
+    double* txpart = partial + ((n_part + 31) & ~(size_t)31);
+    const float4* nodes = scene ? scene->d_nodes : nullptr;
+    const float4* tris = scene ? scene->d_tris : nullptr;
+    if (work) {
+        ProfScope ps(UTD_K_PREP, s);
+        e = utd::launch_prep(L, bodies->sph, bodies->cyl, freqs, w.prep, w.fc, s);
+    }
+    if (work && e == hipSuccess) {
+        ProfScope ps(UTD_K_OCCLUDE, s);
+        e = utd::launch_paths(L, opt->precision, rx, bodies->sph, bodies->cyl, w.prep, nodes, tris, w.mask, w.rec,
+                              w.flags, s);
+    }
+    if (e == hipSuccess) {
+        ProfScope ps(UTD_K_BACKWARD, s);
+        e = utd::launch_adjoint(L, opt->precision, rx, bodies->sph, bodies->cyl, w.prep, w.fc, w.mask, w.rec, w.flags,
+                                grad_E, nblk, partial, txpart, d_sph, d_cyl, d_tx, s);
+    }
+    char* ws = w.base;
+    hipError_t e2 = hipFreeAsync(ws, s);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
+    return UTD_OK;
 }
 
 utd_status utd_smooth_field_batched(const utd_scene*, int64_t, const int64_t*, const float*, const int64_t*,

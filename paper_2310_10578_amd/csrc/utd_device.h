@@ -36,19 +36,19 @@ struct LaunchParams {
 };
 
 // Per-body quantities that depend only on the source (computed once per call).
-struct BodyPrep {
-    double c[3];      // sphere centre / cylinder axis point (cx, cy, 0)
-    double a;         // radius
+template <typename G> struct BodyPrepT {
+    G c[3];           // sphere centre / cylinder axis point (cx, cy, 0)
+    G a;              // radius
     double z0, h;     // cylinder lateral surface z0 .. z0 + h
-    double eT[3];     // sphere: unit (T - C); cylinder: unit (T - c) in xy
-    double dT;        // sphere: |T - C|; cylinder: rho_T (distance to axis)
-    double sI0;       // tangent length sqrt(dT^2 - a^2)
-    double gT;        // tangent half-angle gamma_T = atan2(sI0, a)
-    double aT;        // cylinder: azimuth of T about the axis
+    G eT[3];          // sphere: unit (T - C); cylinder: unit (T - c) in xy
+    G dT;             // sphere: |T - C|; cylinder: rho_T (distance to axis)
+    G sI0;            // tangent length sqrt(dT^2 - a^2)
+    G gT;             // tangent half-angle gamma_T = atan2(sI0, a)
+    G aT;             // cylinder: azimuth of T about the axis
     int kind;         // 0 sphere, 1 cylinder
     int ok;           // 1 if T lies outside the body's circle/sphere
-    int pad[2];
 };
+using BodyPrep = BodyPrepT<double>;
 
 // Per-frequency constants (computed once per call): phase revolutions per
 // metre f/c, wavenumber k and k^{1/3}, k^{1/6}, k^{-1/6} in both precisions.
@@ -59,16 +59,17 @@ struct FreqConst {
 };
 
 // ---------------------------------------------------------------------------
-// small vector helpers (double)
+// small vector helpers (plain double here; generic versions in utd_geom.h)
 // ---------------------------------------------------------------------------
-struct d3 { double x, y, z; };
+template <typename G> struct V3 { G x, y, z; };
+using d3 = V3<double>;
 __device__ __forceinline__ d3 mk(double x, double y, double z) { return d3{x, y, z}; }
-__device__ __forceinline__ d3 operator+(d3 a, d3 b) { return mk(a.x + b.x, a.y + b.y, a.z + b.z); }
-__device__ __forceinline__ d3 operator-(d3 a, d3 b) { return mk(a.x - b.x, a.y - b.y, a.z - b.z); }
-__device__ __forceinline__ d3 operator*(double s, d3 a) { return mk(s * a.x, s * a.y, s * a.z); }
-__device__ __forceinline__ double dot(d3 a, d3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
-__device__ __forceinline__ d3 cross(d3 a, d3 b) {
-    return mk(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+template <typename G> __device__ __forceinline__ V3<G> operator+(V3<G> a, V3<G> b) { return V3<G>{a.x + b.x, a.y + b.y, a.z + b.z}; }
+template <typename G> __device__ __forceinline__ V3<G> operator-(V3<G> a, V3<G> b) { return V3<G>{a.x - b.x, a.y - b.y, a.z - b.z}; }
+template <typename G, typename S> __device__ __forceinline__ V3<G> operator*(S s, V3<G> a) { return V3<G>{s * a.x, s * a.y, s * a.z}; }
+template <typename G> __device__ __forceinline__ G dot(V3<G> a, V3<G> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+template <typename G> __device__ __forceinline__ V3<G> cross(V3<G> a, V3<G> b) {
+    return V3<G>{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
 __device__ __forceinline__ double norm(d3 a) { return sqrt(dot(a, a)); }
 

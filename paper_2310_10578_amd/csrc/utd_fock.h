@@ -17,6 +17,7 @@
 
 #include "fock_tables.h"
 #include "utd_device.h"
+#include "utd_dual.h"
 
 namespace utd {
 
@@ -39,15 +40,17 @@ template <> struct TabDims<double> {
 // Pointers to the regime tables ([seg][DEG+1][4] = (re_s, im_s, re_h, im_h))
 // and the transition tables ([seg][DEG+1][2] = (re, im)), in LDS (FP32) or
 // global memory (FP64).
-template <typename R> struct Tabs {
-    const R* reg;   // PT segments, then DS, then CL
-    const R* tf;    // FA segments, then FH
+template <typename T> struct Tabs {
+    const T* reg;   // PT segments, then DS, then CL
+    const T* tf;    // FA segments, then FH
 };
 
-template <typename R>
-__device__ __forceinline__ void horner4(const R* seg, R s, R out[4]) {
-    constexpr int D = TabDims<R>::DEG;
-    const R* c = seg + 4 * D;
+// Polynomials are evaluated in the arithmetic type R (plain or dual) from
+// coefficients of the table type T.
+template <typename T, typename R>
+__device__ __forceinline__ void horner4(const T* seg, R s, R out[4]) {
+    constexpr int D = TabDims<T>::DEG;
+    const T* c = seg + 4 * D;
     R a0 = c[0], a1 = c[1], a2 = c[2], a3 = c[3];
 #pragma unroll
     for (int k = D - 1; k >= 0; --k) {
@@ -62,7 +65,7 @@ __device__ __forceinline__ void horner4(const R* seg, R s, R out[4]) {
 
 // float specialisation reading float4 rows (one 16-byte LDS read per coefficient)
 template <>
-__device__ __forceinline__ void horner4<float>(const float* seg, float s, float out[4]) {
+__device__ __forceinline__ void horner4<float, float>(const float* seg, float s, float out[4]) {
     constexpr int D = TabDims<float>::DEG;
     const float4* c = reinterpret_cast<const float4*>(seg) + D;
     float4 a = *c;
@@ -78,10 +81,10 @@ __device__ __forceinline__ void horner4<float>(const float* seg, float s, float 
     out[0] = a.x; out[1] = a.y; out[2] = a.z; out[3] = a.w;
 }
 
-template <typename R>
-__device__ __forceinline__ void horner2(const R* seg, R s, R out[2]) {
-    constexpr int D = TabDims<R>::DEG;
-    const R* c = seg + 2 * D;
+template <typename T, typename R>
+__device__ __forceinline__ void horner2(const T* seg, R s, R out[2]) {
+    constexpr int D = TabDims<T>::DEG;
+    const T* c = seg + 2 * D;
     R a0 = c[0], a1 = c[1];
 #pragma unroll
     for (int k = D - 1; k >= 0; --k) {
@@ -96,7 +99,7 @@ __device__ __forceinline__ void horner2(const R* seg, R s, R out[2]) {
 template <typename R>
 __device__ __forceinline__ int locate(R x, R lo, R inv_w, int n, R* s) {
     R u = (x - lo) * inv_w;
-    int i = (int)RT<R>::floor_(u);
+    int i = (int)val(RT<R>::floor_(u));
     i = i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
     *s = (R)2 * (u - (R)i) - (R)1;
     return i;
@@ -118,9 +121,10 @@ template <typename R> struct FockArgs {
 };
 
 template <typename R>
-__device__ __forceinline__ void fock_kernel(const Tabs<R>& tb, const FockArgs<R>& A, bool refl, bool any_refl,
-                                            cplx<R>* Ks, cplx<R>* Kh) {
-    using D = TabDims<R>;
+__device__ __forceinline__ void fock_kernel(const Tabs<typename BaseOf<R>::type>& tb, const FockArgs<R>& A, bool refl,
+                                            bool any_refl, cplx<R>* Ks, cplx<R>* Kh) {
+    using T = typename BaseOf<R>::type;
+    using D = TabDims<T>;
     const R e4 = (R)kRs2;                     // e^{-j pi/4} = e4 (1 - j)
     const R c2 = (R)kInv2SqrtPi;
     const R xi = A.xi, u = A.u, q = A.q, ixi = A.ixi;
@@ -136,7 +140,7 @@ __device__ __forceinline__ void fock_kernel(const Tabs<R>& tb, const FockArgs<R>
     R st;
     int tseg = (big ? D::NFA : 0) + locate<R>(targ, (R)0, invw, nseg, &st);
     R v[2];
-    horner2<R>(tb.tf + tseg * 2 * (D::DEG + 1), st, v);
+    horner2<T, R>(tb.tf + tseg * 2 * (D::DEG + 1), st, v);
     // small u: G = F/sqrt(X) = 2j A, F = u G; large u: 1 - F = -H/X, G = F/u
     R omr = -iX * v[0], omi = -iX * v[1];
     cplx<R> G, omF;
@@ -157,7 +161,7 @@ __device__ __forceinline__ void fock_kernel(const Tabs<R>& tb, const FockArgs<R>
     R s;
     int seg = rbase + locate<R>(arg, rlo, rinv, rn, &s);
     R w4[4];
-    horner4<R>(tb.reg + seg * 4 * (D::DEG + 1), s, w4);
+    horner4<T, R>(tb.reg + seg * 4 * (D::DEG + 1), s, w4);
     cplx<R> ps{w4[0], w4[1]}, ph{w4[2], w4[3]};
     if (regime == 0 && xi > (R)FT_DS_HI) {
         // past the table only the first creeping mode survives:

@@ -13,9 +13,15 @@
 // in the distances.  Frames, spreading and Fock arguments are computed in
 // the field precision R.  The reflection point is solved once (FP64
 // safeguarded Newton) by the visibility pass and its angle is reused.
+//
+// Every function is templated on the geometry scalar G (double, or a dual
+// number for the adjoint) and the field scalar R; the forward kernels
+// instantiate G = double.
 #pragma once
 
 #include "utd_device.h"
+#include "utd_dual.h"
+
 
 namespace utd {
 
@@ -26,22 +32,27 @@ namespace utd {
 //   1/xi = k^{-1/3} ixh,  sqrt(-xi) = k^{1/6} sxh,
 // and the contribution is
 //   e^{-j 2pi rev} k^{-1/6} (a_s K_s v_s + a_h K_h v_h),  rev = (f/c) s_tot - nc/4.
-template <typename R> struct PathEval {
-    double s_tot;     // total path length s^i + t + s^d (or s^i + s^r)
+template <typename R, typename G = double> struct PathEvalT {
+    G s_tot;          // total path length s^i + t + s^d (or s^i + s^r)
     int nc;           // caustics passed (each +pi/2)
     int refl;
     R xh, uh, qhat, ixh, sxh;
     R a_s, a_h;       // incident projections x spreading x prefactor
     R vs[3], vh[3];   // output polarisation vectors at R
 };
+template <typename R> using PathEval = PathEvalT<R, double>;
+
+template <typename G> __device__ __forceinline__ V3<G> v3(const G c[3]) { return V3<G>{c[0], c[1], c[2]}; }
+template <typename G> __device__ __forceinline__ G gnorm(V3<G> a) { return gsqrt(dot(a, a)); }
 
 // Fill the Fock-argument constants from mhat, phi_e and L (= L^d or L^r).
-template <typename R>
-__device__ __forceinline__ void set_fock_consts(PathEval<R>* pe, R mhat, R phi_e, R Ld) {
+template <typename R, typename G>
+__device__ __forceinline__ void set_fock_consts(PathEvalT<R, G>* pe, R mhat, R phi_e, R Ld) {
     R xh = mhat * phi_e;
+    R sl = RT<R>::sqrt_((R)0.5 * Ld);
     pe->xh = xh;
-    pe->uh = RT<R>::sqrt_((R)0.5 * Ld) * (phi_e < (R)0 ? -phi_e : phi_e);
-    pe->qhat = RT<R>::sqrt_((R)0.5 * Ld) / mhat;
+    pe->uh = sl * (phi_e < (R)0 ? -phi_e : phi_e);
+    pe->qhat = sl / mhat;
     pe->ixh = xh != (R)0 ? (R)1 / xh : (R)0;
     pe->sxh = RT<R>::sqrt_(xh < (R)0 ? -xh : (R)0);
 }
@@ -52,39 +63,51 @@ struct PathPts {
     d3 P2, P3;        // second leg Q2 (or Q_R) -> R
 };
 
-__device__ __forceinline__ BodyPrep body_prep(const double T[3], const float* sph, int n_sph,
-                                              const float* cyl, int b) {
-    BodyPrep p;
-    p.pad[0] = p.pad[1] = 0;
+// Source-dependent constants of a sphere (centre C, radius a) and of a
+// vertical cylinder (axis through (cx, cy), lateral surface z0 .. z0 + h).
+template <typename G>
+__device__ __forceinline__ BodyPrepT<G> prep_sphere(V3<G> T, V3<G> C, G a) {
+    BodyPrepT<G> p;
+    p.kind = 0;
+    p.c[0] = C.x; p.c[1] = C.y; p.c[2] = C.z;
+    p.a = a;
+    p.z0 = 0; p.h = 0;
+    V3<G> v = T - C;
+    p.dT = gnorm(v);
+    G idT = G(1.0) / p.dT;
+    p.eT[0] = v.x * idT; p.eT[1] = v.y * idT; p.eT[2] = v.z * idT;
+    p.ok = p.dT > p.a;
+    p.sI0 = p.ok ? gsqrt((p.dT - p.a) * (p.dT + p.a)) : G(0.0);
+    p.gT = gatan2(p.sI0, p.a);
+    p.aT = G(0.0);
+    return p;
+}
+
+template <typename G>
+__device__ __forceinline__ BodyPrepT<G> prep_cylinder(V3<G> T, G cx, G cy, double z0, double h, G a) {
+    BodyPrepT<G> p;
+    p.kind = 1;
+    p.c[0] = cx; p.c[1] = cy; p.c[2] = G(0.0);
+    p.z0 = z0; p.h = h; p.a = a;
+    G tx = T.x - cx, ty = T.y - cy;
+    p.dT = gsqrt(tx * tx + ty * ty);
+    p.eT[0] = tx / p.dT; p.eT[1] = ty / p.dT; p.eT[2] = G(0.0);
+    p.ok = p.dT > p.a;
+    p.sI0 = p.ok ? gsqrt((p.dT - p.a) * (p.dT + p.a)) : G(0.0);
+    p.gT = gatan2(p.sI0, p.a);
+    p.aT = gatan2(ty, tx);
+    return p;
+}
+
+__device__ __forceinline__ BodyPrep body_prep(const double T[3], const float* sph, int n_sph, const float* cyl,
+                                              int b) {
     d3 t = mk(T[0], T[1], T[2]);
     if (b < n_sph) {
         const float* s = sph + 4 * b;
-        p.kind = 0;
-        p.c[0] = s[0]; p.c[1] = s[1]; p.c[2] = s[2];
-        p.a = s[3];
-        p.z0 = 0; p.h = 0;
-        d3 v = t - mk(p.c[0], p.c[1], p.c[2]);
-        p.dT = norm(v);
-        d3 e = (1.0 / p.dT) * v;
-        p.eT[0] = e.x; p.eT[1] = e.y; p.eT[2] = e.z;
-        p.ok = p.dT > p.a;
-        p.sI0 = p.ok ? sqrt((p.dT - p.a) * (p.dT + p.a)) : 0.0;
-        p.gT = atan2(p.sI0, p.a);
-        p.aT = 0;
-    } else {
-        const float* c = cyl + 5 * (b - n_sph);
-        p.kind = 1;
-        p.c[0] = c[0]; p.c[1] = c[1]; p.c[2] = 0;
-        p.z0 = c[2]; p.h = c[3]; p.a = c[4];
-        double tx = T[0] - p.c[0], ty = T[1] - p.c[1];
-        p.dT = sqrt(tx * tx + ty * ty);
-        p.eT[0] = tx / p.dT; p.eT[1] = ty / p.dT; p.eT[2] = 0;
-        p.ok = p.dT > p.a;
-        p.sI0 = p.ok ? sqrt((p.dT - p.a) * (p.dT + p.a)) : 0.0;
-        p.gT = atan2(p.sI0, p.a);
-        p.aT = atan2(ty, tx);
+        return prep_sphere<double>(t, mk(s[0], s[1], s[2]), (double)s[3]);
     }
-    return p;
+    const float* c = cyl + 5 * (b - n_sph);
+    return prep_cylinder<double>(t, c[0], c[1], c[2], c[3], c[4]);
 }
 
 __device__ __forceinline__ bool inside_body(const BodyPrep& b, d3 P) {
@@ -103,68 +126,75 @@ __device__ __forceinline__ bool inside_body(const BodyPrep& b, d3 P) {
 //   cylinder: everything in projection; u2_+ / u2_- the unit directions of the
 //             detachment points (R's tangent points) from the axis.
 // phi_p is the arc of side + (phi_m = arc_sum - phi_p) with ell = 0.
-struct RxGeo {
-    double dR, sD0;       // distance to centre / axis, tangent length
-    double phi_p, phi_m;  // arcs of the two sides
-    double wn;            // sphere: distance of R from the source axis
-    double along;         // sphere: component of R - C along e_T
-    double c2p, s2p, c2m, s2m;   // sphere: cos/sin of th2_+/-; cylinder: u2_+/- (x, y)
-    d3 eperp;             // sphere only
+template <typename G> struct RxGeoT {
+    G dR, sD0;            // distance to centre / axis, tangent length
+    G phi_p, phi_m;       // arcs of the two sides
+    G wn;                 // sphere: distance of R from the source axis
+    G along;              // sphere: component of R - C along e_T
+    G c2p, s2p, c2m, s2m; // sphere: cos/sin of th2_+/-; cylinder: u2_+/- (x, y)
+    V3<G> eperp;          // sphere only
     int ok;               // R outside the body's sphere / circle
 };
+using RxGeo = RxGeoT<double>;
 
-__device__ __forceinline__ RxGeo rx_geo(const BodyPrep& b, d3 R) {
-    RxGeo g;
-    double a = b.a;
-    double cgT = a / b.dT, sgT = b.sI0 / b.dT;
+template <typename G>
+__device__ __forceinline__ RxGeoT<G> rx_geo(const BodyPrepT<G>& b, V3<G> R) {
+    RxGeoT<G> g;
+    G a = b.a;
+    G cgT = a / b.dT, sgT = b.sI0 / b.dT;
     if (b.kind == 0) {
-        d3 C = mk(b.c[0], b.c[1], b.c[2]);
-        d3 eT = mk(b.eT[0], b.eT[1], b.eT[2]);
-        d3 v = R - C;
-        double d2 = dot(v, v);
-        double along = dot(v, eT);
+        V3<G> C = v3(b.c);
+        V3<G> eT = v3(b.eT);
+        V3<G> v = R - C;
+        G d2 = dot(v, v);
+        G along = dot(v, eT);
         g.along = along;
-        d3 w = v - along * eT;
-        g.wn = norm(w);
-        g.eperp = g.wn > 1e-300 ? (1.0 / g.wn) * w : any_perp(eT);
-        g.dR = sqrt(d2);
+        V3<G> w = v - along * eT;
+        g.wn = gnorm(w);
+        if (g.wn > 1e-300) {
+            g.eperp = (G(1.0) / g.wn) * w;
+        } else {
+            d3 ap = any_perp(val3(eT));
+            g.eperp = V3<G>{ap.x, ap.y, ap.z};
+        }
+        g.dR = gsqrt(d2);
         g.ok = g.dR > a;
-        g.sD0 = g.ok ? sqrt((g.dR - a) * (g.dR + a)) : 0.0;
-        double id2 = 1.0 / d2;
+        g.sD0 = g.ok ? gsqrt((g.dR - a) * (g.dR + a)) : G(0.0);
+        G id2 = G(1.0) / d2;
         // th2_+ = theta_R - gR ; th2_- = 2 pi - theta_R - gR
         g.c2p = (along * a + g.wn * g.sD0) * id2;
         g.s2p = (g.wn * a - along * g.sD0) * id2;
         g.c2m = (along * a - g.wn * g.sD0) * id2;
         g.s2m = -(g.wn * a + along * g.sD0) * id2;
         // phi_+ = th2_+ - gT in (-pi, pi)
-        double cp = g.c2p * cgT + g.s2p * sgT;
-        double sp = g.s2p * cgT - g.c2p * sgT;
-        g.phi_p = atan2(sp, cp);
-        double gR = atan2(g.sD0, a);
+        G cp = g.c2p * cgT + g.s2p * sgT;
+        G sp = g.s2p * cgT - g.c2p * sgT;
+        g.phi_p = gatan2(sp, cp);
+        G gR = gatan2(g.sD0, a);
         g.phi_m = (kTwoPi - 2.0 * b.gT - 2.0 * gR) - g.phi_p;
     } else {
-        double x = R.x - b.c[0], y = R.y - b.c[1];
-        double r2 = x * x + y * y;
-        g.dR = sqrt(r2);
+        G x = R.x - b.c[0], y = R.y - b.c[1];
+        G r2 = x * x + y * y;
+        g.dR = gsqrt(r2);
         g.ok = g.dR > a;
-        g.sD0 = g.ok ? sqrt((g.dR - a) * (g.dR + a)) : 0.0;
-        g.wn = 0;
-        g.along = 0;
-        g.eperp = mk(0, 0, 0);
-        double ir = 1.0 / r2;
+        g.sD0 = g.ok ? gsqrt((g.dR - a) * (g.dR + a)) : G(0.0);
+        g.wn = G(0.0);
+        g.along = G(0.0);
+        g.eperp = V3<G>{G(0.0), G(0.0), G(0.0)};
+        G ir = G(1.0) / r2;
         // R's tangent points: u_R rotated by -gR (side +) and +gR (side -)
-        double cg = a, sg = g.sD0;     // times 1/dR each, folded into ir
+        G cg = a, sg = g.sD0;     // times 1/dR each, folded into ir
         g.c2p = (x * cg + y * sg) * ir;
         g.s2p = (y * cg - x * sg) * ir;
         g.c2m = (x * cg - y * sg) * ir;
         g.s2m = (y * cg + x * sg) * ir;
         // T's tangent point of side +: u_T rotated by +gT
-        double u1x = b.eT[0] * cgT - b.eT[1] * sgT, u1y = b.eT[1] * cgT + b.eT[0] * sgT;
-        double p = atan2(u1x * g.s2p - u1y * g.c2p, u1x * g.c2p + u1y * g.s2p);
-        double gR = atan2(g.sD0, a);
-        double G = b.gT + gR;
-        g.phi_p = p >= -G ? p : p + kTwoPi;
-        g.phi_m = (kTwoPi - 2.0 * G) - g.phi_p;
+        G u1x = b.eT[0] * cgT - b.eT[1] * sgT, u1y = b.eT[1] * cgT + b.eT[0] * sgT;
+        G p = gatan2(u1x * g.s2p - u1y * g.c2p, u1x * g.c2p + u1y * g.s2p);
+        G gR = gatan2(g.sD0, a);
+        G gsum = b.gT + gR;
+        g.phi_p = p >= -gsum ? p : p + kTwoPi;
+        g.phi_m = (kTwoPi - 2.0 * gsum) - g.phi_p;
     }
     return g;
 }
@@ -179,31 +209,32 @@ __device__ __forceinline__ RxGeo rx_geo(const BodyPrep& b, d3 R) {
 // the distance of R from the source axis; one +pi/2 per caustic:
 // floor(theta2/pi) surface poles plus one axis crossing when sgn differs from
 // the sign of sin(theta2).
-template <typename R>
-__device__ __forceinline__ bool sphere_creep(const BodyPrep& b, const RxGeo& g, d3 Rp, const LaunchParams& L,
-                                             int sgn, int ell, bool* caustic, PathEval<R>* pe, PathPts* pts) {
-    double phi = (sgn > 0 ? g.phi_p : g.phi_m) + kTwoPi * ell;
+template <typename R, typename G>
+__device__ __forceinline__ bool sphere_creep(const BodyPrepT<G>& b, const RxGeoT<G>& g, V3<G> Rp, V3<G> T,
+                                             const LaunchParams& L, int sgn, int ell, bool* caustic,
+                                             PathEvalT<R, G>* pe, PathPts* pts) {
+    G phi = (sgn > 0 ? g.phi_p : g.phi_m) + kTwoPi * ell;
     *caustic = false;
-    if (!(b.ok && g.ok) || phi < 0) return false;
+    if (!(b.ok && g.ok) || phi < 0.0) return false;
     if (g.wn < L.caustic_guard) { *caustic = true; return false; }
-    double a = b.a;
-    double cg = a / b.dT, sg = b.sI0 / b.dT;
-    double c2 = sgn > 0 ? g.c2p : g.c2m, s2 = sgn > 0 ? g.s2p : g.s2m;
-    d3 eT = mk(b.eT[0], b.eT[1], b.eT[2]);
-    d3 ep = (double)sgn * g.eperp;
+    G a = b.a;
+    G cg = a / b.dT, sg = b.sI0 / b.dT;
+    G c2 = sgn > 0 ? g.c2p : g.c2m, s2 = sgn > 0 ? g.s2p : g.s2m;
+    V3<G> eT = v3(b.eT);
+    V3<G> ep = (double)sgn * g.eperp;
     if (pts) {
-        d3 C = mk(b.c[0], b.c[1], b.c[2]);
-        pts->P0 = mk(L.T[0], L.T[1], L.T[2]);
-        pts->P1 = C + a * (cg * eT + sg * ep);
-        pts->P2 = C + a * (c2 * eT + s2 * ep);
-        pts->P3 = Rp;
+        V3<G> C = v3(b.c);
+        pts->P0 = val3(T);
+        pts->P1 = val3(C + a * (cg * eT + sg * ep));
+        pts->P2 = val3(C + a * (c2 * eT + s2 * ep));
+        pts->P3 = val3(Rp);
     }
     if (pe) {
-        double th2 = b.gT + phi;
-        int npi = (int)floor(th2 * (1.0 / kPi));
+        G th2 = b.gT + phi;
+        int npi = (int)gfloor(th2 * (1.0 / kPi));
         bool s2pos = (npi & 1) == 0;
         int Nc = npi + ((sgn > 0) != s2pos ? 1 : 0);
-        double sI = b.sI0, sD = g.sD0;
+        G sI = b.sI0, sD = g.sD0;
         pe->s_tot = sI + a * phi + sD;
         pe->nc = Nc;
         // frames in precision R: n1 = cg eT + sg ep, t1 = -sg eT + cg ep,
@@ -219,7 +250,7 @@ __device__ __forceinline__ bool sphere_creep(const BodyPrep& b, const RxGeo& g, 
         R mhat = RT<R>::cbrt_((R)0.5 * aR);
         R Smod = RT<R>::sqrt_(aR * sgR / (sDR * (R)g.wn));
         R A = (R)L.amp * Smod / sIR * ((R)-1.4142135623730951 * mhat);
-        set_fock_consts<R>(pe, mhat, (R)phi, Ld);
+        set_fock_consts<R, G>(pe, mhat, (R)phi, Ld);
         pe->a_s = A * (px * bx + py * by + pz * bz);
         pe->a_h = A * (px * n1x + py * n1y + pz * n1z);
         pe->vs[0] = bx; pe->vs[1] = by; pe->vs[2] = bz;
@@ -235,38 +266,39 @@ __device__ __forceinline__ bool sphere_creep(const BodyPrep& b, const RxGeo& g, 
 // L2 = d_T + a phi + d_R, cos(delta) = L2 / sqrt(L2^2 + dz^2), rho_g = a/cos^2,
 // xi / m = t / rho_g = phi cos(delta); spreading sqrt(s^i / (s^d (s^i + t + s^d))).
 // Valid only if both attachment heights lie on the lateral surface.
-template <typename R>
-__device__ __forceinline__ bool cyl_creep(const BodyPrep& b, const RxGeo& g, d3 Rp, const LaunchParams& L,
-                                          int sgn, int ell, PathEval<R>* pe, PathPts* pts) {
+template <typename R, typename G>
+__device__ __forceinline__ bool cyl_creep(const BodyPrepT<G>& b, const RxGeoT<G>& g, V3<G> Rp, V3<G> T,
+                                          const LaunchParams& L, int sgn, int ell, PathEvalT<R, G>* pe,
+                                          PathPts* pts) {
     if (!(b.ok && g.ok)) return false;
-    double phi = (sgn > 0 ? g.phi_p : g.phi_m) + kTwoPi * ell;
-    if (phi < 0) return false;
-    double a = b.a;
-    double dT = b.sI0, dR = g.sD0;
-    double L2 = dT + a * phi + dR;
-    double dz = Rp.z - L.T[2];
-    double zQ1 = L.T[2] + dz * dT / L2;
-    double zQ2 = L.T[2] + dz * (dT + a * phi) / L2;
+    G phi = (sgn > 0 ? g.phi_p : g.phi_m) + kTwoPi * ell;
+    if (phi < 0.0) return false;
+    G a = b.a;
+    G dT = b.sI0, dR = g.sD0;
+    G L2 = dT + a * phi + dR;
+    G dz = Rp.z - T.z;
+    G zQ1 = T.z + dz * dT / L2;
+    G zQ2 = T.z + dz * (dT + a * phi) / L2;
     if (zQ1 < b.z0 || zQ1 > b.z0 + b.h || zQ2 < b.z0 || zQ2 > b.z0 + b.h) return false;
-    double cgT = a / b.dT, sgT = b.sI0 / b.dT;
+    G cgT = a / b.dT, sgT = b.sI0 / b.dT;
     // attachment direction: u_T rotated by sgn*gT; detachment: u2 of this side
-    double c1 = b.eT[0] * cgT - sgn * b.eT[1] * sgT, s1 = b.eT[1] * cgT + sgn * b.eT[0] * sgT;
-    double c2 = sgn > 0 ? g.c2p : g.c2m, s2 = sgn > 0 ? g.s2p : g.s2m;
+    G c1 = b.eT[0] * cgT - (double)sgn * b.eT[1] * sgT, s1 = b.eT[1] * cgT + (double)sgn * b.eT[0] * sgT;
+    G c2 = sgn > 0 ? g.c2p : g.c2m, s2 = sgn > 0 ? g.s2p : g.s2m;
     if (pts) {
-        pts->P0 = mk(L.T[0], L.T[1], L.T[2]);
-        pts->P1 = mk(b.c[0] + a * c1, b.c[1] + a * s1, zQ1);
-        pts->P2 = mk(b.c[0] + a * c2, b.c[1] + a * s2, zQ2);
-        pts->P3 = Rp;
+        pts->P0 = val3(T);
+        pts->P1 = mk(val(b.c[0] + a * c1), val(b.c[1] + a * s1), val(zQ1));
+        pts->P2 = mk(val(b.c[0] + a * c2), val(b.c[1] + a * s2), val(zQ2));
+        pts->P3 = val3(Rp);
     }
     if (pe) {
-        double Stot = sqrt(L2 * L2 + dz * dz);
+        G Stot = gsqrt(L2 * L2 + dz * dz);
         pe->s_tot = Stot;
         pe->nc = 0;
         R cosd = (R)(L2 / Stot), sind = (R)(dz / Stot);
         R idc = (R)1 / cosd;
-        R sI = (R)dT * idc, t = (R)(a * phi) * idc, sD = (R)dR * idc;
+        R sI = (R)dT * idc, sD = (R)dR * idc;
         R c1R = (R)c1, s1R = (R)s1, c2R = (R)c2, s2R = (R)s2;
-        R sg = (R)sgn;
+        R sg = (R)(double)sgn;
         // t_i = cosd * sgn (-s_i, c_i, 0) + sind z;  b_i = t_i x n_i, n_i = (c_i, s_i, 0)
         R b1x = -sind * s1R, b1y = sind * c1R, b1z = -cosd * sg;
         R b2x = -sind * s2R, b2y = sind * c2R, b2z = b1z;
@@ -276,8 +308,7 @@ __device__ __forceinline__ bool cyl_creep(const BodyPrep& b, const RxGeo& g, d3 
         R Smod = RT<R>::sqrt_(sI / (sD * (R)Stot));
         R px = (R)L.p[0], py = (R)L.p[1], pz = (R)L.p[2];
         R A = (R)L.amp * Smod / sI * ((R)-1.4142135623730951 * mhat);
-        (void)t;
-        set_fock_consts<R>(pe, mhat, (R)phi * cosd, Ld);
+        set_fock_consts<R, G>(pe, mhat, (R)phi * cosd, Ld);
         pe->a_s = A * (px * b1x + py * b1y + pz * b1z);
         pe->a_h = A * (px * c1R + py * s1R);
         pe->vs[0] = b2x; pe->vs[1] = b2y; pe->vs[2] = b2z;
@@ -291,30 +322,33 @@ __device__ __forceinline__ bool cyl_creep(const BodyPrep& b, const RxGeo& g, d3 
 // reflection
 // ---------------------------------------------------------------------------
 
-// Alhazen's problem on a circle of radius a centred at the origin: the point
-// Q = a (cos th, sin th), th in [lo, hi], where d/dth (|Q - P1| + |Q - P2|) = 0.
+// Stationarity condition of Alhazen's problem on a circle of radius a
+// centred at the origin: with Q = a (cos th, sin th),
+// g(th) = d/dth (|Q - P1| + |Q - P2|) / a = (Q - P1).t/|Q - P1| + (Q - P2).t/|Q - P2|,
+// t the unit tangent; *dg = g'(th).
+template <typename G>
+__device__ __forceinline__ G alhazen_fun(G a, G p1x, G p1y, G p2x, G p2y, G th, G* dg) {
+    G s, c;
+    gsincos(th, &s, &c);
+    G qx = a * c, qy = a * s;
+    G d1x = qx - p1x, d1y = qy - p1y, d2x = qx - p2x, d2y = qy - p2y;
+    G l1 = gsqrt(d1x * d1x + d1y * d1y), l2 = gsqrt(d2x * d2x + d2y * d2y);
+    G t1 = -d1x * s + d1y * c, t2 = -d2x * s + d2y * c;      // (Q-P).t
+    G n1 = d1x * c + d1y * s, n2 = d2x * c + d2y * s;        // (Q-P).n
+    *dg = (a - n1) / l1 - a * t1 * t1 / (l1 * l1 * l1) + (a - n2) / l2 - a * t2 * t2 / (l2 * l2 * l2);
+    return t1 / l1 + t2 / l2;
+}
+
 // Safeguarded Newton in FP64 (bisection step whenever Newton leaves the
-// bracket); the bracket ends are the tangent points, where the derivative has
-// opposite signs.
+// bracket); the bracket ends are the tangent points, where g has opposite
+// signs.
 __device__ __forceinline__ double alhazen(double a, double p1x, double p1y, double p2x, double p2y,
                                           double lo, double hi) {
-    auto gfun = [&](double th, double* dg) {
-        double s, c;
-        sincos(th, &s, &c);
-        double qx = a * c, qy = a * s;
-        double d1x = qx - p1x, d1y = qy - p1y, d2x = qx - p2x, d2y = qy - p2y;
-        double l1 = sqrt(d1x * d1x + d1y * d1y), l2 = sqrt(d2x * d2x + d2y * d2y);
-        double t1 = -d1x * s + d1y * c, t2 = -d2x * s + d2y * c;      // (Q-P).t
-        double n1 = d1x * c + d1y * s, n2 = d2x * c + d2y * s;        // (Q-P).n
-        double g = t1 / l1 + t2 / l2;
-        *dg = (a - n1) / l1 - a * t1 * t1 / (l1 * l1 * l1) + (a - n2) / l2 - a * t2 * t2 / (l2 * l2 * l2);
-        return g;
-    };
     double dg;
-    double glo = gfun(lo, &dg);
+    double glo = alhazen_fun<double>(a, p1x, p1y, p2x, p2y, lo, &dg);
     double th = 0.5 * (lo + hi);
     for (int it = 0; it < 60; ++it) {
-        double g = gfun(th, &dg);
+        double g = alhazen_fun<double>(a, p1x, p1y, p2x, p2y, th, &dg);
         if ((g < 0) == (glo < 0)) { lo = th; glo = g; } else { hi = th; }
         double nt = th - g / dg;
         if (!(nt > lo && nt < hi)) nt = 0.5 * (lo + hi);
@@ -325,10 +359,9 @@ __device__ __forceinline__ double alhazen(double a, double p1x, double p1y, doub
 }
 
 // Reflection point for a lit receiver: the angle parameter (sphere: polar
-// angle in the T-C-R plane; cylinder: azimuth) or a negative status if the
-// receiver is not lit by this body or the point is off the lateral surface.
-__device__ __forceinline__ bool refl_angle(const BodyPrep& b, const RxGeo& g, d3 Rp, const LaunchParams& L,
-                                           double* th_out) {
+// angle in the T-C-R plane; cylinder: azimuth), false if the receiver is not
+// lit by this body or the point is off the lateral surface.
+__device__ __forceinline__ bool refl_angle(const BodyPrep& b, const RxGeo& g, d3 Rp, d3 T, double* th_out) {
     if (!(b.ok && g.ok)) return false;
     double a = b.a;
     if (b.kind == 0) {
@@ -348,7 +381,7 @@ __device__ __forceinline__ bool refl_angle(const BodyPrep& b, const RxGeo& g, d3
     } else {
         return false;
     }
-    double tx = L.T[0] - b.c[0], ty = L.T[1] - b.c[1];
+    double tx = T.x - b.c[0], ty = T.y - b.c[1];
     double rx = Rp.x - b.c[0], ry = Rp.y - b.c[1];
     double al = alhazen(a, tx, ty, rx, ry, lo, hi);
     double s, c;
@@ -356,31 +389,46 @@ __device__ __forceinline__ bool refl_angle(const BodyPrep& b, const RxGeo& g, d3
     double qx = a * c, qy = a * s;
     double lt = sqrt((qx - tx) * (qx - tx) + (qy - ty) * (qy - ty));
     double lr = sqrt((qx - rx) * (qx - rx) + (qy - ry) * (qy - ry));
-    double zQ = L.T[2] + (Rp.z - L.T[2]) * lt / (lt + lr);
+    double zQ = T.z + (Rp.z - T.z) * lt / (lt + lr);
     if (zQ < b.z0 || zQ > b.z0 + b.h) return false;
     *th_out = al;
     return true;
 }
 
-// Reflection point and its normal from the stored angle.
-__device__ __forceinline__ void refl_point(const BodyPrep& b, const RxGeo& g, d3 Rp, const LaunchParams& L,
-                                           double th, d3* Q, d3* n) {
-    double s, c;
-    sincos(th, &s, &c);
+// The reflection angle as a function of the geometry: one Newton step from
+// the converged FP64 root th, taken in G.  For a dual G the step carries
+// d th = -(dg/dp) / g'(th) (implicit differentiation of g(th, p) = 0).
+template <typename G>
+__device__ __forceinline__ G refl_angle_g(const BodyPrepT<G>& b, const RxGeoT<G>& g, V3<G> Rp, V3<G> T, double th) {
+    G dg;
+    G r;
+    if (b.kind == 0)
+        r = alhazen_fun<G>(b.a, b.dT, G(0.0), g.along, g.wn, G(th), &dg);
+    else
+        r = alhazen_fun<G>(b.a, T.x - b.c[0], T.y - b.c[1], Rp.x - b.c[0], Rp.y - b.c[1], G(th), &dg);
+    return G(th) - r / G(val(dg));
+}
+
+// Reflection point and its normal from the angle.
+template <typename G>
+__device__ __forceinline__ void refl_point(const BodyPrepT<G>& b, const RxGeoT<G>& g, V3<G> Rp, V3<G> T, G th,
+                                           V3<G>* Q, V3<G>* n) {
+    G s, c;
+    gsincos(th, &s, &c);
     if (b.kind == 0) {
-        d3 eT = mk(b.eT[0], b.eT[1], b.eT[2]);
+        V3<G> eT = v3(b.eT);
         *n = c * eT + s * g.eperp;
-        *Q = mk(b.c[0], b.c[1], b.c[2]) + b.a * (*n);
+        *Q = v3(b.c) + b.a * (*n);
     } else {
-        double a = b.a;
-        double tx = L.T[0] - b.c[0], ty = L.T[1] - b.c[1];
-        double rx = Rp.x - b.c[0], ry = Rp.y - b.c[1];
-        double qx = a * c, qy = a * s;
-        double lt = sqrt((qx - tx) * (qx - tx) + (qy - ty) * (qy - ty));
-        double lr = sqrt((qx - rx) * (qx - rx) + (qy - ry) * (qy - ry));
-        double zQ = L.T[2] + (Rp.z - L.T[2]) * lt / (lt + lr);
-        *Q = mk(b.c[0] + qx, b.c[1] + qy, zQ);
-        *n = mk(c, s, 0);
+        G a = b.a;
+        G tx = T.x - b.c[0], ty = T.y - b.c[1];
+        G rx = Rp.x - b.c[0], ry = Rp.y - b.c[1];
+        G qx = a * c, qy = a * s;
+        G lt = gsqrt((qx - tx) * (qx - tx) + (qy - ty) * (qy - ty));
+        G lr = gsqrt((qx - rx) * (qx - rx) + (qy - ry) * (qy - ry));
+        G zQ = T.z + (Rp.z - T.z) * lt / (lt + lr);
+        *Q = V3<G>{b.c[0] + qx, b.c[1] + qy, zQ};
+        *n = V3<G>{c, s, G(0.0)};
     }
 }
 
@@ -388,15 +436,14 @@ __device__ __forceinline__ void refl_point(const BodyPrep& b, const RxGeo& g, d3
 // 1/rho_1 = 1/s^i + f1/cos(th_i), 1/rho_2 = 1/s^i + f2 cos(th_i)
 // (sphere: f1 = f2 = 2/a, rho_g = a; cylinder: f1 = 2 cos^2(beta)/a, f2 = 0,
 // rho_g = a / cos^2(delta_R)).
-template <typename R>
-__device__ __forceinline__ void refl_eval(const BodyPrep& b, d3 Q, d3 n, d3 Rp, const LaunchParams& L,
-                                          PathEval<R>* pe) {
-    d3 T = mk(L.T[0], L.T[1], L.T[2]);
-    d3 vi = Q - T, vr = Rp - Q;
-    double sI = norm(vi), sR = norm(vr);
+template <typename R, typename G>
+__device__ __forceinline__ void refl_eval(const BodyPrepT<G>& b, V3<G> Q, V3<G> n, V3<G> Rp, V3<G> T,
+                                          const LaunchParams& L, PathEvalT<R, G>* pe) {
+    V3<G> vi = Q - T, vr = Rp - Q;
+    G sI = gnorm(vi), sR = gnorm(vr);
     pe->s_tot = sI + sR;
     pe->nc = 0;
-    R isI = (R)(1.0 / sI), isR = (R)(1.0 / sR);
+    R isI = (R)(G(1.0) / sI), isR = (R)(G(1.0) / sR);
     R six = (R)vi.x * isI, siy = (R)vi.y * isI, siz = (R)vi.z * isI;
     R srx = (R)vr.x * isR, sry = (R)vr.y * isR, srz = (R)vr.z * isR;
     R nx = (R)n.x, ny = (R)n.y, nz = (R)n.z;
@@ -431,7 +478,7 @@ __device__ __forceinline__ void refl_eval(const BodyPrep& b, d3 Q, d3 n, d3 Rp, 
         R ic = (R)1 / cn;
         cx *= ic; cy *= ic; cz *= ic;
     } else {
-        d3 ap = any_perp(n);
+        d3 ap = any_perp(val3(n));
         cx = (R)ap.x; cy = (R)ap.y; cz = (R)ap.z;
     }
     R pix = cy * siz - cz * siy, piy = cz * six - cx * siz, piz = cx * siy - cy * six;
@@ -441,7 +488,7 @@ __device__ __forceinline__ void refl_eval(const BodyPrep& b, d3 Q, d3 n, d3 Rp, 
     R P0 = (R)2 * RT<R>::sqrt_(r1c / ((R)2 * mhat)) * RT<R>::sqrt_(rho2 / ((rho1 + sRR) * (rho2 + sRR)));
     R px = (R)L.p[0], py = (R)L.p[1], pz = (R)L.p[2];
     R A = (R)L.amp * isI * P0;
-    set_fock_consts<R>(pe, mhat, (R)-2 * ci, Lr);
+    set_fock_consts<R, G>(pe, mhat, (R)-2 * ci, Lr);
     pe->a_s = A * (px * cx + py * cy + pz * cz);
     pe->a_h = A * (px * pix + py * piy + pz * piz);
     pe->vs[0] = cx; pe->vs[1] = cy; pe->vs[2] = cz;

@@ -18,6 +18,11 @@ size_t path_record_bytes(int precision);
 hipError_t launch_field(const LaunchParams& L, int precision, int fc, const float* rx, const FreqConst* fcs,
                         const uint8_t* mask, const void* rec, uint8_t* flags, void* E, hipStream_t s);
 
+hipError_t launch_adjoint(const LaunchParams& L, int precision, const float* rx, const float* sph, const float* cyl,
+                          const BodyPrep* prep, const FreqConst* fcs, const uint8_t* mask, const void* rec,
+                          const uint8_t* flags, const void* gE, int64_t nblk, double* partial, double* txpart,
+                          void* d_sph, void* d_cyl, void* d_tx, hipStream_t s);
+
 hipError_t launch_census(int64_t n_mask, const uint8_t* mask, int64_t n_rx, const uint8_t* flags,
                          unsigned long long* counts, hipStream_t s);
 

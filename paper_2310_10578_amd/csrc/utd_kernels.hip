@@ -163,9 +163,9 @@ __global__ void __launch_bounds__(256) k_paths(LaunchParams L, const float* __re
             PathPts pts;
             bool ok, caus = false;
             if (P.kind == 0)
-                ok = sphere_creep<R>(P, g, R3, L, sgn, ell, &caus, (PathEval<R>*)nullptr, &pts);
+                ok = sphere_creep<R, double>(P, g, R3, T, L, sgn, ell, &caus, (PathEval<R>*)nullptr, &pts);
             else
-                ok = cyl_creep<R>(P, g, R3, L, sgn, ell, (PathEval<R>*)nullptr, &pts);
+                ok = cyl_creep<R, double>(P, g, R3, T, L, sgn, ell, (PathEval<R>*)nullptr, &pts);
             if (caus) m |= (uint8_t)(1u << kBitCaustic);
             if (!ok) continue;
             if (seg_blocked(pts.P0, pts.P1, L, sph, cyl, b, bo, nodes, tris, stk, stride)) continue;
@@ -174,22 +174,22 @@ __global__ void __launch_bounds__(256) k_paths(LaunchParams L, const float* __re
             PathEval<R> pe;
             bool cz;
             if (P.kind == 0)
-                sphere_creep<R>(P, g, R3, L, sgn, ell, &cz, &pe, nullptr);
+                sphere_creep<R, double>(P, g, R3, T, L, sgn, ell, &cz, &pe, nullptr);
             else
-                cyl_creep<R>(P, g, R3, L, sgn, ell, &pe, nullptr);
+                cyl_creep<R, double>(P, g, R3, T, L, sgn, ell, &pe, nullptr);
             if (nrec < S) pack(pe, &rec[((int64_t)b * S + nrec) * L.n_rx + i]);
             ++nrec;
         }
     }
     double th = 0.0;
-    if (L.lit_branch && refl_angle(P, g, R3, L, &th)) {
+    if (L.lit_branch && refl_angle(P, g, R3, T, &th)) {
         d3 Q, n;
-        refl_point(P, g, R3, L, th, &Q, &n);
+        refl_point<double>(P, g, R3, T, th, &Q, &n);
         if (!seg_blocked(T, Q, L, sph, cyl, b, bo, nodes, tris, stk, stride) &&
             !seg_blocked(Q, R3, L, sph, cyl, b, bo, nodes, tris, stk, stride)) {
             m |= (uint8_t)(1u << kBitRefl);
             PathEval<R> pe;
-            refl_eval<R>(P, Q, n, R3, L, &pe);
+            refl_eval<R, double>(P, Q, n, R3, T, L, &pe);
             if (nrec < S) pack(pe, &rec[((int64_t)b * S + nrec) * L.n_rx + i]);
             ++nrec;
         }
@@ -468,3 +468,5 @@ hipError_t launch_field(const LaunchParams& L, int precision, int fc, const floa
 }
 
 }  // namespace utd
+
+#include "utd_adjoint.h"

@@ -1,0 +1,316 @@
+"""Parity of the HIP adjoint (utd_smooth_field_backward, through the C ABI
+and the autograd binding) against the oracle's frozen-classification
+finite-difference gradient, plus checks against central differences of the
+library's own FP64 forward field.
+
+Gradient vectors (source, then sphere and cylinder parameters) are compared
+normwise: ||g_gpu - g_ref|| / ||g_ref||.  Tolerances: 1e-7 for the FP64 path
+(the oracle's extrapolated differences are good to ~1e-9: (k h)^4 / 480 with
+k h <= 6e-3, plus rounding); 1e-4 for the FP32 path, the field tolerance.  The
+gradient is dominated by the phase term k ds/dtheta, which keeps the FP32
+value accuracy (~1e-7); the slopes of the FP32 table polynomials are less
+accurate than their values (by ~deg^2 / segment half-width) but enter only
+the amplitude terms."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import run_oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-4, 1: 1e-7}
+
+
+def _weights(shape, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def _flat(g):
+    return np.concatenate([np.ravel(g["tx"]), np.ravel(g["sph"]), np.ravel(g["cyl"])])
+
+
+def _tensors(cfg, rx=None, freqs=None):
+    import torch
+    sc = cfg["scene"]
+    sph = torch.from_numpy(np.ascontiguousarray(sc["spheres"], np.float32)).cuda()
+    cyl = torch.from_numpy(np.ascontiguousarray(sc["cylinders"], np.float32)).cuda()
+    rx = cfg["rx"] if rx is None else rx
+    freqs = cfg["freqs"] if freqs is None else freqs
+    rxt = torch.from_numpy(np.ascontiguousarray(rx, np.float32)).cuda()
+    ft = torch.from_numpy(np.ascontiguousarray(freqs, np.float64)).cuda()
+    return sph, cyl, rxt, ft
+
+
+def gpu_grad(cfg, G, precision, rx=None, freqs=None, **kw):
+    import torch
+
+    import paper_2310_10578_amd as utd
+    scene = utd.Scene(cfg["scene"].get("tri"))
+    sph, cyl, rxt, ft = _tensors(cfg, rx, freqs)
+    tx = cfg["tx"]
+    src = utd.make_source(tx["pos"], tx["dipole"], tx["amplitude"])
+    cdt = torch.complex64 if precision == 0 else torch.complex128
+    gt = torch.from_numpy(np.ascontiguousarray(G)).to(cdt).cuda()
+    ds, dc, dt = utd.smooth_field_backward(scene, sph, cyl, src, rxt, ft, gt, precision=precision, **kw)
+    torch.cuda.synchronize()
+    out = dict(tx=dt.cpu().numpy().astype(float), sph=ds.cpu().numpy().astype(float),
+               cyl=dc.cpu().numpy().astype(float))
+    scene.close()
+    return out
+
+
+def oracle_grad(cfg, G, rx=None, freqs=None, opts=None, bodies=None):
+    from oracle import grad
+    sc, tx, r = W.to_oracle(cfg["scene"], cfg["tx"], cfg["rx"] if rx is None else rx)
+    freqs = cfg["freqs"] if freqs is None else freqs
+    return grad.loss_grad(sc, tx, r, freqs, G, opts=opts, bodies=bodies)
+
+
+def _err(a, b):
+    a, b = _flat(a), _flat(b)
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _report(name, e):
+    print("%s gradient normwise error: %.2e" % (name, e), flush=True)
+
+
+# ---------------------------------------------------------------------------
+# against the oracle
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def room_case():
+    cfg = W.small_room(n_cyl=8, n_side=12, spheres=True)
+    G = _weights((cfg["freqs"].size, 3, cfg["rx"].shape[0]), 11)
+    return cfg, G, oracle_grad(cfg, G)
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_small_room_vs_oracle(room_case, precision):
+    """Coarse room: walls and furniture occlude, 8 cylinders and 2 spheres,
+    144 receivers, 5 and 28 GHz; creeping and reflected paths of both body
+    kinds and the direct ray."""
+    cfg, G, go = room_case
+    gg = gpu_grad(cfg, G, precision)
+    e = _err(gg, go)
+    _report("small room p%d" % precision, e)
+    assert e <= TOL[precision]
+
+
+@pytest.fixture(scope="module")
+def sphere_case():
+    cfg = W.config1(n_rx=96, polarisation="hard")
+    cfg["tx"]["dipole"] = np.array([0.6, 0.3, 0.74], np.float32)
+    rng = np.random.default_rng(12)
+    cfg["rx"] = (cfg["rx"] + rng.normal(0, 0.3, cfg["rx"].shape)).astype(np.float32)
+    cfg["freqs"] = np.array([1e9, 2.5e9])
+    G = _weights((2, 3, 96), 13)
+    return cfg, G, oracle_grad(cfg, G, opts=dict(l_enc=1))
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_sphere_encircling_vs_oracle(sphere_case, precision):
+    """Config-1 sphere with receivers jittered off the plane, a tilted dipole
+    and one extra encirclement per side (l_enc = 1)."""
+    cfg, G, go = sphere_case
+    gg = gpu_grad(cfg, G, precision, l_enc=1)
+    e = _err(gg, go)
+    _report("sphere l_enc=1 p%d" % precision, e)
+    assert e <= TOL[precision]
+
+
+def test_adjoint_full_size_sampled():
+    """The adjoint workload at full size in the launch configuration the bench
+    times (room with 200k triangles, 64 cylinders, 128 x 128 receivers, 16
+    frequencies, FP32).  The loss weight is non-zero on 16 sampled receivers
+    only (L is linear in the weight, so the gradient is that of the sampled
+    receivers' loss); the oracle differentiates the source and the 6 bodies
+    with the most paths to them, and every body with no valid path to them
+    must get exactly zero."""
+    cfg = W.config5()
+    n = cfg["rx"].shape[0]
+    rng = np.random.default_rng(14)
+    idx = np.sort(rng.choice(n, 16, replace=False))
+    Eo, info = run_oracle(cfg, rx=cfg["rx"][idx])
+    Gs = 2 * Eo                                   # loss sum |E|^2 over the sampled receivers
+    G = np.zeros((cfg["freqs"].size, 3, n), complex)
+    G[:, :, idx] = Gs
+    gg = gpu_grad(cfg, G, 0)
+    count = {}
+    for key, rec in info["paths"]:
+        if rec["valid"].any():
+            count[key[1]] = count.get(key[1], 0) + int(rec["valid"].sum())
+    top = sorted(count, key=lambda b: -count[b])[:6]
+    go = oracle_grad(cfg, Gs, rx=cfg["rx"][idx], bodies=[("cyl", b) for b in top])
+    sel = dict(tx=gg["tx"], sph=gg["sph"], cyl=gg["cyl"][top])
+    ref = dict(tx=go["tx"], sph=go["sph"], cyl=go["cyl"][top])
+    e = _err(sel, ref)
+    _report("config5 full sampled", e)
+    assert e <= TOL[0]
+    none = [b for b in range(cfg["scene"]["cylinders"].shape[0]) if b not in count]
+    assert np.all(gg["cyl"][none] == 0)
+
+
+# ---------------------------------------------------------------------------
+# against the library's own forward field
+# ---------------------------------------------------------------------------
+
+def _gpu_loss(cfg, G, tx_pos=None, cyl=None, sph=None):
+    import torch
+
+    import paper_2310_10578_amd as utd
+    scene = utd.Scene(cfg["scene"].get("tri"))
+    s, c, rxt, ft = _tensors(cfg)
+    if cyl is not None:
+        c = torch.from_numpy(np.ascontiguousarray(cyl, np.float32)).cuda()
+    if sph is not None:
+        s = torch.from_numpy(np.ascontiguousarray(sph, np.float32)).cuda()
+    tx = cfg["tx"]
+    src = utd.make_source(tx["pos"] if tx_pos is None else tx_pos, tx["dipole"], tx["amplitude"])
+    E, _ = utd.smooth_field(scene, s, c, src, rxt, ft, precision=1)
+    val = float(torch.sum(torch.conj(torch.from_numpy(G).cuda()) * E).real.cpu())
+    scene.close()
+    return val
+
+
+def test_central_differences_of_forward_field():
+    """Central differences (h = 1e-4 m) of the library's FP64 forward field
+    against its FP64 adjoint, on the small room.  The inputs are float32, so
+    the step actually taken is float32(x + h) - float32(x - h).  A step that
+    moves a visibility boundary makes D(h) and D(h/2) disagree by far more
+    than the truncation error; such parameters are skipped (a few).  A plain
+    central difference of e^{-j k s(theta)} has relative error
+    (k h ds/dtheta)^2 / 6, up to ~2.3e-3 at 28 GHz with |ds/dtheta| <= 2 (a
+    reflection point moving along the normal); the extrapolation
+    (4 D(h/2) - D(h)) / 3 removes that term."""
+    cfg = W.small_room(n_cyl=8, n_side=12, spheres=True)
+    G = _weights((cfg["freqs"].size, 3, cfg["rx"].shape[0]), 15)
+    ga = gpu_grad(cfg, G, 1)
+    sc = cfg["scene"]
+    params = [("tx", 0, c) for c in range(3)]
+    params += [("sph", i, c) for i in range(sc["spheres"].shape[0]) for c in range(4)]
+    params += [("cyl", i, c) for i in range(sc["cylinders"].shape[0]) for c in (0, 1, 4)]
+    scale = np.abs(_flat(ga)).max()
+
+    def fd(p, h):
+        grp, i, c = p
+        vals = []
+        steps = []
+        for sgn in (1, -1):
+            tx = np.array(cfg["tx"]["pos"], np.float32)
+            cyl = np.array(sc["cylinders"], np.float32)
+            sph = np.array(sc["spheres"], np.float32)
+            arr = tx if grp == "tx" else (sph[i] if grp == "sph" else cyl[i])
+            arr[c] = np.float32(float(arr[c]) + sgn * h)
+            steps.append(float(arr[c]))
+            vals.append(_gpu_loss(cfg, G, tx_pos=tx, cyl=cyl, sph=sph))
+        return (vals[0] - vals[1]) / (steps[0] - steps[1])
+
+    skipped, a_all, d_all, r_all = 0, [], [], []
+    for p in params:
+        grp, i, c = p
+        a = ga["tx"][c] if grp == "tx" else (ga["sph"][i, c] if grp == "sph" else ga["cyl"][i, {0: 0, 1: 1, 4: 2}[c]])
+        d1, d2 = fd(p, 1e-4), fd(p, 5e-5)
+        if abs(d1 - d2) > 0.02 * scale:
+            skipped += 1
+            continue
+        a_all.append(a)
+        d_all.append(d1)
+        r_all.append((4 * d2 - d1) / 3)
+    a_all, d_all, r_all = map(np.array, (a_all, d_all, r_all))
+    e_plain = np.linalg.norm(d_all - a_all) / np.linalg.norm(a_all)
+    e_rich = np.linalg.norm(r_all - a_all) / np.linalg.norm(a_all)
+    print("central differences h=1e-4: normwise %.2e; extrapolated %.2e; %d of %d parameters skipped"
+          % (e_plain, e_rich, skipped, len(params)), flush=True)
+    assert skipped <= 6
+    assert e_plain <= 3e-3
+    assert e_rich <= 2e-5
+
+
+# ---------------------------------------------------------------------------
+# autograd, determinism, edge cases
+# ---------------------------------------------------------------------------
+
+def test_autograd_matches_c_abi_and_oracle(room_case):
+    """loss = Re sum conj(G) E through ``field`` + ``backward()`` gives the
+    C-ABI gradient (cylinder heights get zero) and hence the oracle's."""
+    import torch
+
+    import paper_2310_10578_amd as utd
+    cfg, G, go = room_case
+    scene = utd.Scene(cfg["scene"].get("tri"))
+    sph, cyl, rxt, ft = _tensors(cfg)
+    sph.requires_grad_(True)
+    cyl.requires_grad_(True)
+    txp = torch.tensor(np.asarray(cfg["tx"]["pos"], np.float32), requires_grad=True)
+    E = utd.field(scene, sph, cyl, txp, rxt, ft, dipole=cfg["tx"]["dipole"], amplitude=cfg["tx"]["amplitude"],
+                  precision=1)
+    Gt = torch.from_numpy(G).cuda()
+    L = torch.sum(torch.conj(Gt) * E).real
+    L.backward()
+    ga = gpu_grad(cfg, G, 1)
+    np.testing.assert_array_equal(cyl.grad[:, 2:4].cpu().numpy(), 0)
+    np.testing.assert_allclose(cyl.grad[:, [0, 1, 4]].cpu().numpy(), ga["cyl"].astype(np.float32), rtol=1e-6,
+                               atol=0)
+    np.testing.assert_allclose(sph.grad.cpu().numpy(), ga["sph"].astype(np.float32), rtol=1e-6, atol=0)
+    np.testing.assert_allclose(txp.grad.numpy(), ga["tx"].astype(np.float32), rtol=1e-6, atol=0)
+    scene.close()
+    got = dict(tx=txp.grad.numpy(), sph=sph.grad.cpu().numpy(), cyl=cyl.grad[:, [0, 1, 4]].cpu().numpy())
+    assert _err(got, go) <= 1e-6
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_reduction_is_bitwise_reproducible(room_case, precision):
+    cfg, G, _ = room_case
+    a = _flat(gpu_grad(cfg, G, precision))
+    b = _flat(gpu_grad(cfg, G, precision))
+    np.testing.assert_array_equal(a, b)
+
+
+def test_empty_inputs_give_zero_gradients():
+    cfg = W.small_room(n_cyl=3, n_side=4, spheres=True)
+    g = gpu_grad(cfg, np.zeros((2, 3, 0), complex), 0, rx=np.zeros((0, 3), np.float32))
+    assert np.all(_flat(g) == 0)
+    g = gpu_grad(cfg, np.zeros((0, 3, 16), complex), 1, freqs=np.zeros(0))
+    assert np.all(_flat(g) == 0)
+
+
+def test_receivers_inside_bodies_contribute_nothing():
+    """A receiver inside a body has E = 0 for every parameter value nearby,
+    so its weight must not change the gradient."""
+    cfg = W.small_room(n_cyl=3, n_side=8, spheres=True)
+    c0 = cfg["scene"]["cylinders"][0]
+    s0 = cfg["scene"]["spheres"][0]
+    extra = np.array([[c0[0], c0[1], 1.2], [s0[0], s0[1], s0[2]]], np.float32)
+    rx = np.concatenate([cfg["rx"], extra])
+    G = _weights((2, 3, rx.shape[0]), 16)
+    g1 = gpu_grad(cfg, G, 1, rx=rx)
+    G[:, :, -2:] *= 7.0
+    g2 = gpu_grad(cfg, G, 1, rx=rx)
+    np.testing.assert_array_equal(_flat(g1), _flat(g2))
+
+
+def test_bad_arguments_are_rejected():
+    import torch
+
+    import paper_2310_10578_amd as utd
+    lib = utd.load_library()
+    cfg = W.small_room(n_cyl=2, n_side=4)
+    sph, cyl, rxt, ft = _tensors(cfg)
+    b, keep = utd._bodies(sph, cyl)
+    src = utd.make_source(cfg["tx"]["pos"])
+    opt = utd.make_options(0)
+    g = torch.zeros((2, 3, 16), dtype=torch.complex64, device="cuda")
+    d = torch.zeros(64, dtype=torch.float32, device="cuda")
+    args = [None, ctypes.byref(b), ctypes.byref(src), rxt.data_ptr(), 16, ft.data_ptr(), 2, ctypes.byref(opt)]
+    st = lib.utd_smooth_field_backward(*args, g.data_ptr(), d.data_ptr(), None, None, None)
+    assert st == -1 and b"d_tx" in lib.utd_last_error()
+    st = lib.utd_smooth_field_backward(*args, g.data_ptr(), None, None, d.data_ptr(), None)
+    assert st == -1 and b"d_cyl" in lib.utd_last_error()
+    st = lib.utd_smooth_field_backward(*args, None, d.data_ptr(), None, d.data_ptr(), None)
+    assert st == -1 and b"grad_E" in lib.utd_last_error()

