@@ -33,6 +33,43 @@ FLOPS_LOS = 36
 PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (published, packed-FP32 rate)
 
 
+TRAFFIC_PROFILE = {"config2": "profiles/hbm_sphere-plane-64f.md"}
+
+
+def kernel_source_digest():
+    """SHA-256 over the device sources (names and contents, sorted by name)."""
+    import glob
+    import hashlib
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2310_10578_amd", "csrc", "*.h")) +
+                   glob.glob(os.path.join(ROOT, "paper_2310_10578_amd", "csrc", "*.hip")))
+    h = hashlib.sha256()
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload_name, kernel_prefix):
+    """HBM bytes per launch of the field kernel from the committed PMC summary
+    (FETCH_SIZE and WRITE_SIZE runs, calibrated against a device copy), or
+    None when there is none for this workload or the device sources have
+    changed since the counters were taken."""
+    rel = TRAFFIC_PROFILE.get(workload_name)
+    if rel is None or not os.path.exists(os.path.join(ROOT, rel)):
+        return None
+    digest, val = None, None
+    with open(os.path.join(ROOT, rel)) as fh:
+        for line in fh:
+            if line.startswith("kernel_sources_sha256:"):
+                digest = line.split(":", 1)[1].strip()
+            if line.startswith("traffic_bytes " + kernel_prefix):
+                val = float(line.rsplit("=", 1)[1])
+    if digest != kernel_source_digest():
+        return None
+    return val
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -221,7 +258,8 @@ def main():
         "config": {"workload": cfg["name"], "receivers": n_rx, "bodies": n_body, "frequencies": n_f,
                    "triangles": scene.n_tri, "evals_per_step": evals, "parallelism": "single-gpu"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": measured_traffic(args.workload, "utd::k_field<float"),
                      "kernel": "k_field<float>", "kernel_ms": field_avg_s * 1e3,
                      "flops_per_launch": flops, "paths": n_paths, "los_receivers": los},
         "kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]},
