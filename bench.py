@@ -81,6 +81,9 @@ def parse():
     ap.add_argument("--adjoint", type=int, default=1,
                     help="also time forward + backward on the adjoint workload (room, 64 cylinders, 128^2 rx, 16 f)")
     ap.add_argument("--adjoint-steps", type=int, default=3)
+    ap.add_argument("--batched", type=int, default=1,
+                    help="also time the batched crowd workload (256 frames) against per-frame calls")
+    ap.add_argument("--batched-steps", type=int, default=3)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device copy of this size (HBM counter calibration under a profiler)")
     return ap.parse_args()
@@ -179,6 +182,55 @@ def adjoint_bench(steps):
             "bwd_kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]}}
 
 
+def batched_bench(steps):
+    """The crowd workload (256 frames of the room, 0-64 moving cylinders and
+    1k-64k receivers per frame, 8 frequencies): one batched call (autotuned
+    tiles, graph replay) against the same frames as per-frame calls."""
+    import torch
+
+    import paper_2310_10578_amd as utd
+    import workloads as W
+    from paper_2310_10578_amd.autotune import tune_batched
+    cfg = W.config4()
+    dev = "cuda:0"
+    scene = utd.Scene(cfg["tri"])
+    bo_h, ro_h = cfg["body_off"], cfg["rx_off"]
+    bo = torch.from_numpy(bo_h).to(dev)
+    ro = torch.from_numpy(ro_h).to(dev)
+    cyl = torch.from_numpy(cfg["cylinders"]).to(dev)
+    rx = torch.from_numpy(cfg["rx"]).to(dev)
+    freqs = torch.tensor(cfg["freqs"], dtype=torch.float64, device=dev)
+    src = utd.make_source(cfg["tx"]["pos"], cfg["tx"]["dipole"], cfg["tx"]["amplitude"])
+    n_rx, n_f = rx.shape[0], freqs.shape[0]
+    out = torch.empty((3 * n_f * n_rx,), dtype=torch.complex64, device=dev)
+    flags = torch.empty((n_rx,), dtype=torch.uint8, device=dev)
+    tune = tune_batched(scene, bo, cyl, ro, rx, src, freqs, out=out, flags=flags)
+    b_ms = _timed(lambda: utd.smooth_field_batched(scene, bo, cyl, ro, rx, src, freqs, out=out, flags=flags),
+                  steps, 1)
+    frames = []
+    for f in range(len(bo_h) - 1):
+        n = int(ro_h[f + 1] - ro_h[f])
+        if n == 0:
+            continue
+        frames.append((cyl[bo_h[f]:bo_h[f + 1]], rx[ro_h[f]:ro_h[f + 1]],
+                       out[3 * n_f * ro_h[f]: 3 * n_f * ro_h[f + 1]].view(n_f, 3, n), flags[ro_h[f]:ro_h[f + 1]]))
+
+    def per_frame():
+        for c, r, o, fl in frames:
+            utd.smooth_field(scene, None, c, src, r, freqs, out=o, flags=fl)
+
+    p_ms = _timed(per_frame, max(1, steps - 1), 1)
+    nb = np.diff(bo_h)
+    nr = np.diff(ro_h)
+    evals = int((nb * nr).sum()) * n_f
+    scene.close()
+    return {"workload": cfg["name"], "frames": len(bo_h) - 1, "receivers": n_rx, "triangles": int(cfg["tri"].shape[0]),
+            "evals_per_step": evals, "batched_ms": b_ms, "per_frame_ms": p_ms,
+            "batched_evals_per_s": evals / (b_ms / 1e3), "per_frame_evals_per_s": evals / (p_ms / 1e3),
+            "batched_over_per_frame_speedup": p_ms / b_ms,
+            "tiles": {"best": list(tune["best"]), "ms": {"%dx%d" % k: v for k, v in tune["ms"].items()}}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -267,6 +319,8 @@ def main():
     }
     if args.adjoint:
         res["adjoint"] = adjoint_bench(args.adjoint_steps)
+    if args.batched:
+        res["batched"] = batched_bench(args.batched_steps)
     if args.cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(cfg, min(args.cpu_sample, n_rx))
     print(json.dumps(res))

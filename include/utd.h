@@ -146,23 +146,41 @@ utd_status utd_smooth_field_backward(const utd_scene *scene, const utd_bodies *b
                                      const void *grad_E, void *d_cyl, void *d_sph, void *d_tx,
                                      void *stream);
 
-/* Many frames in one launch: frame f has cylinders cyl[body_off[f] .. body_off[f+1])
- * and receivers rx[rx_off[f] .. rx_off[f+1]); all frames share the scene, the
- * source and the frequencies.  body_off, rx_off: device int64 [n_frames+1],
- * non-decreasing, starting at 0.  E_out: device complex; each frame keeps the
- * layout of utd_smooth_field and frames are concatenated: frame f occupies
- * the [n_f][3][n_rx_f] block starting at complex element 3 * n_f * rx_off[f].
- * rx_flags: device uint8 [rx_off[n_frames]] or NULL.
- * max_rx_frame and total_rx (host values) bound the frame sizes and size the
- * work queue; they must be >= the true values.
- * Errors as for utd_smooth_field; UTD_E_ARG if n_frames < 0. */
+/* Many frames in one launch (dynamic scenes: a moving crowd over a static
+ * room, Sec. III; the field of every frame is that of utd_smooth_field with
+ * the frame's cylinders as bodies).  Frame f has the cylinders
+ * cyl[body_off[f] .. body_off[f+1]) and the receivers rx[rx_off[f] .. rx_off[f+1]);
+ * all frames share the scene triangles, the source and the frequencies.
+ *   body_off, rx_off  device int64 [n_frames + 1], non-decreasing, starting at 0
+ *   cyl               device float32 [n_cyl][5] (cx, cy, z0, h, a)
+ *   rx                device float32 [n_rx][3]
+ *   E_out             device complex, precision as utd_smooth_field; frame f
+ *                     occupies the [n_f][3][n_rx_f] block that starts at complex
+ *                     element 3 * n_f * rx_off[f] (frames concatenated)
+ *   rx_flags          device uint8 [n_rx] or NULL
+ * Offsets are clamped to [0, n_cyl] / [0, n_rx] and to non-decreasing values
+ * on the device, so malformed offsets give empty frames, never out-of-bounds
+ * accesses.  One work queue over (frame, tile of receivers) feeds a
+ * persistent kernel; the call replays a captured HIP graph (prep + persistent
+ * kernel) as long as its arguments repeat (device data may change), and when
+ * the stream is itself being captured it records the two launches into the
+ * caller's graph instead (the workspace must then exist from an earlier call
+ * of at least this size).  Tile shape: utd_batched_config.  The library keeps
+ * one workspace per device: concurrent batched calls on one device race.
+ * Errors as for utd_smooth_field; UTD_E_ARG for n_frames < 0, n_cyl < 0, NULL
+ * offsets with n_frames, n_rx, n_f > 0, or a capture without workspace. */
 utd_status utd_smooth_field_batched(const utd_scene *scene, int64_t n_frames,
-                                    const int64_t *body_off, const float *cyl,
-                                    const int64_t *rx_off, const float *rx,
-                                    int64_t max_rx_frame, int64_t total_rx,
+                                    const int64_t *body_off, const float *cyl, int64_t n_cyl,
+                                    const int64_t *rx_off, const float *rx, int64_t n_rx,
                                     const utd_source *tx, const double *freqs_hz, int n_f,
                                     const utd_options *opt, void *E_out, uint8_t *rx_flags,
                                     void *stream);
+
+/* Tile shape of utd_smooth_field_batched: receivers per work item (64, 128
+ * or 256; one lane per receiver) and resident workgroups per compute unit of
+ * the persistent grid (1..16).  Chosen by the autotuner of the Python
+ * package; applies to later calls.  Errors: UTD_E_ARG for other values. */
+utd_status utd_batched_config(int tile_rx, int blocks_per_cu);
 
 /* Path census (reporting): runs the classification and visibility stage of
  * utd_smooth_field for the same inputs and writes, to the host array

@@ -18,7 +18,7 @@ FLAG_INSIDE, FLAG_CAUSTIC, FLAG_LOS, FLAG_TX_INSIDE = 1, 2, 4, 8
 
 EXPORTS = ["utd_default_options", "utd_scene_create", "utd_scene_destroy", "utd_scene_triangles",
            "utd_scene_nodes", "utd_smooth_field", "utd_smooth_field_backward", "utd_smooth_field_batched",
-           "utd_path_census", "utd_profile_enable", "utd_profile_read", "utd_last_error"]
+           "utd_path_census", "utd_batched_config", "utd_profile_enable", "utd_profile_read", "utd_last_error"]
 KERNELS = ["prep", "occlude", "field", "backward", "reduce", "batched"]
 
 
@@ -46,6 +46,11 @@ def load_library(path=LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError("libutd.so is not built (%s); run __graft_entry__.build()" % path)
+    # One HIP runtime per process: PyTorch bundles its own libamdhip64, so it
+    # is loaded first and libutd's dependency resolves to that copy (stream
+    # handles and device pointers then belong to the same runtime).  Loading
+    # libutd first would bring in a second runtime that hides the GPU from torch.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
     lib.utd_default_options.argtypes = [ctypes.POINTER(Options)]
@@ -64,8 +69,10 @@ def load_library(path=LIB_PATH):
     lib.utd_smooth_field_backward.argtypes = [vp, ctypes.POINTER(Bodies), ctypes.POINTER(Source), vp, i64, vp, i32,
                                               ctypes.POINTER(Options), vp, vp, vp, vp, vp]
     lib.utd_smooth_field_backward.restype = i32
-    lib.utd_smooth_field_batched.argtypes = [vp, i64, vp, vp, vp, vp, i64, i64, ctypes.POINTER(Source), vp, i32,
+    lib.utd_smooth_field_batched.argtypes = [vp, i64, vp, vp, i64, vp, vp, i64, ctypes.POINTER(Source), vp, i32,
                                              ctypes.POINTER(Options), vp, vp, vp]
+    lib.utd_batched_config.argtypes = [i32, i32]
+    lib.utd_batched_config.restype = i32
     lib.utd_smooth_field_batched.restype = i32
     lib.utd_path_census.argtypes = [vp, ctypes.POINTER(Bodies), ctypes.POINTER(Source), vp, i64,
                                     ctypes.POINTER(Options), vp, vp]
@@ -271,6 +278,42 @@ def field(scene, spheres, cylinders, tx_pos, rx, freqs, dipole=(0.0, 0.0, 1.0), 
     kw = dict(precision=precision, l_enc=l_enc, bodies_occlude=bodies_occlude, lit_branch=lit_branch,
               caustic_guard=caustic_guard)
     return _autograd_function().apply(spheres, cylinders, tx_pos, rx, freqs, scene, dipole, amplitude, kw)
+
+
+def batched_config(tile_rx, blocks_per_cu):
+    """Tile shape of the batched kernel (receivers per work item, workgroups per CU)."""
+    _check(load_library().utd_batched_config(int(tile_rx), int(blocks_per_cu)))
+
+
+def smooth_field_batched(scene, body_off, cylinders, rx_off, rx, source, freqs, precision=0, l_enc=0,
+                         bodies_occlude=True, lit_branch=True, caustic_guard=1e-6, out=None, flags=None, stream=None):
+    """Fields of many frames in one launch.  body_off, rx_off: int64 GPU tensors
+    [n_frames + 1]; cylinders [n_cyl, 5], rx [n_rx, 3]: float32 GPU tensors.
+    Returns (E, flags): E is a flat complex tensor of 3 * n_f * n_rx elements,
+    frame f's [n_f, 3, n_rx_f] block starting at 3 * n_f * rx_off[f]."""
+    torch = _torch()
+    lib = load_library()
+    _dev(rx, torch.float32, (3,), "rx")
+    _dev(cylinders, torch.float32, (5,), "cylinders")
+    _dev(freqs, torch.float64, None, "freqs")
+    _dev(body_off, torch.int64, None, "body_off")
+    _dev(rx_off, torch.int64, None, "rx_off")
+    if body_off.dim() != 1 or rx_off.shape != body_off.shape:
+        raise ValueError("body_off and rx_off must be 1-D of equal length n_frames + 1")
+    n_frames = body_off.shape[0] - 1
+    n, nf, nc = rx.shape[0], freqs.shape[0], cylinders.shape[0]
+    cdt = torch.complex64 if precision == 0 else torch.complex128
+    if out is None:
+        out = torch.empty((3 * nf * n,), dtype=cdt, device=rx.device)
+    if flags is None:
+        flags = torch.empty((n,), dtype=torch.uint8, device=rx.device)
+    opt = make_options(precision, l_enc, bodies_occlude, lit_branch, caustic_guard)
+    _check(lib.utd_smooth_field_batched(
+        scene.handle if scene is not None else None, max(n_frames, 0), body_off.data_ptr(),
+        cylinders.data_ptr() if nc else None, nc, rx_off.data_ptr(), rx.data_ptr() if n else None, n,
+        ctypes.byref(source), freqs.data_ptr() if nf else None, nf, ctypes.byref(opt),
+        out.data_ptr() if out.numel() else None, flags.data_ptr() if n else None, _stream(stream)))
+    return out, flags
 
 
 def profile_enable(on=True):

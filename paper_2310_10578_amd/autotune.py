@@ -1,0 +1,48 @@
+"""Tile autotuner of the batched entry point.
+
+The persistent kernel of ``utd_smooth_field_batched`` has two shape knobs:
+receivers per work item (one lane each: 64, 128 or 256) and resident
+workgroups per compute unit of the grid.  Small tiles balance frames of very
+different cost (the body count per frame varies from 0 to 64) but share the
+LDS-staged tables over fewer lanes; more workgroups per CU hide the latency
+of the BVH traversal until registers and LDS run out.  ``tune_batched`` times
+every candidate on the caller's own workload with HIP events on the current
+stream and leaves the fastest configured in the library.
+"""
+from . import batched_config, smooth_field_batched
+
+CANDIDATES = ((64, 2), (64, 4), (64, 8), (128, 1), (128, 2), (128, 4), (256, 1), (256, 2))
+
+
+def tune_batched(scene, body_off, cylinders, rx_off, rx, source, freqs, precision=0, reps=2, candidates=CANDIDATES,
+                 out=None, flags=None, **kw):
+    """Returns {"best": (tile_rx, blocks_per_cu), "ms": {(tile, bpc): ms per call}}."""
+    import torch
+    n, nf = rx.shape[0], freqs.shape[0]
+    cdt = torch.complex64 if precision == 0 else torch.complex128
+    if out is None:
+        out = torch.empty((3 * nf * n,), dtype=cdt, device=rx.device)
+    if flags is None:
+        flags = torch.empty((n,), dtype=torch.uint8, device=rx.device)
+    stream = torch.cuda.current_stream()
+    ms = {}
+    for tile, bpc in candidates:
+        batched_config(tile, bpc)
+
+        def call():
+            smooth_field_batched(scene, body_off, cylinders, rx_off, rx, source, freqs, precision=precision,
+                                 out=out, flags=flags, **kw)
+
+        call()                                    # capture + warm
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            call()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms[(tile, bpc)] = e0.elapsed_time(e1) / reps
+    best = min(ms, key=ms.get)
+    batched_config(*best)
+    return {"best": best, "ms": ms}

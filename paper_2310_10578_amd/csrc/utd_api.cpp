@@ -7,6 +7,7 @@
 #include <new>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -154,6 +155,21 @@ struct Workspace {
         return hipSuccess;
     }
 };
+
+// Batched calls: tile shape (set by utd_batched_config, normally from the
+// autotuner) and, per device, the workspace and the last captured graph.
+struct BatchState {
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<unsigned char> key;
+};
+std::mutex g_batch_mu;
+std::map<int, BatchState> g_batch;
+int g_batch_tile = 128;
+int g_batch_bpc = 4;
 
 int pick_fc(int precision, int64_t n_rx, int n_f) {
     int fc = precision == 0 ? 4 : 2;
@@ -357,10 +373,143 @@ utd_status utd_smooth_field_backward(const utd_scene* scene, const utd_bodies* b
     return UTD_OK;
 }
 
-utd_status utd_smooth_field_batched(const utd_scene*, int64_t, const int64_t*, const float*, const int64_t*,
-                                    const float*, int64_t, int64_t, const utd_source*, const double*, int,
-                                    const utd_options*, void*, uint8_t*, void*) {
-    return fail(UTD_E_UNSUPPORTED, "batched not built yet");
+utd_status utd_batched_config(int tile_rx, int blocks_per_cu) {
+    if (tile_rx != 64 && tile_rx != 128 && tile_rx != 256) return fail(UTD_E_ARG, "tile_rx must be 64, 128 or 256");
+    if (blocks_per_cu < 1 || blocks_per_cu > 16) return fail(UTD_E_ARG, "blocks_per_cu must be in 1..16");
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    g_batch_tile = tile_rx;
+    g_batch_bpc = blocks_per_cu;
+    return UTD_OK;
+}
+
+utd_status utd_smooth_field_batched(const utd_scene* scene, int64_t n_frames, const int64_t* body_off,
+                                    const float* cyl, int64_t n_cyl, const int64_t* rx_off, const float* rx,
+                                    int64_t n_rx, const utd_source* tx, const double* freqs, int n_f,
+                                    const utd_options* opt, void* E_out, uint8_t* rx_flags, void* stream) {
+    utd_bodies bodies{nullptr, 0, cyl, n_cyl};
+    if (n_frames < 0) return fail(UTD_E_ARG, "n_frames < 0");
+    if (n_cyl < 0) return fail(UTD_E_ARG, "n_cyl < 0");
+    if (n_cyl > ((int64_t)1 << 31) / 8) return fail(UTD_E_ARG, "too many cylinders");
+    if (n_frames > ((int64_t)1 << 31) / 8) return fail(UTD_E_ARG, "too many frames");
+    if (n_cyl && !cyl) return fail(UTD_E_ARG, "cyl is NULL with n_cyl > 0");
+    if (n_rx < 0 || n_f < 0) return fail(UTD_E_ARG, "negative n_rx or n_f");
+    if (n_rx && !rx) return fail(UTD_E_ARG, "rx is NULL");
+    if (n_f && !freqs) return fail(UTD_E_ARG, "freqs is NULL");
+    if (!tx || !opt) return fail(UTD_E_ARG, "tx and opt must not be NULL");
+    if (opt->precision != 0 && opt->precision != 1) return fail(UTD_E_ARG, "precision must be 0 or 1");
+    if (opt->l_enc < 0 || opt->l_enc > 2) return fail(UTD_E_ARG, "l_enc must be in 0..2");
+    if (!(opt->caustic_guard >= 0)) return fail(UTD_E_ARG, "caustic_guard must be >= 0");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(tx->pos[a]) || !std::isfinite(tx->dipole[a]))
+            return fail(UTD_E_ARG, "non-finite source position or dipole");
+    if (!std::isfinite(tx->amplitude)) return fail(UTD_E_ARG, "non-finite amplitude");
+    if (n_frames == 0 || n_rx == 0 || n_f == 0) return UTD_OK;
+    if (!body_off || !rx_off) return fail(UTD_E_ARG, "body_off and rx_off must not be NULL");
+    if (!E_out) return fail(UTD_E_ARG, "E_out is NULL");
+    hipError_t e = ensure_tables();
+    if (e != hipSuccess) return hip_fail(e, "table upload");
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0;
+    e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    BatchState& st = g_batch[dev];
+    utd::BatchParams B;
+    B.L = make_params(&bodies, tx, 0, n_f, opt);
+    B.L.n_sph = 0;
+    B.n_frames = n_frames;
+    B.n_cyl = n_cyl;
+    B.n_rx = n_rx;
+    B.tile = g_batch_tile;
+    int ncu = 0;
+    e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "device attribute");
+    int n_blocks = g_batch_bpc * (ncu > 0 ? ncu : 1);
+
+    // workspace: body and frequency constants, sanitised offsets, tile prefix sum, counter
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    size_t o_prep = 0;
+    size_t o_fc = up(o_prep + sizeof(utd::BodyPrep) * (size_t)(n_cyl > 0 ? n_cyl : 1));
+    size_t o_bo = up(o_fc + sizeof(utd::FreqConst) * (size_t)n_f);
+    size_t o_ro = up(o_bo + sizeof(int64_t) * (size_t)(n_frames + 1));
+    size_t o_to = up(o_ro + sizeof(int64_t) * (size_t)(n_frames + 1));
+    size_t o_cnt = up(o_to + sizeof(int64_t) * (size_t)(n_frames + 1));
+    size_t need = o_cnt + 256;
+
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    e = hipStreamIsCapturing(s, &cs);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+    const bool caller_capturing = cs != hipStreamCaptureStatusNone;
+    if (st.ws_bytes < need) {
+        if (caller_capturing)
+            return fail(UTD_E_ARG, "workspace too small while the stream is being captured: make one call of this "
+                                   "size outside capture first");
+        if (st.exec) { (void)hipGraphExecDestroy(st.exec); st.exec = nullptr; }
+        if (st.graph) { (void)hipGraphDestroy(st.graph); st.graph = nullptr; }
+        if (st.ws) (void)hipFree(st.ws);
+        st.ws = nullptr;
+        st.ws_bytes = 0;
+        e = hipMalloc((void**)&st.ws, need);
+        if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(UTD_E_OOM, "batched workspace") : hip_fail(e, "hipMalloc");
+        st.ws_bytes = need;
+        st.key.clear();
+    }
+    char* w = st.ws;
+    auto launch = [&](hipStream_t ls) {
+        return utd::launch_batch(B, opt->precision, n_blocks, body_off, rx_off, rx, cyl, freqs,
+                                 (utd::BodyPrep*)(w + o_prep), (utd::FreqConst*)(w + o_fc), (int64_t*)(w + o_bo),
+                                 (int64_t*)(w + o_ro), (int64_t*)(w + o_to), (unsigned*)(w + o_cnt),
+                                 scene ? scene->d_nodes : nullptr, scene ? scene->d_tris : nullptr, E_out, rx_flags,
+                                 ls);
+    };
+    if (caller_capturing) {
+        // the caller records these launches into its own graph
+        ProfScope ps(UTD_K_BATCHED, s);
+        e = launch(s);
+        return e == hipSuccess ? UTD_OK : hip_fail(e, "kernel launch");
+    }
+    // one graph (prep + persistent kernel) per distinct argument set, replayed
+    // while the arguments repeat (device data may change between calls)
+    std::vector<unsigned char> key;
+    auto put = [&key](const void* p, size_t n) {
+        const unsigned char* c = (const unsigned char*)p;
+        key.insert(key.end(), c, c + n);
+    };
+    const void* ptrs[] = {scene, body_off, cyl, rx_off, rx, freqs, E_out, rx_flags};
+    int64_t ints[] = {n_frames, n_cyl, n_rx, (int64_t)n_f, (int64_t)g_batch_tile, (int64_t)n_blocks};
+    put(ptrs, sizeof ptrs);
+    put(ints, sizeof ints);
+    put(tx, sizeof *tx);
+    put(opt, sizeof *opt);
+    if (!st.exec || key != st.key) {
+        if (st.exec) { (void)hipGraphExecDestroy(st.exec); st.exec = nullptr; }
+        if (st.graph) { (void)hipGraphDestroy(st.graph); st.graph = nullptr; }
+        st.key.clear();
+        if (!st.cap) {
+            e = hipStreamCreateWithFlags(&st.cap, hipStreamNonBlocking);
+            if (e != hipSuccess) return hip_fail(e, "capture stream");
+        }
+        e = hipStreamBeginCapture(st.cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        hipError_t el = launch(st.cap);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(st.cap, &g);
+        if (el != hipSuccess || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return hip_fail(el != hipSuccess ? el : e, "graph capture");
+        }
+        st.graph = g;
+        e = hipGraphInstantiate(&st.exec, st.graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            st.exec = nullptr;
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        st.key = key;
+    }
+    ProfScope ps(UTD_K_BATCHED, s);
+    e = hipGraphLaunch(st.exec, s);
+    return e == hipSuccess ? UTD_OK : hip_fail(e, "hipGraphLaunch");
 }
 
 }  // extern "C"

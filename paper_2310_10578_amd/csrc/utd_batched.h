@@ -1,0 +1,361 @@
+// Many frames in one launch (utd_smooth_field_batched): every frame has its
+// own cylinders and receivers (CSR offsets), all frames share the scene
+// triangles, the source and the frequencies.  Included by utd_kernels.hip.
+//
+//   k_batch_prep   body constants of every cylinder, frequency constants,
+//                  sanitised per-frame offsets, the tile prefix sum and the
+//                  work-queue counter reset (one block does the scan)
+//   k_batch        persistent: each workgroup takes the next (frame, tile of
+//                  TILE receivers) from an atomic work queue until the queue
+//                  is empty.  A lane owns one receiver: inside / line-of-sight
+//                  flags, then per body of its frame the path geometry, the
+//                  visibility tests, and for each visible path the Fock
+//                  evaluation of every frequency, added in place to the
+//                  lane's slice of E (initialised with the direct ray).
+//
+// Fusing visibility and field keeps no per-path records (config-4 sized runs
+// have ~2.7e8 receiver-body pairs); the per-receiver accumulation order is
+// that of the single-frame kernels (direct ray, then bodies in order, paths
+// in (ell, side) order, reflection last), so a frame gives the same field as
+// utd_smooth_field on that frame up to floating-point contraction.
+#pragma once
+
+namespace utd {
+
+// One block scans the frames; all threads fill body and frequency constants.
+__global__ void __launch_bounds__(1024) k_batch_prep(BatchParams B, const int64_t* __restrict__ body_off,
+                                                     const int64_t* __restrict__ rx_off,
+                                                     const float* __restrict__ cyl, const double* __restrict__ freqs,
+                                                     BodyPrep* __restrict__ prep, FreqConst* __restrict__ fc,
+                                                     int64_t* __restrict__ bo, int64_t* __restrict__ ro,
+                                                     int64_t* __restrict__ tile_off, unsigned* __restrict__ counter) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nt = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t b = tid; b < B.n_cyl; b += nt) prep[b] = body_prep(B.L.T, nullptr, 0, cyl, (int)b);
+    for (int64_t f = tid; f < B.L.n_f; f += nt) {
+        double k = kTwoPi * freqs[f] / kC0;
+        double k13 = cbrt(k), k16 = sqrt(k13);
+        FreqConst c;
+        c.rev_per_m = freqs[f] / kC0;
+        c.kd = k; c.k13d = k13; c.k16d = k16; c.km16d = 1.0 / k16; c.skd = sqrt(k); c.ik13d = 1.0 / k13;
+        c.kf = (float)k; c.k13f = (float)k13; c.k16f = (float)k16; c.km16f = (float)(1.0 / k16);
+        c.skf = (float)sqrt(k); c.ik13f = (float)(1.0 / k13);
+        fc[f] = c;
+    }
+    if (blockIdx.x != 0) return;
+    // Sanitised offsets: clamped to [0, n] and made non-decreasing, so a
+    // malformed frame becomes empty instead of indexing out of bounds.
+    __shared__ int64_t s_scan[1024];
+    __shared__ int64_t s_carry[3];
+    if (threadIdx.x == 0) {
+        s_carry[0] = 0;   // tiles
+        s_carry[1] = 0;   // running max of body offsets
+        s_carry[2] = 0;   // running max of receiver offsets
+        tile_off[0] = 0;
+        bo[0] = 0;
+        ro[0] = 0;
+        *counter = 0u;
+    }
+    __syncthreads();
+    for (int64_t base = 0; base < B.n_frames; base += blockDim.x) {
+        int64_t f = base + threadIdx.x;
+        int64_t b1 = 0, r1 = 0;
+        if (f < B.n_frames) {
+            b1 = body_off[f + 1];
+            r1 = rx_off[f + 1];
+            b1 = b1 < 0 ? 0 : (b1 > B.n_cyl ? B.n_cyl : b1);
+            r1 = r1 < 0 ? 0 : (r1 > B.n_rx ? B.n_rx : r1);
+        }
+        // running maxima (prefix max) of the clamped end offsets
+        s_scan[threadIdx.x] = b1;
+        __syncthreads();
+        for (int w = 1; w < (int)blockDim.x; w <<= 1) {
+            int64_t v = threadIdx.x >= (unsigned)w ? s_scan[threadIdx.x - w] : 0;
+            __syncthreads();
+            if (v > s_scan[threadIdx.x]) s_scan[threadIdx.x] = v;
+            __syncthreads();
+        }
+        int64_t bm = s_scan[threadIdx.x] > s_carry[1] ? s_scan[threadIdx.x] : s_carry[1];
+        __syncthreads();
+        s_scan[threadIdx.x] = r1;
+        __syncthreads();
+        for (int w = 1; w < (int)blockDim.x; w <<= 1) {
+            int64_t v = threadIdx.x >= (unsigned)w ? s_scan[threadIdx.x - w] : 0;
+            __syncthreads();
+            if (v > s_scan[threadIdx.x]) s_scan[threadIdx.x] = v;
+            __syncthreads();
+        }
+        int64_t rm = s_scan[threadIdx.x] > s_carry[2] ? s_scan[threadIdx.x] : s_carry[2];
+        __syncthreads();
+        // receivers of frame f: [ro[f], rm); its start is the previous frame's end
+        s_scan[threadIdx.x] = rm;
+        __syncthreads();
+        int64_t r0 = threadIdx.x == 0 ? s_carry[2] : s_scan[threadIdx.x - 1];
+        int64_t nt_f = f < B.n_frames ? (rm - r0 + B.tile - 1) / B.tile : 0;
+        __syncthreads();
+        // tile counts: inclusive prefix sum
+        s_scan[threadIdx.x] = nt_f;
+        __syncthreads();
+        for (int w = 1; w < (int)blockDim.x; w <<= 1) {
+            int64_t v = threadIdx.x >= (unsigned)w ? s_scan[threadIdx.x - w] : 0;
+            __syncthreads();
+            s_scan[threadIdx.x] += v;
+            __syncthreads();
+        }
+        int64_t toff = s_carry[0] + s_scan[threadIdx.x];
+        if (f < B.n_frames) {
+            tile_off[f + 1] = toff;
+            bo[f + 1] = bm;
+            ro[f + 1] = rm;
+        }
+        __syncthreads();
+        int last = (int)((B.n_frames - base < (int64_t)blockDim.x ? B.n_frames - base : blockDim.x) - 1);
+        if ((int)threadIdx.x == last) {
+            s_carry[0] = toff;
+            s_carry[1] = bm;
+            s_carry[2] = rm;
+        }
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Per-lane list of visible paths (body << 3 | path bit), a column of LDS per
+// lane.  A lane first runs the visibility of all of its frame's paths, then
+// evaluates the listed paths at every frequency; the list is flushed early
+// when it could overflow.  Keeping the two phases apart keeps the traversal
+// state and the Fock evaluation from being live at once.
+constexpr int kListCap = 32;
+
+template <typename R>
+__device__ __forceinline__ void eval_listed(const LaunchParams& L, d3 R3, d3 T, int64_t li,
+                                            const BodyPrep* __restrict__ fprep, const FreqConst* __restrict__ fcs,
+                                            const Tabs<R>& tb, const uint16_t* list, int stride, int n,
+                                            R* __restrict__ E) {
+    const int64_t nrx = L.n_rx;
+#pragma unroll 1
+    for (int k = 0; k < n; ++k) {
+        const int ent = list[k * stride];
+        const int b = ent >> 3, bit = ent & 7;
+        const BodyPrep P = fprep[b];
+        RxGeo g = rx_geo<double, Kinds::Cylinders>(P, R3);
+        PathEval<R> pe;
+        if (bit == kBitRefl) {
+            double th = 0.0;
+            refl_angle<Kinds::Cylinders>(P, g, R3, T, &th);
+            d3 Q, n3;
+            refl_point<double, Kinds::Cylinders>(P, g, R3, T, th, &Q, &n3);
+            refl_eval<R, double>(P, Q, n3, R3, T, L, &pe);
+        } else {
+            const int ell = bit >> 1, sgn = (bit & 1) ? -1 : 1;
+            cyl_creep<R, double>(P, g, R3, T, L, sgn, ell, &pe, nullptr);
+        }
+        const bool any_refl = __any(pe.refl != 0);
+#pragma unroll 1
+        for (int j = 0; j < L.n_f; ++j) {
+            R e[6];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                int64_t o = ((int64_t)j * 3 + c) * nrx + li;
+                e[2 * c] = E[2 * o];
+                e[2 * c + 1] = E[2 * o + 1];
+            }
+            FreqC<R> fc(fcs[j]);
+            add_path<R>(pe, tb, fc, any_refl, e);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                int64_t o = ((int64_t)j * 3 + c) * nrx + li;
+                E[2 * o] = e[2 * c];
+                E[2 * o + 1] = e[2 * c + 1];
+            }
+        }
+    }
+}
+
+// The work of one receiver lane of a tile.
+template <typename R>
+__device__ __forceinline__ void batch_lane(const LaunchParams& L, d3 R3, int64_t li, const float* __restrict__ fcyl,
+                                           const BodyPrep* __restrict__ fprep, const FreqConst* __restrict__ fcs,
+                                           const Tabs<R>& tb, const float4* __restrict__ nodes,
+                                           const float4* __restrict__ tris, int* stk, uint16_t* list, int stride,
+                                           R* __restrict__ E, uint8_t* fl_out) {
+    const int nb = L.n_cyl;
+    const int64_t nrx = L.n_rx;
+    d3 T = mk(L.T[0], L.T[1], L.T[2]);
+    bool inside = false, tx_inside = false;
+    for (int b = 0; b < nb; ++b) {
+        inside |= inside_body(fprep[b], R3);
+        tx_inside |= inside_body(fprep[b], T);
+    }
+    uint8_t fl = (tx_inside ? kFlagTxInside : 0) | (inside ? kFlagInside : 0);
+    const bool dead = inside || tx_inside;
+    bool los = false;
+    if (!dead) los = !seg_blocked(T, R3, L, nullptr, fcyl, -1, true, nodes, tris, stk, stride);
+    if (los) fl |= kFlagLos;
+    // direct ray (or zero) initialises the lane's field
+    R e3[3] = {(R)0, (R)0, (R)0};
+    double sd = 0.0;
+    const bool use_los = los && L.lit_branch;
+    if (use_los) {
+        d3 v = mk(R3.x - L.T[0], R3.y - L.T[1], R3.z - L.T[2]);
+        sd = norm(v);
+        R isd = (R)(1.0 / sd);
+        R shx = (R)v.x * isd, shy = (R)v.y * isd, shz = (R)v.z * isd;
+        R px = (R)L.p[0], py = (R)L.p[1], pz = (R)L.p[2];
+        R pd = px * shx + py * shy + pz * shz;
+        R A = (R)L.amp * isd;
+        e3[0] = A * (px - pd * shx); e3[1] = A * (py - pd * shy); e3[2] = A * (pz - pd * shz);
+    }
+#pragma unroll 1
+    for (int j = 0; j < L.n_f; ++j) {
+        cplx<R> ph{(R)0, (R)0};
+        if (use_los) ph = phase_rev<R>(fcs[j].rev_per_m * sd);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            int64_t o = ((int64_t)j * 3 + c) * nrx + li;
+            E[2 * o] = (R)0 + e3[c] * ph.re;
+            E[2 * o + 1] = (R)0 + e3[c] * ph.im;
+        }
+    }
+    if (!dead) {
+        const bool bo_ = L.bodies_occlude != 0;
+        const int per_body = 2 * (L.l_enc + 1) + 1;
+        int n = 0;
+#pragma unroll 1
+        for (int b = 0; b <= nb; ++b) {
+            if (b == nb || n > kListCap - per_body) {
+                eval_listed<R>(L, R3, T, li, fprep, fcs, tb, list, stride, n, E);
+                n = 0;
+                if (b == nb) break;
+            }
+            const BodyPrep P = fprep[b];
+            RxGeo g = rx_geo<double, Kinds::Cylinders>(P, R3);
+            // paths in (ell, side) order, reflection last; one visibility
+            // call site (legs in a loop) keeps the traversal code single
+#pragma unroll 1
+            for (int bit = 0; bit <= kBitRefl; ++bit) {
+                const bool refl = bit == kBitRefl;
+                if (!refl && bit >= 2 * (L.l_enc + 1)) continue;
+                if (refl && !L.lit_branch) continue;
+                PathPts pts;
+                bool ok;
+                if (refl) {
+                    double th = 0.0;
+                    ok = refl_angle<Kinds::Cylinders>(P, g, R3, T, &th);
+                    if (ok) {
+                        d3 Q, n3;
+                        refl_point<double, Kinds::Cylinders>(P, g, R3, T, th, &Q, &n3);
+                        pts.P0 = T; pts.P1 = Q; pts.P2 = Q; pts.P3 = R3;
+                    }
+                } else {
+                    const int ell = bit >> 1, sgn = (bit & 1) ? -1 : 1;
+                    ok = cyl_creep<R, double>(P, g, R3, T, L, sgn, ell, (PathEval<R>*)nullptr, &pts);
+                }
+#pragma unroll 1
+                for (int leg = 0; leg < 2 && ok; ++leg) {
+                    d3 a = leg ? pts.P2 : pts.P0, c = leg ? pts.P3 : pts.P1;
+                    ok = !seg_blocked(a, c, L, nullptr, fcyl, b, bo_, nodes, tris, stk, stride);
+                }
+                if (ok) list[(n++) * stride] = (uint16_t)((b << 3) | bit);
+            }
+        }
+    }
+    if (fl_out) *fl_out = fl;
+}
+
+template <typename R, int TILE>
+__global__ void __launch_bounds__(TILE) k_batch(BatchParams B, const float* __restrict__ rx,
+                                                const float* __restrict__ cyl, const BodyPrep* __restrict__ prep,
+                                                const FreqConst* __restrict__ fcs, const int64_t* __restrict__ bo,
+                                                const int64_t* __restrict__ ro, const int64_t* __restrict__ tile_off,
+                                                unsigned* __restrict__ counter, const float4* __restrict__ nodes,
+                                                const float4* __restrict__ tris, R* __restrict__ E_out,
+                                                uint8_t* __restrict__ flags) {
+    __shared__ int stack[kStackDepth * TILE];
+    __shared__ uint16_t s_list[kListCap * TILE];
+    __shared__ R s_reg[TableStage<R>::NREG];
+    __shared__ R s_tf[TableStage<R>::NTF];
+    __shared__ int64_t s_tile;
+    Tabs<R> tb = TableStage<R>::stage(s_reg, s_tf);
+    const int64_t total = tile_off[B.n_frames];
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(counter, 1u);
+        __syncthreads();
+        // the tile index is workgroup-uniform: keep it (and everything derived
+        // from it: frame, offsets, body constants) in scalar registers
+        const int64_t t = uniform64(s_tile);
+        __syncthreads();
+        if (t >= total) break;
+        // frame: the last f with tile_off[f] <= t (empty frames are skipped)
+        int64_t lo = 0, hi = B.n_frames;
+        while (hi - lo > 1) {
+            int64_t mid = (lo + hi) >> 1;
+            if (tile_off[mid] <= t) lo = mid; else hi = mid;
+        }
+        const int64_t fr = lo;
+        const int64_t r0 = ro[fr], r1 = ro[fr + 1];
+        const int64_t li = (t - tile_off[fr]) * TILE + threadIdx.x;
+        if (r0 + li < r1) {
+            const int64_t i = r0 + li;
+            const int64_t b0 = bo[fr];
+            LaunchParams L = B.L;
+            L.n_sph = 0;
+            L.n_cyl = (int)(bo[fr + 1] - b0);
+            L.n_rx = r1 - r0;
+            d3 R3 = mk(rx[3 * i], rx[3 * i + 1], rx[3 * i + 2]);
+            R* E = E_out + 2 * 3 * (int64_t)B.L.n_f * r0;
+            batch_lane<R>(L, R3, li, cyl + 5 * b0, prep + b0, fcs, tb, nodes, tris, stack + threadIdx.x,
+                          s_list + threadIdx.x, TILE, E, flags ? flags + i : nullptr);
+        }
+    }
+}
+
+// Work-queue launch: the grid is persistent (blocks_per_cu x CUs workgroups).
+template <typename R, int TILE>
+static hipError_t launch_batch_tile(const BatchParams& B, int n_blocks, const float* rx, const float* cyl,
+                                    const BodyPrep* prep, const FreqConst* fcs, const int64_t* bo, const int64_t* ro,
+                                    const int64_t* tile_off, unsigned* counter, const float4* nodes,
+                                    const float4* tris, void* E, uint8_t* flags, hipStream_t s) {
+    hipLaunchKernelGGL((k_batch<R, TILE>), dim3(n_blocks), dim3(TILE), 0, s, B, rx, cyl, prep, fcs, bo, ro, tile_off,
+                       counter, nodes, tris, (R*)E, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchParams& B, int precision, int n_blocks, const int64_t* body_off,
+                        const int64_t* rx_off, const float* rx, const float* cyl, const double* freqs,
+                        BodyPrep* prep, FreqConst* fcs, int64_t* bo, int64_t* ro, int64_t* tile_off,
+                        unsigned* counter, const float4* nodes, const float4* tris, void* E, uint8_t* flags,
+                        hipStream_t s) {
+    int64_t nwork = B.n_cyl > B.L.n_f ? B.n_cyl : B.L.n_f;
+    int pb = (int)((nwork + 1023) / 1024);
+    pb = pb < 1 ? 1 : (pb > 1024 ? 1024 : pb);
+    hipLaunchKernelGGL(k_batch_prep, dim3(pb), dim3(1024), 0, s, B, body_off, rx_off, cyl, freqs, prep, fcs, bo, ro,
+                       tile_off, counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (precision == 0) {
+        switch (B.tile) {
+            case 64: return launch_batch_tile<float, 64>(B, n_blocks, rx, cyl, prep, fcs, bo, ro, tile_off, counter,
+                                                         nodes, tris, E, flags, s);
+            case 128: return launch_batch_tile<float, 128>(B, n_blocks, rx, cyl, prep, fcs, bo, ro, tile_off,
+                                                           counter, nodes, tris, E, flags, s);
+            default: return launch_batch_tile<float, 256>(B, n_blocks, rx, cyl, prep, fcs, bo, ro, tile_off,
+                                                          counter, nodes, tris, E, flags, s);
+        }
+    }
+    switch (B.tile) {
+        case 64: return launch_batch_tile<double, 64>(B, n_blocks, rx, cyl, prep, fcs, bo, ro, tile_off, counter,
+                                                      nodes, tris, E, flags, s);
+        case 128: return launch_batch_tile<double, 128>(B, n_blocks, rx, cyl, prep, fcs, bo, ro, tile_off, counter,
+                                                        nodes, tris, E, flags, s);
+        default: return launch_batch_tile<double, 256>(B, n_blocks, rx, cyl, prep, fcs, bo, ro, tile_off, counter,
+                                                       nodes, tris, E, flags, s);
+    }
+}
+
+}  // namespace utd

@@ -132,8 +132,26 @@ __device__ __forceinline__ bool bvh_anyhit(const float4* __restrict__ nodes, con
     }
 }
 
+// Conservative FP32 reject: the closest approach of the segment to the
+// point (axis) C is farther than a by more than the rounding error of the
+// computation (bounded by tol = 4e-6 (|w|^2 + |d|^2), with w = P0 - C and
+// d = P1 - P0), so the exact FP64 test below would also say "not crossed".
+// Most bodies are far from most segments; this skips their FP64 solve.
+__device__ __forceinline__ bool far_from(float wx, float wy, float wz, float dx, float dy, float dz, float a) {
+    float dd = dx * dx + dy * dy + dz * dz;
+    float wd = wx * dx + wy * dy + wz * dz;
+    float ww = wx * wx + wy * wy + wz * wz;
+    float t = dd > 0.0f ? fminf(fmaxf(-wd / dd, 0.0f), 1.0f) : 0.0f;
+    float qx = wx + t * dx, qy = wy + t * dy, qz = wz + t * dz;
+    float dist2 = qx * qx + qy * qy + qz * qz;
+    return dist2 > a * a + 4e-6f * (ww + dd);
+}
+
 // Solid sphere (cx, cy, cz, a) crossed strictly inside the segment.
 __device__ __forceinline__ bool seg_sphere(d3 P0, d3 P1, const float* s) {
+    if (far_from((float)(P0.x - s[0]), (float)(P0.y - s[1]), (float)(P0.z - s[2]), (float)(P1.x - P0.x),
+                 (float)(P1.y - P0.y), (float)(P1.z - P0.z), s[3]))
+        return false;
     d3 d = P1 - P0;
     d3 w = P0 - mk(s[0], s[1], s[2]);
     double a = s[3];
@@ -147,6 +165,9 @@ __device__ __forceinline__ bool seg_sphere(d3 P0, d3 P1, const float* s) {
 
 // Solid finite vertical cylinder (cx, cy, z0, h, a).
 __device__ __forceinline__ bool seg_cylinder(d3 P0, d3 P1, const float* c) {
+    if (far_from((float)(P0.x - c[0]), (float)(P0.y - c[1]), 0.0f, (float)(P1.x - P0.x), (float)(P1.y - P0.y),
+                 0.0f, c[4]))
+        return false;
     d3 d = P1 - P0;
     double wx = P0.x - c[0], wy = P0.y - c[1];
     double a = c[4];

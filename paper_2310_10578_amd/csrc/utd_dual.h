@@ -50,10 +50,49 @@ __device__ __forceinline__ float val(float x) { return x; }
 template <typename T> __device__ __forceinline__ T val(Dual<T> x) { return x.v; }
 template <typename G> __device__ __forceinline__ d3 val3(V3<G> a) { return d3{val(a.x), val(a.y), val(a.z)}; }
 
+// sin and cos of a moderate FP64 angle (|x| < 1e4: the geometry's angles
+// stay within a few turns).  Cody-Waite reduction by pi/2 with a two-term
+// constant (pi/2 = P1 + P2, P1 the double nearest pi/2, the first product
+// exact through the fused multiply-add), then the Taylor series of sin and
+// cos on [-pi/4, pi/4] to the x^17 / x^18 terms (truncation < 2e-19).  Short
+// and register-light compared with a full-range library routine.
+__device__ __forceinline__ void sincos_moderate(double x, double* s, double* c) {
+    const double P1 = 1.5707963267948966192;          // double nearest pi/2
+    const double P2 = 6.123233995736766036e-17;        // pi/2 - P1
+    double k = rint(x * 0.63661977236758134308);       // x * 2/pi
+    double r = fma(-k, P1, x);
+    r = fma(-k, P2, r);
+    double r2 = r * r;
+    // sin r = r - r^3 (1/3! - r^2/5! + ... - r^14/17!), cos r = 1 - r^2 (1/2! - r^2/4! + ... + r^16/18!)
+    double ps = -1.0 / 355687428096000.0;              // -1/17!
+    ps = fma(ps, r2, 1.0 / 1307674368000.0);           //  1/15!
+    ps = fma(ps, r2, -1.0 / 6227020800.0);             // -1/13!
+    ps = fma(ps, r2, 1.0 / 39916800.0);                //  1/11!
+    ps = fma(ps, r2, -1.0 / 362880.0);                 // -1/9!
+    ps = fma(ps, r2, 1.0 / 5040.0);                    //  1/7!
+    ps = fma(ps, r2, -1.0 / 120.0);                    // -1/5!
+    ps = fma(ps, r2, 1.0 / 6.0);                       //  1/3!
+    double sn = fma(-r * r2, ps, r);
+    double pc = 1.0 / 6402373705728000.0;              //  1/18!
+    pc = fma(pc, r2, -1.0 / 20922789888000.0);         // -1/16!
+    pc = fma(pc, r2, 1.0 / 87178291200.0);             //  1/14!
+    pc = fma(pc, r2, -1.0 / 479001600.0);              // -1/12!
+    pc = fma(pc, r2, 1.0 / 3628800.0);                 //  1/10!
+    pc = fma(pc, r2, -1.0 / 40320.0);                  // -1/8!
+    pc = fma(pc, r2, 1.0 / 720.0);                     //  1/6!
+    pc = fma(pc, r2, -1.0 / 24.0);                     // -1/4!
+    pc = fma(pc, r2, 0.5);                             //  1/2!
+    double cs = fma(-r2, pc, 1.0);
+    int q = ((int)k) & 3;
+    double so = (q & 1) ? cs : sn, co = (q & 1) ? sn : cs;
+    *s = (q & 2) ? -so : so;
+    *c = ((q + 1) & 2) ? -co : co;
+}
+
 // elementary functions of the geometry scalar (FP64 or dual FP64)
 __device__ __forceinline__ double gsqrt(double x) { return ::sqrt(x); }
 __device__ __forceinline__ double gatan2(double y, double x) { return ::atan2(y, x); }
-__device__ __forceinline__ void gsincos(double x, double* s, double* c) { ::sincos(x, s, c); }
+__device__ __forceinline__ void gsincos(double x, double* s, double* c) { sincos_moderate(x, s, c); }
 __device__ __forceinline__ double gfloor(double x) { return ::floor(x); }
 
 __device__ __forceinline__ Dual<double> gsqrt(Dual<double> x) {
@@ -66,7 +105,7 @@ __device__ __forceinline__ Dual<double> gatan2(Dual<double> y, Dual<double> x) {
 }
 __device__ __forceinline__ void gsincos(Dual<double> x, Dual<double>* s, Dual<double>* c) {
     double sv, cv;
-    ::sincos(x.v, &sv, &cv);
+    sincos_moderate(x.v, &sv, &cv);
     *s = Dual<double>(sv, cv * x.d);
     *c = Dual<double>(cv, -sv * x.d);
 }

@@ -138,65 +138,79 @@ template <typename G> struct RxGeoT {
 using RxGeo = RxGeoT<double>;
 
 template <typename G>
-__device__ __forceinline__ RxGeoT<G> rx_geo(const BodyPrepT<G>& b, V3<G> R) {
+__device__ __forceinline__ RxGeoT<G> rx_geo_sphere(const BodyPrepT<G>& b, V3<G> R) {
     RxGeoT<G> g;
     G a = b.a;
     G cgT = a / b.dT, sgT = b.sI0 / b.dT;
-    if (b.kind == 0) {
-        V3<G> C = v3(b.c);
-        V3<G> eT = v3(b.eT);
-        V3<G> v = R - C;
-        G d2 = dot(v, v);
-        G along = dot(v, eT);
-        g.along = along;
-        V3<G> w = v - along * eT;
-        g.wn = gnorm(w);
-        if (g.wn > 1e-300) {
-            g.eperp = (G(1.0) / g.wn) * w;
-        } else {
-            d3 ap = any_perp(val3(eT));
-            g.eperp = V3<G>{ap.x, ap.y, ap.z};
-        }
-        g.dR = gsqrt(d2);
-        g.ok = g.dR > a;
-        g.sD0 = g.ok ? gsqrt((g.dR - a) * (g.dR + a)) : G(0.0);
-        G id2 = G(1.0) / d2;
-        // th2_+ = theta_R - gR ; th2_- = 2 pi - theta_R - gR
-        g.c2p = (along * a + g.wn * g.sD0) * id2;
-        g.s2p = (g.wn * a - along * g.sD0) * id2;
-        g.c2m = (along * a - g.wn * g.sD0) * id2;
-        g.s2m = -(g.wn * a + along * g.sD0) * id2;
-        // phi_+ = th2_+ - gT in (-pi, pi)
-        G cp = g.c2p * cgT + g.s2p * sgT;
-        G sp = g.s2p * cgT - g.c2p * sgT;
-        g.phi_p = gatan2(sp, cp);
-        G gR = gatan2(g.sD0, a);
-        g.phi_m = (kTwoPi - 2.0 * b.gT - 2.0 * gR) - g.phi_p;
+    V3<G> C = v3(b.c);
+    V3<G> eT = v3(b.eT);
+    V3<G> v = R - C;
+    G d2 = dot(v, v);
+    G along = dot(v, eT);
+    g.along = along;
+    V3<G> w = v - along * eT;
+    g.wn = gnorm(w);
+    if (g.wn > 1e-300) {
+        g.eperp = (G(1.0) / g.wn) * w;
     } else {
-        G x = R.x - b.c[0], y = R.y - b.c[1];
-        G r2 = x * x + y * y;
-        g.dR = gsqrt(r2);
-        g.ok = g.dR > a;
-        g.sD0 = g.ok ? gsqrt((g.dR - a) * (g.dR + a)) : G(0.0);
-        g.wn = G(0.0);
-        g.along = G(0.0);
-        g.eperp = V3<G>{G(0.0), G(0.0), G(0.0)};
-        G ir = G(1.0) / r2;
-        // R's tangent points: u_R rotated by -gR (side +) and +gR (side -)
-        G cg = a, sg = g.sD0;     // times 1/dR each, folded into ir
-        g.c2p = (x * cg + y * sg) * ir;
-        g.s2p = (y * cg - x * sg) * ir;
-        g.c2m = (x * cg - y * sg) * ir;
-        g.s2m = (y * cg + x * sg) * ir;
-        // T's tangent point of side +: u_T rotated by +gT
-        G u1x = b.eT[0] * cgT - b.eT[1] * sgT, u1y = b.eT[1] * cgT + b.eT[0] * sgT;
-        G p = gatan2(u1x * g.s2p - u1y * g.c2p, u1x * g.c2p + u1y * g.s2p);
-        G gR = gatan2(g.sD0, a);
-        G gsum = b.gT + gR;
-        g.phi_p = p >= -gsum ? p : p + kTwoPi;
-        g.phi_m = (kTwoPi - 2.0 * gsum) - g.phi_p;
+        d3 ap = any_perp(val3(eT));
+        g.eperp = V3<G>{ap.x, ap.y, ap.z};
     }
+    g.dR = gsqrt(d2);
+    g.ok = g.dR > a;
+    g.sD0 = g.ok ? gsqrt((g.dR - a) * (g.dR + a)) : G(0.0);
+    G id2 = G(1.0) / d2;
+    // th2_+ = theta_R - gR ; th2_- = 2 pi - theta_R - gR
+    g.c2p = (along * a + g.wn * g.sD0) * id2;
+    g.s2p = (g.wn * a - along * g.sD0) * id2;
+    g.c2m = (along * a - g.wn * g.sD0) * id2;
+    g.s2m = -(g.wn * a + along * g.sD0) * id2;
+    // phi_+ = th2_+ - gT in (-pi, pi)
+    G cp = g.c2p * cgT + g.s2p * sgT;
+    G sp = g.s2p * cgT - g.c2p * sgT;
+    g.phi_p = gatan2(sp, cp);
+    G gR = gatan2(g.sD0, a);
+    g.phi_m = (kTwoPi - 2.0 * b.gT - 2.0 * gR) - g.phi_p;
     return g;
+}
+
+template <typename G>
+__device__ __forceinline__ RxGeoT<G> rx_geo_cylinder(const BodyPrepT<G>& b, V3<G> R) {
+    RxGeoT<G> g;
+    G a = b.a;
+    G cgT = a / b.dT, sgT = b.sI0 / b.dT;
+    G x = R.x - b.c[0], y = R.y - b.c[1];
+    G r2 = x * x + y * y;
+    g.dR = gsqrt(r2);
+    g.ok = g.dR > a;
+    g.sD0 = g.ok ? gsqrt((g.dR - a) * (g.dR + a)) : G(0.0);
+    g.wn = G(0.0);
+    g.along = G(0.0);
+    g.eperp = V3<G>{G(0.0), G(0.0), G(0.0)};
+    G ir = G(1.0) / r2;
+    // R's tangent points: u_R rotated by -gR (side +) and +gR (side -)
+    G cg = a, sg = g.sD0;     // times 1/dR each, folded into ir
+    g.c2p = (x * cg + y * sg) * ir;
+    g.s2p = (y * cg - x * sg) * ir;
+    g.c2m = (x * cg - y * sg) * ir;
+    g.s2m = (y * cg + x * sg) * ir;
+    // T's tangent point of side +: u_T rotated by +gT
+    G u1x = b.eT[0] * cgT - b.eT[1] * sgT, u1y = b.eT[1] * cgT + b.eT[0] * sgT;
+    G p = gatan2(u1x * g.s2p - u1y * g.c2p, u1x * g.c2p + u1y * g.s2p);
+    G gR = gatan2(g.sD0, a);
+    G gsum = b.gT + gR;
+    g.phi_p = p >= -gsum ? p : p + kTwoPi;
+    g.phi_m = (kTwoPi - 2.0 * gsum) - g.phi_p;
+    return g;
+}
+
+// Body kinds a kernel handles: both (dispatch on b.kind) or cylinders only.
+enum class Kinds { Any, Cylinders };
+
+template <typename G, Kinds K = Kinds::Any>
+__device__ __forceinline__ RxGeoT<G> rx_geo(const BodyPrepT<G>& b, V3<G> R) {
+    if (K == Kinds::Cylinders || b.kind == 1) return rx_geo_cylinder<G>(b, R);
+    return rx_geo_sphere<G>(b, R);
 }
 
 // ---------------------------------------------------------------------------
@@ -361,10 +375,11 @@ __device__ __forceinline__ double alhazen(double a, double p1x, double p1y, doub
 // Reflection point for a lit receiver: the angle parameter (sphere: polar
 // angle in the T-C-R plane; cylinder: azimuth), false if the receiver is not
 // lit by this body or the point is off the lateral surface.
+template <Kinds K = Kinds::Any>
 __device__ __forceinline__ bool refl_angle(const BodyPrep& b, const RxGeo& g, d3 Rp, d3 T, double* th_out) {
     if (!(b.ok && g.ok)) return false;
     double a = b.a;
-    if (b.kind == 0) {
+    if (K == Kinds::Any && b.kind == 0) {
         if (!(g.phi_p < 0)) return false;
         // T at (dT, 0), R at (along, wn) in the plane basis; the arc seen
         // from both runs from R's tangent point (thR - gR = phi_+ + gT) to T's (gT)
@@ -385,7 +400,7 @@ __device__ __forceinline__ bool refl_angle(const BodyPrep& b, const RxGeo& g, d3
     double rx = Rp.x - b.c[0], ry = Rp.y - b.c[1];
     double al = alhazen(a, tx, ty, rx, ry, lo, hi);
     double s, c;
-    sincos(al, &s, &c);
+    gsincos(al, &s, &c);
     double qx = a * c, qy = a * s;
     double lt = sqrt((qx - tx) * (qx - tx) + (qy - ty) * (qy - ty));
     double lr = sqrt((qx - rx) * (qx - rx) + (qy - ry) * (qy - ry));
@@ -410,12 +425,12 @@ __device__ __forceinline__ G refl_angle_g(const BodyPrepT<G>& b, const RxGeoT<G>
 }
 
 // Reflection point and its normal from the angle.
-template <typename G>
+template <typename G, Kinds K = Kinds::Any>
 __device__ __forceinline__ void refl_point(const BodyPrepT<G>& b, const RxGeoT<G>& g, V3<G> Rp, V3<G> T, G th,
                                            V3<G>* Q, V3<G>* n) {
     G s, c;
     gsincos(th, &s, &c);
-    if (b.kind == 0) {
+    if (K == Kinds::Any && b.kind == 0) {
         V3<G> eT = v3(b.eT);
         *n = c * eT + s * g.eperp;
         *Q = v3(b.c) + b.a * (*n);

@@ -9,6 +9,15 @@
 namespace utd {
 
 hipError_t pack_tables(hipStream_t s);
+
+// Frames of a batched call (see utd_batched.h).
+struct BatchParams {
+    LaunchParams L;          // source, frequency count and options (n_sph = 0)
+    int64_t n_frames;
+    int64_t n_cyl;           // cylinders in the array (bound for body_off)
+    int64_t n_rx;            // receivers in the array (bound for rx_off)
+    int tile;                // receivers per work item (= blockDim.x)
+};
 hipError_t launch_prep(const LaunchParams& L, const float* sph, const float* cyl, const double* freqs,
                        BodyPrep* prep, FreqConst* fc, hipStream_t s);
 hipError_t launch_paths(const LaunchParams& L, int precision, const float* rx, const float* sph, const float* cyl,
@@ -22,6 +31,12 @@ hipError_t launch_adjoint(const LaunchParams& L, int precision, const float* rx,
                           const BodyPrep* prep, const FreqConst* fcs, const uint8_t* mask, const void* rec,
                           const uint8_t* flags, const void* gE, int64_t nblk, double* partial, double* txpart,
                           void* d_sph, void* d_cyl, void* d_tx, hipStream_t s);
+
+hipError_t launch_batch(const BatchParams& B, int precision, int n_blocks, const int64_t* body_off,
+                        const int64_t* rx_off, const float* rx, const float* cyl, const double* freqs,
+                        BodyPrep* prep, FreqConst* fcs, int64_t* bo, int64_t* ro, int64_t* tile_off,
+                        unsigned* counter, const float4* nodes, const float4* tris, void* E, uint8_t* flags,
+                        hipStream_t s);
 
 hipError_t launch_census(int64_t n_mask, const uint8_t* mask, int64_t n_rx, const uint8_t* flags,
                          unsigned long long* counts, hipStream_t s);

@@ -470,3 +470,4 @@ hipError_t launch_field(const LaunchParams& L, int precision, int fc, const floa
 }  // namespace utd
 
 #include "utd_adjoint.h"
+#include "utd_batched.h"
