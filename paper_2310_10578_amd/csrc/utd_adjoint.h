@@ -8,8 +8,8 @@
 // Per (receiver, body) lane and per valid path:
 //   1. record adjoint (reverse mode over the frequency loop): lambda_r =
 //      dL/dr for every frequency-independent record scalar r (path length,
-//      Fock constants xh / uh / qhat, amplitudes, polarisation vectors),
-//      summed over all frequencies.  The partial derivatives of the Fock
+//      Fock constants xh / uh / qhat, amplitude-weighted polarisation
+//      vectors), summed over all frequencies.  The partial derivatives of the Fock
 //      coefficients come from the table polynomials evaluated on dual numbers
 //      (three directions: xh, uh, qhat).
 //   2. geometry tangents (forward mode): the path geometry re-evaluated on
@@ -31,7 +31,7 @@ constexpr int kAdjComp = 8;   // per-block record: 3 source + 4 body + pad
 
 template <typename R> struct RecAdj {
     double s;                  // path length (the phase term dominates)
-    R xh, uh, qhat, a_s, a_h;
+    R xh, uh, qhat;
     R vs[3], vh[3];
 };
 
@@ -43,7 +43,7 @@ __device__ __forceinline__ void record_adjoint(const PathEval<R>& pe, const Tabs
     using D = Dual<R>;
     RecAdj<R> l;
     l.s = 0.0;
-    l.xh = l.uh = l.qhat = l.a_s = l.a_h = (R)0;
+    l.xh = l.uh = l.qhat = (R)0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) l.vs[c] = l.vh[c] = (R)0;
     const bool refl = pe.refl != 0;
@@ -71,7 +71,7 @@ __device__ __forceinline__ void record_adjoint(const PathEval<R>& pe, const Tabs
             a.ixi = D(ixi, dir == 0 ? dixi : (R)0);
             a.h = D(h, dir == 0 ? dh : (R)0);
             cplx<D> ks, kh;
-            fock_kernel<D>(tb, a, refl, refl, &ks, &kh);
+            fock_kernel<D, true>(tb, a, refl, &ks, &kh);
             if (dir == 0) {
                 Ks = cplx<R>{ks.re.v, ks.im.v};
                 Kh = cplx<R>{kh.re.v, kh.im.v};
@@ -89,24 +89,21 @@ __device__ __forceinline__ void record_adjoint(const PathEval<R>& pe, const Tabs
             gh.re += g[c].re * pe.vh[c]; gh.im -= g[c].im * pe.vh[c];
         }
         cplx<R> Zs = cmul(P, gs), Zh = cmul(P, gh);
-        // L_f = Re(a_s K_s Zs + a_h K_h Zh)
+        // L_f = Re(K_s Zs + K_h Zh)
         cplx<R> KZs = cmul(Ks, Zs), KZh = cmul(Kh, Zh);
-        l.a_s += KZs.re;
-        l.a_h += KZh.re;
-        l.s += kTwoPi * fc.rev_per_m * (double)(pe.a_s * KZs.im + pe.a_h * KZh.im);
+        l.s += kTwoPi * fc.rev_per_m * (double)(KZs.im + KZh.im);
         R dx[3];
 #pragma unroll
         for (int dir = 0; dir < 3; ++dir)
-            dx[dir] = pe.a_s * (dKs[dir].re * Zs.re - dKs[dir].im * Zs.im) +
-                      pe.a_h * (dKh[dir].re * Zh.re - dKh[dir].im * Zh.im);
+            dx[dir] = (dKs[dir].re * Zs.re - dKs[dir].im * Zs.im) + (dKh[dir].re * Zh.re - dKh[dir].im * Zh.im);
         l.xh += dx[0];
         l.uh += dx[1];
         l.qhat += dx[2];
         cplx<R> Ws = cmul(P, Ks), Wh = cmul(P, Kh);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            l.vs[c] += pe.a_s * (Ws.re * g[c].re + Ws.im * g[c].im);
-            l.vh[c] += pe.a_h * (Wh.re * g[c].re + Wh.im * g[c].im);
+            l.vs[c] += Ws.re * g[c].re + Ws.im * g[c].im;
+            l.vh[c] += Wh.re * g[c].re + Wh.im * g[c].im;
         }
     }
     *out = l;
@@ -115,7 +112,7 @@ __device__ __forceinline__ void record_adjoint(const PathEval<R>& pe, const Tabs
 // Step 2: sum_r lambda_r dr/dtheta for one tangent.
 template <typename R, typename RD, typename GD>
 __device__ __forceinline__ double contract(const RecAdj<R>& l, const PathEvalT<RD, GD>& p) {
-    R r = l.xh * p.xh.d + l.uh * p.uh.d + l.qhat * p.qhat.d + l.a_s * p.a_s.d + l.a_h * p.a_h.d;
+    R r = l.xh * p.xh.d + l.uh * p.uh.d + l.qhat * p.qhat.d;
 #pragma unroll
     for (int c = 0; c < 3; ++c) r += l.vs[c] * p.vs[c].d + l.vh[c] * p.vh[c].d;
     return l.s * p.s_tot.d + (double)r;

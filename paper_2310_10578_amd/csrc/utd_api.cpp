@@ -273,13 +273,9 @@ utd_status utd_smooth_field(const utd_scene* scene, const utd_bodies* bodies, co
     const float4* nodes = scene ? scene->d_nodes : nullptr;
     const float4* tris = scene ? scene->d_tris : nullptr;
     {
-        ProfScope ps(UTD_K_PREP, s);
-        e = utd::launch_prep(L, bodies->sph, bodies->cyl, freqs, w.prep, w.fc, s);
-    }
-    if (e == hipSuccess) {
         ProfScope ps(UTD_K_OCCLUDE, s);
-        e = utd::launch_paths(L, opt->precision, rx, bodies->sph, bodies->cyl, w.prep, nodes, tris, w.mask, w.rec,
-                              flags, s);
+        e = utd::launch_paths(L, opt->precision, rx, bodies->sph, bodies->cyl, freqs, w.prep, w.fc, nodes, tris,
+                              w.mask, w.rec, flags, s);
     }
     int fc = pick_fc(opt->precision, n_rx, n_f);
     if (e == hipSuccess) {
@@ -312,10 +308,10 @@ utd_status utd_path_census(const utd_scene* scene, const utd_bodies* bodies, con
     char* ws = w.base;
     unsigned long long host[10] = {0};
     e = hipMemsetAsync(w.counters, 0, 16 * sizeof(unsigned long long), s);
-    if (e == hipSuccess) e = utd::launch_prep(L, bodies->sph, bodies->cyl, nullptr, w.prep, w.fc, s);
     if (e == hipSuccess)
-        e = utd::launch_paths(L, 0, rx, bodies->sph, bodies->cyl, w.prep, scene ? scene->d_nodes : nullptr,
-                              scene ? scene->d_tris : nullptr, w.mask, w.rec, w.flags, s);
+        e = utd::launch_paths(L, 0, rx, bodies->sph, bodies->cyl, nullptr, w.prep, w.fc,
+                              scene ? scene->d_nodes : nullptr, scene ? scene->d_tris : nullptr, w.mask, w.rec,
+                              w.flags, s);
     if (e == hipSuccess) e = utd::launch_census(nb > 0 ? (int64_t)nb * n_rx : 0, w.mask, n_rx, w.flags, w.counters, s);
     if (e == hipSuccess) e = hipMemcpyAsync(host, w.counters, sizeof host, hipMemcpyDeviceToHost, s);
     hipError_t e2 = hipFreeAsync(ws, s);
@@ -353,13 +349,9 @@ utd_status utd_smooth_field_backward(const utd_scene* scene, const utd_bodies* b
     const float4* nodes = scene ? scene->d_nodes : nullptr;
     const float4* tris = scene ? scene->d_tris : nullptr;
     if (work) {
-        ProfScope ps(UTD_K_PREP, s);
-        e = utd::launch_prep(L, bodies->sph, bodies->cyl, freqs, w.prep, w.fc, s);
-    }
-    if (work && e == hipSuccess) {
         ProfScope ps(UTD_K_OCCLUDE, s);
-        e = utd::launch_paths(L, opt->precision, rx, bodies->sph, bodies->cyl, w.prep, nodes, tris, w.mask, w.rec,
-                              w.flags, s);
+        e = utd::launch_paths(L, opt->precision, rx, bodies->sph, bodies->cyl, freqs, w.prep, w.fc, nodes, tris,
+                              w.mask, w.rec, w.flags, s);
     }
     if (e == hipSuccess) {
         ProfScope ps(UTD_K_BACKWARD, s);

@@ -32,16 +32,7 @@ __global__ void __launch_bounds__(1024) k_batch_prep(BatchParams B, const int64_
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nt = (int64_t)gridDim.x * blockDim.x;
     for (int64_t b = tid; b < B.n_cyl; b += nt) prep[b] = body_prep(B.L.T, nullptr, 0, cyl, (int)b);
-    for (int64_t f = tid; f < B.L.n_f; f += nt) {
-        double k = kTwoPi * freqs[f] / kC0;
-        double k13 = cbrt(k), k16 = sqrt(k13);
-        FreqConst c;
-        c.rev_per_m = freqs[f] / kC0;
-        c.kd = k; c.k13d = k13; c.k16d = k16; c.km16d = 1.0 / k16; c.skd = sqrt(k); c.ik13d = 1.0 / k13;
-        c.kf = (float)k; c.k13f = (float)k13; c.k16f = (float)k16; c.km16f = (float)(1.0 / k16);
-        c.skf = (float)sqrt(k); c.ik13f = (float)(1.0 / k13);
-        fc[f] = c;
-    }
+    for (int64_t f = tid; f < B.L.n_f; f += nt) fc[f] = freq_const(freqs[f]);
     if (blockIdx.x != 0) return;
     // Sanitised offsets: clamped to [0, n] and made non-decreasing, so a
     // malformed frame becomes empty instead of indexing out of bounds.
@@ -166,7 +157,10 @@ __device__ __forceinline__ void eval_listed(const LaunchParams& L, d3 R3, d3 T, 
                 e[2 * c + 1] = E[2 * o + 1];
             }
             FreqC<R> fc(fcs[j]);
-            add_path<R>(pe, tb, fc, any_refl, e);
+            if (any_refl)
+                add_path<R, true>(pe, tb, fc, e);
+            else
+                add_path<R, false>(pe, tb, fc, e);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 int64_t o = ((int64_t)j * 3 + c) * nrx + li;

@@ -26,19 +26,24 @@ constexpr double kRs2 = 0.70710678118654752440;          // 1/sqrt(2)
 
 // Table geometry shared by both precisions (segment counts differ).
 template <typename R> struct TabDims;
+// ROWS: coefficient rows stored per segment (DEG + 1, padded to a power of
+// two for the LDS copy of the FP32 tables so the segment offset is a shift).
 template <> struct TabDims<float> {
     static constexpr int DEG = FT_F32_PT_DEG;
+    static constexpr int ROWS = 8;
     static constexpr int NPT = FT_F32_PT_NSEG, NDS = FT_F32_DS_NSEG, NCL = FT_F32_CL_NSEG;
     static constexpr int NFA = FT_F32_FA_NSEG, NFH = FT_F32_FH_NSEG;
+    static_assert(DEG + 1 <= ROWS, "row padding");
 };
 template <> struct TabDims<double> {
     static constexpr int DEG = FT_F64_PT_DEG;
+    static constexpr int ROWS = FT_F64_PT_DEG + 1;
     static constexpr int NPT = FT_F64_PT_NSEG, NDS = FT_F64_DS_NSEG, NCL = FT_F64_CL_NSEG;
     static constexpr int NFA = FT_F64_FA_NSEG, NFH = FT_F64_FH_NSEG;
 };
 
-// Pointers to the regime tables ([seg][DEG+1][4] = (re_s, im_s, re_h, im_h))
-// and the transition tables ([seg][DEG+1][2] = (re, im)), in LDS (FP32) or
+// Pointers to the regime tables ([seg][ROWS][4] = (re_s, im_s, re_h, im_h))
+// and the transition tables ([seg][ROWS][2] = (re, im)), in LDS (FP32) or
 // global memory (FP64).
 template <typename T> struct Tabs {
     const T* reg;   // PT segments, then DS, then CL
@@ -112,6 +117,8 @@ __device__ __forceinline__ int locate(R x, R lo, R inv_w, int n, R* s) {
 // Written without data-dependent branches: the regime and the transition
 // range only select the segment, the local variable and a few operands, so a
 // wavefront whose lanes sit in different regimes stays converged.
+// LIT = false is the creeping-only specialisation (no lane of the wavefront
+// holds a reflection, so xi >= 0 and K = B_p); LIT = true handles all paths.
 template <typename R> struct FockArgs {
     R xi;    // Fock parameter
     R u;     // sqrt(X), X the transition-function argument
@@ -120,15 +127,14 @@ template <typename R> struct FockArgs {
     R h;     // sqrt(-xi)/2 (deep lit; 0 otherwise)
 };
 
-template <typename R>
+template <typename R, bool LIT = true>
 __device__ __forceinline__ void fock_kernel(const Tabs<typename BaseOf<R>::type>& tb, const FockArgs<R>& A, bool refl,
-                                            bool any_refl, cplx<R>* Ks, cplx<R>* Kh) {
+                                            cplx<R>* Ks, cplx<R>* Kh) {
     using T = typename BaseOf<R>::type;
     using D = TabDims<T>;
     const R e4 = (R)kRs2;                     // e^{-j pi/4} = e4 (1 - j)
     const R c2 = (R)kInv2SqrtPi;
     const R xi = A.xi, u = A.u, q = A.q, ixi = A.ixi;
-    const R X = u * u;
 
     // --- transition function: A(u) for u <= FA_HI, H(1/X) beyond -----------
     bool big = u > (R)FT_FA_HI;
@@ -140,7 +146,7 @@ __device__ __forceinline__ void fock_kernel(const Tabs<typename BaseOf<R>::type>
     R st;
     int tseg = (big ? D::NFA : 0) + locate<R>(targ, (R)0, invw, nseg, &st);
     R v[2];
-    horner2<T, R>(tb.tf + tseg * 2 * (D::DEG + 1), st, v);
+    horner2<T, R>(tb.tf + tseg * 2 * D::ROWS, st, v);
     // small u: G = F/sqrt(X) = 2j A, F = u G; large u: 1 - F = -H/X, G = F/u
     R omr = -iX * v[0], omi = -iX * v[1];
     cplx<R> G, omF;
@@ -150,18 +156,30 @@ __device__ __forceinline__ void fock_kernel(const Tabs<typename BaseOf<R>::type>
     omF.im = big ? omi : -u * G.im;
 
     // --- regime table ------------------------------------------------------
-    int regime = xi >= (R)FT_PT_HI ? 0 : (xi >= (R)FT_PT_LO ? 1 : 2);
-    R r3 = (R)FT_PT_LO * ixi;
-    R arg = regime == 0 ? (xi < (R)FT_DS_HI ? xi : (R)FT_DS_HI) : (regime == 1 ? xi : r3 * r3 * r3);
-    R rlo = regime == 0 ? (R)FT_PT_HI : (regime == 1 ? (R)FT_PT_LO : (R)0);
-    R rinv = regime == 0 ? (R)(D::NDS / (FT_DS_HI - FT_PT_HI))
-                         : (regime == 1 ? (R)(D::NPT / (FT_PT_HI - FT_PT_LO)) : (R)D::NCL);
-    int rn = regime == 0 ? D::NDS : (regime == 1 ? D::NPT : D::NCL);
-    int rbase = regime == 0 ? D::NPT : (regime == 1 ? 0 : D::NPT + D::NDS);
+    // Creeping paths (LIT == false) have xi >= 0: regimes 0 and 1 only.
+    int regime = xi >= (R)FT_PT_HI ? 0 : ((!LIT || xi >= (R)FT_PT_LO) ? 1 : 2);
     R s;
-    int seg = rbase + locate<R>(arg, rlo, rinv, rn, &s);
+    int seg;
+    if (!LIT) {
+        // both regimes read xi itself, clamped to the deep-shadow table's end
+        R arg = xi < (R)FT_DS_HI ? xi : (R)FT_DS_HI;
+        bool r0 = regime == 0;
+        seg = (r0 ? D::NPT : 0) +
+              locate<R>(arg, r0 ? (R)FT_PT_HI : (R)FT_PT_LO,
+                        r0 ? (R)(D::NDS / (FT_DS_HI - FT_PT_HI)) : (R)(D::NPT / (FT_PT_HI - FT_PT_LO)),
+                        r0 ? D::NDS : D::NPT, &s);
+    } else {
+        R r3 = (R)FT_PT_LO * ixi;
+        R arg = regime == 0 ? (xi < (R)FT_DS_HI ? xi : (R)FT_DS_HI) : (regime == 1 ? xi : r3 * r3 * r3);
+        R rlo = regime == 0 ? (R)FT_PT_HI : (regime == 1 ? (R)FT_PT_LO : (R)0);
+        R rinv = regime == 0 ? (R)(D::NDS / (FT_DS_HI - FT_PT_HI))
+                             : (regime == 1 ? (R)(D::NPT / (FT_PT_HI - FT_PT_LO)) : (R)D::NCL);
+        int rn = regime == 0 ? D::NDS : (regime == 1 ? D::NPT : D::NCL);
+        int rbase = regime == 0 ? D::NPT : (regime == 1 ? 0 : D::NPT + D::NDS);
+        seg = rbase + locate<R>(arg, rlo, rinv, rn, &s);
+    }
     R w4[4];
-    horner4<T, R>(tb.reg + seg * 4 * (D::DEG + 1), s, w4);
+    horner4<T, R>(tb.reg + seg * 4 * D::ROWS, s, w4);
     cplx<R> ps{w4[0], w4[1]}, ph{w4[2], w4[3]};
     if (regime == 0 && xi > (R)FT_DS_HI) {
         // past the table only the first creeping mode survives:
@@ -176,17 +194,24 @@ __device__ __forceinline__ void fock_kernel(const Tabs<typename BaseOf<R>::type>
     // --- combine ------------------------------------------------------------
     // CW = e^{-j pi/4} coef W:  regime 1: coef = -sgn q/(2 sqrt pi), W = G
     //                          regimes 0, 2: coef = 1/(2 sqrt(pi) xi), W = 1 - F
+    cplx<R> W = regime == 1 ? G : omF;
+    if (!LIT) {
+        // sgn(xi) = +1 for creeping paths (xi >= 0); K = P + CW
+        R f = (regime == 1 ? -q * c2 : c2 * ixi) * e4;
+        cplx<R> CW{f * (W.re + W.im), f * (W.im - W.re)};
+        *Ks = cplx<R>{ps.re + CW.re, ps.im + CW.im};
+        *Kh = cplx<R>{ph.re + CW.re, ph.im + CW.im};
+        return;
+    }
     R sg = refl ? (xi > (R)0 ? (R)1 : (R)-1) : (xi < (R)0 ? (R)-1 : (R)1);
     R coef = regime == 1 ? -sg * q * c2 : c2 * ixi;
-    cplx<R> W = regime == 1 ? G : omF;
     R f = coef * e4;
     cplx<R> CW{f * (W.re + W.im), f * (W.im - W.re)};
     // creeping: K = P + CW
     // reflection / deep lit: K = -(alpha P + e CW), e = e^{-j xi^3/12},
     //   alpha = e (regimes 0, 1) or sqrt(-xi)/2 (regime 2, P = c)
     bool lit = refl || regime == 2;
-    cplx<R> e{(R)1, (R)0};
-    if (any_refl) e = expmj<R>(xi * xi * xi * (R)(1.0 / 12));
+    cplx<R> e = expmj<R>(xi * xi * xi * (R)(1.0 / 12));
     cplx<R> alpha = regime == 2 ? cplx<R>{A.h, (R)0} : e;
     cplx<R> eCW = cmul(e, CW);
     cplx<R> as = cmul(alpha, ps), ah = cmul(alpha, ph);

@@ -31,14 +31,15 @@ namespace utd {
 //   xi = k^{1/3} xh,  sqrt(X) = k^{1/2} uh,  q = k^{1/6} qhat,
 //   1/xi = k^{-1/3} ixh,  sqrt(-xi) = k^{1/6} sxh,
 // and the contribution is
-//   e^{-j 2pi rev} k^{-1/6} (a_s K_s v_s + a_h K_h v_h),  rev = (f/c) s_tot - nc/4.
+//   e^{-j 2pi rev} k^{-1/6} (K_s v_s + K_h v_h),  rev = (f/c) s_tot - nc/4,
+// where v_s, v_h are the output polarisation vectors at R scaled by the
+// incident projection, the spreading and the constant prefactor.
 template <typename R, typename G = double> struct PathEvalT {
     G s_tot;          // total path length s^i + t + s^d (or s^i + s^r)
     int nc;           // caustics passed (each +pi/2)
     int refl;
     R xh, uh, qhat, ixh, sxh;
-    R a_s, a_h;       // incident projections x spreading x prefactor
-    R vs[3], vh[3];   // output polarisation vectors at R
+    R vs[3], vh[3];   // amplitude-weighted polarisation vectors
 };
 template <typename R> using PathEval = PathEvalT<R, double>;
 
@@ -265,12 +266,12 @@ __device__ __forceinline__ bool sphere_creep(const BodyPrepT<G>& b, const RxGeoT
         R Smod = RT<R>::sqrt_(aR * sgR / (sDR * (R)g.wn));
         R A = (R)L.amp * Smod / sIR * ((R)-1.4142135623730951 * mhat);
         set_fock_consts<R, G>(pe, mhat, (R)phi, Ld);
-        pe->a_s = A * (px * bx + py * by + pz * bz);
-        pe->a_h = A * (px * n1x + py * n1y + pz * n1z);
-        pe->vs[0] = bx; pe->vs[1] = by; pe->vs[2] = bz;
-        pe->vh[0] = c2R * eTx + s2R * epx;
-        pe->vh[1] = c2R * eTy + s2R * epy;
-        pe->vh[2] = c2R * eTz + s2R * epz;
+        R as = A * (px * bx + py * by + pz * bz);
+        R ah = A * (px * n1x + py * n1y + pz * n1z);
+        pe->vs[0] = as * bx; pe->vs[1] = as * by; pe->vs[2] = as * bz;
+        pe->vh[0] = ah * (c2R * eTx + s2R * epx);
+        pe->vh[1] = ah * (c2R * eTy + s2R * epy);
+        pe->vh[2] = ah * (c2R * eTz + s2R * epz);
         pe->refl = 0;
     }
     return true;
@@ -323,10 +324,10 @@ __device__ __forceinline__ bool cyl_creep(const BodyPrepT<G>& b, const RxGeoT<G>
         R px = (R)L.p[0], py = (R)L.p[1], pz = (R)L.p[2];
         R A = (R)L.amp * Smod / sI * ((R)-1.4142135623730951 * mhat);
         set_fock_consts<R, G>(pe, mhat, (R)phi * cosd, Ld);
-        pe->a_s = A * (px * b1x + py * b1y + pz * b1z);
-        pe->a_h = A * (px * c1R + py * s1R);
-        pe->vs[0] = b2x; pe->vs[1] = b2y; pe->vs[2] = b2z;
-        pe->vh[0] = c2R; pe->vh[1] = s2R; pe->vh[2] = (R)0;
+        R as = A * (px * b1x + py * b1y + pz * b1z);
+        R ah = A * (px * c1R + py * s1R);
+        pe->vs[0] = as * b2x; pe->vs[1] = as * b2y; pe->vs[2] = as * b2z;
+        pe->vh[0] = ah * c2R; pe->vh[1] = ah * s2R; pe->vh[2] = (R)0;
         pe->refl = 0;
     }
     return true;
@@ -504,10 +505,10 @@ __device__ __forceinline__ void refl_eval(const BodyPrepT<G>& b, V3<G> Q, V3<G> 
     R px = (R)L.p[0], py = (R)L.p[1], pz = (R)L.p[2];
     R A = (R)L.amp * isI * P0;
     set_fock_consts<R, G>(pe, mhat, (R)-2 * ci, Lr);
-    pe->a_s = A * (px * cx + py * cy + pz * cz);
-    pe->a_h = A * (px * pix + py * piy + pz * piz);
-    pe->vs[0] = cx; pe->vs[1] = cy; pe->vs[2] = cz;
-    pe->vh[0] = prx; pe->vh[1] = pry; pe->vh[2] = prz;
+    R as = A * (px * cx + py * cy + pz * cz);
+    R ah = A * (px * pix + py * piy + pz * piz);
+    pe->vs[0] = as * cx; pe->vs[1] = as * cy; pe->vs[2] = as * cz;
+    pe->vh[0] = ah * prx; pe->vh[1] = ah * pry; pe->vh[2] = ah * prz;
     pe->refl = 1;
 }
 

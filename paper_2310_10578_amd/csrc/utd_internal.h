@@ -18,11 +18,11 @@ struct BatchParams {
     int64_t n_rx;            // receivers in the array (bound for rx_off)
     int tile;                // receivers per work item (= blockDim.x)
 };
-hipError_t launch_prep(const LaunchParams& L, const float* sph, const float* cyl, const double* freqs,
-                       BodyPrep* prep, FreqConst* fc, hipStream_t s);
+// Visibility pass; also stores the body constants (prep) and, when freqs is
+// not NULL, the frequency constants (fcs) for the later kernels of the call.
 hipError_t launch_paths(const LaunchParams& L, int precision, const float* rx, const float* sph, const float* cyl,
-                        const BodyPrep* prep, const float4* nodes, const float4* tris, uint8_t* mask, void* rec,
-                        uint8_t* flags, hipStream_t s);
+                        const double* freqs, BodyPrep* prep, FreqConst* fcs, const float4* nodes, const float4* tris,
+                        uint8_t* mask, void* rec, uint8_t* flags, hipStream_t s);
 size_t path_record_bytes(int precision);
 hipError_t launch_field(const LaunchParams& L, int precision, int fc, const float* rx, const FreqConst* fcs,
                         const uint8_t* mask, const void* rec, uint8_t* flags, void* E, hipStream_t s);

@@ -1,9 +1,9 @@
 // HIP kernels of the smooth-surface UTD field evaluation (gfx950).
 //
-//   k_prep     per body, source-dependent constants (FP64)
 //   k_paths    per (receiver, body) path validity + visibility bits (the U of
 //              Eqs. (1)-(2)) and the frequency-independent constants of every
-//              valid path; per receiver inside / line-of-sight flags
+//              valid path; per receiver inside / line-of-sight flags; it also
+//              stores the body and frequency constants used later
 //   k_field    per (receiver, frequency chunk) coherent field of Eqs. (1)-(4)
 //
 // In k_field one lane owns one receiver and a chunk of FC frequencies; it
@@ -20,24 +20,29 @@
 namespace utd {
 
 // ---------------------------------------------------------------------------
-// body constants
+// frequency constants
 // ---------------------------------------------------------------------------
-__global__ void k_prep(LaunchParams L, const float* __restrict__ sph, const float* __restrict__ cyl,
-                       const double* __restrict__ freqs, BodyPrep* __restrict__ out, FreqConst* __restrict__ fc) {
-    int nb = L.n_sph + L.n_cyl;
-    int tid = blockIdx.x * blockDim.x + threadIdx.x, nt = gridDim.x * blockDim.x;
-    for (int b = tid; b < nb; b += nt) out[b] = body_prep(L.T, sph, L.n_sph, cyl, b);
-    if (freqs)
-        for (int f = tid; f < L.n_f; f += nt) {
-            double k = kTwoPi * freqs[f] / kC0;
-            double k13 = cbrt(k), k16 = sqrt(k13);
-            FreqConst c;
-            c.rev_per_m = freqs[f] / kC0;
-            c.kd = k; c.k13d = k13; c.k16d = k16; c.km16d = 1.0 / k16; c.skd = sqrt(k); c.ik13d = 1.0 / k13;
-            c.kf = (float)k; c.k13f = (float)k13; c.k16f = (float)k16; c.km16f = (float)(1.0 / k16);
-            c.skf = (float)sqrt(k); c.ik13f = (float)(1.0 / k13);
-            fc[f] = c;
-        }
+__device__ __forceinline__ FreqConst freq_const(double f) {
+    double k = kTwoPi * f / kC0;
+    double k13 = cbrt(k), k16 = sqrt(k13);
+    FreqConst c;
+    c.rev_per_m = f / kC0;
+    c.kd = k; c.k13d = k13; c.k16d = k16; c.km16d = 1.0 / k16; c.skd = sqrt(k); c.ik13d = 1.0 / k13;
+    c.kf = (float)k; c.k13f = (float)k13; c.k16f = (float)k16; c.km16f = (float)(1.0 / k16);
+    c.skf = (float)sqrt(k); c.ik13f = (float)(1.0 / k13);
+    return c;
+}
+
+// Receiver (or source) inside the solid body b.
+__device__ __forceinline__ bool inside_raw(const LaunchParams& L, const float* sph, const float* cyl, int b, d3 P) {
+    if (b < L.n_sph) {
+        const float* s = sph + 4 * b;
+        double x = P.x - s[0], y = P.y - s[1], z = P.z - s[2];
+        return x * x + y * y + z * z <= (double)s[3] * s[3];
+    }
+    const float* c = cyl + 5 * (b - L.n_sph);
+    double x = P.x - c[0], y = P.y - c[1];
+    return x * x + y * y <= (double)c[4] * c[4] && P.z >= c[2] && P.z <= (double)c[2] + c[3];
 }
 
 // ---------------------------------------------------------------------------
@@ -71,14 +76,14 @@ template <> struct PathRec<float> {          // 64 bytes
     int16_t nc;                               // caustic quarter turns
     int16_t refl;
     float xh, uh, qhat;                       // see PathEval
-    float4 q0;                                // (ixh, sxh, a_s, a_h)
-    float4 q1;                                // (vs0, vs1, vs2, vh0)
-    float2 q2;                                // (vh1, vh2)
+    float4 q0;                                // (ixh, sxh, vs0, vs1)
+    float4 q1;                                // (vs2, vh0, vh1, vh2)
+    float2 pad;
 };
-template <> struct PathRec<double> {         // 136 bytes
+template <> struct PathRec<double> {         // 120 bytes
     double s_tot;
     int32_t nc, refl;
-    double v[15];
+    double v[13];
 };
 
 __device__ __forceinline__ void pack(const PathEval<float>& p, PathRec<float>* r) {
@@ -87,9 +92,9 @@ __device__ __forceinline__ void pack(const PathEval<float>& p, PathRec<float>* r
     o.nc = (int16_t)p.nc;
     o.refl = (int16_t)p.refl;
     o.xh = p.xh; o.uh = p.uh; o.qhat = p.qhat;
-    o.q0 = make_float4(p.ixh, p.sxh, p.a_s, p.a_h);
-    o.q1 = make_float4(p.vs[0], p.vs[1], p.vs[2], p.vh[0]);
-    o.q2 = make_float2(p.vh[1], p.vh[2]);
+    o.q0 = make_float4(p.ixh, p.sxh, p.vs[0], p.vs[1]);
+    o.q1 = make_float4(p.vs[2], p.vh[0], p.vh[1], p.vh[2]);
+    o.pad = make_float2(0.0f, 0.0f);
     *r = o;
 }
 __device__ __forceinline__ void unpack(const PathRec<float>& o, PathEval<float>* p) {
@@ -97,39 +102,43 @@ __device__ __forceinline__ void unpack(const PathRec<float>& o, PathEval<float>*
     p->nc = o.nc;
     p->refl = o.refl;
     p->xh = o.xh; p->uh = o.uh; p->qhat = o.qhat;
-    p->ixh = o.q0.x; p->sxh = o.q0.y; p->a_s = o.q0.z; p->a_h = o.q0.w;
-    p->vs[0] = o.q1.x; p->vs[1] = o.q1.y; p->vs[2] = o.q1.z; p->vh[0] = o.q1.w;
-    p->vh[1] = o.q2.x; p->vh[2] = o.q2.y;
+    p->ixh = o.q0.x; p->sxh = o.q0.y; p->vs[0] = o.q0.z; p->vs[1] = o.q0.w;
+    p->vs[2] = o.q1.x; p->vh[0] = o.q1.y; p->vh[1] = o.q1.z; p->vh[2] = o.q1.w;
 }
 __device__ __forceinline__ void pack(const PathEval<double>& p, PathRec<double>* r) {
     PathRec<double> o;
     o.s_tot = p.s_tot; o.nc = p.nc; o.refl = p.refl;
-    double v[15] = {p.xh, p.uh, p.qhat, p.ixh, p.sxh, p.a_s, p.a_h, p.vs[0], p.vs[1], p.vs[2],
-                    p.vh[0], p.vh[1], p.vh[2], 0.0, 0.0};
-    for (int k = 0; k < 15; ++k) o.v[k] = v[k];
+    double v[13] = {p.xh, p.uh, p.qhat, p.ixh, p.sxh, p.vs[0], p.vs[1], p.vs[2], p.vh[0], p.vh[1], p.vh[2],
+                    0.0, 0.0};
+    for (int k = 0; k < 13; ++k) o.v[k] = v[k];
     *r = o;
 }
 __device__ __forceinline__ void unpack(const PathRec<double>& o, PathEval<double>* p) {
     p->s_tot = o.s_tot; p->nc = o.nc; p->refl = o.refl;
     p->xh = o.v[0]; p->uh = o.v[1]; p->qhat = o.v[2]; p->ixh = o.v[3]; p->sxh = o.v[4];
-    p->a_s = o.v[5]; p->a_h = o.v[6];
-    p->vs[0] = o.v[7]; p->vs[1] = o.v[8]; p->vs[2] = o.v[9];
-    p->vh[0] = o.v[10]; p->vh[1] = o.v[11]; p->vh[2] = o.v[12];
+    p->vs[0] = o.v[5]; p->vs[1] = o.v[6]; p->vs[2] = o.v[7];
+    p->vh[0] = o.v[8]; p->vh[1] = o.v[9]; p->vh[2] = o.v[10];
 }
 
 // Visibility and path constants.  grid: x over receivers (blockDim 256),
 // y over slot = 0 (receiver flags) or 1 + body.  mask[body][rx] gets the path
 // bits, flags[rx] the slot-0 bits, rec the constants of each valid path in
 // set-bit order.
+// The body constants of slot b are computed by every block of the slot (a
+// few FP64 operations); the x = 0 block also stores them, and the (0, 0)
+// block the frequency constants, for the later kernels of the call.
 template <typename R>
 __global__ void __launch_bounds__(256) k_paths(LaunchParams L, const float* __restrict__ rx,
                                                const float* __restrict__ sph, const float* __restrict__ cyl,
-                                               const BodyPrep* __restrict__ prep, const float4* __restrict__ nodes,
+                                               const double* __restrict__ freqs, BodyPrep* __restrict__ prep,
+                                               FreqConst* __restrict__ fcs, const float4* __restrict__ nodes,
                                                const float4* __restrict__ tris, uint8_t* __restrict__ mask,
                                                PathRec<R>* __restrict__ rec, uint8_t* __restrict__ flags) {
     __shared__ int stack[kStackDepth * 256];
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int slot = blockIdx.y;
+    if (slot == 0 && blockIdx.x == 0 && freqs)
+        for (int f = threadIdx.x; f < L.n_f; f += blockDim.x) fcs[f] = freq_const(freqs[f]);
     if (i >= L.n_rx) return;
     int* stk = stack + threadIdx.x;
     const int stride = 256;
@@ -140,8 +149,8 @@ __global__ void __launch_bounds__(256) k_paths(LaunchParams L, const float* __re
         uint8_t f = 0;
         bool inside = false, tx_inside = false;
         for (int b = 0; b < nb; ++b) {
-            inside |= inside_body(prep[b], R3);
-            tx_inside |= inside_body(prep[b], T);
+            inside |= inside_raw(L, sph, cyl, b, R3);
+            tx_inside |= inside_raw(L, sph, cyl, b, T);
         }
         if (tx_inside) f |= kFlagTxInside;
         if (inside) f |= kFlagInside;
@@ -151,7 +160,8 @@ __global__ void __launch_bounds__(256) k_paths(LaunchParams L, const float* __re
         return;
     }
     int b = slot - 1;
-    const BodyPrep P = prep[b];
+    const BodyPrep P = body_prep(L.T, sph, L.n_sph, cyl, b);
+    if (blockIdx.x == 0 && threadIdx.x == 0) prep[b] = P;
     RxGeo g = rx_geo(P, R3);
     uint8_t m = 0;
     int nrec = 0;
@@ -216,12 +226,11 @@ template <> struct FreqC<double> {
 
 // One path at one frequency: the Fock arguments scale with powers of k
 // (xi ~ k^{1/3}, sqrt(X) ~ k^{1/2}, q ~ k^{1/6}), so they are products of the
-// path's constants and the frequency's.  any_refl tells whether any lane of
-// the wavefront holds a reflection (the e^{-j xi^3/12} factor is skipped
-// otherwise).
-template <typename R>
-__device__ __forceinline__ void add_path(const PathEval<R>& pe, const Tabs<R>& tb, const FreqC<R>& fc,
-                                         bool any_refl, R* E) {
+// path's constants and the frequency's.  LIT selects the general Fock
+// combine (some lane of the wavefront holds a reflection) or the creeping-only
+// one (xi >= 0, no e^{-j xi^3/12}); callers branch on a wave-uniform flag.
+template <typename R, bool LIT>
+__device__ __forceinline__ void add_path(const PathEval<R>& pe, const Tabs<R>& tb, const FreqC<R>& fc, R* E) {
     FockArgs<R> a;
     a.xi = fc.k13 * pe.xh;
     a.u = fc.sk * pe.uh;
@@ -229,40 +238,42 @@ __device__ __forceinline__ void add_path(const PathEval<R>& pe, const Tabs<R>& t
     a.ixi = fc.ik13 * pe.ixh;
     a.h = (R)0.5 * fc.k16 * pe.sxh;
     cplx<R> Ks, Kh;
-    fock_kernel<R>(tb, a, pe.refl != 0, any_refl, &Ks, &Kh);
+    fock_kernel<R, LIT>(tb, a, pe.refl != 0, &Ks, &Kh);
     cplx<R> ph = phase_rev<R>(fc.rev_per_m * pe.s_tot - 0.25 * pe.nc);
-    R as = pe.a_s * fc.km16, ah = pe.a_h * fc.km16;
+    ph.re *= fc.km16;
+    ph.im *= fc.km16;
     cplx<R> cs = cmul(Ks, ph), ch = cmul(Kh, ph);
-    cs.re *= as; cs.im *= as;
-    ch.re *= ah; ch.im *= ah;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        E[2 * c] += cs.re * pe.vs[c] + ch.re * pe.vh[c];
-        E[2 * c + 1] += cs.im * pe.vs[c] + ch.im * pe.vh[c];
+        E[2 * c] = fma(cs.re, pe.vs[c], E[2 * c]);
+        E[2 * c] = fma(ch.re, pe.vh[c], E[2 * c]);
+        E[2 * c + 1] = fma(cs.im, pe.vs[c], E[2 * c + 1]);
+        E[2 * c + 1] = fma(ch.im, pe.vh[c], E[2 * c + 1]);
     }
 }
 
 template <typename R> struct TableStage;
 
 template <> struct TableStage<float> {
-    static constexpr int NREG = (FT_F32_PT_NSEG + FT_F32_DS_NSEG + FT_F32_CL_NSEG) * (FT_F32_PT_DEG + 1) * 4;
-    static constexpr int NTF = (FT_F32_FA_NSEG + FT_F32_FH_NSEG) * (FT_F32_PT_DEG + 1) * 2;
+    using D = TabDims<float>;
+    static constexpr int ROWS = D::ROWS, DEG = D::DEG;
+    static constexpr int NREG = (D::NPT + D::NDS + D::NCL) * ROWS * 4;
+    static constexpr int NTF = (D::NFA + D::NFH) * ROWS * 2;
+    // copy [seg][DEG + 1][W] into [seg][ROWS][W] (padding rows never read)
+    template <int W>
+    static __device__ __forceinline__ void copy(float* dst, const float* src, int nseg) {
+        const int n = nseg * (DEG + 1) * W;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            int sg = i / ((DEG + 1) * W), r = i - sg * (DEG + 1) * W;
+            dst[sg * ROWS * W + r] = src[i];
+        }
+    }
     static __device__ __forceinline__ Tabs<float> stage(float* reg, float* tf) {
-        const float* a = &ft_f32_pt[0][0][0];
-        const float* b = &ft_f32_ds[0][0][0];
-        const float* c = &ft_f32_cl[0][0][0];
-        constexpr int na = FT_F32_PT_NSEG * (FT_F32_PT_DEG + 1) * 4;
-        constexpr int nb = FT_F32_DS_NSEG * (FT_F32_PT_DEG + 1) * 4;
-        constexpr int nc = FT_F32_CL_NSEG * (FT_F32_PT_DEG + 1) * 4;
-        for (int i = threadIdx.x; i < na; i += blockDim.x) reg[i] = a[i];
-        for (int i = threadIdx.x; i < nb; i += blockDim.x) reg[na + i] = b[i];
-        for (int i = threadIdx.x; i < nc; i += blockDim.x) reg[na + nb + i] = c[i];
-        const float* d = &ft_f32_fa[0][0][0];
-        const float* e = &ft_f32_fh[0][0][0];
-        constexpr int nd = FT_F32_FA_NSEG * (FT_F32_PT_DEG + 1) * 2;
-        constexpr int ne = FT_F32_FH_NSEG * (FT_F32_PT_DEG + 1) * 2;
-        for (int i = threadIdx.x; i < nd; i += blockDim.x) tf[i] = d[i];
-        for (int i = threadIdx.x; i < ne; i += blockDim.x) tf[nd + i] = e[i];
+        copy<4>(reg, &ft_f32_pt[0][0][0], D::NPT);
+        copy<4>(reg + D::NPT * ROWS * 4, &ft_f32_ds[0][0][0], D::NDS);
+        copy<4>(reg + (D::NPT + D::NDS) * ROWS * 4, &ft_f32_cl[0][0][0], D::NCL);
+        copy<2>(tf, &ft_f32_fa[0][0][0], D::NFA);
+        copy<2>(tf + D::NFA * ROWS * 2, &ft_f32_fh[0][0][0], D::NFH);
         __syncthreads();
         return Tabs<float>{reg, tf};
     }
@@ -348,12 +359,21 @@ __global__ void __launch_bounds__(256) k_field(LaunchParams L, const float* __re
             for (int k = 0; k < n; ++k) {
                 PathEval<R> pe;
                 unpack(rec[((int64_t)b * S + k) * L.n_rx + i], &pe);
-                bool any_refl = __any(pe.refl != 0);
+                if (__any(pe.refl != 0)) {
 #pragma unroll
-                for (int j = 0; j < FC; ++j) {
-                    if (j < nfc) {
-                        FreqC<R> fc(fcs[f0 + j]);
-                        add_path<R>(pe, tb, fc, any_refl, E[j]);
+                    for (int j = 0; j < FC; ++j) {
+                        if (j < nfc) {
+                            FreqC<R> fc(fcs[f0 + j]);
+                            add_path<R, true>(pe, tb, fc, E[j]);
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < FC; ++j) {
+                        if (j < nfc) {
+                            FreqC<R> fc(fcs[f0 + j]);
+                            add_path<R, false>(pe, tb, fc, E[j]);
+                        }
                     }
                 }
             }
@@ -413,31 +433,23 @@ hipError_t launch_census(int64_t n_mask, const uint8_t* mask, int64_t n_rx, cons
     return hipGetLastError();
 }
 
-hipError_t launch_prep(const LaunchParams& L, const float* sph, const float* cyl, const double* freqs,
-                       BodyPrep* prep, FreqConst* fc, hipStream_t s) {
-    int nb = L.n_sph + L.n_cyl;
-    int n = nb > L.n_f ? nb : L.n_f;
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_prep, dim3((n + 63) / 64), dim3(64), 0, s, L, sph, cyl, freqs, prep, fc);
-    return hipGetLastError();
-}
-
 template <typename R>
 static hipError_t launch_paths_t(const LaunchParams& L, const float* rx, const float* sph, const float* cyl,
-                                 const BodyPrep* prep, const float4* nodes, const float4* tris, uint8_t* mask,
-                                 void* rec, uint8_t* flags, hipStream_t s) {
+                                 const double* freqs, BodyPrep* prep, FreqConst* fcs, const float4* nodes,
+                                 const float4* tris, uint8_t* mask, void* rec, uint8_t* flags, hipStream_t s) {
     int nb = L.n_sph + L.n_cyl;
     dim3 grid((unsigned)((L.n_rx + 255) / 256), (unsigned)(nb + 1));
-    hipLaunchKernelGGL((k_paths<R>), grid, dim3(256), 0, s, L, rx, sph, cyl, prep, nodes, tris, mask,
+    hipLaunchKernelGGL((k_paths<R>), grid, dim3(256), 0, s, L, rx, sph, cyl, freqs, prep, fcs, nodes, tris, mask,
                        (PathRec<R>*)rec, flags);
     return hipGetLastError();
 }
 
 hipError_t launch_paths(const LaunchParams& L, int precision, const float* rx, const float* sph, const float* cyl,
-                        const BodyPrep* prep, const float4* nodes, const float4* tris, uint8_t* mask, void* rec,
-                        uint8_t* flags, hipStream_t s) {
-    return precision == 0 ? launch_paths_t<float>(L, rx, sph, cyl, prep, nodes, tris, mask, rec, flags, s)
-                          : launch_paths_t<double>(L, rx, sph, cyl, prep, nodes, tris, mask, rec, flags, s);
+                        const double* freqs, BodyPrep* prep, FreqConst* fcs, const float4* nodes, const float4* tris,
+                        uint8_t* mask, void* rec, uint8_t* flags, hipStream_t s) {
+    return precision == 0
+               ? launch_paths_t<float>(L, rx, sph, cyl, freqs, prep, fcs, nodes, tris, mask, rec, flags, s)
+               : launch_paths_t<double>(L, rx, sph, cyl, freqs, prep, fcs, nodes, tris, mask, rec, flags, s);
 }
 
 size_t path_record_bytes(int precision) { return precision == 0 ? sizeof(PathRec<float>) : sizeof(PathRec<double>); }
