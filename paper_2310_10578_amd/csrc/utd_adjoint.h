@@ -71,7 +71,7 @@ __device__ __forceinline__ void record_adjoint(const PathEval<R>& pe, const Tabs
             a.ixi = D(ixi, dir == 0 ? dixi : (R)0);
             a.h = D(h, dir == 0 ? dh : (R)0);
             cplx<D> ks, kh;
-            fock_kernel<D, true>(tb, a, refl, &ks, &kh);
+            fock_kernel<D, kAny>(tb, a, refl, &ks, &kh);
             if (dir == 0) {
                 Ks = cplx<R>{ks.re.v, ks.im.v};
                 Kh = cplx<R>{kh.re.v, kh.im.v};
@@ -187,14 +187,17 @@ __device__ __forceinline__ void body_adjoint(const LaunchParams& L, d3 R3, int b
     const int ndir = is_sph ? 7 : 6;
     d3 T0 = mk(L.T[0], L.T[1], L.T[2]);
     V3<GD> Rg{GD(R3.x), GD(R3.y), GD(R3.z)};
+    // records: creeping paths in slots 0, 1, ... (bit order), reflection in S - 1
+    const bool has_refl = (m >> kBitRefl) & 1u;
+    const int ncap = has_refl ? S - 1 : S;
     int k = 0;
     for (int bit = 0; bit <= kBitRefl; ++bit) {
         if (!((m >> bit) & 1u)) continue;
         if (bit < kBitRefl && bit >= 2 * (L.l_enc + 1)) continue;
-        if (k >= S) break;
+        if (bit < kBitRefl && k >= ncap) continue;
+        const int slot = bit == kBitRefl ? S - 1 : k++;
         PathEval<R> pe;
-        unpack(rec[((int64_t)b * S + k) * L.n_rx + i], &pe);
-        ++k;
+        unpack(rec[((int64_t)b * S + slot) * L.n_rx + i], &pe);
         RecAdj<R> lam;
         record_adjoint<R>(pe, tb, fcs, L.n_f, gE, L.n_rx, i, &lam);
         const bool refl = bit == kBitRefl;

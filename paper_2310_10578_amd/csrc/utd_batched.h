@@ -146,7 +146,9 @@ __device__ __forceinline__ void eval_listed(const LaunchParams& L, d3 R3, d3 T, 
             const int ell = bit >> 1, sgn = (bit & 1) ? -1 : 1;
             cyl_creep<R, double>(P, g, R3, T, L, sgn, ell, &pe, nullptr);
         }
-        const bool any_refl = __any(pe.refl != 0);
+        // wave-uniform choice of the Fock specialisation
+        const bool any_refl = __any(pe.refl != 0), any_creep = __any(pe.refl == 0);
+        const int mode = !any_refl ? kCreep : (!any_creep ? kRefl : kAny);
 #pragma unroll 1
         for (int j = 0; j < L.n_f; ++j) {
             R e[6];
@@ -157,10 +159,12 @@ __device__ __forceinline__ void eval_listed(const LaunchParams& L, d3 R3, d3 T, 
                 e[2 * c + 1] = E[2 * o + 1];
             }
             FreqC<R> fc(fcs[j]);
-            if (any_refl)
-                add_path<R, true>(pe, tb, fc, e);
+            if (mode == kCreep)
+                add_path<R, kCreep>(pe, tb, fc, e);
+            else if (mode == kRefl)
+                add_path<R, kRefl>(pe, tb, fc, e);
             else
-                add_path<R, false>(pe, tb, fc, e);
+                add_path<R, kAny>(pe, tb, fc, e);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 int64_t o = ((int64_t)j * 3 + c) * nrx + li;

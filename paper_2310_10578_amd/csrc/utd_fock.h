@@ -117,8 +117,10 @@ __device__ __forceinline__ int locate(R x, R lo, R inv_w, int n, R* s) {
 // Written without data-dependent branches: the regime and the transition
 // range only select the segment, the local variable and a few operands, so a
 // wavefront whose lanes sit in different regimes stays converged.
-// LIT = false is the creeping-only specialisation (no lane of the wavefront
-// holds a reflection, so xi >= 0 and K = B_p); LIT = true handles all paths.
+// MODE selects a specialisation for wavefronts whose lanes all hold the same
+// kind of path: kCreep (creeping paths: xi >= 0, regimes 0/1, K = B_p), kRefl
+// (reflections: xi <= 0, regimes 1/2, K = Rbar_p) or kAny (mixed lanes).
+enum { kAny = 0, kCreep = 1, kRefl = 2 };
 template <typename R> struct FockArgs {
     R xi;    // Fock parameter
     R u;     // sqrt(X), X the transition-function argument
@@ -127,7 +129,7 @@ template <typename R> struct FockArgs {
     R h;     // sqrt(-xi)/2 (deep lit; 0 otherwise)
 };
 
-template <typename R, bool LIT = true>
+template <typename R, int MODE = kAny>
 __device__ __forceinline__ void fock_kernel(const Tabs<typename BaseOf<R>::type>& tb, const FockArgs<R>& A, bool refl,
                                             cplx<R>* Ks, cplx<R>* Kh) {
     using T = typename BaseOf<R>::type;
@@ -156,11 +158,11 @@ __device__ __forceinline__ void fock_kernel(const Tabs<typename BaseOf<R>::type>
     omF.im = big ? omi : -u * G.im;
 
     // --- regime table ------------------------------------------------------
-    // Creeping paths (LIT == false) have xi >= 0: regimes 0 and 1 only.
-    int regime = xi >= (R)FT_PT_HI ? 0 : ((!LIT || xi >= (R)FT_PT_LO) ? 1 : 2);
+    // creeping paths have xi >= 0 (regimes 0, 1), reflections xi <= 0 (1, 2)
+    int regime = (MODE != kRefl && xi >= (R)FT_PT_HI) ? 0 : ((MODE == kCreep || xi >= (R)FT_PT_LO) ? 1 : 2);
     R s;
     int seg;
-    if (!LIT) {
+    if (MODE == kCreep) {
         // both regimes read xi itself, clamped to the deep-shadow table's end
         R arg = xi < (R)FT_DS_HI ? xi : (R)FT_DS_HI;
         bool r0 = regime == 0;
@@ -168,6 +170,12 @@ __device__ __forceinline__ void fock_kernel(const Tabs<typename BaseOf<R>::type>
               locate<R>(arg, r0 ? (R)FT_PT_HI : (R)FT_PT_LO,
                         r0 ? (R)(D::NDS / (FT_DS_HI - FT_PT_HI)) : (R)(D::NPT / (FT_PT_HI - FT_PT_LO)),
                         r0 ? D::NDS : D::NPT, &s);
+    } else if (MODE == kRefl) {
+        R r3 = (R)FT_PT_LO * ixi;
+        bool r1 = regime == 1;
+        seg = (r1 ? 0 : D::NPT + D::NDS) +
+              locate<R>(r1 ? xi : r3 * r3 * r3, r1 ? (R)FT_PT_LO : (R)0,
+                        r1 ? (R)(D::NPT / (FT_PT_HI - FT_PT_LO)) : (R)D::NCL, r1 ? D::NPT : D::NCL, &s);
     } else {
         R r3 = (R)FT_PT_LO * ixi;
         R arg = regime == 0 ? (xi < (R)FT_DS_HI ? xi : (R)FT_DS_HI) : (regime == 1 ? xi : r3 * r3 * r3);
@@ -181,7 +189,7 @@ __device__ __forceinline__ void fock_kernel(const Tabs<typename BaseOf<R>::type>
     R w4[4];
     horner4<T, R>(tb.reg + seg * 4 * D::ROWS, s, w4);
     cplx<R> ps{w4[0], w4[1]}, ph{w4[2], w4[3]};
-    if (regime == 0 && xi > (R)FT_DS_HI) {
+    if (MODE != kRefl && regime == 0 && xi > (R)FT_DS_HI) {
         // past the table only the first creeping mode survives:
         // scale the end value by e^{z1 (xi - DS_HI)} (rare)
         R dx = xi - (R)FT_DS_HI;
@@ -195,12 +203,27 @@ __device__ __forceinline__ void fock_kernel(const Tabs<typename BaseOf<R>::type>
     // CW = e^{-j pi/4} coef W:  regime 1: coef = -sgn q/(2 sqrt pi), W = G
     //                          regimes 0, 2: coef = 1/(2 sqrt(pi) xi), W = 1 - F
     cplx<R> W = regime == 1 ? G : omF;
-    if (!LIT) {
+    if (MODE == kCreep) {
         // sgn(xi) = +1 for creeping paths (xi >= 0); K = P + CW
         R f = (regime == 1 ? -q * c2 : c2 * ixi) * e4;
         cplx<R> CW{f * (W.re + W.im), f * (W.im - W.re)};
         *Ks = cplx<R>{ps.re + CW.re, ps.im + CW.im};
         *Kh = cplx<R>{ph.re + CW.re, ph.im + CW.im};
+        return;
+    }
+    cplx<R> e = expmj<R>(xi * xi * xi * (R)(1.0 / 12));
+    if (MODE == kRefl) {
+        // sgn = -1 on the lit side (xi <= 0): coef = q/(2 sqrt pi) in regime 1;
+        // K = -(alpha P + e CW), alpha = e (regime 1) or sqrt(-xi)/2 (regime 2)
+        R f = (regime == 1 ? q * c2 : c2 * ixi) * e4;
+        cplx<R> CW{f * (W.re + W.im), f * (W.im - W.re)};
+        cplx<R> eCW = cmul(e, CW);
+        bool r2 = regime == 2;
+        cplx<R> as = cmul(e, ps), ah = cmul(e, ph);
+        Ks->re = -((r2 ? A.h * ps.re : as.re) + eCW.re);
+        Ks->im = -((r2 ? A.h * ps.im : as.im) + eCW.im);
+        Kh->re = -((r2 ? A.h * ph.re : ah.re) + eCW.re);
+        Kh->im = -((r2 ? A.h * ph.im : ah.im) + eCW.im);
         return;
     }
     R sg = refl ? (xi > (R)0 ? (R)1 : (R)-1) : (xi < (R)0 ? (R)-1 : (R)1);
@@ -211,7 +234,6 @@ __device__ __forceinline__ void fock_kernel(const Tabs<typename BaseOf<R>::type>
     // reflection / deep lit: K = -(alpha P + e CW), e = e^{-j xi^3/12},
     //   alpha = e (regimes 0, 1) or sqrt(-xi)/2 (regime 2, P = c)
     bool lit = refl || regime == 2;
-    cplx<R> e = expmj<R>(xi * xi * xi * (R)(1.0 / 12));
     cplx<R> alpha = regime == 2 ? cplx<R>{A.h, (R)0} : e;
     cplx<R> eCW = cmul(e, CW);
     cplx<R> as = cmul(alpha, ps), ah = cmul(alpha, ph);

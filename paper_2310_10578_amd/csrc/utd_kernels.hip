@@ -70,6 +70,9 @@ __device__ __forceinline__ bool seg_blocked(d3 P0, d3 P1, const LaunchParams& L,
 // layout rec[(body * S + slot) * n_rx + rx] keeps both passes coalesced;
 // S = 2 (l_enc + 1) bounds the valid paths of a (receiver, body) pair (one
 // side of a lit receiver carries the reflection instead of a creeping path).
+// Creeping paths fill slots 0, 1, ... in (ell, side) order; the reflection,
+// when present, always sits in slot S - 1 (it then leaves at most S - 1
+// creeping paths), so the field kernel can treat the two kinds separately.
 template <typename R> struct PathRec;
 template <> struct PathRec<float> {          // 64 bytes
     double s_tot;
@@ -200,8 +203,7 @@ __global__ void __launch_bounds__(256) k_paths(LaunchParams L, const float* __re
             m |= (uint8_t)(1u << kBitRefl);
             PathEval<R> pe;
             refl_eval<R, double>(P, Q, n, R3, T, L, &pe);
-            if (nrec < S) pack(pe, &rec[((int64_t)b * S + nrec) * L.n_rx + i]);
-            ++nrec;
+            pack(pe, &rec[((int64_t)b * S + (S - 1)) * L.n_rx + i]);
         }
     }
     mask[(int64_t)b * L.n_rx + i] = m;
@@ -226,10 +228,10 @@ template <> struct FreqC<double> {
 
 // One path at one frequency: the Fock arguments scale with powers of k
 // (xi ~ k^{1/3}, sqrt(X) ~ k^{1/2}, q ~ k^{1/6}), so they are products of the
-// path's constants and the frequency's.  LIT selects the general Fock
-// combine (some lane of the wavefront holds a reflection) or the creeping-only
-// one (xi >= 0, no e^{-j xi^3/12}); callers branch on a wave-uniform flag.
-template <typename R, bool LIT>
+// path's constants and the frequency's.  MODE picks the Fock specialisation
+// (kCreep, kRefl or kAny for mixed wavefronts); callers branch on
+// wave-uniform conditions.
+template <typename R, int MODE>
 __device__ __forceinline__ void add_path(const PathEval<R>& pe, const Tabs<R>& tb, const FreqC<R>& fc, R* E) {
     FockArgs<R> a;
     a.xi = fc.k13 * pe.xh;
@@ -238,7 +240,7 @@ __device__ __forceinline__ void add_path(const PathEval<R>& pe, const Tabs<R>& t
     a.ixi = fc.ik13 * pe.ixh;
     a.h = (R)0.5 * fc.k16 * pe.sxh;
     cplx<R> Ks, Kh;
-    fock_kernel<R, LIT>(tb, a, pe.refl != 0, &Ks, &Kh);
+    fock_kernel<R, MODE>(tb, a, pe.refl != 0, &Ks, &Kh);
     cplx<R> ph = phase_rev<R>(fc.rev_per_m * pe.s_tot - 0.25 * pe.nc);
     ph.re *= fc.km16;
     ph.im *= fc.km16;
@@ -354,26 +356,28 @@ __global__ void __launch_bounds__(256) k_field(LaunchParams L, const float* __re
         for (int b = 0; b < nb; ++b) {
             uint8_t m = mask[(int64_t)b * L.n_rx + i];
             caus |= m;
-            int n = __builtin_popcount(m & 0x7fu);
-            n = n < S ? n : S;
+            const bool has_refl = (m >> kBitRefl) & 1u;
+            int n = __builtin_popcount(m & 0x3fu);
+            n = n < (has_refl ? S - 1 : S) ? n : (has_refl ? S - 1 : S);
             for (int k = 0; k < n; ++k) {
                 PathEval<R> pe;
                 unpack(rec[((int64_t)b * S + k) * L.n_rx + i], &pe);
-                if (__any(pe.refl != 0)) {
 #pragma unroll
-                    for (int j = 0; j < FC; ++j) {
-                        if (j < nfc) {
-                            FreqC<R> fc(fcs[f0 + j]);
-                            add_path<R, true>(pe, tb, fc, E[j]);
-                        }
+                for (int j = 0; j < FC; ++j) {
+                    if (j < nfc) {
+                        FreqC<R> fc(fcs[f0 + j]);
+                        add_path<R, kCreep>(pe, tb, fc, E[j]);
                     }
-                } else {
+                }
+            }
+            if (__any(has_refl) && has_refl) {
+                PathEval<R> pe;
+                unpack(rec[((int64_t)b * S + (S - 1)) * L.n_rx + i], &pe);
 #pragma unroll
-                    for (int j = 0; j < FC; ++j) {
-                        if (j < nfc) {
-                            FreqC<R> fc(fcs[f0 + j]);
-                            add_path<R, false>(pe, tb, fc, E[j]);
-                        }
+                for (int j = 0; j < FC; ++j) {
+                    if (j < nfc) {
+                        FreqC<R> fc(fcs[f0 + j]);
+                        add_path<R, kRefl>(pe, tb, fc, E[j]);
                     }
                 }
             }
