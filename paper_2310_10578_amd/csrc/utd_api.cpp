@@ -53,7 +53,7 @@ hipError_t ensure_tables() {
     return g_tables_err;
 }
 
-constexpr int kMaxDepth = 40;   // < kStackDepth of the device traversal
+constexpr int kMaxDepth = 22;   // < kStackDepth of the device traversal (a 2e5-triangle room needs 19)
 
 // --- optional per-kernel event timing (utd_profile_*) ---
 struct ProfRec {

@@ -9,7 +9,7 @@
 namespace utd {
 
 constexpr float kSegEps = 1e-6f;   // open parameter interval (eps, 1 - eps)
-constexpr int kStackDepth = 48;    // per-lane traversal stack (LDS)
+constexpr int kStackDepth = 24;    // per-lane traversal stack (LDS); the builder caps the depth below
 
 // Node: two child boxes and their references, 64 bytes:
 //   q0 = (lo0.x, lo0.y, lo0.z, hi0.x)  q1 = (hi0.y, hi0.z, lo1.x, lo1.y)
