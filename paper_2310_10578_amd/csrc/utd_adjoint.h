@@ -5,7 +5,7 @@
 // utd_kernels.hip after the forward kernels (it reuses their path records,
 // table staging and frequency constants).
 //
-// Per (receiver, body) lane and per valid path:
+// Per valid path (one lane each, over a compacted list of the paths):
 //   1. record adjoint (reverse mode over the frequency loop): lambda_r =
 //      dL/dr for every frequency-independent record scalar r (path length,
 //      Fock constants xh / uh / qhat, amplitude-weighted polarisation
@@ -19,10 +19,11 @@
 // condition taken on duals (implicit differentiation).  The direct ray's
 // gradient (source only) uses the same two steps.
 //
-// Reduction: each lane holds 7 FP64 sums (3 source + up to 4 body); a fixed
-// shuffle tree and a fixed LDS order reduce them per block, a second kernel
-// sums the blocks of each (body slot) in a fixed order and a third sums the
-// source partials over slots: the result does not depend on scheduling.
+// Reduction: every path writes its 7 FP64 contributions (3 source + up to 4
+// body); the paths of a body form one contiguous segment of the list, summed
+// by one block in a fixed strided order and a fixed tree; the direct ray's
+// source gradient is reduced per block of receivers the same way.  The result
+// does not depend on scheduling.
 #pragma once
 
 namespace utd {
@@ -163,52 +164,156 @@ __device__ __forceinline__ void los_adjoint(const LaunchParams& L, d3 R3, const 
     }
 }
 
-// All valid paths of one (receiver, body) pair.
+// ---------------------------------------------------------------------------
+// Work list.  Valid paths are sparse over (receiver, body) pairs (a few per
+// cent in a furnished room), so the per-path work runs over a compacted list
+// instead of one lane per pair: a scan of the per-pair record counts in
+// body-major order e = body * n_rx + rx gives every path an entry
+// (rx | body << 32 | bit << 48) and every body a contiguous segment of the
+// list; per-entry contributions are summed per segment in a fixed order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int pair_records(uint8_t m, uint8_t fl, int S) {
+    if (fl & (kFlagInside | kFlagTxInside)) return 0;
+    const bool has_refl = (m >> kBitRefl) & 1u;
+    int n = __builtin_popcount(m & 0x3fu);
+    const int cap = has_refl ? S - 1 : S;
+    return (n < cap ? n : cap) + (has_refl ? 1 : 0);
+}
+
+constexpr int kScanBlock = 1024;
+
+// Per-block exclusive scan of the record counts: loc[e] (offset inside the
+// block) and bsum[block].
+__global__ void __launch_bounds__(kScanBlock) k_adj_count(LaunchParams L, const uint8_t* __restrict__ mask,
+                                                          const uint8_t* __restrict__ flags, int64_t n_pairs,
+                                                          uint16_t* __restrict__ loc, uint32_t* __restrict__ bsum) {
+    __shared__ uint32_t sc[kScanBlock];
+    const int64_t e = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
+    const int S = 2 * (L.l_enc + 1);
+    uint32_t c = 0;
+    if (e < n_pairs) {
+        const int64_t i = e % L.n_rx;
+        c = (uint32_t)pair_records(mask[e], flags[i], S);
+    }
+    sc[threadIdx.x] = c;
+    __syncthreads();
+    for (int w = 1; w < kScanBlock; w <<= 1) {
+        uint32_t v = threadIdx.x >= (unsigned)w ? sc[threadIdx.x - w] : 0u;
+        __syncthreads();
+        sc[threadIdx.x] += v;
+        __syncthreads();
+    }
+    if (e < n_pairs) loc[e] = (uint16_t)(sc[threadIdx.x] - c);
+    if (threadIdx.x == kScanBlock - 1) bsum[blockIdx.x] = sc[threadIdx.x];
+}
+
+// One block: exclusive scan of the block sums (boff[nblk] = total entries).
+__global__ void __launch_bounds__(kScanBlock) k_adj_scan_top(const uint32_t* __restrict__ bsum, int64_t nblk,
+                                                             int64_t* __restrict__ boff) {
+    __shared__ int64_t sc[kScanBlock];
+    __shared__ int64_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < nblk; base += kScanBlock) {
+        const int64_t j = base + threadIdx.x;
+        const int64_t c = j < nblk ? (int64_t)bsum[j] : 0;
+        sc[threadIdx.x] = c;
+        __syncthreads();
+        for (int w = 1; w < kScanBlock; w <<= 1) {
+            int64_t v = threadIdx.x >= (unsigned)w ? sc[threadIdx.x - w] : 0;
+            __syncthreads();
+            sc[threadIdx.x] += v;
+            __syncthreads();
+        }
+        if (j < nblk) boff[j] = carry + sc[threadIdx.x] - c;
+        __syncthreads();
+        if (threadIdx.x == kScanBlock - 1) carry += sc[threadIdx.x];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) boff[nblk] = carry;
+}
+
+// Entries of every path and the first entry of every body's segment.
+__global__ void __launch_bounds__(kScanBlock) k_adj_emit(LaunchParams L, const uint8_t* __restrict__ mask,
+                                                         const uint8_t* __restrict__ flags, int64_t n_pairs,
+                                                         const uint16_t* __restrict__ loc,
+                                                         const int64_t* __restrict__ boff, uint64_t* __restrict__ ent,
+                                                         int64_t* __restrict__ seg) {
+    const int64_t e = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
+    if (e >= n_pairs) return;
+    const int S = 2 * (L.l_enc + 1);
+    const int64_t i = e % L.n_rx, b = e / L.n_rx;
+    const int64_t base = boff[blockIdx.x] + loc[e];
+    if (i == 0) seg[b] = base;
+    if (e == 0) seg[n_pairs / L.n_rx] = boff[(n_pairs + kScanBlock - 1) / kScanBlock];   // end of the last segment
+    const uint8_t m = mask[e];
+    const int n = pair_records(m, flags[i], S);
+    if (n == 0) return;
+    const bool has_refl = (m >> kBitRefl) & 1u;
+    int k = 0;
+    for (int bit = 0; bit < kBitRefl && k < n - (has_refl ? 1 : 0); ++bit)
+        if ((m >> bit) & 1u) ent[base + k++] = (uint64_t)i | ((uint64_t)b << 32) | ((uint64_t)bit << 48);
+    if (has_refl) ent[base + k] = (uint64_t)i | ((uint64_t)b << 32) | ((uint64_t)kBitRefl << 48);
+}
+
+// One path per lane (grid-stride over the entries): record adjoint over all
+// frequencies, then the dual-number geometry per parameter; writes the 7
+// contributions (3 source + up to 4 body) of the path.
 template <typename R>
-__device__ __forceinline__ void body_adjoint(const LaunchParams& L, d3 R3, int b, const float* __restrict__ sph,
-                                             const float* __restrict__ cyl, const BodyPrep& P0,
-                                             const FreqConst* __restrict__ fcs, uint8_t m,
-                                             const PathRec<R>* __restrict__ rec, const Tabs<R>& tb,
-                                             const R* __restrict__ gE, int64_t i, double acc[kAdjComp]) {
+__global__ void __launch_bounds__(256) k_adj_paths(LaunchParams L, const float* __restrict__ rx,
+                                                   const float* __restrict__ sph, const float* __restrict__ cyl,
+                                                   const BodyPrep* __restrict__ prep,
+                                                   const FreqConst* __restrict__ fcs, const uint8_t* __restrict__ mask,
+                                                   const PathRec<R>* __restrict__ rec, const R* __restrict__ gE,
+                                                   const uint64_t* __restrict__ ent, const int64_t* __restrict__ ntot,
+                                                   double* __restrict__ contrib) {
     using GD = Dual<double>;
     using RD = Dual<R>;
+    __shared__ R s_reg[TableStage<R>::NREG];
+    __shared__ R s_tf[TableStage<R>::NTF];
+    Tabs<R> tb = TableStage<R>::stage(s_reg, s_tf);
+    const int64_t total = *ntot;
     const int S = 2 * (L.l_enc + 1);
-    const bool is_sph = b < L.n_sph;
-    double bp[4];
-    double z0 = 0.0, hh = 0.0;
-    if (is_sph) {
-        const float* s = sph + 4 * b;
-        bp[0] = s[0]; bp[1] = s[1]; bp[2] = s[2]; bp[3] = s[3];
-    } else {
-        const float* c = cyl + 5 * (b - L.n_sph);
-        bp[0] = c[0]; bp[1] = c[1]; bp[2] = c[4]; bp[3] = 0.0;
-        z0 = c[2]; hh = c[3];
-    }
-    const int ndir = is_sph ? 7 : 6;
-    d3 T0 = mk(L.T[0], L.T[1], L.T[2]);
-    V3<GD> Rg{GD(R3.x), GD(R3.y), GD(R3.z)};
-    // records: creeping paths in slots 0, 1, ... (bit order), reflection in S - 1
-    const bool has_refl = (m >> kBitRefl) & 1u;
-    const int ncap = has_refl ? S - 1 : S;
-    int k = 0;
-    for (int bit = 0; bit <= kBitRefl; ++bit) {
-        if (!((m >> bit) & 1u)) continue;
-        if (bit < kBitRefl && bit >= 2 * (L.l_enc + 1)) continue;
-        if (bit < kBitRefl && k >= ncap) continue;
-        const int slot = bit == kBitRefl ? S - 1 : k++;
+    const d3 T0 = mk(L.T[0], L.T[1], L.T[2]);
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t en = ent[q];
+        const int64_t i = (int64_t)(en & 0xffffffffu);
+        const int b = (int)((en >> 32) & 0xffffu);
+        const int bit = (int)(en >> 48);
+        const uint8_t m = mask[(int64_t)b * L.n_rx + i];
+        // slot of the record: reflection in S - 1, creeping paths by rank of their bit
+        const int slot = bit == kBitRefl ? S - 1 : __builtin_popcount(m & ((1u << bit) - 1u) & 0x3fu);
         PathEval<R> pe;
         unpack(rec[((int64_t)b * S + slot) * L.n_rx + i], &pe);
         RecAdj<R> lam;
         record_adjoint<R>(pe, tb, fcs, L.n_f, gE, L.n_rx, i, &lam);
+        const d3 R3 = mk(rx[3 * i], rx[3 * i + 1], rx[3 * i + 2]);
+        const bool is_sph = b < L.n_sph;
+        double bp[4];
+        double z0 = 0.0, hh = 0.0;
+        if (is_sph) {
+            const float* sp = sph + 4 * b;
+            bp[0] = sp[0]; bp[1] = sp[1]; bp[2] = sp[2]; bp[3] = sp[3];
+        } else {
+            const float* c = cyl + 5 * (b - L.n_sph);
+            bp[0] = c[0]; bp[1] = c[1]; bp[2] = c[4]; bp[3] = 0.0;
+            z0 = c[2]; hh = c[3];
+        }
+        const int ndir = is_sph ? 7 : 6;
         const bool refl = bit == kBitRefl;
         const int ell = bit >> 1, sgn = (bit & 1) ? -1 : 1;
         double th = 0.0;
+        bool ok0 = true;
         if (refl) {
+            const BodyPrep P0 = prep[b];
             RxGeo g0 = rx_geo<double>(P0, R3);
-            if (!refl_angle(P0, g0, R3, T0, &th)) continue;
+            ok0 = refl_angle(P0, g0, R3, T0, &th);
         }
+        V3<GD> Rg{GD(R3.x), GD(R3.y), GD(R3.z)};
+        double out[7] = {0, 0, 0, 0, 0, 0, 0};
 #pragma unroll 1
-        for (int dir = 0; dir < ndir; ++dir) {
+        for (int dir = 0; dir < ndir && ok0; ++dir) {
             V3<GD> T{GD(T0.x, dir == 0 ? 1.0 : 0.0), GD(T0.y, dir == 1 ? 1.0 : 0.0), GD(T0.z, dir == 2 ? 1.0 : 0.0)};
             GD p0(bp[0], dir == 3 ? 1.0 : 0.0), p1(bp[1], dir == 4 ? 1.0 : 0.0), p2(bp[2], dir == 5 ? 1.0 : 0.0);
             BodyPrepT<GD> P = is_sph ? prep_sphere<GD>(T, V3<GD>{p0, p1, p2}, GD(bp[3], dir == 6 ? 1.0 : 0.0))
@@ -227,68 +332,61 @@ __device__ __forceinline__ void body_adjoint(const LaunchParams& L, d3 R3, int b
             } else {
                 ok = cyl_creep<RD, GD>(P, g, Rg, T, L, sgn, ell, &pd, nullptr);
             }
-            if (ok) acc[dir] += contract(lam, pd);
+            if (ok) out[dir] = contract(lam, pd);
         }
+        // cylinders: parameters (cx, cy, a) go to components 3, 4, 5
+#pragma unroll
+        for (int d = 0; d < 7; ++d) contrib[q * 8 + d] = out[d];
     }
 }
 
-// grid: x over receivers (256 per block), y over slot = 0 (direct ray) or
-// 1 + body.  partial[(slot * gridDim.x + block) * kAdjComp + d].
+// Direct ray (source gradient only): one lane per receiver, block partials.
 template <typename R>
-__global__ void __launch_bounds__(256) k_adjoint(LaunchParams L, const float* __restrict__ rx,
-                                                 const float* __restrict__ sph, const float* __restrict__ cyl,
-                                                 const BodyPrep* __restrict__ prep, const FreqConst* __restrict__ fcs,
-                                                 const uint8_t* __restrict__ mask, const PathRec<R>* __restrict__ rec,
+__global__ void __launch_bounds__(256) k_adj_los(LaunchParams L, const float* __restrict__ rx,
+                                                 const FreqConst* __restrict__ fcs,
                                                  const uint8_t* __restrict__ flags, const R* __restrict__ gE,
-                                                 double* __restrict__ partial) {
-    __shared__ R s_reg[TableStage<R>::NREG];
-    __shared__ R s_tf[TableStage<R>::NTF];
-    __shared__ double s_red[4][kAdjComp];
-    Tabs<R> tb = TableStage<R>::stage(s_reg, s_tf);
+                                                 double* __restrict__ part) {
+    __shared__ double s_red[4][4];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int slot = blockIdx.y;
     double acc[kAdjComp];
 #pragma unroll
     for (int d = 0; d < kAdjComp; ++d) acc[d] = 0.0;
     if (i < L.n_rx) {
         uint8_t fl = flags[i];
-        if (!(fl & (kFlagInside | kFlagTxInside))) {
-            d3 R3 = mk(rx[3 * i], rx[3 * i + 1], rx[3 * i + 2]);
-            if (slot == 0) {
-                if ((fl & kFlagLos) && L.lit_branch) los_adjoint<R>(L, R3, fcs, gE, i, acc);
-            } else {
-                int b = slot - 1;
-                uint8_t m = mask[(int64_t)b * L.n_rx + i];
-                if (m & 0x7fu) body_adjoint<R>(L, R3, b, sph, cyl, prep[b], fcs, m, rec, tb, gE, i, acc);
-            }
-        }
+        if (!(fl & (kFlagInside | kFlagTxInside)) && (fl & kFlagLos) && L.lit_branch)
+            los_adjoint<R>(L, mk(rx[3 * i], rx[3 * i + 1], rx[3 * i + 2]), fcs, gE, i, acc);
     }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-    for (int d = 0; d < kAdjComp; ++d) {
+    for (int d = 0; d < 3; ++d) {
         double v = acc[d];
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
         if (lane == 0) s_red[wid][d] = v;
     }
     __syncthreads();
-    if (threadIdx.x < kAdjComp) {
+    if (threadIdx.x < 3) {
         int d = threadIdx.x;
-        double t = (s_red[0][d] + s_red[1][d]) + (s_red[2][d] + s_red[3][d]);
-        partial[((int64_t)slot * gridDim.x + blockIdx.x) * kAdjComp + d] = t;
+        part[(int64_t)blockIdx.x * 4 + d] = (s_red[0][d] + s_red[1][d]) + (s_red[2][d] + s_red[3][d]);
     }
 }
 
-// Sum of the block partials of one slot (block per slot), fixed order.
+// Block per body (segment sums of the path contributions) plus one block for
+// the direct-ray partials; fixed strided order and a fixed tree.
 template <typename R>
-__global__ void __launch_bounds__(256) k_adjoint_reduce(const double* __restrict__ partial, int64_t nblk, int n_sph,
-                                                        R* __restrict__ d_sph, R* __restrict__ d_cyl,
-                                                        double* __restrict__ txpart) {
+__global__ void __launch_bounds__(256) k_adj_reduce(const double* __restrict__ contrib, const int64_t* __restrict__ seg,
+                                                    const double* __restrict__ los_part, int64_t n_los_blk, int nb,
+                                                    int has_paths, int n_sph, R* __restrict__ d_sph,
+                                                    R* __restrict__ d_cyl, double* __restrict__ txpart) {
     __shared__ double red[256];
-    const int slot = blockIdx.x;
-    for (int d = 0; d < 7; ++d) {
+    const int slot = blockIdx.x;            // body, or nb for the direct ray
+    const bool los = slot == nb;
+    const int64_t lo = los ? 0 : (has_paths ? seg[slot] : 0);
+    const int64_t hi = los ? n_los_blk : (has_paths ? seg[slot + 1] : 0);
+    const int nd = los ? 3 : 7;
+    for (int d = 0; d < nd; ++d) {
         double s = 0.0;
-        for (int64_t j = threadIdx.x; j < nblk; j += 256) s += partial[((int64_t)slot * nblk + j) * kAdjComp + d];
+        for (int64_t j = lo + threadIdx.x; j < hi; j += 256) s += los ? los_part[j * 4 + d] : contrib[j * 8 + d];
         red[threadIdx.x] = s;
         __syncthreads();
         for (int w = 128; w > 0; w >>= 1) {
@@ -299,10 +397,9 @@ __global__ void __launch_bounds__(256) k_adjoint_reduce(const double* __restrict
             double t = red[0];
             if (d < 3) {
                 txpart[slot * 3 + d] = t;
-            } else if (slot > 0) {
-                int b = slot - 1;
-                if (b < n_sph) d_sph[b * 4 + (d - 3)] = (R)t;
-                else if (d < 6) d_cyl[(b - n_sph) * 3 + (d - 3)] = (R)t;
+            } else {
+                if (slot < n_sph) d_sph[slot * 4 + (d - 3)] = (R)t;
+                else if (d < 6) d_cyl[(slot - n_sph) * 3 + (d - 3)] = (R)t;
             }
         }
         __syncthreads();
@@ -319,35 +416,75 @@ __global__ void k_adjoint_tx(const double* __restrict__ txpart, int nslot, R* __
     }
 }
 
+// Scratch of the adjoint beyond the forward workspace, in bytes.
+size_t adjoint_scratch_bytes(const LaunchParams& L) {
+    const int64_t nb = L.n_sph + L.n_cyl;
+    const int64_t n_pairs = nb * L.n_rx;
+    const int64_t nblk = (n_pairs + kScanBlock - 1) / kScanBlock;
+    const int64_t max_ent = n_pairs * 2 * (L.l_enc + 1);
+    const int64_t nlos = (L.n_rx + 255) / 256;
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    return up(sizeof(uint16_t) * n_pairs) + up(sizeof(uint32_t) * nblk) + up(sizeof(int64_t) * (nblk + 1)) +
+           up(sizeof(int64_t) * (nb + 1)) + up(sizeof(uint64_t) * max_ent) + up(sizeof(double) * 8 * max_ent) +
+           up(sizeof(double) * 4 * nlos) + up(sizeof(double) * 3 * (nb + 1)) + 256;
+}
+
 template <typename R>
 static hipError_t launch_adjoint_t(const LaunchParams& L, const float* rx, const float* sph, const float* cyl,
                                    const BodyPrep* prep, const FreqConst* fcs, const uint8_t* mask, const void* rec,
-                                   const uint8_t* flags, const void* gE, int64_t nblk, double* partial,
-                                   double* txpart, void* d_sph, void* d_cyl, void* d_tx, hipStream_t s) {
-    int nb = L.n_sph + L.n_cyl;
-    if (nblk > 0) {
-        dim3 grid((unsigned)nblk, (unsigned)(nb + 1));
-        hipLaunchKernelGGL((k_adjoint<R>), grid, dim3(256), 0, s, L, rx, sph, cyl, prep, fcs, mask,
-                           (const PathRec<R>*)rec, flags, (const R*)gE, partial);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+                                   const uint8_t* flags, const void* gE, char* scratch, void* d_sph, void* d_cyl,
+                                   void* d_tx, hipStream_t s) {
+    const int nb = L.n_sph + L.n_cyl;
+    const int64_t n_pairs = (int64_t)nb * L.n_rx;
+    const int64_t nblk = (n_pairs + kScanBlock - 1) / kScanBlock;
+    const int64_t max_ent = n_pairs * 2 * (L.l_enc + 1);
+    const int64_t nlos = (L.n_rx + 255) / 256;
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    char* p = scratch;
+    uint16_t* loc = (uint16_t*)p; p += up(sizeof(uint16_t) * n_pairs);
+    uint32_t* bsum = (uint32_t*)p; p += up(sizeof(uint32_t) * nblk);
+    int64_t* boff = (int64_t*)p; p += up(sizeof(int64_t) * (nblk + 1));
+    int64_t* seg = (int64_t*)p; p += up(sizeof(int64_t) * (nb + 1));
+    uint64_t* ent = (uint64_t*)p; p += up(sizeof(uint64_t) * max_ent);
+    double* contrib = (double*)p; p += up(sizeof(double) * 8 * max_ent);
+    double* los_part = (double*)p; p += up(sizeof(double) * 4 * nlos);
+    double* txpart = (double*)p;
+    hipError_t e;
+    if (n_pairs > 0) {
+        hipLaunchKernelGGL(k_adj_count, dim3((unsigned)nblk), dim3(kScanBlock), 0, s, L, mask, flags, n_pairs, loc,
+                           bsum);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_adj_scan_top, dim3(1), dim3(kScanBlock), 0, s, bsum, nblk, boff);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_adj_emit, dim3((unsigned)nblk), dim3(kScanBlock), 0, s, L, mask, flags, n_pairs, loc,
+                           boff, ent, seg);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        int64_t grid = (max_ent + 255) / 256;
+        grid = grid < 1 ? 1 : (grid > 256 * 8 ? 256 * 8 : grid);
+        hipLaunchKernelGGL((k_adj_paths<R>), dim3((unsigned)grid), dim3(256), 0, s, L, rx, sph, cyl, prep, fcs, mask,
+                           (const PathRec<R>*)rec, (const R*)gE, ent, boff + nblk, contrib);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_adjoint_reduce<R>), dim3(nb + 1), dim3(256), 0, s, partial, nblk, L.n_sph, (R*)d_sph,
-                       (R*)d_cyl, txpart);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (nlos > 0) {
+        hipLaunchKernelGGL((k_adj_los<R>), dim3((unsigned)nlos), dim3(256), 0, s, L, rx, fcs, flags, (const R*)gE,
+                           los_part);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_adj_reduce<R>), dim3(nb + 1), dim3(256), 0, s, contrib, seg, los_part, nlos, nb,
+                       n_pairs > 0 ? 1 : 0, L.n_sph, (R*)d_sph, (R*)d_cyl, txpart);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL((k_adjoint_tx<R>), dim3(1), dim3(64), 0, s, txpart, nb + 1, (R*)d_tx);
     return hipGetLastError();
 }
 
 hipError_t launch_adjoint(const LaunchParams& L, int precision, const float* rx, const float* sph, const float* cyl,
                           const BodyPrep* prep, const FreqConst* fcs, const uint8_t* mask, const void* rec,
-                          const uint8_t* flags, const void* gE, int64_t nblk, double* partial, double* txpart,
-                          void* d_sph, void* d_cyl, void* d_tx, hipStream_t s) {
-    return precision == 0 ? launch_adjoint_t<float>(L, rx, sph, cyl, prep, fcs, mask, rec, flags, gE, nblk, partial,
-                                                    txpart, d_sph, d_cyl, d_tx, s)
-                          : launch_adjoint_t<double>(L, rx, sph, cyl, prep, fcs, mask, rec, flags, gE, nblk, partial,
-                                                     txpart, d_sph, d_cyl, d_tx, s);
+                          const uint8_t* flags, const void* gE, char* scratch, void* d_sph, void* d_cyl, void* d_tx,
+                          hipStream_t s) {
+    return precision == 0 ? launch_adjoint_t<float>(L, rx, sph, cyl, prep, fcs, mask, rec, flags, gE, scratch, d_sph,
+                                                    d_cyl, d_tx, s)
+                          : launch_adjoint_t<double>(L, rx, sph, cyl, prep, fcs, mask, rec, flags, gE, scratch, d_sph,
+                                                     d_cyl, d_tx, s);
 }
 
 }  // namespace utd

@@ -338,14 +338,11 @@ utd_status utd_smooth_field_backward(const utd_scene* scene, const utd_bodies* b
     hipStream_t s = (hipStream_t)stream;
     utd::LaunchParams L = make_params(bodies, tx, n_rx, n_f, opt);
     int nb = L.n_sph + L.n_cyl;
-    int64_t nblk = work ? (n_rx + 255) / 256 : 0;
-    size_t n_part = (size_t)(nb + 1) * (size_t)nblk * 8;
-    size_t extra = sizeof(double) * (n_part + (size_t)(nb + 1) * 3) + 256;
+    if (!work) L.n_rx = 0;                  // no paths: every gradient is zero
+    size_t extra = utd::adjoint_scratch_bytes(L);
     Workspace w;
     e = w.alloc(nb, work ? n_rx : 0, n_f, opt->l_enc, opt->precision, true, s, extra);
     if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(UTD_E_OOM, "workspace allocation") : hip_fail(e, "hipMallocAsync");
-    double* partial = (double*)w.extra;
-    double* txpart = partial + ((n_part + 31) & ~(size_t)31);
     const float4* nodes = scene ? scene->d_nodes : nullptr;
     const float4* tris = scene ? scene->d_tris : nullptr;
     if (work) {
@@ -356,7 +353,7 @@ utd_status utd_smooth_field_backward(const utd_scene* scene, const utd_bodies* b
     if (e == hipSuccess) {
         ProfScope ps(UTD_K_BACKWARD, s);
         e = utd::launch_adjoint(L, opt->precision, rx, bodies->sph, bodies->cyl, w.prep, w.fc, w.mask, w.rec, w.flags,
-                                grad_E, nblk, partial, txpart, d_sph, d_cyl, d_tx, s);
+                                grad_E, w.extra, d_sph, d_cyl, d_tx, s);
     }
     char* ws = w.base;
     hipError_t e2 = hipFreeAsync(ws, s);

@@ -27,10 +27,12 @@ size_t path_record_bytes(int precision);
 hipError_t launch_field(const LaunchParams& L, int precision, int fc, const float* rx, const FreqConst* fcs,
                         const uint8_t* mask, const void* rec, uint8_t* flags, void* E, hipStream_t s);
 
+// Adjoint (utd_adjoint.h): scratch is adjoint_scratch_bytes(L) bytes.
+size_t adjoint_scratch_bytes(const LaunchParams& L);
 hipError_t launch_adjoint(const LaunchParams& L, int precision, const float* rx, const float* sph, const float* cyl,
                           const BodyPrep* prep, const FreqConst* fcs, const uint8_t* mask, const void* rec,
-                          const uint8_t* flags, const void* gE, int64_t nblk, double* partial, double* txpart,
-                          void* d_sph, void* d_cyl, void* d_tx, hipStream_t s);
+                          const uint8_t* flags, const void* gE, char* scratch, void* d_sph, void* d_cyl, void* d_tx,
+                          hipStream_t s);
 
 hipError_t launch_batch(const BatchParams& B, int precision, int n_blocks, const int64_t* body_off,
                         const int64_t* rx_off, const float* rx, const float* cyl, const double* freqs,
