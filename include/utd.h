@@ -113,8 +113,14 @@ int64_t utd_scene_nodes(const utd_scene *scene);
  *            Fully overwritten.
  *   rx_flags device uint8 [n_rx] or NULL.
  * n_rx == 0 or n_f == 0 enqueues nothing and returns UTD_OK.
+ * Scratch (path masks and records, the candidate-path queue) comes from a
+ * grow-only buffer the library keeps per (device, stream) between calls,
+ * allocated stream-ordered and released at process exit; calls on one stream
+ * are ordered by the stream, so issuing them from several host threads at
+ * once is not supported.
  * Errors: UTD_E_ARG for NULL pointers with non-zero sizes, n_rx < 0, n_f < 0,
- * l_enc outside 0..2, precision outside {0, 1}; UTD_E_DEVICE on launch failure. */
+ * l_enc outside 0..2, precision outside {0, 1}; UTD_E_OOM when the scratch
+ * cannot be allocated; UTD_E_DEVICE on launch failure. */
 utd_status utd_smooth_field(const utd_scene *scene, const utd_bodies *bodies,
                             const utd_source *tx, const float *rx, int64_t n_rx,
                             const double *freqs_hz, int n_f, const utd_options *opt,
@@ -136,7 +142,7 @@ utd_status utd_smooth_field(const utd_scene *scene, const utd_bodies *bodies,
  * those of the forward evaluation at the same inputs and are held fixed;
  * receivers inside a body or with the source inside one contribute nothing.
  * The reduction over receivers and frequencies runs in FP64 in a fixed order
- * (bitwise reproducible).  Allocates stream-ordered workspace like
+ * (bitwise reproducible).  Uses the per-stream scratch of
  * utd_smooth_field.
  * Errors as for utd_smooth_field; UTD_E_ARG if d_tx is NULL, d_cyl / d_sph is
  * NULL with a non-zero count, or grad_E is NULL with n_rx, n_f > 0. */

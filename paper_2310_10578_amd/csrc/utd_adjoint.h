@@ -174,10 +174,7 @@ __device__ __forceinline__ void los_adjoint(const LaunchParams& L, d3 R3, const 
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int pair_records(uint8_t m, uint8_t fl, int S) {
     if (fl & (kFlagInside | kFlagTxInside)) return 0;
-    const bool has_refl = (m >> kBitRefl) & 1u;
-    int n = __builtin_popcount(m & 0x3fu);
-    const int cap = has_refl ? S - 1 : S;
-    return (n < cap ? n : cap) + (has_refl ? 1 : 0);
+    return __builtin_popcount(m & ((1u << S) - 1u)) + ((m >> kBitRefl) & 1u);
 }
 
 constexpr int kScanBlock = 1024;
@@ -249,11 +246,10 @@ __global__ void __launch_bounds__(kScanBlock) k_adj_emit(LaunchParams L, const u
     const uint8_t m = mask[e];
     const int n = pair_records(m, flags[i], S);
     if (n == 0) return;
-    const bool has_refl = (m >> kBitRefl) & 1u;
     int k = 0;
-    for (int bit = 0; bit < kBitRefl && k < n - (has_refl ? 1 : 0); ++bit)
+    for (int bit = 0; bit < S; ++bit)
         if ((m >> bit) & 1u) ent[base + k++] = (uint64_t)i | ((uint64_t)b << 32) | ((uint64_t)bit << 48);
-    if (has_refl) ent[base + k] = (uint64_t)i | ((uint64_t)b << 32) | ((uint64_t)kBitRefl << 48);
+    if ((m >> kBitRefl) & 1u) ent[base + k] = (uint64_t)i | ((uint64_t)b << 32) | ((uint64_t)kBitRefl << 48);
 }
 
 // One path per lane (grid-stride over the entries): record adjoint over all
@@ -273,7 +269,6 @@ __global__ void __launch_bounds__(256) k_adj_paths(LaunchParams L, const float* 
     __shared__ R s_tf[TableStage<R>::NTF];
     Tabs<R> tb = TableStage<R>::stage(s_reg, s_tf);
     const int64_t total = *ntot;
-    const int S = 2 * (L.l_enc + 1);
     const d3 T0 = mk(L.T[0], L.T[1], L.T[2]);
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
          q += (int64_t)gridDim.x * blockDim.x) {
@@ -281,11 +276,8 @@ __global__ void __launch_bounds__(256) k_adj_paths(LaunchParams L, const float* 
         const int64_t i = (int64_t)(en & 0xffffffffu);
         const int b = (int)((en >> 32) & 0xffffu);
         const int bit = (int)(en >> 48);
-        const uint8_t m = mask[(int64_t)b * L.n_rx + i];
-        // slot of the record: reflection in S - 1, creeping paths by rank of their bit
-        const int slot = bit == kBitRefl ? S - 1 : __builtin_popcount(m & ((1u << bit) - 1u) & 0x3fu);
         PathEval<R> pe;
-        unpack(rec[((int64_t)b * S + slot) * L.n_rx + i], &pe);
+        unpack(rec[((int64_t)b * rec_slots(L) + rec_slot(L, bit)) * L.n_rx + i], &pe);
         RecAdj<R> lam;
         record_adjoint<R>(pe, tb, fcs, L.n_f, gE, L.n_rx, i, &lam);
         const d3 R3 = mk(rx[3 * i], rx[3 * i + 1], rx[3 * i + 2]);
@@ -421,7 +413,7 @@ size_t adjoint_scratch_bytes(const LaunchParams& L) {
     const int64_t nb = L.n_sph + L.n_cyl;
     const int64_t n_pairs = nb * L.n_rx;
     const int64_t nblk = (n_pairs + kScanBlock - 1) / kScanBlock;
-    const int64_t max_ent = n_pairs * 2 * (L.l_enc + 1);
+    const int64_t max_ent = n_pairs * (2 * (L.l_enc + 1) + 1);
     const int64_t nlos = (L.n_rx + 255) / 256;
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
     return up(sizeof(uint16_t) * n_pairs) + up(sizeof(uint32_t) * nblk) + up(sizeof(int64_t) * (nblk + 1)) +
@@ -437,7 +429,7 @@ static hipError_t launch_adjoint_t(const LaunchParams& L, const float* rx, const
     const int nb = L.n_sph + L.n_cyl;
     const int64_t n_pairs = (int64_t)nb * L.n_rx;
     const int64_t nblk = (n_pairs + kScanBlock - 1) / kScanBlock;
-    const int64_t max_ent = n_pairs * 2 * (L.l_enc + 1);
+    const int64_t max_ent = n_pairs * (2 * (L.l_enc + 1) + 1);
     const int64_t nlos = (L.n_rx + 255) / 256;
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
     char* p = scratch;

@@ -121,6 +121,41 @@ utd::LaunchParams make_params(const utd_bodies* bodies, const utd_source* tx, in
 // Stream-ordered scratch of one call: body constants, frequency constants,
 // path masks, reflection angles, flags (when the caller passed none) and
 // counters.
+// Per (device, stream) scratch kept between calls (grow-only, stream-ordered
+// allocation): calls on one stream reuse it in stream order, calls on
+// different streams get different buffers.  Released when the process ends.
+struct WsCache {
+    char* p = nullptr;
+    size_t bytes = 0;
+};
+std::mutex g_ws_mu;
+std::map<std::pair<int, hipStream_t>, WsCache> g_ws;
+
+hipError_t ws_get(size_t total, hipStream_t s, char** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    WsCache& c = g_ws[std::make_pair(dev, s)];
+    if (c.bytes < total) {
+        if (c.p) {
+            e = hipFreeAsync(c.p, s);
+            if (e != hipSuccess) return e;
+            c.p = nullptr;
+            c.bytes = 0;
+        }
+        size_t want = total + total / 4;
+        e = hipMallocAsync((void**)&c.p, want, s);
+        if (e != hipSuccess) {
+            c.p = nullptr;
+            return e;
+        }
+        c.bytes = want;
+    }
+    *out = c.p;
+    return hipSuccess;
+}
+
 struct Workspace {
     char* base = nullptr;
     utd::BodyPrep* prep = nullptr;
@@ -128,22 +163,29 @@ struct Workspace {
     uint8_t* mask = nullptr;
     void* rec = nullptr;
     uint8_t* flags = nullptr;
-    unsigned long long* counters = nullptr;
+    unsigned long long* counters = nullptr;   // [0..9] census, [12] queue length
+    uint64_t* ent = nullptr;                  // candidate-path queue
+    double* ent_th = nullptr;
+    int64_t cap = 0;
     char* extra = nullptr;
     hipError_t alloc(int nb, int64_t n_rx, int n_f, int l_enc, int precision, bool need_flags, hipStream_t s,
                      size_t extra_bytes = 0) {
         auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
         size_t nbb = (size_t)(nb > 0 ? nb : 1);
+        size_t slots = (size_t)(2 * (l_enc + 1) + 1);
+        cap = n_rx * (1 + (int64_t)nb * (int64_t)slots);
         size_t o_prep = 0;
         size_t o_fc = up(o_prep + sizeof(utd::BodyPrep) * nbb);
         size_t o_mask = up(o_fc + sizeof(utd::FreqConst) * (size_t)(n_f > 0 ? n_f : 1));
-        size_t o_rec = up(o_mask + (size_t)n_rx * nbb);
-        size_t rec_bytes = utd::path_record_bytes(precision) * (size_t)(2 * (l_enc + 1)) * (size_t)n_rx * nbb;
+        size_t o_rec = up(o_mask + (size_t)n_rx * nbb + 4);
+        size_t rec_bytes = utd::path_record_bytes(precision) * slots * (size_t)n_rx * nbb;
         size_t o_flag = up(o_rec + rec_bytes);
         size_t o_cnt = up(o_flag + (need_flags ? (size_t)n_rx : 0));
-        size_t o_extra = up(o_cnt + 16 * sizeof(unsigned long long));
+        size_t o_ent = up(o_cnt + 16 * sizeof(unsigned long long));
+        size_t o_th = up(o_ent + sizeof(uint64_t) * (size_t)cap);
+        size_t o_extra = up(o_th + sizeof(double) * (size_t)cap);
         size_t total = o_extra + extra_bytes;
-        hipError_t e = hipMallocAsync((void**)&base, total, s);
+        hipError_t e = ws_get(total, s, &base);
         if (e != hipSuccess) return e;
         prep = (utd::BodyPrep*)(base + o_prep);
         fc = (utd::FreqConst*)(base + o_fc);
@@ -151,6 +193,8 @@ struct Workspace {
         rec = (void*)(base + o_rec);
         flags = need_flags ? (uint8_t*)(base + o_flag) : nullptr;
         counters = (unsigned long long*)(base + o_cnt);
+        ent = (uint64_t*)(base + o_ent);
+        ent_th = (double*)(base + o_th);
         extra = extra_bytes ? base + o_extra : nullptr;
         return hipSuccess;
     }
@@ -275,17 +319,14 @@ utd_status utd_smooth_field(const utd_scene* scene, const utd_bodies* bodies, co
     {
         ProfScope ps(UTD_K_OCCLUDE, s);
         e = utd::launch_paths(L, opt->precision, rx, bodies->sph, bodies->cyl, freqs, w.prep, w.fc, nodes, tris,
-                              w.mask, w.rec, flags, s);
+                              w.mask, w.rec, flags, w.ent, w.ent_th, w.counters + 12, w.cap, s);
     }
     int fc = pick_fc(opt->precision, n_rx, n_f);
     if (e == hipSuccess) {
         ProfScope ps(UTD_K_FIELD, s);
         e = utd::launch_field(L, opt->precision, fc, rx, w.fc, w.mask, w.rec, flags, E_out, s);
     }
-    char* ws = w.base;
-    hipError_t e2 = hipFreeAsync(ws, s);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
-    if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
     return UTD_OK;
 }
 
@@ -305,19 +346,16 @@ utd_status utd_path_census(const utd_scene* scene, const utd_bodies* bodies, con
     Workspace w;
     e = w.alloc(nb, n_rx, 0, opt->l_enc, 0, true, s);
     if (e != hipSuccess) return hip_fail(e, "hipMallocAsync");
-    char* ws = w.base;
     unsigned long long host[10] = {0};
     e = hipMemsetAsync(w.counters, 0, 16 * sizeof(unsigned long long), s);
     if (e == hipSuccess)
         e = utd::launch_paths(L, 0, rx, bodies->sph, bodies->cyl, nullptr, w.prep, w.fc,
                               scene ? scene->d_nodes : nullptr, scene ? scene->d_tris : nullptr, w.mask, w.rec,
-                              w.flags, s);
+                              w.flags, w.ent, w.ent_th, w.counters + 12, w.cap, s);
     if (e == hipSuccess) e = utd::launch_census(nb > 0 ? (int64_t)nb * n_rx : 0, w.mask, n_rx, w.flags, w.counters, s);
     if (e == hipSuccess) e = hipMemcpyAsync(host, w.counters, sizeof host, hipMemcpyDeviceToHost, s);
-    hipError_t e2 = hipFreeAsync(ws, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "path census");
-    if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
     for (int k = 0; k < 10; ++k) counts[k] = (int64_t)host[k];
     return UTD_OK;
 }
@@ -348,17 +386,14 @@ utd_status utd_smooth_field_backward(const utd_scene* scene, const utd_bodies* b
     if (work) {
         ProfScope ps(UTD_K_OCCLUDE, s);
         e = utd::launch_paths(L, opt->precision, rx, bodies->sph, bodies->cyl, freqs, w.prep, w.fc, nodes, tris,
-                              w.mask, w.rec, w.flags, s);
+                              w.mask, w.rec, w.flags, w.ent, w.ent_th, w.counters + 12, w.cap, s);
     }
     if (e == hipSuccess) {
         ProfScope ps(UTD_K_BACKWARD, s);
         e = utd::launch_adjoint(L, opt->precision, rx, bodies->sph, bodies->cyl, w.prep, w.fc, w.mask, w.rec, w.flags,
                                 grad_E, w.extra, d_sph, d_cyl, d_tx, s);
     }
-    char* ws = w.base;
-    hipError_t e2 = hipFreeAsync(ws, s);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
-    if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
     return UTD_OK;
 }
 
@@ -424,7 +459,8 @@ utd_status utd_smooth_field_batched(const utd_scene* scene, int64_t n_frames, co
     size_t o_ro = up(o_bo + sizeof(int64_t) * (size_t)(n_frames + 1));
     size_t o_to = up(o_ro + sizeof(int64_t) * (size_t)(n_frames + 1));
     size_t o_cnt = up(o_to + sizeof(int64_t) * (size_t)(n_frames + 1));
-    size_t need = o_cnt + 256;
+    size_t o_th = up(o_cnt + 256);
+    size_t need = o_th + utd::batch_scratch_bytes(n_blocks);
 
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     e = hipStreamIsCapturing(s, &cs);
@@ -449,8 +485,8 @@ utd_status utd_smooth_field_batched(const utd_scene* scene, int64_t n_frames, co
         return utd::launch_batch(B, opt->precision, n_blocks, body_off, rx_off, rx, cyl, freqs,
                                  (utd::BodyPrep*)(w + o_prep), (utd::FreqConst*)(w + o_fc), (int64_t*)(w + o_bo),
                                  (int64_t*)(w + o_ro), (int64_t*)(w + o_to), (unsigned*)(w + o_cnt),
-                                 scene ? scene->d_nodes : nullptr, scene ? scene->d_tris : nullptr, E_out, rx_flags,
-                                 ls);
+                                 scene ? scene->d_nodes : nullptr, scene ? scene->d_tris : nullptr,
+                                 (double*)(w + o_th), E_out, rx_flags, ls);
     };
     if (caller_capturing) {
         // the caller records these launches into its own graph

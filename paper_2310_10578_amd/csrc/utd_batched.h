@@ -116,155 +116,20 @@ __device__ __forceinline__ int64_t uniform64(int64_t v) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-// Per-lane list of visible paths (body << 3 | path bit), a column of LDS per
-// lane.  A lane first runs the visibility of all of its frame's paths, then
-// evaluates the listed paths at every frequency; the list is flushed early
-// when it could overflow.  Keeping the two phases apart keeps the traversal
-// state and the Fock evaluation from being live at once.
-constexpr int kListCap = 32;
-
-template <typename R>
-__device__ __forceinline__ void eval_listed(const LaunchParams& L, d3 R3, d3 T, int64_t li,
-                                            const BodyPrep* __restrict__ fprep, const FreqConst* __restrict__ fcs,
-                                            const Tabs<R>& tb, const uint16_t* list, int stride, int n,
-                                            R* __restrict__ E) {
-    const int64_t nrx = L.n_rx;
-#pragma unroll 1
-    for (int k = 0; k < n; ++k) {
-        const int ent = list[k * stride];
-        const int b = ent >> 3, bit = ent & 7;
-        const BodyPrep P = fprep[b];
-        RxGeo g = rx_geo<double, Kinds::Cylinders>(P, R3);
-        PathEval<R> pe;
-        if (bit == kBitRefl) {
-            double th = 0.0;
-            refl_angle<Kinds::Cylinders>(P, g, R3, T, &th);
-            d3 Q, n3;
-            refl_point<double, Kinds::Cylinders>(P, g, R3, T, th, &Q, &n3);
-            refl_eval<R, double>(P, Q, n3, R3, T, L, &pe);
-        } else {
-            const int ell = bit >> 1, sgn = (bit & 1) ? -1 : 1;
-            cyl_creep<R, double>(P, g, R3, T, L, sgn, ell, &pe, nullptr);
-        }
-        // wave-uniform choice of the Fock specialisation
-        const bool any_refl = __any(pe.refl != 0), any_creep = __any(pe.refl == 0);
-        const int mode = !any_refl ? kCreep : (!any_creep ? kRefl : kAny);
-#pragma unroll 1
-        for (int j = 0; j < L.n_f; ++j) {
-            R e[6];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                int64_t o = ((int64_t)j * 3 + c) * nrx + li;
-                e[2 * c] = E[2 * o];
-                e[2 * c + 1] = E[2 * o + 1];
-            }
-            FreqC<R> fc(fcs[j]);
-            if (mode == kCreep)
-                add_path<R, kCreep>(pe, tb, fc, e);
-            else if (mode == kRefl)
-                add_path<R, kRefl>(pe, tb, fc, e);
-            else
-                add_path<R, kAny>(pe, tb, fc, e);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                int64_t o = ((int64_t)j * 3 + c) * nrx + li;
-                E[2 * o] = e[2 * c];
-                E[2 * o + 1] = e[2 * c + 1];
-            }
-        }
-    }
-}
-
-// The work of one receiver lane of a tile.
-template <typename R>
-__device__ __forceinline__ void batch_lane(const LaunchParams& L, d3 R3, int64_t li, const float* __restrict__ fcyl,
-                                           const BodyPrep* __restrict__ fprep, const FreqConst* __restrict__ fcs,
-                                           const Tabs<R>& tb, const float4* __restrict__ nodes,
-                                           const float4* __restrict__ tris, int* stk, uint16_t* list, int stride,
-                                           R* __restrict__ E, uint8_t* fl_out) {
-    const int nb = L.n_cyl;
-    const int64_t nrx = L.n_rx;
-    d3 T = mk(L.T[0], L.T[1], L.T[2]);
-    bool inside = false, tx_inside = false;
-    for (int b = 0; b < nb; ++b) {
-        inside |= inside_body(fprep[b], R3);
-        tx_inside |= inside_body(fprep[b], T);
-    }
-    uint8_t fl = (tx_inside ? kFlagTxInside : 0) | (inside ? kFlagInside : 0);
-    const bool dead = inside || tx_inside;
-    bool los = false;
-    if (!dead) los = !seg_blocked(T, R3, L, nullptr, fcyl, -1, true, nodes, tris, stk, stride);
-    if (los) fl |= kFlagLos;
-    // direct ray (or zero) initialises the lane's field
-    R e3[3] = {(R)0, (R)0, (R)0};
-    double sd = 0.0;
-    const bool use_los = los && L.lit_branch;
-    if (use_los) {
-        d3 v = mk(R3.x - L.T[0], R3.y - L.T[1], R3.z - L.T[2]);
-        sd = norm(v);
-        R isd = (R)(1.0 / sd);
-        R shx = (R)v.x * isd, shy = (R)v.y * isd, shz = (R)v.z * isd;
-        R px = (R)L.p[0], py = (R)L.p[1], pz = (R)L.p[2];
-        R pd = px * shx + py * shy + pz * shz;
-        R A = (R)L.amp * isd;
-        e3[0] = A * (px - pd * shx); e3[1] = A * (py - pd * shy); e3[2] = A * (pz - pd * shz);
-    }
-#pragma unroll 1
-    for (int j = 0; j < L.n_f; ++j) {
-        cplx<R> ph{(R)0, (R)0};
-        if (use_los) ph = phase_rev<R>(fcs[j].rev_per_m * sd);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            int64_t o = ((int64_t)j * 3 + c) * nrx + li;
-            E[2 * o] = (R)0 + e3[c] * ph.re;
-            E[2 * o + 1] = (R)0 + e3[c] * ph.im;
-        }
-    }
-    if (!dead) {
-        const bool bo_ = L.bodies_occlude != 0;
-        const int per_body = 2 * (L.l_enc + 1) + 1;
-        int n = 0;
-#pragma unroll 1
-        for (int b = 0; b <= nb; ++b) {
-            if (b == nb || n > kListCap - per_body) {
-                eval_listed<R>(L, R3, T, li, fprep, fcs, tb, list, stride, n, E);
-                n = 0;
-                if (b == nb) break;
-            }
-            const BodyPrep P = fprep[b];
-            RxGeo g = rx_geo<double, Kinds::Cylinders>(P, R3);
-            // paths in (ell, side) order, reflection last; one visibility
-            // call site (legs in a loop) keeps the traversal code single
-#pragma unroll 1
-            for (int bit = 0; bit <= kBitRefl; ++bit) {
-                const bool refl = bit == kBitRefl;
-                if (!refl && bit >= 2 * (L.l_enc + 1)) continue;
-                if (refl && !L.lit_branch) continue;
-                PathPts pts;
-                bool ok;
-                if (refl) {
-                    double th = 0.0;
-                    ok = refl_angle<Kinds::Cylinders>(P, g, R3, T, &th);
-                    if (ok) {
-                        d3 Q, n3;
-                        refl_point<double, Kinds::Cylinders>(P, g, R3, T, th, &Q, &n3);
-                        pts.P0 = T; pts.P1 = Q; pts.P2 = Q; pts.P3 = R3;
-                    }
-                } else {
-                    const int ell = bit >> 1, sgn = (bit & 1) ? -1 : 1;
-                    ok = cyl_creep<R, double>(P, g, R3, T, L, sgn, ell, (PathEval<R>*)nullptr, &pts);
-                }
-#pragma unroll 1
-                for (int leg = 0; leg < 2 && ok; ++leg) {
-                    d3 a = leg ? pts.P2 : pts.P0, c = leg ? pts.P3 : pts.P1;
-                    ok = !seg_blocked(a, c, L, nullptr, fcyl, b, bo_, nodes, tris, stk, stride);
-                }
-                if (ok) list[(n++) * stride] = (uint16_t)((b << 3) | bit);
-            }
-        }
-    }
-    if (fl_out) *fl_out = fl;
-}
+// One work item = one frame's tile of TILE receivers (one lane each).  Its
+// bodies are taken in groups of kBGroup; per group:
+//   1. candidates: per body, every lane decides which of its receiver's paths
+//      exist (geometry and, for the reflection, the FP64 point solve) and
+//      pushes one key per candidate into an LDS queue (receiver lane, body in
+//      group, path bit); reflection angles go to the work item's scratch;
+//   2. visibility: whenever another body's candidates might not fit, and after
+//      the last body, all lanes drain the queue, one candidate each (legs
+//      against the frame's other bodies and the BVH), and set visible bits
+//      in the group's LDS masks -- so the traversal runs with every lane busy
+//      however sparse the valid paths are;
+//   3. field: every lane evaluates its receiver's visible paths of the group,
+//      bodies and paths in order, at every frequency, adding to E in place.
+constexpr int kBGroup = 32;
 
 template <typename R, int TILE>
 __global__ void __launch_bounds__(TILE) k_batch(BatchParams B, const float* __restrict__ rx,
@@ -272,17 +137,28 @@ __global__ void __launch_bounds__(TILE) k_batch(BatchParams B, const float* __re
                                                 const FreqConst* __restrict__ fcs, const int64_t* __restrict__ bo,
                                                 const int64_t* __restrict__ ro, const int64_t* __restrict__ tile_off,
                                                 unsigned* __restrict__ counter, const float4* __restrict__ nodes,
-                                                const float4* __restrict__ tris, R* __restrict__ E_out,
-                                                uint8_t* __restrict__ flags) {
+                                                const float4* __restrict__ tris, double* __restrict__ th_scratch,
+                                                R* __restrict__ E_out, uint8_t* __restrict__ flags) {
+    static_assert(TILE <= 256, "lane index is stored in 8 bits");
+    constexpr int QCAP = 8 * TILE;
     __shared__ int stack[kStackDepth * TILE];
-    __shared__ uint16_t s_list[kListCap * TILE];
+    __shared__ unsigned int s_mask[kBGroup * TILE / 4];   // bytes [body in group][lane]
+    __shared__ uint32_t s_q[QCAP];
+    __shared__ int s_qn;
     __shared__ R s_reg[TableStage<R>::NREG];
     __shared__ R s_tf[TableStage<R>::NTF];
     __shared__ int64_t s_tile;
     Tabs<R> tb = TableStage<R>::stage(s_reg, s_tf);
+    uint8_t* mask8 = reinterpret_cast<uint8_t*>(s_mask);
+    double* thb = th_scratch + (int64_t)blockIdx.x * kBGroup * TILE;
+    int* stk = stack + threadIdx.x;
+    const int tid = threadIdx.x;
+    const int n_creep = 2 * (B.L.l_enc + 1);
+    const int per_pair = n_creep + 1;
     const int64_t total = tile_off[B.n_frames];
+    const d3 T = mk(B.L.T[0], B.L.T[1], B.L.T[2]);
     for (;;) {
-        if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(counter, 1u);
+        if (tid == 0) s_tile = (int64_t)atomicAdd(counter, 1u);
         __syncthreads();
         // the tile index is workgroup-uniform: keep it (and everything derived
         // from it: frame, offsets, body constants) in scalar registers
@@ -297,19 +173,175 @@ __global__ void __launch_bounds__(TILE) k_batch(BatchParams B, const float* __re
         }
         const int64_t fr = lo;
         const int64_t r0 = ro[fr], r1 = ro[fr + 1];
-        const int64_t li = (t - tile_off[fr]) * TILE + threadIdx.x;
-        if (r0 + li < r1) {
-            const int64_t i = r0 + li;
-            const int64_t b0 = bo[fr];
-            LaunchParams L = B.L;
-            L.n_sph = 0;
-            L.n_cyl = (int)(bo[fr + 1] - b0);
-            L.n_rx = r1 - r0;
-            d3 R3 = mk(rx[3 * i], rx[3 * i + 1], rx[3 * i + 2]);
-            R* E = E_out + 2 * 3 * (int64_t)B.L.n_f * r0;
-            batch_lane<R>(L, R3, li, cyl + 5 * b0, prep + b0, fcs, tb, nodes, tris, stack + threadIdx.x,
-                          s_list + threadIdx.x, TILE, E, flags ? flags + i : nullptr);
+        const int64_t lbase = (t - tile_off[fr]) * TILE;      // first receiver of the tile (in the frame)
+        const int64_t li = lbase + tid;
+        const bool act = r0 + li < r1;
+        const int64_t b0 = bo[fr];
+        LaunchParams L = B.L;
+        L.n_sph = 0;
+        L.n_cyl = (int)(bo[fr + 1] - b0);
+        L.n_rx = r1 - r0;
+        const int nbf = L.n_cyl;
+        const float* fcyl = cyl + 5 * b0;
+        const BodyPrep* fprep = prep + b0;
+        R* E = E_out + 2 * 3 * (int64_t)B.L.n_f * r0;
+        const int64_t i = r0 + li;
+        const d3 R3 = act ? mk(rx[3 * i], rx[3 * i + 1], rx[3 * i + 2]) : mk(0.0, 0.0, 0.0);
+
+        // --- flags, direct ray, E initialisation ---------------------------
+        bool dead = true;
+        uint8_t fl = 0;
+        if (act) {
+            bool inside = false, tx_inside = false;
+            for (int b = 0; b < nbf; ++b) {
+                inside |= inside_body(fprep[b], R3);
+                tx_inside |= inside_body(fprep[b], T);
+            }
+            fl = (uint8_t)((tx_inside ? kFlagTxInside : 0) | (inside ? kFlagInside : 0));
+            dead = inside || tx_inside;
+            const bool los = !dead && !seg_blocked(T, R3, L, nullptr, fcyl, -1, true, nodes, tris, stk, TILE);
+            if (los) fl |= kFlagLos;
+            R e3[3] = {(R)0, (R)0, (R)0};
+            double sd = 0.0;
+            const bool use_los = los && L.lit_branch;
+            if (use_los) {
+                d3 v = mk(R3.x - T.x, R3.y - T.y, R3.z - T.z);
+                sd = norm(v);
+                R isd = (R)(1.0 / sd);
+                R shx = (R)v.x * isd, shy = (R)v.y * isd, shz = (R)v.z * isd;
+                R px = (R)L.p[0], py = (R)L.p[1], pz = (R)L.p[2];
+                R pd = px * shx + py * shy + pz * shz;
+                R A = (R)L.amp * isd;
+                e3[0] = A * (px - pd * shx); e3[1] = A * (py - pd * shy); e3[2] = A * (pz - pd * shz);
+            }
+#pragma unroll 1
+            for (int j = 0; j < L.n_f; ++j) {
+                cplx<R> ph{(R)0, (R)0};
+                if (use_los) ph = phase_rev<R>(fcs[j].rev_per_m * sd);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    int64_t o = ((int64_t)j * 3 + c) * L.n_rx + li;
+                    E[2 * o] = (R)0 + e3[c] * ph.re;
+                    E[2 * o + 1] = (R)0 + e3[c] * ph.im;
+                }
+            }
         }
+
+        for (int g0 = 0; g0 < nbf; g0 += kBGroup) {
+            const int ng = nbf - g0 < kBGroup ? nbf - g0 : kBGroup;
+            for (int k = tid; k < kBGroup * TILE / 4; k += TILE) s_mask[k] = 0u;
+            if (tid == 0) s_qn = 0;
+            __syncthreads();
+            for (int bl = 0; bl < ng; ++bl) {
+                // --- 1. candidates of (receiver, body g0 + bl) --------------
+                if (act && !dead) {
+                    const BodyPrep P = fprep[g0 + bl];
+                    RxGeo g = rx_geo<double, Kinds::Cylinders>(P, R3);
+                    uint32_t cand = 0;
+                    for (int bit = 0; bit < n_creep; ++bit) {
+                        PathPts pts;
+                        if (cyl_creep<R, double>(P, g, R3, T, L, (bit & 1) ? -1 : 1, bit >> 1, (PathEval<R>*)nullptr,
+                                                 &pts))
+                            cand |= 1u << bit;
+                    }
+                    double th;
+                    if (L.lit_branch && refl_angle<Kinds::Cylinders>(P, g, R3, T, &th)) {
+                        cand |= 1u << kBitRefl;
+                        thb[bl * TILE + tid] = th;
+                    }
+                    if (cand) {
+                        int q = atomicAdd(&s_qn, __builtin_popcount(cand));
+                        for (int bit = 0; bit <= kBitRefl; ++bit)
+                            if ((cand >> bit) & 1u) s_q[q++] = (uint32_t)tid | ((uint32_t)bl << 8) | ((uint32_t)bit << 13);
+                    }
+                }
+                __syncthreads();
+                // --- 2. drain the queue when the next body might not fit ---
+                const int qn = s_qn;
+                if (qn > QCAP - TILE * per_pair || bl == ng - 1) {
+                    for (int k = tid; k < qn; k += TILE) {
+                        const uint32_t key = s_q[k];
+                        const int lane = (int)(key & 0xffu), blk = (int)((key >> 8) & 0x1fu), bit = (int)(key >> 13);
+                        const int64_t i2 = r0 + lbase + lane;
+                        const d3 R2 = mk(rx[3 * i2], rx[3 * i2 + 1], rx[3 * i2 + 2]);
+                        const int b = g0 + blk;
+                        const BodyPrep P = fprep[b];
+                        RxGeo g = rx_geo<double, Kinds::Cylinders>(P, R2);
+                        PathPts pts;
+                        if (bit == kBitRefl) {
+                            d3 Q, n3;
+                            refl_point<double, Kinds::Cylinders>(P, g, R2, T, thb[blk * TILE + lane], &Q, &n3);
+                            pts.P0 = T; pts.P1 = Q; pts.P2 = Q; pts.P3 = R2;
+                        } else {
+                            cyl_creep<R, double>(P, g, R2, T, L, (bit & 1) ? -1 : 1, bit >> 1, (PathEval<R>*)nullptr,
+                                                 &pts);
+                        }
+                        bool vis = true;
+#pragma unroll 1
+                        for (int leg = 0; leg < 2 && vis; ++leg) {
+                            d3 a = leg ? pts.P2 : pts.P0, c = leg ? pts.P3 : pts.P1;
+                            vis = !seg_blocked(a, c, L, nullptr, fcyl, b, L.bodies_occlude != 0, nodes, tris, stk,
+                                               TILE);
+                        }
+                        if (vis) {
+                            const int mb = blk * TILE + lane;
+                            atomicOr(&s_mask[mb >> 2], (1u << bit) << (8 * (mb & 3)));
+                        }
+                    }
+                    __syncthreads();
+                    if (tid == 0) s_qn = 0;
+                    __syncthreads();
+                }
+            }
+            // --- 3. field of this group's visible paths ---------------------
+            if (act && !dead) {
+                for (int bl = 0; bl < ng; ++bl) {
+                    const uint32_t m = mask8[bl * TILE + tid];
+                    if (!m) continue;
+                    const BodyPrep P = fprep[g0 + bl];
+                    RxGeo g = rx_geo<double, Kinds::Cylinders>(P, R3);
+                    for (int bit = 0; bit <= kBitRefl; ++bit) {
+                        if (!((m >> bit) & 1u)) continue;
+                        PathEval<R> pe;
+                        if (bit == kBitRefl) {
+                            d3 Q, n3;
+                            refl_point<double, Kinds::Cylinders>(P, g, R3, T, thb[bl * TILE + tid], &Q, &n3);
+                            refl_eval<R, double>(P, Q, n3, R3, T, L, &pe);
+                        } else {
+                            cyl_creep<R, double>(P, g, R3, T, L, (bit & 1) ? -1 : 1, bit >> 1, &pe, nullptr);
+                        }
+                        // wave-uniform choice of the Fock specialisation
+                        const bool any_refl = __any(pe.refl != 0), any_creep = __any(pe.refl == 0);
+                        const int mode = !any_refl ? kCreep : (!any_creep ? kRefl : kAny);
+#pragma unroll 1
+                        for (int j = 0; j < L.n_f; ++j) {
+                            R e[6];
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) {
+                                int64_t o = ((int64_t)j * 3 + c) * L.n_rx + li;
+                                e[2 * c] = E[2 * o];
+                                e[2 * c + 1] = E[2 * o + 1];
+                            }
+                            FreqC<R> fc(fcs[j]);
+                            if (mode == kCreep)
+                                add_path<R, kCreep>(pe, tb, fc, e);
+                            else if (mode == kRefl)
+                                add_path<R, kRefl>(pe, tb, fc, e);
+                            else
+                                add_path<R, kAny>(pe, tb, fc, e);
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) {
+                                int64_t o = ((int64_t)j * 3 + c) * L.n_rx + li;
+                                E[2 * o] = e[2 * c];
+                                E[2 * o + 1] = e[2 * c + 1];
+                            }
+                        }
+                    }
+                }
+            }
+            __syncthreads();      // masks, queue and angle scratch are reused by the next group
+        }
+        if (act && flags) flags[i] = fl;
     }
 }
 
@@ -318,17 +350,19 @@ template <typename R, int TILE>
 static hipError_t launch_batch_tile(const BatchParams& B, int n_blocks, const float* rx, const float* cyl,
                                     const BodyPrep* prep, const FreqConst* fcs, const int64_t* bo, const int64_t* ro,
                                     const int64_t* tile_off, unsigned* counter, const float4* nodes,
-                                    const float4* tris, void* E, uint8_t* flags, hipStream_t s) {
+                                    const float4* tris, double* th, void* E, uint8_t* flags, hipStream_t s) {
     hipLaunchKernelGGL((k_batch<R, TILE>), dim3(n_blocks), dim3(TILE), 0, s, B, rx, cyl, prep, fcs, bo, ro, tile_off,
-                       counter, nodes, tris, (R*)E, flags);
+                       counter, nodes, tris, th, (R*)E, flags);
     return hipGetLastError();
 }
+
+size_t batch_scratch_bytes(int n_blocks) { return sizeof(double) * (size_t)n_blocks * kBGroup * 256; }
 
 hipError_t launch_batch(const BatchParams& B, int precision, int n_blocks, const int64_t* body_off,
                         const int64_t* rx_off, const float* rx, const float* cyl, const double* freqs,
                         BodyPrep* prep, FreqConst* fcs, int64_t* bo, int64_t* ro, int64_t* tile_off,
-                        unsigned* counter, const float4* nodes, const float4* tris, void* E, uint8_t* flags,
-                        hipStream_t s) {
+                        unsigned* counter, const float4* nodes, const float4* tris, double* th, void* E,
+                        uint8_t* flags, hipStream_t s) {
     int64_t nwork = B.n_cyl > B.L.n_f ? B.n_cyl : B.L.n_f;
     int pb = (int)((nwork + 1023) / 1024);
     pb = pb < 1 ? 1 : (pb > 1024 ? 1024 : pb);
@@ -339,20 +373,20 @@ hipError_t launch_batch(const BatchParams& B, int precision, int n_blocks, const
     if (precision == 0) {
         switch (B.tile) {
             case 64: return launch_batch_tile<float, 64>(B, n_blocks, rx, cyl, prep, fcs, bo, ro, tile_off, counter,
-                                                         nodes, tris, E, flags, s);
+                                                         nodes, tris, th, E, flags, s);
             case 128: return launch_batch_tile<float, 128>(B, n_blocks, rx, cyl, prep, fcs, bo, ro, tile_off,
-                                                           counter, nodes, tris, E, flags, s);
+                                                           counter, nodes, tris, th, E, flags, s);
             default: return launch_batch_tile<float, 256>(B, n_blocks, rx, cyl, prep, fcs, bo, ro, tile_off,
-                                                          counter, nodes, tris, E, flags, s);
+                                                          counter, nodes, tris, th, E, flags, s);
         }
     }
     switch (B.tile) {
         case 64: return launch_batch_tile<double, 64>(B, n_blocks, rx, cyl, prep, fcs, bo, ro, tile_off, counter,
-                                                      nodes, tris, E, flags, s);
+                                                      nodes, tris, th, E, flags, s);
         case 128: return launch_batch_tile<double, 128>(B, n_blocks, rx, cyl, prep, fcs, bo, ro, tile_off, counter,
-                                                        nodes, tris, E, flags, s);
+                                                        nodes, tris, th, E, flags, s);
         default: return launch_batch_tile<double, 256>(B, n_blocks, rx, cyl, prep, fcs, bo, ro, tile_off, counter,
-                                                       nodes, tris, E, flags, s);
+                                                       nodes, tris, th, E, flags, s);
     }
 }
 

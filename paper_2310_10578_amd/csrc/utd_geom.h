@@ -347,11 +347,11 @@ __device__ __forceinline__ G alhazen_fun(G a, G p1x, G p1y, G p2x, G p2y, G th, 
     gsincos(th, &s, &c);
     G qx = a * c, qy = a * s;
     G d1x = qx - p1x, d1y = qy - p1y, d2x = qx - p2x, d2y = qy - p2y;
-    G l1 = gsqrt(d1x * d1x + d1y * d1y), l2 = gsqrt(d2x * d2x + d2y * d2y);
-    G t1 = -d1x * s + d1y * c, t2 = -d2x * s + d2y * c;      // (Q-P).t
-    G n1 = d1x * c + d1y * s, n2 = d2x * c + d2y * s;        // (Q-P).n
-    *dg = (a - n1) / l1 - a * t1 * t1 / (l1 * l1 * l1) + (a - n2) / l2 - a * t2 * t2 / (l2 * l2 * l2);
-    return t1 / l1 + t2 / l2;
+    G i1 = G(1.0) / gsqrt(d1x * d1x + d1y * d1y), i2 = G(1.0) / gsqrt(d2x * d2x + d2y * d2y);   // 1/|Q - P|
+    G t1 = (-d1x * s + d1y * c) * i1, t2 = (-d2x * s + d2y * c) * i2;   // unit (Q-P).t
+    G n1 = d1x * c + d1y * s, n2 = d2x * c + d2y * s;                  // (Q-P).n
+    *dg = ((a - n1) - a * t1 * t1) * i1 + ((a - n2) - a * t2 * t2) * i2;
+    return t1 + t2;
 }
 
 // Safeguarded Newton in FP64 (bisection step whenever Newton leaves the

@@ -18,11 +18,15 @@ struct BatchParams {
     int64_t n_rx;            // receivers in the array (bound for rx_off)
     int tile;                // receivers per work item (= blockDim.x)
 };
-// Visibility pass; also stores the body constants (prep) and, when freqs is
-// not NULL, the frequency constants (fcs) for the later kernels of the call.
+// Visibility (two passes through a queue of candidate paths); also stores
+// the body constants (prep) and, when freqs is not NULL, the frequency
+// constants (fcs) for the later kernels of the call.  Record slots per
+// (receiver, body): 2 (l_enc + 1) + 1.  Queue capacity cap entries
+// (n_rx (1 + n_bodies (2 l_enc + 3)) always suffices).
 hipError_t launch_paths(const LaunchParams& L, int precision, const float* rx, const float* sph, const float* cyl,
                         const double* freqs, BodyPrep* prep, FreqConst* fcs, const float4* nodes, const float4* tris,
-                        uint8_t* mask, void* rec, uint8_t* flags, hipStream_t s);
+                        uint8_t* mask, void* rec, uint8_t* flags, uint64_t* ent, double* ent_th,
+                        unsigned long long* counter, int64_t cap, hipStream_t s);
 size_t path_record_bytes(int precision);
 hipError_t launch_field(const LaunchParams& L, int precision, int fc, const float* rx, const FreqConst* fcs,
                         const uint8_t* mask, const void* rec, uint8_t* flags, void* E, hipStream_t s);
@@ -34,11 +38,12 @@ hipError_t launch_adjoint(const LaunchParams& L, int precision, const float* rx,
                           const uint8_t* flags, const void* gE, char* scratch, void* d_sph, void* d_cyl, void* d_tx,
                           hipStream_t s);
 
+size_t batch_scratch_bytes(int n_blocks);
 hipError_t launch_batch(const BatchParams& B, int precision, int n_blocks, const int64_t* body_off,
                         const int64_t* rx_off, const float* rx, const float* cyl, const double* freqs,
                         BodyPrep* prep, FreqConst* fcs, int64_t* bo, int64_t* ro, int64_t* tile_off,
-                        unsigned* counter, const float4* nodes, const float4* tris, void* E, uint8_t* flags,
-                        hipStream_t s);
+                        unsigned* counter, const float4* nodes, const float4* tris, double* th, void* E,
+                        uint8_t* flags, hipStream_t s);
 
 hipError_t launch_census(int64_t n_mask, const uint8_t* mask, int64_t n_rx, const uint8_t* flags,
                          unsigned long long* counts, hipStream_t s);

@@ -123,13 +123,231 @@ __device__ __forceinline__ void unpack(const PathRec<double>& o, PathEval<double
     p->vh[0] = o.v[8]; p->vh[1] = o.v[9]; p->vh[2] = o.v[10];
 }
 
-// Visibility and path constants.  grid: x over receivers (blockDim 256),
-// y over slot = 0 (receiver flags) or 1 + body.  mask[body][rx] gets the path
-// bits, flags[rx] the slot-0 bits, rec the constants of each valid path in
-// set-bit order.
-// The body constants of slot b are computed by every block of the slot (a
-// few FP64 operations); the x = 0 block also stores them, and the (0, 0)
-// block the frequency constants, for the later kernels of the call.
+// Record slots per (receiver, body): one per possible path, creeping paths at
+// their mask bit 2 ell + side, the reflection after them.
+__device__ __forceinline__ int rec_slots(const LaunchParams& L) { return 2 * (L.l_enc + 1) + 1; }
+__device__ __forceinline__ int rec_slot(const LaunchParams& L, int bit) {
+    return bit == kBitRefl ? 2 * (L.l_enc + 1) : bit;
+}
+
+// ---------------------------------------------------------------------------
+// Visibility in two passes.  Geometric validity is cheap and decided per
+// (receiver, body) lane, but only a fraction of the pairs have valid paths
+// (in a room with the source above the cylinder tops most helices leave the
+// lateral surface), so the BVH traversal, the expensive part, runs over a
+// compacted queue of candidate paths with every lane busy:
+//   k_cand  one lane per (receiver, body) pair (slot 0: the receiver's flags
+//           and its direct ray): classification, path existence, reflection
+//           point; appends one queue entry per candidate path (wave-level
+//           prefix sum, one atomic per wavefront).
+//   k_vis   one lane per queue entry: the path's legs against the other
+//           bodies and the BVH; a visible path sets its mask bit and writes
+//           its record.
+// The queue order varies between runs; the outputs (mask bits, records,
+// flags) do not.
+// ---------------------------------------------------------------------------
+constexpr uint64_t kLosEntry = 0xffffull;   // body field of a direct-ray entry
+
+__device__ __forceinline__ uint64_t make_entry(int64_t i, int64_t b, int bit) {
+    return (uint64_t)i | ((uint64_t)b << 32) | ((uint64_t)bit << 48);
+}
+
+// Exclusive prefix of cnt over the wavefront plus one atomic per wavefront;
+// every lane of the wavefront must call it.
+__device__ __forceinline__ int64_t wave_append(int cnt, unsigned long long* counter) {
+    const int lane = threadIdx.x & 63;
+    int x = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    const int total = __shfl(x, 63, 64);
+    unsigned long long base = 0;
+    if (lane == 63 && total > 0) base = atomicAdd(counter, (unsigned long long)total);
+    base = __shfl(base, 63, 64);
+    return (int64_t)base + x - cnt;
+}
+
+__global__ void k_zero_counter(unsigned long long* counter) { *counter = 0ull; }
+
+// Pass 1.  grid: x over receivers (blockDim 256), y over slot = 0 (receiver
+// flags, direct ray) or 1 + body.  Body constants of slot b are computed by
+// every block of the slot (the x = 0 block stores them); the (0, 0) block
+// stores the frequency constants.
+template <typename R>
+__global__ void __launch_bounds__(256) k_cand(LaunchParams L, const float* __restrict__ rx,
+                                              const float* __restrict__ sph, const float* __restrict__ cyl,
+                                              const double* __restrict__ freqs, BodyPrep* __restrict__ prep,
+                                              FreqConst* __restrict__ fcs, uint8_t* __restrict__ mask,
+                                              uint8_t* __restrict__ flags, uint64_t* __restrict__ ent,
+                                              double* __restrict__ ent_th, unsigned long long* __restrict__ counter,
+                                              int64_t cap) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int slot = blockIdx.y;
+    if (slot == 0 && blockIdx.x == 0 && freqs)
+        for (int f = threadIdx.x; f < L.n_f; f += blockDim.x) fcs[f] = freq_const(freqs[f]);
+    const bool act = i < L.n_rx;
+    const d3 R3 = act ? mk(rx[3 * i], rx[3 * i + 1], rx[3 * i + 2]) : mk(0.0, 0.0, 0.0);
+    const d3 T = mk(L.T[0], L.T[1], L.T[2]);
+    const int nb = L.n_sph + L.n_cyl;
+    uint8_t cand = 0;            // candidate bits (creeping 2 ell + side, reflection kBitRefl)
+    bool los_cand = false;
+    double th = 0.0;
+    int b = slot - 1;
+    if (slot == 0) {
+        if (act) {
+            bool inside = false, tx_inside = false;
+            for (int k = 0; k < nb; ++k) {
+                inside |= inside_raw(L, sph, cyl, k, R3);
+                tx_inside |= inside_raw(L, sph, cyl, k, T);
+            }
+            flags[i] = (uint8_t)((tx_inside ? kFlagTxInside : 0) | (inside ? kFlagInside : 0));
+            los_cand = !inside && !tx_inside;
+        }
+    } else {
+        const BodyPrep P = body_prep(L.T, sph, L.n_sph, cyl, b);
+        if (blockIdx.x == 0 && threadIdx.x == 0) prep[b] = P;
+        if (act) {
+            RxGeo g = rx_geo(P, R3);
+            uint8_t m = 0;
+            for (int ell = 0; ell <= L.l_enc; ++ell) {
+                for (int side = 0; side < 2; ++side) {
+                    const int sgn = side == 0 ? 1 : -1;
+                    PathPts pts;
+                    bool ok, caus = false;
+                    if (P.kind == 0)
+                        ok = sphere_creep<R, double>(P, g, R3, T, L, sgn, ell, &caus, (PathEval<R>*)nullptr, &pts);
+                    else
+                        ok = cyl_creep<R, double>(P, g, R3, T, L, sgn, ell, (PathEval<R>*)nullptr, &pts);
+                    if (caus) m |= (uint8_t)(1u << kBitCaustic);
+                    if (ok) cand |= (uint8_t)(1u << (2 * ell + side));
+                }
+            }
+            if (L.lit_branch && refl_angle(P, g, R3, T, &th)) cand |= (uint8_t)(1u << kBitRefl);
+            mask[(int64_t)b * L.n_rx + i] = m;     // visible bits are added by k_vis
+        }
+    }
+    const int cnt = (los_cand ? 1 : 0) + __builtin_popcount(cand);
+    int64_t q = wave_append(cnt, counter);
+    if (los_cand && q < cap) {
+        ent[q] = make_entry(i, kLosEntry, 0);
+        ent_th[q] = 0.0;
+        ++q;
+    }
+    for (int bit = 0; bit <= kBitRefl; ++bit) {
+        if (!((cand >> bit) & 1u)) continue;
+        if (q < cap) {
+            ent[q] = make_entry(i, b, bit);
+            ent_th[q] = bit == kBitRefl ? th : 0.0;
+        }
+        ++q;
+    }
+}
+
+// Pass 2: one lane per queue entry (grid-stride).
+template <typename R>
+__device__ __forceinline__ void vis_body(const LaunchParams& L, const float* __restrict__ rx,
+                                         const float* __restrict__ sph, const float* __restrict__ cyl,
+                                         const BodyPrep* __restrict__ prep, const float4* __restrict__ nodes,
+                                         const float4* __restrict__ tris, const uint64_t* __restrict__ ent,
+                                         const double* __restrict__ ent_th,
+                                         const unsigned long long* __restrict__ counter, int64_t cap,
+                                         uint8_t* __restrict__ mask, uint8_t* __restrict__ flags,
+                                         PathRec<R>* __restrict__ rec, int* stack) {
+    int* stk = stack + threadIdx.x;
+    const int stride = 256;
+    int64_t total = (int64_t)*counter;
+    total = total < cap ? total : cap;
+    const d3 T = mk(L.T[0], L.T[1], L.T[2]);
+    const bool bo = L.bodies_occlude != 0;
+    const int NS = rec_slots(L);
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t en = ent[q];
+        const int64_t i = (int64_t)(en & 0xffffffffu);
+        const int64_t bb = (int64_t)((en >> 32) & 0xffffu);
+        const int bit = (int)(en >> 48);
+        const d3 R3 = mk(rx[3 * i], rx[3 * i + 1], rx[3 * i + 2]);
+        if (bb == (int64_t)kLosEntry) {
+            // the receiver's only entry of this kind: a plain byte update
+            if (!seg_blocked(T, R3, L, sph, cyl, -1, true, nodes, tris, stk, stride))
+                flags[i] = (uint8_t)(flags[i] | kFlagLos);
+            continue;
+        }
+        const int b = (int)bb;
+        const BodyPrep P = prep[b];
+        RxGeo g = rx_geo(P, R3);
+        const bool refl = bit == kBitRefl;
+        const int ell = bit >> 1, sgn = (bit & 1) ? -1 : 1;
+        PathPts pts;
+        d3 Q, n;
+        const double th = ent_th[q];
+        if (refl) {
+            refl_point<double>(P, g, R3, T, th, &Q, &n);
+            pts.P0 = T; pts.P1 = Q; pts.P2 = Q; pts.P3 = R3;
+        } else {
+            bool cz;
+            if (P.kind == 0)
+                sphere_creep<R, double>(P, g, R3, T, L, sgn, ell, &cz, (PathEval<R>*)nullptr, &pts);
+            else
+                cyl_creep<R, double>(P, g, R3, T, L, sgn, ell, (PathEval<R>*)nullptr, &pts);
+        }
+        bool vis = true;
+#pragma unroll 1
+        for (int leg = 0; leg < 2 && vis; ++leg) {
+            d3 a = leg ? pts.P2 : pts.P0, c = leg ? pts.P3 : pts.P1;
+            vis = !seg_blocked(a, c, L, sph, cyl, b, bo, nodes, tris, stk, stride);
+        }
+        if (!vis) continue;
+        // mask bytes of one pair can be set by concurrent lanes: OR into the word
+        const int64_t mb = (int64_t)b * L.n_rx + i;
+        atomicOr(reinterpret_cast<unsigned int*>(mask + (mb & ~(int64_t)3)), (1u << bit) << (8 * (mb & 3)));
+        PathEval<R> pe;
+        if (refl) {
+            refl_eval<R, double>(P, Q, n, R3, T, L, &pe);
+        } else {
+            bool cz;
+            if (P.kind == 0)
+                sphere_creep<R, double>(P, g, R3, T, L, sgn, ell, &cz, &pe, nullptr);
+            else
+                cyl_creep<R, double>(P, g, R3, T, L, sgn, ell, &pe, nullptr);
+        }
+        pack(pe, &rec[((int64_t)b * NS + rec_slot(L, bit)) * L.n_rx + i]);
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_vis(LaunchParams L, const float* __restrict__ rx,
+                                             const float* __restrict__ sph, const float* __restrict__ cyl,
+                                             const BodyPrep* __restrict__ prep, const float4* __restrict__ nodes,
+                                             const float4* __restrict__ tris, const uint64_t* __restrict__ ent,
+                                             const double* __restrict__ ent_th,
+                                             const unsigned long long* __restrict__ counter, int64_t cap,
+                                             uint8_t* __restrict__ mask, uint8_t* __restrict__ flags,
+                                             PathRec<R>* __restrict__ rec) {
+    __shared__ int stack[kStackDepth * 256];
+    vis_body<R>(L, rx, sph, cyl, prep, nodes, tris, ent, ent_th, counter, cap, mask, flags, rec, stack);
+}
+
+// Three waves per SIMD (168 VGPRs, a few spills) for long queues: more
+// traversals in flight hide more of their memory latency.
+template <typename R>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
+k_vis_occ3(LaunchParams L, const float* __restrict__ rx, const float* __restrict__ sph, const float* __restrict__ cyl,
+           const BodyPrep* __restrict__ prep, const float4* __restrict__ nodes, const float4* __restrict__ tris,
+           const uint64_t* __restrict__ ent, const double* __restrict__ ent_th,
+           const unsigned long long* __restrict__ counter, int64_t cap, uint8_t* __restrict__ mask,
+           uint8_t* __restrict__ flags, PathRec<R>* __restrict__ rec) {
+    __shared__ int stack[kStackDepth * 256];
+    vis_body<R>(L, rx, sph, cyl, prep, nodes, tris, ent, ent_th, counter, cap, mask, flags, rec, stack);
+}
+
+// Single-pass visibility for scenes without triangles (bodies only): the
+// per-pair work is short and uniform there, so one lane per (receiver, body)
+// pair decides and records everything without a queue.  grid: x over
+// receivers (blockDim 256), y over slot = 0 (receiver flags) or 1 + body;
+// same outputs as k_cand + k_vis.
 template <typename R>
 __device__ __forceinline__ void paths_body(const LaunchParams& L, const float* __restrict__ rx,
                                            const float* __restrict__ sph, const float* __restrict__ cyl,
@@ -166,8 +384,7 @@ __device__ __forceinline__ void paths_body(const LaunchParams& L, const float* _
     if (blockIdx.x == 0 && threadIdx.x == 0) prep[b] = P;
     RxGeo g = rx_geo(P, R3);
     uint8_t m = 0;
-    int nrec = 0;
-    const int S = 2 * (L.l_enc + 1);
+    const int NS = rec_slots(L);
     bool bo = L.bodies_occlude != 0;
     for (int ell = 0; ell <= L.l_enc; ++ell) {
         for (int side = 0; side < 2; ++side) {
@@ -189,8 +406,7 @@ __device__ __forceinline__ void paths_body(const LaunchParams& L, const float* _
                 sphere_creep<R, double>(P, g, R3, T, L, sgn, ell, &cz, &pe, nullptr);
             else
                 cyl_creep<R, double>(P, g, R3, T, L, sgn, ell, &pe, nullptr);
-            if (nrec < S) pack(pe, &rec[((int64_t)b * S + nrec) * L.n_rx + i]);
-            ++nrec;
+            pack(pe, &rec[((int64_t)b * NS + rec_slot(L, 2 * ell + side)) * L.n_rx + i]);
         }
     }
     double th = 0.0;
@@ -202,16 +418,12 @@ __device__ __forceinline__ void paths_body(const LaunchParams& L, const float* _
             m |= (uint8_t)(1u << kBitRefl);
             PathEval<R> pe;
             refl_eval<R, double>(P, Q, n, R3, T, L, &pe);
-            pack(pe, &rec[((int64_t)b * S + (S - 1)) * L.n_rx + i]);
+            pack(pe, &rec[((int64_t)b * NS + rec_slot(L, kBitRefl)) * L.n_rx + i]);
         }
     }
     mask[(int64_t)b * L.n_rx + i] = m;
 }
 
-// Two register budgets of the same pass: the default (no spills, two waves
-// per SIMD) for grids that do not fill the chip at that occupancy, and three
-// waves per SIMD (168 VGPRs, a few spills), which hides more traversal
-// latency on large grids (measured -20% on the room workloads).
 template <typename R>
 __global__ void __launch_bounds__(256) k_paths(LaunchParams L, const float* __restrict__ rx,
                                                const float* __restrict__ sph, const float* __restrict__ cyl,
@@ -219,16 +431,6 @@ __global__ void __launch_bounds__(256) k_paths(LaunchParams L, const float* __re
                                                FreqConst* __restrict__ fcs, const float4* __restrict__ nodes,
                                                const float4* __restrict__ tris, uint8_t* __restrict__ mask,
                                                PathRec<R>* __restrict__ rec, uint8_t* __restrict__ flags) {
-    __shared__ int stack[kStackDepth * 256];
-    paths_body<R>(L, rx, sph, cyl, freqs, prep, fcs, nodes, tris, mask, rec, flags, stack);
-}
-
-template <typename R>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
-k_paths_occ3(LaunchParams L, const float* __restrict__ rx, const float* __restrict__ sph,
-             const float* __restrict__ cyl, const double* __restrict__ freqs, BodyPrep* __restrict__ prep,
-             FreqConst* __restrict__ fcs, const float4* __restrict__ nodes, const float4* __restrict__ tris,
-             uint8_t* __restrict__ mask, PathRec<R>* __restrict__ rec, uint8_t* __restrict__ flags) {
     __shared__ int stack[kStackDepth * 256];
     paths_body<R>(L, rx, sph, cyl, freqs, prep, fcs, nodes, tris, mask, rec, flags, stack);
 }
@@ -345,7 +547,7 @@ __global__ void __launch_bounds__(256) k_field(LaunchParams L, const float* __re
     if (i >= L.n_rx) return;
     const int f0 = blockIdx.y * FC;
     const int nfc = L.n_f - f0 < FC ? L.n_f - f0 : FC;
-    const int S = 2 * (L.l_enc + 1);
+    const int NS = rec_slots(L);
     R E[FC][6];
 #pragma unroll
     for (int j = 0; j < FC; ++j)
@@ -381,11 +583,13 @@ __global__ void __launch_bounds__(256) k_field(LaunchParams L, const float* __re
             uint8_t m = mask[(int64_t)b * L.n_rx + i];
             caus |= m;
             const bool has_refl = (m >> kBitRefl) & 1u;
-            int n = __builtin_popcount(m & 0x3fu);
-            n = n < (has_refl ? S - 1 : S) ? n : (has_refl ? S - 1 : S);
-            for (int k = 0; k < n; ++k) {
+            // creeping paths in bit order, then the reflection
+            uint32_t cb = m & ((1u << (2 * (L.l_enc + 1))) - 1u);
+            while (cb) {
+                const int k = __builtin_ctz(cb);
+                cb &= cb - 1u;
                 PathEval<R> pe;
-                unpack(rec[((int64_t)b * S + k) * L.n_rx + i], &pe);
+                unpack(rec[((int64_t)b * NS + k) * L.n_rx + i], &pe);
 #pragma unroll
                 for (int j = 0; j < FC; ++j) {
                     if (j < nfc) {
@@ -396,7 +600,7 @@ __global__ void __launch_bounds__(256) k_field(LaunchParams L, const float* __re
             }
             if (__any(has_refl) && has_refl) {
                 PathEval<R> pe;
-                unpack(rec[((int64_t)b * S + (S - 1)) * L.n_rx + i], &pe);
+                unpack(rec[((int64_t)b * NS + rec_slot(L, kBitRefl)) * L.n_rx + i], &pe);
 #pragma unroll
                 for (int j = 0; j < FC; ++j) {
                     if (j < nfc) {
@@ -464,26 +668,42 @@ hipError_t launch_census(int64_t n_mask, const uint8_t* mask, int64_t n_rx, cons
 template <typename R>
 static hipError_t launch_paths_t(const LaunchParams& L, const float* rx, const float* sph, const float* cyl,
                                  const double* freqs, BodyPrep* prep, FreqConst* fcs, const float4* nodes,
-                                 const float4* tris, uint8_t* mask, void* rec, uint8_t* flags, hipStream_t s) {
+                                 const float4* tris, uint8_t* mask, void* rec, uint8_t* flags, uint64_t* ent,
+                                 double* ent_th, unsigned long long* counter, int64_t cap, hipStream_t s) {
     int nb = L.n_sph + L.n_cyl;
+    if (!nodes) {
+        dim3 grid((unsigned)((L.n_rx + 255) / 256), (unsigned)(nb + 1));
+        hipLaunchKernelGGL((k_paths<R>), grid, dim3(256), 0, s, L, rx, sph, cyl, freqs, prep, fcs, nodes, tris, mask,
+                           (PathRec<R>*)rec, flags);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     dim3 grid((unsigned)((L.n_rx + 255) / 256), (unsigned)(nb + 1));
-    // waves of the grid against what 256 CUs hold at two waves per SIMD
-    const int64_t waves = (int64_t)grid.x * grid.y * 4;
-    if (waves > 256 * 4 * 2 * 2)
-        hipLaunchKernelGGL((k_paths_occ3<R>), grid, dim3(256), 0, s, L, rx, sph, cyl, freqs, prep, fcs, nodes, tris,
-                           mask, (PathRec<R>*)rec, flags);
+    hipLaunchKernelGGL((k_cand<R>), grid, dim3(256), 0, s, L, rx, sph, cyl, freqs, prep, fcs, mask, flags, ent, ent_th,
+                       counter, cap);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // persistent grid over the queue: enough workgroups to fill the chip
+    int64_t vgrid = (cap + 255) / 256;
+    vgrid = vgrid < 1 ? 1 : (vgrid > 256 * 12 ? 256 * 12 : vgrid);
+    if (vgrid * 4 > 256 * 4 * 2 * 2)
+        hipLaunchKernelGGL((k_vis_occ3<R>), dim3((unsigned)vgrid), dim3(256), 0, s, L, rx, sph, cyl, prep, nodes,
+                           tris, ent, ent_th, counter, cap, mask, flags, (PathRec<R>*)rec);
     else
-        hipLaunchKernelGGL((k_paths<R>), grid, dim3(256), 0, s, L, rx, sph, cyl, freqs, prep, fcs, nodes, tris,
-                           mask, (PathRec<R>*)rec, flags);
+        hipLaunchKernelGGL((k_vis<R>), dim3((unsigned)vgrid), dim3(256), 0, s, L, rx, sph, cyl, prep, nodes, tris,
+                           ent, ent_th, counter, cap, mask, flags, (PathRec<R>*)rec);
     return hipGetLastError();
 }
 
 hipError_t launch_paths(const LaunchParams& L, int precision, const float* rx, const float* sph, const float* cyl,
                         const double* freqs, BodyPrep* prep, FreqConst* fcs, const float4* nodes, const float4* tris,
-                        uint8_t* mask, void* rec, uint8_t* flags, hipStream_t s) {
-    return precision == 0
-               ? launch_paths_t<float>(L, rx, sph, cyl, freqs, prep, fcs, nodes, tris, mask, rec, flags, s)
-               : launch_paths_t<double>(L, rx, sph, cyl, freqs, prep, fcs, nodes, tris, mask, rec, flags, s);
+                        uint8_t* mask, void* rec, uint8_t* flags, uint64_t* ent, double* ent_th,
+                        unsigned long long* counter, int64_t cap, hipStream_t s) {
+    return precision == 0 ? launch_paths_t<float>(L, rx, sph, cyl, freqs, prep, fcs, nodes, tris, mask, rec, flags,
+                                                  ent, ent_th, counter, cap, s)
+                          : launch_paths_t<double>(L, rx, sph, cyl, freqs, prep, fcs, nodes, tris, mask, rec, flags,
+                                                   ent, ent_th, counter, cap, s);
 }
 
 size_t path_record_bytes(int precision) { return precision == 0 ? sizeof(PathRec<float>) : sizeof(PathRec<double>); }
