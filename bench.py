@@ -22,18 +22,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # FP32 operations per (path, frequency) of the field kernel, counted from its
-# formula set (utd_fock.h / add_path): argument scaling 6, sqrt 1, transition
-# function 39 (locate 6, degree-6 complex Horner 24, combine 9), regime lookup
-# 65 (locate 6, degree-6 soft+hard complex Horner 48, combine 11), phase 30
-# (range reduction and degree-9/8 sin/cos polynomials), coefficient scaling 18,
-# accumulation into 3 complex components 24.  Direct field per (receiver,
-# frequency): 36 (phase 30 + 6 FMA).
-FLOPS_PER_PATH_FREQ = 6 + 1 + 39 + 65 + 30 + 18 + 24
+# formula set for a creeping path (utd_fock.h / add_path): argument scaling 5,
+# transition function 31 (index map and local variable 5, degree-4 complex
+# Horner 16, combine 10), regime lookup 45 (index map 4, degree-4 soft+hard
+# complex Horner 32, combine 9), phase 30 (range reduction and degree-9/8
+# sin/cos polynomials), phase times coefficients 12, accumulation into 3
+# complex components 24.  The per-frequency k^{-1/6} scaling of each
+# receiver's sum is not counted.  Direct field per (receiver, frequency): 36
+# (phase 30 + 6 FMA).
+FLOPS_PER_PATH_FREQ = 5 + 31 + 45 + 30 + 12 + 24
 FLOPS_LOS = 36
 PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (published, packed-FP32 rate)
 
 
-TRAFFIC_PROFILE = {"config2": "profiles/hbm_sphere-plane-64f.md"}
+TRAFFIC_PROFILE = {"config2": "profiles/hbm_sphere-plane-64f.md",
+                   "config3": "profiles/hbm_room-512x512-2f.md"}
 
 
 def kernel_source_digest():

@@ -32,6 +32,15 @@ monomial coefficients for Horner evaluation.  Two sets are emitted: float
 (for the FP32 kernel) and double (for the FP64 kernel).  The script prints
 the maximum error of every table on a dense check grid.
 
+Layout.  The device locates a segment with one affine map, so the pieces are
+laid out on a common index axis w (segment j covers w in [j, j + 1], s =
+2 (w - j) - 1):
+  regime table  [CL | PT | DS]:  w = NCL t for xi < PT_LO (t = (PT_LO/xi)^3),
+                w = NCL + RW (xi - PT_LO) for xi >= PT_LO, PT and DS sharing
+                the width 1/RW, so one map covers both;
+  transition    [FA | FH]:       w = NT u / FA_HI for u < FA_HI,
+                w = 2 NT - NT FA_HI^2 / X beyond (FH stored with its
+                variable reversed, so w grows with u across the junction).
 Run:  python gen_fock_tables.py  (takes a few minutes)
 """
 import os
@@ -47,10 +56,11 @@ PT_LO, PT_HI = -3.0, 2.0
 DS_HI = 24.0
 FA_HI = 4.0
 
-# (segments, degree) per table and precision
+# per precision: polynomial degree, regime segments per unit xi (PT and DS),
+# deep-lit segments, transition segments (FA and FH each)
 LAYOUT = {
-    "f32": dict(PT=(40, 6), DS=(88, 6), CL=(16, 6), FA=(16, 6), FH=(4, 6)),
-    "f64": dict(PT=(80, 11), DS=(88, 11), CL=(32, 11), FA=(32, 11), FH=(8, 11)),
+    "f32": dict(deg=4, rw=8, ncl=16, nt=32),
+    "f64": dict(deg=11, rw=8, ncl=32, nt=32),
 }
 
 SQPI = mp.sqrt(mp.pi)
@@ -278,12 +288,18 @@ def _fh(v):
     return (H_of_v(v),)
 
 
+def _fhr(r):
+    # FH on the reversed variable r = 1 - FA_HI^2 / X in [0, 1]
+    return (H_of_v((1.0 - r) / FA_HI ** 2),)
+
+
 FUNS = {
     "PT": (ptilde, PT_LO, PT_HI),
     "DS": (dshadow, PT_HI, DS_HI),
     "CL": (clit_t, 0.0, 1.0),
     "FA": (_fa, 0.0, FA_HI),
     "FH": (_fh, 0.0, 1.0 / FA_HI ** 2),
+    "FHR": (_fhr, 0.0, 1.0),
 }
 
 
@@ -313,6 +329,11 @@ def emit_array(fh, cname, tab, ctype):
     fh.write("};\n")
 
 
+def emit_concat(fh, cname, tabs, ctype):
+    """Concatenate tables along the segment axis and emit them as one array."""
+    emit_array(fh, cname, np.concatenate(tabs, axis=0), ctype)
+
+
 def main(out_path):
     import multiprocessing as mproc
     zs, ws, zh, wh = residues()
@@ -321,17 +342,23 @@ def main(out_path):
     report = []
     with mproc.get_context("fork").Pool(min(8, os.cpu_count() or 1)) as pool:
         for prec, lay in LAYOUT.items():
-            for name, (nseg, deg) in lay.items():
+            deg, rw, ncl, nt = lay["deg"], lay["rw"], lay["ncl"], lay["nt"]
+            npt = int(round(rw * (PT_HI - PT_LO)))
+            nds = int(round(rw * (DS_HI - PT_HI)))
+            assert npt == rw * (PT_HI - PT_LO) and nds == rw * (DS_HI - PT_HI)
+            lay.update(npt=npt, nds=nds)
+            for name, nseg in (("CL", ncl), ("PT", npt), ("DS", nds), ("FA", nt), ("FHR", nt)):
                 fn, lo, hi = FUNS[name]
                 tab = build_table(name, lo, hi, nseg, deg, pool)
-                err = check(name, tab, prec, pool)
+                err = check(name, tab, prec, pool, npts=397)
                 report.append("%s %s nseg=%d deg=%d max rel err %.2e" % (prec, name, nseg, deg, err))
                 print(report[-1], flush=True)
                 tables[(prec, name)] = tab
     with open(out_path, "w") as fh:
         fh.write("// Generated by gen_fock_tables.py -- do not edit.\n")
         fh.write("// Piecewise polynomials (Horner in s in [-1,1] per segment) of the\n")
-        fh.write("// Pekeris/Fock functions and the transition function; see the generator.\n")
+        fh.write("// Pekeris/Fock functions and the transition function; see the generator\n")
+        fh.write("// for the functions and the index layout.\n")
         for line in report:
             fh.write("// %s\n" % line)
         fh.write("#pragma once\n")
@@ -340,19 +367,15 @@ def main(out_path):
         fh.write("#define FT_DS_HI (%.17g)\n#define FT_FA_HI (%.17g)\n" % (DS_HI, FA_HI))
         for prec, lay in LAYOUT.items():
             P = prec.upper()
-            for name, (nseg, deg) in lay.items():
-                fh.write("#define FT_%s_%s_NSEG %d\n#define FT_%s_%s_DEG %d\n" % (P, name, nseg, P, name, deg))
-        # first creeping mode exponent and weight, and the second, for xi > DS_HI
-        def c2(z):
-            return complex(z)
-        fh.write("#define FT_Z1S_RE (%.17e)\n#define FT_Z1S_IM (%.17e)\n" % (c2(zs[0]).real, c2(zs[0]).imag))
-        fh.write("#define FT_Z1H_RE (%.17e)\n#define FT_Z1H_IM (%.17e)\n" % (c2(zh[0]).real, c2(zh[0]).imag))
-        fh.write("#define FT_W1S_RE (%.17e)\n#define FT_W1S_IM (%.17e)\n" % (c2(ws[0]).real, c2(ws[0]).imag))
-        fh.write("#define FT_W1H_RE (%.17e)\n#define FT_W1H_IM (%.17e)\n" % (c2(wh[0]).real, c2(wh[0]).imag))
-        for prec, lay in LAYOUT.items():
+            for key in ("deg", "rw", "ncl", "npt", "nds", "nt"):
+                fh.write("#define FT_%s_%s %d\n" % (P, key.upper(), lay[key]))
+        # first creeping-mode exponents, for xi > DS_HI
+        fh.write("#define FT_Z1S_RE (%.17e)\n#define FT_Z1S_IM (%.17e)\n" % (complex(zs[0]).real, complex(zs[0]).imag))
+        fh.write("#define FT_Z1H_RE (%.17e)\n#define FT_Z1H_IM (%.17e)\n" % (complex(zh[0]).real, complex(zh[0]).imag))
+        for prec in LAYOUT:
             ctype = "float" if prec == "f32" else "double"
-            for name in lay:
-                emit_array(fh, "ft_%s_%s" % (prec, name.lower()), tables[(prec, name)], ctype)
+            emit_concat(fh, "ft_%s_reg" % prec, [tables[(prec, n)] for n in ("CL", "PT", "DS")], ctype)
+            emit_concat(fh, "ft_%s_tf" % prec, [tables[(prec, n)] for n in ("FA", "FHR")], ctype)
     print("wrote", out_path)
 
 

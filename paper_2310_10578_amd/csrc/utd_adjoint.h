@@ -68,6 +68,7 @@ __device__ __forceinline__ void record_adjoint(const PathEval<R>& pe, const Tabs
             FockArgs<D> a;
             a.xi = D(xi, dir == 0 ? fc.k13 : (R)0);
             a.u = D(u, dir == 1 ? fc.sk : (R)0);
+            a.iu = RT<D>::rcp(u > (R)0 ? a.u : D((R)1));
             a.q = D(q, dir == 2 ? fc.k16 : (R)0);
             a.ixi = D(ixi, dir == 0 ? dixi : (R)0);
             a.h = D(h, dir == 0 ? dh : (R)0);
@@ -265,8 +266,8 @@ __global__ void __launch_bounds__(256) k_adj_paths(LaunchParams L, const float* 
                                                    double* __restrict__ contrib) {
     using GD = Dual<double>;
     using RD = Dual<R>;
-    __shared__ R s_reg[TableStage<R>::NREG];
-    __shared__ R s_tf[TableStage<R>::NTF];
+    __shared__ __attribute__((aligned(16))) R s_reg[TableStage<R>::NREG];
+    __shared__ __attribute__((aligned(16))) R s_tf[TableStage<R>::NTF];
     Tabs<R> tb = TableStage<R>::stage(s_reg, s_tf);
     const int64_t total = *ntot;
     const d3 T0 = mk(L.T[0], L.T[1], L.T[2]);

@@ -42,17 +42,6 @@ utd_status hip_fail(hipError_t e, const char* what) {
     return fail(UTD_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-std::once_flag g_tables_once;
-hipError_t g_tables_err = hipSuccess;
-
-hipError_t ensure_tables() {
-    std::call_once(g_tables_once, [] {
-        g_tables_err = utd::pack_tables(nullptr);
-        if (g_tables_err == hipSuccess) g_tables_err = hipDeviceSynchronize();
-    });
-    return g_tables_err;
-}
-
 constexpr int kMaxDepth = 22;   // < kStackDepth of the device traversal (a 2e5-triangle room needs 19)
 
 // --- optional per-kernel event timing (utd_profile_*) ---
@@ -305,8 +294,7 @@ utd_status utd_smooth_field(const utd_scene* scene, const utd_bodies* bodies, co
     if (st != UTD_OK) return st;
     if (n_rx == 0 || n_f == 0) return UTD_OK;
     if (!E_out) return fail(UTD_E_ARG, "E_out is NULL");
-    hipError_t e = ensure_tables();
-    if (e != hipSuccess) return hip_fail(e, "table upload");
+    hipError_t e = hipSuccess;
     hipStream_t s = (hipStream_t)stream;
     utd::LaunchParams L = make_params(bodies, tx, n_rx, n_f, opt);
     int nb = L.n_sph + L.n_cyl;
@@ -338,8 +326,7 @@ utd_status utd_path_census(const utd_scene* scene, const utd_bodies* bodies, con
     if (!counts) return fail(UTD_E_ARG, "counts is NULL");
     for (int k = 0; k < 10; ++k) counts[k] = 0;
     if (n_rx == 0) return UTD_OK;
-    hipError_t e = ensure_tables();
-    if (e != hipSuccess) return hip_fail(e, "table upload");
+    hipError_t e = hipSuccess;
     hipStream_t s = (hipStream_t)stream;
     utd::LaunchParams L = make_params(bodies, tx, n_rx, 0, opt);
     int nb = L.n_sph + L.n_cyl;
@@ -371,8 +358,7 @@ utd_status utd_smooth_field_backward(const utd_scene* scene, const utd_bodies* b
     if (bodies->n_sph && !d_sph) return fail(UTD_E_ARG, "d_sph is NULL with n_sph > 0");
     const bool work = n_rx > 0 && n_f > 0;
     if (work && !grad_E) return fail(UTD_E_ARG, "grad_E is NULL");
-    hipError_t e = ensure_tables();
-    if (e != hipSuccess) return hip_fail(e, "table upload");
+    hipError_t e = hipSuccess;
     hipStream_t s = (hipStream_t)stream;
     utd::LaunchParams L = make_params(bodies, tx, n_rx, n_f, opt);
     int nb = L.n_sph + L.n_cyl;
@@ -430,8 +416,7 @@ utd_status utd_smooth_field_batched(const utd_scene* scene, int64_t n_frames, co
     if (n_frames == 0 || n_rx == 0 || n_f == 0) return UTD_OK;
     if (!body_off || !rx_off) return fail(UTD_E_ARG, "body_off and rx_off must not be NULL");
     if (!E_out) return fail(UTD_E_ARG, "E_out is NULL");
-    hipError_t e = ensure_tables();
-    if (e != hipSuccess) return hip_fail(e, "table upload");
+    hipError_t e = hipSuccess;
     hipStream_t s = (hipStream_t)stream;
     int dev = 0;
     e = hipGetDevice(&dev);

@@ -145,8 +145,8 @@ __global__ void __launch_bounds__(TILE) k_batch(BatchParams B, const float* __re
     __shared__ unsigned int s_mask[kBGroup * TILE / 4];   // bytes [body in group][lane]
     __shared__ uint32_t s_q[QCAP];
     __shared__ int s_qn;
-    __shared__ R s_reg[TableStage<R>::NREG];
-    __shared__ R s_tf[TableStage<R>::NTF];
+    __shared__ __attribute__((aligned(16))) R s_reg[TableStage<R>::NREG];
+    __shared__ __attribute__((aligned(16))) R s_tf[TableStage<R>::NTF];
     __shared__ int64_t s_tile;
     Tabs<R> tb = TableStage<R>::stage(s_reg, s_tf);
     uint8_t* mask8 = reinterpret_cast<uint8_t*>(s_mask);

@@ -51,11 +51,12 @@ template <typename G> struct BodyPrepT {
 using BodyPrep = BodyPrepT<double>;
 
 // Per-frequency constants (computed once per call): phase revolutions per
-// metre f/c, wavenumber k and k^{1/3}, k^{1/6}, k^{-1/6} in both precisions.
+// metre f/c, wavenumber k, k^{1/3}, k^{1/6}, k^{-1/6}, sqrt(k) and the
+// reciprocals of k^{1/3} and sqrt(k), in both precisions.
 struct FreqConst {
     double rev_per_m;
-    double kd, k13d, k16d, km16d, skd, ik13d;
-    float kf, k13f, k16f, km16f, skf, ik13f;
+    double kd, k13d, k16d, km16d, skd, ik13d, iskd;
+    float kf, k13f, k16f, km16f, skf, ik13f, iskf;
 };
 
 // ---------------------------------------------------------------------------

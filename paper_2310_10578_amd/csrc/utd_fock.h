@@ -24,30 +24,28 @@ namespace utd {
 constexpr double kInv2SqrtPi = 0.28209479177387814347;   // 1/(2 sqrt(pi))
 constexpr double kRs2 = 0.70710678118654752440;          // 1/sqrt(2)
 
-// Table geometry shared by both precisions (segment counts differ).
-template <typename R> struct TabDims;
-// ROWS: coefficient rows stored per segment (DEG + 1, padded to a power of
-// two for the LDS copy of the FP32 tables so the segment offset is a shift).
+// Table geometry per precision.  Segments sit on a common index axis w
+// (segment j covers [j, j + 1], local variable s = 2 (w - j) - 1):
+//   regime table     [CL | PT | DS]: w = NCL t for xi < PT_LO
+//                    (t = (PT_LO/xi)^3), w = NCL + RW (xi - PT_LO) beyond;
+//   transition table [FA | FH]:      w = NT u / FA_HI for u < FA_HI,
+//                    w = 2 NT - NT FA_HI^2 / X beyond.
+template <typename T> struct TabDims;
 template <> struct TabDims<float> {
-    static constexpr int DEG = FT_F32_PT_DEG;
-    static constexpr int ROWS = 8;
-    static constexpr int NPT = FT_F32_PT_NSEG, NDS = FT_F32_DS_NSEG, NCL = FT_F32_CL_NSEG;
-    static constexpr int NFA = FT_F32_FA_NSEG, NFH = FT_F32_FH_NSEG;
-    static_assert(DEG + 1 <= ROWS, "row padding");
+    static constexpr int DEG = FT_F32_DEG, ROWS = DEG + 1;
+    static constexpr int RW = FT_F32_RW, NCL = FT_F32_NCL, NPT = FT_F32_NPT, NDS = FT_F32_NDS, NT = FT_F32_NT;
 };
 template <> struct TabDims<double> {
-    static constexpr int DEG = FT_F64_PT_DEG;
-    static constexpr int ROWS = FT_F64_PT_DEG + 1;
-    static constexpr int NPT = FT_F64_PT_NSEG, NDS = FT_F64_DS_NSEG, NCL = FT_F64_CL_NSEG;
-    static constexpr int NFA = FT_F64_FA_NSEG, NFH = FT_F64_FH_NSEG;
+    static constexpr int DEG = FT_F64_DEG, ROWS = DEG + 1;
+    static constexpr int RW = FT_F64_RW, NCL = FT_F64_NCL, NPT = FT_F64_NPT, NDS = FT_F64_NDS, NT = FT_F64_NT;
 };
 
-// Pointers to the regime tables ([seg][ROWS][4] = (re_s, im_s, re_h, im_h))
-// and the transition tables ([seg][ROWS][2] = (re, im)), in LDS (FP32) or
+// Pointers to the regime table ([seg][ROWS][4] = (re_s, im_s, re_h, im_h))
+// and the transition table ([seg][ROWS][2] = (re, im)), in LDS (FP32) or
 // global memory (FP64).
 template <typename T> struct Tabs {
-    const T* reg;   // PT segments, then DS, then CL
-    const T* tf;    // FA segments, then FH
+    const T* reg;
+    const T* tf;
 };
 
 // Polynomials are evaluated in the arithmetic type R (plain or dual) from
@@ -100,14 +98,50 @@ __device__ __forceinline__ void horner2(const T* seg, R s, R out[2]) {
     out[0] = a0; out[1] = a1;
 }
 
-// Locate x in [lo, hi] split into n equal segments: index and s in [-1, 1].
+// Segment j = floor(w) of index-axis position w clamped to [0, wmax] (wmax
+// just below the table's segment count) and the local variable s in [-1, 1].
+__device__ __forceinline__ int seg_at(float w, float wmax, float* s) {
+    w = __builtin_amdgcn_fmed3f(w, 0.0f, wmax);
+    *s = fmaf(__builtin_amdgcn_fractf(w), 2.0f, -1.0f);
+    return (int)w;
+}
+__device__ __forceinline__ int seg_at(double w, double wmax, double* s) {
+    w = fmin(fmax(w, 0.0), wmax);
+    *s = fma(__builtin_amdgcn_fract(w), 2.0, -1.0);
+    return (int)w;
+}
+template <typename T>
+__device__ __forceinline__ int seg_at(Dual<T> w, Dual<T> wmax, Dual<T>* s) {
+    T v = w.v < (T)0 ? (T)0 : (w.v > wmax.v ? wmax.v : w.v);
+    int j = (int)v;
+    // a clamped position does not move with the parameter
+    *s = Dual<T>((T)2 * (v - (T)j) - (T)1, v == w.v ? (T)2 * w.d : (T)0);
+    return j;
+}
+
+// largest representable value below the segment count n, as the clamp
+template <typename T> __host__ __device__ constexpr T below(int n) {
+    return (T)n * ((T)1 - (T)(sizeof(T) == 4 ? 1.1920928955078125e-07 : 4.4408920985006262e-16));
+}
+
+// e^{z dx} for the first creeping mode z = zre + j zim (deep shadow beyond
+// the table); the FP32 version takes the hardware exp2 and the revolution-
+// argument sin/cos directly.
 template <typename R>
-__device__ __forceinline__ int locate(R x, R lo, R inv_w, int n, R* s) {
-    R u = (x - lo) * inv_w;
-    int i = (int)val(RT<R>::floor_(u));
-    i = i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
-    *s = (R)2 * (u - (R)i) - (R)1;
-    return i;
+__device__ __forceinline__ cplx<R> mode_factor(R dx, double zre, double zim) {
+    R e = RT<R>::exp_((R)zre * dx);
+    cplx<R> r = expmj<R>(-(R)zim * dx);
+    return cplx<R>{e * r.re, e * r.im};
+}
+template <>
+__device__ __forceinline__ cplx<float> mode_factor<float>(float dx, double zre, double zim) {
+    constexpr double kLog2e = 1.4426950408889634074;
+    float e = __builtin_amdgcn_exp2f((float)(zre * kLog2e) * dx);
+    float r = (float)(-zim * kInvTwoPi) * dx;
+    r -= rintf(r);
+    float sn, cs;
+    sincos_rev(r, &sn, &cs);
+    return cplx<float>{e * cs, -e * sn};
 }
 
 // B-type kernels K_s, K_h of one path at one frequency.
@@ -124,6 +158,7 @@ enum { kAny = 0, kCreep = 1, kRefl = 2 };
 template <typename R> struct FockArgs {
     R xi;    // Fock parameter
     R u;     // sqrt(X), X the transition-function argument
+    R iu;    // 1/u (any value when u < FA_HI)
     R q;     // sqrt(X)/|xi|
     R ixi;   // 1/xi (0 when xi == 0)
     R h;     // sqrt(-xi)/2 (deep lit; 0 otherwise)
@@ -134,21 +169,20 @@ __device__ __forceinline__ void fock_kernel(const Tabs<typename BaseOf<R>::type>
                                             cplx<R>* Ks, cplx<R>* Kh) {
     using T = typename BaseOf<R>::type;
     using D = TabDims<T>;
-    const R e4 = (R)kRs2;                     // e^{-j pi/4} = e4 (1 - j)
-    const R c2 = (R)kInv2SqrtPi;
+    const R c2e4 = (R)(kInv2SqrtPi * kRs2);   // e^{-j pi/4}/(2 sqrt pi) = c2e4 (1 - j)
     const R xi = A.xi, u = A.u, q = A.q, ixi = A.ixi;
 
-    // --- transition function: A(u) for u <= FA_HI, H(1/X) beyond -----------
-    bool big = u > (R)FT_FA_HI;
-    R iu = RT<R>::rcp(big ? u : (R)1);
-    R iX = iu * iu;
-    R targ = big ? iX : u;
-    R invw = big ? (R)(D::NFH * FT_FA_HI * FT_FA_HI) : (R)(D::NFA / FT_FA_HI);
-    int nseg = big ? D::NFH : D::NFA;
+    // --- transition function: A(u) for u < FA_HI, H(1/X) beyond -------------
+    // The segment decides which of the two is read, so the two sides of the
+    // junction stay consistent under rounding.
+    const R iu = A.iu, iX = iu * iu;
+    R wt = u >= (R)FT_FA_HI ? (R)(2 * D::NT) - (R)(D::NT * FT_FA_HI * FT_FA_HI) * iX
+                            : u * (R)(D::NT / FT_FA_HI);
     R st;
-    int tseg = (big ? D::NFA : 0) + locate<R>(targ, (R)0, invw, nseg, &st);
+    const int tseg = seg_at(wt, (R)below<T>(2 * D::NT), &st);
+    const bool big = tseg >= D::NT;
     R v[2];
-    horner2<T, R>(tb.tf + tseg * 2 * D::ROWS, st, v);
+    horner2<T, R>(tb.tf + __umul24((unsigned)tseg, 2 * D::ROWS), st, v);
     // small u: G = F/sqrt(X) = 2j A, F = u G; large u: 1 - F = -H/X, G = F/u
     R omr = -iX * v[0], omi = -iX * v[1];
     cplx<R> G, omF;
@@ -158,45 +192,28 @@ __device__ __forceinline__ void fock_kernel(const Tabs<typename BaseOf<R>::type>
     omF.im = big ? omi : -u * G.im;
 
     // --- regime table ------------------------------------------------------
-    // creeping paths have xi >= 0 (regimes 0, 1), reflections xi <= 0 (1, 2)
-    int regime = (MODE != kRefl && xi >= (R)FT_PT_HI) ? 0 : ((MODE == kCreep || xi >= (R)FT_PT_LO) ? 1 : 2);
-    R s;
-    int seg;
+    // creeping paths have xi >= 0 (regimes 0, 1), reflections xi <= 0 (1, 2);
+    // the regime follows from the segment
+    const R w_xi = xi * (R)D::RW + (R)(D::NCL - FT_PT_LO * D::RW);
+    R w;
     if (MODE == kCreep) {
-        // both regimes read xi itself, clamped to the deep-shadow table's end
-        R arg = xi < (R)FT_DS_HI ? xi : (R)FT_DS_HI;
-        bool r0 = regime == 0;
-        seg = (r0 ? D::NPT : 0) +
-              locate<R>(arg, r0 ? (R)FT_PT_HI : (R)FT_PT_LO,
-                        r0 ? (R)(D::NDS / (FT_DS_HI - FT_PT_HI)) : (R)(D::NPT / (FT_PT_HI - FT_PT_LO)),
-                        r0 ? D::NDS : D::NPT, &s);
-    } else if (MODE == kRefl) {
-        R r3 = (R)FT_PT_LO * ixi;
-        bool r1 = regime == 1;
-        seg = (r1 ? 0 : D::NPT + D::NDS) +
-              locate<R>(r1 ? xi : r3 * r3 * r3, r1 ? (R)FT_PT_LO : (R)0,
-                        r1 ? (R)(D::NPT / (FT_PT_HI - FT_PT_LO)) : (R)D::NCL, r1 ? D::NPT : D::NCL, &s);
+        w = w_xi;
     } else {
         R r3 = (R)FT_PT_LO * ixi;
-        R arg = regime == 0 ? (xi < (R)FT_DS_HI ? xi : (R)FT_DS_HI) : (regime == 1 ? xi : r3 * r3 * r3);
-        R rlo = regime == 0 ? (R)FT_PT_HI : (regime == 1 ? (R)FT_PT_LO : (R)0);
-        R rinv = regime == 0 ? (R)(D::NDS / (FT_DS_HI - FT_PT_HI))
-                             : (regime == 1 ? (R)(D::NPT / (FT_PT_HI - FT_PT_LO)) : (R)D::NCL);
-        int rn = regime == 0 ? D::NDS : (regime == 1 ? D::NPT : D::NCL);
-        int rbase = regime == 0 ? D::NPT : (regime == 1 ? 0 : D::NPT + D::NDS);
-        seg = rbase + locate<R>(arg, rlo, rinv, rn, &s);
+        w = xi >= (R)FT_PT_LO ? w_xi : r3 * r3 * r3 * (R)D::NCL;
     }
+    R s;
+    const int seg = seg_at(w, (R)below<T>(D::NCL + D::NPT + D::NDS), &s);
+    const int regime = (MODE != kRefl && seg >= D::NCL + D::NPT) ? 0 : ((MODE == kCreep || seg >= D::NCL) ? 1 : 2);
     R w4[4];
-    horner4<T, R>(tb.reg + seg * 4 * D::ROWS, s, w4);
+    horner4<T, R>(tb.reg + __umul24((unsigned)seg, 4 * D::ROWS), s, w4);
     cplx<R> ps{w4[0], w4[1]}, ph{w4[2], w4[3]};
-    if (MODE != kRefl && regime == 0 && xi > (R)FT_DS_HI) {
+    if (MODE != kRefl && xi > (R)FT_DS_HI) {
         // past the table only the first creeping mode survives:
         // scale the end value by e^{z1 (xi - DS_HI)} (rare)
         R dx = xi - (R)FT_DS_HI;
-        R es = RT<R>::exp_((R)FT_Z1S_RE * dx), eh = RT<R>::exp_((R)FT_Z1H_RE * dx);
-        cplx<R> rs = expmj<R>(-(R)FT_Z1S_IM * dx), rh = expmj<R>(-(R)FT_Z1H_IM * dx);
-        ps = cmul(ps, cplx<R>{es * rs.re, es * rs.im});
-        ph = cmul(ph, cplx<R>{eh * rh.re, eh * rh.im});
+        ps = cmul(ps, mode_factor<R>(dx, FT_Z1S_RE, FT_Z1S_IM));
+        ph = cmul(ph, mode_factor<R>(dx, FT_Z1H_RE, FT_Z1H_IM));
     }
 
     // --- combine ------------------------------------------------------------
@@ -205,7 +222,7 @@ __device__ __forceinline__ void fock_kernel(const Tabs<typename BaseOf<R>::type>
     cplx<R> W = regime == 1 ? G : omF;
     if (MODE == kCreep) {
         // sgn(xi) = +1 for creeping paths (xi >= 0); K = P + CW
-        R f = (regime == 1 ? -q * c2 : c2 * ixi) * e4;
+        R f = regime == 1 ? -q * c2e4 : ixi * c2e4;
         cplx<R> CW{f * (W.re + W.im), f * (W.im - W.re)};
         *Ks = cplx<R>{ps.re + CW.re, ps.im + CW.im};
         *Kh = cplx<R>{ph.re + CW.re, ph.im + CW.im};
@@ -215,7 +232,7 @@ __device__ __forceinline__ void fock_kernel(const Tabs<typename BaseOf<R>::type>
     if (MODE == kRefl) {
         // sgn = -1 on the lit side (xi <= 0): coef = q/(2 sqrt pi) in regime 1;
         // K = -(alpha P + e CW), alpha = e (regime 1) or sqrt(-xi)/2 (regime 2)
-        R f = (regime == 1 ? q * c2 : c2 * ixi) * e4;
+        R f = regime == 1 ? q * c2e4 : ixi * c2e4;
         cplx<R> CW{f * (W.re + W.im), f * (W.im - W.re)};
         cplx<R> eCW = cmul(e, CW);
         bool r2 = regime == 2;
@@ -227,8 +244,7 @@ __device__ __forceinline__ void fock_kernel(const Tabs<typename BaseOf<R>::type>
         return;
     }
     R sg = refl ? (xi > (R)0 ? (R)1 : (R)-1) : (xi < (R)0 ? (R)-1 : (R)1);
-    R coef = regime == 1 ? -sg * q * c2 : c2 * ixi;
-    R f = coef * e4;
+    R f = regime == 1 ? -sg * q * c2e4 : ixi * c2e4;
     cplx<R> CW{f * (W.re + W.im), f * (W.im - W.re)};
     // creeping: K = P + CW
     // reflection / deep lit: K = -(alpha P + e CW), e = e^{-j xi^3/12},

@@ -38,7 +38,7 @@ template <typename R, typename G = double> struct PathEvalT {
     G s_tot;          // total path length s^i + t + s^d (or s^i + s^r)
     int nc;           // caustics passed (each +pi/2)
     int refl;
-    R xh, uh, qhat, ixh, sxh;
+    R xh, uh, qhat, ixh, sxh, iuh;
     R vs[3], vh[3];   // amplitude-weighted polarisation vectors
 };
 template <typename R> using PathEval = PathEvalT<R, double>;
@@ -56,6 +56,7 @@ __device__ __forceinline__ void set_fock_consts(PathEvalT<R, G>* pe, R mhat, R p
     pe->qhat = sl / mhat;
     pe->ixh = xh != (R)0 ? (R)1 / xh : (R)0;
     pe->sxh = RT<R>::sqrt_(xh < (R)0 ? -xh : (R)0);
+    pe->iuh = pe->uh > (R)0 ? (R)1 / pe->uh : (R)0;
 }
 
 // Points of a path (for the visibility tests).

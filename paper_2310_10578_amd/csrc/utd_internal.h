@@ -8,7 +8,6 @@
 
 namespace utd {
 
-hipError_t pack_tables(hipStream_t s);
 
 // Frames of a batched call (see utd_batched.h).
 struct BatchParams {

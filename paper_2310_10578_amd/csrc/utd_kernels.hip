@@ -11,7 +11,7 @@
 // Fock-coefficient evaluation for every frequency of the chunk, accumulating E
 // in registers.  Frequency constants are uniform across the workgroup (scalar
 // loads).  The Fock tables sit in LDS (FP32) or global memory (FP64).
-#define FT_QUAL __device__ const
+#define FT_QUAL __device__ const __attribute__((aligned(16)))
 #include "utd_internal.h"
 #include "utd_bvh.h"
 #include "utd_fock.h"
@@ -28,8 +28,9 @@ __device__ __forceinline__ FreqConst freq_const(double f) {
     FreqConst c;
     c.rev_per_m = f / kC0;
     c.kd = k; c.k13d = k13; c.k16d = k16; c.km16d = 1.0 / k16; c.skd = sqrt(k); c.ik13d = 1.0 / k13;
+    c.iskd = 1.0 / c.skd;
     c.kf = (float)k; c.k13f = (float)k13; c.k16f = (float)k16; c.km16f = (float)(1.0 / k16);
-    c.skf = (float)sqrt(k); c.ik13f = (float)(1.0 / k13);
+    c.skf = (float)sqrt(k); c.ik13f = (float)(1.0 / k13); c.iskf = (float)c.iskd;
     return c;
 }
 
@@ -81,7 +82,8 @@ template <> struct PathRec<float> {          // 64 bytes
     float xh, uh, qhat;                       // see PathEval
     float4 q0;                                // (ixh, sxh, vs0, vs1)
     float4 q1;                                // (vs2, vh0, vh1, vh2)
-    float2 pad;
+    float iuh;
+    float pad;
 };
 template <> struct PathRec<double> {         // 120 bytes
     double s_tot;
@@ -97,7 +99,8 @@ __device__ __forceinline__ void pack(const PathEval<float>& p, PathRec<float>* r
     o.xh = p.xh; o.uh = p.uh; o.qhat = p.qhat;
     o.q0 = make_float4(p.ixh, p.sxh, p.vs[0], p.vs[1]);
     o.q1 = make_float4(p.vs[2], p.vh[0], p.vh[1], p.vh[2]);
-    o.pad = make_float2(0.0f, 0.0f);
+    o.iuh = p.iuh;
+    o.pad = 0.0f;
     *r = o;
 }
 __device__ __forceinline__ void unpack(const PathRec<float>& o, PathEval<float>* p) {
@@ -107,12 +110,13 @@ __device__ __forceinline__ void unpack(const PathRec<float>& o, PathEval<float>*
     p->xh = o.xh; p->uh = o.uh; p->qhat = o.qhat;
     p->ixh = o.q0.x; p->sxh = o.q0.y; p->vs[0] = o.q0.z; p->vs[1] = o.q0.w;
     p->vs[2] = o.q1.x; p->vh[0] = o.q1.y; p->vh[1] = o.q1.z; p->vh[2] = o.q1.w;
+    p->iuh = o.iuh;
 }
 __device__ __forceinline__ void pack(const PathEval<double>& p, PathRec<double>* r) {
     PathRec<double> o;
     o.s_tot = p.s_tot; o.nc = p.nc; o.refl = p.refl;
     double v[13] = {p.xh, p.uh, p.qhat, p.ixh, p.sxh, p.vs[0], p.vs[1], p.vs[2], p.vh[0], p.vh[1], p.vh[2],
-                    0.0, 0.0};
+                    p.iuh, 0.0};
     for (int k = 0; k < 13; ++k) o.v[k] = v[k];
     *r = o;
 }
@@ -121,6 +125,7 @@ __device__ __forceinline__ void unpack(const PathRec<double>& o, PathEval<double
     p->xh = o.v[0]; p->uh = o.v[1]; p->qhat = o.v[2]; p->ixh = o.v[3]; p->sxh = o.v[4];
     p->vs[0] = o.v[5]; p->vs[1] = o.v[6]; p->vs[2] = o.v[7];
     p->vh[0] = o.v[8]; p->vh[1] = o.v[9]; p->vh[2] = o.v[10];
+    p->iuh = o.v[11];
 }
 
 // Record slots per (receiver, body): one per possible path, creeping paths at
@@ -441,35 +446,42 @@ __global__ void __launch_bounds__(256) k_paths(LaunchParams L, const float* __re
 template <typename R> struct FreqC;
 template <> struct FreqC<float> {
     double rev_per_m;
-    float kf, k13, k16, km16, sk, ik13;
+    float kf, k13, k16, km16, sk, ik13, isk;
     __device__ __forceinline__ FreqC(const FreqConst& c)
-        : rev_per_m(c.rev_per_m), kf(c.kf), k13(c.k13f), k16(c.k16f), km16(c.km16f), sk(c.skf), ik13(c.ik13f) {}
+        : rev_per_m(c.rev_per_m), kf(c.kf), k13(c.k13f), k16(c.k16f), km16(c.km16f), sk(c.skf), ik13(c.ik13f),
+          isk(c.iskf) {}
 };
 template <> struct FreqC<double> {
     double rev_per_m;
-    double kf, k13, k16, km16, sk, ik13;
+    double kf, k13, k16, km16, sk, ik13, isk;
     __device__ __forceinline__ FreqC(const FreqConst& c)
-        : rev_per_m(c.rev_per_m), kf(c.kd), k13(c.k13d), k16(c.k16d), km16(c.km16d), sk(c.skd), ik13(c.ik13d) {}
+        : rev_per_m(c.rev_per_m), kf(c.kd), k13(c.k13d), k16(c.k16d), km16(c.km16d), sk(c.skd), ik13(c.ik13d),
+          isk(c.iskd) {}
 };
 
 // One path at one frequency: the Fock arguments scale with powers of k
 // (xi ~ k^{1/3}, sqrt(X) ~ k^{1/2}, q ~ k^{1/6}), so they are products of the
 // path's constants and the frequency's.  MODE picks the Fock specialisation
 // (kCreep, kRefl or kAny for mixed wavefronts); callers branch on
-// wave-uniform conditions.
-template <typename R, int MODE>
+// wave-uniform conditions.  Every diffracted term carries the factor
+// k^{-1/6}; with KM16 = false it is left out, for callers that apply it once
+// to their sum.
+template <typename R, int MODE, bool KM16 = true>
 __device__ __forceinline__ void add_path(const PathEval<R>& pe, const Tabs<R>& tb, const FreqC<R>& fc, R* E) {
     FockArgs<R> a;
     a.xi = fc.k13 * pe.xh;
     a.u = fc.sk * pe.uh;
+    a.iu = fc.isk * pe.iuh;
     a.q = fc.k16 * pe.qhat;
     a.ixi = fc.ik13 * pe.ixh;
     a.h = (R)0.5 * fc.k16 * pe.sxh;
     cplx<R> Ks, Kh;
     fock_kernel<R, MODE>(tb, a, pe.refl != 0, &Ks, &Kh);
     cplx<R> ph = phase_rev<R>(fc.rev_per_m * pe.s_tot - 0.25 * pe.nc);
-    ph.re *= fc.km16;
-    ph.im *= fc.km16;
+    if (KM16) {
+        ph.re *= fc.km16;
+        ph.im *= fc.km16;
+    }
     cplx<R> cs = cmul(Ks, ph), ch = cmul(Kh, ph);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -480,59 +492,35 @@ __device__ __forceinline__ void add_path(const PathEval<R>& pe, const Tabs<R>& t
     }
 }
 
+// The FP32 tables are copied into LDS once per workgroup: the generated
+// arrays already have the LDS layout, so the copy is a straight 16-byte
+// vector copy.  The FP64 tables stay in global memory (L2 resident).
 template <typename R> struct TableStage;
 
 template <> struct TableStage<float> {
     using D = TabDims<float>;
-    static constexpr int ROWS = D::ROWS, DEG = D::DEG;
-    static constexpr int NREG = (D::NPT + D::NDS + D::NCL) * ROWS * 4;
-    static constexpr int NTF = (D::NFA + D::NFH) * ROWS * 2;
-    // copy [seg][DEG + 1][W] into [seg][ROWS][W] (padding rows never read)
-    template <int W>
-    static __device__ __forceinline__ void copy(float* dst, const float* src, int nseg) {
-        const int n = nseg * (DEG + 1) * W;
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            int sg = i / ((DEG + 1) * W), r = i - sg * (DEG + 1) * W;
-            dst[sg * ROWS * W + r] = src[i];
-        }
-    }
+    static constexpr int NREG = (D::NCL + D::NPT + D::NDS) * D::ROWS * 4;
+    static constexpr int NTF = 2 * D::NT * D::ROWS * 2;
+    static_assert(NREG % 4 == 0 && NTF % 4 == 0, "float4 copy");
+    static_assert(sizeof(ft_f32_reg) == NREG * sizeof(float) && sizeof(ft_f32_tf) == NTF * sizeof(float),
+                  "table layout");
     static __device__ __forceinline__ Tabs<float> stage(float* reg, float* tf) {
-        copy<4>(reg, &ft_f32_pt[0][0][0], D::NPT);
-        copy<4>(reg + D::NPT * ROWS * 4, &ft_f32_ds[0][0][0], D::NDS);
-        copy<4>(reg + (D::NPT + D::NDS) * ROWS * 4, &ft_f32_cl[0][0][0], D::NCL);
-        copy<2>(tf, &ft_f32_fa[0][0][0], D::NFA);
-        copy<2>(tf + D::NFA * ROWS * 2, &ft_f32_fh[0][0][0], D::NFH);
+        const float4* a = reinterpret_cast<const float4*>(&ft_f32_reg[0][0][0]);
+        const float4* b = reinterpret_cast<const float4*>(&ft_f32_tf[0][0][0]);
+        float4* ra = reinterpret_cast<float4*>(reg);
+        float4* rb = reinterpret_cast<float4*>(tf);
+        for (int i = threadIdx.x; i < NREG / 4; i += blockDim.x) ra[i] = a[i];
+        for (int i = threadIdx.x; i < NTF / 4; i += blockDim.x) rb[i] = b[i];
         __syncthreads();
         return Tabs<float>{reg, tf};
     }
 };
 
-// FP64 tables stay in global memory (81 KB; L2 resident).  They are laid out
-// back to back in one device array built once at library load.
-__device__ double g_f64_reg[(FT_F64_PT_NSEG + FT_F64_DS_NSEG + FT_F64_CL_NSEG) * (FT_F64_PT_DEG + 1) * 4];
-__device__ double g_f64_tf[(FT_F64_FA_NSEG + FT_F64_FH_NSEG) * (FT_F64_PT_DEG + 1) * 2];
-
-__global__ void k_pack_f64_tables() {
-    constexpr int na = FT_F64_PT_NSEG * (FT_F64_PT_DEG + 1) * 4;
-    constexpr int nb = FT_F64_DS_NSEG * (FT_F64_PT_DEG + 1) * 4;
-    constexpr int nc = FT_F64_CL_NSEG * (FT_F64_PT_DEG + 1) * 4;
-    constexpr int nd = FT_F64_FA_NSEG * (FT_F64_PT_DEG + 1) * 2;
-    constexpr int ne = FT_F64_FH_NSEG * (FT_F64_PT_DEG + 1) * 2;
-    const double* a = &ft_f64_pt[0][0][0];
-    const double* b = &ft_f64_ds[0][0][0];
-    const double* c = &ft_f64_cl[0][0][0];
-    const double* d = &ft_f64_fa[0][0][0];
-    const double* e = &ft_f64_fh[0][0][0];
-    for (int i = threadIdx.x; i < na; i += blockDim.x) g_f64_reg[i] = a[i];
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) g_f64_reg[na + i] = b[i];
-    for (int i = threadIdx.x; i < nc; i += blockDim.x) g_f64_reg[na + nb + i] = c[i];
-    for (int i = threadIdx.x; i < nd; i += blockDim.x) g_f64_tf[i] = d[i];
-    for (int i = threadIdx.x; i < ne; i += blockDim.x) g_f64_tf[nd + i] = e[i];
-}
-
 template <> struct TableStage<double> {
     static constexpr int NREG = 1, NTF = 1;
-    static __device__ __forceinline__ Tabs<double> stage(double*, double*) { return Tabs<double>{g_f64_reg, g_f64_tf}; }
+    static __device__ __forceinline__ Tabs<double> stage(double*, double*) {
+        return Tabs<double>{&ft_f64_reg[0][0][0], &ft_f64_tf[0][0][0]};
+    }
 };
 
 template <typename R, int FC>
@@ -540,8 +528,8 @@ __global__ void __launch_bounds__(256) k_field(LaunchParams L, const float* __re
                                                const FreqConst* __restrict__ fcs, const uint8_t* __restrict__ mask,
                                                const PathRec<R>* __restrict__ rec, uint8_t* __restrict__ flags,
                                                R* __restrict__ E_out) {
-    __shared__ R s_reg[TableStage<R>::NREG];
-    __shared__ R s_tf[TableStage<R>::NTF];
+    __shared__ __attribute__((aligned(16))) R s_reg[TableStage<R>::NREG];
+    __shared__ __attribute__((aligned(16))) R s_tf[TableStage<R>::NTF];
     Tabs<R> tb = TableStage<R>::stage(s_reg, s_tf);
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= L.n_rx) return;
@@ -555,6 +543,50 @@ __global__ void __launch_bounds__(256) k_field(LaunchParams L, const float* __re
         for (int c = 0; c < 6; ++c) E[j][c] = (R)0;
     uint8_t fl = flags[i];
     if (!(fl & (kFlagInside | kFlagTxInside))) {
+        // diffracted and reflected paths, Eqs. (2)-(4), without their common
+        // factor k^{-1/6} (applied once per frequency below)
+        int nb = L.n_sph + L.n_cyl;
+        uint8_t caus = 0;
+        for (int b = 0; b < nb; ++b) {
+            uint8_t m = mask[(int64_t)b * L.n_rx + i];
+            caus |= m;
+            const bool has_refl = (m >> kBitRefl) & 1u;
+            // creeping paths in bit order, then the reflection
+            uint32_t cb = m & ((1u << (2 * (L.l_enc + 1))) - 1u);
+            while (cb) {
+                const int k = __builtin_ctz(cb);
+                cb &= cb - 1u;
+                PathEval<R> pe;
+                unpack(rec[((int64_t)b * NS + k) * L.n_rx + i], &pe);
+#pragma unroll
+                for (int j = 0; j < FC; ++j) {
+                    if (j < nfc) {
+                        FreqC<R> fc(fcs[f0 + j]);
+                        add_path<R, kCreep, false>(pe, tb, fc, E[j]);
+                    }
+                }
+            }
+            if (__any(has_refl) && has_refl) {
+                PathEval<R> pe;
+                unpack(rec[((int64_t)b * NS + rec_slot(L, kBitRefl)) * L.n_rx + i], &pe);
+#pragma unroll
+                for (int j = 0; j < FC; ++j) {
+                    if (j < nfc) {
+                        FreqC<R> fc(fcs[f0 + j]);
+                        add_path<R, kRefl, false>(pe, tb, fc, E[j]);
+                    }
+                }
+            }
+        }
+        if (blockIdx.y == 0 && (caus & (1u << kBitCaustic))) flags[i] = fl | kFlagCaustic;
+#pragma unroll
+        for (int j = 0; j < FC; ++j) {
+            if (j < nfc) {
+                const R km16 = FreqC<R>(fcs[f0 + j]).km16;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) E[j][c] *= km16;
+            }
+        }
         // direct field, Eq. (1): A (p - (p.s)s) e^{-jks}/s
         if ((fl & kFlagLos) && L.lit_branch) {
             d3 v = mk(rx[3 * i] - L.T[0], rx[3 * i + 1] - L.T[1], rx[3 * i + 2] - L.T[2]);
@@ -577,40 +609,6 @@ __global__ void __launch_bounds__(256) k_field(LaunchParams L, const float* __re
                 }
             }
         }
-        int nb = L.n_sph + L.n_cyl;
-        uint8_t caus = 0;
-        for (int b = 0; b < nb; ++b) {
-            uint8_t m = mask[(int64_t)b * L.n_rx + i];
-            caus |= m;
-            const bool has_refl = (m >> kBitRefl) & 1u;
-            // creeping paths in bit order, then the reflection
-            uint32_t cb = m & ((1u << (2 * (L.l_enc + 1))) - 1u);
-            while (cb) {
-                const int k = __builtin_ctz(cb);
-                cb &= cb - 1u;
-                PathEval<R> pe;
-                unpack(rec[((int64_t)b * NS + k) * L.n_rx + i], &pe);
-#pragma unroll
-                for (int j = 0; j < FC; ++j) {
-                    if (j < nfc) {
-                        FreqC<R> fc(fcs[f0 + j]);
-                        add_path<R, kCreep>(pe, tb, fc, E[j]);
-                    }
-                }
-            }
-            if (__any(has_refl) && has_refl) {
-                PathEval<R> pe;
-                unpack(rec[((int64_t)b * NS + rec_slot(L, kBitRefl)) * L.n_rx + i], &pe);
-#pragma unroll
-                for (int j = 0; j < FC; ++j) {
-                    if (j < nfc) {
-                        FreqC<R> fc(fcs[f0 + j]);
-                        add_path<R, kRefl>(pe, tb, fc, E[j]);
-                    }
-                }
-            }
-        }
-        if (blockIdx.y == 0 && (caus & (1u << kBitCaustic))) flags[i] = fl | kFlagCaustic;
     }
 #pragma unroll
     for (int j = 0; j < FC; ++j) {
@@ -654,11 +652,6 @@ __global__ void __launch_bounds__(256) k_census(int64_t n_mask, const uint8_t* _
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-hipError_t pack_tables(hipStream_t s) {
-    hipLaunchKernelGGL(k_pack_f64_tables, dim3(1), dim3(256), 0, s);
-    return hipGetLastError();
-}
-
 hipError_t launch_census(int64_t n_mask, const uint8_t* mask, int64_t n_rx, const uint8_t* flags,
                          unsigned long long* counts, hipStream_t s) {
     hipLaunchKernelGGL(k_census, dim3(512), dim3(256), 0, s, n_mask, mask, n_rx, flags, counts);
