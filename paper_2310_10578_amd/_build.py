@@ -7,7 +7,6 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libutd.so")
 SOURCES = ["utd_kernels.hip", "utd_api.cpp", "bvh.cpp"]
-HEADERS = ["utd_device.h", "utd_fock.h", "utd_geom.h", "utd_bvh.h", "utd_internal.h", "fock_tables.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -11,9 +11,10 @@ Functions tabulated (xi real):
   PT : Ptilde_p(xi) = p*_p(xi) + e^{-j pi/4}/(2 sqrt(pi) xi)       xi in [PT_LO, PT_HI]
   DS : p*_p(xi) itself (the creeping-wave modes)                   xi in [PT_HI, DS_HI]
   CL : c_p(t) = sqrt(-4/xi) e^{-j xi^3/12} p*_p(xi), t = (PT_LO/xi)^3 in (0, 1]
-  FA : A(u) = e^{j u^2} Int_u^inf e^{-j s^2} ds                    u in [0, FA_HI]
-  FH : H(v) = (F(X) - 1) X, v = 1/X                               v in [0, 1/FA_HI^2]
-with F(X) = 2j sqrt(X) A(sqrt(X)).
+  FA : G(u) = F(X)/sqrt(X) = 2j A(u),
+       A(u) = e^{j u^2} Int_u^inf e^{-j s^2} ds                     u in [0, FA_HI]
+  FH : -H(v) = (1 - F(X)) X, v = 1/X                              v in [0, 1/FA_HI^2]
+with F(X) = 2j sqrt(X) A(sqrt(X)), u = sqrt(X).
 
 Evaluation routes (multiple precision, 30 digits):
   * PT: the Fourier integral split at t = 0; t > 0 on the real axis with
@@ -26,10 +27,11 @@ Evaluation routes (multiple precision, 30 digits):
     Gauss-Legendre panels scaled with sqrt(|xi|).
   * FA/FH: A(u) = (sqrt(pi)/2) e^{-j pi/4} e^{j u^2} erfc(e^{j pi/4} u).
 
-Each piece is a degree-DEG polynomial in the local variable s in [-1, 1]
-fitted by Chebyshev interpolation (at DEG+1 Chebyshev points) and stored as
-monomial coefficients for Horner evaluation.  Two sets are emitted: float
-(for the FP32 kernel) and double (for the FP64 kernel).  The script prints
+Each piece is a degree-DEG polynomial fitted by Chebyshev interpolation (at
+DEG+1 Chebyshev points) and stored as monomial coefficients for Horner
+evaluation: in s = 2 (w - j) - 1 in [-1, 1] for the double set (FP64 kernel),
+in sigma = w - j in [0, 1) for the float set (FP32 kernel: one operation less
+per lookup; at degree 4 the shifted basis rounds no worse in FP32).  The script prints
 the maximum error of every table on a dense check grid.
 
 Layout.  The device locates a segment with one affine map, so the pieces are
@@ -41,6 +43,7 @@ laid out on a common index axis w (segment j covers w in [j, j + 1], s =
   transition    [FA | FH]:       w = NT u / FA_HI for u < FA_HI,
                 w = 2 NT - NT FA_HI^2 / X beyond (FH stored with its
                 variable reversed, so w grows with u across the junction).
+(s or sigma above is the local variable of segment j = floor(w).)
 Run:  python gen_fock_tables.py  (takes a few minutes)
 """
 import os
@@ -263,11 +266,23 @@ def build_table(name, lo, hi, nseg, deg, pool):
     return np.array(segs)   # (nseg, deg+1, nfun) complex
 
 
-def eval_table(tab, lo, hi, x, dtype):
+def to_sigma(tab):
+    """Monomial coefficients in s in [-1, 1] -> in sigma = (s + 1)/2 in [0, 1]."""
+    out = np.zeros_like(tab)
+    for k in range(tab.shape[1]):
+        c = np.polynomial.polynomial.polypow([-1.0, 2.0], k)   # (2 sigma - 1)^k
+        for m in range(k + 1):
+            out[:, m, :] += tab[:, k, :] * c[m]
+    return out
+
+
+def eval_table(tab, lo, hi, x, dtype, sigma=False):
     nseg = tab.shape[0]
     w = (hi - lo) / nseg
     idx = np.clip(np.floor((x - lo) / w).astype(int), 0, nseg - 1)
-    s = ((x - lo) / w - idx) * 2 - 1
+    s = (x - lo) / w - idx
+    if not sigma:
+        s = s * 2 - 1
     s = s.astype(dtype)
     out = np.zeros((x.size, tab.shape[2]), complex)
     for j in range(tab.shape[2]):
@@ -281,7 +296,7 @@ def eval_table(tab, lo, hi, x, dtype):
 
 
 def _fa(u):
-    return (A_of_u(u),)
+    return (2j * A_of_u(u),)
 
 
 def _fh(v):
@@ -289,8 +304,8 @@ def _fh(v):
 
 
 def _fhr(r):
-    # FH on the reversed variable r = 1 - FA_HI^2 / X in [0, 1]
-    return (H_of_v((1.0 - r) / FA_HI ** 2),)
+    # -H on the reversed variable r = 1 - FA_HI^2 / X in [0, 1]
+    return (-H_of_v((1.0 - r) / FA_HI ** 2),)
 
 
 FUNS = {
@@ -307,7 +322,7 @@ def check(name, tab, prec, pool, npts=41):
     fn, lo, hi = FUNS[name]
     x = lo + (hi - lo) * (np.arange(npts) + 0.37) / npts
     ref = np.array(pool.map(_call, [(name, float(xx)) for xx in x]))
-    got = eval_table(tab, lo, hi, x, np.float32 if prec == "f32" else np.float64)
+    got = eval_table(tab, lo, hi, x, np.float32 if prec == "f32" else np.float64, sigma=(prec == "f32"))
     return np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3))
 
 
@@ -350,6 +365,8 @@ def main(out_path):
             for name, nseg in (("CL", ncl), ("PT", npt), ("DS", nds), ("FA", nt), ("FHR", nt)):
                 fn, lo, hi = FUNS[name]
                 tab = build_table(name, lo, hi, nseg, deg, pool)
+                if prec == "f32":
+                    tab = to_sigma(tab)
                 err = check(name, tab, prec, pool, npts=397)
                 report.append("%s %s nseg=%d deg=%d max rel err %.2e" % (prec, name, nseg, deg, err))
                 print(report[-1], flush=True)

@@ -152,9 +152,10 @@ struct Workspace {
     uint8_t* mask = nullptr;
     void* rec = nullptr;
     uint8_t* flags = nullptr;
-    unsigned long long* counters = nullptr;   // [0..9] census, [12] queue length
+    unsigned long long* counters = nullptr;   // [0..9] census, [12] queue length, [13] visible-list length
     uint64_t* ent = nullptr;                  // candidate-path queue
     double* ent_th = nullptr;
+    uint64_t* vis = nullptr;                  // queue positions of the visible paths
     int64_t cap = 0;
     char* extra = nullptr;
     hipError_t alloc(int nb, int64_t n_rx, int n_f, int l_enc, int precision, bool need_flags, hipStream_t s,
@@ -172,7 +173,8 @@ struct Workspace {
         size_t o_cnt = up(o_flag + (need_flags ? (size_t)n_rx : 0));
         size_t o_ent = up(o_cnt + 16 * sizeof(unsigned long long));
         size_t o_th = up(o_ent + sizeof(uint64_t) * (size_t)cap);
-        size_t o_extra = up(o_th + sizeof(double) * (size_t)cap);
+        size_t o_vis = up(o_th + sizeof(double) * (size_t)cap);
+        size_t o_extra = up(o_vis + sizeof(uint64_t) * (size_t)cap);
         size_t total = o_extra + extra_bytes;
         hipError_t e = ws_get(total, s, &base);
         if (e != hipSuccess) return e;
@@ -184,6 +186,7 @@ struct Workspace {
         counters = (unsigned long long*)(base + o_cnt);
         ent = (uint64_t*)(base + o_ent);
         ent_th = (double*)(base + o_th);
+        vis = (uint64_t*)(base + o_vis);
         extra = extra_bytes ? base + o_extra : nullptr;
         return hipSuccess;
     }
@@ -205,7 +208,7 @@ int g_batch_tile = 128;
 int g_batch_bpc = 4;
 
 int pick_fc(int precision, int64_t n_rx, int n_f) {
-    int fc = precision == 0 ? 4 : 2;
+    int fc = precision == 0 ? 8 : 2;
     while (fc > 1 && (fc / 2 >= n_f || n_rx * ((n_f + fc - 1) / fc) < 256 * 2048)) fc /= 2;
     return fc;
 }
@@ -307,7 +310,7 @@ utd_status utd_smooth_field(const utd_scene* scene, const utd_bodies* bodies, co
     {
         ProfScope ps(UTD_K_OCCLUDE, s);
         e = utd::launch_paths(L, opt->precision, rx, bodies->sph, bodies->cyl, freqs, w.prep, w.fc, nodes, tris,
-                              w.mask, w.rec, flags, w.ent, w.ent_th, w.counters + 12, w.cap, s);
+                              w.mask, w.rec, flags, w.ent, w.ent_th, w.vis, w.counters + 12, w.cap, s);
     }
     int fc = pick_fc(opt->precision, n_rx, n_f);
     if (e == hipSuccess) {
@@ -338,7 +341,7 @@ utd_status utd_path_census(const utd_scene* scene, const utd_bodies* bodies, con
     if (e == hipSuccess)
         e = utd::launch_paths(L, 0, rx, bodies->sph, bodies->cyl, nullptr, w.prep, w.fc,
                               scene ? scene->d_nodes : nullptr, scene ? scene->d_tris : nullptr, w.mask, w.rec,
-                              w.flags, w.ent, w.ent_th, w.counters + 12, w.cap, s);
+                              w.flags, w.ent, w.ent_th, w.vis, w.counters + 12, w.cap, s);
     if (e == hipSuccess) e = utd::launch_census(nb > 0 ? (int64_t)nb * n_rx : 0, w.mask, n_rx, w.flags, w.counters, s);
     if (e == hipSuccess) e = hipMemcpyAsync(host, w.counters, sizeof host, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -372,7 +375,7 @@ utd_status utd_smooth_field_backward(const utd_scene* scene, const utd_bodies* b
     if (work) {
         ProfScope ps(UTD_K_OCCLUDE, s);
         e = utd::launch_paths(L, opt->precision, rx, bodies->sph, bodies->cyl, freqs, w.prep, w.fc, nodes, tris,
-                              w.mask, w.rec, w.flags, w.ent, w.ent_th, w.counters + 12, w.cap, s);
+                              w.mask, w.rec, w.flags, w.ent, w.ent_th, w.vis, w.counters + 12, w.cap, s);
     }
     if (e == hipSuccess) {
         ProfScope ps(UTD_K_BACKWARD, s);

@@ -107,20 +107,21 @@ template <typename R> __device__ __forceinline__ cplx<R> cmul(cplx<R> a, cplx<R>
     return cplx<R>{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
 }
 
-// sin and cos of 2 pi r for r in [-1/2, 1/2] (revolutions).  FP64: the device
+// sin and cos of 2 pi r for r in [-1/2, 1] (revolutions).  FP64: the device
 // library's sincospi.
 // FP32: the hardware v_sin_f32 / v_cos_f32, which take their argument in
-// revolutions (measured on gfx950 over [-1/2, 1/2]: max abs error 1.3e-7,
-// the same as a degree-9 polynomial after octant reduction).
+// revolutions (measured on gfx950 over [-1/2, 1/2] and over [0, 1): max abs
+// error 1.25e-7, the same as a degree-9 polynomial after octant reduction).
 __device__ __forceinline__ void sincos_rev(float r, float* s, float* c) {
     *s = __builtin_amdgcn_sinf(r);
     *c = __builtin_amdgcn_cosf(r);
 }
 __device__ __forceinline__ void sincos_rev(double r, double* s, double* c) { sincospi(2.0 * r, s, c); }
 
-// e^{-j theta} for theta given in revolutions as an FP64 value (reduced in FP64).
+// e^{-j theta} for theta given in revolutions as an FP64 value, reduced to
+// its fractional part in [0, 1) in FP64.
 template <typename R> __device__ __forceinline__ cplx<R> phase_rev(double rev) {
-    double fr = rev - rint(rev);
+    double fr = __builtin_amdgcn_fract(rev);
     R s, c;
     sincos_rev((R)fr, &s, &c);
     return cplx<R>{c, -s};

@@ -99,10 +99,12 @@ __device__ __forceinline__ void horner2(const T* seg, R s, R out[2]) {
 }
 
 // Segment j = floor(w) of index-axis position w clamped to [0, wmax] (wmax
-// just below the table's segment count) and the local variable s in [-1, 1].
+// just below the table's segment count) and the segment's local variable:
+// sigma = w - j in [0, 1) for the FP32 tables, s = 2 (w - j) - 1 in [-1, 1]
+// for the FP64 tables (their coefficients are stored in those variables).
 __device__ __forceinline__ int seg_at(float w, float wmax, float* s) {
     w = __builtin_amdgcn_fmed3f(w, 0.0f, wmax);
-    *s = fmaf(__builtin_amdgcn_fractf(w), 2.0f, -1.0f);
+    *s = __builtin_amdgcn_fractf(w);
     return (int)w;
 }
 __device__ __forceinline__ int seg_at(double w, double wmax, double* s) {
@@ -112,10 +114,12 @@ __device__ __forceinline__ int seg_at(double w, double wmax, double* s) {
 }
 template <typename T>
 __device__ __forceinline__ int seg_at(Dual<T> w, Dual<T> wmax, Dual<T>* s) {
+    constexpr bool kSigma = sizeof(T) == 4;
     T v = w.v < (T)0 ? (T)0 : (w.v > wmax.v ? wmax.v : w.v);
     int j = (int)v;
     // a clamped position does not move with the parameter
-    *s = Dual<T>((T)2 * (v - (T)j) - (T)1, v == w.v ? (T)2 * w.d : (T)0);
+    T dv = v == w.v ? w.d : (T)0;
+    *s = kSigma ? Dual<T>(v - (T)j, dv) : Dual<T>((T)2 * (v - (T)j) - (T)1, (T)2 * dv);
     return j;
 }
 
@@ -183,13 +187,13 @@ __device__ __forceinline__ void fock_kernel(const Tabs<typename BaseOf<R>::type>
     const bool big = tseg >= D::NT;
     R v[2];
     horner2<T, R>(tb.tf + __umul24((unsigned)tseg, 2 * D::ROWS), st, v);
-    // small u: G = F/sqrt(X) = 2j A, F = u G; large u: 1 - F = -H/X, G = F/u
-    R omr = -iX * v[0], omi = -iX * v[1];
+    // the table holds G = F/sqrt(X) below FA_HI and -H = (1 - F) X above
     cplx<R> G, omF;
-    G.re = big ? ((R)1 - omr) * iu : (R)-2 * v[1];
-    G.im = big ? -omi * iu : (R)2 * v[0];
-    omF.re = big ? omr : (R)1 - u * G.re;
-    omF.im = big ? omi : -u * G.im;
+    const R omr = iX * v[0], omi = iX * v[1];
+    G.re = big ? ((R)1 - omr) * iu : v[0];
+    G.im = big ? -omi * iu : v[1];
+    omF.re = big ? omr : (R)1 - u * v[0];
+    omF.im = big ? omi : -u * v[1];
 
     // --- regime table ------------------------------------------------------
     // creeping paths have xi >= 0 (regimes 0, 1), reflections xi <= 0 (1, 2);

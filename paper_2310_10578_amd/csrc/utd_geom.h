@@ -437,10 +437,11 @@ __device__ __forceinline__ void refl_point(const BodyPrepT<G>& b, const RxGeoT<G
                                            V3<G>* Q, V3<G>* n) {
     G s, c;
     gsincos(th, &s, &c);
+    V3<G> q, nn;   // written once at the end: keeps both in registers
     if (K == Kinds::Any && b.kind == 0) {
         V3<G> eT = v3(b.eT);
-        *n = c * eT + s * g.eperp;
-        *Q = v3(b.c) + b.a * (*n);
+        nn = c * eT + s * g.eperp;
+        q = v3(b.c) + b.a * nn;
     } else {
         G a = b.a;
         G tx = T.x - b.c[0], ty = T.y - b.c[1];
@@ -449,9 +450,11 @@ __device__ __forceinline__ void refl_point(const BodyPrepT<G>& b, const RxGeoT<G
         G lt = gsqrt((qx - tx) * (qx - tx) + (qy - ty) * (qy - ty));
         G lr = gsqrt((qx - rx) * (qx - rx) + (qy - ry) * (qy - ry));
         G zQ = T.z + (Rp.z - T.z) * lt / (lt + lr);
-        *Q = V3<G>{b.c[0] + qx, b.c[1] + qy, zQ};
-        *n = V3<G>{c, s, G(0.0)};
+        q = V3<G>{b.c[0] + qx, b.c[1] + qy, zQ};
+        nn = V3<G>{c, s, G(0.0)};
     }
+    *Q = q;
+    *n = nn;
 }
 
 // Reflected-field constants.  Caustic distances written as

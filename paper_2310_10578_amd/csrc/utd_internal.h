@@ -25,7 +25,7 @@ struct BatchParams {
 hipError_t launch_paths(const LaunchParams& L, int precision, const float* rx, const float* sph, const float* cyl,
                         const double* freqs, BodyPrep* prep, FreqConst* fcs, const float4* nodes, const float4* tris,
                         uint8_t* mask, void* rec, uint8_t* flags, uint64_t* ent, double* ent_th,
-                        unsigned long long* counter, int64_t cap, hipStream_t s);
+                        uint64_t* vis_list, unsigned long long* counter, int64_t cap, hipStream_t s);
 size_t path_record_bytes(int precision);
 hipError_t launch_field(const LaunchParams& L, int precision, int fc, const float* rx, const FreqConst* fcs,
                         const uint8_t* mask, const void* rec, uint8_t* flags, void* E, hipStream_t s);

@@ -62,6 +62,7 @@ __device__ __forceinline__ bool seg_blocked(d3 P0, d3 P1, const LaunchParams& L,
                                             const float* cyl, int skip, bool bodies, const float4* nodes,
                                             const float4* tris, int* stack, int stride) {
     if (bodies && blocked_by_bodies(P0, P1, L, sph, cyl, skip)) return true;
+    if (!nodes) return false;
     SegRay r = make_ray(P0, P1);
     return bvh_anyhit(nodes, tris, r, stack, stride);
 }
@@ -174,7 +175,24 @@ __device__ __forceinline__ int64_t wave_append(int cnt, unsigned long long* coun
     return (int64_t)base + x - cnt;
 }
 
-__global__ void k_zero_counter(unsigned long long* counter) { *counter = 0ull; }
+// One slot per flagged lane among the lanes active at the call (one atomic
+// per wavefront); the returned slot is meaningful for flagged lanes.
+__device__ __forceinline__ int64_t wave_append_active(bool flag, unsigned long long* counter) {
+    const uint64_t act = __ballot(1);
+    const uint64_t bal = __ballot(flag);
+    const int lane = threadIdx.x & 63;
+    const int leader = __builtin_ctzll(act);
+    unsigned long long base = 0;
+    if (lane == leader && bal) base = atomicAdd(counter, (unsigned long long)__popcll(bal));
+    base = __shfl(base, leader, 64);
+    return (int64_t)base + __popcll(bal & ((1ull << lane) - 1ull));
+}
+
+// Queue and visible-list lengths.
+__global__ void k_zero_counter(unsigned long long* counter) {
+    counter[0] = 0ull;
+    counter[1] = 0ull;
+}
 
 // Pass 1.  grid: x over receivers (blockDim 256), y over slot = 0 (receiver
 // flags, direct ray) or 1 + body.  Body constants of slot b are computed by
@@ -250,23 +268,24 @@ __global__ void __launch_bounds__(256) k_cand(LaunchParams L, const float* __res
     }
 }
 
-// Pass 2: one lane per queue entry (grid-stride).
+// Pass 2: one lane per queue entry (grid-stride): the path's legs against
+// the bodies and the BVH.  A visible path ORs its bit into the (rx, body)
+// mask and joins the visible list; its record is written by pass 3.  Kept
+// free of the record arithmetic so the traversal runs at higher occupancy.
 template <typename R>
 __device__ __forceinline__ void vis_body(const LaunchParams& L, const float* __restrict__ rx,
                                          const float* __restrict__ sph, const float* __restrict__ cyl,
                                          const BodyPrep* __restrict__ prep, const float4* __restrict__ nodes,
                                          const float4* __restrict__ tris, const uint64_t* __restrict__ ent,
-                                         const double* __restrict__ ent_th,
-                                         const unsigned long long* __restrict__ counter, int64_t cap,
-                                         uint8_t* __restrict__ mask, uint8_t* __restrict__ flags,
-                                         PathRec<R>* __restrict__ rec, int* stack) {
+                                         const double* __restrict__ ent_th, unsigned long long* __restrict__ counter,
+                                         int64_t cap, uint8_t* __restrict__ mask, uint8_t* __restrict__ flags,
+                                         uint64_t* __restrict__ vis_list, int* stack) {
     int* stk = stack + threadIdx.x;
     const int stride = 256;
-    int64_t total = (int64_t)*counter;
+    int64_t total = (int64_t)counter[0];
     total = total < cap ? total : cap;
     const d3 T = mk(L.T[0], L.T[1], L.T[2]);
     const bool bo = L.bodies_occlude != 0;
-    const int NS = rec_slots(L);
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
          q += (int64_t)gridDim.x * blockDim.x) {
         const uint64_t en = ent[q];
@@ -283,35 +302,71 @@ __device__ __forceinline__ void vis_body(const LaunchParams& L, const float* __r
         const int b = (int)bb;
         const BodyPrep P = prep[b];
         RxGeo g = rx_geo(P, R3);
-        const bool refl = bit == kBitRefl;
-        const int ell = bit >> 1, sgn = (bit & 1) ? -1 : 1;
         PathPts pts;
-        d3 Q, n;
-        const double th = ent_th[q];
-        if (refl) {
-            refl_point<double>(P, g, R3, T, th, &Q, &n);
+        if (bit == kBitRefl) {
+            d3 Q, n;
+            refl_point<double>(P, g, R3, T, ent_th[q], &Q, &n);
             pts.P0 = T; pts.P1 = Q; pts.P2 = Q; pts.P3 = R3;
         } else {
+            const int ell = bit >> 1, sgn = (bit & 1) ? -1 : 1;
             bool cz;
             if (P.kind == 0)
                 sphere_creep<R, double>(P, g, R3, T, L, sgn, ell, &cz, (PathEval<R>*)nullptr, &pts);
             else
                 cyl_creep<R, double>(P, g, R3, T, L, sgn, ell, (PathEval<R>*)nullptr, &pts);
         }
-        bool vis = true;
-#pragma unroll 1
-        for (int leg = 0; leg < 2 && vis; ++leg) {
-            d3 a = leg ? pts.P2 : pts.P0, c = leg ? pts.P3 : pts.P1;
-            vis = !seg_blocked(a, c, L, sph, cyl, b, bo, nodes, tris, stk, stride);
+        bool vis = !seg_blocked(pts.P0, pts.P1, L, sph, cyl, b, bo, nodes, tris, stk, stride);
+        if (vis) vis = !seg_blocked(pts.P2, pts.P3, L, sph, cyl, b, bo, nodes, tris, stk, stride);
+        if (vis) {
+            // mask bytes of one pair can be set by concurrent lanes: OR into the word
+            const int64_t mb = (int64_t)b * L.n_rx + i;
+            atomicOr(reinterpret_cast<unsigned int*>(mask + (mb & ~(int64_t)3)), (1u << bit) << (8 * (mb & 3)));
         }
-        if (!vis) continue;
-        // mask bytes of one pair can be set by concurrent lanes: OR into the word
-        const int64_t mb = (int64_t)b * L.n_rx + i;
-        atomicOr(reinterpret_cast<unsigned int*>(mask + (mb & ~(int64_t)3)), (1u << bit) << (8 * (mb & 3)));
+        const int64_t k = wave_append_active(vis, counter + 1);
+        if (vis) vis_list[k] = (uint64_t)q;
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_vis(LaunchParams L, const float* __restrict__ rx,
+                                             const float* __restrict__ sph, const float* __restrict__ cyl,
+                                             const BodyPrep* __restrict__ prep, const float4* __restrict__ nodes,
+                                             const float4* __restrict__ tris, const uint64_t* __restrict__ ent,
+                                             const double* __restrict__ ent_th,
+                                             unsigned long long* __restrict__ counter, int64_t cap,
+                                             uint8_t* __restrict__ mask, uint8_t* __restrict__ flags,
+                                             uint64_t* __restrict__ vis_list) {
+    __shared__ int stack[kStackDepth * 256];
+    vis_body<R>(L, rx, sph, cyl, prep, nodes, tris, ent, ent_th, counter, cap, mask, flags, vis_list, stack);
+}
+
+// Pass 3: one lane per visible path (grid-stride over the visible list): the
+// frequency-independent constants of the path, packed into its record slot.
+template <typename R>
+__global__ void __launch_bounds__(256) k_rec(LaunchParams L, const float* __restrict__ rx,
+                                             const BodyPrep* __restrict__ prep, const uint64_t* __restrict__ ent,
+                                             const double* __restrict__ ent_th,
+                                             const unsigned long long* __restrict__ counter,
+                                             const uint64_t* __restrict__ vis_list, PathRec<R>* __restrict__ rec) {
+    const int64_t n = (int64_t)counter[1];
+    const d3 T = mk(L.T[0], L.T[1], L.T[2]);
+    const int NS = rec_slots(L);
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = (int64_t)vis_list[k];
+        const uint64_t en = ent[q];
+        const int64_t i = (int64_t)(en & 0xffffffffu);
+        const int b = (int)((en >> 32) & 0xffffu);
+        const int bit = (int)(en >> 48);
+        const d3 R3 = mk(rx[3 * i], rx[3 * i + 1], rx[3 * i + 2]);
+        const BodyPrep P = prep[b];
+        RxGeo g = rx_geo(P, R3);
         PathEval<R> pe;
-        if (refl) {
-            refl_eval<R, double>(P, Q, n, R3, T, L, &pe);
+        if (bit == kBitRefl) {
+            d3 Q, n3;
+            refl_point<double>(P, g, R3, T, ent_th[q], &Q, &n3);
+            refl_eval<R, double>(P, Q, n3, R3, T, L, &pe);
         } else {
+            const int ell = bit >> 1, sgn = (bit & 1) ? -1 : 1;
             bool cz;
             if (P.kind == 0)
                 sphere_creep<R, double>(P, g, R3, T, L, sgn, ell, &cz, &pe, nullptr);
@@ -322,55 +377,34 @@ __device__ __forceinline__ void vis_body(const LaunchParams& L, const float* __r
     }
 }
 
-template <typename R>
-__global__ void __launch_bounds__(256) k_vis(LaunchParams L, const float* __restrict__ rx,
-                                             const float* __restrict__ sph, const float* __restrict__ cyl,
-                                             const BodyPrep* __restrict__ prep, const float4* __restrict__ nodes,
-                                             const float4* __restrict__ tris, const uint64_t* __restrict__ ent,
-                                             const double* __restrict__ ent_th,
-                                             const unsigned long long* __restrict__ counter, int64_t cap,
-                                             uint8_t* __restrict__ mask, uint8_t* __restrict__ flags,
-                                             PathRec<R>* __restrict__ rec) {
-    __shared__ int stack[kStackDepth * 256];
-    vis_body<R>(L, rx, sph, cyl, prep, nodes, tris, ent, ent_th, counter, cap, mask, flags, rec, stack);
-}
-
-// Three waves per SIMD (168 VGPRs, a few spills) for long queues: more
-// traversals in flight hide more of their memory latency.
-template <typename R>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
-k_vis_occ3(LaunchParams L, const float* __restrict__ rx, const float* __restrict__ sph, const float* __restrict__ cyl,
-           const BodyPrep* __restrict__ prep, const float4* __restrict__ nodes, const float4* __restrict__ tris,
-           const uint64_t* __restrict__ ent, const double* __restrict__ ent_th,
-           const unsigned long long* __restrict__ counter, int64_t cap, uint8_t* __restrict__ mask,
-           uint8_t* __restrict__ flags, PathRec<R>* __restrict__ rec) {
-    __shared__ int stack[kStackDepth * 256];
-    vis_body<R>(L, rx, sph, cyl, prep, nodes, tris, ent, ent_th, counter, cap, mask, flags, rec, stack);
-}
-
 // Single-pass visibility for scenes without triangles (bodies only): the
 // per-pair work is short and uniform there, so one lane per (receiver, body)
 // pair decides and records everything without a queue.  grid: x over
 // receivers (blockDim 256), y over slot = 0 (receiver flags) or 1 + body;
 // same outputs as k_cand + k_vis.
+// Scenes of bodies only (no triangles): one pass, no queue.
+// grid (ceil(n_rx / 64), 1 + bodies), 64 K threads, K = 2 (l_enc + 1) + 1
+// path kinds.  Slot 0: one lane per receiver (64 K receivers per block):
+// inside / source-inside flags and the direct ray.  Slot 1 + b: wave k of the
+// block takes path kind k of the block's 64 receivers (creeping (ell, side) =
+// (k >> 1, k & 1), the reflection for k = K - 1), so every wavefront runs one
+// kind of path; the mask bits of a receiver meet in LDS.
 template <typename R>
-__device__ __forceinline__ void paths_body(const LaunchParams& L, const float* __restrict__ rx,
-                                           const float* __restrict__ sph, const float* __restrict__ cyl,
-                                           const double* __restrict__ freqs, BodyPrep* __restrict__ prep,
-                                           FreqConst* __restrict__ fcs, const float4* __restrict__ nodes,
-                                           const float4* __restrict__ tris, uint8_t* __restrict__ mask,
-                                           PathRec<R>* __restrict__ rec, uint8_t* __restrict__ flags, int* stack) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int slot = blockIdx.y;
-    if (slot == 0 && blockIdx.x == 0 && freqs)
-        for (int f = threadIdx.x; f < L.n_f; f += blockDim.x) fcs[f] = freq_const(freqs[f]);
-    if (i >= L.n_rx) return;
-    int* stk = stack + threadIdx.x;
-    const int stride = 256;
-    d3 R3 = mk(rx[3 * i], rx[3 * i + 1], rx[3 * i + 2]);
-    d3 T = mk(L.T[0], L.T[1], L.T[2]);
-    int nb = L.n_sph + L.n_cyl;
+__global__ void __launch_bounds__(448) k_paths(LaunchParams L, const float* __restrict__ rx,
+                                               const float* __restrict__ sph, const float* __restrict__ cyl,
+                                               const double* __restrict__ freqs, BodyPrep* __restrict__ prep,
+                                               FreqConst* __restrict__ fcs, uint8_t* __restrict__ mask,
+                                               PathRec<R>* __restrict__ rec, uint8_t* __restrict__ flags) {
+    __shared__ unsigned s_m[64];
+    const int slot = blockIdx.y;
+    const d3 T = mk(L.T[0], L.T[1], L.T[2]);
+    const int nb = L.n_sph + L.n_cyl;
     if (slot == 0) {
+        if (blockIdx.x == 0 && freqs)
+            for (int f = threadIdx.x; f < L.n_f; f += blockDim.x) fcs[f] = freq_const(freqs[f]);
+        const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        if (i >= L.n_rx) return;
+        const d3 R3 = mk(rx[3 * i], rx[3 * i + 1], rx[3 * i + 2]);
         uint8_t f = 0;
         bool inside = false, tx_inside = false;
         for (int b = 0; b < nb; ++b) {
@@ -379,69 +413,64 @@ __device__ __forceinline__ void paths_body(const LaunchParams& L, const float* _
         }
         if (tx_inside) f |= kFlagTxInside;
         if (inside) f |= kFlagInside;
-        if (!inside && !tx_inside && !seg_blocked(T, R3, L, sph, cyl, -1, true, nodes, tris, stk, stride))
+        if (!inside && !tx_inside && !seg_blocked(T, R3, L, sph, cyl, -1, true, nullptr, nullptr, nullptr, 0))
             f |= kFlagLos;
         flags[i] = f;
         return;
     }
-    int b = slot - 1;
+    const int lane = threadIdx.x & 63, kind = threadIdx.x >> 6;
+    const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+    if (threadIdx.x < 64) s_m[lane] = 0u;
+    __syncthreads();
+    const int b = slot - 1;
     const BodyPrep P = body_prep(L.T, sph, L.n_sph, cyl, b);
     if (blockIdx.x == 0 && threadIdx.x == 0) prep[b] = P;
-    RxGeo g = rx_geo(P, R3);
-    uint8_t m = 0;
     const int NS = rec_slots(L);
-    bool bo = L.bodies_occlude != 0;
-    for (int ell = 0; ell <= L.l_enc; ++ell) {
-        for (int side = 0; side < 2; ++side) {
-            int sgn = side == 0 ? 1 : -1;
+    const bool bo = L.bodies_occlude != 0;
+    unsigned m = 0u;
+    if (i < L.n_rx) {
+        const d3 R3 = mk(rx[3 * i], rx[3 * i + 1], rx[3 * i + 2]);
+        RxGeo g = rx_geo(P, R3);
+        if (kind < NS - 1) {
+            const int ell = kind >> 1, sgn = (kind & 1) ? -1 : 1;
             PathPts pts;
             bool ok, caus = false;
             if (P.kind == 0)
                 ok = sphere_creep<R, double>(P, g, R3, T, L, sgn, ell, &caus, (PathEval<R>*)nullptr, &pts);
             else
                 ok = cyl_creep<R, double>(P, g, R3, T, L, sgn, ell, (PathEval<R>*)nullptr, &pts);
-            if (caus) m |= (uint8_t)(1u << kBitCaustic);
-            if (!ok) continue;
-            if (seg_blocked(pts.P0, pts.P1, L, sph, cyl, b, bo, nodes, tris, stk, stride)) continue;
-            if (seg_blocked(pts.P2, pts.P3, L, sph, cyl, b, bo, nodes, tris, stk, stride)) continue;
-            m |= (uint8_t)(1u << (2 * ell + side));
-            PathEval<R> pe;
-            bool cz;
-            if (P.kind == 0)
-                sphere_creep<R, double>(P, g, R3, T, L, sgn, ell, &cz, &pe, nullptr);
-            else
-                cyl_creep<R, double>(P, g, R3, T, L, sgn, ell, &pe, nullptr);
-            pack(pe, &rec[((int64_t)b * NS + rec_slot(L, 2 * ell + side)) * L.n_rx + i]);
+            if (caus) m |= 1u << kBitCaustic;
+            if (ok && !seg_blocked(pts.P0, pts.P1, L, sph, cyl, b, bo, nullptr, nullptr, nullptr, 0) &&
+                !seg_blocked(pts.P2, pts.P3, L, sph, cyl, b, bo, nullptr, nullptr, nullptr, 0)) {
+                m |= 1u << kind;
+                PathEval<R> pe;
+                bool cz;
+                if (P.kind == 0)
+                    sphere_creep<R, double>(P, g, R3, T, L, sgn, ell, &cz, &pe, nullptr);
+                else
+                    cyl_creep<R, double>(P, g, R3, T, L, sgn, ell, &pe, nullptr);
+                pack(pe, &rec[((int64_t)b * NS + rec_slot(L, kind)) * L.n_rx + i]);
+            }
+        } else if (kind == NS - 1) {
+            double th = 0.0;
+            if (L.lit_branch && refl_angle(P, g, R3, T, &th)) {
+                d3 Q, n;
+                refl_point<double>(P, g, R3, T, th, &Q, &n);
+                if (!seg_blocked(T, Q, L, sph, cyl, b, bo, nullptr, nullptr, nullptr, 0) &&
+                    !seg_blocked(Q, R3, L, sph, cyl, b, bo, nullptr, nullptr, nullptr, 0)) {
+                    m |= 1u << kBitRefl;
+                    PathEval<R> pe;
+                    refl_eval<R, double>(P, Q, n, R3, T, L, &pe);
+                    pack(pe, &rec[((int64_t)b * NS + rec_slot(L, kBitRefl)) * L.n_rx + i]);
+                }
+            }
         }
     }
-    double th = 0.0;
-    if (L.lit_branch && refl_angle(P, g, R3, T, &th)) {
-        d3 Q, n;
-        refl_point<double>(P, g, R3, T, th, &Q, &n);
-        if (!seg_blocked(T, Q, L, sph, cyl, b, bo, nodes, tris, stk, stride) &&
-            !seg_blocked(Q, R3, L, sph, cyl, b, bo, nodes, tris, stk, stride)) {
-            m |= (uint8_t)(1u << kBitRefl);
-            PathEval<R> pe;
-            refl_eval<R, double>(P, Q, n, R3, T, L, &pe);
-            pack(pe, &rec[((int64_t)b * NS + rec_slot(L, kBitRefl)) * L.n_rx + i]);
-        }
-    }
-    mask[(int64_t)b * L.n_rx + i] = m;
+    if (m) atomicOr(&s_m[lane], m);
+    __syncthreads();
+    if (threadIdx.x < 64 && i < L.n_rx) mask[(int64_t)b * L.n_rx + i] = (uint8_t)s_m[lane];
 }
 
-template <typename R>
-__global__ void __launch_bounds__(256) k_paths(LaunchParams L, const float* __restrict__ rx,
-                                               const float* __restrict__ sph, const float* __restrict__ cyl,
-                                               const double* __restrict__ freqs, BodyPrep* __restrict__ prep,
-                                               FreqConst* __restrict__ fcs, const float4* __restrict__ nodes,
-                                               const float4* __restrict__ tris, uint8_t* __restrict__ mask,
-                                               PathRec<R>* __restrict__ rec, uint8_t* __restrict__ flags) {
-    __shared__ int stack[kStackDepth * 256];
-    paths_body<R>(L, rx, sph, cyl, freqs, prep, fcs, nodes, tris, mask, rec, flags, stack);
-}
-
-// ---------------------------------------------------------------------------
-// field
 // ---------------------------------------------------------------------------
 template <typename R> struct FreqC;
 template <> struct FreqC<float> {
@@ -662,11 +691,14 @@ template <typename R>
 static hipError_t launch_paths_t(const LaunchParams& L, const float* rx, const float* sph, const float* cyl,
                                  const double* freqs, BodyPrep* prep, FreqConst* fcs, const float4* nodes,
                                  const float4* tris, uint8_t* mask, void* rec, uint8_t* flags, uint64_t* ent,
-                                 double* ent_th, unsigned long long* counter, int64_t cap, hipStream_t s) {
+                                 double* ent_th, uint64_t* vis_list, unsigned long long* counter, int64_t cap,
+                                 hipStream_t s) {
     int nb = L.n_sph + L.n_cyl;
     if (!nodes) {
-        dim3 grid((unsigned)((L.n_rx + 255) / 256), (unsigned)(nb + 1));
-        hipLaunchKernelGGL((k_paths<R>), grid, dim3(256), 0, s, L, rx, sph, cyl, freqs, prep, fcs, nodes, tris, mask,
+        // one wavefront per path kind and 64 receivers (slot 0: 64 K receivers per block)
+        const int K = 2 * (L.l_enc + 1) + 1;
+        dim3 grid((unsigned)((L.n_rx + 63) / 64), (unsigned)(nb + 1));
+        hipLaunchKernelGGL((k_paths<R>), grid, dim3(64 * K), 0, s, L, rx, sph, cyl, freqs, prep, fcs, mask,
                            (PathRec<R>*)rec, flags);
         return hipGetLastError();
     }
@@ -677,26 +709,27 @@ static hipError_t launch_paths_t(const LaunchParams& L, const float* rx, const f
     hipLaunchKernelGGL((k_cand<R>), grid, dim3(256), 0, s, L, rx, sph, cyl, freqs, prep, fcs, mask, flags, ent, ent_th,
                        counter, cap);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    // persistent grid over the queue: enough workgroups to fill the chip
+    // persistent grids over the queue and the visible list: enough
+    // workgroups to fill the chip
     int64_t vgrid = (cap + 255) / 256;
     vgrid = vgrid < 1 ? 1 : (vgrid > 256 * 12 ? 256 * 12 : vgrid);
-    if (vgrid * 4 > 256 * 4 * 2 * 2)
-        hipLaunchKernelGGL((k_vis_occ3<R>), dim3((unsigned)vgrid), dim3(256), 0, s, L, rx, sph, cyl, prep, nodes,
-                           tris, ent, ent_th, counter, cap, mask, flags, (PathRec<R>*)rec);
-    else
-        hipLaunchKernelGGL((k_vis<R>), dim3((unsigned)vgrid), dim3(256), 0, s, L, rx, sph, cyl, prep, nodes, tris,
-                           ent, ent_th, counter, cap, mask, flags, (PathRec<R>*)rec);
+    hipLaunchKernelGGL((k_vis<R>), dim3((unsigned)vgrid), dim3(256), 0, s, L, rx, sph, cyl, prep, nodes, tris, ent,
+                       ent_th, counter, cap, mask, flags, vis_list);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    int64_t rgrid = vgrid < 256 * 8 ? vgrid : 256 * 8;
+    hipLaunchKernelGGL((k_rec<R>), dim3((unsigned)rgrid), dim3(256), 0, s, L, rx, prep, ent, ent_th, counter,
+                       vis_list, (PathRec<R>*)rec);
     return hipGetLastError();
 }
 
 hipError_t launch_paths(const LaunchParams& L, int precision, const float* rx, const float* sph, const float* cyl,
                         const double* freqs, BodyPrep* prep, FreqConst* fcs, const float4* nodes, const float4* tris,
                         uint8_t* mask, void* rec, uint8_t* flags, uint64_t* ent, double* ent_th,
-                        unsigned long long* counter, int64_t cap, hipStream_t s) {
+                        uint64_t* vis_list, unsigned long long* counter, int64_t cap, hipStream_t s) {
     return precision == 0 ? launch_paths_t<float>(L, rx, sph, cyl, freqs, prep, fcs, nodes, tris, mask, rec, flags,
-                                                  ent, ent_th, counter, cap, s)
+                                                  ent, ent_th, vis_list, counter, cap, s)
                           : launch_paths_t<double>(L, rx, sph, cyl, freqs, prep, fcs, nodes, tris, mask, rec, flags,
-                                                   ent, ent_th, counter, cap, s);
+                                                   ent, ent_th, vis_list, counter, cap, s);
 }
 
 size_t path_record_bytes(int precision) { return precision == 0 ? sizeof(PathRec<float>) : sizeof(PathRec<double>); }
@@ -716,7 +749,8 @@ hipError_t launch_field(const LaunchParams& L, int precision, int fc, const floa
         switch (fc) {
             case 1: return launch_field_fc<float, 1>(L, rx, fcs, mask, rec, flags, e, s);
             case 2: return launch_field_fc<float, 2>(L, rx, fcs, mask, rec, flags, e, s);
-            default: return launch_field_fc<float, 4>(L, rx, fcs, mask, rec, flags, e, s);
+            case 4: return launch_field_fc<float, 4>(L, rx, fcs, mask, rec, flags, e, s);
+            default: return launch_field_fc<float, 8>(L, rx, fcs, mask, rec, flags, e, s);
         }
     }
     double* e = (double*)E;
