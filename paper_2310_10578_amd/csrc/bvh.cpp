@@ -1,6 +1,14 @@
 // Host-side BVH builder for the occluder triangles (binned SAH, two children
 // per node, leaves of at most 4 triangles).  The visibility steps U of
-// Eqs. (1)-(2) are decided by walking this tree on the GPU (utd_bvh.h).
+// Eqs. (1)-(2) are decided by walking these trees on the GPU (utd_bvh.h).
+//
+// Two trees share the output arrays: the first (root node 0) holds the
+// interior triangles, the second (root node `broot`, when there is one) the
+// boundary triangles, those lying in a face plane of the scene's bounding
+// box (the walls, floor and ceiling of a room).  A segment with both end
+// points inside the closed box meets such a triangle at most at an end point,
+// which the open-segment test excludes, so the device walks the second tree
+// only for segments reaching outside the box.
 //
 // Output layout (read by the device traversal):
 //   node  = 4 float4: (lo0.xyz, hi0.x) (hi0.yz, lo1.xy) (lo1.z, hi1.xyz) (c0, n0, c1, n1)
@@ -121,22 +129,23 @@ int64_t split(std::vector<Prim>& P, int64_t b, int64_t e) {
     return mid;
 }
 
-}  // namespace
-
-int build_bvh(const float* tri, int64_t n, int max_depth, HostBvh* out) {
-    *out = HostBvh();
-    if (n <= 0) return 0;
+// Appends the tree over tri[ids] to the output arrays: nodes numbered from
+// node_base, triangles from tri_base (references are absolute).  An empty set
+// gives one node with two empty children.
+void build_tree(const float* tri, const std::vector<int64_t>& ids, int max_depth, int node_base, int64_t tri_base,
+                std::vector<float>& out_nodes, std::vector<float>& out_tris, int* depth_out) {
+    const int64_t n = (int64_t)ids.size();
     std::vector<Prim> P((size_t)n);
     for (int64_t i = 0; i < n; ++i) {
         Prim& p = P[(size_t)i];
-        for (int v = 0; v < 3; ++v) p.box.grow(tri + 9 * i + 3 * v);
+        for (int v = 0; v < 3; ++v) p.box.grow(tri + 9 * ids[(size_t)i] + 3 * v);
         for (int a = 0; a < 3; ++a) p.c[a] = 0.5f * (p.box.lo[a] + p.box.hi[a]);
-        p.idx = i;
+        p.idx = ids[(size_t)i];
     }
     std::vector<Node> nodes(1);
     struct Task { int node; int64_t b, e; int depth; };
     std::vector<Task> todo;
-    todo.push_back({0, 0, n, 1});
+    if (n > 0) todo.push_back({0, 0, n, 1});
     int depth_seen = 1;
     while (!todo.empty()) {
         Task t = todo.back();
@@ -169,31 +178,66 @@ int build_bvh(const float* tri, int64_t n, int max_depth, HostBvh* out) {
             nodes[(size_t)t.node].ch[c] = ch;
         }
     }
-    out->n_nodes = (int64_t)nodes.size();
-    out->depth = depth_seen;
-    out->nodes = (float*)std::malloc(sizeof(float) * 16 * nodes.size());
-    out->tris = (float*)std::malloc(sizeof(float) * 12 * (size_t)n);
-    if (!out->nodes || !out->tris) { free_bvh(out); return -1; }
     for (size_t k = 0; k < nodes.size(); ++k) {
-        float* q = out->nodes + 16 * k;
+        float q[16];
         const Child& a = nodes[k].ch[0];
         const Child& b = nodes[k].ch[1];
         q[0] = a.box.lo[0]; q[1] = a.box.lo[1]; q[2] = a.box.lo[2]; q[3] = a.box.hi[0];
         q[4] = a.box.hi[1]; q[5] = a.box.hi[2]; q[6] = b.box.lo[0]; q[7] = b.box.lo[1];
         q[8] = b.box.lo[2]; q[9] = b.box.hi[0]; q[10] = b.box.hi[1]; q[11] = b.box.hi[2];
-        int refs[4] = {a.ref, a.count, b.ref, b.count};
+        auto absref = [&](const Child& ch) {
+            if (ch.ref < 0) return -1;
+            return ch.count > 0 ? (int)(ch.ref + tri_base) : ch.ref + node_base;
+        };
+        int refs[4] = {absref(a), a.count, absref(b), b.count};
         std::memcpy(q + 12, refs, sizeof refs);
+        out_nodes.insert(out_nodes.end(), q, q + 16);
     }
     for (int64_t i = 0; i < n; ++i) {
-        const float* s = tri + 9 * P[(size_t)i].idx;
-        float* d = out->tris + 12 * i;
+        const float* src = tri + 9 * P[(size_t)i].idx;
         for (int v = 0; v < 3; ++v) {
-            d[4 * v + 0] = s[3 * v + 0];
-            d[4 * v + 1] = s[3 * v + 1];
-            d[4 * v + 2] = s[3 * v + 2];
-            d[4 * v + 3] = 0.0f;
+            out_tris.push_back(src[3 * v + 0]);
+            out_tris.push_back(src[3 * v + 1]);
+            out_tris.push_back(src[3 * v + 2]);
+            out_tris.push_back(0.0f);
         }
     }
+    *depth_out = depth_seen;
+}
+
+}  // namespace
+
+int build_bvh(const float* tri, int64_t n, int max_depth, HostBvh* out) {
+    *out = HostBvh();
+    if (n <= 0) return 0;
+    Box scene;
+    for (int64_t i = 0; i < 3 * n; ++i) scene.grow(tri + 3 * i);
+    std::vector<int64_t> inner, bound;
+    for (int64_t i = 0; i < n; ++i) {
+        const float* t = tri + 9 * i;
+        bool on_face = false;
+        for (int a = 0; a < 3 && !on_face; ++a)
+            on_face = (t[a] == scene.lo[a] && t[3 + a] == scene.lo[a] && t[6 + a] == scene.lo[a]) ||
+                      (t[a] == scene.hi[a] && t[3 + a] == scene.hi[a] && t[6 + a] == scene.hi[a]);
+        (on_face ? bound : inner).push_back(i);
+    }
+    std::vector<float> nodes, tris;
+    int d0 = 0, d1 = 0;
+    build_tree(tri, inner, max_depth, 0, 0, nodes, tris, &d0);
+    out->broot = -1;
+    if (!bound.empty()) {
+        out->broot = (int64_t)(nodes.size() / 16);
+        build_tree(tri, bound, max_depth, (int)out->broot, (int64_t)inner.size(), nodes, tris, &d1);
+    }
+    for (int a = 0; a < 3; ++a) { out->lo[a] = scene.lo[a]; out->hi[a] = scene.hi[a]; }
+    out->n_nodes = (int64_t)(nodes.size() / 16);
+    out->n_inner_tris = (int64_t)inner.size();
+    out->depth = std::max(d0, d1);
+    out->nodes = (float*)std::malloc(sizeof(float) * nodes.size());
+    out->tris = (float*)std::malloc(sizeof(float) * tris.size());
+    if (!out->nodes || !out->tris) { free_bvh(out); return -1; }
+    std::memcpy(out->nodes, nodes.data(), sizeof(float) * nodes.size());
+    std::memcpy(out->tris, tris.data(), sizeof(float) * tris.size());
     return 0;
 }
 

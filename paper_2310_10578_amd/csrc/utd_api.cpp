@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -16,8 +17,11 @@
 #include "utd_internal.h"
 
 struct utd_scene {
+    uint64_t id = 0;                     // unique per created scene (graph keys)
     int64_t n_tri = 0;
     int64_t n_nodes = 0;
+    int64_t broot = -1;                  // boundary-triangle tree root (-1: none)
+    float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
     int depth = 0;
     float4* d_nodes = nullptr;
     float4* d_tris = nullptr;
@@ -89,9 +93,14 @@ utd_status check_common(const utd_bodies* bodies, const utd_source* tx, const fl
     return UTD_OK;
 }
 
-utd::LaunchParams make_params(const utd_bodies* bodies, const utd_source* tx, int64_t n_rx, int n_f,
-                              const utd_options* opt) {
+utd::LaunchParams make_params(const utd_scene* scene, const utd_bodies* bodies, const utd_source* tx, int64_t n_rx,
+                              int n_f, const utd_options* opt) {
     utd::LaunchParams L;
+    L.broot = scene ? (int)scene->broot : -1;
+    for (int a = 0; a < 3; ++a) {
+        L.blo[a] = scene ? scene->lo[a] : 0.0f;
+        L.bhi[a] = scene ? scene->hi[a] : 0.0f;
+    }
     for (int a = 0; a < 3; ++a) { L.T[a] = tx->pos[a]; L.p[a] = tx->dipole[a]; }
     L.amp = tx->amplitude;
     L.n_sph = (int)bodies->n_sph;
@@ -105,8 +114,6 @@ utd::LaunchParams make_params(const utd_bodies* bodies, const utd_source* tx, in
     return L;
 }
 
-// Frequencies per lane: more frequencies per lane amortise the path geometry,
-// fewer keep enough lanes in flight.
 // Stream-ordered scratch of one call: body constants, frequency constants,
 // path masks, reflection angles, flags (when the caller passed none) and
 // counters.
@@ -207,6 +214,8 @@ std::map<int, BatchState> g_batch;
 int g_batch_tile = 128;
 int g_batch_bpc = 4;
 
+// Frequencies per lane: more frequencies per lane amortise the path geometry,
+// fewer keep enough lanes in flight.
 int pick_fc(int precision, int64_t n_rx, int n_f) {
     int fc = precision == 0 ? 8 : 2;
     while (fc > 1 && (fc / 2 >= n_f || n_rx * ((n_f + fc - 1) / fc) < 256 * 2048)) fc /= 2;
@@ -256,6 +265,8 @@ utd_status utd_scene_create(const float* tri, int64_t n_tri, utd_scene** out) {
     if (n_tri > ((int64_t)1 << 30)) return fail(UTD_E_ARG, "too many triangles");
     utd_scene* s = new (std::nothrow) utd_scene();
     if (!s) return fail(UTD_E_OOM, "host allocation failed");
+    static std::atomic<uint64_t> next_id{1};
+    s->id = next_id++;
     s->n_tri = n_tri;
     if (n_tri > 0) {
         utd::HostBvh b;
@@ -264,6 +275,8 @@ utd_status utd_scene_create(const float* tri, int64_t n_tri, utd_scene** out) {
             return fail(UTD_E_OOM, "BVH build: host allocation failed");
         }
         s->n_nodes = b.n_nodes;
+        s->broot = b.broot;
+        for (int a = 0; a < 3; ++a) { s->lo[a] = b.lo[a]; s->hi[a] = b.hi[a]; }
         s->depth = b.depth;
         hipError_t e = hipMalloc(&s->d_nodes, sizeof(float4) * 4 * b.n_nodes);
         if (e == hipSuccess) e = hipMalloc(&s->d_tris, sizeof(float4) * 3 * n_tri);
@@ -299,7 +312,7 @@ utd_status utd_smooth_field(const utd_scene* scene, const utd_bodies* bodies, co
     if (!E_out) return fail(UTD_E_ARG, "E_out is NULL");
     hipError_t e = hipSuccess;
     hipStream_t s = (hipStream_t)stream;
-    utd::LaunchParams L = make_params(bodies, tx, n_rx, n_f, opt);
+    utd::LaunchParams L = make_params(scene, bodies, tx, n_rx, n_f, opt);
     int nb = L.n_sph + L.n_cyl;
     Workspace w;
     e = w.alloc(nb, n_rx, n_f, opt->l_enc, opt->precision, rx_flags == nullptr, s);
@@ -331,7 +344,7 @@ utd_status utd_path_census(const utd_scene* scene, const utd_bodies* bodies, con
     if (n_rx == 0) return UTD_OK;
     hipError_t e = hipSuccess;
     hipStream_t s = (hipStream_t)stream;
-    utd::LaunchParams L = make_params(bodies, tx, n_rx, 0, opt);
+    utd::LaunchParams L = make_params(scene, bodies, tx, n_rx, 0, opt);
     int nb = L.n_sph + L.n_cyl;
     Workspace w;
     e = w.alloc(nb, n_rx, 0, opt->l_enc, 0, true, s);
@@ -363,7 +376,7 @@ utd_status utd_smooth_field_backward(const utd_scene* scene, const utd_bodies* b
     if (work && !grad_E) return fail(UTD_E_ARG, "grad_E is NULL");
     hipError_t e = hipSuccess;
     hipStream_t s = (hipStream_t)stream;
-    utd::LaunchParams L = make_params(bodies, tx, n_rx, n_f, opt);
+    utd::LaunchParams L = make_params(scene, bodies, tx, n_rx, n_f, opt);
     int nb = L.n_sph + L.n_cyl;
     if (!work) L.n_rx = 0;                  // no paths: every gradient is zero
     size_t extra = utd::adjoint_scratch_bytes(L);
@@ -428,7 +441,7 @@ utd_status utd_smooth_field_batched(const utd_scene* scene, int64_t n_frames, co
     std::lock_guard<std::mutex> lk(g_batch_mu);
     BatchState& st = g_batch[dev];
     utd::BatchParams B;
-    B.L = make_params(&bodies, tx, 0, n_f, opt);
+    B.L = make_params(scene, &bodies, tx, 0, n_f, opt);
     B.L.n_sph = 0;
     B.n_frames = n_frames;
     B.n_cyl = n_cyl;
@@ -489,8 +502,11 @@ utd_status utd_smooth_field_batched(const utd_scene* scene, int64_t n_frames, co
         const unsigned char* c = (const unsigned char*)p;
         key.insert(key.end(), c, c + n);
     };
-    const void* ptrs[] = {scene, body_off, cyl, rx_off, rx, freqs, E_out, rx_flags};
-    int64_t ints[] = {n_frames, n_cyl, n_rx, (int64_t)n_f, (int64_t)g_batch_tile, (int64_t)n_blocks};
+    // the scene enters by its id: a destroyed scene's address can come back
+    // for a new one, whose device arrays the old graph does not know
+    const void* ptrs[] = {body_off, cyl, rx_off, rx, freqs, E_out, rx_flags};
+    int64_t ints[] = {n_frames, n_cyl, n_rx, (int64_t)n_f, (int64_t)g_batch_tile, (int64_t)n_blocks,
+                      scene ? (int64_t)scene->id : 0};
     put(ptrs, sizeof ptrs);
     put(ints, sizeof ints);
     put(tx, sizeof *tx);

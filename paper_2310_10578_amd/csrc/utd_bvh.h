@@ -89,11 +89,12 @@ __device__ __forceinline__ bool tri_hit(const SegRay& r, float4 a, float4 b, flo
     return det > 0.0f ? (T > lo && T < hi) : (T < lo && T > hi);
 }
 
+// Any-hit walk of the tree rooted at node `root`.
 __device__ __forceinline__ bool bvh_anyhit(const float4* __restrict__ nodes, const float4* __restrict__ tris,
-                                           const SegRay& r, int* stack, int stride) {
+                                           const SegRay& r, int* stack, int stride, int root = 0) {
     if (!nodes) return false;
     int sp = 0;
-    int node = 0;
+    int node = root;
     for (;;) {
         float4 q0 = nodes[4 * node + 0];
         float4 q1 = nodes[4 * node + 1];

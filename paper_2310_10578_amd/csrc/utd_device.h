@@ -33,6 +33,8 @@ struct LaunchParams {
     int n_f;
     int l_enc, bodies_occlude, lit_branch;
     double caustic_guard;
+    int broot;            // root node of the boundary-triangle tree (-1: none)
+    float blo[3], bhi[3]; // scene bounding box (the boundary triangles lie in its faces)
 };
 
 // Per-body quantities that depend only on the source (computed once per call).

@@ -50,6 +50,9 @@ hipError_t launch_census(int64_t n_mask, const uint8_t* mask, int64_t n_rx, cons
 // host BVH over a triangle soup (bvh.cpp)
 struct HostBvh {
     int64_t n_nodes = 0;
+    int64_t broot = -1;       // root of the boundary-triangle tree (-1: none)
+    int64_t n_inner_tris = 0;
+    float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};   // scene bounding box
     int depth = 0;
     float* nodes = nullptr;   // n_nodes * 16 floats (4 float4 per node)
     float* tris = nullptr;    // n_tri * 12 floats (3 float4 per triangle), leaf order

@@ -64,7 +64,18 @@ __device__ __forceinline__ bool seg_blocked(d3 P0, d3 P1, const LaunchParams& L,
     if (bodies && blocked_by_bodies(P0, P1, L, sph, cyl, skip)) return true;
     if (!nodes) return false;
     SegRay r = make_ray(P0, P1);
-    return bvh_anyhit(nodes, tris, r, stack, stride);
+    if (bvh_anyhit(nodes, tris, r, stack, stride)) return true;
+    if (L.broot < 0) return false;
+    // the boundary triangles lie in the faces of the scene box: a segment
+    // with both (FP32) end points inside the closed box can meet them only
+    // at an end point, which the open-segment test excludes
+    const float ex = (float)P1.x, ey = (float)P1.y, ez = (float)P1.z;
+    const bool in0 = r.ox >= L.blo[0] && r.ox <= L.bhi[0] && r.oy >= L.blo[1] && r.oy <= L.bhi[1] &&
+                     r.oz >= L.blo[2] && r.oz <= L.bhi[2];
+    const bool in1 = ex >= L.blo[0] && ex <= L.bhi[0] && ey >= L.blo[1] && ey <= L.bhi[1] && ez >= L.blo[2] &&
+                     ez <= L.bhi[2];
+    if (in0 && in1) return false;
+    return bvh_anyhit(nodes, tris, r, stack, stride, L.broot);
 }
 
 // Path records: the frequency-independent constants of one valid path,
