@@ -165,3 +165,31 @@ def test_room_full_size_sampled(cfg_name):
     err = normwise(Eg[:, :, idx][:, :, ~bad], Eo[:, :, ~bad])
     _report(cfg_name + " sampled", err)
     assert np.all(err <= TOL[0])
+
+
+@pytest.mark.parametrize("tx_outside", [False, True])
+def test_receivers_and_source_outside_the_room(tx_outside):
+    """Segments that leave the room: receivers on a grid reaching 1 m beyond
+    the walls (some exactly on the wall planes), and the source inside or
+    outside.  The walls, floor and ceiling lie in the faces of the scene box
+    and sit in the BVH's second tree, which only such segments walk; every
+    path to an outside point must be blocked by them."""
+    cfg = W.small_room(n_cyl=4)
+    xs, ys = np.meshgrid(np.linspace(-1.0, 11.0, 13), np.linspace(-1.0, 9.0, 11), indexing="ij")
+    rx = np.stack([xs.ravel(), ys.ravel(), np.full(xs.size, 1.2)], 1).astype(np.float32)
+    cfg = dict(cfg, rx=rx)
+    if tx_outside:
+        cfg["tx"] = dict(cfg["tx"], pos=np.array([5.0, -0.5, 1.5], np.float32))
+    Eg, fg = run_library(cfg, 1)
+    Eo, info = run_oracle(cfg)
+    outside = (rx[:, 0] < 0) | (rx[:, 0] > 10) | (rx[:, 1] < 0) | (rx[:, 1] > 8)
+    inside = (rx[:, 0] > 0) & (rx[:, 0] < 10) & (rx[:, 1] > 0) & (rx[:, 1] < 8)
+    ok = (fg & 5) == (info["flags"] & 5)
+    assert ok.mean() > 0.98
+    # the walls separate the source's side from the other side
+    far = inside if tx_outside else outside
+    assert not np.any(fg[far] & 4)
+    assert np.all(np.abs(Eg[:, :, far]) == 0)
+    err = normwise(Eg[:, :, ok], Eo[:, :, ok])
+    _report("segments leaving the room (source %s)" % ("outside" if tx_outside else "inside"), err)
+    assert np.all(err <= TOL[1])
