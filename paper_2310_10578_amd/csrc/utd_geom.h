@@ -403,6 +403,18 @@ __device__ __forceinline__ bool refl_angle(const BodyPrep& b, const RxGeo& g, d3
     } else {
         return false;
     }
+    // Height of the reflection point before solving: on the arc seen from
+    // both ends, the horizontal distances obey rho_T - a <= l_T <= s_T and
+    // rho_R - a <= l_R <= s_R (s the tangent lengths), so
+    // z_Q = z_T + (z_R - z_T) l_T / (l_T + l_R) lies between the values at
+    // the extreme ratios; no solve when that range misses the lateral surface.
+    {
+        const double fa = (b.dT - a) / ((b.dT - a) + g.sD0), fb = b.sI0 / (b.sI0 + (g.dR - a));
+        const double dz = Rp.z - T.z;
+        const double za = T.z + dz * fa, zb = T.z + dz * fb;
+        const double slack = 1e-9 * (1.0 + fabs(T.z) + fabs(Rp.z));
+        if (fmax(za, zb) < b.z0 - slack || fmin(za, zb) > b.z0 + b.h + slack) return false;
+    }
     double tx = T.x - b.c[0], ty = T.y - b.c[1];
     double rx = Rp.x - b.c[0], ry = Rp.y - b.c[1];
     double al = alhazen(a, tx, ty, rx, ry, lo, hi);

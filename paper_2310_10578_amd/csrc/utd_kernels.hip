@@ -199,20 +199,27 @@ __device__ __forceinline__ int64_t wave_append_active(bool flag, unsigned long l
     return (int64_t)base + __popcll(bal & ((1ull << lane) - 1ull));
 }
 
-// Queue and visible-list lengths.
-__global__ void k_zero_counter(unsigned long long* counter) {
-    counter[0] = 0ull;
-    counter[1] = 0ull;
+// Set-up of the two-pass visibility: queue and visible-list lengths, and the
+// per-body constants (which depend on the source only).
+__global__ void __launch_bounds__(256) k_setup(LaunchParams L, const float* __restrict__ sph,
+                                               const float* __restrict__ cyl, BodyPrep* __restrict__ prep,
+                                               unsigned long long* __restrict__ counter) {
+    if (threadIdx.x == 0) {
+        counter[0] = 0ull;
+        counter[1] = 0ull;
+    }
+    const int nb = L.n_sph + L.n_cyl;
+    for (int b = (int)(blockIdx.x * blockDim.x + threadIdx.x); b < nb; b += (int)(gridDim.x * blockDim.x))
+        prep[b] = body_prep(L.T, sph, L.n_sph, cyl, b);
 }
 
 // Pass 1.  grid: x over receivers (blockDim 256), y over slot = 0 (receiver
-// flags, direct ray) or 1 + body.  Body constants of slot b are computed by
-// every block of the slot (the x = 0 block stores them); the (0, 0) block
+// flags, direct ray) or 1 + body (constants from k_setup); the (0, 0) block
 // stores the frequency constants.
 template <typename R>
 __global__ void __launch_bounds__(256) k_cand(LaunchParams L, const float* __restrict__ rx,
                                               const float* __restrict__ sph, const float* __restrict__ cyl,
-                                              const double* __restrict__ freqs, BodyPrep* __restrict__ prep,
+                                              const double* __restrict__ freqs, const BodyPrep* __restrict__ prep,
                                               FreqConst* __restrict__ fcs, uint8_t* __restrict__ mask,
                                               uint8_t* __restrict__ flags, uint64_t* __restrict__ ent,
                                               double* __restrict__ ent_th, unsigned long long* __restrict__ counter,
@@ -240,8 +247,7 @@ __global__ void __launch_bounds__(256) k_cand(LaunchParams L, const float* __res
             los_cand = !inside && !tx_inside;
         }
     } else {
-        const BodyPrep P = body_prep(L.T, sph, L.n_sph, cyl, b);
-        if (blockIdx.x == 0 && threadIdx.x == 0) prep[b] = P;
+        const BodyPrep P = prep[b];
         if (act) {
             RxGeo g = rx_geo(P, R3);
             uint8_t m = 0;
@@ -431,11 +437,16 @@ __global__ void __launch_bounds__(448) k_paths(LaunchParams L, const float* __re
     }
     const int lane = threadIdx.x & 63, kind = threadIdx.x >> 6;
     const int64_t i = (int64_t)blockIdx.x * 64 + lane;
-    if (threadIdx.x < 64) s_m[lane] = 0u;
-    __syncthreads();
     const int b = slot - 1;
-    const BodyPrep P = body_prep(L.T, sph, L.n_sph, cyl, b);
-    if (blockIdx.x == 0 && threadIdx.x == 0) prep[b] = P;
+    // body constants: computed by one lane, shared through LDS
+    __shared__ BodyPrep s_prep;
+    if (threadIdx.x < 64) s_m[lane] = 0u;
+    if (threadIdx.x == 0) {
+        s_prep = body_prep(L.T, sph, L.n_sph, cyl, b);
+        if (blockIdx.x == 0) prep[b] = s_prep;
+    }
+    __syncthreads();
+    const BodyPrep P = s_prep;
     const int NS = rec_slots(L);
     const bool bo = L.bodies_occlude != 0;
     unsigned m = 0u;
@@ -713,7 +724,8 @@ static hipError_t launch_paths_t(const LaunchParams& L, const float* rx, const f
                            (PathRec<R>*)rec, flags);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, counter);
+    hipLaunchKernelGGL(k_setup, dim3((unsigned)((nb + 255) / 256 > 0 ? (nb + 255) / 256 : 1)), dim3(256), 0, s, L,
+                       sph, cyl, prep, counter);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     dim3 grid((unsigned)((L.n_rx + 255) / 256), (unsigned)(nb + 1));
