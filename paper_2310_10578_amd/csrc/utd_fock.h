@@ -239,12 +239,11 @@ __device__ __forceinline__ void fock_kernel(const Tabs<typename BaseOf<R>::type>
         R f = regime == 1 ? q * c2e4 : ixi * c2e4;
         cplx<R> CW{f * (W.re + W.im), f * (W.im - W.re)};
         cplx<R> eCW = cmul(e, CW);
-        bool r2 = regime == 2;
-        cplx<R> as = cmul(e, ps), ah = cmul(e, ph);
-        Ks->re = -((r2 ? A.h * ps.re : as.re) + eCW.re);
-        Ks->im = -((r2 ? A.h * ps.im : as.im) + eCW.im);
-        Kh->re = -((r2 ? A.h * ph.re : ah.re) + eCW.re);
-        Kh->im = -((r2 ? A.h * ph.im : ah.im) + eCW.im);
+        const bool r2 = regime == 2;
+        const cplx<R> al{r2 ? A.h : e.re, r2 ? (R)0 : e.im};
+        cplx<R> as = cmul(al, ps), ah = cmul(al, ph);
+        *Ks = cplx<R>{-(as.re + eCW.re), -(as.im + eCW.im)};
+        *Kh = cplx<R>{-(ah.re + eCW.re), -(ah.im + eCW.im)};
         return;
     }
     R sg = refl ? (xi > (R)0 ? (R)1 : (R)-1) : (xi < (R)0 ? (R)-1 : (R)1);

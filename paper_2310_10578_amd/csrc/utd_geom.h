@@ -355,26 +355,64 @@ __device__ __forceinline__ G alhazen_fun(G a, G p1x, G p1y, G p2x, G p2y, G th, 
     return t1 + t2;
 }
 
-// Safeguarded Newton in FP64 (bisection step whenever Newton leaves the
-// bracket); the bracket ends are the tangent points, where g has opposite
-// signs.  Convergence is tested on the Newton step before the bracket test,
-// so a step that lands on the root (g = 0 makes it a bracket end) ends the
-// iteration instead of falling back to bisection; typically 3-4 iterations.
+// The same function in FP32 (hardware sin/cos of revolutions, reciprocal
+// square roots): good to about 1e-6 in th, enough to start the FP64 polish
+// within its quadratic range.
+__device__ __forceinline__ float alhazen_fun_f32(float a, float p1x, float p1y, float p2x, float p2y, float th,
+                                                 float* dg) {
+    float r = th * 0.159154943091895336f;
+    r -= rintf(r);
+    float s, c;
+    sincos_rev(r, &s, &c);
+    const float qx = a * c, qy = a * s;
+    const float d1x = qx - p1x, d1y = qy - p1y, d2x = qx - p2x, d2y = qy - p2y;
+    const float i1 = __builtin_amdgcn_rsqf(d1x * d1x + d1y * d1y), i2 = __builtin_amdgcn_rsqf(d2x * d2x + d2y * d2y);
+    const float t1 = (-d1x * s + d1y * c) * i1, t2 = (-d2x * s + d2y * c) * i2;
+    const float n1 = d1x * c + d1y * s, n2 = d2x * c + d2y * s;
+    *dg = ((a - n1) - a * t1 * t1) * i1 + ((a - n2) - a * t2 * t2) * i2;
+    return t1 + t2;
+}
+
+// Root of g between the tangent points lo and hi (either order; g has
+// opposite signs there).  Safeguarded Newton (a bisection step whenever
+// Newton leaves the bracket) in FP32 to about 1e-6, then the same in FP64
+// from there.  The FP64 iteration stops after a Newton step below
+// 1e-11 (1 + |th|): with quadratic convergence the accepted iterate is then
+// exact to far below FP64 rounding.  Typically 4-5 FP32 and 2-3 FP64
+// evaluations.
 __device__ __forceinline__ double alhazen(double a, double p1x, double p1y, double p2x, double p2y,
                                           double lo, double hi) {
+    const float fa = (float)a, f1x = (float)p1x, f1y = (float)p1y, f2x = (float)p2x, f2y = (float)p2y;
+    float flo = (float)lo, fhi = (float)hi, fdg;
+    const float glo32 = alhazen_fun_f32(fa, f1x, f1y, f2x, f2y, flo, &fdg);
+    float fg_lo = glo32;
+    float fth = 0.5f * (flo + fhi);
+    for (int it = 0; it < 40; ++it) {
+        const float g = alhazen_fun_f32(fa, f1x, f1y, f2x, f2y, fth, &fdg);
+        if (g == 0.0f) break;
+        if ((g < 0.0f) == (fg_lo < 0.0f)) { flo = fth; fg_lo = g; } else { fhi = fth; }
+        float nt = fth - g / fdg;
+        const float tol = 2e-6f * (1.0f + fabsf(fth));
+        if (fabsf(nt - fth) <= tol) { fth = nt; break; }
+        if (!(nt > fminf(flo, fhi) && nt < fmaxf(flo, fhi))) nt = 0.5f * (flo + fhi);
+        fth = nt;
+        if (fabsf(fhi - flo) <= tol) break;
+    }
+    // sign of g at lo: from the FP32 value unless that is too small to trust
     double dg;
-    double glo = alhazen_fun<double>(a, p1x, p1y, p2x, p2y, lo, &dg);
-    double th = 0.5 * (lo + hi);
+    bool lo_neg = glo32 < 0.0f;
+    if (fabsf(glo32) < 1e-4f) lo_neg = alhazen_fun<double>(a, p1x, p1y, p2x, p2y, lo, &dg) < 0.0;
+    double th = (double)fth;
+    if (!(th > fmin(lo, hi) && th < fmax(lo, hi))) th = 0.5 * (lo + hi);
     for (int it = 0; it < 60; ++it) {
-        double g = alhazen_fun<double>(a, p1x, p1y, p2x, p2y, th, &dg);
+        const double g = alhazen_fun<double>(a, p1x, p1y, p2x, p2y, th, &dg);
         if (g == 0.0) break;
-        if ((g < 0) == (glo < 0)) { lo = th; glo = g; } else { hi = th; }
+        if ((g < 0) == lo_neg) lo = th; else hi = th;
         double nt = th - g / dg;
-        const double tol = 1e-15 * (1.0 + fabs(th));
-        if (fabs(nt - th) <= tol) { th = nt; break; }
+        if (fabs(nt - th) <= 1e-11 * (1.0 + fabs(th))) { th = nt; break; }
         if (!(nt > fmin(lo, hi) && nt < fmax(lo, hi))) nt = 0.5 * (lo + hi);
         th = nt;
-        if (fabs(hi - lo) <= tol) break;
+        if (fabs(hi - lo) <= 1e-15 * (1.0 + fabs(th))) break;
     }
     return th;
 }
