@@ -138,21 +138,36 @@ __device__ __forceinline__ bool bvh_anyhit(const float4* __restrict__ nodes, con
 // computation (bounded by tol = 4e-6 (|w|^2 + |d|^2), with w = P0 - C and
 // d = P1 - P0), so the exact FP64 test below would also say "not crossed".
 // Most bodies are far from most segments; this skips their FP64 solve.
-__device__ __forceinline__ bool far_from(float wx, float wy, float wz, float dx, float dy, float dz, float a) {
-    float dd = dx * dx + dy * dy + dz * dz;
+// The segment's FP32 form (origin, direction, |d|^2 and its reciprocal) is
+// set up once per segment and shared by all bodies.
+struct SegF {
+    float ox, oy, oz, dx, dy, dz;
+    float dd3, id3;     // |d|^2 and 1/|d|^2 (0 for a point)
+    float dd2, id2;     // the same in the xy plane
+};
+__device__ __forceinline__ SegF make_segf(d3 P0, d3 P1) {
+    SegF f;
+    f.ox = (float)P0.x; f.oy = (float)P0.y; f.oz = (float)P0.z;
+    f.dx = (float)(P1.x - P0.x); f.dy = (float)(P1.y - P0.y); f.dz = (float)(P1.z - P0.z);
+    f.dd2 = f.dx * f.dx + f.dy * f.dy;
+    f.dd3 = f.dd2 + f.dz * f.dz;
+    f.id2 = f.dd2 > 0.0f ? 1.0f / f.dd2 : 0.0f;
+    f.id3 = f.dd3 > 0.0f ? 1.0f / f.dd3 : 0.0f;
+    return f;
+}
+__device__ __forceinline__ bool far_from(float wx, float wy, float wz, float dx, float dy, float dz, float dd,
+                                         float idd, float a) {
     float wd = wx * dx + wy * dy + wz * dz;
     float ww = wx * wx + wy * wy + wz * wz;
-    float t = dd > 0.0f ? fminf(fmaxf(-wd / dd, 0.0f), 1.0f) : 0.0f;
+    float t = __builtin_amdgcn_fmed3f(-wd * idd, 0.0f, 1.0f);
     float qx = wx + t * dx, qy = wy + t * dy, qz = wz + t * dz;
     float dist2 = qx * qx + qy * qy + qz * qz;
     return dist2 > a * a + 4e-6f * (ww + dd);
 }
 
 // Solid sphere (cx, cy, cz, a) crossed strictly inside the segment.
-__device__ __forceinline__ bool seg_sphere(d3 P0, d3 P1, const float* s) {
-    if (far_from((float)(P0.x - s[0]), (float)(P0.y - s[1]), (float)(P0.z - s[2]), (float)(P1.x - P0.x),
-                 (float)(P1.y - P0.y), (float)(P1.z - P0.z), s[3]))
-        return false;
+__device__ __forceinline__ bool seg_sphere(d3 P0, d3 P1, const SegF& f, const float* s) {
+    if (far_from(f.ox - s[0], f.oy - s[1], f.oz - s[2], f.dx, f.dy, f.dz, f.dd3, f.id3, s[3])) return false;
     d3 d = P1 - P0;
     d3 w = P0 - mk(s[0], s[1], s[2]);
     double a = s[3];
@@ -165,10 +180,8 @@ __device__ __forceinline__ bool seg_sphere(d3 P0, d3 P1, const float* s) {
 }
 
 // Solid finite vertical cylinder (cx, cy, z0, h, a).
-__device__ __forceinline__ bool seg_cylinder(d3 P0, d3 P1, const float* c) {
-    if (far_from((float)(P0.x - c[0]), (float)(P0.y - c[1]), 0.0f, (float)(P1.x - P0.x), (float)(P1.y - P0.y),
-                 0.0f, c[4]))
-        return false;
+__device__ __forceinline__ bool seg_cylinder(d3 P0, d3 P1, const SegF& f, const float* c) {
+    if (far_from(f.ox - c[0], f.oy - c[1], 0.0f, f.dx, f.dy, 0.0f, f.dd2, f.id2, c[4])) return false;
     d3 d = P1 - P0;
     double wx = P0.x - c[0], wy = P0.y - c[1];
     double a = c[4];

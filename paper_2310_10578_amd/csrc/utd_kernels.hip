@@ -51,10 +51,11 @@ __device__ __forceinline__ bool inside_raw(const LaunchParams& L, const float* s
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool blocked_by_bodies(d3 P0, d3 P1, const LaunchParams& L, const float* sph,
                                                   const float* cyl, int skip) {
+    const SegF f = make_segf(P0, P1);
     for (int i = 0; i < L.n_sph; ++i)
-        if (i != skip && seg_sphere(P0, P1, sph + 4 * i)) return true;
+        if (i != skip && seg_sphere(P0, P1, f, sph + 4 * i)) return true;
     for (int i = 0; i < L.n_cyl; ++i)
-        if (L.n_sph + i != skip && seg_cylinder(P0, P1, cyl + 5 * i)) return true;
+        if (L.n_sph + i != skip && seg_cylinder(P0, P1, f, cyl + 5 * i)) return true;
     return false;
 }
 
