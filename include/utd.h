@@ -93,7 +93,10 @@ void utd_default_options(utd_options *opt);
 
 /* Builds the occluder scene: copies n_tri triangles (host float32
  * [n_tri][3][3], vertex-major) to the device and builds a BVH over them
- * (binned SAH, host C++).  n_tri may be 0.  *out receives the handle.
+ * (binned SAH, host C++).  Triangles lying in a face plane of the scene's
+ * bounding box (a room's walls, floor and ceiling) go to a second tree that
+ * only segments reaching outside the box have to walk.  n_tri may be 0.
+ * *out receives the handle.
  * Errors: UTD_E_ARG (out NULL, n_tri < 0, tri NULL with n_tri > 0),
  * UTD_E_OOM, UTD_E_DEVICE. */
 utd_status utd_scene_create(const float *tri_xyz, int64_t n_tri, utd_scene **out);

@@ -217,7 +217,7 @@ int g_batch_bpc = 4;
 // Frequencies per lane: more frequencies per lane amortise the path geometry,
 // fewer keep enough lanes in flight.
 int pick_fc(int precision, int64_t n_rx, int n_f) {
-    int fc = precision == 0 ? 8 : 2;
+    int fc = precision == 0 ? 4 : 2;
     while (fc > 1 && (fc / 2 >= n_f || n_rx * ((n_f + fc - 1) / fc) < 256 * 2048)) fc /= 2;
     return fc;
 }

@@ -345,8 +345,11 @@ __device__ __forceinline__ void vis_body(const LaunchParams& L, const float* __r
     }
 }
 
+// Four waves per SIMD (128 VGPRs, a few spills): more traversals in flight
+// hide more of their memory latency (measured faster than three without
+// spills).
 template <typename R>
-__global__ void __launch_bounds__(256) k_vis(LaunchParams L, const float* __restrict__ rx,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_vis(LaunchParams L, const float* __restrict__ rx,
                                              const float* __restrict__ sph, const float* __restrict__ cyl,
                                              const BodyPrep* __restrict__ prep, const float4* __restrict__ nodes,
                                              const float4* __restrict__ tris, const uint64_t* __restrict__ ent,
@@ -736,7 +739,7 @@ static hipError_t launch_paths_t(const LaunchParams& L, const float* rx, const f
     // persistent grids over the queue and the visible list: enough
     // workgroups to fill the chip
     int64_t vgrid = (cap + 255) / 256;
-    vgrid = vgrid < 1 ? 1 : (vgrid > 256 * 12 ? 256 * 12 : vgrid);
+    vgrid = vgrid < 1 ? 1 : (vgrid > 256 * 20 ? 256 * 20 : vgrid);
     hipLaunchKernelGGL((k_vis<R>), dim3((unsigned)vgrid), dim3(256), 0, s, L, rx, sph, cyl, prep, nodes, tris, ent,
                        ent_th, counter, cap, mask, flags, vis_list);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -773,8 +776,7 @@ hipError_t launch_field(const LaunchParams& L, int precision, int fc, const floa
         switch (fc) {
             case 1: return launch_field_fc<float, 1>(L, rx, fcs, mask, rec, flags, e, s);
             case 2: return launch_field_fc<float, 2>(L, rx, fcs, mask, rec, flags, e, s);
-            case 4: return launch_field_fc<float, 4>(L, rx, fcs, mask, rec, flags, e, s);
-            default: return launch_field_fc<float, 8>(L, rx, fcs, mask, rec, flags, e, s);
+            default: return launch_field_fc<float, 4>(L, rx, fcs, mask, rec, flags, e, s);
         }
     }
     double* e = (double*)E;
