@@ -53,6 +53,25 @@ def kernel_source_digest():
     return h.hexdigest()
 
 
+VIS_KERNELS = ("utd::k_setup", "utd::k_cand<float", "utd::k_vis<float", "utd::k_rec<float", "utd::k_paths<float")
+
+
+def occlusion_summary(workload_name, prof, n_rx, n_body, n_paths, census):
+    """Classification and visibility pass per call: time, active paths per
+    (receiver, body) pair, and HBM bytes and GB/s from the committed PMC
+    summary of the same kernels (null when it does not match the sources)."""
+    occ_ms, occ_n = prof.get("occlude", (0.0, 0))
+    ms = occ_ms / max(occ_n, 1)
+    nbytes = None
+    vals = [measured_traffic(workload_name, k) for k in VIS_KERNELS]
+    if any(v is not None for v in vals):
+        nbytes = sum(v for v in vals if v is not None)
+    return {"ms": ms, "pairs": n_rx * max(n_body, 1), "active_paths": n_paths,
+            "active_paths_per_pair": n_paths / max(n_rx * max(n_body, 1), 1),
+            "los_receivers": census["los"], "hbm_bytes": nbytes,
+            "hbm_GBps": (nbytes / (ms / 1e3) / 1e9) if (nbytes is not None and ms > 0) else None}
+
+
 def measured_traffic(workload_name, kernel_prefix):
     """HBM bytes per launch of the field kernel from the committed PMC summary
     (FETCH_SIZE and WRITE_SIZE runs, calibrated against a device copy), or
@@ -323,6 +342,7 @@ def main():
                      "kernel": "k_field<float>", "kernel_ms": field_avg_s * 1e3,
                      "flops_per_launch": flops, "paths": n_paths, "los_receivers": los},
         "kernels_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]},
+        "occlusion": occlusion_summary(args.workload, prof, n_rx, n_body, n_paths, census),
         "wall_s": wall,
     }
     if args.adjoint:
