@@ -122,9 +122,11 @@ def workload(name):
     return W.config1()
 
 
-def cpu_baseline(cfg, n_sample):
+def cpu_baseline(cfg, n_sample, E_gpu=None):
     """The FP64 oracle on a bounded receiver sample, all frequencies, in a
-    pool of worker processes (one receiver chunk each)."""
+    pool of worker processes (one receiver chunk each).  With the GPU field
+    of the same call, also the error of that result on the sample (relative
+    normwise per frequency, the largest over frequencies)."""
     import multiprocessing as mp
 
     import workloads as W
@@ -136,20 +138,28 @@ def cpu_baseline(cfg, n_sample):
     args = [(sc, tx, rx[c], cfg["freqs"]) for c in chunks if c.size]
     t0 = time.perf_counter()
     with mp.get_context("fork").Pool(len(args)) as pool:
-        pool.map(_oracle_chunk, args)
+        parts = pool.map(_oracle_chunk, args)
     dt = time.perf_counter() - t0
     nb = len(sc["spheres"]) + len(sc["cylinders"])
     evals = n_sample * max(nb, 1) * len(cfg["freqs"])
-    return dict(value=evals / dt, unit="evals/s", cores=len(args), kind="oracle",
-                sample="%d receivers x %d bodies x %d frequencies of the workload, %.1f s wall"
-                       % (n_sample, nb, len(cfg["freqs"]), dt))
+    out = dict(value=evals / dt, unit="evals/s", cores=len(args), kind="oracle",
+               sample="%d receivers x %d bodies x %d frequencies of the workload, %.1f s wall"
+                      % (n_sample, nb, len(cfg["freqs"]), dt))
+    if E_gpu is not None:
+        Eo = np.concatenate(parts, axis=2)
+        Eg = E_gpu[:, :, idx]
+        num = np.sqrt(np.sum(np.abs(Eg - Eo) ** 2, axis=(1, 2)))
+        den = np.sqrt(np.sum(np.abs(Eo) ** 2, axis=(1, 2)))
+        out["fp32_field_error"] = {"max_normwise_rel": float(np.max(num / den)), "receivers": int(n_sample),
+                                   "against": "FP64 oracle, same float32 inputs"}
+    return out
 
 
 def _oracle_chunk(a):
     os.environ["OMP_NUM_THREADS"] = "1"
     from oracle import field
     sc, tx, rx, freqs = a
-    return field.field(sc, tx, rx, freqs).shape
+    return field.field(sc, tx, rx, freqs)
 
 
 def _timed(fn, steps, warmup):
@@ -350,7 +360,7 @@ def main():
     if args.batched:
         res["batched"] = batched_bench(args.batched_steps)
     if args.cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(cfg, min(args.cpu_sample, n_rx))
+        res["cpu_baseline"] = cpu_baseline(cfg, min(args.cpu_sample, n_rx), out.cpu().numpy().astype(np.complex128))
     print(json.dumps(res))
 
 
