@@ -404,57 +404,57 @@ __global__ void __launch_bounds__(256) k_rec(LaunchParams L, const float* __rest
 // receivers (blockDim 256), y over slot = 0 (receiver flags) or 1 + body;
 // same outputs as k_cand + k_vis.
 // Scenes of bodies only (no triangles): one pass, no queue.
-// grid (ceil(n_rx / 64), 1 + bodies), 64 K threads, K = 2 (l_enc + 1) + 1
-// path kinds.  Slot 0: one lane per receiver (64 K receivers per block):
-// inside / source-inside flags and the direct ray.  Slot 1 + b: wave k of the
-// block takes path kind k of the block's 64 receivers (creeping (ell, side) =
-// (k >> 1, k & 1), the reflection for k = K - 1), so every wavefront runs one
-// kind of path; the mask bits of a receiver meet in LDS.
+// grid (ceil(n_rx / 64), max(bodies, 1)), 64 (K + 1) threads, K =
+// 2 (l_enc + 1) + 1 path kinds; a workgroup covers 64 receivers of one body.
+// Wave k < K takes path kind k (creeping (ell, side) = (k >> 1, k & 1), the
+// reflection for k = K - 1), so every wavefront runs one kind of path; the
+// mask bits of a receiver meet in LDS.  Wave K of the body-0 workgroups sets
+// the receivers' inside / source-inside flags and tests the direct ray.
+// Every wavefront computes the body constants itself (the chains are
+// latency-bound; waiting for one lane to share them costs more).
 template <typename R>
-__global__ void __launch_bounds__(448) k_paths(LaunchParams L, const float* __restrict__ rx,
+__global__ void __launch_bounds__(512) k_paths(LaunchParams L, const float* __restrict__ rx,
                                                const float* __restrict__ sph, const float* __restrict__ cyl,
                                                const double* __restrict__ freqs, BodyPrep* __restrict__ prep,
                                                FreqConst* __restrict__ fcs, uint8_t* __restrict__ mask,
                                                PathRec<R>* __restrict__ rec, uint8_t* __restrict__ flags) {
     __shared__ unsigned s_m[64];
-    const int slot = blockIdx.y;
     const d3 T = mk(L.T[0], L.T[1], L.T[2]);
     const int nb = L.n_sph + L.n_cyl;
-    if (slot == 0) {
-        if (blockIdx.x == 0 && freqs)
-            for (int f = threadIdx.x; f < L.n_f; f += blockDim.x) fcs[f] = freq_const(freqs[f]);
-        const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-        if (i >= L.n_rx) return;
-        const d3 R3 = mk(rx[3 * i], rx[3 * i + 1], rx[3 * i + 2]);
-        uint8_t f = 0;
-        bool inside = false, tx_inside = false;
-        for (int b = 0; b < nb; ++b) {
-            inside |= inside_raw(L, sph, cyl, b, R3);
-            tx_inside |= inside_raw(L, sph, cyl, b, T);
-        }
-        if (tx_inside) f |= kFlagTxInside;
-        if (inside) f |= kFlagInside;
-        if (!inside && !tx_inside && !seg_blocked(T, R3, L, sph, cyl, -1, true, nullptr, nullptr, nullptr, 0))
-            f |= kFlagLos;
-        flags[i] = f;
-        return;
-    }
+    const int b = blockIdx.y;
     const int lane = threadIdx.x & 63, kind = threadIdx.x >> 6;
+    const int K = rec_slots(L);
     const int64_t i = (int64_t)blockIdx.x * 64 + lane;
-    const int b = slot - 1;
-    // body constants: computed by one lane, shared through LDS
-    __shared__ BodyPrep s_prep;
-    if (threadIdx.x < 64) s_m[lane] = 0u;
-    if (threadIdx.x == 0) {
-        s_prep = body_prep(L.T, sph, L.n_sph, cyl, b);
-        if (blockIdx.x == 0) prep[b] = s_prep;
+    // every wavefront reaches both barriers below (none returns early, except
+    // all of them together when there are no bodies)
+    const bool flags_wave = kind == K;
+    if (flags_wave && b == 0) {
+        if (blockIdx.x == 0 && freqs)
+            for (int f = lane; f < L.n_f; f += 64) fcs[f] = freq_const(freqs[f]);
+        if (i < L.n_rx) {
+            const d3 R3 = mk(rx[3 * i], rx[3 * i + 1], rx[3 * i + 2]);
+            uint8_t f = 0;
+            bool inside = false, tx_inside = false;
+            for (int k = 0; k < nb; ++k) {
+                inside |= inside_raw(L, sph, cyl, k, R3);
+                tx_inside |= inside_raw(L, sph, cyl, k, T);
+            }
+            if (tx_inside) f |= kFlagTxInside;
+            if (inside) f |= kFlagInside;
+            if (!inside && !tx_inside && !seg_blocked(T, R3, L, sph, cyl, -1, true, nullptr, nullptr, nullptr, 0))
+                f |= kFlagLos;
+            flags[i] = f;
+        }
     }
+    if (b >= nb) return;
+    if (threadIdx.x < 64) s_m[lane] = 0u;
     __syncthreads();
-    const BodyPrep P = s_prep;
-    const int NS = rec_slots(L);
+    const BodyPrep P = body_prep(L.T, sph, L.n_sph, cyl, b);
+    if (blockIdx.x == 0 && threadIdx.x == 0) prep[b] = P;
+    const int NS = K;
     const bool bo = L.bodies_occlude != 0;
     unsigned m = 0u;
-    if (i < L.n_rx) {
+    if (!flags_wave && i < L.n_rx) {
         const d3 R3 = mk(rx[3 * i], rx[3 * i + 1], rx[3 * i + 2]);
         RxGeo g = rx_geo(P, R3);
         if (kind < NS - 1) {
@@ -721,10 +721,10 @@ static hipError_t launch_paths_t(const LaunchParams& L, const float* rx, const f
                                  hipStream_t s) {
     int nb = L.n_sph + L.n_cyl;
     if (!nodes) {
-        // one wavefront per path kind and 64 receivers (slot 0: 64 K receivers per block)
+        // one wavefront per path kind and 64 receivers, plus the flags wavefront
         const int K = 2 * (L.l_enc + 1) + 1;
-        dim3 grid((unsigned)((L.n_rx + 63) / 64), (unsigned)(nb + 1));
-        hipLaunchKernelGGL((k_paths<R>), grid, dim3(64 * K), 0, s, L, rx, sph, cyl, freqs, prep, fcs, mask,
+        dim3 grid((unsigned)((L.n_rx + 63) / 64), (unsigned)(nb > 0 ? nb : 1));
+        hipLaunchKernelGGL((k_paths<R>), grid, dim3(64 * (K + 1)), 0, s, L, rx, sph, cyl, freqs, prep, fcs, mask,
                            (PathRec<R>*)rec, flags);
         return hipGetLastError();
     }
