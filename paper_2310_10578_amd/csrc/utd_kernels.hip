@@ -1,10 +1,18 @@
 // HIP kernels of the smooth-surface UTD field evaluation (gfx950).
 //
-//   k_paths    per (receiver, body) path validity + visibility bits (the U of
-//              Eqs. (1)-(2)) and the frequency-independent constants of every
-//              valid path; per receiver inside / line-of-sight flags; it also
-//              stores the body and frequency constants used later
+// Visibility and path constants (frequency independent):
+//   k_setup / k_cand / k_vis / k_rec   scenes with triangles: candidate
+//              paths per (receiver, body), queued; any-hit tests of their
+//              legs; records of the visible ones
+//   k_paths    scenes of bodies only: the same in one pass without a queue
+// Both produce the per (receiver, body) mask bits (the U of Eqs. (1)-(2)),
+// one record of frequency-independent constants per visible path, the
+// receiver flags, and the body and frequency constants used later.
+// Field:
 //   k_field    per (receiver, frequency chunk) coherent field of Eqs. (1)-(4)
+//   k_census   per-bit counts of the masks (measurement)
+// The adjoint (utd_adjoint.h) and the batched kernel (utd_batched.h) are
+// included at the end.
 //
 // In k_field one lane owns one receiver and a chunk of FC frequencies; it
 // walks the bodies in order, reads each valid path's record once and runs the
@@ -82,11 +90,10 @@ __device__ __forceinline__ bool seg_blocked(d3 P0, d3 P1, const LaunchParams& L,
 // Path records: the frequency-independent constants of one valid path,
 // written by the visibility pass and read by the field kernel.  Slot-major
 // layout rec[(body * S + slot) * n_rx + rx] keeps both passes coalesced;
-// S = 2 (l_enc + 1) bounds the valid paths of a (receiver, body) pair (one
-// side of a lit receiver carries the reflection instead of a creeping path).
-// Creeping paths fill slots 0, 1, ... in (ell, side) order; the reflection,
-// when present, always sits in slot S - 1 (it then leaves at most S - 1
-// creeping paths), so the field kernel can treat the two kinds separately.
+// S = 2 (l_enc + 1) + 1 slots per (receiver, body) pair, one per possible
+// path: the creeping path of mask bit 2 ell + side in slot 2 ell + side, the
+// reflection in the last slot.  Only the slots of set mask bits are written
+// or read.
 template <typename R> struct PathRec;
 template <> struct PathRec<float> {          // 64 bytes
     double s_tot;
@@ -154,15 +161,17 @@ __device__ __forceinline__ int rec_slot(const LaunchParams& L, int bit) {
 // (in a room with the source above the cylinder tops most helices leave the
 // lateral surface), so the BVH traversal, the expensive part, runs over a
 // compacted queue of candidate paths with every lane busy:
+//   k_setup queue counters and the per-body constants.
 //   k_cand  one lane per (receiver, body) pair (slot 0: the receiver's flags
 //           and its direct ray): classification, path existence, reflection
 //           point; appends one queue entry per candidate path (wave-level
 //           prefix sum, one atomic per wavefront).
 //   k_vis   one lane per queue entry: the path's legs against the other
-//           bodies and the BVH; a visible path sets its mask bit and writes
-//           its record.
-// The queue order varies between runs; the outputs (mask bits, records,
-// flags) do not.
+//           bodies and the BVH; a visible path sets its mask bit and joins
+//           the visible list.
+//   k_rec   one lane per visible path: its record.
+// The queue and list orders vary between runs; the outputs (mask bits,
+// records, flags) do not.
 // ---------------------------------------------------------------------------
 constexpr uint64_t kLosEntry = 0xffffull;   // body field of a direct-ray entry
 

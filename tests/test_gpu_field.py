@@ -193,3 +193,20 @@ def test_receivers_and_source_outside_the_room(tx_outside):
     err = normwise(Eg[:, :, ok], Eo[:, :, ok])
     _report("segments leaving the room (source %s)" % ("outside" if tx_outside else "inside"), err)
     assert np.all(err <= TOL[1])
+
+
+@pytest.mark.parametrize("l_enc", [0, 1, 2])
+def test_bodies_only_scene_all_path_kinds(l_enc):
+    """A scene of bodies only (spheres and cylinders, no triangles) takes the
+    single-pass visibility kernel, one wavefront per path kind: 2 (l_enc + 1)
+    creeping paths and the reflection, and the flags wavefront.  FP64 and
+    FP32 against the oracle for every encirclement count."""
+    cfg = W.small_room(n_cyl=4, n_side=12, spheres=True)
+    cfg = dict(cfg, scene=dict(cfg["scene"], tri=np.zeros((0, 3, 3), np.float32)))
+    Eo, info = run_oracle(cfg, opts=dict(l_enc=l_enc))
+    for precision in (1, 0):
+        Eg, fg = run_library(cfg, precision, l_enc=l_enc)
+        np.testing.assert_array_equal(fg & 13, info["flags"] & 13)
+        err = normwise(Eg, Eo)
+        _report("bodies only, l_enc=%d p%d" % (l_enc, precision), err)
+        assert np.all(err <= TOL[precision])
