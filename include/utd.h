@@ -116,7 +116,8 @@ int64_t utd_scene_nodes(const utd_scene *scene);
  *            Fully overwritten.
  *   rx_flags device uint8 [n_rx] or NULL.
  * n_rx == 0 or n_f == 0 enqueues nothing and returns UTD_OK.
- * Scratch (path masks and records, the candidate-path queue) comes from a
+ * Scratch (path masks and records, the candidate-path queue and visible
+ * list) comes from a
  * grow-only buffer the library keeps per (device, stream) between calls,
  * allocated stream-ordered and released at process exit; calls on one stream
  * are ordered by the stream, so issuing them from several host threads at

@@ -17,11 +17,13 @@ struct BatchParams {
     int64_t n_rx;            // receivers in the array (bound for rx_off)
     int tile;                // receivers per work item (= blockDim.x)
 };
-// Visibility (two passes through a queue of candidate paths); also stores
-// the body constants (prep) and, when freqs is not NULL, the frequency
-// constants (fcs) for the later kernels of the call.  Record slots per
-// (receiver, body): 2 (l_enc + 1) + 1.  Queue capacity cap entries
-// (n_rx (1 + n_bodies (2 l_enc + 3)) always suffices).
+// Visibility: with triangles (nodes != NULL) through a queue of candidate
+// paths (ent, ent_th) and a list of the visible ones (vis_list), each of cap
+// entries (n_rx (1 + n_bodies (2 l_enc + 3)) always suffices), with their
+// lengths in counter[0] and counter[1]; without triangles in one pass.  Also
+// stores the body constants (prep) and, when freqs is not NULL, the
+// frequency constants (fcs) for the later kernels of the call.  Record slots
+// per (receiver, body): 2 (l_enc + 1) + 1.
 hipError_t launch_paths(const LaunchParams& L, int precision, const float* rx, const float* sph, const float* cyl,
                         const double* freqs, BodyPrep* prep, FreqConst* fcs, const float4* nodes, const float4* tris,
                         uint8_t* mask, void* rec, uint8_t* flags, uint64_t* ent, double* ent_th,
