@@ -23,14 +23,14 @@ sys.path.insert(0, ROOT)
 
 # FP32 operations per (path, frequency) of the field kernel, counted from its
 # formula set for a creeping path (utd_fock.h / add_path): argument scaling 5,
-# transition function 31 (index map and local variable 5, degree-4 complex
-# Horner 16, combine 10), regime lookup 45 (index map 4, degree-4 soft+hard
-# complex Horner 32, combine 9), phase 30 (range reduction and degree-9/8
+# transition function 23 (index map 3, degree-4 complex Horner 16, combine
+# into W = A0 + A1 v 4), regime lookup 42 (index map 2, degree-4 soft+hard
+# complex Horner 32, combine 8), phase 30 (range reduction and degree-9/8
 # sin/cos polynomials), phase times coefficients 12, accumulation into 3
 # complex components 24.  The per-frequency k^{-1/6} scaling of each
 # receiver's sum is not counted.  Direct field per (receiver, frequency): 36
 # (phase 30 + 6 FMA).
-FLOPS_PER_PATH_FREQ = 5 + 31 + 45 + 30 + 12 + 24
+FLOPS_PER_PATH_FREQ = 5 + 23 + 42 + 30 + 12 + 24
 FLOPS_LOS = 36
 PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (published, packed-FP32 rate)
 

@@ -69,9 +69,10 @@ __device__ __forceinline__ void record_adjoint(const PathEval<R>& pe, const Tabs
             a.xi = D(xi, dir == 0 ? fc.k13 : (R)0);
             a.u = D(u, dir == 1 ? fc.sk : (R)0);
             a.iu = RT<D>::rcp(u > (R)0 ? a.u : D((R)1));
-            a.q = D(q, dir == 2 ? fc.k16 : (R)0);
             a.ixi = D(ixi, dir == 0 ? dixi : (R)0);
             a.h = D(h, dir == 0 ? dh : (R)0);
+            a.qc = D(q, dir == 2 ? fc.k16 : (R)0) * D((R)-kC2E4);
+            a.xc = a.ixi * D((R)kC2E4);
             cplx<D> ks, kh;
             fock_kernel<D, kAny>(tb, a, refl, &ks, &kh);
             if (dir == 0) {

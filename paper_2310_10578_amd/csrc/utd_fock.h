@@ -151,7 +151,9 @@ __device__ __forceinline__ cplx<float> mode_factor<float>(float dx, double zre, 
 // B-type kernels K_s, K_h of one path at one frequency.
 //   creeping (refl = false): K = B_p(xi, X)
 //   reflection (refl = true): K = Rbar_p = -e^{-j xi^3/12} B_p(xi, X)
-// q = sqrt(X)/|xi| = sqrt(k L / 2)/m is passed explicitly (finite at xi = 0).
+// q = sqrt(X)/|xi| = sqrt(k L / 2)/m enters explicitly (finite at xi = 0), as
+// qc = -kC2E4 q, and 1/xi also as xc = kC2E4/xi: per path the constant
+// factor folds into the path's own constant.
 // Written without data-dependent branches: the regime and the transition
 // range only select the segment, the local variable and a few operands, so a
 // wavefront whose lanes sit in different regimes stays converged.
@@ -159,13 +161,17 @@ __device__ __forceinline__ cplx<float> mode_factor<float>(float dx, double zre, 
 // kind of path: kCreep (creeping paths: xi >= 0, regimes 0/1, K = B_p), kRefl
 // (reflections: xi <= 0, regimes 1/2, K = Rbar_p) or kAny (mixed lanes).
 enum { kAny = 0, kCreep = 1, kRefl = 2 };
+// e^{-j pi/4}/(2 sqrt pi) = kC2E4 (1 - j)
+constexpr double kC2E4 = kInv2SqrtPi * kRs2;
+
 template <typename R> struct FockArgs {
     R xi;    // Fock parameter
     R u;     // sqrt(X), X the transition-function argument
     R iu;    // 1/u (any value when u < FA_HI)
-    R q;     // sqrt(X)/|xi|
     R ixi;   // 1/xi (0 when xi == 0)
     R h;     // sqrt(-xi)/2 (deep lit; 0 otherwise)
+    R qc;    // -kC2E4 q, q = sqrt(X)/|xi| (finite at xi = 0)
+    R xc;    // kC2E4 / xi
 };
 
 template <typename R, int MODE = kAny>
@@ -173,8 +179,7 @@ __device__ __forceinline__ void fock_kernel(const Tabs<typename BaseOf<R>::type>
                                             cplx<R>* Ks, cplx<R>* Kh) {
     using T = typename BaseOf<R>::type;
     using D = TabDims<T>;
-    const R c2e4 = (R)(kInv2SqrtPi * kRs2);   // e^{-j pi/4}/(2 sqrt pi) = c2e4 (1 - j)
-    const R xi = A.xi, u = A.u, q = A.q, ixi = A.ixi;
+    const R xi = A.xi, u = A.u, ixi = A.ixi;
 
     // --- transition function: A(u) for u < FA_HI, H(1/X) beyond -------------
     // The segment decides which of the two is read, so the two sides of the
@@ -187,13 +192,9 @@ __device__ __forceinline__ void fock_kernel(const Tabs<typename BaseOf<R>::type>
     const bool big = tseg >= D::NT;
     R v[2];
     horner2<T, R>(tb.tf + __umul24((unsigned)tseg, 2 * D::ROWS), st, v);
-    // the table holds G = F/sqrt(X) below FA_HI and -H = (1 - F) X above
-    cplx<R> G, omF;
-    const R omr = iX * v[0], omi = iX * v[1];
-    G.re = big ? ((R)1 - omr) * iu : v[0];
-    G.im = big ? -omi * iu : v[1];
-    omF.re = big ? omr : (R)1 - u * v[0];
-    omF.im = big ? omi : -u * v[1];
+    // the table holds v = G = F/sqrt(X) below FA_HI and v = -H = (1 - F) X
+    // above; G and 1 - F follow as A0 + A1 v (below: G = v, 1 - F = 1 - u v;
+    // above: G = (1 - iX v) iu, 1 - F = iX v) with real A0, A1 chosen below
 
     // --- regime table ------------------------------------------------------
     // creeping paths have xi >= 0 (regimes 0, 1), reflections xi <= 0 (1, 2);
@@ -223,10 +224,13 @@ __device__ __forceinline__ void fock_kernel(const Tabs<typename BaseOf<R>::type>
     // --- combine ------------------------------------------------------------
     // CW = e^{-j pi/4} coef W:  regime 1: coef = -sgn q/(2 sqrt pi), W = G
     //                          regimes 0, 2: coef = 1/(2 sqrt(pi) xi), W = 1 - F
-    cplx<R> W = regime == 1 ? G : omF;
+    const bool r1 = regime == 1;
+    const R A1 = big ? (r1 ? -(iX * iu) : iX) : (r1 ? (R)1 : -u);
+    const R A0 = big ? (r1 ? iu : (R)0) : (r1 ? (R)0 : (R)1);
+    const cplx<R> W{A0 + A1 * v[0], A1 * v[1]};
     if (MODE == kCreep) {
         // sgn(xi) = +1 for creeping paths (xi >= 0); K = P + CW
-        R f = regime == 1 ? -q * c2e4 : ixi * c2e4;
+        R f = r1 ? A.qc : A.xc;
         cplx<R> CW{f * (W.re + W.im), f * (W.im - W.re)};
         *Ks = cplx<R>{ps.re + CW.re, ps.im + CW.im};
         *Kh = cplx<R>{ph.re + CW.re, ph.im + CW.im};
@@ -236,7 +240,7 @@ __device__ __forceinline__ void fock_kernel(const Tabs<typename BaseOf<R>::type>
     if (MODE == kRefl) {
         // sgn = -1 on the lit side (xi <= 0): coef = q/(2 sqrt pi) in regime 1;
         // K = -(alpha P + e CW), alpha = e (regime 1) or sqrt(-xi)/2 (regime 2)
-        R f = regime == 1 ? q * c2e4 : ixi * c2e4;
+        R f = r1 ? -A.qc : A.xc;
         cplx<R> CW{f * (W.re + W.im), f * (W.im - W.re)};
         cplx<R> eCW = cmul(e, CW);
         const bool r2 = regime == 2;
@@ -247,7 +251,7 @@ __device__ __forceinline__ void fock_kernel(const Tabs<typename BaseOf<R>::type>
         return;
     }
     R sg = refl ? (xi > (R)0 ? (R)1 : (R)-1) : (xi < (R)0 ? (R)-1 : (R)1);
-    R f = regime == 1 ? -sg * q * c2e4 : ixi * c2e4;
+    R f = r1 ? sg * A.qc : A.xc;
     cplx<R> CW{f * (W.re + W.im), f * (W.im - W.re)};
     // creeping: K = P + CW
     // reflection / deep lit: K = -(alpha P + e CW), e = e^{-j xi^3/12},

@@ -536,9 +536,11 @@ __device__ __forceinline__ void add_path(const PathEval<R>& pe, const Tabs<R>& t
     a.xi = fc.k13 * pe.xh;
     a.u = fc.sk * pe.uh;
     a.iu = fc.isk * pe.iuh;
-    a.q = fc.k16 * pe.qhat;
     a.ixi = fc.ik13 * pe.ixh;
     a.h = (R)0.5 * fc.k16 * pe.sxh;
+    // the path factors are the same for every frequency of the lane's chunk
+    a.qc = fc.k16 * (pe.qhat * (R)-kC2E4);
+    a.xc = fc.ik13 * (pe.ixh * (R)kC2E4);
     cplx<R> Ks, Kh;
     fock_kernel<R, MODE>(tb, a, pe.refl != 0, &Ks, &Kh);
     cplx<R> ph = phase_rev<R>(fc.rev_per_m * pe.s_tot - 0.25 * pe.nc);
