@@ -188,8 +188,9 @@ utd_status utd_smooth_field_batched(const utd_scene *scene, int64_t n_frames,
 
 /* Tile shape of utd_smooth_field_batched: receivers per work item (64, 128
  * or 256; one lane per receiver) and resident workgroups per compute unit of
- * the persistent grid (1..16).  Chosen by the autotuner of the Python
- * package; applies to later calls.  Errors: UTD_E_ARG for other values. */
+ * the persistent grid (1..16; default 256 and 3).  Chosen by the autotuner
+ * of the Python package; applies to later calls.  Errors: UTD_E_ARG for
+ * other values. */
 utd_status utd_batched_config(int tile_rx, int blocks_per_cu);
 
 /* Path census (reporting): runs the classification and visibility stage of

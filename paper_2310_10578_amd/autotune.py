@@ -11,7 +11,7 @@ stream and leaves the fastest configured in the library.
 """
 from . import batched_config, smooth_field_batched
 
-CANDIDATES = ((64, 2), (64, 4), (64, 8), (128, 1), (128, 2), (128, 4), (256, 1), (256, 2))
+CANDIDATES = ((64, 4), (64, 8), (64, 12), (128, 2), (128, 4), (128, 6), (256, 1), (256, 2), (256, 3))
 
 
 def tune_batched(scene, body_off, cylinders, rx_off, rx, source, freqs, precision=0, reps=2, candidates=CANDIDATES,

@@ -211,8 +211,8 @@ struct BatchState {
 };
 std::mutex g_batch_mu;
 std::map<int, BatchState> g_batch;
-int g_batch_tile = 128;
-int g_batch_bpc = 4;
+int g_batch_tile = 256;
+int g_batch_bpc = 3;
 
 // Frequencies per lane: more frequencies per lane amortise the path geometry,
 // fewer keep enough lanes in flight.

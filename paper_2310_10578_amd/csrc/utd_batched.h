@@ -131,8 +131,21 @@ __device__ __forceinline__ int64_t uniform64(int64_t v) {
 //      bodies and paths in order, at every frequency, adding to E in place.
 constexpr int kBGroup = 32;
 
+// The Fock tables are read through the caches here, not staged in LDS: the
+// 20 KB of LDS they would take is what lets three workgroups of 256 share a
+// CU (measured 9 % faster on the crowd than two with the tables in LDS).
+template <typename R> struct GlobalTabs;
+template <> struct GlobalTabs<float> {
+    static __device__ __forceinline__ Tabs<float> get() { return Tabs<float>{&ft_f32_reg[0][0][0], &ft_f32_tf[0][0][0]}; }
+};
+template <> struct GlobalTabs<double> {
+    static __device__ __forceinline__ Tabs<double> get() {
+        return Tabs<double>{&ft_f64_reg[0][0][0], &ft_f64_tf[0][0][0]};
+    }
+};
+
 template <typename R, int TILE>
-__global__ void __launch_bounds__(TILE) k_batch(BatchParams B, const float* __restrict__ rx,
+__global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(3, 8))) k_batch(BatchParams B, const float* __restrict__ rx,
                                                 const float* __restrict__ cyl, const BodyPrep* __restrict__ prep,
                                                 const FreqConst* __restrict__ fcs, const int64_t* __restrict__ bo,
                                                 const int64_t* __restrict__ ro, const int64_t* __restrict__ tile_off,
@@ -145,10 +158,8 @@ __global__ void __launch_bounds__(TILE) k_batch(BatchParams B, const float* __re
     __shared__ unsigned int s_mask[kBGroup * TILE / 4];   // bytes [body in group][lane]
     __shared__ uint32_t s_q[QCAP];
     __shared__ int s_qn;
-    __shared__ __attribute__((aligned(16))) R s_reg[TableStage<R>::NREG];
-    __shared__ __attribute__((aligned(16))) R s_tf[TableStage<R>::NTF];
     __shared__ int64_t s_tile;
-    Tabs<R> tb = TableStage<R>::stage(s_reg, s_tf);
+    const Tabs<R> tb = GlobalTabs<R>::get();
     uint8_t* mask8 = reinterpret_cast<uint8_t*>(s_mask);
     double* thb = th_scratch + (int64_t)blockIdx.x * kBGroup * TILE;
     int* stk = stack + threadIdx.x;
