@@ -245,7 +245,7 @@ __global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(3, 8)
             __syncthreads();
             for (int bl = 0; bl < ng; ++bl) {
                 // --- 1. candidates of (receiver, body g0 + bl) --------------
-                if (act && !dead) {
+                if (act && !dead && cyl_paths_possible(fprep[g0 + bl], R3, T, L)) {
                     const BodyPrep P = fprep[g0 + bl];
                     RxGeo g = rx_geo<double, Kinds::Cylinders>(P, R3);
                     uint32_t cand = 0;

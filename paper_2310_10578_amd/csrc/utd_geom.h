@@ -417,6 +417,38 @@ __device__ __forceinline__ double alhazen(double a, double p1x, double p1y, doub
     return th;
 }
 
+// Whether a finite vertical cylinder can carry any path to the receiver at
+// all, from distances alone (no angles): a creeping path needs both its
+// attachment heights on the lateral surface, z_Q1 = z_T + dz d_T / L2 and
+// z_Q2 = z_T + dz (1 - d_R / L2), with L2 = d_T + a phi + d_R and
+// 0 <= phi < 2 pi (l_enc + 1) (d_T, d_R the tangent lengths); a reflection
+// needs its point's height (bounded as in refl_angle) there.  False only
+// when every such height range misses the surface, so the classification
+// (two atan2 per pair) can be skipped; a necessary condition, never a
+// sufficient one.
+__device__ __forceinline__ bool cyl_paths_possible(const BodyPrep& b, d3 Rp, d3 T, const LaunchParams& L) {
+    if (!b.ok) return false;
+    const double x = Rp.x - b.c[0], y = Rp.y - b.c[1];
+    const double a = b.a, dR = sqrt(x * x + y * y);
+    if (!(dR > a)) return false;
+    const double sD = sqrt((dR - a) * (dR + a));
+    const double dz = Rp.z - T.z;
+    const double slack = 1e-9 * (1.0 + fabs(T.z) + fabs(Rp.z));
+    const double zlo = b.z0 - slack, zhi = b.z0 + b.h + slack;
+    // z = z_T + dz f over f between fa and fb meets [zlo, zhi]
+    auto meets = [&](double fa, double fb) {
+        const double za = T.z + dz * fa, zb = T.z + dz * fb;
+        return fmax(za, zb) >= zlo && fmin(za, zb) <= zhi;
+    };
+    const double l0 = b.sI0 + sD, l1 = l0 + kTwoPi * (L.l_enc + 1) * a;
+    if (meets(b.sI0 / l1, b.sI0 / l0) && meets(1.0 - sD / l0, 1.0 - sD / l1)) return true;
+    if (L.lit_branch) {
+        const double fa = (b.dT - a) / ((b.dT - a) + sD), fb = b.sI0 / (b.sI0 + (dR - a));
+        if (meets(fa, fb)) return true;
+    }
+    return false;
+}
+
 // Reflection point for a lit receiver: the angle parameter (sphere: polar
 // angle in the T-C-R plane; cylinder: azimuth), false if the receiver is not
 // lit by this body or the point is off the lateral surface.

@@ -258,7 +258,7 @@ __global__ void __launch_bounds__(256) k_cand(LaunchParams L, const float* __res
         }
     } else {
         const BodyPrep P = prep[b];
-        if (act) {
+        if (act && (P.kind == 0 || cyl_paths_possible(P, R3, T, L))) {
             RxGeo g = rx_geo(P, R3);
             uint8_t m = 0;
             for (int ell = 0; ell <= L.l_enc; ++ell) {
@@ -276,6 +276,8 @@ __global__ void __launch_bounds__(256) k_cand(LaunchParams L, const float* __res
             }
             if (L.lit_branch && refl_angle(P, g, R3, T, &th)) cand |= (uint8_t)(1u << kBitRefl);
             mask[(int64_t)b * L.n_rx + i] = m;     // visible bits are added by k_vis
+        } else if (act) {
+            mask[(int64_t)b * L.n_rx + i] = 0;
         }
     }
     const int cnt = (los_cand ? 1 : 0) + __builtin_popcount(cand);
