@@ -196,6 +196,32 @@ __device__ __forceinline__ int64_t wave_append(int cnt, unsigned long long* coun
     return (int64_t)base + x - cnt;
 }
 
+// The same over a workgroup of 256 lanes: wave prefixes, the four wave
+// totals through LDS, one atomic per workgroup (the counter is shared by the
+// whole grid, so fewer atomics on it means less serialisation).  Every lane
+// of the workgroup must call it.
+__device__ __forceinline__ int64_t block_append(int cnt, unsigned long long* counter) {
+    __shared__ int s_wt[4];
+    __shared__ unsigned long long s_base;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int x = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_wt[wave] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int tot = s_wt[0] + s_wt[1] + s_wt[2] + s_wt[3];
+        s_base = tot > 0 ? atomicAdd(counter, (unsigned long long)tot) : 0ull;
+    }
+    __syncthreads();
+    int before = 0;
+    for (int w = 0; w < wave; ++w) before += s_wt[w];
+    return (int64_t)s_base + before + x - cnt;
+}
+
 // One slot per flagged lane among the lanes active at the call (one atomic
 // per wavefront); the returned slot is meaningful for flagged lanes.
 __device__ __forceinline__ int64_t wave_append_active(bool flag, unsigned long long* counter) {
@@ -281,7 +307,7 @@ __global__ void __launch_bounds__(256) k_cand(LaunchParams L, const float* __res
         }
     }
     const int cnt = (los_cand ? 1 : 0) + __builtin_popcount(cand);
-    int64_t q = wave_append(cnt, counter);
+    int64_t q = block_append(cnt, counter);
     if (los_cand && q < cap) {
         ent[q] = make_entry(i, kLosEntry, 0);
         ent_th[q] = 0.0;
