@@ -179,25 +179,8 @@ __device__ __forceinline__ uint64_t make_entry(int64_t i, int64_t b, int bit) {
     return (uint64_t)i | ((uint64_t)b << 32) | ((uint64_t)bit << 48);
 }
 
-// Exclusive prefix of cnt over the wavefront plus one atomic per wavefront;
-// every lane of the wavefront must call it.
-__device__ __forceinline__ int64_t wave_append(int cnt, unsigned long long* counter) {
-    const int lane = threadIdx.x & 63;
-    int x = cnt;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        int y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    const int total = __shfl(x, 63, 64);
-    unsigned long long base = 0;
-    if (lane == 63 && total > 0) base = atomicAdd(counter, (unsigned long long)total);
-    base = __shfl(base, 63, 64);
-    return (int64_t)base + x - cnt;
-}
-
-// The same over a workgroup of 256 lanes: wave prefixes, the four wave
-// totals through LDS, one atomic per workgroup (the counter is shared by the
+// Exclusive prefix of cnt over a workgroup of 256 lanes plus one atomic per
+// workgroup: wave prefixes, the four wave totals through LDS (the counter is shared by the
 // whole grid, so fewer atomics on it means less serialisation).  Every lane
 // of the workgroup must call it.
 __device__ __forceinline__ int64_t block_append(int cnt, unsigned long long* counter) {
@@ -220,19 +203,6 @@ __device__ __forceinline__ int64_t block_append(int cnt, unsigned long long* cou
     int before = 0;
     for (int w = 0; w < wave; ++w) before += s_wt[w];
     return (int64_t)s_base + before + x - cnt;
-}
-
-// One slot per flagged lane among the lanes active at the call (one atomic
-// per wavefront); the returned slot is meaningful for flagged lanes.
-__device__ __forceinline__ int64_t wave_append_active(bool flag, unsigned long long* counter) {
-    const uint64_t act = __ballot(1);
-    const uint64_t bal = __ballot(flag);
-    const int lane = threadIdx.x & 63;
-    const int leader = __builtin_ctzll(act);
-    unsigned long long base = 0;
-    if (lane == leader && bal) base = atomicAdd(counter, (unsigned long long)__popcll(bal));
-    base = __shfl(base, leader, 64);
-    return (int64_t)base + __popcll(bal & ((1ull << lane) - 1ull));
 }
 
 // Set-up of the two-pass visibility: queue and visible-list lengths, and the
@@ -334,15 +304,25 @@ __device__ __forceinline__ void vis_body(const LaunchParams& L, const float* __r
                                          const float4* __restrict__ tris, const uint64_t* __restrict__ ent,
                                          const double* __restrict__ ent_th, unsigned long long* __restrict__ counter,
                                          int64_t cap, uint8_t* __restrict__ mask, uint8_t* __restrict__ flags,
-                                         uint64_t* __restrict__ vis_list, int* stack) {
+                                         uint64_t* __restrict__ vis_list, int* stack, uint64_t* vbuf) {
     int* stk = stack + threadIdx.x;
+    // Visible paths collect in the wavefront's own LDS buffer (vbuf, 128
+    // entries) and go to the global list 64 at a time: one atomic on the
+    // grid-wide counter per 64 visible paths instead of one per wavefront
+    // and iteration.  The loop runs the same trip count on every lane of a
+    // wavefront, so all 64 lanes take part in each buffer step.
+    const int lane = threadIdx.x & 63;
+    int nbuf = 0;                                     // wave-uniform
     const int stride = 256;
     int64_t total = (int64_t)counter[0];
     total = total < cap ? total : cap;
     const d3 T = mk(L.T[0], L.T[1], L.T[2]);
     const bool bo = L.bodies_occlude != 0;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
-         q += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t qw = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); qw < total;
+         qw += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = qw + lane;
+        bool vis = false;
+        if (q < total) {
         const uint64_t en = ent[q];
         const int64_t i = (int64_t)(en & 0xffffffffu);
         const int64_t bb = (int64_t)((en >> 32) & 0xffffu);
@@ -352,8 +332,7 @@ __device__ __forceinline__ void vis_body(const LaunchParams& L, const float* __r
             // the receiver's only entry of this kind: a plain byte update
             if (!seg_blocked(T, R3, L, sph, cyl, -1, true, nodes, tris, stk, stride))
                 flags[i] = (uint8_t)(flags[i] | kFlagLos);
-            continue;
-        }
+        } else {
         const int b = (int)bb;
         const BodyPrep P = prep[b];
         RxGeo g = rx_geo(P, R3);
@@ -370,15 +349,35 @@ __device__ __forceinline__ void vis_body(const LaunchParams& L, const float* __r
             else
                 cyl_creep<R, double>(P, g, R3, T, L, sgn, ell, (PathEval<R>*)nullptr, &pts);
         }
-        bool vis = !seg_blocked(pts.P0, pts.P1, L, sph, cyl, b, bo, nodes, tris, stk, stride);
+        vis = !seg_blocked(pts.P0, pts.P1, L, sph, cyl, b, bo, nodes, tris, stk, stride);
         if (vis) vis = !seg_blocked(pts.P2, pts.P3, L, sph, cyl, b, bo, nodes, tris, stk, stride);
         if (vis) {
             // mask bytes of one pair can be set by concurrent lanes: OR into the word
             const int64_t mb = (int64_t)b * L.n_rx + i;
             atomicOr(reinterpret_cast<unsigned int*>(mask + (mb & ~(int64_t)3)), (1u << bit) << (8 * (mb & 3)));
         }
-        const int64_t k = wave_append_active(vis, counter + 1);
-        if (vis) vis_list[k] = (uint64_t)q;
+        }
+        }
+        // all 64 lanes: buffer this iteration's visible paths
+        const uint64_t bal = __ballot(vis);
+        if (vis) vbuf[nbuf + __popcll(bal & ((1ull << lane) - 1ull))] = (uint64_t)q;
+        nbuf += __popcll(bal);
+        if (nbuf >= 64) {
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(counter + 1, 64ull);
+            base = __shfl(base, 0, 64);
+            vis_list[base + lane] = vbuf[lane];
+            const uint64_t rest = lane + 64 < nbuf ? vbuf[lane + 64] : 0ull;
+            __builtin_amdgcn_wave_barrier();
+            if (lane + 64 < nbuf) vbuf[lane] = rest;
+            nbuf -= 64;
+        }
+    }
+    if (nbuf > 0) {
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(counter + 1, (unsigned long long)nbuf);
+        base = __shfl(base, 0, 64);
+        if (lane < nbuf) vis_list[base + lane] = vbuf[lane];
     }
 }
 
@@ -395,7 +394,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
                                              uint8_t* __restrict__ mask, uint8_t* __restrict__ flags,
                                              uint64_t* __restrict__ vis_list) {
     __shared__ int stack[kStackDepth * 256];
-    vis_body<R>(L, rx, sph, cyl, prep, nodes, tris, ent, ent_th, counter, cap, mask, flags, vis_list, stack);
+    __shared__ uint64_t vbuf[4 * 128];
+    vis_body<R>(L, rx, sph, cyl, prep, nodes, tris, ent, ent_th, counter, cap, mask, flags, vis_list, stack,
+                vbuf + 128 * (threadIdx.x >> 6));
 }
 
 // Pass 3: one lane per visible path (grid-stride over the visible list): the
