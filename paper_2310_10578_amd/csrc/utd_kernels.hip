@@ -164,8 +164,8 @@ __device__ __forceinline__ int rec_slot(const LaunchParams& L, int bit) {
 //   k_setup queue counters and the per-body constants.
 //   k_cand  one lane per (receiver, body) pair (slot 0: the receiver's flags
 //           and its direct ray): classification, path existence, reflection
-//           point; appends one queue entry per candidate path (wave-level
-//           prefix sum, one atomic per wavefront).
+//           point; appends one queue entry per candidate path (prefix sum
+//           over the workgroup, one atomic per workgroup).
 //   k_vis   one lane per queue entry: the path's legs against the other
 //           bodies and the BVH; a visible path sets its mask bit and joins
 //           the visible list.
@@ -180,9 +180,9 @@ __device__ __forceinline__ uint64_t make_entry(int64_t i, int64_t b, int bit) {
 }
 
 // Exclusive prefix of cnt over a workgroup of 256 lanes plus one atomic per
-// workgroup: wave prefixes, the four wave totals through LDS (the counter is shared by the
-// whole grid, so fewer atomics on it means less serialisation).  Every lane
-// of the workgroup must call it.
+// workgroup: wave prefixes, the four wave totals through LDS.  The counter is
+// shared by the whole grid, so fewer atomics on it means less serialisation.
+// Every lane of the workgroup must call it.
 __device__ __forceinline__ int64_t block_append(int cnt, unsigned long long* counter) {
     __shared__ int s_wt[4];
     __shared__ unsigned long long s_base;
@@ -323,40 +323,41 @@ __device__ __forceinline__ void vis_body(const LaunchParams& L, const float* __r
         const int64_t q = qw + lane;
         bool vis = false;
         if (q < total) {
-        const uint64_t en = ent[q];
-        const int64_t i = (int64_t)(en & 0xffffffffu);
-        const int64_t bb = (int64_t)((en >> 32) & 0xffffu);
-        const int bit = (int)(en >> 48);
-        const d3 R3 = mk(rx[3 * i], rx[3 * i + 1], rx[3 * i + 2]);
-        if (bb == (int64_t)kLosEntry) {
-            // the receiver's only entry of this kind: a plain byte update
-            if (!seg_blocked(T, R3, L, sph, cyl, -1, true, nodes, tris, stk, stride))
-                flags[i] = (uint8_t)(flags[i] | kFlagLos);
-        } else {
-        const int b = (int)bb;
-        const BodyPrep P = prep[b];
-        RxGeo g = rx_geo(P, R3);
-        PathPts pts;
-        if (bit == kBitRefl) {
-            d3 Q, n;
-            refl_point<double>(P, g, R3, T, ent_th[q], &Q, &n);
-            pts.P0 = T; pts.P1 = Q; pts.P2 = Q; pts.P3 = R3;
-        } else {
-            const int ell = bit >> 1, sgn = (bit & 1) ? -1 : 1;
-            bool cz;
-            if (P.kind == 0)
-                sphere_creep<R, double>(P, g, R3, T, L, sgn, ell, &cz, (PathEval<R>*)nullptr, &pts);
-            else
-                cyl_creep<R, double>(P, g, R3, T, L, sgn, ell, (PathEval<R>*)nullptr, &pts);
-        }
-        vis = !seg_blocked(pts.P0, pts.P1, L, sph, cyl, b, bo, nodes, tris, stk, stride);
-        if (vis) vis = !seg_blocked(pts.P2, pts.P3, L, sph, cyl, b, bo, nodes, tris, stk, stride);
-        if (vis) {
-            // mask bytes of one pair can be set by concurrent lanes: OR into the word
-            const int64_t mb = (int64_t)b * L.n_rx + i;
-            atomicOr(reinterpret_cast<unsigned int*>(mask + (mb & ~(int64_t)3)), (1u << bit) << (8 * (mb & 3)));
-        }
-        }
+            const uint64_t en = ent[q];
+            const int64_t i = (int64_t)(en & 0xffffffffu);
+            const int64_t bb = (int64_t)((en >> 32) & 0xffffu);
+            const int bit = (int)(en >> 48);
+            const d3 R3 = mk(rx[3 * i], rx[3 * i + 1], rx[3 * i + 2]);
+            if (bb == (int64_t)kLosEntry) {
+                // the receiver's only entry of this kind: a plain byte update
+                if (!seg_blocked(T, R3, L, sph, cyl, -1, true, nodes, tris, stk, stride))
+                    flags[i] = (uint8_t)(flags[i] | kFlagLos);
+            } else {
+                const int b = (int)bb;
+                const BodyPrep P = prep[b];
+                RxGeo g = rx_geo(P, R3);
+                PathPts pts;
+                if (bit == kBitRefl) {
+                    d3 Q, n;
+                    refl_point<double>(P, g, R3, T, ent_th[q], &Q, &n);
+                    pts.P0 = T; pts.P1 = Q; pts.P2 = Q; pts.P3 = R3;
+                } else {
+                    const int ell = bit >> 1, sgn = (bit & 1) ? -1 : 1;
+                    bool cz;
+                    if (P.kind == 0)
+                        sphere_creep<R, double>(P, g, R3, T, L, sgn, ell, &cz, (PathEval<R>*)nullptr, &pts);
+                    else
+                        cyl_creep<R, double>(P, g, R3, T, L, sgn, ell, (PathEval<R>*)nullptr, &pts);
+                }
+                vis = !seg_blocked(pts.P0, pts.P1, L, sph, cyl, b, bo, nodes, tris, stk, stride);
+                if (vis) vis = !seg_blocked(pts.P2, pts.P3, L, sph, cyl, b, bo, nodes, tris, stk, stride);
+                if (vis) {
+                    // mask bytes of one pair can be set by concurrent lanes: OR into the word
+                    const int64_t mb = (int64_t)b * L.n_rx + i;
+                    atomicOr(reinterpret_cast<unsigned int*>(mask + (mb & ~(int64_t)3)),
+                             (1u << bit) << (8 * (mb & 3)));
+                }
+            }
         }
         // all 64 lanes: buffer this iteration's visible paths
         const uint64_t bal = __ballot(vis);
