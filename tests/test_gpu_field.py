@@ -229,3 +229,25 @@ def test_ragged_receivers_and_frequency_chunks(n_side, n_f):
     _report("ragged %d rx x %d f" % (n, n_f), err)
     assert np.all(err <= TOL[0])
     np.testing.assert_array_equal(fg[idx] & 5, info["flags"] & 5)
+
+
+@pytest.mark.parametrize("seed", list(range(8)))
+def test_random_scenes(seed):
+    """Seeded random small rooms (cylinders of random base, height and radius,
+    spheres at random heights, the source anywhere, receivers on a grid and at
+    random points, random frequencies, l_enc = seed mod 3): FP64 and FP32
+    against the oracle.  Receivers whose visibility decisions differ between
+    the FP32 BVH test and the oracle's FP64 test (grazing segments) are
+    counted and excluded, as in the room tests."""
+    cfg = W.random_scene(seed)
+    kw = dict(l_enc=seed % 3)
+    Eo, info = run_oracle(cfg, opts=kw)
+    for precision in (1, 0):
+        Eg, fg = run_library(cfg, precision, **kw)
+        ok = (fg & 13) == (info["flags"] & 13)
+        d = np.linalg.norm(Eg - Eo, axis=1) / np.maximum(np.linalg.norm(Eo, axis=1), 1e-30)
+        bad = (d.max(axis=0) > (1e-6 if precision else 1e-3)) | ~ok
+        assert bad.mean() < 0.02, (seed, precision, int(bad.sum()))
+        err = normwise(Eg[:, :, ~bad], Eo[:, :, ~bad])
+        _report("random scene %d p%d (%d excluded)" % (seed, precision, bad.sum()), err)
+        assert np.all(err <= TOL[precision])

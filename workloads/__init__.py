@@ -239,3 +239,51 @@ def small_room(n_cyl=8, edge=0.5, n_side=24, freqs=(5e9, 28e9), spheres=False):
         sc["spheres"] = np.array([[2.0, 6.5, 0.6, 0.35], [8.2, 1.4, 1.0, 0.5]], np.float32)
     return dict(name="room-coarse-%dcyl-%dx%d" % (n_cyl, n_side, n_side), scene=sc, tx=room_tx(),
                 rx=room_grid(n_side), freqs=np.asarray(freqs, float), boxes=boxes)
+
+
+def random_scene(seed, n_cyl=4, n_sph=2, n_box=3, n_rx_side=(11, 9), n_f=2):
+    """A seeded random small room for parity sweeps: a coarse shell, a few
+    boxes, cylinders with random base heights, heights and radii, spheres at
+    random heights, the source anywhere in the room (below or above the
+    bodies' tops), receivers on a grid at a random height plus random points,
+    and random frequencies in 1-30 GHz.  Bodies do not overlap each other or
+    the boxes, and the source and receivers may be anywhere (inside bodies
+    too: those receivers are flagged)."""
+    rng = _rng(8, seed)
+    Lx, Ly, Lz = ROOM
+    boxes = []
+    for _ in range(n_box):
+        sz = rng.uniform(0.3, 1.5, 3)
+        x0, y0 = rng.uniform(0, Lx - sz[0]), rng.uniform(0, Ly - sz[1])
+        boxes.append((np.array([x0, y0, 0.0]), np.array([x0 + sz[0], y0 + sz[1], sz[2]])))
+    tri = np.concatenate([room_shell(1.0)] + [box_triangles(lo, hi) for lo, hi in boxes]).astype(np.float32)
+    discs = []
+    cyl, sph = [], []
+    tries = 0
+    while len(cyl) + len(sph) < n_cyl + n_sph and tries < 100000:
+        tries += 1
+        a = rng.uniform(0.1, 0.5)
+        cx, cy = rng.uniform(a + 0.05, Lx - a - 0.05), rng.uniform(a + 0.05, Ly - a - 0.05)
+        if any(_disc_hits_box(cx, cy, a, lo, hi) for lo, hi in boxes):
+            continue
+        if any((cx - d[0]) ** 2 + (cy - d[1]) ** 2 <= (a + d[2] + 0.05) ** 2 for d in discs):
+            continue
+        discs.append((cx, cy, a))
+        if len(cyl) < n_cyl:
+            z0 = rng.uniform(0.0, 0.5)
+            cyl.append((cx, cy, z0, rng.uniform(0.8, 2.5 - z0), a))
+        else:
+            sph.append((cx, cy, rng.uniform(a, Lz - a), a))
+    tx = dict(pos=np.array([rng.uniform(0.2, Lx - 0.2), rng.uniform(0.2, Ly - 0.2), rng.uniform(0.3, 2.8)],
+                           np.float32),
+              dipole=rng.normal(size=3).astype(np.float32), amplitude=1.0)
+    nx, ny = n_rx_side
+    xs, ys = np.meshgrid(Lx * (np.arange(nx) + 0.5) / nx, Ly * (np.arange(ny) + 0.5) / ny, indexing="ij")
+    grid = np.stack([xs.ravel(), ys.ravel(), np.full(xs.size, rng.uniform(0.2, 2.8))], 1)
+    pts = np.stack([rng.uniform(0, Lx, 32), rng.uniform(0, Ly, 32), rng.uniform(0, Lz, 32)], 1)
+    sc = dict(tri=tri, spheres=np.array(sph, np.float32).reshape(-1, 4),
+              cylinders=np.array(cyl, np.float32).reshape(-1, 5))
+    return dict(name="random-room-%d" % seed, scene=sc, tx=tx,
+                rx=np.concatenate([grid, pts]).astype(np.float32),
+                freqs=np.sort(rng.uniform(1e9, 30e9, n_f)), boxes=boxes)
+
