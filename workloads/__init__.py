@@ -241,7 +241,7 @@ def small_room(n_cyl=8, edge=0.5, n_side=24, freqs=(5e9, 28e9), spheres=False):
                 rx=room_grid(n_side), freqs=np.asarray(freqs, float), boxes=boxes)
 
 
-def random_scene(seed, n_cyl=4, n_sph=2, n_box=3, n_rx_side=(11, 9), n_f=2):
+def random_scene(seed, n_cyl=4, n_sph=2, n_box=3, n_rx_side=(11, 9), n_pts=32, n_f=2):
     """A seeded random small room for parity sweeps: a coarse shell, a few
     boxes, cylinders with random base heights, heights and radii, spheres at
     random heights, the source anywhere in the room (below or above the
@@ -280,7 +280,7 @@ def random_scene(seed, n_cyl=4, n_sph=2, n_box=3, n_rx_side=(11, 9), n_f=2):
     nx, ny = n_rx_side
     xs, ys = np.meshgrid(Lx * (np.arange(nx) + 0.5) / nx, Ly * (np.arange(ny) + 0.5) / ny, indexing="ij")
     grid = np.stack([xs.ravel(), ys.ravel(), np.full(xs.size, rng.uniform(0.2, 2.8))], 1)
-    pts = np.stack([rng.uniform(0, Lx, 32), rng.uniform(0, Ly, 32), rng.uniform(0, Lz, 32)], 1)
+    pts = np.stack([rng.uniform(0, Lx, n_pts), rng.uniform(0, Ly, n_pts), rng.uniform(0, Lz, n_pts)], 1)
     sc = dict(tri=tri, spheres=np.array(sph, np.float32).reshape(-1, 4),
               cylinders=np.array(cyl, np.float32).reshape(-1, 5))
     return dict(name="random-room-%d" % seed, scene=sc, tx=tx,
