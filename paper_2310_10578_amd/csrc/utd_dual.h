@@ -94,6 +94,26 @@ __device__ __forceinline__ double gsqrt(double x) { return ::sqrt(x); }
 __device__ __forceinline__ double gatan2(double y, double x) { return ::atan2(y, x); }
 __device__ __forceinline__ void gsincos(double x, double* s, double* c) { sincos_moderate(x, s, c); }
 __device__ __forceinline__ double gfloor(double x) { return ::floor(x); }
+// 1/x and 1/sqrt(x): the hardware estimate refined by two Newton steps (each
+// squares the relative error), within a few ulp of the rounded quotient and
+// without a division's scaling and fix-up steps.  For zero or infinite x the
+// estimate itself (infinity or zero) is returned.
+__device__ __forceinline__ double grcp(double x) {
+    const double r0 = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r0, 1.0);
+    double r = fma(r0, e, r0);
+    e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    return r == r ? r : r0;
+}
+__device__ __forceinline__ double grsqrt(double x) {
+    const double y0 = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * y0, y0, 1.0);   // 1 - x y^2
+    double y = fma(0.5 * y0, e, y0);
+    e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    return y == y ? y : y0;
+}
 
 __device__ __forceinline__ Dual<double> gsqrt(Dual<double> x) {
     double r = ::sqrt(x.v);
@@ -110,6 +130,14 @@ __device__ __forceinline__ void gsincos(Dual<double> x, Dual<double>* s, Dual<do
     *c = Dual<double>(cv, -sv * x.d);
 }
 __device__ __forceinline__ double gfloor(Dual<double> x) { return ::floor(x.v); }
+__device__ __forceinline__ Dual<double> grcp(Dual<double> x) {
+    const double r = grcp(x.v);
+    return Dual<double>(r, -x.d * r * r);
+}
+__device__ __forceinline__ Dual<double> grsqrt(Dual<double> x) {
+    const double y = grsqrt(x.v);
+    return Dual<double>(y, -0.5 * x.d * y * y * y);
+}
 
 template <> struct RT<Dual<float>> {
     using D = Dual<float>;

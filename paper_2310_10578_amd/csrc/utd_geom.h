@@ -53,10 +53,10 @@ __device__ __forceinline__ void set_fock_consts(PathEvalT<R, G>* pe, R mhat, R p
     R sl = RT<R>::sqrt_((R)0.5 * Ld);
     pe->xh = xh;
     pe->uh = sl * (phi_e < (R)0 ? -phi_e : phi_e);
-    pe->qhat = sl / mhat;
-    pe->ixh = xh != (R)0 ? (R)1 / xh : (R)0;
+    pe->qhat = sl * RT<R>::rcp(mhat);
+    pe->ixh = xh != (R)0 ? RT<R>::rcp(xh) : (R)0;
     pe->sxh = RT<R>::sqrt_(xh < (R)0 ? -xh : (R)0);
-    pe->iuh = pe->uh > (R)0 ? (R)1 / pe->uh : (R)0;
+    pe->iuh = pe->uh > (R)0 ? RT<R>::rcp(pe->uh) : (R)0;
 }
 
 // Points of a path (for the visibility tests).
@@ -76,7 +76,7 @@ __device__ __forceinline__ BodyPrepT<G> prep_sphere(V3<G> T, V3<G> C, G a) {
     p.z0 = 0; p.h = 0;
     V3<G> v = T - C;
     p.dT = gnorm(v);
-    G idT = G(1.0) / p.dT;
+    G idT = grcp(p.dT);
     p.eT[0] = v.x * idT; p.eT[1] = v.y * idT; p.eT[2] = v.z * idT;
     p.ok = p.dT > p.a;
     p.sI0 = p.ok ? gsqrt((p.dT - p.a) * (p.dT + p.a)) : G(0.0);
@@ -93,7 +93,8 @@ __device__ __forceinline__ BodyPrepT<G> prep_cylinder(V3<G> T, G cx, G cy, doubl
     p.z0 = z0; p.h = h; p.a = a;
     G tx = T.x - cx, ty = T.y - cy;
     p.dT = gsqrt(tx * tx + ty * ty);
-    p.eT[0] = tx / p.dT; p.eT[1] = ty / p.dT; p.eT[2] = G(0.0);
+    const G idT = grcp(p.dT);
+    p.eT[0] = tx * idT; p.eT[1] = ty * idT; p.eT[2] = G(0.0);
     p.ok = p.dT > p.a;
     p.sI0 = p.ok ? gsqrt((p.dT - p.a) * (p.dT + p.a)) : G(0.0);
     p.gT = gatan2(p.sI0, p.a);
@@ -143,7 +144,8 @@ template <typename G>
 __device__ __forceinline__ RxGeoT<G> rx_geo_sphere(const BodyPrepT<G>& b, V3<G> R) {
     RxGeoT<G> g;
     G a = b.a;
-    G cgT = a / b.dT, sgT = b.sI0 / b.dT;
+    const G idT = grcp(b.dT);
+    G cgT = a * idT, sgT = b.sI0 * idT;
     V3<G> C = v3(b.c);
     V3<G> eT = v3(b.eT);
     V3<G> v = R - C;
@@ -153,7 +155,7 @@ __device__ __forceinline__ RxGeoT<G> rx_geo_sphere(const BodyPrepT<G>& b, V3<G> 
     V3<G> w = v - along * eT;
     g.wn = gnorm(w);
     if (g.wn > 1e-300) {
-        g.eperp = (G(1.0) / g.wn) * w;
+        g.eperp = grcp(g.wn) * w;
     } else {
         d3 ap = any_perp(val3(eT));
         g.eperp = V3<G>{ap.x, ap.y, ap.z};
@@ -161,7 +163,7 @@ __device__ __forceinline__ RxGeoT<G> rx_geo_sphere(const BodyPrepT<G>& b, V3<G> 
     g.dR = gsqrt(d2);
     g.ok = g.dR > a;
     g.sD0 = g.ok ? gsqrt((g.dR - a) * (g.dR + a)) : G(0.0);
-    G id2 = G(1.0) / d2;
+    G id2 = grcp(d2);
     // th2_+ = theta_R - gR ; th2_- = 2 pi - theta_R - gR
     g.c2p = (along * a + g.wn * g.sD0) * id2;
     g.s2p = (g.wn * a - along * g.sD0) * id2;
@@ -180,7 +182,8 @@ template <typename G>
 __device__ __forceinline__ RxGeoT<G> rx_geo_cylinder(const BodyPrepT<G>& b, V3<G> R) {
     RxGeoT<G> g;
     G a = b.a;
-    G cgT = a / b.dT, sgT = b.sI0 / b.dT;
+    const G idT = grcp(b.dT);
+    G cgT = a * idT, sgT = b.sI0 * idT;
     G x = R.x - b.c[0], y = R.y - b.c[1];
     G r2 = x * x + y * y;
     g.dR = gsqrt(r2);
@@ -189,7 +192,7 @@ __device__ __forceinline__ RxGeoT<G> rx_geo_cylinder(const BodyPrepT<G>& b, V3<G
     g.wn = G(0.0);
     g.along = G(0.0);
     g.eperp = V3<G>{G(0.0), G(0.0), G(0.0)};
-    G ir = G(1.0) / r2;
+    G ir = grcp(r2);
     // R's tangent points: u_R rotated by -gR (side +) and +gR (side -)
     G cg = a, sg = g.sD0;     // times 1/dR each, folded into ir
     g.c2p = (x * cg + y * sg) * ir;
@@ -234,7 +237,8 @@ __device__ __forceinline__ bool sphere_creep(const BodyPrepT<G>& b, const RxGeoT
     if (!(b.ok && g.ok) || phi < 0.0) return false;
     if (g.wn < L.caustic_guard) { *caustic = true; return false; }
     G a = b.a;
-    G cg = a / b.dT, sg = b.sI0 / b.dT;
+    const G idT = grcp(b.dT);
+    G cg = a * idT, sg = b.sI0 * idT;
     G c2 = sgn > 0 ? g.c2p : g.c2m, s2 = sgn > 0 ? g.s2p : g.s2m;
     V3<G> eT = v3(b.eT);
     V3<G> ep = (double)sgn * g.eperp;
@@ -262,10 +266,10 @@ __device__ __forceinline__ bool sphere_creep(const BodyPrepT<G>& b, const RxGeoT
         R n1x = cgR * eTx + sgR * epx, n1y = cgR * eTy + sgR * epy, n1z = cgR * eTz + sgR * epz;
         R px = (R)L.p[0], py = (R)L.p[1], pz = (R)L.p[2];
         R sIR = (R)sI, sDR = (R)sD, aR = (R)a;
-        R Ld = sIR * sDR / (sIR + sDR);
+        R Ld = sIR * sDR * RT<R>::rcp(sIR + sDR);
         R mhat = RT<R>::cbrt_((R)0.5 * aR);
-        R Smod = RT<R>::sqrt_(aR * sgR / (sDR * (R)g.wn));
-        R A = (R)L.amp * Smod / sIR * ((R)-1.4142135623730951 * mhat);
+        R Smod = RT<R>::sqrt_(aR * sgR * RT<R>::rcp(sDR * (R)g.wn));
+        R A = (R)L.amp * Smod * RT<R>::rcp(sIR) * ((R)-1.4142135623730951 * mhat);
         set_fock_consts<R, G>(pe, mhat, (R)phi, Ld);
         R as = A * (px * bx + py * by + pz * bz);
         R ah = A * (px * n1x + py * n1y + pz * n1z);
@@ -293,10 +297,12 @@ __device__ __forceinline__ bool cyl_creep(const BodyPrepT<G>& b, const RxGeoT<G>
     G dT = b.sI0, dR = g.sD0;
     G L2 = dT + a * phi + dR;
     G dz = Rp.z - T.z;
-    G zQ1 = T.z + dz * dT / L2;
-    G zQ2 = T.z + dz * (dT + a * phi) / L2;
+    const G iL2 = grcp(L2);
+    G zQ1 = T.z + dz * dT * iL2;
+    G zQ2 = T.z + dz * (dT + a * phi) * iL2;
     if (zQ1 < b.z0 || zQ1 > b.z0 + b.h || zQ2 < b.z0 || zQ2 > b.z0 + b.h) return false;
-    G cgT = a / b.dT, sgT = b.sI0 / b.dT;
+    const G idT = grcp(b.dT);
+    G cgT = a * idT, sgT = b.sI0 * idT;
     // attachment direction: u_T rotated by sgn*gT; detachment: u2 of this side
     G c1 = b.eT[0] * cgT - (double)sgn * b.eT[1] * sgT, s1 = b.eT[1] * cgT + (double)sgn * b.eT[0] * sgT;
     G c2 = sgn > 0 ? g.c2p : g.c2m, s2 = sgn > 0 ? g.s2p : g.s2m;
@@ -310,8 +316,9 @@ __device__ __forceinline__ bool cyl_creep(const BodyPrepT<G>& b, const RxGeoT<G>
         G Stot = gsqrt(L2 * L2 + dz * dz);
         pe->s_tot = Stot;
         pe->nc = 0;
-        R cosd = (R)(L2 / Stot), sind = (R)(dz / Stot);
-        R idc = (R)1 / cosd;
+        const G iS = grcp(Stot);
+        R cosd = (R)(L2 * iS), sind = (R)(dz * iS);
+        R idc = RT<R>::rcp(cosd);
         R sI = (R)dT * idc, sD = (R)dR * idc;
         R c1R = (R)c1, s1R = (R)s1, c2R = (R)c2, s2R = (R)s2;
         R sg = (R)(double)sgn;
@@ -320,10 +327,10 @@ __device__ __forceinline__ bool cyl_creep(const BodyPrepT<G>& b, const RxGeoT<G>
         R b2x = -sind * s2R, b2y = sind * c2R, b2z = b1z;
         R rho_g = (R)a * idc * idc;
         R mhat = RT<R>::cbrt_((R)0.5 * rho_g);
-        R Ld = sI * sD / (sI + sD);
-        R Smod = RT<R>::sqrt_(sI / (sD * (R)Stot));
+        R Ld = sI * sD * RT<R>::rcp(sI + sD);
+        R Smod = RT<R>::sqrt_(sI * RT<R>::rcp(sD * (R)Stot));
         R px = (R)L.p[0], py = (R)L.p[1], pz = (R)L.p[2];
-        R A = (R)L.amp * Smod / sI * ((R)-1.4142135623730951 * mhat);
+        R A = (R)L.amp * Smod * RT<R>::rcp(sI) * ((R)-1.4142135623730951 * mhat);
         set_fock_consts<R, G>(pe, mhat, (R)phi * cosd, Ld);
         R as = A * (px * b1x + py * b1y + pz * b1z);
         R ah = A * (px * c1R + py * s1R);
@@ -348,7 +355,7 @@ __device__ __forceinline__ G alhazen_fun(G a, G p1x, G p1y, G p2x, G p2y, G th, 
     gsincos(th, &s, &c);
     G qx = a * c, qy = a * s;
     G d1x = qx - p1x, d1y = qy - p1y, d2x = qx - p2x, d2y = qy - p2y;
-    G i1 = G(1.0) / gsqrt(d1x * d1x + d1y * d1y), i2 = G(1.0) / gsqrt(d2x * d2x + d2y * d2y);   // 1/|Q - P|
+    G i1 = grsqrt(d1x * d1x + d1y * d1y), i2 = grsqrt(d2x * d2x + d2y * d2y);   // 1/|Q - P|
     G t1 = (-d1x * s + d1y * c) * i1, t2 = (-d2x * s + d2y * c) * i2;   // unit (Q-P).t
     G n1 = d1x * c + d1y * s, n2 = d2x * c + d2y * s;                  // (Q-P).n
     *dg = ((a - n1) - a * t1 * t1) * i1 + ((a - n2) - a * t2 * t2) * i2;
@@ -391,7 +398,7 @@ __device__ __forceinline__ double alhazen(double a, double p1x, double p1y, doub
         const float g = alhazen_fun_f32(fa, f1x, f1y, f2x, f2y, fth, &fdg);
         if (g == 0.0f) break;
         if ((g < 0.0f) == (fg_lo < 0.0f)) { flo = fth; fg_lo = g; } else { fhi = fth; }
-        float nt = fth - g / fdg;
+        float nt = fth - g * __builtin_amdgcn_rcpf(fdg);
         const float tol = 2e-6f * (1.0f + fabsf(fth));
         if (fabsf(nt - fth) <= tol) { fth = nt; break; }
         if (!(nt > fminf(flo, fhi) && nt < fmaxf(flo, fhi))) nt = 0.5f * (flo + fhi);
@@ -408,7 +415,7 @@ __device__ __forceinline__ double alhazen(double a, double p1x, double p1y, doub
         const double g = alhazen_fun<double>(a, p1x, p1y, p2x, p2y, th, &dg);
         if (g == 0.0) break;
         if ((g < 0) == lo_neg) lo = th; else hi = th;
-        double nt = th - g / dg;
+        double nt = th - g * grcp(dg);
         if (fabs(nt - th) <= 1e-11 * (1.0 + fabs(th))) { th = nt; break; }
         if (!(nt > fmin(lo, hi) && nt < fmax(lo, hi))) nt = 0.5 * (lo + hi);
         th = nt;
@@ -550,7 +557,7 @@ __device__ __forceinline__ void refl_eval(const BodyPrepT<G>& b, V3<G> Q, V3<G> 
     G sI = gnorm(vi), sR = gnorm(vr);
     pe->s_tot = sI + sR;
     pe->nc = 0;
-    R isI = (R)(G(1.0) / sI), isR = (R)(G(1.0) / sR);
+    R isI = (R)grcp(sI), isR = (R)grcp(sR);
     R six = (R)vi.x * isI, siy = (R)vi.y * isI, siz = (R)vi.z * isI;
     R srx = (R)vr.x * isR, sry = (R)vr.y * isR, srz = (R)vr.z * isR;
     R nx = (R)n.x, ny = (R)n.y, nz = (R)n.z;
@@ -560,7 +567,7 @@ __device__ __forceinline__ void refl_eval(const BodyPrepT<G>& b, V3<G> Q, V3<G> 
     R rho_g, f1, f2;
     if (b.kind == 0) {
         rho_g = a;
-        f1 = (R)2 / a;
+        f1 = (R)2 * RT<R>::rcp(a);
         f2 = f1;
     } else {
         // circumferential unit (-n_y, n_x, 0); trace of the incidence plane
@@ -568,21 +575,21 @@ __device__ __forceinline__ void refl_eval(const BodyPrepT<G>& b, V3<G> Q, V3<G> 
         R tgx = six - sn * nx, tgy = siy - sn * ny, tgz = siz - sn * nz;
         R tn2 = tgx * tgx + tgy * tgy + tgz * tgz;
         R tc = -tgx * ny + tgy * nx;
-        R cos2d = tn2 > (R)0 ? tc * tc / tn2 : (R)1;
+        R cos2d = tn2 > (R)0 ? tc * tc * RT<R>::rcp(tn2) : (R)1;
         cos2d = cos2d < (R)1e-12 ? (R)1e-12 : cos2d;
-        rho_g = a / cos2d;
-        f1 = (R)2 * ((R)1 - siz * siz) / a;
+        rho_g = a * RT<R>::rcp(cos2d);
+        f1 = (R)2 * ((R)1 - siz * siz) * RT<R>::rcp(a);
         f2 = (R)0;
     }
     R sIR = (R)sI, sRR = (R)sR;
-    R r1c = (R)1 / (ci / sIR + f1);
+    R r1c = RT<R>::rcp(ci * isI + f1);
     R rho1 = r1c * ci;
-    R rho2 = (R)1 / ((R)1 / sIR + f2 * ci);
+    R rho2 = RT<R>::rcp(isI + f2 * ci);
     // e_perp = s_i x n / |.|, e_par^i = e_perp x s_i, e_par^r = e_perp x s_r
     R cx = siy * nz - siz * ny, cy = siz * nx - six * nz, cz = six * ny - siy * nx;
     R cn = RT<R>::sqrt_(cx * cx + cy * cy + cz * cz);
     if (cn > (R)1e-6) {
-        R ic = (R)1 / cn;
+        R ic = RT<R>::rcp(cn);
         cx *= ic; cy *= ic; cz *= ic;
     } else {
         d3 ap = any_perp(val3(n));
@@ -591,8 +598,9 @@ __device__ __forceinline__ void refl_eval(const BodyPrepT<G>& b, V3<G> Q, V3<G> 
     R pix = cy * siz - cz * siy, piy = cz * six - cx * siz, piz = cx * siy - cy * six;
     R prx = cy * srz - cz * sry, pry = cz * srx - cx * srz, prz = cx * sry - cy * srx;
     R mhat = RT<R>::cbrt_((R)0.5 * rho_g);
-    R Lr = sIR * sRR / (sIR + sRR);
-    R P0 = (R)2 * RT<R>::sqrt_(r1c / ((R)2 * mhat)) * RT<R>::sqrt_(rho2 / ((rho1 + sRR) * (rho2 + sRR)));
+    R Lr = sIR * sRR * RT<R>::rcp(sIR + sRR);
+    R P0 = (R)2 * RT<R>::sqrt_(r1c * RT<R>::rcp((R)2 * mhat)) *
+           RT<R>::sqrt_(rho2 * RT<R>::rcp((rho1 + sRR) * (rho2 + sRR)));
     R px = (R)L.p[0], py = (R)L.p[1], pz = (R)L.p[2];
     R A = (R)L.amp * isI * P0;
     set_fock_consts<R, G>(pe, mhat, (R)-2 * ci, Lr);

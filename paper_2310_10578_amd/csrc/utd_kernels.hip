@@ -437,103 +437,99 @@ __global__ void __launch_bounds__(256) k_rec(LaunchParams L, const float* __rest
     }
 }
 
-// Single-pass visibility for scenes without triangles (bodies only): the
-// per-pair work is short and uniform there, so one lane per (receiver, body)
-// pair decides and records everything without a queue.  grid: x over
-// receivers (blockDim 256), y over slot = 0 (receiver flags) or 1 + body;
-// same outputs as k_cand + k_vis.
 // Scenes of bodies only (no triangles): one pass, no queue.
-// grid (ceil(n_rx / 64), max(bodies, 1)), 64 (K + 1) threads, K =
-// 2 (l_enc + 1) + 1 path kinds; a workgroup covers 64 receivers of one body.
-// Wave k < K takes path kind k (creeping (ell, side) = (k >> 1, k & 1), the
-// reflection for k = K - 1), so every wavefront runs one kind of path; the
-// mask bits of a receiver meet in LDS.  Wave K of the body-0 workgroups sets
-// the receivers' inside / source-inside flags and tests the direct ray.
-// Every wavefront computes the body constants itself (the chains are
-// latency-bound; waiting for one lane to share them costs more).
+// grid (ceil(n_rx / 64), max(bodies, 1)), 64 K threads, K = 2 (l_enc + 1) + 1
+// path kinds; a workgroup covers 64 receivers of one body.  Wave k takes
+// path kind k (creeping (ell, side) = (k >> 1, k & 1), the reflection for
+// k = K - 1), so every wavefront runs one kind of path.  Each wave leaves its
+// mask bits in its own LDS row; after the one barrier wave 0 merges the rows.
+// Wave 0 of the body-0 workgroups (the side-+ creeping wave, which ends
+// earliest: its path does not exist for lit receivers) then sets the
+// receivers' inside / source-inside flags and tests the direct ray; wave 1 of
+// workgroup (0, 0) converts the frequencies.  Every wavefront computes the
+// body constants itself (the chains are latency-bound; waiting for one lane
+// to share them costs more), after issuing its receiver load.
 template <typename R>
 __global__ void __launch_bounds__(512) k_paths(LaunchParams L, const float* __restrict__ rx,
                                                const float* __restrict__ sph, const float* __restrict__ cyl,
                                                const double* __restrict__ freqs, BodyPrep* __restrict__ prep,
                                                FreqConst* __restrict__ fcs, uint8_t* __restrict__ mask,
                                                PathRec<R>* __restrict__ rec, uint8_t* __restrict__ flags) {
-    __shared__ unsigned s_m[64];
+    __shared__ unsigned s_m[8][64];
     const d3 T = mk(L.T[0], L.T[1], L.T[2]);
     const int nb = L.n_sph + L.n_cyl;
     const int b = blockIdx.y;
     const int lane = threadIdx.x & 63, kind = threadIdx.x >> 6;
     const int K = rec_slots(L);
     const int64_t i = (int64_t)blockIdx.x * 64 + lane;
-    // every wavefront reaches both barriers below (none returns early, except
-    // all of them together when there are no bodies)
-    const bool flags_wave = kind == K;
-    if (flags_wave && b == 0) {
-        if (blockIdx.x == 0 && freqs)
-            for (int f = lane; f < L.n_f; f += 64) fcs[f] = freq_const(freqs[f]);
-        if (i < L.n_rx) {
-            const d3 R3 = mk(rx[3 * i], rx[3 * i + 1], rx[3 * i + 2]);
-            uint8_t f = 0;
-            bool inside = false, tx_inside = false;
-            for (int k = 0; k < nb; ++k) {
-                inside |= inside_raw(L, sph, cyl, k, R3);
-                tx_inside |= inside_raw(L, sph, cyl, k, T);
-            }
-            if (tx_inside) f |= kFlagTxInside;
-            if (inside) f |= kFlagInside;
-            if (!inside && !tx_inside && !seg_blocked(T, R3, L, sph, cyl, -1, true, nullptr, nullptr, nullptr, 0))
-                f |= kFlagLos;
-            flags[i] = f;
-        }
-    }
-    if (b >= nb) return;
-    if (threadIdx.x < 64) s_m[lane] = 0u;
-    __syncthreads();
-    const BodyPrep P = body_prep(L.T, sph, L.n_sph, cyl, b);
-    if (blockIdx.x == 0 && threadIdx.x == 0) prep[b] = P;
-    const int NS = K;
-    const bool bo = L.bodies_occlude != 0;
+    const bool have = i < L.n_rx;
+    const d3 R3 = have ? mk(rx[3 * i], rx[3 * i + 1], rx[3 * i + 2]) : T;
     unsigned m = 0u;
-    if (!flags_wave && i < L.n_rx) {
-        const d3 R3 = mk(rx[3 * i], rx[3 * i + 1], rx[3 * i + 2]);
-        RxGeo g = rx_geo(P, R3);
-        if (kind < NS - 1) {
-            const int ell = kind >> 1, sgn = (kind & 1) ? -1 : 1;
-            PathPts pts;
-            bool ok, caus = false;
-            if (P.kind == 0)
-                ok = sphere_creep<R, double>(P, g, R3, T, L, sgn, ell, &caus, (PathEval<R>*)nullptr, &pts);
-            else
-                ok = cyl_creep<R, double>(P, g, R3, T, L, sgn, ell, (PathEval<R>*)nullptr, &pts);
-            if (caus) m |= 1u << kBitCaustic;
-            if (ok && !seg_blocked(pts.P0, pts.P1, L, sph, cyl, b, bo, nullptr, nullptr, nullptr, 0) &&
-                !seg_blocked(pts.P2, pts.P3, L, sph, cyl, b, bo, nullptr, nullptr, nullptr, 0)) {
-                m |= 1u << kind;
-                PathEval<R> pe;
-                bool cz;
+    if (b < nb) {
+        const BodyPrep P = body_prep(L.T, sph, L.n_sph, cyl, b);
+        if (blockIdx.x == 0 && threadIdx.x == 0) prep[b] = P;
+        const bool bo = L.bodies_occlude != 0;
+        if (have) {
+            RxGeo g = rx_geo(P, R3);
+            if (kind < K - 1) {
+                const int ell = kind >> 1, sgn = (kind & 1) ? -1 : 1;
+                PathPts pts;
+                bool ok, caus = false;
                 if (P.kind == 0)
-                    sphere_creep<R, double>(P, g, R3, T, L, sgn, ell, &cz, &pe, nullptr);
+                    ok = sphere_creep<R, double>(P, g, R3, T, L, sgn, ell, &caus, (PathEval<R>*)nullptr, &pts);
                 else
-                    cyl_creep<R, double>(P, g, R3, T, L, sgn, ell, &pe, nullptr);
-                pack(pe, &rec[((int64_t)b * NS + rec_slot(L, kind)) * L.n_rx + i]);
-            }
-        } else if (kind == NS - 1) {
-            double th = 0.0;
-            if (L.lit_branch && refl_angle(P, g, R3, T, &th)) {
-                d3 Q, n;
-                refl_point<double>(P, g, R3, T, th, &Q, &n);
-                if (!seg_blocked(T, Q, L, sph, cyl, b, bo, nullptr, nullptr, nullptr, 0) &&
-                    !seg_blocked(Q, R3, L, sph, cyl, b, bo, nullptr, nullptr, nullptr, 0)) {
-                    m |= 1u << kBitRefl;
+                    ok = cyl_creep<R, double>(P, g, R3, T, L, sgn, ell, (PathEval<R>*)nullptr, &pts);
+                if (caus) m |= 1u << kBitCaustic;
+                if (ok && !seg_blocked(pts.P0, pts.P1, L, sph, cyl, b, bo, nullptr, nullptr, nullptr, 0) &&
+                    !seg_blocked(pts.P2, pts.P3, L, sph, cyl, b, bo, nullptr, nullptr, nullptr, 0)) {
+                    m |= 1u << kind;
                     PathEval<R> pe;
-                    refl_eval<R, double>(P, Q, n, R3, T, L, &pe);
-                    pack(pe, &rec[((int64_t)b * NS + rec_slot(L, kBitRefl)) * L.n_rx + i]);
+                    bool cz;
+                    if (P.kind == 0)
+                        sphere_creep<R, double>(P, g, R3, T, L, sgn, ell, &cz, &pe, nullptr);
+                    else
+                        cyl_creep<R, double>(P, g, R3, T, L, sgn, ell, &pe, nullptr);
+                    pack(pe, &rec[((int64_t)b * K + rec_slot(L, kind)) * L.n_rx + i]);
+                }
+            } else {
+                double th = 0.0;
+                if (L.lit_branch && refl_angle(P, g, R3, T, &th)) {
+                    d3 Q, n;
+                    refl_point<double>(P, g, R3, T, th, &Q, &n);
+                    if (!seg_blocked(T, Q, L, sph, cyl, b, bo, nullptr, nullptr, nullptr, 0) &&
+                        !seg_blocked(Q, R3, L, sph, cyl, b, bo, nullptr, nullptr, nullptr, 0)) {
+                        m |= 1u << kBitRefl;
+                        PathEval<R> pe;
+                        refl_eval<R, double>(P, Q, n, R3, T, L, &pe);
+                        pack(pe, &rec[((int64_t)b * K + rec_slot(L, kBitRefl)) * L.n_rx + i]);
+                    }
                 }
             }
         }
     }
-    if (m) atomicOr(&s_m[lane], m);
+    if (b == 0 && kind == (K > 1 ? 1 : 0) && blockIdx.x == 0 && freqs)
+        for (int f = lane; f < L.n_f; f += 64) fcs[f] = freq_const(freqs[f]);
+    if (b == 0 && kind == 0 && have) {
+        uint8_t f = 0;
+        bool inside = false, tx_inside = false;
+        for (int k = 0; k < nb; ++k) {
+            inside |= inside_raw(L, sph, cyl, k, R3);
+            tx_inside |= inside_raw(L, sph, cyl, k, T);
+        }
+        if (tx_inside) f |= kFlagTxInside;
+        if (inside) f |= kFlagInside;
+        if (!inside && !tx_inside && !seg_blocked(T, R3, L, sph, cyl, -1, true, nullptr, nullptr, nullptr, 0))
+            f |= kFlagLos;
+        flags[i] = f;
+    }
+    if (b >= nb) return;   // the whole workgroup: no barrier below is skipped by part of it
+    s_m[kind][lane] = m;
     __syncthreads();
-    if (threadIdx.x < 64 && i < L.n_rx) mask[(int64_t)b * L.n_rx + i] = (uint8_t)s_m[lane];
+    if (kind == 0 && have) {
+        unsigned mm = 0u;
+        for (int k = 0; k < K; ++k) mm |= s_m[k][lane];
+        mask[(int64_t)b * L.n_rx + i] = (uint8_t)mm;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -762,10 +758,10 @@ static hipError_t launch_paths_t(const LaunchParams& L, const float* rx, const f
                                  hipStream_t s) {
     int nb = L.n_sph + L.n_cyl;
     if (!nodes) {
-        // one wavefront per path kind and 64 receivers, plus the flags wavefront
+        // one wavefront per path kind and 64 receivers
         const int K = 2 * (L.l_enc + 1) + 1;
         dim3 grid((unsigned)((L.n_rx + 63) / 64), (unsigned)(nb > 0 ? nb : 1));
-        hipLaunchKernelGGL((k_paths<R>), grid, dim3(64 * (K + 1)), 0, s, L, rx, sph, cyl, freqs, prep, fcs, mask,
+        hipLaunchKernelGGL((k_paths<R>), grid, dim3(64 * K), 0, s, L, rx, sph, cyl, freqs, prep, fcs, mask,
                            (PathRec<R>*)rec, flags);
         return hipGetLastError();
     }
