@@ -269,7 +269,7 @@ __global__ void __launch_bounds__(256) k_adj_paths(LaunchParams L, const float* 
     using RD = Dual<R>;
     __shared__ __attribute__((aligned(16))) R s_reg[TableStage<R>::NREG];
     __shared__ __attribute__((aligned(16))) R s_tf[TableStage<R>::NTF];
-    Tabs<R> tb = TableStage<R>::stage(s_reg, s_tf);
+    Tabs<R> tb = TableStage<R>::template stage<256>(s_reg, s_tf);
     const int64_t total = *ntot;
     const d3 T0 = mk(L.T[0], L.T[1], L.T[2]);
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;

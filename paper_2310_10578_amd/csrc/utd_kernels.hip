@@ -586,7 +586,11 @@ __device__ __forceinline__ void add_path(const PathEval<R>& pe, const Tabs<R>& t
 
 // The FP32 tables are copied into LDS once per workgroup: the generated
 // arrays already have the LDS layout, so the copy is a straight 16-byte
-// vector copy.  The FP64 tables stay in global memory (L2 resident).
+// vector copy.  NT is the workgroup size the caller is launched with; the
+// copy is unrolled to a fixed count per thread so that every lane issues all
+// of its loads before the first LDS write (a plain strided loop waits for
+// each load in turn, one L2 round trip per iteration).  The FP64 tables stay
+// in global memory (L2 resident).
 template <typename R> struct TableStage;
 
 template <> struct TableStage<float> {
@@ -596,13 +600,27 @@ template <> struct TableStage<float> {
     static_assert(NREG % 4 == 0 && NTF % 4 == 0, "float4 copy");
     static_assert(sizeof(ft_f32_reg) == NREG * sizeof(float) && sizeof(ft_f32_tf) == NTF * sizeof(float),
                   "table layout");
+    template <int NT>
     static __device__ __forceinline__ Tabs<float> stage(float* reg, float* tf) {
+        constexpr int NA = NREG / 4, NB = NTF / 4;
+        constexpr int RA = (NA + NT - 1) / NT, RB = (NB + NT - 1) / NT;
         const float4* a = reinterpret_cast<const float4*>(&ft_f32_reg[0][0][0]);
         const float4* b = reinterpret_cast<const float4*>(&ft_f32_tf[0][0][0]);
         float4* ra = reinterpret_cast<float4*>(reg);
         float4* rb = reinterpret_cast<float4*>(tf);
-        for (int i = threadIdx.x; i < NREG / 4; i += blockDim.x) ra[i] = a[i];
-        for (int i = threadIdx.x; i < NTF / 4; i += blockDim.x) rb[i] = b[i];
+        const int t = threadIdx.x;
+        // no branches (a branch lets the compiler sink each load to its store):
+        // indices past the end are clamped to the last entry, so those lanes
+        // load and store that entry's own value again
+        float4 va[RA], vb[RB];
+#pragma unroll
+        for (int r = 0; r < RA; ++r) va[r] = a[t + r * NT < NA ? t + r * NT : NA - 1];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) vb[r] = b[t + r * NT < NB ? t + r * NT : NB - 1];
+#pragma unroll
+        for (int r = 0; r < RA; ++r) ra[t + r * NT < NA ? t + r * NT : NA - 1] = va[r];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) rb[t + r * NT < NB ? t + r * NT : NB - 1] = vb[r];
         __syncthreads();
         return Tabs<float>{reg, tf};
     }
@@ -610,6 +628,7 @@ template <> struct TableStage<float> {
 
 template <> struct TableStage<double> {
     static constexpr int NREG = 1, NTF = 1;
+    template <int NT>
     static __device__ __forceinline__ Tabs<double> stage(double*, double*) {
         return Tabs<double>{&ft_f64_reg[0][0][0], &ft_f64_tf[0][0][0]};
     }
@@ -622,7 +641,7 @@ __global__ void __launch_bounds__(256) k_field(LaunchParams L, const float* __re
                                                R* __restrict__ E_out) {
     __shared__ __attribute__((aligned(16))) R s_reg[TableStage<R>::NREG];
     __shared__ __attribute__((aligned(16))) R s_tf[TableStage<R>::NTF];
-    Tabs<R> tb = TableStage<R>::stage(s_reg, s_tf);
+    Tabs<R> tb = TableStage<R>::template stage<256>(s_reg, s_tf);
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= L.n_rx) return;
     const int f0 = blockIdx.y * FC;
