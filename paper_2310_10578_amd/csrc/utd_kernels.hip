@@ -634,17 +634,12 @@ template <> struct TableStage<double> {
     }
 };
 
+// Receiver i at frequencies f0 .. f0 + FC - 1 (those below n_f).
 template <typename R, int FC>
-__global__ void __launch_bounds__(256) k_field(LaunchParams L, const float* __restrict__ rx,
-                                               const FreqConst* __restrict__ fcs, const uint8_t* __restrict__ mask,
-                                               const PathRec<R>* __restrict__ rec, uint8_t* __restrict__ flags,
-                                               R* __restrict__ E_out) {
-    __shared__ __attribute__((aligned(16))) R s_reg[TableStage<R>::NREG];
-    __shared__ __attribute__((aligned(16))) R s_tf[TableStage<R>::NTF];
-    Tabs<R> tb = TableStage<R>::template stage<256>(s_reg, s_tf);
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= L.n_rx) return;
-    const int f0 = blockIdx.y * FC;
+__device__ __forceinline__ void field_rx(const LaunchParams& L, const float* __restrict__ rx,
+                                         const FreqConst* __restrict__ fcs, const uint8_t* __restrict__ mask,
+                                         const PathRec<R>* __restrict__ rec, uint8_t* __restrict__ flags,
+                                         R* __restrict__ E_out, const Tabs<R>& tb, int64_t i, int f0) {
     const int nfc = L.n_f - f0 < FC ? L.n_f - f0 : FC;
     const int NS = rec_slots(L);
     R E[FC][6];
@@ -689,7 +684,7 @@ __global__ void __launch_bounds__(256) k_field(LaunchParams L, const float* __re
                 }
             }
         }
-        if (blockIdx.y == 0 && (caus & (1u << kBitCaustic))) flags[i] = fl | kFlagCaustic;
+        if (f0 == 0 && (caus & (1u << kBitCaustic))) flags[i] = fl | kFlagCaustic;
 #pragma unroll
         for (int j = 0; j < FC; ++j) {
             if (j < nfc) {
@@ -732,6 +727,29 @@ __global__ void __launch_bounds__(256) k_field(LaunchParams L, const float* __re
             }
         }
     }
+}
+
+// grid (ceil(n_rx / 256), y_big + n_f - FC y_big): rows y < y_big take FC
+// frequencies per lane; the rows after them one frequency each, so the last
+// workgroups of the launch are short and the chip drains evenly.
+template <typename R, int FC>
+__global__ void __launch_bounds__(256) k_field(LaunchParams L, const float* __restrict__ rx,
+                                               const FreqConst* __restrict__ fcs, const uint8_t* __restrict__ mask,
+                                               const PathRec<R>* __restrict__ rec, uint8_t* __restrict__ flags,
+                                               R* __restrict__ E_out, int y_big) {
+    __shared__ __attribute__((aligned(16))) R s_reg[TableStage<R>::NREG];
+    __shared__ __attribute__((aligned(16))) R s_tf[TableStage<R>::NTF];
+    Tabs<R> tb = TableStage<R>::template stage<256>(s_reg, s_tf);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= L.n_rx) return;
+    const int y = (int)blockIdx.y;
+    if constexpr (FC > 1) {
+        if (y >= y_big) {
+            field_rx<R, 1>(L, rx, fcs, mask, rec, flags, E_out, tb, i, y_big * FC + (y - y_big));
+            return;
+        }
+    }
+    field_rx<R, FC>(L, rx, fcs, mask, rec, flags, E_out, tb, i, y * FC);
 }
 
 // ---------------------------------------------------------------------------
@@ -820,8 +838,13 @@ size_t path_record_bytes(int precision) { return precision == 0 ? sizeof(PathRec
 template <typename R, int FC>
 static hipError_t launch_field_fc(const LaunchParams& L, const float* rx, const FreqConst* fcs, const uint8_t* mask,
                                   const void* rec, uint8_t* flags, R* E, hipStream_t s) {
-    dim3 grid((unsigned)((L.n_rx + 255) / 256), (unsigned)((L.n_f + FC - 1) / FC));
-    hipLaunchKernelGGL((k_field<R, FC>), grid, dim3(256), 0, s, L, rx, fcs, mask, (const PathRec<R>*)rec, flags, E);
+    // the last frequency chunk as one-frequency rows once there are enough full rows
+    const int nch = (L.n_f + FC - 1) / FC;
+    const int y_big = (FC > 1 && nch >= 4) ? nch - 1 : nch;
+    const int rows = y_big < nch ? y_big + (L.n_f - FC * y_big) : nch;
+    dim3 grid((unsigned)((L.n_rx + 255) / 256), (unsigned)rows);
+    hipLaunchKernelGGL((k_field<R, FC>), grid, dim3(256), 0, s, L, rx, fcs, mask, (const PathRec<R>*)rec, flags, E,
+                       y_big);
     return hipGetLastError();
 }
 
