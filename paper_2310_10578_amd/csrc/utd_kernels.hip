@@ -729,9 +729,10 @@ __device__ __forceinline__ void field_rx(const LaunchParams& L, const float* __r
     }
 }
 
-// grid (ceil(n_rx / 256), y_big + n_f - FC y_big): rows y < y_big take FC
-// frequencies per lane; the rows after them one frequency each, so the last
-// workgroups of the launch are short and the chip drains evenly.
+// grid (ceil(n_rx / 256), y_big + ceil((n_f - FC y_big) / FS)): rows
+// y < y_big take FC frequencies per lane, the rows after them FS = FC / 2
+// (at least 1), so the last workgroups of the launch are short and the chip
+// drains evenly.
 template <typename R, int FC>
 __global__ void __launch_bounds__(256) k_field(LaunchParams L, const float* __restrict__ rx,
                                                const FreqConst* __restrict__ fcs, const uint8_t* __restrict__ mask,
@@ -744,8 +745,9 @@ __global__ void __launch_bounds__(256) k_field(LaunchParams L, const float* __re
     if (i >= L.n_rx) return;
     const int y = (int)blockIdx.y;
     if constexpr (FC > 1) {
+        constexpr int FS = FC > 2 ? FC / 2 : 1;
         if (y >= y_big) {
-            field_rx<R, 1>(L, rx, fcs, mask, rec, flags, E_out, tb, i, y_big * FC + (y - y_big));
+            field_rx<R, FS>(L, rx, fcs, mask, rec, flags, E_out, tb, i, y_big * FC + FS * (y - y_big));
             return;
         }
     }
@@ -838,10 +840,11 @@ size_t path_record_bytes(int precision) { return precision == 0 ? sizeof(PathRec
 template <typename R, int FC>
 static hipError_t launch_field_fc(const LaunchParams& L, const float* rx, const FreqConst* fcs, const uint8_t* mask,
                                   const void* rec, uint8_t* flags, R* E, hipStream_t s) {
-    // the last frequency chunk as one-frequency rows once there are enough full rows
+    // the last frequency chunk as rows of FS frequencies once there are enough full rows
+    constexpr int FS = FC > 2 ? FC / 2 : 1;
     const int nch = (L.n_f + FC - 1) / FC;
     const int y_big = (FC > 1 && nch >= 4) ? nch - 1 : nch;
-    const int rows = y_big < nch ? y_big + (L.n_f - FC * y_big) : nch;
+    const int rows = y_big < nch ? y_big + (L.n_f - FC * y_big + FS - 1) / FS : nch;
     dim3 grid((unsigned)((L.n_rx + 255) / 256), (unsigned)rows);
     hipLaunchKernelGGL((k_field<R, FC>), grid, dim3(256), 0, s, L, rx, fcs, mask, (const PathRec<R>*)rec, flags, E,
                        y_big);
