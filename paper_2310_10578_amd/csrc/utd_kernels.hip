@@ -722,8 +722,10 @@ __device__ __forceinline__ void field_rx(const LaunchParams& L, const float* __r
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 int64_t o = ((int64_t)(f0 + j) * 3 + c) * L.n_rx + i;
-                E_out[2 * o] = E[j][2 * c];
-                E_out[2 * o + 1] = E[j][2 * c + 1];
+                // streaming stores: the field is not read again here, and lines
+                // left dirty in L2 would be written back at the kernel boundary
+                __builtin_nontemporal_store(E[j][2 * c], &E_out[2 * o]);
+                __builtin_nontemporal_store(E[j][2 * c + 1], &E_out[2 * o + 1]);
             }
         }
     }
