@@ -447,10 +447,12 @@ __device__ __forceinline__ bool cyl_paths_possible(const BodyPrep& b, d3 Rp, d3 
         const double za = T.z + dz * fa, zb = T.z + dz * fb;
         return fmax(za, zb) >= zlo && fmin(za, zb) <= zhi;
     };
+    // reciprocals within a few ulp: far below the slack
     const double l0 = b.sI0 + sD, l1 = l0 + kTwoPi * (L.l_enc + 1) * a;
-    if (meets(b.sI0 / l1, b.sI0 / l0) && meets(1.0 - sD / l0, 1.0 - sD / l1)) return true;
+    const double il0 = grcp(l0), il1 = grcp(l1);
+    if (meets(b.sI0 * il1, b.sI0 * il0) && meets(1.0 - sD * il0, 1.0 - sD * il1)) return true;
     if (L.lit_branch) {
-        const double fa = (b.dT - a) / ((b.dT - a) + sD), fb = b.sI0 / (b.sI0 + (dR - a));
+        const double fa = (b.dT - a) * grcp((b.dT - a) + sD), fb = b.sI0 * grcp(b.sI0 + (dR - a));
         if (meets(fa, fb)) return true;
     }
     return false;
@@ -486,7 +488,7 @@ __device__ __forceinline__ bool refl_angle(const BodyPrep& b, const RxGeo& g, d3
     // z_Q = z_T + (z_R - z_T) l_T / (l_T + l_R) lies between the values at
     // the extreme ratios; no solve when that range misses the lateral surface.
     {
-        const double fa = (b.dT - a) / ((b.dT - a) + g.sD0), fb = b.sI0 / (b.sI0 + (g.dR - a));
+        const double fa = (b.dT - a) * grcp((b.dT - a) + g.sD0), fb = b.sI0 * grcp(b.sI0 + (g.dR - a));
         const double dz = Rp.z - T.z;
         const double za = T.z + dz * fa, zb = T.z + dz * fb;
         const double slack = 1e-9 * (1.0 + fabs(T.z) + fabs(Rp.z));
@@ -500,7 +502,7 @@ __device__ __forceinline__ bool refl_angle(const BodyPrep& b, const RxGeo& g, d3
     double qx = a * c, qy = a * s;
     double lt = sqrt((qx - tx) * (qx - tx) + (qy - ty) * (qy - ty));
     double lr = sqrt((qx - rx) * (qx - rx) + (qy - ry) * (qy - ry));
-    double zQ = T.z + (Rp.z - T.z) * lt / (lt + lr);
+    double zQ = T.z + (Rp.z - T.z) * lt * grcp(lt + lr);
     if (zQ < b.z0 || zQ > b.z0 + b.h) return false;
     *th_out = al;
     return true;
@@ -538,7 +540,7 @@ __device__ __forceinline__ void refl_point(const BodyPrepT<G>& b, const RxGeoT<G
         G qx = a * c, qy = a * s;
         G lt = gsqrt((qx - tx) * (qx - tx) + (qy - ty) * (qy - ty));
         G lr = gsqrt((qx - rx) * (qx - rx) + (qy - ry) * (qy - ry));
-        G zQ = T.z + (Rp.z - T.z) * lt / (lt + lr);
+        G zQ = T.z + (Rp.z - T.z) * lt * grcp(lt + lr);
         q = V3<G>{b.c[0] + qx, b.c[1] + qy, zQ};
         nn = V3<G>{c, s, G(0.0)};
     }

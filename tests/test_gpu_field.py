@@ -212,22 +212,22 @@ def test_bodies_only_scene_all_path_kinds(l_enc):
         assert np.all(err <= TOL[precision])
 
 
-@pytest.mark.parametrize("n_side,n_f", [(255, 63), (255, 17)])
-def test_ragged_receivers_and_frequency_chunks(n_side, n_f):
+@pytest.mark.parametrize("n_side,n_f,precision", [(255, 63, 0), (255, 17, 0), (255, 17, 1)])
+def test_ragged_receivers_and_frequency_chunks(n_side, n_f, precision):
     """Receiver counts that fill no whole workgroup and frequency counts that
     leave a partial chunk, at sizes that select several frequencies per lane
-    (65025 x 63: four per lane, last chunk of 3; 65025 x 17: two per lane,
-    last chunk of 1); sampled receivers against the oracle, including the
-    last ones."""
+    (FP32 65025 x 63: four per lane, the last chunk of 3 in rows of two;
+    FP32 and FP64 65025 x 17: two per lane, the last chunk of 1 in rows of
+    one); sampled receivers against the oracle, including the last ones."""
     cfg = W.config2(n_side=n_side, n_f=n_f)
-    Eg, fg = run_library(cfg, 0)
+    Eg, fg = run_library(cfg, precision)
     n = cfg["rx"].shape[0]
     rng = np.random.default_rng(9)
     idx = np.unique(np.concatenate([rng.choice(n, 300, replace=False), np.arange(n - 64, n)]))
     Eo, info = run_oracle(cfg, rx=cfg["rx"][idx])
     err = normwise(Eg[:, :, idx], Eo)
-    _report("ragged %d rx x %d f" % (n, n_f), err)
-    assert np.all(err <= TOL[0])
+    _report("ragged %d rx x %d f p%d" % (n, n_f, precision), err)
+    assert np.all(err <= TOL[precision])
     np.testing.assert_array_equal(fg[idx] & 5, info["flags"] & 5)
 
 
