@@ -95,7 +95,7 @@ __device__ __forceinline__ bool seg_blocked(d3 P0, d3 P1, const LaunchParams& L,
 // reflection in the last slot.  Only the slots of set mask bits are written
 // or read.
 template <typename R> struct PathRec;
-template <> struct PathRec<float> {          // 64 bytes
+template <> struct PathRec<float> {          // 80 bytes (q0 and q1 aligned to 16)
     double s_tot;
     int16_t nc;                               // caustic quarter turns
     int16_t refl;
@@ -110,6 +110,7 @@ template <> struct PathRec<double> {         // 120 bytes
     int32_t nc, refl;
     double v[13];
 };
+static_assert(sizeof(PathRec<float>) == 80 && sizeof(PathRec<double>) == 120, "path record sizes");
 
 __device__ __forceinline__ void pack(const PathEval<float>& p, PathRec<float>* r) {
     PathRec<float> o;
@@ -122,6 +123,21 @@ __device__ __forceinline__ void pack(const PathEval<float>& p, PathRec<float>* r
     o.iuh = p.iuh;
     o.pad = 0.0f;
     *r = o;
+}
+// The same with streaming (non-temporal) stores, for the single-pass
+// bodies-only kernel: the field kernel that follows reads the record on
+// whichever XCD takes its receiver, and lines left dirty in this XCD's L2
+// would be written back at the kernel boundary, delaying the next launch.
+// (The queue path's k_rec writes scattered records; there ordinary stores
+// measured faster.)
+__device__ __forceinline__ void pack_stream(const PathEval<float>& p, PathRec<float>* r) {
+    PathRec<float> o;
+    pack(p, &o);
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4* src = reinterpret_cast<const u32x4*>(&o);
+    u32x4* dst = reinterpret_cast<u32x4*>(r);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(PathRec<float>) / sizeof(u32x4)); ++k) __builtin_nontemporal_store(src[k], dst + k);
 }
 __device__ __forceinline__ void unpack(const PathRec<float>& o, PathEval<float>* p) {
     p->s_tot = o.s_tot;
@@ -140,6 +156,7 @@ __device__ __forceinline__ void pack(const PathEval<double>& p, PathRec<double>*
     for (int k = 0; k < 13; ++k) o.v[k] = v[k];
     *r = o;
 }
+__device__ __forceinline__ void pack_stream(const PathEval<double>& p, PathRec<double>* r) { pack(p, r); }
 __device__ __forceinline__ void unpack(const PathRec<double>& o, PathEval<double>* p) {
     p->s_tot = o.s_tot; p->nc = o.nc; p->refl = o.refl;
     p->xh = o.v[0]; p->uh = o.v[1]; p->qhat = o.v[2]; p->ixh = o.v[3]; p->sxh = o.v[4];
@@ -489,7 +506,7 @@ __global__ void __launch_bounds__(512) k_paths(LaunchParams L, const float* __re
                         sphere_creep<R, double>(P, g, R3, T, L, sgn, ell, &cz, &pe, nullptr);
                     else
                         cyl_creep<R, double>(P, g, R3, T, L, sgn, ell, &pe, nullptr);
-                    pack(pe, &rec[((int64_t)b * K + rec_slot(L, kind)) * L.n_rx + i]);
+                    pack_stream(pe, &rec[((int64_t)b * K + rec_slot(L, kind)) * L.n_rx + i]);
                 }
             } else {
                 double th = 0.0;
@@ -501,7 +518,7 @@ __global__ void __launch_bounds__(512) k_paths(LaunchParams L, const float* __re
                         m |= 1u << kBitRefl;
                         PathEval<R> pe;
                         refl_eval<R, double>(P, Q, n, R3, T, L, &pe);
-                        pack(pe, &rec[((int64_t)b * K + rec_slot(L, kBitRefl)) * L.n_rx + i]);
+                        pack_stream(pe, &rec[((int64_t)b * K + rec_slot(L, kBitRefl)) * L.n_rx + i]);
                     }
                 }
             }
