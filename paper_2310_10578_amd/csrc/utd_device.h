@@ -88,9 +88,12 @@ __device__ __forceinline__ d3 any_perp(d3 e) {
 // ---------------------------------------------------------------------------
 template <typename R> struct RT;
 template <> struct RT<float> {
-    static __device__ __forceinline__ float sqrt_(float x) { return __builtin_sqrtf(x); }
+    // the hardware square root (about an ulp) and the cube root from the
+    // hardware base-2 logarithm and exponential (a few ulp, positive
+    // arguments only): FP32 path constants, far from the FP32 tolerance
+    static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
     static __device__ __forceinline__ float exp_(float x) { return expf(x); }
-    static __device__ __forceinline__ float cbrt_(float x) { return cbrtf(x); }
+    static __device__ __forceinline__ float cbrt_(float x) { return __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(x) * (1.0f / 3.0f)); }
     static __device__ __forceinline__ float rint_(float x) { return rintf(x); }
     static __device__ __forceinline__ float floor_(float x) { return floorf(x); }
     static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
