@@ -7,7 +7,7 @@ Default workload: PEC sphere a = 1 m, source at 4 m, 256 x 256 receivers on
 the plane x = -3 m, 64 frequencies in 1-6 GHz, FP32 field with FP64 phase.
 Inputs are resident in HBM before the timed region.
 
-Prints one JSON line (rank 0).  ``--gpus`` above 1 is refused: this build
+Prints one JSON line (rank 0).  ``--gpus`` above 1 is refused: this library
 runs on one GPU.
 """
 import argparse
@@ -267,7 +267,7 @@ def batched_bench(steps):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU (this build has no multi-GPU path); got --gpus %d" % args.gpus,
+        print("bench.py runs on exactly one GPU (this library has no multi-GPU path); got --gpus %d" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
     import torch

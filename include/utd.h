@@ -45,7 +45,7 @@ typedef enum {
     UTD_E_ARG = -1,          /* invalid argument (NULL, negative size, bad option) */
     UTD_E_DEVICE = -2,       /* a HIP runtime call failed */
     UTD_E_OOM = -3,          /* device or host allocation failed */
-    UTD_E_UNSUPPORTED = -5   /* valid but not supported by this build */
+    UTD_E_UNSUPPORTED = -5   /* valid but not supported by this library */
 } utd_status;
 
 /* Per-receiver flags written to rx_flags (bit set = condition holds). */
