@@ -256,7 +256,7 @@ __global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(3, 8)
                             cand |= 1u << bit;
                     }
                     double th;
-                    if (L.lit_branch && refl_angle<Kinds::Cylinders>(P, g, R3, T, &th)) {
+                    if (L.lit_branch && refl_angle<Kinds::Cylinders, (sizeof(R) == 8)>(P, g, R3, T, &th)) {
                         cand |= 1u << kBitRefl;
                         thb[bl * TILE + tid] = th;
                     }

@@ -386,7 +386,12 @@ __device__ __forceinline__ float alhazen_fun_f32(float a, float p1x, float p1y, 
 // from there.  The FP64 iteration stops after a Newton step below
 // 1e-11 (1 + |th|): with quadratic convergence the accepted iterate is then
 // exact to far below FP64 rounding.  Typically 4-5 FP32 and 2-3 FP64
-// evaluations.
+// evaluations.  With FULL = false (paths whose constants are FP32) one FP64
+// Newton step from the FP32 root is accepted when it is below
+// 1e-5 (1 + |th|): the root is then within about 1e-9 rad (far inside the FP32
+// constants, and the path length is stationary in th); otherwise the full
+// iteration runs.
+template <bool FULL = true>
 __device__ __forceinline__ double alhazen(double a, double p1x, double p1y, double p2x, double p2y,
                                           double lo, double hi) {
     const float fa = (float)a, f1x = (float)p1x, f1y = (float)p1y, f2x = (float)p2x, f2y = (float)p2y;
@@ -405,8 +410,16 @@ __device__ __forceinline__ double alhazen(double a, double p1x, double p1y, doub
         fth = nt;
         if (fabsf(fhi - flo) <= tol) break;
     }
-    // sign of g at lo: from the FP32 value unless that is too small to trust
     double dg;
+    if (!FULL) {
+        const double th0 = (double)fth;
+        if (th0 > fmin(lo, hi) && th0 < fmax(lo, hi)) {
+            const double g = alhazen_fun<double>(a, p1x, p1y, p2x, p2y, th0, &dg);
+            const double nt = th0 - g / dg;
+            if (fabs(nt - th0) <= 1e-5 * (1.0 + fabs(th0)) && nt > fmin(lo, hi) && nt < fmax(lo, hi)) return nt;
+        }
+    }
+    // sign of g at lo: from the FP32 value unless that is too small to trust
     bool lo_neg = glo32 < 0.0f;
     if (fabsf(glo32) < 1e-4f) lo_neg = alhazen_fun<double>(a, p1x, p1y, p2x, p2y, lo, &dg) < 0.0;
     double th = (double)fth;
@@ -461,7 +474,7 @@ __device__ __forceinline__ bool cyl_paths_possible(const BodyPrep& b, d3 Rp, d3 
 // Reflection point for a lit receiver: the angle parameter (sphere: polar
 // angle in the T-C-R plane; cylinder: azimuth), false if the receiver is not
 // lit by this body or the point is off the lateral surface.
-template <Kinds K = Kinds::Any>
+template <Kinds K = Kinds::Any, bool FULL = true>
 __device__ __forceinline__ bool refl_angle(const BodyPrep& b, const RxGeo& g, d3 Rp, d3 T, double* th_out) {
     if (!(b.ok && g.ok)) return false;
     double a = b.a;
@@ -469,7 +482,7 @@ __device__ __forceinline__ bool refl_angle(const BodyPrep& b, const RxGeo& g, d3
         if (!(g.phi_p < 0)) return false;
         // T at (dT, 0), R at (along, wn) in the plane basis; the arc seen
         // from both runs from R's tangent point (thR - gR = phi_+ + gT) to T's (gT)
-        *th_out = alhazen(a, b.dT, 0.0, g.along, g.wn, g.phi_p + b.gT, b.gT);
+        *th_out = alhazen<FULL>(a, b.dT, 0.0, g.along, g.wn, g.phi_p + b.gT, b.gT);
         return true;
     }
     double lo, hi;
@@ -496,7 +509,7 @@ __device__ __forceinline__ bool refl_angle(const BodyPrep& b, const RxGeo& g, d3
     }
     double tx = T.x - b.c[0], ty = T.y - b.c[1];
     double rx = Rp.x - b.c[0], ry = Rp.y - b.c[1];
-    double al = alhazen(a, tx, ty, rx, ry, lo, hi);
+    double al = alhazen<FULL>(a, tx, ty, rx, ry, lo, hi);
     double s, c;
     gsincos(al, &s, &c);
     double qx = a * c, qy = a * s;

@@ -287,7 +287,7 @@ __global__ void __launch_bounds__(256) k_cand(LaunchParams L, const float* __res
                     if (ok) cand |= (uint8_t)(1u << (2 * ell + side));
                 }
             }
-            if (L.lit_branch && refl_angle(P, g, R3, T, &th)) cand |= (uint8_t)(1u << kBitRefl);
+            if (L.lit_branch && refl_angle<Kinds::Any, (sizeof(R) == 8)>(P, g, R3, T, &th)) cand |= (uint8_t)(1u << kBitRefl);
             mask[(int64_t)b * L.n_rx + i] = m;     // visible bits are added by k_vis
         } else if (act) {
             mask[(int64_t)b * L.n_rx + i] = 0;
@@ -510,7 +510,7 @@ __global__ void __launch_bounds__(512) k_paths(LaunchParams L, const float* __re
                 }
             } else {
                 double th = 0.0;
-                if (L.lit_branch && refl_angle(P, g, R3, T, &th)) {
+                if (L.lit_branch && refl_angle<Kinds::Any, (sizeof(R) == 8)>(P, g, R3, T, &th)) {
                     d3 Q, n;
                     refl_point<double>(P, g, R3, T, th, &Q, &n);
                     if (!seg_blocked(T, Q, L, sph, cyl, b, bo, nullptr, nullptr, nullptr, 0) &&
