@@ -251,3 +251,32 @@ def test_random_scenes(seed):
         err = normwise(Eg[:, :, ~bad], Eo[:, :, ~bad])
         _report("random scene %d p%d (%d excluded)" % (seed, precision, bad.sum()), err)
         assert np.all(err <= TOL[precision])
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_shadow_boundary_band(precision):
+    """Receivers in a narrow band around the shadow boundary of the config-2
+    sphere (radius r_b = sqrt(49/15) on the plane x = -3, where the ray from
+    the source grazes the sphere), r = r_b (1 + d) for d in [-1e-3, 1e-3] at
+    spread azimuths, and a few far from it: grazing reflections (where the
+    reflection-point solve takes its longest paths, including the full
+    iteration after the FP32 stage) and creeping paths of nearly zero arc.
+    Both sides of the boundary against the oracle; flags equal.  FP32 at the
+    usual 1e-4.  FP64 at 5e-9: the reflection at grazing incidence is
+    ill-conditioned, and moving a receiver by 1e-15 of its coordinates
+    changes the oracle's own field by up to 1.4e-9 at d = 3.9e-6 (1.2e-10 at
+    d = 1e-4), which bounds the agreement of any two FP64 evaluations."""
+    cfg = W.config2(n_side=4, n_f=4)
+    n = 256
+    d = np.linspace(-1e-3, 1e-3, n)
+    psi = np.arange(n) * 2.399963229728653          # golden-angle azimuths
+    rb = np.sqrt(49.0 / 15.0)
+    r = rb * (1.0 + d)
+    rx = np.stack([np.full(n, -3.0), r * np.cos(psi), r * np.sin(psi)], 1)
+    rx = np.concatenate([rx, [[-3.0, 0.3, 0.2], [-3.0, 3.5, -1.0]]]).astype(np.float32)
+    Eg, fg = run_library(cfg, precision, rx=rx)
+    Eo, info = run_oracle(cfg, rx=rx)
+    np.testing.assert_array_equal(fg & 5, info["flags"] & 5)
+    err = normwise(Eg, Eo)
+    _report("shadow-boundary band p%d (%d lit)" % (precision, int(((fg & 4) != 0).sum())), err)
+    assert np.all(err <= {0: 1e-4, 1: 5e-9}[precision])
