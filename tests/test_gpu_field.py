@@ -253,30 +253,52 @@ def test_random_scenes(seed):
         assert np.all(err <= TOL[precision])
 
 
-@pytest.mark.parametrize("precision", [1, 0])
-def test_shadow_boundary_band(precision):
-    """Receivers in a narrow band around the shadow boundary of the config-2
-    sphere (radius r_b = sqrt(49/15) on the plane x = -3, where the ray from
-    the source grazes the sphere), r = r_b (1 + d) for d in [-1e-3, 1e-3] at
-    spread azimuths, and a few far from it: grazing reflections (where the
-    reflection-point solve takes its longest paths, including the full
-    iteration after the FP32 stage) and creeping paths of nearly zero arc.
-    Both sides of the boundary against the oracle; flags equal.  FP32 at the
-    usual 1e-4.  FP64 at 5e-9: the reflection at grazing incidence is
-    ill-conditioned, and moving a receiver by 1e-15 of its coordinates
-    changes the oracle's own field by up to 1.4e-9 at d = 3.9e-6 (1.2e-10 at
-    d = 1e-4), which bounds the agreement of any two FP64 evaluations."""
-    cfg = W.config2(n_side=4, n_f=4)
+def _band_case(body):
+    """256 receivers r = r_b (1 + d), d in [-1e-3, 1e-3], around the shadow
+    boundary of one body (r_b: where the ray from the source grazes it)."""
     n = 256
     d = np.linspace(-1e-3, 1e-3, n)
-    psi = np.arange(n) * 2.399963229728653          # golden-angle azimuths
-    rb = np.sqrt(49.0 / 15.0)
-    r = rb * (1.0 + d)
-    rx = np.stack([np.full(n, -3.0), r * np.cos(psi), r * np.sin(psi)], 1)
+    if body == "sphere":
+        # config-2 sphere (a = 1, source (4, 0, 0)), receivers on x = -3:
+        # r_b = sqrt(49/15), spread azimuths
+        cfg = W.config2(n_side=4, n_f=4)
+        psi = np.arange(n) * 2.399963229728653
+        r = np.sqrt(49.0 / 15.0) * (1.0 + d)
+        rx = np.stack([np.full(n, -3.0), r * np.cos(psi), r * np.sin(psi)], 1)
+    else:
+        # vertical cylinder a = 0.5 over z in [0, 3], source (4, 0, 1.5),
+        # receivers on x = -3 at heights 1.2..1.8: y_b = sqrt(12.25/15.75),
+        # both sides of the axis
+        sc = W.empty_scene()
+        sc["cylinders"] = np.array([[0.0, 0.0, 0.0, 3.0, 0.5]], np.float32)
+        cfg = dict(name="cylinder-band", scene=sc,
+                   tx=dict(pos=np.array([4.0, 0.0, 1.5], np.float32),
+                           dipole=np.array([0.3, 0.5, 0.8], np.float32), amplitude=1.0),
+                   rx=np.zeros((1, 3), np.float32), freqs=np.array([1e9, 5e9, 12e9, 28e9]))
+        sgn = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+        z = 1.2 + 0.6 * ((np.arange(n) * 0.618034) % 1.0)
+        rx = np.stack([np.full(n, -3.0), sgn * np.sqrt(12.25 / 15.75) * (1.0 + d), z], 1)
     rx = np.concatenate([rx, [[-3.0, 0.3, 0.2], [-3.0, 3.5, -1.0]]]).astype(np.float32)
+    return cfg, rx
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+@pytest.mark.parametrize("body", ["sphere", "cylinder"])
+def test_shadow_boundary_band(body, precision):
+    """Receivers in a narrow band around the shadow boundary of a sphere and
+    of a vertical cylinder: grazing reflections (where the reflection-point
+    solve takes its longest paths, including the full iteration after the
+    FP32 stage) and creeping paths of nearly zero arc, both sides of the
+    boundary, against the oracle; flags equal.  FP32 at the usual 1e-4.
+    FP64 at 5e-9: the reflection at grazing incidence is ill-conditioned.
+    Moving a receiver by 1e-15 of its coordinates changes the oracle's own
+    field by up to 1.4e-9 (sphere) and 5.9e-9 (cylinder, 28 GHz) at
+    d = 3.9e-6, and by 1e-11 at d = 5e-4, which bounds the agreement of any
+    two FP64 evaluations there."""
+    cfg, rx = _band_case(body)
     Eg, fg = run_library(cfg, precision, rx=rx)
     Eo, info = run_oracle(cfg, rx=rx)
     np.testing.assert_array_equal(fg & 5, info["flags"] & 5)
     err = normwise(Eg, Eo)
-    _report("shadow-boundary band p%d (%d lit)" % (precision, int(((fg & 4) != 0).sum())), err)
+    _report("shadow-boundary band %s p%d (%d lit)" % (body, precision, int(((fg & 4) != 0).sum())), err)
     assert np.all(err <= {0: 1e-4, 1: 5e-9}[precision])
