@@ -302,3 +302,31 @@ def test_shadow_boundary_band(body, precision):
     err = normwise(Eg, Eo)
     _report("shadow-boundary band %s p%d (%d lit)" % (body, precision, int(((fg & 4) != 0).sum())), err)
     assert np.all(err <= {0: 1e-4, 1: 5e-9}[precision])
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_cylinder_height_limits(precision):
+    """A finite vertical cylinder (z in [0, 1.7]) with the source above its
+    top (z = 2.5), receivers on vertical lines behind and beside it at 301
+    heights from 0 to 3 m: creeping and reflected paths switch on and off as
+    their attachment or reflection heights cross the lateral surface's ends
+    (the height cull and the exact height tests decide).  Against the oracle
+    at the usual tolerances; flags equal; the sweep must cross at least one
+    such switch (checked on the oracle's per-path validity)."""
+    sc = W.empty_scene()
+    sc["cylinders"] = np.array([[0.0, 0.0, 0.0, 1.7, 0.5]], np.float32)
+    cfg = dict(name="cylinder-heights", scene=sc,
+               tx=dict(pos=np.array([4.0, 0.0, 2.5], np.float32),
+                       dipole=np.array([0.3, 0.5, 0.8], np.float32), amplitude=1.0),
+               rx=np.zeros((1, 3), np.float32), freqs=np.array([1e9, 5e9, 28e9]))
+    zs = np.linspace(0.0, 3.0, 301)
+    rx = np.concatenate([np.stack([np.full(zs.size, -3.0), np.full(zs.size, y), zs], 1)
+                         for y in (0.3, -0.6, 1.5)]).astype(np.float32)
+    Eg, fg = run_library(cfg, precision, rx=rx)
+    Eo, info = run_oracle(cfg, rx=rx)
+    valid = [np.asarray(rec["valid"]) for _, rec in info["paths"]]
+    assert any(0 < v.sum() < v.size for v in valid)
+    np.testing.assert_array_equal(fg & 5, info["flags"] & 5)
+    err = normwise(Eg, Eo)
+    _report("cylinder height limits p%d" % precision, err)
+    assert np.all(err <= TOL[precision])
