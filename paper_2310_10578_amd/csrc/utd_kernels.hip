@@ -713,8 +713,11 @@ __device__ __forceinline__ void field_rx(const LaunchParams& L, const float* __r
         // direct field, Eq. (1): A (p - (p.s)s) e^{-jks}/s
         if ((fl & kFlagLos) && L.lit_branch) {
             d3 v = mk(rx[3 * i] - L.T[0], rx[3 * i + 1] - L.T[1], rx[3 * i + 2] - L.T[2]);
-            double sd = norm(v);
-            R isd = (R)(1.0 / sd);
+            // 1/s from grsqrt and s = |v|^2 / s: within an ulp, without the
+            // library square root and a division
+            const double d2v = dot(v, v), isd_d = grsqrt(d2v);
+            const double sd = d2v * isd_d;
+            R isd = (R)isd_d;
             R shx = (R)v.x * isd, shy = (R)v.y * isd, shz = (R)v.z * isd;
             R px = (R)L.p[0], py = (R)L.p[1], pz = (R)L.p[2];
             R pd = px * shx + py * shy + pz * shz;
