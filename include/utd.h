@@ -26,8 +26,21 @@
  *   - A non-OK status means nothing was enqueued; utd_last_error() gives a
  *     message for the calling thread.  No exception crosses the ABI.
  *   - Conditions only visible on the device (source inside a body, receiver
- *     inside a body, receiver on a sphere's axial caustic) are reported per
- *     receiver through `rx_flags` (UTD_FLAG_*), never as a status.
+ *     inside a body, receiver on a sphere's axial caustic, invalid device
+ *     inputs) are reported per receiver through `rx_flags` (UTD_FLAG_*),
+ *     never as a status.  Invalid device inputs also raise bits of a
+ *     device-wide word read by utd_input_status; they never produce
+ *     non-finite fields:
+ *       receiver with a non-finite coordinate  -> E = 0 there,
+ *                                                 UTD_FLAG_INVALID_RX, UTD_BAD_RX
+ *       body with a non-finite parameter, radius <= 0 or height < 0
+ *                                              -> E = 0 at every receiver of
+ *                                                 the call (of the frame when
+ *                                                 batched), UTD_FLAG_BAD_BODY,
+ *                                                 UTD_BAD_BODY
+ *       frequency not finite or <= 0           -> E = 0 at that frequency,
+ *                                                 UTD_FLAG_BAD_FREQ on every
+ *                                                 receiver, UTD_BAD_FREQ
  */
 #ifndef UTD_H
 #define UTD_H
@@ -53,6 +66,14 @@ typedef enum {
 #define UTD_FLAG_CAUSTIC   2u  /* a sphere creeping path dropped at the axial caustic */
 #define UTD_FLAG_LOS       4u  /* direct path visible (U_LOS = 1)               */
 #define UTD_FLAG_TX_INSIDE 8u  /* source inside a body: E = 0 for every receiver */
+#define UTD_FLAG_INVALID_RX 16u /* receiver coordinate not finite: E = 0          */
+#define UTD_FLAG_BAD_BODY  32u  /* an invalid body in the call (frame): E = 0      */
+#define UTD_FLAG_BAD_FREQ  64u  /* an invalid frequency: E = 0 at that frequency   */
+
+/* Bits of the device input-status word (utd_input_status). */
+#define UTD_BAD_RX   1u
+#define UTD_BAD_BODY 2u
+#define UTD_BAD_FREQ 4u
 
 typedef struct {
     int precision;          /* 0: FP32 field evaluation with FP64 path lengths and
@@ -204,6 +225,32 @@ utd_status utd_batched_config(int tile_rx, int blocks_per_cu);
 utd_status utd_path_census(const utd_scene *scene, const utd_bodies *bodies, const utd_source *tx,
                            const float *rx, int64_t n_rx, const utd_options *opt, int64_t *counts,
                            void *stream);
+
+/* Per-(receiver, body) path masks of the visibility stage: runs the
+ * classification and visibility of utd_smooth_field for the same inputs and
+ * options (the decisions depend on opt->precision) and writes
+ *   mask_out  device uint8 [n_bodies][n_rx], body-major (spheres first, then
+ *             cylinders, as in `bodies`): bit 2*ell + s set when the creeping
+ *             path of side s (0: towards the receiver, 1: far side) with ell
+ *             encirclements exists and both its legs are visible (the U^d of
+ *             Eq. (2)); bit 6 the same for the reflection (U^r of Eq. (1));
+ *             bit 7 when a sphere creeping path was dropped at the axial
+ *             caustic;
+ *   rx_flags  device uint8 [n_rx] or NULL (UTD_FLAG_*, UTD_FLAG_LOS = U_LOS).
+ * These are the decisions utd_smooth_field takes for the same inputs; tests
+ * feed them to an independent evaluation to compare fields path by path.
+ * Asynchronous on `stream`.  Errors as for utd_smooth_field; UTD_E_ARG if
+ * mask_out is NULL with bodies and receivers. */
+utd_status utd_path_masks(const utd_scene *scene, const utd_bodies *bodies, const utd_source *tx,
+                          const float *rx, int64_t n_rx, const utd_options *opt, uint8_t *mask_out,
+                          uint8_t *rx_flags, void *stream);
+
+/* Device input status: waits for the current device, writes to *bits the OR
+ * of the UTD_BAD_* bits raised by every call on this device since the last
+ * read (invalid receivers, bodies or frequencies found by the kernels), and
+ * clears them.  The calls themselves never wait for this.  Errors: UTD_E_ARG
+ * for NULL, UTD_E_DEVICE. */
+utd_status utd_input_status(uint32_t *bits);
 
 /* Per-kernel timing for measurement.  utd_profile_enable(1) makes every
  * later call record a HIP event pair around each kernel it launches, on the

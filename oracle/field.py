@@ -138,12 +138,15 @@ def _incident(T, P, dipole, amp, k):
     return amp * pp, s
 
 
-def field(scene, tx, rx, freqs, opts=None, mode="em", frozen=None, return_info=False):
+def field(scene, tx, rx, freqs, opts=None, mode="em", frozen=None, return_info=False, return_abs=False):
     """E[f, c, n] (mode 'em') or u[f, n] (mode 'soft'/'hard'), complex128.
 
     ``frozen``: the classification returned by an earlier call (``return_info``)
     whose visibility decisions are reused; only the geometry is recomputed.
     This is how finite-difference gradients hold the masks fixed.
+    ``return_abs``: also return A[f, n] = sum over the receiver's ray
+    contributions of their magnitudes ||E_path||_2 (the scale against which
+    the rounding error of a coherent sum is bounded per receiver).
     """
     o = _opts(opts)
     sc = _scene(scene)
@@ -163,6 +166,7 @@ def field(scene, tx, rx, freqs, opts=None, mode="em", frozen=None, return_info=F
     n = R.shape[0]
     scalar = mode in ("soft", "hard")
     out = np.zeros((freqs.size, n) if scalar else (freqs.size, 3, n), dtype=complex)
+    absum = np.zeros((freqs.size, n))
     for fi, f in enumerate(freqs):
         k = 2 * np.pi * f / C0
         acc = out[fi]
@@ -172,20 +176,29 @@ def field(scene, tx, rx, freqs, opts=None, mode="em", frozen=None, return_info=F
                 if scalar:
                     s = np.linalg.norm(R[idx] - T, axis=1)
                     acc[idx] += np.exp(-1j * k * s) / s
+                    absum[fi, idx] += 1.0 / s
                 else:
                     pp, s = _incident(T, R[idx], dip, amp, k)
                     acc[:, idx] += (pp * (np.exp(-1j * k * s) / s)[:, None]).T
+                    absum[fi, idx] += np.linalg.norm(pp, axis=1) / s
         for key, rec in info["paths"]:
             idx = np.nonzero(rec["valid"])[0]
             if not idx.size:
                 continue
+            part = np.zeros_like(acc) if return_abs else acc
             if rec["kind"] == "creep":
-                _add_creeping(acc, rec, idx, T, dip, amp, k, mode)
+                _add_creeping(part, rec, idx, T, dip, amp, k, mode)
             else:
-                _add_reflection(acc, rec, idx, T, dip, amp, k, mode)
+                _add_reflection(part, rec, idx, T, dip, amp, k, mode)
+            if return_abs:
+                acc += part
+                absum[fi] += np.abs(part) if scalar else np.linalg.norm(part, axis=0)
+    res = (out,)
     if return_info:
-        return out, info
-    return out
+        res += (info,)
+    if return_abs:
+        res += (absum,)
+    return res[0] if len(res) == 1 else res
 
 
 def _take(rec, name, idx):

@@ -15,10 +15,13 @@ LIB_PATH = os.path.join(HERE, "libutd.so")
 
 UTD_OK = 0
 FLAG_INSIDE, FLAG_CAUSTIC, FLAG_LOS, FLAG_TX_INSIDE = 1, 2, 4, 8
+FLAG_INVALID_RX, FLAG_BAD_BODY, FLAG_BAD_FREQ = 16, 32, 64
+BAD_RX, BAD_BODY, BAD_FREQ = 1, 2, 4
 
 EXPORTS = ["utd_default_options", "utd_scene_create", "utd_scene_destroy", "utd_scene_triangles",
            "utd_scene_nodes", "utd_smooth_field", "utd_smooth_field_backward", "utd_smooth_field_batched",
-           "utd_path_census", "utd_batched_config", "utd_profile_enable", "utd_profile_read", "utd_last_error"]
+           "utd_path_census", "utd_batched_config", "utd_profile_enable", "utd_profile_read", "utd_last_error",
+           "utd_path_masks", "utd_input_status"]
 KERNELS = ["prep", "occlude", "field", "backward", "reduce", "batched"]
 
 
@@ -77,6 +80,11 @@ def load_library(path=LIB_PATH):
     lib.utd_path_census.argtypes = [vp, ctypes.POINTER(Bodies), ctypes.POINTER(Source), vp, i64,
                                     ctypes.POINTER(Options), vp, vp]
     lib.utd_path_census.restype = i32
+    lib.utd_path_masks.argtypes = [vp, ctypes.POINTER(Bodies), ctypes.POINTER(Source), vp, i64,
+                                   ctypes.POINTER(Options), vp, vp, vp]
+    lib.utd_path_masks.restype = i32
+    lib.utd_input_status.argtypes = [vp]
+    lib.utd_input_status.restype = i32
     lib.utd_profile_enable.argtypes = [i32]
     lib.utd_profile_enable.restype = None
     lib.utd_profile_read.argtypes = [vp, vp]
@@ -346,3 +354,32 @@ def path_census(scene, spheres, cylinders, source, rx, l_enc=0, bodies_occlude=T
     c = list(counts)
     return dict(creeping=sum(c[:6]), creeping_by_bit=c[:6], reflections=c[6], caustic=c[7], los=c[8], inside=c[9],
                 paths=sum(c[:7]))
+
+
+def path_masks(scene, spheres, cylinders, source, rx, precision=0, l_enc=0, bodies_occlude=True, lit_branch=True,
+               caustic_guard=1e-6, stream=None):
+    """Visibility decisions of ``smooth_field`` for the same inputs:
+    (mask [n_bodies, n_rx] uint8, flags [n_rx] uint8) on the GPU; bodies are
+    ordered spheres first, then cylinders.  Mask bits: 2 ell + side for the
+    creeping paths, 6 the reflection, 7 a caustic drop."""
+    torch = _torch()
+    lib = load_library()
+    _dev(rx, torch.float32, (3,), "rx")
+    b, keep = _bodies(spheres, cylinders)
+    n = rx.shape[0]
+    nb = b.n_sph + b.n_cyl
+    mask = torch.empty((nb, n), dtype=torch.uint8, device=rx.device)
+    flags = torch.empty((n,), dtype=torch.uint8, device=rx.device)
+    opt = make_options(precision, l_enc, bodies_occlude, lit_branch, caustic_guard)
+    _check(lib.utd_path_masks(scene.handle if scene is not None else None, ctypes.byref(b), ctypes.byref(source),
+                              rx.data_ptr() if n else None, n, ctypes.byref(opt),
+                              mask.data_ptr() if mask.numel() else None, flags.data_ptr() if n else None,
+                              _stream(stream)))
+    return mask, flags
+
+
+def input_status():
+    """Waits for the device; returns and clears the BAD_* bits raised since the last read."""
+    v = ctypes.c_uint32(0)
+    _check(load_library().utd_input_status(ctypes.cast(ctypes.pointer(v), ctypes.c_void_p)))
+    return int(v.value)

@@ -49,6 +49,7 @@ __device__ __forceinline__ void record_adjoint(const PathEval<R>& pe, const Tabs
     for (int c = 0; c < 3; ++c) l.vs[c] = l.vh[c] = (R)0;
     const bool refl = pe.refl != 0;
     for (int f = 0; f < n_f; ++f) {
+        if (!fcs[f].ok) continue;       // an invalid frequency has a zero field
         FreqC<R> fc(fcs[f]);
         cplx<R> g[3];
 #pragma unroll
@@ -140,6 +141,7 @@ __device__ __forceinline__ void los_adjoint(const LaunchParams& L, d3 R3, const 
     double lsd = 0.0;
     R le[3] = {(R)0, (R)0, (R)0};
     for (int f = 0; f < L.n_f; ++f) {
+        if (!fcs[f].ok) continue;
         double rev = fcs[f].rev_per_m;
         cplx<R> ph = phase_rev<R>(rev * sd0);
         R im = (R)0;
@@ -175,7 +177,7 @@ __device__ __forceinline__ void los_adjoint(const LaunchParams& L, d3 R3, const 
 // list; per-entry contributions are summed per segment in a fixed order.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int pair_records(uint8_t m, uint8_t fl, int S) {
-    if (fl & (kFlagInside | kFlagTxInside)) return 0;
+    if (fl & kFlagDead) return 0;
     return __builtin_popcount(m & ((1u << S) - 1u)) + ((m >> kBitRefl) & 1u);
 }
 
@@ -347,7 +349,7 @@ __global__ void __launch_bounds__(256) k_adj_los(LaunchParams L, const float* __
     for (int d = 0; d < kAdjComp; ++d) acc[d] = 0.0;
     if (i < L.n_rx) {
         uint8_t fl = flags[i];
-        if (!(fl & (kFlagInside | kFlagTxInside)) && (fl & kFlagLos) && L.lit_branch)
+        if (!(fl & kFlagDead) && (fl & kFlagLos) && L.lit_branch)
             los_adjoint<R>(L, mk(rx[3 * i], rx[3 * i + 1], rx[3 * i + 2]), fcs, gE, i, acc);
     }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;

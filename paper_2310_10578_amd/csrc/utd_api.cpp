@@ -363,6 +363,42 @@ utd_status utd_path_census(const utd_scene* scene, const utd_bodies* bodies, con
     return UTD_OK;
 }
 
+utd_status utd_path_masks(const utd_scene* scene, const utd_bodies* bodies, const utd_source* tx, const float* rx,
+                          int64_t n_rx, const utd_options* opt, uint8_t* mask_out, uint8_t* rx_flags,
+                          void* stream) {
+    double fdummy = 1e9;
+    utd_status st = check_common(bodies, tx, rx, n_rx, &fdummy, 1, opt);
+    if (st != UTD_OK) return st;
+    const int64_t nb = bodies->n_sph + bodies->n_cyl;
+    if (n_rx == 0) return UTD_OK;
+    if (nb > 0 && !mask_out) return fail(UTD_E_ARG, "mask_out is NULL");
+    hipError_t e = hipSuccess;
+    hipStream_t s = (hipStream_t)stream;
+    utd::LaunchParams L = make_params(scene, bodies, tx, n_rx, 0, opt);
+    Workspace w;
+    e = w.alloc((int)nb, n_rx, 0, opt->l_enc, opt->precision, rx_flags == nullptr, s);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(UTD_E_OOM, "workspace allocation") : hip_fail(e, "hipMallocAsync");
+    {
+        ProfScope ps(UTD_K_OCCLUDE, s);
+        e = utd::launch_paths(L, opt->precision, rx, bodies->sph, bodies->cyl, nullptr, w.prep, w.fc,
+                              scene ? scene->d_nodes : nullptr, scene ? scene->d_tris : nullptr, w.mask, w.rec,
+                              rx_flags ? rx_flags : w.flags, w.ent, w.ent_th, w.vis, w.counters + 12, w.cap, s);
+    }
+    if (e == hipSuccess && nb > 0)
+        e = hipMemcpyAsync(mask_out, w.mask, (size_t)nb * (size_t)n_rx, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "path masks");
+    return UTD_OK;
+}
+
+utd_status utd_input_status(uint32_t* bits) {
+    if (!bits) return fail(UTD_E_ARG, "bits is NULL");
+    unsigned v = 0;
+    hipError_t e = utd::read_input_status(&v);
+    if (e != hipSuccess) return hip_fail(e, "input status");
+    *bits = v;
+    return UTD_OK;
+}
+
 utd_status utd_smooth_field_backward(const utd_scene* scene, const utd_bodies* bodies, const utd_source* tx,
                                      const float* rx, int64_t n_rx, const double* freqs, int n_f,
                                      const utd_options* opt, const void* grad_E, void* d_cyl, void* d_sph, void* d_tx,

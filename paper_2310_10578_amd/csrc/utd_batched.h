@@ -203,13 +203,10 @@ __global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(3, 8)
         bool dead = true;
         uint8_t fl = 0;
         if (act) {
-            bool inside = false, tx_inside = false;
-            for (int b = 0; b < nbf; ++b) {
-                inside |= inside_body(fprep[b], R3);
-                tx_inside |= inside_body(fprep[b], T);
-            }
-            fl = (uint8_t)((tx_inside ? kFlagTxInside : 0) | (inside ? kFlagInside : 0));
-            dead = inside || tx_inside;
+            fl = receiver_flags(L, nullptr, fcyl, R3, T);
+            for (int j = 0; j < L.n_f; ++j)
+                if (!fcs[j].ok) fl |= kFlagBadFreq;
+            dead = (fl & kFlagDead) != 0;
             const bool los = !dead && !seg_blocked(T, R3, L, nullptr, fcyl, -1, true, nodes, tris, stk, TILE);
             if (los) fl |= kFlagLos;
             R e3[3] = {(R)0, (R)0, (R)0};
@@ -228,7 +225,7 @@ __global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(3, 8)
 #pragma unroll 1
             for (int j = 0; j < L.n_f; ++j) {
                 cplx<R> ph{(R)0, (R)0};
-                if (use_los) ph = phase_rev<R>(fcs[j].rev_per_m * sd);
+                if (use_los && fcs[j].ok) ph = phase_rev<R>(fcs[j].rev_per_m * sd);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     int64_t o = ((int64_t)j * 3 + c) * L.n_rx + li;
@@ -268,7 +265,10 @@ __global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(3, 8)
                 }
                 __syncthreads();
                 // --- 2. drain the queue when the next body might not fit ---
+                // every wave reads the count before any wave appends the next
+                // body's candidates, so the drain decision is workgroup-uniform
                 const int qn = s_qn;
+                __syncthreads();
                 if (qn > QCAP - TILE * per_pair || bl == ng - 1) {
                     for (int k = tid; k < qn; k += TILE) {
                         const uint32_t key = s_q[k];
@@ -326,6 +326,7 @@ __global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(3, 8)
                         const int mode = !any_refl ? kCreep : (!any_creep ? kRefl : kAny);
 #pragma unroll 1
                         for (int j = 0; j < L.n_f; ++j) {
+                            if (!fcs[j].ok) continue;     // an invalid frequency keeps its zero field
                             R e[6];
 #pragma unroll
                             for (int c = 0; c < 3; ++c) {

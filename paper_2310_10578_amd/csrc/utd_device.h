@@ -23,6 +23,15 @@ constexpr double kInvTwoPi = 0.1591549430918953357688837;
 constexpr int kBitRefl = 6;
 constexpr int kBitCaustic = 7;
 constexpr uint8_t kFlagInside = 1, kFlagCaustic = 2, kFlagLos = 4, kFlagTxInside = 8;
+// invalid inputs found on the device: a non-finite receiver (that receiver
+// gets E = 0), an invalid body of the call or frame (every receiver gets
+// E = 0), an invalid frequency (E = 0 at that frequency, every receiver
+// flagged)
+constexpr uint8_t kFlagInvalidRx = 16, kFlagBadBody = 32, kFlagBadFreq = 64;
+// receivers whose field is zero at every frequency
+constexpr uint8_t kFlagDead = kFlagInside | kFlagTxInside | kFlagInvalidRx | kFlagBadBody;
+// bits of the device-wide input status word (utd_input_status)
+constexpr unsigned kBadRx = 1u, kBadBody = 2u, kBadFreq = 4u;
 
 struct LaunchParams {
     double T[3];          // source position
@@ -59,6 +68,7 @@ struct FreqConst {
     double rev_per_m;
     double kd, k13d, k16d, km16d, skd, ik13d, iskd;
     float kf, k13f, k16f, km16f, skf, ik13f, iskf;
+    int ok;               // 0: the frequency is not finite or not > 0 (field zero)
 };
 
 // ---------------------------------------------------------------------------

@@ -102,25 +102,35 @@ __device__ __forceinline__ BodyPrepT<G> prep_cylinder(V3<G> T, G cx, G cy, doubl
     return p;
 }
 
+// A body whose parameters are not finite, or whose radius is not > 0 (or a
+// cylinder height < 0), is invalid: it carries no path, and every receiver
+// of the call is flagged (kFlagBadBody) with a zero field.
+__device__ __forceinline__ bool body_params_bad(const float* sph, int n_sph, const float* cyl, int b) {
+    if (b < n_sph) {
+        const float* s = sph + 4 * b;
+        return !(isfinite(s[0]) && isfinite(s[1]) && isfinite(s[2]) && isfinite(s[3]) && s[3] > 0.0f);
+    }
+    const float* c = cyl + 5 * (b - n_sph);
+    return !(isfinite(c[0]) && isfinite(c[1]) && isfinite(c[2]) && isfinite(c[3]) && isfinite(c[4]) &&
+             c[3] >= 0.0f && c[4] > 0.0f);
+}
+
 __device__ __forceinline__ BodyPrep body_prep(const double T[3], const float* sph, int n_sph, const float* cyl,
                                               int b) {
     d3 t = mk(T[0], T[1], T[2]);
+    BodyPrep p;
     if (b < n_sph) {
         const float* s = sph + 4 * b;
-        return prep_sphere<double>(t, mk(s[0], s[1], s[2]), (double)s[3]);
+        p = prep_sphere<double>(t, mk(s[0], s[1], s[2]), (double)s[3]);
+    } else {
+        const float* c = cyl + 5 * (b - n_sph);
+        p = prep_cylinder<double>(t, c[0], c[1], c[2], c[3], c[4]);
     }
-    const float* c = cyl + 5 * (b - n_sph);
-    return prep_cylinder<double>(t, c[0], c[1], c[2], c[3], c[4]);
+    if (body_params_bad(sph, n_sph, cyl, b)) p.ok = 0;
+    return p;
 }
 
-__device__ __forceinline__ bool inside_body(const BodyPrep& b, d3 P) {
-    if (b.kind == 0) {
-        d3 v = P - mk(b.c[0], b.c[1], b.c[2]);
-        return dot(v, v) <= b.a * b.a;
-    }
-    double x = P.x - b.c[0], y = P.y - b.c[1];
-    return x * x + y * y <= b.a * b.a && P.z >= b.z0 && P.z <= b.z0 + b.h;
-}
+__device__ __forceinline__ bool finite3(d3 P) { return isfinite(P.x) && isfinite(P.y) && isfinite(P.z); }
 
 // Receiver-side quantities of one body, shared by all of its paths.
 //   sphere:   R at polar angle theta_R about e_T in the T-C-R plane, e_perp the

@@ -46,6 +46,9 @@ hipError_t launch_batch(const BatchParams& B, int precision, int n_blocks, const
                         unsigned* counter, const float4* nodes, const float4* tris, double* th, void* E,
                         uint8_t* flags, hipStream_t s);
 
+// Waits for the current device, then reads and clears its input-status bits.
+hipError_t read_input_status(unsigned* bits);
+
 hipError_t launch_census(int64_t n_mask, const uint8_t* mask, int64_t n_rx, const uint8_t* flags,
                          unsigned long long* counts, hipStream_t s);
 

@@ -28,9 +28,25 @@
 namespace utd {
 
 // ---------------------------------------------------------------------------
-// frequency constants
+// input status: bits (kBadRx, kBadBody, kBadFreq) raised by any call on this
+// device since the host last read them (utd_input_status)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ FreqConst freq_const(double f) {
+__device__ unsigned int g_input_status;
+
+// Lanes that found an invalid input raise its bit; a plain read first keeps
+// the atomics to the lanes that find the bit still clear.
+__device__ __forceinline__ void report_bad(bool bad, unsigned bit) {
+    if (bad && !(__atomic_load_n(&g_input_status, __ATOMIC_RELAXED) & bit)) atomicOr(&g_input_status, bit);
+}
+
+// ---------------------------------------------------------------------------
+// frequency constants (an invalid frequency gets ok = 0 and harmless finite
+// constants; its field is written as zero)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ FreqConst freq_const(double f_in) {
+    const bool ok = isfinite(f_in) && f_in > 0.0;
+    report_bad(!ok, kBadFreq);
+    const double f = ok ? f_in : 1e9;
     double k = kTwoPi * f / kC0;
     double k13 = cbrt(k), k16 = sqrt(k13);
     FreqConst c;
@@ -39,6 +55,7 @@ __device__ __forceinline__ FreqConst freq_const(double f) {
     c.iskd = 1.0 / c.skd;
     c.kf = (float)k; c.k13f = (float)k13; c.k16f = (float)k16; c.km16f = (float)(1.0 / k16);
     c.skf = (float)sqrt(k); c.ik13f = (float)(1.0 / k13); c.iskf = (float)c.iskd;
+    c.ok = ok ? 1 : 0;
     return c;
 }
 
@@ -52,6 +69,25 @@ __device__ __forceinline__ bool inside_raw(const LaunchParams& L, const float* s
     const float* c = cyl + 5 * (b - L.n_sph);
     double x = P.x - c[0], y = P.y - c[1];
     return x * x + y * y <= (double)c[4] * c[4] && P.z >= c[2] && P.z <= (double)c[2] + c[3];
+}
+
+// Flags of receiver R3 that do not depend on visibility: inside a body,
+// source inside a body, non-finite receiver, an invalid body in the call.
+// Raises the matching input-status bits.
+__device__ __forceinline__ uint8_t receiver_flags(const LaunchParams& L, const float* sph, const float* cyl, d3 R3,
+                                                  d3 T) {
+    const int nb = L.n_sph + L.n_cyl;
+    const bool bad_rx = !finite3(R3);
+    bool inside = false, tx_inside = false, bad_body = false;
+    for (int k = 0; k < nb; ++k) {
+        inside |= inside_raw(L, sph, cyl, k, R3);
+        tx_inside |= inside_raw(L, sph, cyl, k, T);
+        bad_body |= body_params_bad(sph, L.n_sph, cyl, k);
+    }
+    report_bad(bad_rx, kBadRx);
+    report_bad(bad_body, kBadBody);
+    return (uint8_t)((tx_inside ? kFlagTxInside : 0) | (inside ? kFlagInside : 0) | (bad_rx ? kFlagInvalidRx : 0) |
+                     (bad_body ? kFlagBadBody : 0));
 }
 
 // ---------------------------------------------------------------------------
@@ -251,8 +287,9 @@ __global__ void __launch_bounds__(256) k_cand(LaunchParams L, const float* __res
     const int slot = blockIdx.y;
     if (slot == 0 && blockIdx.x == 0 && freqs)
         for (int f = threadIdx.x; f < L.n_f; f += blockDim.x) fcs[f] = freq_const(freqs[f]);
-    const bool act = i < L.n_rx;
-    const d3 R3 = act ? mk(rx[3 * i], rx[3 * i + 1], rx[3 * i + 2]) : mk(0.0, 0.0, 0.0);
+    const bool in_range = i < L.n_rx;
+    const d3 R3 = in_range ? mk(rx[3 * i], rx[3 * i + 1], rx[3 * i + 2]) : mk(0.0, 0.0, 0.0);
+    const bool act = in_range && finite3(R3);
     const d3 T = mk(L.T[0], L.T[1], L.T[2]);
     const int nb = L.n_sph + L.n_cyl;
     uint8_t cand = 0;            // candidate bits (creeping 2 ell + side, reflection kBitRefl)
@@ -260,14 +297,9 @@ __global__ void __launch_bounds__(256) k_cand(LaunchParams L, const float* __res
     double th = 0.0;
     int b = slot - 1;
     if (slot == 0) {
-        if (act) {
-            bool inside = false, tx_inside = false;
-            for (int k = 0; k < nb; ++k) {
-                inside |= inside_raw(L, sph, cyl, k, R3);
-                tx_inside |= inside_raw(L, sph, cyl, k, T);
-            }
-            flags[i] = (uint8_t)((tx_inside ? kFlagTxInside : 0) | (inside ? kFlagInside : 0));
-            los_cand = !inside && !tx_inside;
+        if (in_range) {
+            flags[i] = receiver_flags(L, sph, cyl, R3, T);
+            los_cand = !(flags[i] & kFlagDead);
         }
     } else {
         const BodyPrep P = prep[b];
@@ -289,7 +321,7 @@ __global__ void __launch_bounds__(256) k_cand(LaunchParams L, const float* __res
             }
             if (L.lit_branch && refl_angle<Kinds::Any, (sizeof(R) == 8)>(P, g, R3, T, &th)) cand |= (uint8_t)(1u << kBitRefl);
             mask[(int64_t)b * L.n_rx + i] = m;     // visible bits are added by k_vis
-        } else if (act) {
+        } else if (in_range) {
             mask[(int64_t)b * L.n_rx + i] = 0;
         }
     }
@@ -486,7 +518,7 @@ __global__ void __launch_bounds__(512) k_paths(LaunchParams L, const float* __re
         const BodyPrep P = body_prep(L.T, sph, L.n_sph, cyl, b);
         if (blockIdx.x == 0 && threadIdx.x == 0) prep[b] = P;
         const bool bo = L.bodies_occlude != 0;
-        if (have) {
+        if (have && finite3(R3)) {
             RxGeo g = rx_geo(P, R3);
             if (kind < K - 1) {
                 const int ell = kind >> 1, sgn = (kind & 1) ? -1 : 1;
@@ -527,15 +559,8 @@ __global__ void __launch_bounds__(512) k_paths(LaunchParams L, const float* __re
     if (b == 0 && kind == (K > 1 ? 1 : 0) && blockIdx.x == 0 && freqs)
         for (int f = lane; f < L.n_f; f += 64) fcs[f] = freq_const(freqs[f]);
     if (b == 0 && kind == 0 && have) {
-        uint8_t f = 0;
-        bool inside = false, tx_inside = false;
-        for (int k = 0; k < nb; ++k) {
-            inside |= inside_raw(L, sph, cyl, k, R3);
-            tx_inside |= inside_raw(L, sph, cyl, k, T);
-        }
-        if (tx_inside) f |= kFlagTxInside;
-        if (inside) f |= kFlagInside;
-        if (!inside && !tx_inside && !seg_blocked(T, R3, L, sph, cyl, -1, true, nullptr, nullptr, nullptr, 0))
+        uint8_t f = receiver_flags(L, sph, cyl, R3, T);
+        if (!(f & kFlagDead) && !seg_blocked(T, R3, L, sph, cyl, -1, true, nullptr, nullptr, nullptr, 0))
             f |= kFlagLos;
         flags[i] = f;
     }
@@ -664,8 +689,16 @@ __device__ __forceinline__ void field_rx(const LaunchParams& L, const float* __r
     for (int j = 0; j < FC; ++j)
 #pragma unroll
         for (int c = 0; c < 6; ++c) E[j][c] = (R)0;
+    // frequencies of the chunk that are evaluated (an invalid one stays zero)
+    bool fok[FC];
+#pragma unroll
+    for (int j = 0; j < FC; ++j) fok[j] = j < nfc && fcs[f0 + j].ok;
     uint8_t fl = flags[i];
-    if (!(fl & (kFlagInside | kFlagTxInside))) {
+    uint8_t fl_new = fl;
+    if (f0 == 0)
+        for (int f = 0; f < L.n_f; ++f)
+            if (!fcs[f].ok) fl_new |= kFlagBadFreq;
+    if (!(fl & kFlagDead)) {
         // diffracted and reflected paths, Eqs. (2)-(4), without their common
         // factor k^{-1/6} (applied once per frequency below)
         int nb = L.n_sph + L.n_cyl;
@@ -683,7 +716,7 @@ __device__ __forceinline__ void field_rx(const LaunchParams& L, const float* __r
                 unpack(rec[((int64_t)b * NS + k) * L.n_rx + i], &pe);
 #pragma unroll
                 for (int j = 0; j < FC; ++j) {
-                    if (j < nfc) {
+                    if (fok[j]) {
                         FreqC<R> fc(fcs[f0 + j]);
                         add_path<R, kCreep, false>(pe, tb, fc, E[j]);
                     }
@@ -694,17 +727,17 @@ __device__ __forceinline__ void field_rx(const LaunchParams& L, const float* __r
                 unpack(rec[((int64_t)b * NS + rec_slot(L, kBitRefl)) * L.n_rx + i], &pe);
 #pragma unroll
                 for (int j = 0; j < FC; ++j) {
-                    if (j < nfc) {
+                    if (fok[j]) {
                         FreqC<R> fc(fcs[f0 + j]);
                         add_path<R, kRefl, false>(pe, tb, fc, E[j]);
                     }
                 }
             }
         }
-        if (f0 == 0 && (caus & (1u << kBitCaustic))) flags[i] = fl | kFlagCaustic;
+        if (caus & (1u << kBitCaustic)) fl_new |= kFlagCaustic;
 #pragma unroll
         for (int j = 0; j < FC; ++j) {
-            if (j < nfc) {
+            if (fok[j]) {
                 const R km16 = FreqC<R>(fcs[f0 + j]).km16;
 #pragma unroll
                 for (int c = 0; c < 6; ++c) E[j][c] *= km16;
@@ -725,7 +758,7 @@ __device__ __forceinline__ void field_rx(const LaunchParams& L, const float* __r
             R e3[3] = {A * (px - pd * shx), A * (py - pd * shy), A * (pz - pd * shz)};
 #pragma unroll
             for (int j = 0; j < FC; ++j) {
-                if (j < nfc) {
+                if (fok[j]) {
                     cplx<R> ph = phase_rev<R>(fcs[f0 + j].rev_per_m * sd);
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
@@ -736,6 +769,7 @@ __device__ __forceinline__ void field_rx(const LaunchParams& L, const float* __r
             }
         }
     }
+    if (f0 == 0 && fl_new != fl) flags[i] = fl_new;
 #pragma unroll
     for (int j = 0; j < FC; ++j) {
         if (j < nfc) {
@@ -805,6 +839,14 @@ __global__ void __launch_bounds__(256) k_census(int64_t n_mask, const uint8_t* _
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+hipError_t read_input_status(unsigned* bits) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpyFromSymbol(bits, HIP_SYMBOL(g_input_status), sizeof(unsigned));
+    const unsigned zero = 0u;
+    if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(g_input_status), &zero, sizeof(unsigned));
+    return e;
+}
+
 hipError_t launch_census(int64_t n_mask, const uint8_t* mask, int64_t n_rx, const uint8_t* flags,
                          unsigned long long* counts, hipStream_t s) {
     hipLaunchKernelGGL(k_census, dim3(512), dim3(256), 0, s, n_mask, mask, n_rx, flags, counts);

@@ -1,35 +1,36 @@
 """Parity of the HIP forward field (through the C ABI) against the FP64 oracle.
 
-Tolerances: relative normwise field error per frequency <= 1e-4 for the FP32
-path and <= 1e-10 for the FP64 path, on the same float32 inputs.  Visibility
-decisions may differ only where a segment grazes an occluder (FP32 watertight
-test on the GPU, FP64 Moller-Trumbore in the oracle); such receivers are
-counted and, when present, the field is compared on the others."""
+Every comparison is receiver-exact (``gpu_util.parity``): the oracle
+evaluates the field with the library's own visibility decisions (exported by
+``utd_path_masks``) and the fields must agree at every receiver -- normwise
+per frequency and per receiver relative to the sum of that receiver's path
+magnitudes -- within 1e-4 (FP32 path) and 1e-10 (FP64 path).  The library's
+decisions are then compared with the oracle's own: inside and caustic flags
+exactly, line-of-sight and path visibility exactly except where a segment
+grazes an occluder (moving its end points by 2e-5 m flips the oracle's own
+decision), on at most 2 % of the receivers.  Reading 14's per-receiver metric
+|dE| / max(|E_ref|, 1e-3 RMS) is bounded by 1e-3 (FP32) and 1e-9 (FP64)."""
 import numpy as np
 import pytest
 
 import workloads as W
-from gpu_util import normwise, run_library, run_oracle
+from gpu_util import TOL, normwise, parity, run_library, run_oracle
 
 pytestmark = pytest.mark.gpu
 
-TOL = {0: 1e-4, 1: 1e-10}
-
-
-def _report(name, err):
-    print("%s normwise error per frequency: %s" % (name, np.array2string(np.asarray(err), precision=2)), flush=True)
+# Reading 14's metric: the per-path relative error of the FP32 path is about
+# 1e-6 (degree-4 Fock tables, hardware sin/cos of an FP64-reduced phase) and
+# that of the FP64 path about 1e-13; a receiver's sum of path magnitudes stays
+# within 100x max(|E|, 1e-3 RMS) on these workloads (a deeper null is floored
+# by the 1e-3 RMS term), which gives these bounds with a factor 10 to spare.
+R14 = {0: 1e-3, 1: 1e-9}
 
 
 @pytest.mark.parametrize("precision", [1, 0])
 @pytest.mark.parametrize("pol", ["hard", "soft"])
 def test_config1_sphere_ring(precision, pol):
     cfg = W.config1(polarisation=pol)
-    Eg, fg = run_library(cfg, precision)
-    Eo, info = run_oracle(cfg)
-    err = normwise(Eg, Eo)
-    _report("config1 %s p%d" % (pol, precision), err)
-    assert np.all(err <= TOL[precision])
-    np.testing.assert_array_equal(fg & 5, info["flags"] & 5)
+    parity(cfg, precision, name="config1 %s" % pol, r14_bound=R14[precision], max_mismatch=0)
 
 
 @pytest.mark.parametrize("precision", [1, 0])
@@ -39,50 +40,40 @@ def test_config2_plane_subsample(precision):
     frequency chunks also end ragged."""
     cfg = W.config2()
     rx = cfg["rx"].reshape(256, 256, 3)[3::8, 5::8].reshape(-1, 3)
-    freqs = cfg["freqs"][::7]
-    Eg, fg = run_library(cfg, precision, rx=rx, freqs=freqs)
-    Eo, info = run_oracle(cfg, rx=rx, freqs=freqs)
-    err = normwise(Eg, Eo)
-    _report("config2 subsample p%d" % precision, err)
-    assert np.all(err <= TOL[precision])
+    parity(cfg, precision, rx=rx, freqs=cfg["freqs"][::7], name="config2 subsample", r14_bound=R14[precision],
+           max_mismatch=0)
 
 
-def test_config2_full_size_sampled():
+@pytest.mark.parametrize("lit_branch", [True, False])
+def test_config2_full_size_sampled(lit_branch):
     """Config 2 at full size in the launch configuration the bench times
-    (65536 receivers, 64 frequencies, FP32); 1500 sampled receivers are
-    recomputed by the oracle one by one."""
+    (65536 receivers, 64 frequencies, FP32), with and without the lit branch
+    (creeping fields alone: the deep-shadow field, 20-40 dB below the direct
+    ray, is compared on its own); 1500 sampled receivers recomputed by the
+    oracle one by one."""
     cfg = W.config2()
-    Eg, fg = run_library(cfg, 0)
     rng = np.random.default_rng(3)
     idx = np.sort(rng.choice(cfg["rx"].shape[0], 1500, replace=False))
-    Eo, info = run_oracle(cfg, rx=cfg["rx"][idx])
-    err = normwise(Eg[:, :, idx], Eo)
-    _report("config2 full sampled", err)
-    assert np.all(err <= TOL[0])
-    np.testing.assert_array_equal(fg[idx] & 5, info["flags"] & 5)
+    opts = dict(lit_branch=lit_branch)
+    res = parity(cfg, 0, sample=idx, opts=opts, name="config2 full sampled lit_branch=%s" % lit_branch,
+                 r14_bound=R14[0], max_mismatch=0)
+    if not lit_branch:
+        # the sample reaches into the shadow, where only creeping paths exist
+        assert np.sum(np.any(res["mask"] != 0, axis=0) & ((res["flags"] & 4) == 0)) > 100
 
 
 @pytest.mark.parametrize("precision", [1, 0])
 @pytest.mark.parametrize("spheres", [False, True])
 def test_small_room(precision, spheres):
     cfg = W.small_room(spheres=spheres)
-    Eg, fg = run_library(cfg, precision)
-    Eo, info = run_oracle(cfg)
-    ok = (fg & 5) == (info["flags"] & 5)
-    assert ok.mean() > 0.995
-    err = normwise(Eg[:, :, ok], Eo[:, :, ok])
-    _report("small room spheres=%s p%d (%d flag mismatches)" % (spheres, precision, (~ok).sum()), err)
-    assert np.all(err <= TOL[precision])
+    parity(cfg, precision, name="small room spheres=%s" % spheres, r14_bound=R14[precision])
 
 
-def test_encirclements_and_creeping_only():
+@pytest.mark.parametrize("precision", [1, 0])
+def test_encirclements_and_creeping_only(precision):
     cfg = W.small_room(n_cyl=4, n_side=12, spheres=True)
     for kw in (dict(l_enc=2), dict(lit_branch=False), dict(bodies_occlude=False)):
-        Eg, fg = run_library(cfg, 1, **kw)
-        Eo, info = run_oracle(cfg, opts=kw)
-        err = normwise(Eg, Eo)
-        _report("options %s" % kw, err)
-        assert np.all(err <= TOL[1])
+        parity(cfg, precision, opts=kw, name="options %s" % kw, r14_bound=R14[precision])
 
 
 def test_inside_and_degenerate_receivers():
@@ -105,6 +96,59 @@ def test_source_inside_body_zeroes_field():
                      amplitude=1.0)
     Eg, fg = run_library(cfg, 0)
     assert np.all(Eg == 0) and np.all(fg & 8)
+
+
+def _invalid_case():
+    """A small room with a sphere and cylinders; returns the configuration."""
+    cfg = W.small_room(n_cyl=4, n_side=8, spheres=True)
+    return cfg
+
+
+@pytest.mark.parametrize("triangles", [True, False])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_invalid_device_inputs_are_flagged(precision, triangles):
+    """Invalid values in device inputs never give non-finite fields:
+    non-finite receivers get E = 0 and their flag; a zero radius, a negative
+    height or a NaN in a body zeroes every receiver's field and flags them; a
+    negative, zero or NaN frequency zeroes that frequency's field and flags
+    every receiver.  The device status word reports each kind; the valid
+    receivers and frequencies keep their normal field."""
+    import paper_2310_10578_amd as utd
+    cfg = _invalid_case()
+    if not triangles:
+        cfg = dict(cfg, scene=dict(cfg["scene"], tri=np.zeros((0, 3, 3), np.float32)))
+    utd.input_status()                                   # clear
+    rx = cfg["rx"].copy()
+    rx[3, 0] = np.nan
+    rx[7, 2] = np.inf
+    Eg, fg = run_library(cfg, precision, rx=rx)
+    assert np.isfinite(Eg).all()
+    assert fg[3] & utd.FLAG_INVALID_RX and fg[7] & utd.FLAG_INVALID_RX
+    assert np.all(Eg[:, :, [3, 7]] == 0)
+    assert utd.input_status() == utd.BAD_RX
+    good = np.setdiff1d(np.arange(rx.shape[0]), [3, 7])
+    E0, f0 = run_library(cfg, precision, rx=cfg["rx"][good])
+    assert np.all(normwise(Eg[:, :, good], E0) <= {0: 1e-6, 1: 1e-13}[precision])
+    np.testing.assert_array_equal(fg[good], f0)
+    assert utd.input_status() == 0
+    for col, val in ((4, 0.0), (3, -1.0), (0, np.nan)):
+        bad = dict(cfg, scene=dict(cfg["scene"], cylinders=cfg["scene"]["cylinders"].copy()))
+        bad["scene"]["cylinders"][1, col] = val
+        Eg, fg = run_library(bad, precision)
+        assert np.all(Eg == 0) and np.all(fg & utd.FLAG_BAD_BODY), (col, val)
+        assert utd.input_status() == utd.BAD_BODY
+    bad = dict(cfg, scene=dict(cfg["scene"], spheres=cfg["scene"]["spheres"].copy()))
+    bad["scene"]["spheres"][0, 3] = -0.2
+    Eg, fg = run_library(bad, precision)
+    assert np.all(Eg == 0) and np.all(fg & utd.FLAG_BAD_BODY)
+    assert utd.input_status() == utd.BAD_BODY
+    freqs = np.array([2.4e9, -1e9, 0.0, np.nan, 5e9])
+    Eg, fg = run_library(cfg, precision, freqs=freqs)
+    assert np.isfinite(Eg).all() and np.all(Eg[1:4] == 0) and np.all(fg & utd.FLAG_BAD_FREQ)
+    E0, f0 = run_library(cfg, precision, freqs=freqs[[0, 4]])
+    assert np.all(normwise(Eg[[0, 4]], E0) <= {0: 1e-6, 1: 1e-13}[precision])
+    np.testing.assert_array_equal(fg & ~np.uint8(utd.FLAG_BAD_FREQ), f0)
+    assert utd.input_status() == utd.BAD_FREQ
 
 
 def test_empty_inputs():
@@ -146,25 +190,12 @@ def test_room_full_size_sampled(cfg_name):
     """The indoor room at full size (2.0e5 triangles; 32 cylinders, 512^2
     receivers, 5/28 GHz -- or 64 cylinders, 128^2 receivers, 16 frequencies)
     in the bench's launch configuration; 768 sampled receivers recomputed by
-    the oracle (FP64 grid-accelerated occlusion).  Receivers whose visibility
-    decisions differ (grazing segments, FP32 vs FP64 tests) are counted and
-    excluded from the field comparison."""
+    the oracle (FP64 grid-accelerated occlusion) with the library's
+    decisions, every one of them compared."""
     cfg = getattr(W, cfg_name)()
-    Eg, fg = run_library(cfg, 0)
     rng = np.random.default_rng(5)
     idx = np.sort(rng.choice(cfg["rx"].shape[0], 768, replace=False))
-    Eo, info = run_oracle(cfg, rx=cfg["rx"][idx])
-    ok = (fg[idx] & 5) == (info["flags"] & 5)
-    # per-path decisions: compare the field only where all decisions agree --
-    # approximated by requiring agreement of the receiver flags and a small
-    # per-receiver error; report the rest
-    d = np.linalg.norm(Eg[:, :, idx] - Eo, axis=1) / np.maximum(np.linalg.norm(Eo, axis=1), 1e-30)
-    bad = (d.max(axis=0) > 1e-3) | ~ok
-    print("%s: %d/%d receivers with differing visibility decisions" % (cfg_name, bad.sum(), idx.size), flush=True)
-    assert bad.mean() < 0.01
-    err = normwise(Eg[:, :, idx][:, :, ~bad], Eo[:, :, ~bad])
-    _report(cfg_name + " sampled", err)
-    assert np.all(err <= TOL[0])
+    parity(cfg, 0, sample=idx, name=cfg_name + " sampled", r14_bound=R14[0])
 
 
 @pytest.mark.parametrize("tx_outside", [False, True])
@@ -180,19 +211,15 @@ def test_receivers_and_source_outside_the_room(tx_outside):
     cfg = dict(cfg, rx=rx)
     if tx_outside:
         cfg["tx"] = dict(cfg["tx"], pos=np.array([5.0, -0.5, 1.5], np.float32))
-    Eg, fg = run_library(cfg, 1)
-    Eo, info = run_oracle(cfg)
+    res = parity(cfg, 1, name="segments leaving the room (source %s)" % ("outside" if tx_outside else "inside"),
+                 r14_bound=R14[1])
+    Eg, fg = res["E"], res["flags"]
     outside = (rx[:, 0] < 0) | (rx[:, 0] > 10) | (rx[:, 1] < 0) | (rx[:, 1] > 8)
     inside = (rx[:, 0] > 0) & (rx[:, 0] < 10) & (rx[:, 1] > 0) & (rx[:, 1] < 8)
-    ok = (fg & 5) == (info["flags"] & 5)
-    assert ok.mean() > 0.98
     # the walls separate the source's side from the other side
     far = inside if tx_outside else outside
     assert not np.any(fg[far] & 4)
     assert np.all(np.abs(Eg[:, :, far]) == 0)
-    err = normwise(Eg[:, :, ok], Eo[:, :, ok])
-    _report("segments leaving the room (source %s)" % ("outside" if tx_outside else "inside"), err)
-    assert np.all(err <= TOL[1])
 
 
 @pytest.mark.parametrize("l_enc", [0, 1, 2])
@@ -200,16 +227,14 @@ def test_bodies_only_scene_all_path_kinds(l_enc):
     """A scene of bodies only (spheres and cylinders, no triangles) takes the
     single-pass visibility kernel, one wavefront per path kind: 2 (l_enc + 1)
     creeping paths and the reflection, and the flags wavefront.  FP64 and
-    FP32 against the oracle for every encirclement count."""
+    FP32 against the oracle for every encirclement count; the body tests are
+    exact in FP64, so every decision equals the oracle's."""
     cfg = W.small_room(n_cyl=4, n_side=12, spheres=True)
     cfg = dict(cfg, scene=dict(cfg["scene"], tri=np.zeros((0, 3, 3), np.float32)))
-    Eo, info = run_oracle(cfg, opts=dict(l_enc=l_enc))
     for precision in (1, 0):
-        Eg, fg = run_library(cfg, precision, l_enc=l_enc)
-        np.testing.assert_array_equal(fg & 13, info["flags"] & 13)
-        err = normwise(Eg, Eo)
-        _report("bodies only, l_enc=%d p%d" % (l_enc, precision), err)
-        assert np.all(err <= TOL[precision])
+        res = parity(cfg, precision, opts=dict(l_enc=l_enc), name="bodies only, l_enc=%d" % l_enc,
+                     r14_bound=R14[precision], max_mismatch=0)
+        np.testing.assert_array_equal(res["flags"] & 13, res["info"]["flags"] & 13)
 
 
 @pytest.mark.parametrize("n_side,n_f,precision", [(255, 63, 0), (255, 17, 0), (255, 17, 1)])
@@ -220,15 +245,11 @@ def test_ragged_receivers_and_frequency_chunks(n_side, n_f, precision):
     FP32 and FP64 65025 x 17: two per lane, the last chunk of 1 in rows of
     one); sampled receivers against the oracle, including the last ones."""
     cfg = W.config2(n_side=n_side, n_f=n_f)
-    Eg, fg = run_library(cfg, precision)
     n = cfg["rx"].shape[0]
     rng = np.random.default_rng(9)
     idx = np.unique(np.concatenate([rng.choice(n, 300, replace=False), np.arange(n - 64, n)]))
-    Eo, info = run_oracle(cfg, rx=cfg["rx"][idx])
-    err = normwise(Eg[:, :, idx], Eo)
-    _report("ragged %d rx x %d f p%d" % (n, n_f, precision), err)
-    assert np.all(err <= TOL[precision])
-    np.testing.assert_array_equal(fg[idx] & 5, info["flags"] & 5)
+    parity(cfg, precision, sample=idx, name="ragged %d rx x %d f" % (n, n_f), r14_bound=R14[precision],
+           max_mismatch=0)
 
 
 @pytest.mark.parametrize("seed", list(range(8)))
@@ -236,26 +257,16 @@ def test_random_scenes(seed):
     """Seeded random small rooms (cylinders of random base, height and radius,
     spheres at random heights, the source anywhere, receivers on a grid and at
     random points, random frequencies, l_enc = seed mod 3): FP64 and FP32
-    against the oracle.  Receivers whose visibility decisions differ between
-    the FP32 BVH test and the oracle's FP64 test (grazing segments) are
-    counted and excluded, as in the room tests."""
+    against the oracle at every receiver."""
     cfg = W.random_scene(seed)
-    kw = dict(l_enc=seed % 3)
-    Eo, info = run_oracle(cfg, opts=kw)
     for precision in (1, 0):
-        Eg, fg = run_library(cfg, precision, **kw)
-        ok = (fg & 13) == (info["flags"] & 13)
-        d = np.linalg.norm(Eg - Eo, axis=1) / np.maximum(np.linalg.norm(Eo, axis=1), 1e-30)
-        bad = (d.max(axis=0) > (1e-6 if precision else 1e-3)) | ~ok
-        assert bad.mean() < 0.02, (seed, precision, int(bad.sum()))
-        err = normwise(Eg[:, :, ~bad], Eo[:, :, ~bad])
-        _report("random scene %d p%d (%d excluded)" % (seed, precision, bad.sum()), err)
-        assert np.all(err <= TOL[precision])
+        parity(cfg, precision, opts=dict(l_enc=seed % 3), name="random scene %d" % seed, r14_bound=R14[precision])
 
 
 def _band_case(body):
     """256 receivers r = r_b (1 + d), d in [-1e-3, 1e-3], around the shadow
-    boundary of one body (r_b: where the ray from the source grazes it)."""
+    boundary of one body (r_b: where the ray from the source grazes it), and
+    two receivers away from it; returns (cfg, rx, d)."""
     n = 256
     d = np.linspace(-1e-3, 1e-3, n)
     if body == "sphere":
@@ -279,7 +290,22 @@ def _band_case(body):
         z = 1.2 + 0.6 * ((np.arange(n) * 0.618034) % 1.0)
         rx = np.stack([np.full(n, -3.0), sgn * np.sqrt(12.25 / 15.75) * (1.0 + d), z], 1)
     rx = np.concatenate([rx, [[-3.0, 0.3, 0.2], [-3.0, 3.5, -1.0]]]).astype(np.float32)
-    return cfg, rx
+    return cfg, rx, np.concatenate([d, [1.0, 1.0]])
+
+
+def _oracle_sensitivity(cfg, rx, frozen, n_try=4, rel=1e-15, seed=0):
+    """Per receiver and frequency: the largest change of the oracle's field
+    (decisions frozen) when every receiver coordinate moves by rel of its
+    value (about five FP64 ulps) -- the conditioning of the field there."""
+    from oracle import field
+    rng = np.random.default_rng(seed)
+    sc, tx, r = W.to_oracle(cfg["scene"], cfg["tx"], rx)
+    E0 = field.field(sc, tx, r, cfg["freqs"], frozen=frozen)
+    S = np.zeros((len(cfg["freqs"]), r.shape[0]))
+    for _ in range(n_try):
+        rp = r * (1.0 + rel * rng.choice([-1.0, 1.0], size=r.shape))
+        S = np.maximum(S, np.linalg.norm(field.field(sc, tx, rp, cfg["freqs"], frozen=frozen) - E0, axis=1))
+    return S
 
 
 @pytest.mark.parametrize("precision", [1, 0])
@@ -289,19 +315,31 @@ def test_shadow_boundary_band(body, precision):
     of a vertical cylinder: grazing reflections (where the reflection-point
     solve takes its longest paths, including the full iteration after the
     FP32 stage) and creeping paths of nearly zero arc, both sides of the
-    boundary, against the oracle; flags equal.  FP32 at the usual 1e-4.
-    FP64 at 5e-9: the reflection at grazing incidence is ill-conditioned.
-    Moving a receiver by 1e-15 of its coordinates changes the oracle's own
-    field by up to 1.4e-9 (sphere) and 5.9e-9 (cylinder, 28 GHz) at
-    d = 3.9e-6, and by 1e-11 at d = 5e-4, which bounds the agreement of any
-    two FP64 evaluations there."""
-    cfg, rx = _band_case(body)
-    Eg, fg = run_library(cfg, precision, rx=rx)
-    Eo, info = run_oracle(cfg, rx=rx)
-    np.testing.assert_array_equal(fg & 5, info["flags"] & 5)
-    err = normwise(Eg, Eo)
-    _report("shadow-boundary band %s p%d (%d lit)" % (body, precision, int(((fg & 4) != 0).sum())), err)
-    assert np.all(err <= {0: 1e-4, 1: 5e-9}[precision])
+    boundary, against the oracle with equal decisions.  FP32 at 1e-4
+    everywhere.  FP64 at 1e-10 (normwise and per receiver) wherever the
+    receiver lies at |d| >= 1e-4 of the boundary; closer, the reflection at
+    grazing incidence is ill-conditioned, and each receiver is held to 1e-10
+    of its path magnitudes plus 4 times the oracle's own change under a
+    displacement of five FP64 ulps of its coordinates."""
+    from gpu_util import frozen_from_library, per_receiver
+    cfg, rx, d = _band_case(body)
+    lib = run_library(cfg, precision, rx=rx, masks=True)
+    far = np.abs(d) >= 1e-4
+    near = ~far
+    res = parity(cfg, precision, rx=rx, lib=lib, sample=np.nonzero(far)[0] if precision else None,
+                 name="shadow-boundary band %s (|d| >= 1e-4 for FP64)" % body, max_mismatch=0)
+    if precision:
+        Eg, fg, mk = lib[0][:, :, near], lib[1][near], lib[2][:, near]
+        frozen = frozen_from_library(cfg, fg, mk)
+        Eo, info, A = run_oracle(cfg, rx=rx[near], frozen=frozen, absum=True)
+        S = _oracle_sensitivity(cfg, rx[near], frozen)
+        dE = np.linalg.norm(Eg - Eo, axis=1)
+        bound = 1e-10 * A + 4.0 * S
+        print("band %s near (|d| < 1e-4, %d rx): max |dE|/A %.2e, max |dE|/bound %.2f, max S/A %.2e" % (
+            body, near.sum(), (dE / A).max(), (dE / bound).max(), (S / A).max()), flush=True)
+        assert np.all(dE <= bound)
+        _, inf_near = run_oracle(cfg, rx=rx[near], freqs=cfg["freqs"][:1])
+        np.testing.assert_array_equal(fg & 5, inf_near["flags"] & 5)
 
 
 @pytest.mark.parametrize("precision", [1, 0])
@@ -311,8 +349,8 @@ def test_cylinder_height_limits(precision):
     heights from 0 to 3 m: creeping and reflected paths switch on and off as
     their attachment or reflection heights cross the lateral surface's ends
     (the height cull and the exact height tests decide).  Against the oracle
-    at the usual tolerances; flags equal; the sweep must cross at least one
-    such switch (checked on the oracle's per-path validity)."""
+    at the usual tolerances with equal decisions; the sweep must cross at
+    least one such switch (checked on the oracle's per-path validity)."""
     sc = W.empty_scene()
     sc["cylinders"] = np.array([[0.0, 0.0, 0.0, 1.7, 0.5]], np.float32)
     cfg = dict(name="cylinder-heights", scene=sc,
@@ -322,11 +360,6 @@ def test_cylinder_height_limits(precision):
     zs = np.linspace(0.0, 3.0, 301)
     rx = np.concatenate([np.stack([np.full(zs.size, -3.0), np.full(zs.size, y), zs], 1)
                          for y in (0.3, -0.6, 1.5)]).astype(np.float32)
-    Eg, fg = run_library(cfg, precision, rx=rx)
-    Eo, info = run_oracle(cfg, rx=rx)
-    valid = [np.asarray(rec["valid"]) for _, rec in info["paths"]]
+    res = parity(cfg, precision, rx=rx, name="cylinder height limits", r14_bound=R14[precision], max_mismatch=0)
+    valid = [np.asarray(rec["valid"]) for _, rec in res["info"]["paths"]]
     assert any(0 < v.sum() < v.size for v in valid)
-    np.testing.assert_array_equal(fg & 5, info["flags"] & 5)
-    err = normwise(Eg, Eo)
-    _report("cylinder height limits p%d" % precision, err)
-    assert np.all(err <= TOL[precision])
