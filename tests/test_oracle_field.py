@@ -369,6 +369,65 @@ def test_reflection_spreading_against_ray_tube(body):
     np.testing.assert_allclose(df2, rho1 * rho2 / ((rho1 + s) * (rho2 + s)), rtol=1e-5)
 
 
+def _helix_length(T, cyl, P, side, ell):
+    r = geometry.cylinder_creeping(T, cyl, np.atleast_2d(P), side, ell)
+    return (r["s_i"] + r["t"] + r["s_d"])[0]
+
+
+@pytest.mark.parametrize("R,side,ell", [((-2.5, 1.0, 0.3), -1, 0), ((-2.5, -1.2, 0.3), 1, 0),
+                                        ((-1.0, -2.7, -0.5), 1, 1), ((0.4, 2.2, 3.3), -1, 0)])
+def test_cylinder_creeping_spreading_against_wavefronts(R, side, ell):
+    """The helical creeping spreading S^2 = (deta1/deta2) rho^d/(s^d (rho^d + s^d))
+    (Eq. (4) on an obliquely illuminated cylinder) against the curvatures of
+    the wavefronts of the path-length function psi = s^i + t + s^d, taken by
+    finite differences (psi itself is pinned by the brute-force shortest
+    path):
+    * in space at R, the Hessian of psi across the shed ray has the
+      eigenvalues 1/s^d (the caustic of the shed rays on the surface) and
+      1/(s^d + rho^d) (the second caustic, rho^d behind Q2);
+    * on the surface, psi's second derivative across the surface ray is
+      1/D, D the distance to the virtual source of the surface-ray fan, and
+      deta1/deta2 = D(Q1)/D(Q2).
+    A dropped t (rho^d = s^i, or deta ratio 1) fails both."""
+    T = np.array([3.0, 0.4, 2.1])
+    cyl = (0.0, 0.0, -1.0, 5.0, 0.6)
+    R = np.array(R)
+    rec = geometry.cylinder_creeping(T, cyl, R[None, :], side, ell)
+    assert rec["valid"][0] and abs(R[2] - T[2]) > 1.0
+    sI, t, sD = rec["s_i"][0], rec["t"][0], rec["s_d"][0]
+    h = 1e-4
+    E = np.eye(3)
+    f = lambda P: _helix_length(T, cyl, P, side, ell)
+    g = np.array([(f(R + h * E[i]) - f(R - h * E[i])) / (2 * h) for i in range(3)])
+    H = np.array([[(f(R + h * E[i] + h * E[j]) - f(R + h * E[i] - h * E[j]) - f(R - h * E[i] + h * E[j])
+                    + f(R - h * E[i] - h * E[j])) / (4 * h * h) for j in range(3)] for i in range(3)])
+    u = g / np.linalg.norm(g)
+    Pj = np.eye(3) - np.outer(u, u)
+    lam = np.sort(np.linalg.eigvalsh(Pj @ H @ Pj))[1:]
+    np.testing.assert_allclose(lam[1], 1.0 / sD, rtol=1e-5)
+    rho_fd = 1.0 / lam[0] - sD
+    np.testing.assert_allclose(rho_fd, sI + t, rtol=1e-5)
+    assert abs(rho_fd - sI) > 1e-2 * sI
+
+    def surface_radius(Q, tv, l):
+        # psi on the surface along the surface direction normal to the ray
+        a = cyl[4]
+        th = np.arctan2(Q[1] - cyl[1], Q[0] - cyl[0])
+        circ = np.array([-np.sin(th), np.cos(th), 0.0])
+        bc, bz = -tv[2], tv @ circ
+        hh = 1e-3
+        v = [_helix_length(T, cyl, np.array([cyl[0] + a * np.cos(th + k * hh * bc / a),
+                                              cyl[1] + a * np.sin(th + k * hh * bc / a), Q[2] + k * hh * bz]),
+                           side, l) for k in (-1, 0, 1)]
+        return hh * hh / (v[0] - 2 * v[1] + v[2])
+
+    D1 = surface_radius(rec["Q1"][0], rec["t1"][0], 0)      # the surface wave just after attachment
+    D2 = surface_radius(rec["Q2"][0], rec["t2"][0], ell)
+    np.testing.assert_allclose([D1, D2], [sI, sI + t], rtol=1e-6)
+    S2_fd = (D1 / D2) * rho_fd / (sD * (rho_fd + sD))
+    np.testing.assert_allclose(abs(rec["S"][0]) ** 2, S2_fd, rtol=1e-5)
+
+
 # ---------------------------------------------------------------------------
 # occlusion
 # ---------------------------------------------------------------------------
