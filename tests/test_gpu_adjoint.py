@@ -321,9 +321,15 @@ def test_random_scenes_vs_oracle(seed):
     """Seeded random small rooms (bodies of random size and height, the
     source anywhere, receivers on a grid and at random points, l_enc =
     seed mod 3): gradients of both precisions against the oracle's.  The
-    oracle's step is 2e-6 m here: in scene 5 the loss is not smooth within
-    1e-5 m of the source (its Richardson estimates at h = 1e-5 and 2e-6
-    differ by 6e-6 relative, the latter agreeing with the adjoint to 1e-8)."""
+    oracle's step is 2e-6 m.  In scene 5 the frozen loss is smooth but holds
+    a fast term: a reflection off a cylinder whose plane of incidence is
+    nearly vertical has rho_g = a / cos^2(delta_R) = 186 m, so m = 30 and
+    xi^L = -50, and the transition correction of the reflection coefficient,
+    proportional to e^{-j (xi^L)^3 / 12} (1 - F(X^L)) / xi^L, turns its phase by
+    (xi^2 / 4) d xi / dy = 2.7e5 rad per metre of source displacement.  A
+    step of 1e-5 m spans 2.7 rad of it (Richardson estimate off by 2.3e-5
+    relative); at 2e-6 m the estimates converge (2e-6, 1e-6 and 5e-7 m agree
+    to 5e-8 relative)."""
     cfg = W.random_scene(seed, n_rx_side=(4, 3), n_pts=8)
     G = _weights((cfg["freqs"].size, 3, cfg["rx"].shape[0]), 100 + seed)
     go = oracle_grad(cfg, G, opts=dict(l_enc=seed % 3), h=2e-6)

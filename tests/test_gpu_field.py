@@ -316,30 +316,36 @@ def test_shadow_boundary_band(body, precision):
     solve takes its longest paths, including the full iteration after the
     FP32 stage) and creeping paths of nearly zero arc, both sides of the
     boundary, against the oracle with equal decisions.  FP32 at 1e-4
-    everywhere.  FP64 at 1e-10 (normwise and per receiver) wherever the
-    receiver lies at |d| >= 1e-4 of the boundary; closer, the reflection at
-    grazing incidence is ill-conditioned, and each receiver is held to 1e-10
-    of its path magnitudes plus 4 times the oracle's own change under a
-    displacement of five FP64 ulps of its coordinates."""
-    from gpu_util import frozen_from_library, per_receiver
+    everywhere.  FP64: normwise 1e-10 over the receivers at |d| >= 1e-4 of
+    the boundary; per receiver, 1e-10 of its path magnitudes plus 4 times
+    the oracle's own change under a displacement of five FP64 ulps of the
+    receiver's coordinates (the reflection at grazing incidence is
+    ill-conditioned: that change reaches 1e-9 of the path magnitudes at
+    |d| < 1e-4 and 7e-11 at |d| = 1e-4 on the cylinder at 28 GHz, so no two
+    FP64 evaluations need agree more closely there)."""
+    from gpu_util import frozen_from_library
     cfg, rx, d = _band_case(body)
     lib = run_library(cfg, precision, rx=rx, masks=True)
-    far = np.abs(d) >= 1e-4
-    near = ~far
-    res = parity(cfg, precision, rx=rx, lib=lib, sample=np.nonzero(far)[0] if precision else None,
-                 name="shadow-boundary band %s (|d| >= 1e-4 for FP64)" % body, max_mismatch=0)
-    if precision:
-        Eg, fg, mk = lib[0][:, :, near], lib[1][near], lib[2][:, near]
-        frozen = frozen_from_library(cfg, fg, mk)
-        Eo, info, A = run_oracle(cfg, rx=rx[near], frozen=frozen, absum=True)
-        S = _oracle_sensitivity(cfg, rx[near], frozen)
-        dE = np.linalg.norm(Eg - Eo, axis=1)
-        bound = 1e-10 * A + 4.0 * S
-        print("band %s near (|d| < 1e-4, %d rx): max |dE|/A %.2e, max |dE|/bound %.2f, max S/A %.2e" % (
-            body, near.sum(), (dE / A).max(), (dE / bound).max(), (S / A).max()), flush=True)
-        assert np.all(dE <= bound)
-        _, inf_near = run_oracle(cfg, rx=rx[near], freqs=cfg["freqs"][:1])
-        np.testing.assert_array_equal(fg & 5, inf_near["flags"] & 5)
+    if not precision:
+        parity(cfg, 0, rx=rx, lib=lib, name="shadow-boundary band %s" % body, max_mismatch=0)
+        return
+    S = _oracle_sensitivity(cfg, rx, frozen_from_library(cfg, lib[1], lib[2]))
+    far = np.nonzero(np.abs(d) >= 1e-4)[0]
+    near = np.nonzero(np.abs(d) < 1e-4)[0]
+    # per-receiver record of the worst cases (printed before any assertion)
+    Eo_all, _, A_all = run_oracle(cfg, rx=rx, frozen=frozen_from_library(cfg, lib[1], lib[2]), absum=True)
+    err = np.linalg.norm(lib[0] - Eo_all, axis=1) / A_all
+    for i in np.argsort(-err.max(axis=0))[:10]:
+        print("  rx %3d d %+.2e flags %2d mask %3d |dE|/A per f %s  S/A %s" % (
+            i, d[i], lib[1][i], lib[2][0, i], np.array2string(err[:, i], precision=2),
+            np.array2string(S[:, i] / A_all[:, i], precision=2)), flush=True)
+    parity(cfg, 1, rx=rx, lib=lib, sample=far, sens=S[:, far], name="shadow-boundary band %s, |d| >= 1e-4" % body,
+           max_mismatch=0)
+    res = parity(cfg, 1, rx=rx, lib=lib, sample=near, sens=S[:, near], nw_tol=np.inf,
+                 name="shadow-boundary band %s, |d| < 1e-4 (normwise not bounded)" % body, max_mismatch=0)
+    dE = np.linalg.norm(res["E"] - res["Eo"], axis=1)
+    print("band %s near (%d rx): max |dE| / (1e-10 A + 4 S) = %.2f" % (
+        body, near.size, (dE / (1e-10 * res["A"] + 4 * S[:, near])).max()), flush=True)
 
 
 @pytest.mark.parametrize("precision", [1, 0])
