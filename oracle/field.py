@@ -30,7 +30,7 @@ the oracle use it.
 """
 import numpy as np
 
-from . import fock, geometry, occlusion
+from . import fock, geometry, occlusion, walls
 
 C0 = 299792458.0
 
@@ -40,7 +40,7 @@ FLAG_LOS = 4
 
 
 def _opts(opts):
-    o = dict(l_enc=0, bodies_occlude=True, lit_branch=True, caustic_guard=1e-6)
+    o = dict(l_enc=0, bodies_occlude=True, lit_branch=True, caustic_guard=1e-6, walls=None)
     if opts:
         o.update(opts)
     return o
@@ -126,7 +126,18 @@ def _classify(scene, T, R, opts, visibility=True):
                     valid[idx[blk]] = False
             rec["valid"] = valid
             paths.append(((kind, i) + key, rec))
-    return dict(los=los, inside=inside, flags=flags, paths=paths, n=n)
+    wall_paths = []
+    if o["walls"] is not None:
+        # one specular bounce on the scene's planes, alone and feeding the bodies
+        wall_paths = walls.classify(sc, T, R, inside, o, visibility)
+        for key, rec in wall_paths:
+            if "caustic" in rec:
+                flags |= np.where(rec["caustic"], FLAG_CAUSTIC, 0).astype(np.uint8)
+    return dict(los=los, inside=inside, flags=flags, paths=paths, walls=wall_paths, n=n)
+
+
+def n_rx_frozen(frozen):
+    return np.asarray(frozen["los"]).shape[0]
 
 
 def _incident(T, P, dipole, amp, k):
@@ -163,6 +174,9 @@ def field(scene, tx, rx, freqs, opts=None, mode="em", frozen=None, return_info=F
         fz = dict(frozen["paths"])
         for key, rec in info["paths"]:
             rec["valid"] = fz[key]["valid"]
+        fw = dict(frozen.get("walls", []))
+        for key, rec in info["walls"]:
+            rec["valid"] = fw[key]["valid"] if key in fw else np.zeros(n_rx_frozen(frozen), bool)
     n = R.shape[0]
     scalar = mode in ("soft", "hard")
     out = np.zeros((freqs.size, n) if scalar else (freqs.size, 3, n), dtype=complex)
@@ -193,6 +207,15 @@ def field(scene, tx, rx, freqs, opts=None, mode="em", frozen=None, return_info=F
             if return_abs:
                 acc += part
                 absum[fi] += np.abs(part) if scalar else np.linalg.norm(part, axis=0)
+        if info["walls"]:
+            if scalar:
+                raise ValueError("wall reflections need mode 'em'")
+            for key, rec in info["walls"]:
+                part = np.zeros_like(acc) if return_abs else acc
+                walls.add_field(part, [(key, rec)], T, dip, amp, f, o["walls"], mode)
+                if return_abs:
+                    acc += part
+                    absum[fi] += np.linalg.norm(part, axis=0)
     res = (out,)
     if return_info:
         res += (info,)
@@ -206,7 +229,11 @@ def _take(rec, name, idx):
     return v[idx] if np.ndim(v) > 0 else np.full(idx.shape, v)
 
 
-def _add_creeping(acc, rec, idx, T, dip, amp, k, mode):
+def _add_creeping(acc, rec, idx, T, dip, amp, k, mode, inc=None):
+    """Adds the creeping field of the paths idx of rec into acc.  ``inc``:
+    the amplitude-weighted incident polarisation vectors at Q1 when the
+    wave arriving there is not the source's own (a wall reflection); the
+    record's s_i is then the distance from the equivalent (image) source."""
     rho_g = _take(rec, "rho_g", idx)
     sI, t, sD = _take(rec, "s_i", idx), _take(rec, "t", idx), _take(rec, "s_d", idx)
     m = (k * rho_g / 2) ** (1.0 / 3.0)
@@ -223,15 +250,19 @@ def _add_creeping(acc, rec, idx, T, dip, amp, k, mode):
         return
     Ts = pref * fock.shadow_B(xi, X, q, False)
     Th = pref * fock.shadow_B(xi, X, q, True)
-    Q1 = rec["Q1"][idx]
-    pp, s = _incident(T, Q1, dip, amp, k)
+    if inc is None:
+        pp, s = _incident(T, rec["Q1"][idx], dip, amp, k)
+    else:
+        pp = inc
     es = np.einsum("ij,ij->i", pp, rec["b1"][idx]) * Ts
     eh = np.einsum("ij,ij->i", pp, rec["n1"][idx]) * Th
     common = S * phase / sI
     acc[:, idx] += ((es * common)[:, None] * rec["b2"][idx] + (eh * common)[:, None] * rec["n2"][idx]).T
 
 
-def _add_reflection(acc, rec, idx, T, dip, amp, k, mode):
+def _add_reflection(acc, rec, idx, T, dip, amp, k, mode, inc=None):
+    """Adds the reflected field of the paths idx of rec into acc (``inc`` as
+    for _add_creeping, at the reflection point)."""
     rho_g = rec["rho_g"][idx]
     cos_i = rec["cos_i"][idx]
     sI, sR = rec["s_i"][idx], rec["s_r"][idx]
@@ -251,7 +282,10 @@ def _add_reflection(acc, rec, idx, T, dip, amp, k, mode):
         return
     Rs = fock.lit_Rbar(xi, X, q, False)
     Rh = fock.lit_Rbar(xi, X, q, True)
-    pp, s = _incident(T, rec["Q"][idx], dip, amp, k)
+    if inc is None:
+        pp, s = _incident(T, rec["Q"][idx], dip, amp, k)
+    else:
+        pp = inc
     es = np.einsum("ij,ij->i", pp, rec["eperp"][idx]) * Rs
     eh = np.einsum("ij,ij->i", pp, rec["epar_i"][idx]) * Rh
     common = spread * phase / sI
