@@ -188,7 +188,10 @@ def classify(scene, T, R, inside, opts, visibility=True):
     basis, the body record (from the image source, or to the image
     receiver) and the validity after the visibility tests (skipped with
     visibility=False).  The wall-only path tests every body, like the direct
-    ray; the other paths' legs test the other bodies when bodies_occlude."""
+    ray; the other paths' legs test the other bodies when bodies_occlude.
+    Wall-fed body paths take the primary creeping paths (no encirclements).
+    With lit_branch off (creeping fields only) the wall-only path and the
+    body reflections are left out, as the direct ray is."""
     tri = scene.get("tri")
     if tri is None or len(tri) == 0:
         return []
@@ -217,7 +220,7 @@ def classify(scene, T, R, inside, opts, visibility=True):
         Tib = np.broadcast_to(Ti, R.shape)
         # wall only: the image source's ray T' -> R crosses the plane on the reflector
         Qw, ok = crossing(Tib, R, n, d)
-        ok &= ~inside
+        ok &= ~inside & bool(opts["lit_branch"])
         ok[ok] = on_reflector(tri, rf, Qw[ok])
         ok = gate(ok, [(Tb, Qw, None), (Qw, R, None)], True)
         s_in = _unit(Qw - Tb)
@@ -230,14 +233,12 @@ def classify(scene, T, R, inside, opts, visibility=True):
                 src, rcv = (Ti, R) if first == "wb" else (T, Ri)
                 if kind == "s":
                     C, a = b[:3], b[3]
-                    recs = [(("c", s, l), geometry.sphere_creeping(src, C, a, rcv, s, l))
-                            for s in (+1, -1) for l in range(opts["l_enc"] + 1)]
+                    recs = [(("c", s, 0), geometry.sphere_creeping(src, C, a, rcv, s, 0)) for s in (+1, -1)]
                     if opts["lit_branch"]:
                         recs.append((("r",), geometry.sphere_reflection(src, C, a, rcv)))
                 else:
                     plan = geometry.cylinder_plan(src, b, rcv)
-                    recs = [(("c", s, l), geometry.cylinder_creeping(src, b, rcv, s, l, plan))
-                            for s in (+1, -1) for l in range(opts["l_enc"] + 1)]
+                    recs = [(("c", s, 0), geometry.cylinder_creeping(src, b, rcv, s, 0, plan)) for s in (+1, -1)]
                     if opts["lit_branch"]:
                         recs.append((("r",), geometry.cylinder_reflection(src, b, rcv, plan)))
                 for pkey, rec in recs:
