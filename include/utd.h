@@ -214,6 +214,23 @@ utd_status utd_smooth_field_batched(const utd_scene *scene, int64_t n_frames,
  * other values. */
 utd_status utd_batched_config(int tile_rx, int blocks_per_cu);
 
+/* Allocation-free variant of utd_smooth_field, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, results and errors as
+ * utd_smooth_field; it calls no allocating routine.  Its scratch (path
+ * masks and records, the candidate queue, body and frequency constants) is
+ * one static device array of 256 MiB per device, which every call on that
+ * device shares and which the device keeps until the process ends: calls
+ * that overlap on one device (several streams or host threads at once)
+ * race.  A call whose scratch would exceed 256 MiB returns UTD_E_ARG and
+ * enqueues nothing (with l_enc = 0 the FP32 path takes about 460 bytes per
+ * (receiver, body) pair plus 72 per receiver: 65 536 receivers with one
+ * sphere fit, and so do 16 384 receivers with 32 bodies). */
+utd_status utd_smooth_field_noalloc(const utd_scene *scene, const utd_bodies *bodies,
+                                    const utd_source *tx, const float *rx, int64_t n_rx,
+                                    const double *freqs_hz, int n_f, const utd_options *opt,
+                                    void *E_out, uint8_t *rx_flags, void *stream);
+
 /* Path census (reporting): runs the classification and visibility stage of
  * utd_smooth_field for the same inputs and writes, to the host array
  * counts[10], the number of (receiver, body) pairs with each mask bit set --

@@ -21,7 +21,7 @@ BAD_RX, BAD_BODY, BAD_FREQ = 1, 2, 4
 EXPORTS = ["utd_default_options", "utd_scene_create", "utd_scene_destroy", "utd_scene_triangles",
            "utd_scene_nodes", "utd_smooth_field", "utd_smooth_field_backward", "utd_smooth_field_batched",
            "utd_path_census", "utd_batched_config", "utd_profile_enable", "utd_profile_read", "utd_last_error",
-           "utd_path_masks", "utd_input_status"]
+           "utd_path_masks", "utd_input_status", "utd_smooth_field_noalloc"]
 KERNELS = ["prep", "occlude", "field", "backward", "reduce", "batched"]
 
 
@@ -69,6 +69,8 @@ def load_library(path=LIB_PATH):
     lib.utd_smooth_field.argtypes = [vp, ctypes.POINTER(Bodies), ctypes.POINTER(Source), vp, i64, vp, i32,
                                      ctypes.POINTER(Options), vp, vp, vp]
     lib.utd_smooth_field.restype = i32
+    lib.utd_smooth_field_noalloc.argtypes = lib.utd_smooth_field.argtypes
+    lib.utd_smooth_field_noalloc.restype = i32
     lib.utd_smooth_field_backward.argtypes = [vp, ctypes.POINTER(Bodies), ctypes.POINTER(Source), vp, i64, vp, i32,
                                               ctypes.POINTER(Options), vp, vp, vp, vp, vp]
     lib.utd_smooth_field_backward.restype = i32
@@ -195,14 +197,17 @@ def _stream(stream):
 
 
 def smooth_field(scene, spheres, cylinders, source, rx, freqs, precision=0, l_enc=0, bodies_occlude=True,
-                 lit_branch=True, caustic_guard=1e-6, out=None, flags=None, stream=None):
+                 lit_branch=True, caustic_guard=1e-6, out=None, flags=None, stream=None, noalloc=False):
     """E[f, c, n] (complex64 for precision 0, complex128 for 1) and flags[n].
 
     spheres [ns, 4], cylinders [nc, 5], rx [n, 3]: float32 GPU tensors;
     freqs [nf]: float64 GPU tensor; source: a ``Source`` (``make_source``).
+    ``noalloc``: call utd_smooth_field_noalloc (the library's static scratch;
+    pass ``out`` and ``flags`` to keep the call free of allocations).
     """
     torch = _torch()
     lib = load_library()
+    fn = lib.utd_smooth_field_noalloc if noalloc else lib.utd_smooth_field
     _dev(rx, torch.float32, (3,), "rx")
     _dev(freqs, torch.float64, None, "freqs")
     b, keep = _bodies(spheres, cylinders)
@@ -213,7 +218,7 @@ def smooth_field(scene, spheres, cylinders, source, rx, freqs, precision=0, l_en
     if flags is None:
         flags = torch.empty((n,), dtype=torch.uint8, device=rx.device)
     opt = make_options(precision, l_enc, bodies_occlude, lit_branch, caustic_guard)
-    _check(lib.utd_smooth_field(scene.handle if scene is not None else None, ctypes.byref(b), ctypes.byref(source),
+    _check(fn(scene.handle if scene is not None else None, ctypes.byref(b), ctypes.byref(source),
                                 rx.data_ptr() if n else None, n, freqs.data_ptr() if nf else None, nf,
                                 ctypes.byref(opt), out.data_ptr() if out.numel() else None,
                                 flags.data_ptr() if n else None, _stream(stream)))

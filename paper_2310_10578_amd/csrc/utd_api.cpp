@@ -165,26 +165,44 @@ struct Workspace {
     uint64_t* vis = nullptr;                  // queue positions of the visible paths
     int64_t cap = 0;
     char* extra = nullptr;
-    hipError_t alloc(int nb, int64_t n_rx, int n_f, int l_enc, int precision, bool need_flags, hipStream_t s,
-                     size_t extra_bytes = 0) {
+    bool with_flags = false, with_extra = false;
+    size_t o_prep = 0, o_fc = 0, o_mask = 0, o_rec = 0, o_flag = 0, o_cnt = 0, o_ent = 0, o_th = 0, o_vis = 0,
+           o_extra = 0;
+    // Byte offsets of every part; returns the total size.
+    size_t plan(int nb, int64_t n_rx, int n_f, int l_enc, int precision, bool need_flags, size_t extra_bytes = 0) {
         auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
         size_t nbb = (size_t)(nb > 0 ? nb : 1);
         size_t slots = (size_t)(2 * (l_enc + 1) + 1);
         cap = n_rx * (1 + (int64_t)nb * (int64_t)slots);
-        size_t o_prep = 0;
-        size_t o_fc = up(o_prep + sizeof(utd::BodyPrep) * nbb);
-        size_t o_mask = up(o_fc + sizeof(utd::FreqConst) * (size_t)(n_f > 0 ? n_f : 1));
-        size_t o_rec = up(o_mask + (size_t)n_rx * nbb + 4);
+        o_prep = 0;
+        o_fc = up(o_prep + sizeof(utd::BodyPrep) * nbb);
+        o_mask = up(o_fc + sizeof(utd::FreqConst) * (size_t)(n_f > 0 ? n_f : 1));
+        o_rec = up(o_mask + (size_t)n_rx * nbb + 4);
         size_t rec_bytes = utd::path_record_bytes(precision) * slots * (size_t)n_rx * nbb;
-        size_t o_flag = up(o_rec + rec_bytes);
-        size_t o_cnt = up(o_flag + (need_flags ? (size_t)n_rx : 0));
-        size_t o_ent = up(o_cnt + 16 * sizeof(unsigned long long));
-        size_t o_th = up(o_ent + sizeof(uint64_t) * (size_t)cap);
-        size_t o_vis = up(o_th + sizeof(double) * (size_t)cap);
-        size_t o_extra = up(o_vis + sizeof(uint64_t) * (size_t)cap);
-        size_t total = o_extra + extra_bytes;
-        hipError_t e = ws_get(total, s, &base);
+        o_flag = up(o_rec + rec_bytes);
+        o_cnt = up(o_flag + (need_flags ? (size_t)n_rx : 0));
+        o_ent = up(o_cnt + 16 * sizeof(unsigned long long));
+        o_th = up(o_ent + sizeof(uint64_t) * (size_t)cap);
+        o_vis = up(o_th + sizeof(double) * (size_t)cap);
+        o_extra = up(o_vis + sizeof(uint64_t) * (size_t)cap);
+        with_flags = need_flags;
+        with_extra = extra_bytes > 0;
+        return o_extra + extra_bytes;
+    }
+    hipError_t alloc(int nb, int64_t n_rx, int n_f, int l_enc, int precision, bool need_flags, hipStream_t s,
+                     size_t extra_bytes = 0) {
+        size_t total = plan(nb, n_rx, n_f, l_enc, precision, need_flags, extra_bytes);
+        char* b = nullptr;
+        hipError_t e = ws_get(total, s, &b);
         if (e != hipSuccess) return e;
+        bind(b);
+        return hipSuccess;
+    }
+    // Points every part into the buffer at b (laid out by plan).
+    void bind(char* b) {
+        base = b;
+        const bool need_flags = with_flags;
+        const size_t extra_bytes = with_extra ? 1 : 0;
         prep = (utd::BodyPrep*)(base + o_prep);
         fc = (utd::FreqConst*)(base + o_fc);
         mask = (uint8_t*)(base + o_mask);
@@ -195,7 +213,6 @@ struct Workspace {
         ent_th = (double*)(base + o_th);
         vis = (uint64_t*)(base + o_vis);
         extra = extra_bytes ? base + o_extra : nullptr;
-        return hipSuccess;
     }
 };
 
@@ -329,6 +346,44 @@ utd_status utd_smooth_field(const utd_scene* scene, const utd_bodies* bodies, co
     if (e == hipSuccess) {
         ProfScope ps(UTD_K_FIELD, s);
         e = utd::launch_field(L, opt->precision, fc, rx, w.fc, w.mask, w.rec, flags, E_out, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return UTD_OK;
+}
+
+utd_status utd_smooth_field_noalloc(const utd_scene* scene, const utd_bodies* bodies, const utd_source* tx,
+                                    const float* rx, int64_t n_rx, const double* freqs, int n_f,
+                                    const utd_options* opt, void* E_out, uint8_t* rx_flags, void* stream) {
+    utd_status st = check_common(bodies, tx, rx, n_rx, freqs, n_f, opt);
+    if (st != UTD_OK) return st;
+    if (n_rx == 0 || n_f == 0) return UTD_OK;
+    if (!E_out) return fail(UTD_E_ARG, "E_out is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    utd::LaunchParams L = make_params(scene, bodies, tx, n_rx, n_f, opt);
+    int nb = L.n_sph + L.n_cyl;
+    Workspace w;
+    const size_t need = w.plan(nb, n_rx, n_f, opt->l_enc, opt->precision, rx_flags == nullptr);
+    if (need > utd::kNoAllocScratchBytes)
+        return fail(UTD_E_ARG,
+                    "this call needs %zu bytes of scratch; the allocation-free entry point has %zu (fewer "
+                    "receivers or bodies per call, or utd_smooth_field)",
+                    need, utd::kNoAllocScratchBytes);
+    char* p = nullptr;
+    hipError_t e = utd::noalloc_scratch(&p);
+    if (e != hipSuccess) return hip_fail(e, "static scratch address");
+    w.bind(p);
+    uint8_t* flags = rx_flags ? rx_flags : w.flags;
+    const float4* nodes = scene ? scene->d_nodes : nullptr;
+    const float4* tris = scene ? scene->d_tris : nullptr;
+    {
+        ProfScope ps(UTD_K_OCCLUDE, s);
+        e = utd::launch_paths(L, opt->precision, rx, bodies->sph, bodies->cyl, freqs, w.prep, w.fc, nodes, tris,
+                              w.mask, w.rec, flags, w.ent, w.ent_th, w.vis, w.counters + 12, w.cap, s);
+    }
+    if (e == hipSuccess) {
+        ProfScope ps(UTD_K_FIELD, s);
+        e = utd::launch_field(L, opt->precision, pick_fc(opt->precision, n_rx, n_f), rx, w.fc, w.mask, w.rec,
+                              flags, E_out, s);
     }
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return UTD_OK;

@@ -46,6 +46,12 @@ hipError_t launch_batch(const BatchParams& B, int precision, int n_blocks, const
                         unsigned* counter, const float4* nodes, const float4* tris, double* th, void* E,
                         uint8_t* flags, hipStream_t s);
 
+// Scratch of the allocation-free entry point: a static device array of
+// kNoAllocScratchBytes; noalloc_scratch gives its address on the current
+// device (taken once per device with hipGetSymbolAddress).
+constexpr size_t kNoAllocScratchBytes = (size_t)256 << 20;
+hipError_t noalloc_scratch(char** out);
+
 // Waits for the current device, then reads and clears its input-status bits.
 hipError_t read_input_status(unsigned* bits);
 

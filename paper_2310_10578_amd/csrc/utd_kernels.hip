@@ -20,6 +20,9 @@
 // in registers.  Frequency constants are uniform across the workgroup (scalar
 // loads).  The Fock tables sit in LDS (FP32) or global memory (FP64).
 #define FT_QUAL __device__ const __attribute__((aligned(16)))
+#include <map>
+#include <mutex>
+
 #include "utd_internal.h"
 #include "utd_bvh.h"
 #include "utd_fock.h"
@@ -839,6 +842,31 @@ __global__ void __launch_bounds__(256) k_census(int64_t n_mask, const uint8_t* _
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+// Scratch of utd_smooth_field_noalloc: every call on a device shares it
+// (calls that overlap on one device race).  Its device address comes from
+// hipGetSymbolAddress once per device, with that device current; host code
+// uses only that address, never the array's name.
+static __device__ __attribute__((aligned(256))) char scratch[kNoAllocScratchBytes];
+
+hipError_t noalloc_scratch(char** out) {
+    static std::mutex mu;
+    static std::map<int, char*> ptrs;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = ptrs.find(dev);
+    if (it == ptrs.end()) {
+        char* ptr = nullptr;
+        e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        it = ptrs.emplace(dev, ptr).first;
+    }
+    *out = it->second;
+    return hipSuccess;
+}
+
 hipError_t read_input_status(unsigned* bits) {
     hipError_t e = hipDeviceSynchronize();
     if (e == hipSuccess) e = hipMemcpyFromSymbol(bits, HIP_SYMBOL(g_input_status), sizeof(unsigned));
