@@ -87,7 +87,24 @@ typedef struct {
     double caustic_guard;   /* sphere creeping paths whose receiver lies closer
                                than this to the source axis are dropped and
                                flagged (m).  Default 1e-6.                     */
+    int wall_reflections;   /* 1: add one specular bounce on the scene's
+                               triangle planes -- the wall's own reflected ray
+                               and the body paths it feeds or that feed it
+                               (utd_scene_set_wall_material); forward calls
+                               only.  Default 0.                               */
 } utd_options;
+
+/* Wall material of a scene's reflecting planes: a homogeneous slab of
+ * relative permittivity eps_r (>= 1), conductivity sigma (S/m, >= 0) and
+ * thickness (m, > 0; INFINITY for a half-space), or, with perfect_conductor
+ * set, a perfect conductor (R_perp = -1, R_par = +1).  The default is 10 cm
+ * of brick with ITU-R P.2040's values: eps_r 3.75, sigma 0.038 S/m. */
+typedef struct {
+    double eps_r;
+    double sigma;
+    double thickness;
+    int perfect_conductor;
+} utd_wall_material;
 
 /* Bodies, device arrays of float32, row-major:
  *   sph[n_sph][4] = (cx, cy, cz, a)            sphere centre and radius
@@ -129,6 +146,19 @@ void utd_scene_destroy(utd_scene *scene);
 int64_t utd_scene_triangles(const utd_scene *scene);
 int64_t utd_scene_nodes(const utd_scene *scene);
 
+/* Reflecting planes of a scene (Eq. (3) applied to the walls, with the
+ * image-source construction of a planar mirror): all triangles lying in one
+ * plane n.x = d reflect as one mirror; a triangle's unit normal has its
+ * first component of magnitude > 1e-9 positive, triangles whose normals and
+ * offsets agree after rounding to multiples of 1e-6 share a plane, and the
+ * planes are ordered by those rounded values.  Returns their number; when
+ * out (host double [n][4]) is not NULL writes (n_x, n_y, n_z, d) of each. */
+int64_t utd_scene_planes(const utd_scene *scene, double *out);
+
+/* Sets the wall material of the scene's planes (see utd_wall_material).
+ * Errors: UTD_E_ARG for NULL or out-of-range values. */
+utd_status utd_scene_set_wall_material(utd_scene *scene, const utd_wall_material *mat);
+
 /* Forward field (Eqs. (1)-(4)).
  *   rx       device float32 [n_rx][3]  receiver positions
  *   freqs_hz device float64 [n_f]      frequencies (> 0)
@@ -143,6 +173,12 @@ int64_t utd_scene_nodes(const utd_scene *scene);
  * allocated stream-ordered and released at process exit; calls on one stream
  * are ordered by the stream, so issuing them from several host threads at
  * once is not supported.
+ * With opt->wall_reflections the receivers also get one specular bounce on
+ * the scene's planes (Eq. (3) for a planar slab, image source and image
+ * receiver): the wall's reflected ray (with the lit branch), and each body's
+ * two primary creeping paths and its reflection fed by the wall's image
+ * source (Fig. 1's equivalent source) or reaching the receiver through the
+ * wall, every leg tested for visibility.
  * Errors: UTD_E_ARG for NULL pointers with non-zero sizes, n_rx < 0, n_f < 0,
  * l_enc outside 0..2, precision outside {0, 1}; UTD_E_OOM when the scratch
  * cannot be allocated; UTD_E_DEVICE on launch failure. */
@@ -170,7 +206,8 @@ utd_status utd_smooth_field(const utd_scene *scene, const utd_bodies *bodies,
  * (bitwise reproducible).  Uses the per-stream scratch of
  * utd_smooth_field.
  * Errors as for utd_smooth_field; UTD_E_ARG if d_tx is NULL, d_cyl / d_sph is
- * NULL with a non-zero count, or grad_E is NULL with n_rx, n_f > 0. */
+ * NULL with a non-zero count, or grad_E is NULL with n_rx, n_f > 0;
+ * UTD_E_UNSUPPORTED with opt->wall_reflections. */
 utd_status utd_smooth_field_backward(const utd_scene *scene, const utd_bodies *bodies,
                                      const utd_source *tx, const float *rx, int64_t n_rx,
                                      const double *freqs_hz, int n_f, const utd_options *opt,
@@ -199,7 +236,8 @@ utd_status utd_smooth_field_backward(const utd_scene *scene, const utd_bodies *b
  * of at least this size).  Tile shape: utd_batched_config.  The library keeps
  * one workspace per device: concurrent batched calls on one device race.
  * Errors as for utd_smooth_field; UTD_E_ARG for n_frames < 0, n_cyl < 0, NULL
- * offsets with n_frames, n_rx, n_f > 0, or a capture without workspace. */
+ * offsets with n_frames, n_rx, n_f > 0, or a capture without workspace;
+ * UTD_E_UNSUPPORTED with opt->wall_reflections. */
 utd_status utd_smooth_field_batched(const utd_scene *scene, int64_t n_frames,
                                     const int64_t *body_off, const float *cyl, int64_t n_cyl,
                                     const int64_t *rx_off, const float *rx, int64_t n_rx,
@@ -262,6 +300,20 @@ utd_status utd_path_masks(const utd_scene *scene, const utd_bodies *bodies, cons
                           const float *rx, int64_t n_rx, const utd_options *opt, uint8_t *mask_out,
                           uint8_t *rx_flags, void *stream);
 
+/* Wall-bounce decisions of utd_smooth_field with wall reflections for the
+ * same inputs: for every (receiver, plane) a 64-bit word, device uint64
+ * [n_rx][n_planes] (planes as utd_scene_planes orders them): bit 0 the
+ * wall's own reflected ray visible; for body b (spheres first, then
+ * cylinders) bits 1 + 6 b + k: k = 0, 1 the creeping path of side + / - fed
+ * by the wall, 2 the body reflection fed by the wall, 3, 4 the creeping path
+ * of side + / - reaching the receiver through the wall, 5 the body
+ * reflection reaching it through the wall.  Asynchronous on `stream`.
+ * Errors as for utd_smooth_field; UTD_E_UNSUPPORTED for more than 10 bodies;
+ * UTD_E_ARG if mask_out is NULL with planes and receivers. */
+utd_status utd_wall_masks(const utd_scene *scene, const utd_bodies *bodies, const utd_source *tx,
+                          const float *rx, int64_t n_rx, const utd_options *opt, uint64_t *mask_out,
+                          void *stream);
+
 /* Device input status: waits for the current device, writes to *bits the OR
  * of the UTD_BAD_* bits raised by every call on this device since the last
  * read (invalid receivers, bodies or frequencies found by the kernels), and
@@ -282,7 +334,8 @@ utd_status utd_input_status(uint32_t *bits);
 #define UTD_K_BACKWARD 3
 #define UTD_K_REDUCE 4
 #define UTD_K_BATCHED 5
-#define UTD_K_COUNT 6
+#define UTD_K_WALLS 6
+#define UTD_K_COUNT 7
 void utd_profile_enable(int on);
 utd_status utd_profile_read(double *ms, int64_t *count);
 

@@ -21,13 +21,19 @@ BAD_RX, BAD_BODY, BAD_FREQ = 1, 2, 4
 EXPORTS = ["utd_default_options", "utd_scene_create", "utd_scene_destroy", "utd_scene_triangles",
            "utd_scene_nodes", "utd_smooth_field", "utd_smooth_field_backward", "utd_smooth_field_batched",
            "utd_path_census", "utd_batched_config", "utd_profile_enable", "utd_profile_read", "utd_last_error",
-           "utd_path_masks", "utd_input_status", "utd_smooth_field_noalloc"]
-KERNELS = ["prep", "occlude", "field", "backward", "reduce", "batched"]
+           "utd_path_masks", "utd_input_status", "utd_smooth_field_noalloc", "utd_scene_planes",
+           "utd_scene_set_wall_material", "utd_wall_masks"]
+KERNELS = ["prep", "occlude", "field", "backward", "reduce", "batched", "walls"]
 
 
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("l_enc", ctypes.c_int), ("bodies_occlude", ctypes.c_int),
-                ("lit_branch", ctypes.c_int), ("caustic_guard", ctypes.c_double)]
+                ("lit_branch", ctypes.c_int), ("caustic_guard", ctypes.c_double), ("wall_reflections", ctypes.c_int)]
+
+
+class WallMaterial(ctypes.Structure):
+    _fields_ = [("eps_r", ctypes.c_double), ("sigma", ctypes.c_double), ("thickness", ctypes.c_double),
+                ("perfect_conductor", ctypes.c_int)]
 
 
 class Bodies(ctypes.Structure):
@@ -87,6 +93,13 @@ def load_library(path=LIB_PATH):
     lib.utd_path_masks.restype = i32
     lib.utd_input_status.argtypes = [vp]
     lib.utd_input_status.restype = i32
+    lib.utd_scene_planes.argtypes = [vp, vp]
+    lib.utd_scene_planes.restype = i64
+    lib.utd_scene_set_wall_material.argtypes = [vp, ctypes.POINTER(WallMaterial)]
+    lib.utd_scene_set_wall_material.restype = i32
+    lib.utd_wall_masks.argtypes = [vp, ctypes.POINTER(Bodies), ctypes.POINTER(Source), vp, i64,
+                                   ctypes.POINTER(Options), vp, vp]
+    lib.utd_wall_masks.restype = i32
     lib.utd_profile_enable.argtypes = [i32]
     lib.utd_profile_enable.restype = None
     lib.utd_profile_read.argtypes = [vp, vp]
@@ -128,12 +141,14 @@ def _dev(t, dtype, shape_tail, name):
     return t
 
 
-def make_options(precision=0, l_enc=0, bodies_occlude=True, lit_branch=True, caustic_guard=1e-6):
+def make_options(precision=0, l_enc=0, bodies_occlude=True, lit_branch=True, caustic_guard=1e-6,
+                 wall_reflections=False):
     o = Options()
     load_library().utd_default_options(ctypes.byref(o))
     o.precision, o.l_enc = int(precision), int(l_enc)
     o.bodies_occlude, o.lit_branch = int(bool(bodies_occlude)), int(bool(lit_branch))
     o.caustic_guard = float(caustic_guard)
+    o.wall_reflections = int(bool(wall_reflections))
     return o
 
 
@@ -166,6 +181,20 @@ class Scene:
     def handle(self):
         return self._h
 
+    def planes(self):
+        """Reflecting planes: float64 array [n, 4] of (n_x, n_y, n_z, d)."""
+        import numpy as np
+        lib = load_library()
+        n = int(lib.utd_scene_planes(self._h, None))
+        out = np.zeros((n, 4), np.float64)
+        if n:
+            lib.utd_scene_planes(self._h, out.ctypes.data)
+        return out
+
+    def set_wall_material(self, eps_r=3.75, sigma=0.038, thickness=0.10, perfect_conductor=False):
+        m = WallMaterial(float(eps_r), float(sigma), float(thickness), int(bool(perfect_conductor)))
+        _check(load_library().utd_scene_set_wall_material(self._h, ctypes.byref(m)))
+
     def close(self):
         if self._h:
             load_library().utd_scene_destroy(self._h)
@@ -197,7 +226,8 @@ def _stream(stream):
 
 
 def smooth_field(scene, spheres, cylinders, source, rx, freqs, precision=0, l_enc=0, bodies_occlude=True,
-                 lit_branch=True, caustic_guard=1e-6, out=None, flags=None, stream=None, noalloc=False):
+                 lit_branch=True, caustic_guard=1e-6, out=None, flags=None, stream=None, noalloc=False,
+                 wall_reflections=False):
     """E[f, c, n] (complex64 for precision 0, complex128 for 1) and flags[n].
 
     spheres [ns, 4], cylinders [nc, 5], rx [n, 3]: float32 GPU tensors;
@@ -217,7 +247,7 @@ def smooth_field(scene, spheres, cylinders, source, rx, freqs, precision=0, l_en
         out = torch.empty((nf, 3, n), dtype=cdt, device=rx.device)
     if flags is None:
         flags = torch.empty((n,), dtype=torch.uint8, device=rx.device)
-    opt = make_options(precision, l_enc, bodies_occlude, lit_branch, caustic_guard)
+    opt = make_options(precision, l_enc, bodies_occlude, lit_branch, caustic_guard, wall_reflections)
     _check(fn(scene.handle if scene is not None else None, ctypes.byref(b), ctypes.byref(source),
                                 rx.data_ptr() if n else None, n, freqs.data_ptr() if nf else None, nf,
                                 ctypes.byref(opt), out.data_ptr() if out.numel() else None,
@@ -388,3 +418,23 @@ def input_status():
     v = ctypes.c_uint32(0)
     _check(load_library().utd_input_status(ctypes.cast(ctypes.pointer(v), ctypes.c_void_p)))
     return int(v.value)
+
+
+def wall_masks(scene, spheres, cylinders, source, rx, precision=0, l_enc=0, bodies_occlude=True, lit_branch=True,
+               caustic_guard=1e-6, stream=None):
+    """Wall-bounce decisions of ``smooth_field(..., wall_reflections=True)``:
+    uint64 words [n_rx, n_planes] as a GPU int64 tensor (bit 0 the wall's
+    own ray; body b bits 1 + 6 b + k, k = 0/1 wall then creeping side +/-, 2
+    wall then reflection, 3/4 creeping then wall, 5 reflection then wall)."""
+    torch = _torch()
+    lib = load_library()
+    _dev(rx, torch.float32, (3,), "rx")
+    b, keep = _bodies(spheres, cylinders)
+    n = rx.shape[0]
+    n_planes = int(lib.utd_scene_planes(scene.handle, None)) if scene is not None else 0
+    out = torch.zeros((n, n_planes), dtype=torch.int64, device=rx.device)
+    opt = make_options(precision, l_enc, bodies_occlude, lit_branch, caustic_guard, True)
+    _check(lib.utd_wall_masks(scene.handle if scene is not None else None, ctypes.byref(b), ctypes.byref(source),
+                              rx.data_ptr() if n else None, n, ctypes.byref(opt),
+                              out.data_ptr() if out.numel() else None, _stream(stream)))
+    return out

@@ -14,9 +14,21 @@
 //   node  = 4 float4: (lo0.xyz, hi0.x) (hi0.yz, lo1.xy) (lo1.z, hi1.xyz) (c0, n0, c1, n1)
 //           n_i > 0: leaf of n_i triangles starting at c_i; n_i == 0: inner node c_i;
 //           c_i < 0: empty child.
-//   tris  = 3 float4 per triangle (v0, v1, v2), in leaf order.
+//   tris  = 3 float4 per triangle (v0, v1, v2), in leaf order; the w of v0
+//           holds the index of the triangle's reflector plane (int bits, -1
+//           for a degenerate triangle).
+//
+// Reflector planes (one specular wall bounce, utd_walls.h): the triangles
+// lying in one plane n.x = d form one mirror.  A triangle's unit normal is
+// taken with its first component of magnitude above 1e-9 positive;
+// triangles whose normal components and offsets agree after rounding to
+// multiples of 1e-6 share a plane, planes are ordered by those rounded
+// values, and each keeps the normal of its first triangle, the mean offset
+// and its triangles' bounding box.
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <tuple>
 #include <cstdlib>
 #include <cstring>
 #include <vector>
@@ -132,7 +144,58 @@ int64_t split(std::vector<Prim>& P, int64_t b, int64_t e) {
 // Appends the tree over tri[ids] to the output arrays: nodes numbered from
 // node_base, triangles from tri_base (references are absolute).  An empty set
 // gives one node with two empty children.
-void build_tree(const float* tri, const std::vector<int64_t>& ids, int max_depth, int node_base, int64_t tri_base,
+// Reflector plane of every triangle (index into *planes, -1 if degenerate).
+void group_planes(const float* tri, int64_t n, std::vector<int>* plane_of, std::vector<WallPlane>* planes) {
+    typedef std::tuple<long long, long long, long long, long long> Key;
+    std::map<Key, std::vector<int64_t>> groups;
+    std::vector<double> nd(4 * (size_t)n, 0.0);
+    plane_of->assign((size_t)n, -1);
+    for (int64_t i = 0; i < n; ++i) {
+        const float* t = tri + 9 * i;
+        const double e1[3] = {(double)t[3] - t[0], (double)t[4] - t[1], (double)t[5] - t[2]};
+        const double e2[3] = {(double)t[6] - t[0], (double)t[7] - t[1], (double)t[8] - t[2]};
+        double c[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+        const double ln = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+        if (!(ln > 0)) continue;
+        for (int a = 0; a < 3; ++a) c[a] /= ln;
+        for (int a = 0; a < 3; ++a) {
+            if (std::fabs(c[a]) > 1e-9) {
+                if (c[a] < 0)
+                    for (int b = 0; b < 3; ++b) c[b] = -c[b];
+                break;
+            }
+        }
+        const double d = c[0] * t[0] + c[1] * t[1] + c[2] * t[2];
+        for (int a = 0; a < 3; ++a) nd[4 * i + a] = c[a];
+        nd[4 * i + 3] = d;
+        // round half to even, as the default floating-point rounding mode does
+        Key k{(long long)std::nearbyint(c[0] / 1e-6), (long long)std::nearbyint(c[1] / 1e-6),
+              (long long)std::nearbyint(c[2] / 1e-6), (long long)std::nearbyint(d / 1e-6)};
+        groups[k].push_back(i);
+    }
+    planes->clear();
+    for (auto& g : groups) {
+        WallPlane P;
+        const int64_t f = g.second.front();
+        for (int a = 0; a < 3; ++a) P.n[a] = nd[4 * f + a];
+        double sd = 0.0;
+        for (int a = 0; a < 3; ++a) { P.lo[a] = INFINITY; P.hi[a] = -INFINITY; }
+        for (int64_t i : g.second) {
+            sd += nd[4 * i + 3];
+            for (int v = 0; v < 3; ++v)
+                for (int a = 0; a < 3; ++a) {
+                    P.lo[a] = std::min(P.lo[a], tri[9 * i + 3 * v + a]);
+                    P.hi[a] = std::max(P.hi[a], tri[9 * i + 3 * v + a]);
+                }
+            (*plane_of)[(size_t)i] = (int)planes->size();
+        }
+        P.d = sd / (double)g.second.size();
+        planes->push_back(P);
+    }
+}
+
+void build_tree(const float* tri, const std::vector<int>& plane_of, const std::vector<int64_t>& ids, int max_depth,
+                int node_base, int64_t tri_base,
                 std::vector<float>& out_nodes, std::vector<float>& out_tris, int* depth_out) {
     const int64_t n = (int64_t)ids.size();
     std::vector<Prim> P((size_t)n);
@@ -199,7 +262,12 @@ void build_tree(const float* tri, const std::vector<int64_t>& ids, int max_depth
             out_tris.push_back(src[3 * v + 0]);
             out_tris.push_back(src[3 * v + 1]);
             out_tris.push_back(src[3 * v + 2]);
-            out_tris.push_back(0.0f);
+            float w = 0.0f;
+            if (v == 0) {
+                const int pid = plane_of[(size_t)P[(size_t)i].idx];
+                std::memcpy(&w, &pid, sizeof w);
+            }
+            out_tris.push_back(w);
         }
     }
     *depth_out = depth_seen;
@@ -223,11 +291,13 @@ int build_bvh(const float* tri, int64_t n, int max_depth, HostBvh* out) {
     }
     std::vector<float> nodes, tris;
     int d0 = 0, d1 = 0;
-    build_tree(tri, inner, max_depth, 0, 0, nodes, tris, &d0);
+    std::vector<int> plane_of;
+    group_planes(tri, n, &plane_of, &out->planes);
+    build_tree(tri, plane_of, inner, max_depth, 0, 0, nodes, tris, &d0);
     out->broot = -1;
     if (!bound.empty()) {
         out->broot = (int64_t)(nodes.size() / 16);
-        build_tree(tri, bound, max_depth, (int)out->broot, (int64_t)inner.size(), nodes, tris, &d1);
+        build_tree(tri, plane_of, bound, max_depth, (int)out->broot, (int64_t)inner.size(), nodes, tris, &d1);
     }
     for (int a = 0; a < 3; ++a) { out->lo[a] = scene.lo[a]; out->hi[a] = scene.hi[a]; }
     out->n_nodes = (int64_t)(nodes.size() / 16);

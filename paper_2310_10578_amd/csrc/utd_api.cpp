@@ -25,6 +25,9 @@ struct utd_scene {
     int depth = 0;
     float4* d_nodes = nullptr;
     float4* d_tris = nullptr;
+    std::vector<utd::WallPlane> planes;  // reflector planes (host copy)
+    utd::WallPlane* d_planes = nullptr;
+    utd::WallMat mat{3.75, 0.038, 0.10, 0};   // ITU-R P.2040 brick, 10 cm
 };
 
 namespace {
@@ -86,6 +89,7 @@ utd_status check_common(const utd_bodies* bodies, const utd_source* tx, const fl
     if (opt->precision != 0 && opt->precision != 1) return fail(UTD_E_ARG, "precision must be 0 or 1");
     if (opt->l_enc < 0 || opt->l_enc > 2) return fail(UTD_E_ARG, "l_enc must be in 0..2");
     if (!(opt->caustic_guard >= 0)) return fail(UTD_E_ARG, "caustic_guard must be >= 0");
+    if (opt->wall_reflections != 0 && opt->wall_reflections != 1) return fail(UTD_E_ARG, "wall_reflections must be 0 or 1");
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(tx->pos[a]) || !std::isfinite(tx->dipole[a]))
             return fail(UTD_E_ARG, "non-finite source position or dipole");
@@ -112,6 +116,10 @@ utd::LaunchParams make_params(const utd_scene* scene, const utd_bodies* bodies, 
     L.lit_branch = opt->lit_branch;
     L.caustic_guard = opt->caustic_guard;
     return L;
+}
+
+bool walls_on(const utd_scene* scene, const utd_options* opt) {
+    return opt->wall_reflections && scene && !scene->planes.empty();
 }
 
 // Stream-ordered scratch of one call: body constants, frequency constants,
@@ -250,6 +258,7 @@ void utd_default_options(utd_options* opt) {
     opt->bodies_occlude = 1;
     opt->lit_branch = 1;
     opt->caustic_guard = 1e-6;
+    opt->wall_reflections = 0;
 }
 
 const char* utd_last_error(void) { return g_err.c_str(); }
@@ -295,10 +304,17 @@ utd_status utd_scene_create(const float* tri, int64_t n_tri, utd_scene** out) {
         s->broot = b.broot;
         for (int a = 0; a < 3; ++a) { s->lo[a] = b.lo[a]; s->hi[a] = b.hi[a]; }
         s->depth = b.depth;
+        s->planes = b.planes;
         hipError_t e = hipMalloc(&s->d_nodes, sizeof(float4) * 4 * b.n_nodes);
         if (e == hipSuccess) e = hipMalloc(&s->d_tris, sizeof(float4) * 3 * n_tri);
         if (e == hipSuccess) e = hipMemcpy(s->d_nodes, b.nodes, sizeof(float4) * 4 * b.n_nodes, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(s->d_tris, b.tris, sizeof(float4) * 3 * n_tri, hipMemcpyHostToDevice);
+        if (e == hipSuccess && !s->planes.empty()) {
+            e = hipMalloc(&s->d_planes, sizeof(utd::WallPlane) * s->planes.size());
+            if (e == hipSuccess)
+                e = hipMemcpy(s->d_planes, s->planes.data(), sizeof(utd::WallPlane) * s->planes.size(),
+                              hipMemcpyHostToDevice);
+        }
         utd::free_bvh(&b);
         if (e != hipSuccess) {
             utd_scene_destroy(s);
@@ -311,13 +327,35 @@ utd_status utd_scene_create(const float* tri, int64_t n_tri, utd_scene** out) {
 
 void utd_scene_destroy(utd_scene* s) {
     if (!s) return;
-    if (s->d_nodes || s->d_tris) (void)hipDeviceSynchronize();
+    if (s->d_nodes || s->d_tris || s->d_planes) (void)hipDeviceSynchronize();
     if (s->d_nodes) (void)hipFree(s->d_nodes);
     if (s->d_tris) (void)hipFree(s->d_tris);
+    if (s->d_planes) (void)hipFree(s->d_planes);
     delete s;
 }
 
 int64_t utd_scene_triangles(const utd_scene* s) { return s ? s->n_tri : 0; }
+
+int64_t utd_scene_planes(const utd_scene* s, double* out) {
+    if (!s) return 0;
+    if (out)
+        for (size_t k = 0; k < s->planes.size(); ++k) {
+            for (int a = 0; a < 3; ++a) out[4 * k + a] = s->planes[k].n[a];
+            out[4 * k + 3] = s->planes[k].d;
+        }
+    return (int64_t)s->planes.size();
+}
+
+utd_status utd_scene_set_wall_material(utd_scene* s, const utd_wall_material* m) {
+    if (!s || !m) return fail(UTD_E_ARG, "scene and material must not be NULL");
+    if (!m->perfect_conductor) {
+        if (!(m->eps_r >= 1.0) || !std::isfinite(m->eps_r)) return fail(UTD_E_ARG, "eps_r must be finite and >= 1");
+        if (!(m->sigma >= 0.0) || !std::isfinite(m->sigma)) return fail(UTD_E_ARG, "sigma must be finite and >= 0");
+        if (!(m->thickness > 0.0)) return fail(UTD_E_ARG, "thickness must be > 0 (infinite: a half-space)");
+    }
+    s->mat = utd::WallMat{m->eps_r, m->sigma, m->thickness, m->perfect_conductor ? 1 : 0};
+    return UTD_OK;
+}
 int64_t utd_scene_nodes(const utd_scene* s) { return s ? s->n_nodes : 0; }
 
 utd_status utd_smooth_field(const utd_scene* scene, const utd_bodies* bodies, const utd_source* tx, const float* rx,
@@ -331,8 +369,11 @@ utd_status utd_smooth_field(const utd_scene* scene, const utd_bodies* bodies, co
     hipStream_t s = (hipStream_t)stream;
     utd::LaunchParams L = make_params(scene, bodies, tx, n_rx, n_f, opt);
     int nb = L.n_sph + L.n_cyl;
+    const bool walls = walls_on(scene, opt);
+    const int n_planes = walls ? (int)scene->planes.size() : 0;
     Workspace w;
-    e = w.alloc(nb, n_rx, n_f, opt->l_enc, opt->precision, rx_flags == nullptr, s);
+    e = w.alloc(nb, n_rx, n_f, opt->l_enc, opt->precision, rx_flags == nullptr, s,
+                walls ? utd::walls_scratch_bytes(L, n_planes) : 0);
     if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(UTD_E_OOM, "workspace allocation") : hip_fail(e, "hipMallocAsync");
     uint8_t* flags = rx_flags ? rx_flags : w.flags;
     const float4* nodes = scene ? scene->d_nodes : nullptr;
@@ -346,6 +387,12 @@ utd_status utd_smooth_field(const utd_scene* scene, const utd_bodies* bodies, co
     if (e == hipSuccess) {
         ProfScope ps(UTD_K_FIELD, s);
         e = utd::launch_field(L, opt->precision, fc, rx, w.fc, w.mask, w.rec, flags, E_out, s);
+    }
+    if (e == hipSuccess && walls) {
+        ProfScope ps(UTD_K_WALLS, s);
+        e = utd::launch_walls(L, opt->precision, scene->mat, rx, bodies->sph, bodies->cyl, w.prep,
+                              (utd::BodyPrep*)w.extra, scene->d_planes, n_planes, nodes, tris, w.fc, freqs, flags,
+                              E_out, nullptr, s);
     }
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return UTD_OK;
@@ -361,8 +408,11 @@ utd_status utd_smooth_field_noalloc(const utd_scene* scene, const utd_bodies* bo
     hipStream_t s = (hipStream_t)stream;
     utd::LaunchParams L = make_params(scene, bodies, tx, n_rx, n_f, opt);
     int nb = L.n_sph + L.n_cyl;
+    const bool walls = walls_on(scene, opt);
+    const int n_planes = walls ? (int)scene->planes.size() : 0;
     Workspace w;
-    const size_t need = w.plan(nb, n_rx, n_f, opt->l_enc, opt->precision, rx_flags == nullptr);
+    const size_t need = w.plan(nb, n_rx, n_f, opt->l_enc, opt->precision, rx_flags == nullptr,
+                               walls ? utd::walls_scratch_bytes(L, n_planes) : 0);
     if (need > utd::kNoAllocScratchBytes)
         return fail(UTD_E_ARG,
                     "this call needs %zu bytes of scratch; the allocation-free entry point has %zu (fewer "
@@ -384,6 +434,12 @@ utd_status utd_smooth_field_noalloc(const utd_scene* scene, const utd_bodies* bo
         ProfScope ps(UTD_K_FIELD, s);
         e = utd::launch_field(L, opt->precision, pick_fc(opt->precision, n_rx, n_f), rx, w.fc, w.mask, w.rec,
                               flags, E_out, s);
+    }
+    if (e == hipSuccess && walls) {
+        ProfScope ps(UTD_K_WALLS, s);
+        e = utd::launch_walls(L, opt->precision, scene->mat, rx, bodies->sph, bodies->cyl, w.prep,
+                              (utd::BodyPrep*)w.extra, scene->d_planes, n_planes, nodes, tris, w.fc, freqs, flags,
+                              E_out, nullptr, s);
     }
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return UTD_OK;
@@ -445,6 +501,31 @@ utd_status utd_path_masks(const utd_scene* scene, const utd_bodies* bodies, cons
     return UTD_OK;
 }
 
+utd_status utd_wall_masks(const utd_scene* scene, const utd_bodies* bodies, const utd_source* tx, const float* rx,
+                          int64_t n_rx, const utd_options* opt, uint64_t* mask_out, void* stream) {
+    double fdummy = 1e9;
+    utd_status st = check_common(bodies, tx, rx, n_rx, &fdummy, 1, opt);
+    if (st != UTD_OK) return st;
+    const int64_t nb = bodies->n_sph + bodies->n_cyl;
+    if (nb > 10) return fail(UTD_E_UNSUPPORTED, "wall masks hold at most 10 bodies");
+    if (!scene || scene->planes.empty() || n_rx == 0) return UTD_OK;
+    if (!mask_out) return fail(UTD_E_ARG, "mask_out is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    utd::LaunchParams L = make_params(scene, bodies, tx, n_rx, 0, opt);
+    const int n_planes = (int)scene->planes.size();
+    Workspace w;
+    hipError_t e = w.alloc((int)nb, n_rx, 0, opt->l_enc, opt->precision, true, s, utd::walls_scratch_bytes(L, n_planes));
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(UTD_E_OOM, "workspace allocation") : hip_fail(e, "hipMallocAsync");
+    e = utd::launch_paths(L, opt->precision, rx, bodies->sph, bodies->cyl, nullptr, w.prep, w.fc, scene->d_nodes,
+                          scene->d_tris, w.mask, w.rec, w.flags, w.ent, w.ent_th, w.vis, w.counters + 12, w.cap, s);
+    if (e == hipSuccess)
+        e = utd::launch_walls(L, opt->precision, scene->mat, rx, bodies->sph, bodies->cyl, w.prep,
+                              (utd::BodyPrep*)w.extra, scene->d_planes, n_planes, scene->d_nodes, scene->d_tris, w.fc,
+                              nullptr, w.flags, nullptr, mask_out, s);
+    if (e != hipSuccess) return hip_fail(e, "wall masks");
+    return UTD_OK;
+}
+
 utd_status utd_input_status(uint32_t* bits) {
     if (!bits) return fail(UTD_E_ARG, "bits is NULL");
     unsigned v = 0;
@@ -461,6 +542,7 @@ utd_status utd_smooth_field_backward(const utd_scene* scene, const utd_bodies* b
     utd_status st = check_common(bodies, tx, rx, n_rx, freqs, n_f, opt);
     if (st != UTD_OK) return st;
     if (!d_tx) return fail(UTD_E_ARG, "d_tx is NULL");
+    if (opt->wall_reflections) return fail(UTD_E_UNSUPPORTED, "wall reflections have no adjoint");
     if (bodies->n_cyl && !d_cyl) return fail(UTD_E_ARG, "d_cyl is NULL with n_cyl > 0");
     if (bodies->n_sph && !d_sph) return fail(UTD_E_ARG, "d_sph is NULL with n_sph > 0");
     const bool work = n_rx > 0 && n_f > 0;
@@ -516,6 +598,7 @@ utd_status utd_smooth_field_batched(const utd_scene* scene, int64_t n_frames, co
     if (opt->precision != 0 && opt->precision != 1) return fail(UTD_E_ARG, "precision must be 0 or 1");
     if (opt->l_enc < 0 || opt->l_enc > 2) return fail(UTD_E_ARG, "l_enc must be in 0..2");
     if (!(opt->caustic_guard >= 0)) return fail(UTD_E_ARG, "caustic_guard must be >= 0");
+    if (opt->wall_reflections) return fail(UTD_E_UNSUPPORTED, "wall reflections are not batched");
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(tx->pos[a]) || !std::isfinite(tx->dipole[a]))
             return fail(UTD_E_ARG, "non-finite source position or dipole");

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "utd_device.h"
 
 namespace utd {
@@ -58,6 +60,31 @@ hipError_t read_input_status(unsigned* bits);
 hipError_t launch_census(int64_t n_mask, const uint8_t* mask, int64_t n_rx, const uint8_t* flags,
                          unsigned long long* counts, hipStream_t s);
 
+// A reflector plane n.x = d of the scene triangles (one specular wall
+// bounce) with the bounding box of its triangles.
+struct WallPlane {
+    double n[3];
+    double d;
+    float lo[3], hi[3];
+};
+
+// Wall material: a slab of relative permittivity eps_r, conductivity sigma
+// (S/m) and thickness (m; infinite: a half-space), or a perfect conductor.
+struct WallMat {
+    double eps_r, sigma, thickness;
+    int pec;
+};
+
+// One specular wall bounce (utd_walls.h): body constants of the image
+// sources (prep_img, n_planes * bodies entries) then the wall paths of every
+// receiver, added to E; wall decisions to wmask ([n_rx][n_planes]) when not
+// NULL.
+size_t walls_scratch_bytes(const LaunchParams& L, int n_planes);
+hipError_t launch_walls(const LaunchParams& L, int precision, const WallMat& M, const float* rx, const float* sph,
+                        const float* cyl, const BodyPrep* prep, BodyPrep* prep_img, const WallPlane* planes,
+                        int n_planes, const float4* nodes, const float4* tris, const FreqConst* fcs,
+                        const double* freqs, uint8_t* flags, void* E, uint64_t* wmask, hipStream_t s);
+
 // host BVH over a triangle soup (bvh.cpp)
 struct HostBvh {
     int64_t n_nodes = 0;
@@ -67,6 +94,7 @@ struct HostBvh {
     int depth = 0;
     float* nodes = nullptr;   // n_nodes * 16 floats (4 float4 per node)
     float* tris = nullptr;    // n_tri * 12 floats (3 float4 per triangle), leaf order
+    std::vector<WallPlane> planes;   // reflector planes, ordered as described in bvh.cpp
 };
 int build_bvh(const float* tri_xyz, int64_t n_tri, int max_depth, HostBvh* out);
 void free_bvh(HostBvh* b);

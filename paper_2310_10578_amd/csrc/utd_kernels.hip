@@ -964,3 +964,4 @@ hipError_t launch_field(const LaunchParams& L, int precision, int fc, const floa
 
 #include "utd_adjoint.h"
 #include "utd_batched.h"
+#include "utd_walls.h"

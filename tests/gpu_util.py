@@ -29,9 +29,21 @@ def _dev_inputs(cfg, rx, freqs):
     return sph, cyl, rxt, ft
 
 
-def run_library(cfg, precision=0, rx=None, freqs=None, masks=False, **kw):
+def set_walls(scene, walls):
+    """Library wall material from the oracle's description (dict or PEC)."""
+    from oracle import walls as OW
+    if walls == OW.PEC:
+        scene.set_wall_material(perfect_conductor=True)
+    else:
+        scene.set_wall_material(walls["eps_r"], walls["sigma"], walls["thickness"])
+
+
+def run_library(cfg, precision=0, rx=None, freqs=None, masks=False, walls=None, **kw):
     """(E complex128 [nf, 3, n], flags [n]) and, with masks=True, the
-    library's per-(body, receiver) path masks [nb, n] for the same inputs."""
+    library's per-(body, receiver) path masks [nb, n] for the same inputs
+    (and, with walls, its wall masks [n, n_planes] as a fourth item).
+    ``walls``: the oracle's wall material (dict or PEC) to switch wall
+    reflections on."""
     import torch
 
     import paper_2310_10578_amd as utd
@@ -42,15 +54,22 @@ def run_library(cfg, precision=0, rx=None, freqs=None, masks=False, **kw):
     sph, cyl, rxt, ft = _dev_inputs(cfg, rx, freqs)
     tx = cfg["tx"]
     src = utd.make_source(tx["pos"], tx["dipole"], tx["amplitude"])
-    E, flags = utd.smooth_field(scene, sph, cyl, src, rxt, ft, precision=precision, **kw)
+    if walls is not None:
+        set_walls(scene, walls)
+    E, flags = utd.smooth_field(scene, sph, cyl, src, rxt, ft, precision=precision,
+                                wall_reflections=walls is not None, **kw)
     if masks:
         mk, fm = utd.path_masks(scene, sph, cyl, src, rxt, precision=precision, **kw)
+        if walls is not None:
+            wm = utd.wall_masks(scene, sph, cyl, src, rxt, precision=precision, **kw)
     torch.cuda.synchronize()
     out = E.cpu().numpy().astype(np.complex128), flags.cpu().numpy()
     if masks:
         fm = fm.cpu().numpy()
         assert np.array_equal(fm, out[1] & ~np.uint8(2 | 64)), "path_masks flags differ from the field call's"
         out = out + (mk.cpu().numpy(),)
+        if walls is not None:
+            out = out + (wm.cpu().numpy().view(np.uint64),)
     scene.close()
     return out
 
@@ -83,8 +102,22 @@ def path_keys(n_sph, n_cyl, l_enc, lit_branch):
     return out
 
 
-def frozen_from_library(cfg, flags, mask, opts=None):
-    """The library's decisions in the oracle's classification layout."""
+def wall_keys(n_planes, n_sph, n_cyl):
+    """(oracle wall-path key, plane, bit) for every bit of the library's wall masks."""
+    out = []
+    for p in range(n_planes):
+        out.append((("w", p), p, 0))
+        for b in range(n_sph + n_cyl):
+            body = ("s", b) if b < n_sph else ("c", b - n_sph)
+            for k, (first, path) in enumerate([("wb", ("c", 1, 0)), ("wb", ("c", -1, 0)), ("wb", ("r",)),
+                                               ("bw", ("c", 1, 0)), ("bw", ("c", -1, 0)), ("bw", ("r",))]):
+                out.append(((first, p, body, path), p, 1 + 6 * b + k))
+    return out
+
+
+def frozen_from_library(cfg, flags, mask, opts=None, wmask=None):
+    """The library's decisions in the oracle's classification layout (wall
+    paths from its wall masks when given)."""
     o = dict(l_enc=0, lit_branch=True)
     o.update(opts or {})
     ns = np.asarray(cfg["scene"]["spheres"]).reshape(-1, 4).shape[0]
@@ -92,7 +125,49 @@ def frozen_from_library(cfg, flags, mask, opts=None):
     dead = (flags & (1 | 8 | 16 | 32)) != 0
     paths = [(key, dict(valid=((mask[b] >> bit) & 1).astype(bool) & ~dead))
              for key, b, bit in path_keys(ns, nc, o["l_enc"], o["lit_branch"])]
-    return dict(los=(flags & 4) != 0, inside=(flags & 1) != 0, flags=flags.copy(), paths=paths)
+    fz = dict(los=(flags & 4) != 0, inside=(flags & 1) != 0, flags=flags.copy(), paths=paths)
+    if wmask is not None:
+        wm = np.asarray(wmask, np.uint64)
+        fz["walls"] = [(key, dict(valid=((wm[:, p] >> np.uint64(bit)) & np.uint64(1)).astype(bool) & ~dead))
+                       for key, p, bit in wall_keys(wm.shape[1], ns, nc)]
+    return fz
+
+
+def wall_decision_mismatches(cfg, rx, flags, wmask, walls, opts=None, delta=DELTA_GRAZE, n_try=12, seed=0):
+    """The library's wall decisions against the oracle's own.  Returns
+    (n_differing, n_not_grazing); a difference is grazing when moving the
+    receiver by delta in some direction flips the oracle's own decision."""
+    from oracle import field
+    o = dict(l_enc=0, lit_branch=True, bodies_occlude=True, caustic_guard=1e-6)
+    o.update(opts or {})
+    o["walls"] = walls
+    sc, tx, R = W.to_oracle(cfg["scene"], cfg["tx"], rx)
+    T = np.asarray(tx["pos"], float)
+    info = field.classify(sc, T, R, o)
+    ns = np.asarray(cfg["scene"]["spheres"]).reshape(-1, 4).shape[0]
+    nc = np.asarray(cfg["scene"]["cylinders"]).reshape(-1, 5).shape[0]
+    dead = (flags & (1 | 8 | 16 | 32)) != 0
+    own = dict(info["walls"])
+    wm = np.asarray(wmask, np.uint64)
+    diff = []
+    for key, p, bit in wall_keys(wm.shape[1], ns, nc):
+        g = ((wm[:, p] >> np.uint64(bit)) & np.uint64(1)).astype(bool) & ~dead
+        vo = np.asarray(own[key]["valid"], bool) if key in own else np.zeros(len(g), bool)
+        for i in np.nonzero(g != vo)[0]:
+            diff.append((i, key, vo[i]))
+    rng = np.random.default_rng(seed)
+    n_not = 0
+    for i, key, base in diff:
+        flipped = False
+        for _ in range(n_try):
+            u = rng.standard_normal(3)
+            Rp = R[i] + delta * u / np.linalg.norm(u)
+            inf2 = dict(field.classify(sc, T, Rp[None, :], o)["walls"])
+            if key in inf2 and bool(inf2[key]["valid"][0]) != base:
+                flipped = True
+                break
+        n_not += 0 if flipped else 1
+    return len(diff), n_not
 
 
 def _segments(info, key, idx, T, R):
@@ -176,7 +251,7 @@ def per_receiver(Eg, Eo, A):
 
 
 def parity(cfg, precision, rx=None, freqs=None, opts=None, name="", r14_bound=None, check_decisions=True,
-           max_mismatch=0.02, sample=None, tol=None, lib=None, sens=None, nw_tol=None):
+           max_mismatch=0.02, sample=None, tol=None, lib=None, sens=None, nw_tol=None, walls=None):
     """Receiver-exact parity of the library against the oracle.
 
     1. The library's field against the oracle evaluated with the library's
@@ -194,6 +269,8 @@ def parity(cfg, precision, rx=None, freqs=None, opts=None, name="", r14_bound=No
     ulps of receiver displacement (ill-conditioned receivers); the
     per-receiver bound is then TOL times the path magnitudes plus 4 sens.
     ``nw_tol``: the normwise bound when it differs from the per-receiver TOL.
+    ``walls``: the oracle's wall material (dict or PEC): wall reflections on
+    in both, the library's wall decisions frozen into the oracle too.
     Returns a dict of the measured numbers."""
     opts = dict(opts or {})
     tol = TOL[precision] if tol is None else tol
@@ -201,20 +278,27 @@ def parity(cfg, precision, rx=None, freqs=None, opts=None, name="", r14_bound=No
     rx = cfg["rx"] if rx is None else rx
     freqs = cfg["freqs"] if freqs is None else freqs
     if lib is None:
-        lib = run_library(cfg, precision, rx=rx, freqs=freqs, masks=True, **opts)
-    Eg, fg, mk = lib
+        lib = run_library(cfg, precision, rx=rx, freqs=freqs, masks=True, walls=walls, **opts)
+    Eg, fg, mk = lib[:3]
+    wm = lib[3] if len(lib) > 3 else None
     if sample is not None:
         Eg, fg, mk, rx = Eg[:, :, sample], fg[sample], mk[:, sample], rx[sample]
-    frozen = frozen_from_library(cfg, fg, mk, opts)
-    Eo, _, A = run_oracle(cfg, rx=rx, freqs=freqs, opts=opts, frozen=frozen, absum=True)
+        wm = wm[sample] if wm is not None else None
+    frozen = frozen_from_library(cfg, fg, mk, opts, wmask=wm)
+    oopts = dict(opts, walls=walls) if walls is not None else opts
+    Eo, _, A = run_oracle(cfg, rx=rx, freqs=freqs, opts=oopts, frozen=frozen, absum=True)
     nw = normwise(Eg, Eo)
     comp, r14 = per_receiver(Eg, Eo, A)
     res = dict(normwise=nw, comp=comp, r14=r14, flags=fg, mask=mk, E=Eg, Eo=Eo, A=A, rx=rx)
     msg = "%s p%d: normwise max %.2e, per-receiver componentwise max %.2e, reading-14 max %.2e" % (
         name, precision, nw.max(), comp.max(), r14.max())
     if check_decisions:
-        _, info = run_oracle(cfg, rx=rx, freqs=freqs[:1], opts=opts)
+        _, info = run_oracle(cfg, rx=rx, freqs=freqs[:1], opts=oopts)
         n_los, n_path, n_not = decision_mismatches(cfg, rx, fg, mk, info, opts)
+        if wm is not None:
+            n_w, n_w_not = wall_decision_mismatches(cfg, rx, fg, wm, walls, opts)
+            n_path += n_w
+            n_not += n_w_not
         res.update(n_los=n_los, n_path=n_path, n_not_grazing=n_not, info=info)
         msg += "; decisions differing from the oracle's: %d line-of-sight, %d paths (%d not grazing) of %d rx" % (
             n_los, n_path, n_not, fg.size)
