@@ -305,25 +305,39 @@ __global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(3, 8)
                 }
             }
             // --- 3. field of this group's visible paths ---------------------
+            // Each lane walks its own visible paths (creeping paths in
+            // (body, bit) order, then the reflections), so a wavefront runs
+            // as many iterations as its busiest lane: walking the bodies and
+            // bits in lockstep would evaluate every (body, path kind) that
+            // any of the 64 receivers has visible.
             if (act && !dead) {
-                for (int bl = 0; bl < ng; ++bl) {
-                    const uint32_t m = mask8[bl * TILE + tid];
-                    if (!m) continue;
-                    const BodyPrep P = fprep[g0 + bl];
-                    RxGeo g = rx_geo<double, Kinds::Cylinders>(P, R3);
-                    for (int bit = 0; bit <= kBitRefl; ++bit) {
-                        if (!((m >> bit) & 1u)) continue;
+                const uint32_t creep_sel = (1u << n_creep) - 1u;
+#pragma unroll 1
+                for (int pass = 0; pass < 2; ++pass) {
+                    const uint32_t sel = pass == 0 ? creep_sel : (1u << kBitRefl);
+                    int bl = 0;
+                    uint32_t mrem = ng > 0 ? (mask8[tid] & sel) : 0u;
+#pragma unroll 1
+                    for (;;) {
+                        while (mrem == 0u && bl < ng) {
+                            ++bl;
+                            if (bl < ng) mrem = mask8[bl * TILE + tid] & sel;
+                        }
+                        const bool have = bl < ng;
+                        if (!__any(have)) break;
+                        if (!have) continue;
+                        const int bit = __builtin_ctz(mrem);
+                        mrem &= mrem - 1u;
+                        const BodyPrep P = fprep[g0 + bl];
+                        RxGeo g = rx_geo<double, Kinds::Cylinders>(P, R3);
                         PathEval<R> pe;
-                        if (bit == kBitRefl) {
+                        if (pass == 1) {
                             d3 Q, n3;
                             refl_point<double, Kinds::Cylinders>(P, g, R3, T, thb[bl * TILE + tid], &Q, &n3);
                             refl_eval<R, double>(P, Q, n3, R3, T, L, &pe);
                         } else {
                             cyl_creep<R, double>(P, g, R3, T, L, (bit & 1) ? -1 : 1, bit >> 1, &pe, nullptr);
                         }
-                        // wave-uniform choice of the Fock specialisation
-                        const bool any_refl = __any(pe.refl != 0), any_creep = __any(pe.refl == 0);
-                        const int mode = !any_refl ? kCreep : (!any_creep ? kRefl : kAny);
 #pragma unroll 1
                         for (int j = 0; j < L.n_f; ++j) {
                             if (!fcs[j].ok) continue;     // an invalid frequency keeps its zero field
@@ -335,12 +349,10 @@ __global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(3, 8)
                                 e[2 * c + 1] = E[2 * o + 1];
                             }
                             FreqC<R> fc(fcs[j]);
-                            if (mode == kCreep)
+                            if (pass == 0)
                                 add_path<R, kCreep>(pe, tb, fc, e);
-                            else if (mode == kRefl)
-                                add_path<R, kRefl>(pe, tb, fc, e);
                             else
-                                add_path<R, kAny>(pe, tb, fc, e);
+                                add_path<R, kRefl>(pe, tb, fc, e);
 #pragma unroll
                             for (int c = 0; c < 3; ++c) {
                                 int64_t o = ((int64_t)j * 3 + c) * L.n_rx + li;
