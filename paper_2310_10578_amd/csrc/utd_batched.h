@@ -118,18 +118,22 @@ __device__ __forceinline__ int64_t uniform64(int64_t v) {
 
 // One work item = one frame's tile of TILE receivers (one lane each).  Its
 // bodies are taken in groups of kBGroup; per group:
-//   1. candidates: per body, every lane decides which of its receiver's paths
-//      exist (geometry and, for the reflection, the FP64 point solve) and
-//      pushes one key per candidate into an LDS queue (receiver lane, body in
+//   1. cull: per body, every lane checks whether its receiver's height can
+//      see the lateral surface at all; the passing (lane, body) pairs go to
+//      an LDS queue, kPGroup bodies at a time;
+//   2. candidates: the queued pairs are classified one per lane (which paths
+//      exist: geometry and, for the reflection, the FP64 point solve), one
+//      key per candidate into a second LDS queue (receiver lane, body in
 //      group, path bit); reflection angles go to the work item's scratch;
-//   2. visibility: whenever another body's candidates might not fit, and after
-//      the last body, all lanes drain the queue, one candidate each (legs
-//      against the frame's other bodies and the BVH), and set visible bits
-//      in the group's LDS masks -- so the traversal runs with every lane busy
-//      however sparse the valid paths are;
-//   3. field: every lane evaluates its receiver's visible paths of the group,
+//   3. visibility: whenever another chunk's candidates might not fit, and
+//      after the last one, all lanes drain the candidate queue, one candidate
+//      each (legs against the frame's other bodies and the BVH), and set
+//      visible bits in the group's LDS masks -- so classification and
+//      traversal run with every lane busy however sparse the pairs are;
+//   4. field: every lane walks its receiver's visible paths of the group,
 //      bodies and paths in order, at every frequency, adding to E in place.
 constexpr int kBGroup = 32;
+constexpr int kPGroup = 16;   // bodies per cull sub-group (LDS pair queue of kPGroup x TILE)
 
 // The Fock tables are read through the caches here, not staged in LDS: the
 // 20 KB of LDS they would take is what lets three workgroups of 256 share a
@@ -157,7 +161,8 @@ __global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(3, 8)
     __shared__ int stack[kStackDepth * TILE];
     __shared__ unsigned int s_mask[kBGroup * TILE / 4];   // bytes [body in group][lane]
     __shared__ uint32_t s_q[QCAP];
-    __shared__ int s_qn;
+    __shared__ uint16_t s_pq[kPGroup * TILE];             // queued (lane, body) pairs
+    __shared__ int s_qn, s_pn;
     __shared__ int64_t s_tile;
     const Tabs<R> tb = GlobalTabs<R>::get();
     uint8_t* mask8 = reinterpret_cast<uint8_t*>(s_mask);
@@ -240,71 +245,101 @@ __global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(3, 8)
             for (int k = tid; k < kBGroup * TILE / 4; k += TILE) s_mask[k] = 0u;
             if (tid == 0) s_qn = 0;
             __syncthreads();
-            for (int bl = 0; bl < ng; ++bl) {
-                // --- 1. candidates of (receiver, body g0 + bl) --------------
-                if (act && !dead && cyl_paths_possible(fprep[g0 + bl], R3, T, L)) {
-                    const BodyPrep P = fprep[g0 + bl];
-                    RxGeo g = rx_geo<double, Kinds::Cylinders>(P, R3);
-                    uint32_t cand = 0;
-                    for (int bit = 0; bit < n_creep; ++bit) {
-                        PathPts pts;
-                        if (cyl_creep<R, double>(P, g, R3, T, L, (bit & 1) ? -1 : 1, bit >> 1, (PathEval<R>*)nullptr,
-                                                 &pts))
-                            cand |= 1u << bit;
+            // --- 3. visibility: the queued candidates, one per lane (legs
+            // against the frame's other bodies and the BVH); visible bits go
+            // to the group's LDS masks and the queue is emptied
+            auto drain = [&](int qn) {
+                for (int kq = tid; kq < qn; kq += TILE) {
+                    const uint32_t key = s_q[kq];
+                    const int lane = (int)(key & 0xffu), blk = (int)((key >> 8) & 0x1fu), bit = (int)(key >> 13);
+                    const int64_t i2 = r0 + lbase + lane;
+                    const d3 R2 = mk(rx[3 * i2], rx[3 * i2 + 1], rx[3 * i2 + 2]);
+                    const int b = g0 + blk;
+                    const BodyPrep P = fprep[b];
+                    RxGeo g = rx_geo<double, Kinds::Cylinders>(P, R2);
+                    PathPts pts;
+                    if (bit == kBitRefl) {
+                        d3 Q, n3;
+                        refl_point<double, Kinds::Cylinders>(P, g, R2, T, thb[blk * TILE + lane], &Q, &n3);
+                        pts.P0 = T; pts.P1 = Q; pts.P2 = Q; pts.P3 = R2;
+                    } else {
+                        cyl_creep<R, double>(P, g, R2, T, L, (bit & 1) ? -1 : 1, bit >> 1,
+                                             (PathEval<R>*)nullptr, &pts);
                     }
-                    double th;
-                    if (L.lit_branch && refl_angle<Kinds::Cylinders, (sizeof(R) == 8)>(P, g, R3, T, &th)) {
-                        cand |= 1u << kBitRefl;
-                        thb[bl * TILE + tid] = th;
+                    bool vis = true;
+#pragma unroll 1
+                    for (int leg = 0; leg < 2 && vis; ++leg) {
+                        d3 a = leg ? pts.P2 : pts.P0, c = leg ? pts.P3 : pts.P1;
+                        vis = !seg_blocked(a, c, L, nullptr, fcyl, b, L.bodies_occlude != 0, nodes, tris,
+                                           stk, TILE);
                     }
-                    if (cand) {
-                        int q = atomicAdd(&s_qn, __builtin_popcount(cand));
-                        for (int bit = 0; bit <= kBitRefl; ++bit)
-                            if ((cand >> bit) & 1u) s_q[q++] = (uint32_t)tid | ((uint32_t)bl << 8) | ((uint32_t)bit << 13);
+                    if (vis) {
+                        const int mb = blk * TILE + lane;
+                        atomicOr(&s_mask[mb >> 2], (1u << bit) << (8 * (mb & 3)));
                     }
                 }
                 __syncthreads();
-                // --- 2. drain the queue when the next body might not fit ---
-                // every wave reads the count before any wave appends the next
-                // body's candidates, so the drain decision is workgroup-uniform
-                const int qn = s_qn;
+                if (tid == 0) s_qn = 0;
                 __syncthreads();
-                if (qn > QCAP - TILE * per_pair || bl == ng - 1) {
-                    for (int k = tid; k < qn; k += TILE) {
-                        const uint32_t key = s_q[k];
-                        const int lane = (int)(key & 0xffu), blk = (int)((key >> 8) & 0x1fu), bit = (int)(key >> 13);
+            };
+            // --- 1. cull: the (receiver, body) pairs whose heights can reach
+            // the lateral surface, queued in LDS a sub-group of bodies at a
+            // time, so the classification below runs with every lane busy
+#pragma unroll 1
+            for (int c0 = 0; c0 < ng; c0 += kPGroup) {
+                const int nc = ng - c0 < kPGroup ? ng - c0 : kPGroup;
+                if (tid == 0) s_pn = 0;
+                __syncthreads();
+                for (int bl = c0; bl < c0 + nc; ++bl) {
+                    const bool ok = act && !dead && cyl_paths_possible(fprep[g0 + bl], R3, T, L);
+                    if (ok) s_pq[atomicAdd(&s_pn, 1)] = (uint16_t)((uint32_t)tid | ((uint32_t)bl << 8));
+                }
+                __syncthreads();
+                const int np = s_pn;
+                // --- 2. classification of the queued pairs, TILE at a time:
+                // candidate paths (geometry, reflection point) into the
+                // candidate queue; drained whenever another chunk might not fit
+#pragma unroll 1
+                for (int base = 0; base < np; base += TILE) {
+                    const int k = base + tid;
+                    if (k < np) {
+                        const uint32_t pk = s_pq[k];
+                        const int lane = (int)(pk & 0xffu), bl = (int)(pk >> 8);
                         const int64_t i2 = r0 + lbase + lane;
                         const d3 R2 = mk(rx[3 * i2], rx[3 * i2 + 1], rx[3 * i2 + 2]);
-                        const int b = g0 + blk;
-                        const BodyPrep P = fprep[b];
+                        const BodyPrep P = fprep[g0 + bl];
                         RxGeo g = rx_geo<double, Kinds::Cylinders>(P, R2);
-                        PathPts pts;
-                        if (bit == kBitRefl) {
-                            d3 Q, n3;
-                            refl_point<double, Kinds::Cylinders>(P, g, R2, T, thb[blk * TILE + lane], &Q, &n3);
-                            pts.P0 = T; pts.P1 = Q; pts.P2 = Q; pts.P3 = R2;
-                        } else {
-                            cyl_creep<R, double>(P, g, R2, T, L, (bit & 1) ? -1 : 1, bit >> 1, (PathEval<R>*)nullptr,
-                                                 &pts);
+                        uint32_t cand = 0;
+                        for (int bit = 0; bit < n_creep; ++bit) {
+                            PathPts pts;
+                            if (cyl_creep<R, double>(P, g, R2, T, L, (bit & 1) ? -1 : 1, bit >> 1,
+                                                     (PathEval<R>*)nullptr, &pts))
+                                cand |= 1u << bit;
                         }
-                        bool vis = true;
-#pragma unroll 1
-                        for (int leg = 0; leg < 2 && vis; ++leg) {
-                            d3 a = leg ? pts.P2 : pts.P0, c = leg ? pts.P3 : pts.P1;
-                            vis = !seg_blocked(a, c, L, nullptr, fcyl, b, L.bodies_occlude != 0, nodes, tris, stk,
-                                               TILE);
+                        double th;
+                        if (L.lit_branch && refl_angle<Kinds::Cylinders, (sizeof(R) == 8)>(P, g, R2, T, &th)) {
+                            cand |= 1u << kBitRefl;
+                            thb[bl * TILE + lane] = th;
                         }
-                        if (vis) {
-                            const int mb = blk * TILE + lane;
-                            atomicOr(&s_mask[mb >> 2], (1u << bit) << (8 * (mb & 3)));
+                        if (cand) {
+                            int q = atomicAdd(&s_qn, __builtin_popcount(cand));
+                            for (int bit = 0; bit <= kBitRefl; ++bit)
+                                if ((cand >> bit) & 1u)
+                                    s_q[q++] = (uint32_t)lane | ((uint32_t)bl << 8) | ((uint32_t)bit << 13);
                         }
                     }
                     __syncthreads();
-                    if (tid == 0) s_qn = 0;
+                    // every wave reads the count before any wave appends more,
+                    // so the drain decision is workgroup-uniform
+                    const int qn = s_qn;
                     __syncthreads();
+                    if (qn > QCAP - TILE * per_pair) drain(qn);
                 }
             }
-            // --- 3. field of this group's visible paths ---------------------
+            // every write of the count was followed by a barrier
+            const int qe = s_qn;
+            if (qe > 0) drain(qe);
+            // --- 4. field of this group's visible paths ---------------------
             // Each lane walks its own visible paths (creeping paths in
             // (body, bit) order, then the reflections), so a wavefront runs
             // as many iterations as its busiest lane: walking the bodies and
