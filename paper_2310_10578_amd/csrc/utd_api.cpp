@@ -592,6 +592,7 @@ utd_status utd_smooth_field_batched(const utd_scene* scene, int64_t n_frames, co
     if (n_frames > ((int64_t)1 << 31) / 8) return fail(UTD_E_ARG, "too many frames");
     if (n_cyl && !cyl) return fail(UTD_E_ARG, "cyl is NULL with n_cyl > 0");
     if (n_rx < 0 || n_f < 0) return fail(UTD_E_ARG, "negative n_rx or n_f");
+    if (n_rx > INT32_MAX) return fail(UTD_E_ARG, "at most 2^31 - 1 receivers per batched call");
     if (n_rx && !rx) return fail(UTD_E_ARG, "rx is NULL");
     if (n_f && !freqs) return fail(UTD_E_ARG, "freqs is NULL");
     if (!tx || !opt) return fail(UTD_E_ARG, "tx and opt must not be NULL");
@@ -626,16 +627,9 @@ utd_status utd_smooth_field_batched(const utd_scene* scene, int64_t n_frames, co
     if (e != hipSuccess) return hip_fail(e, "device attribute");
     int n_blocks = g_batch_bpc * (ncu > 0 ? ncu : 1);
 
-    // workspace: body and frequency constants, sanitised offsets, tile prefix sum, counter
-    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    size_t o_prep = 0;
-    size_t o_fc = up(o_prep + sizeof(utd::BodyPrep) * (size_t)(n_cyl > 0 ? n_cyl : 1));
-    size_t o_bo = up(o_fc + sizeof(utd::FreqConst) * (size_t)n_f);
-    size_t o_ro = up(o_bo + sizeof(int64_t) * (size_t)(n_frames + 1));
-    size_t o_to = up(o_ro + sizeof(int64_t) * (size_t)(n_frames + 1));
-    size_t o_cnt = up(o_to + sizeof(int64_t) * (size_t)(n_frames + 1));
-    size_t o_th = up(o_cnt + 256);
-    size_t need = o_th + utd::batch_scratch_bytes(n_blocks);
+    // workspace: body and frequency constants, sanitised offsets, tile prefix
+    // sum, counter, receiver order, per-block angle and field scratch
+    const size_t need = utd::batch_workspace(B, opt->precision, n_blocks, nullptr, nullptr);
 
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     e = hipStreamIsCapturing(s, &cs);
@@ -655,13 +649,12 @@ utd_status utd_smooth_field_batched(const utd_scene* scene, int64_t n_frames, co
         st.ws_bytes = need;
         st.key.clear();
     }
-    char* w = st.ws;
+    utd::BatchWs w;
+    utd::batch_workspace(B, opt->precision, n_blocks, st.ws, &w);
     auto launch = [&](hipStream_t ls) {
-        return utd::launch_batch(B, opt->precision, n_blocks, body_off, rx_off, rx, cyl, freqs,
-                                 (utd::BodyPrep*)(w + o_prep), (utd::FreqConst*)(w + o_fc), (int64_t*)(w + o_bo),
-                                 (int64_t*)(w + o_ro), (int64_t*)(w + o_to), (unsigned*)(w + o_cnt),
-                                 scene ? scene->d_nodes : nullptr, scene ? scene->d_tris : nullptr,
-                                 (double*)(w + o_th), E_out, rx_flags, ls);
+        return utd::launch_batch(B, opt->precision, n_blocks, body_off, rx_off, rx, cyl, freqs, w,
+                                 scene ? scene->d_nodes : nullptr, scene ? scene->d_tris : nullptr, E_out, rx_flags,
+                                 ls);
     };
     if (caller_capturing) {
         // the caller records these launches into its own graph

@@ -41,12 +41,25 @@ hipError_t launch_adjoint(const LaunchParams& L, int precision, const float* rx,
                           const uint8_t* flags, const void* gE, char* scratch, void* d_sph, void* d_cyl, void* d_tx,
                           hipStream_t s);
 
-size_t batch_scratch_bytes(int n_blocks);
+// Device workspace of a batched call, carved from one allocation by
+// batch_workspace (which returns its size in bytes; base may be NULL to size).
+struct BatchWs {
+    BodyPrep* prep;          // per cylinder
+    FreqConst* fcs;          // per frequency
+    int64_t* bo;             // sanitised body offsets (n_frames + 1)
+    int64_t* ro;             // sanitised receiver offsets (n_frames + 1)
+    int64_t* tile_off;       // tile prefix sum (n_frames + 1)
+    unsigned* counter;       // work-queue counter
+    uint16_t* key;           // per receiver: spatial cell
+    int* perm;               // per receiver: frame-local index at each sorted position
+    double* th;              // per block: reflection angles of a body group
+    void* ew;                // per block: the tile's field
+};
+size_t batch_workspace(const BatchParams& B, int precision, int n_blocks, char* base, BatchWs* ws);
 hipError_t launch_batch(const BatchParams& B, int precision, int n_blocks, const int64_t* body_off,
                         const int64_t* rx_off, const float* rx, const float* cyl, const double* freqs,
-                        BodyPrep* prep, FreqConst* fcs, int64_t* bo, int64_t* ro, int64_t* tile_off,
-                        unsigned* counter, const float4* nodes, const float4* tris, double* th, void* E,
-                        uint8_t* flags, hipStream_t s);
+                        const BatchWs& ws, const float4* nodes, const float4* tris, void* E, uint8_t* flags,
+                        hipStream_t s);
 
 // Scratch of the allocation-free entry point: a static device array of
 // kNoAllocScratchBytes; noalloc_scratch gives its address on the current
