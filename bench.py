@@ -311,10 +311,8 @@ def field_measure(name, steps, warmup):
 def adjoint_measure(steps):
     """Forward and backward (loss = sum |E|^2, dL/dE = 2E) on the room with
     64 cylinders, 128 x 128 receivers, 16 frequencies, FP32: the backward from
-    scratch (it repeats classification and visibility) and from the state the
-    forward call saved."""
-    import torch
-
+    scratch (it repeats classification and visibility) and the backward from
+    the state a forward call saved (the autograd path)."""
     import paper_2310_10578_amd as utd
     d = single_setup("config5")
     step = single_step(d)
@@ -323,19 +321,24 @@ def adjoint_measure(steps):
     fwd = _event_ms(step, steps, 1)
     bwd = _event_ms(lambda: utd.smooth_field_backward(d["scene"], d["sph"], d["cyl"], d["src"], d["rx"], d["freqs"],
                                                       gE), steps, 1)
-    res = {"workload": d["cfg"]["name"], "evals_per_step": d["evals"], "fwd_ms": fwd, "bwd_ms": bwd,
-           "bwd_over_fwd": bwd / fwd, "gradients": 3 + 3 * d["n_body"]}
-    if hasattr(utd, "ForwardState"):
-        def fwd_bwd_saved():
-            st = utd.smooth_field_saved(d["scene"], d["sph"], d["cyl"], d["src"], d["rx"], d["freqs"],
-                                        out=d["out"], flags=d["flags"])
-            utd.smooth_field_backward_saved(st, gE)
-            st.release()
 
-        fb = _event_ms(fwd_bwd_saved, steps, 1)
-        res.update({"fwd_plus_bwd_saved_ms": fb, "bwd_saved_ms": fb - fwd, "bwd_saved_over_fwd": (fb - fwd) / fwd})
+    def fwd_saved():
+        _, _, st = utd.smooth_field_saved(d["scene"], d["sph"], d["cyl"], d["src"], d["rx"], d["freqs"],
+                                          out=d["out"], flags=d["flags"])
+        st.release()
+
+    fs = _event_ms(fwd_saved, steps, 1)
+    _, _, st = utd.smooth_field_saved(d["scene"], d["sph"], d["cyl"], d["src"], d["rx"], d["freqs"], out=d["out"],
+                                      flags=d["flags"])
+    bs = _event_ms(lambda: utd.smooth_field_backward_saved(st, gE), steps, 1)
+    _, kern = _kernel_ms(lambda: utd.smooth_field_backward_saved(st, gE), steps, "backward")
+    st.release()
+    res = {"workload": d["cfg"]["name"], "evals_per_step": d["evals"], "gradients": 3 + 3 * d["n_body"],
+           "fwd_ms": fwd, "bwd_ms": bwd, "bwd_over_fwd": bwd / fwd,
+           "fwd_saved_ms": fs, "bwd_saved_ms": bs, "bwd_saved_over_fwd": bs / fwd,
+           "fwd_evals_per_s": d["evals"] / (fwd / 1e3), "bwd_saved_evals_per_s": d["evals"] / (bs / 1e3),
+           "bwd_saved_kernels_ms_per_step": kern}
     d["scene"].close()
-    del torch
     return res
 
 

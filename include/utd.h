@@ -214,6 +214,37 @@ utd_status utd_smooth_field_backward(const utd_scene *scene, const utd_bodies *b
                                      const void *grad_E, void *d_cyl, void *d_sph, void *d_tx,
                                      void *stream);
 
+/* Forward evaluation that keeps its classification for the adjoint.  Same
+ * inputs, outputs and errors as utd_smooth_field (rx_flags may be NULL), and
+ * additionally *state receives a handle owning one device allocation (made
+ * stream-ordered on `stream`) with the call's body and frequency constants,
+ * path masks, path records, flags and the adjoint's scratch, and copies of
+ * rx and the bodies; the caller's arrays may change afterwards.
+ * utd_smooth_field_backward_saved(state, ...) then gives exactly the
+ * gradients of utd_smooth_field_backward at the forward's inputs (the same
+ * kernels on the same masks and records, bitwise equal) without repeating
+ * the classification and visibility pass.  The state is read-only for the
+ * backward, which may be called several times; a backward on another stream
+ * must be ordered after the forward by the caller.  Release with
+ * utd_forward_state_release (frees on `stream`, NULL-safe).  Memory held per
+ * state: the forward's workspace, about (80 B FP32 / 120 B FP64)
+ * x (2 l_enc + 3) x n_rx x n_bodies for the records plus 64 B per possible
+ * path for the adjoint.
+ * Errors: those of utd_smooth_field; UTD_E_ARG for a NULL state pointer;
+ * UTD_E_UNSUPPORTED with opt->wall_reflections; UTD_E_OOM when the state
+ * cannot be allocated (*state is NULL after any error). */
+typedef struct utd_forward_state utd_forward_state;
+utd_status utd_smooth_field_saved(const utd_scene *scene, const utd_bodies *bodies,
+                                  const utd_source *tx, const float *rx, int64_t n_rx,
+                                  const double *freqs_hz, int n_f, const utd_options *opt,
+                                  void *E_out, uint8_t *rx_flags, utd_forward_state **state,
+                                  void *stream);
+/* Errors: UTD_E_ARG for a NULL state or d_tx, d_cyl / d_sph NULL with a
+ * non-zero count, grad_E NULL with work; UTD_E_DEVICE on launch failure. */
+utd_status utd_smooth_field_backward_saved(const utd_forward_state *state, const void *grad_E,
+                                           void *d_cyl, void *d_sph, void *d_tx, void *stream);
+utd_status utd_forward_state_release(utd_forward_state *state, void *stream);
+
 /* Many frames in one launch (dynamic scenes: a moving crowd over a static
  * room, Sec. III; the field of every frame is that of utd_smooth_field with
  * the frame's cylinders as bodies).  Frame f has the cylinders
@@ -326,8 +357,11 @@ utd_status utd_input_status(uint32_t *bits);
  * stream it launches on; utd_profile_read waits for those events, writes the
  * summed durations in milliseconds and launch counts into ms[k] and count[k]
  * (k = UTD_K_*; arrays of UTD_K_COUNT entries, host) and clears the record.
- * utd_profile_enable(0) stops recording.  Not for concurrent use from
- * several host threads.  Errors: UTD_E_ARG for NULL outputs, UTD_E_DEVICE. */
+ * utd_profile_enable(0) stops recording.  While recording, a batched call
+ * launches its kernels directly instead of replaying its graph, and times
+ * its constants and receiver order (UTD_K_PREP) apart from its persistent
+ * kernel (UTD_K_BATCHED).  Not for concurrent use from several host
+ * threads.  Errors: UTD_E_ARG for NULL outputs, UTD_E_DEVICE. */
 #define UTD_K_PREP 0
 #define UTD_K_OCCLUDE 1
 #define UTD_K_FIELD 2

@@ -22,7 +22,8 @@ EXPORTS = ["utd_default_options", "utd_scene_create", "utd_scene_destroy", "utd_
            "utd_scene_nodes", "utd_smooth_field", "utd_smooth_field_backward", "utd_smooth_field_batched",
            "utd_path_census", "utd_batched_config", "utd_profile_enable", "utd_profile_read", "utd_last_error",
            "utd_path_masks", "utd_input_status", "utd_smooth_field_noalloc", "utd_scene_planes",
-           "utd_scene_set_wall_material", "utd_wall_masks"]
+           "utd_scene_set_wall_material", "utd_wall_masks", "utd_smooth_field_saved",
+           "utd_smooth_field_backward_saved", "utd_forward_state_release"]
 KERNELS = ["prep", "occlude", "field", "backward", "reduce", "batched", "walls"]
 
 
@@ -80,6 +81,13 @@ def load_library(path=LIB_PATH):
     lib.utd_smooth_field_backward.argtypes = [vp, ctypes.POINTER(Bodies), ctypes.POINTER(Source), vp, i64, vp, i32,
                                               ctypes.POINTER(Options), vp, vp, vp, vp, vp]
     lib.utd_smooth_field_backward.restype = i32
+    lib.utd_smooth_field_saved.argtypes = [vp, ctypes.POINTER(Bodies), ctypes.POINTER(Source), vp, i64, vp, i32,
+                                           ctypes.POINTER(Options), vp, vp, ctypes.POINTER(vp), vp]
+    lib.utd_smooth_field_saved.restype = i32
+    lib.utd_smooth_field_backward_saved.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.utd_smooth_field_backward_saved.restype = i32
+    lib.utd_forward_state_release.argtypes = [vp, vp]
+    lib.utd_forward_state_release.restype = i32
     lib.utd_smooth_field_batched.argtypes = [vp, i64, vp, vp, i64, vp, vp, i64, ctypes.POINTER(Source), vp, i32,
                                              ctypes.POINTER(Options), vp, vp, vp]
     lib.utd_batched_config.argtypes = [i32, i32]
@@ -283,6 +291,81 @@ def smooth_field_backward(scene, spheres, cylinders, source, rx, freqs, grad_E, 
     return d_sph, d_cyl, d_tx
 
 
+class ForwardState:
+    """The classification, visibility and path records of one forward call,
+    kept on the device for ``smooth_field_backward_saved`` (the library's
+    utd_forward_state).  ``release()`` frees it on the given stream; it is
+    also released when the object is collected."""
+
+    def __init__(self, handle, n_sph, n_cyl, n_rx, n_f, precision, device, stream):
+        self.handle = handle
+        self.n_sph, self.n_cyl, self.n_rx, self.n_f = n_sph, n_cyl, n_rx, n_f
+        # the stream of the last call that used the state: freeing there
+        # orders the release after that call
+        self.precision, self.device, self.stream = precision, device, stream
+
+    def release(self, stream=None):
+        if self.handle:
+            h, self.handle = self.handle, None
+            _check(load_library().utd_forward_state_release(h, _stream(stream if stream is not None
+                                                                        else self.stream)))
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+def smooth_field_saved(scene, spheres, cylinders, source, rx, freqs, precision=0, l_enc=0, bodies_occlude=True,
+                       lit_branch=True, caustic_guard=1e-6, out=None, flags=None, stream=None):
+    """``smooth_field`` that also returns a ``ForwardState`` for the adjoint:
+    (E, flags, state)."""
+    torch = _torch()
+    lib = load_library()
+    _dev(rx, torch.float32, (3,), "rx")
+    _dev(freqs, torch.float64, None, "freqs")
+    b, keep = _bodies(spheres, cylinders)
+    n, nf = rx.shape[0], freqs.shape[0]
+    cdt = torch.complex64 if precision == 0 else torch.complex128
+    if out is None:
+        out = torch.empty((nf, 3, n), dtype=cdt, device=rx.device)
+    if flags is None:
+        flags = torch.empty((n,), dtype=torch.uint8, device=rx.device)
+    opt = make_options(precision, l_enc, bodies_occlude, lit_branch, caustic_guard)
+    h = ctypes.c_void_p()
+    _check(lib.utd_smooth_field_saved(scene.handle if scene is not None else None, ctypes.byref(b),
+                                      ctypes.byref(source), rx.data_ptr() if n else None, n,
+                                      freqs.data_ptr() if nf else None, nf, ctypes.byref(opt),
+                                      out.data_ptr() if out.numel() else None, flags.data_ptr() if n else None,
+                                      ctypes.byref(h), _stream(stream)))
+    st = ForwardState(h.value, b.n_sph, b.n_cyl, n, nf, precision, rx.device,
+                      stream if stream is not None else torch.cuda.current_stream())
+    return out, flags, st
+
+
+def smooth_field_backward_saved(state, grad_E, stream=None):
+    """Gradients from a ``ForwardState``: (d_sph [ns, 4], d_cyl [nc, 3],
+    d_tx [3]) exactly as ``smooth_field_backward`` at the forward's inputs."""
+    torch = _torch()
+    if not state.handle:
+        raise ValueError("the forward state was released")
+    cdt = torch.complex64 if state.precision == 0 else torch.complex128
+    rdt = torch.float32 if state.precision == 0 else torch.float64
+    _dev(grad_E, cdt, (3, state.n_rx), "grad_E")
+    if grad_E.shape[0] != state.n_f:
+        raise ValueError("grad_E must have shape [n_f, 3, n_rx]")
+    d_sph = torch.empty((state.n_sph, 4), dtype=rdt, device=state.device)
+    d_cyl = torch.empty((state.n_cyl, 3), dtype=rdt, device=state.device)
+    d_tx = torch.empty((3,), dtype=rdt, device=state.device)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(load_library().utd_smooth_field_backward_saved(
+        state.handle, grad_E.data_ptr() if grad_E.numel() else None, d_cyl.data_ptr() if d_cyl.numel() else None,
+        d_sph.data_ptr() if d_sph.numel() else None, d_tx.data_ptr(), _stream(s)))
+    state.stream = s
+    return d_sph, d_cyl, d_tx
+
+
 def _autograd_function():
     torch = _torch()
 
@@ -291,17 +374,17 @@ def _autograd_function():
         def forward(ctx, spheres, cylinders, tx_pos, rx, freqs, scene, dipole, amplitude, kw):
             src = make_source([float(v) for v in tx_pos.detach().cpu().tolist()], dipole, amplitude)
             sph, cyl = spheres.detach().contiguous(), cylinders.detach().contiguous()
-            E, _ = smooth_field(scene, sph, cyl, src, rx, freqs, **kw)
-            ctx.save_for_backward(sph, cyl, rx, freqs)
-            ctx.scene, ctx.src, ctx.kw, ctx.tx_meta = scene, src, kw, (tx_pos.dtype, tx_pos.device)
+            # the forward keeps its classification and records for the backward
+            E, _, st = smooth_field_saved(scene, sph, cyl, src, rx, freqs, **kw)
+            ctx.save_for_backward(sph, cyl)
+            ctx.state, ctx.tx_meta = st, (tx_pos.dtype, tx_pos.device)
             return E
 
         @staticmethod
         def backward(ctx, gE):
-            sph, cyl, rx, freqs = ctx.saved_tensors
-            d_sph, d_cyl3, d_tx = smooth_field_backward(ctx.scene, sph, cyl, ctx.src, rx, freqs,
-                                                        gE.resolve_conj().resolve_neg().contiguous(),
-                                                        **ctx.kw)
+            sph, cyl = ctx.saved_tensors
+            d_sph, d_cyl3, d_tx = smooth_field_backward_saved(ctx.state,
+                                                              gE.resolve_conj().resolve_neg().contiguous())
             d_cyl = torch.zeros(cyl.shape, dtype=d_cyl3.dtype, device=cyl.device)
             d_cyl[:, 0:2] = d_cyl3[:, 0:2]
             d_cyl[:, 4] = d_cyl3[:, 2]

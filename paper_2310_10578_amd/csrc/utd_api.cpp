@@ -4,12 +4,12 @@
 
 #include <cmath>
 #include <cstdarg>
-#include <new>
 #include <cstdio>
 #include <cstring>
 #include <map>
 #include <atomic>
 #include <mutex>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -572,6 +572,117 @@ utd_status utd_smooth_field_backward(const utd_scene* scene, const utd_bodies* b
     return UTD_OK;
 }
 
+// Forward state kept for the adjoint: the call's workspace (body and
+// frequency constants, masks, records, flags) and the adjoint scratch, with
+// copies of the receivers and bodies, in one stream-ordered allocation.
+struct utd_forward_state {
+    utd::LaunchParams L;
+    int precision = 0;
+    hipStream_t stream = nullptr;
+    char* mem = nullptr;
+    Workspace w;
+    const float* rx = nullptr;
+    const float* sph = nullptr;
+    const float* cyl = nullptr;
+    char* adj = nullptr;
+};
+
+utd_status utd_smooth_field_saved(const utd_scene* scene, const utd_bodies* bodies, const utd_source* tx,
+                                  const float* rx, int64_t n_rx, const double* freqs, int n_f,
+                                  const utd_options* opt, void* E_out, uint8_t* rx_flags, utd_forward_state** state,
+                                  void* stream) {
+    if (!state) return fail(UTD_E_ARG, "state is NULL");
+    *state = nullptr;
+    utd_status st = check_common(bodies, tx, rx, n_rx, freqs, n_f, opt);
+    if (st != UTD_OK) return st;
+    if (opt->wall_reflections) return fail(UTD_E_UNSUPPORTED, "wall reflections have no adjoint");
+    const bool work = n_rx > 0 && n_f > 0;
+    if (work && !E_out) return fail(UTD_E_ARG, "E_out is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    utd_forward_state* fs = new (std::nothrow) utd_forward_state();
+    if (!fs) return fail(UTD_E_OOM, "state");
+    fs->L = make_params(scene, bodies, tx, n_rx, n_f, opt);
+    if (!work) fs->L.n_rx = 0;
+    fs->precision = opt->precision;
+    fs->stream = s;
+    const int nb = fs->L.n_sph + fs->L.n_cyl;
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t ws_bytes = up(fs->w.plan(nb, fs->L.n_rx, n_f, opt->l_enc, opt->precision, true));
+    const size_t adj_bytes = up(utd::adjoint_scratch_bytes(fs->L));
+    const size_t rx_bytes = up(sizeof(float) * 3 * (size_t)fs->L.n_rx);
+    const size_t sph_bytes = up(sizeof(float) * 4 * (size_t)bodies->n_sph);
+    const size_t cyl_bytes = up(sizeof(float) * 5 * (size_t)bodies->n_cyl);
+    hipError_t e = hipMallocAsync((void**)&fs->mem, ws_bytes + adj_bytes + rx_bytes + sph_bytes + cyl_bytes, s);
+    if (e != hipSuccess) {
+        delete fs;
+        return e == hipErrorOutOfMemory ? fail(UTD_E_OOM, "state allocation") : hip_fail(e, "hipMallocAsync");
+    }
+    fs->w.bind(fs->mem);
+    char* p = fs->mem + ws_bytes;
+    fs->adj = p; p += adj_bytes;
+    float* crx = (float*)p; p += rx_bytes;
+    float* csph = (float*)p; p += sph_bytes;
+    float* ccyl = (float*)p;
+    fs->rx = crx;
+    fs->sph = bodies->n_sph ? csph : nullptr;
+    fs->cyl = bodies->n_cyl ? ccyl : nullptr;
+    if (work) e = hipMemcpyAsync(crx, rx, sizeof(float) * 3 * (size_t)n_rx, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && bodies->n_sph)
+        e = hipMemcpyAsync(csph, bodies->sph, sizeof(float) * 4 * (size_t)bodies->n_sph, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && bodies->n_cyl)
+        e = hipMemcpyAsync(ccyl, bodies->cyl, sizeof(float) * 5 * (size_t)bodies->n_cyl, hipMemcpyDeviceToDevice, s);
+    const float4* nodes = scene ? scene->d_nodes : nullptr;
+    const float4* tris = scene ? scene->d_tris : nullptr;
+    Workspace& w = fs->w;
+    if (e == hipSuccess && work) {
+        ProfScope ps(UTD_K_OCCLUDE, s);
+        e = utd::launch_paths(fs->L, opt->precision, fs->rx, fs->sph, fs->cyl, freqs, w.prep, w.fc, nodes, tris,
+                              w.mask, w.rec, w.flags, w.ent, w.ent_th, w.vis, w.counters + 12, w.cap, s);
+    }
+    if (e == hipSuccess && work) {
+        ProfScope ps(UTD_K_FIELD, s);
+        e = utd::launch_field(fs->L, opt->precision, pick_fc(opt->precision, n_rx, n_f), fs->rx, w.fc, w.mask, w.rec,
+                              w.flags, E_out, s);
+    }
+    if (e == hipSuccess && work && rx_flags)
+        e = hipMemcpyAsync(rx_flags, w.flags, (size_t)n_rx, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) {
+        (void)hipFreeAsync(fs->mem, s);
+        delete fs;
+        return hip_fail(e, "kernel launch");
+    }
+    *state = fs;
+    return UTD_OK;
+}
+
+utd_status utd_smooth_field_backward_saved(const utd_forward_state* state, const void* grad_E, void* d_cyl,
+                                           void* d_sph, void* d_tx, void* stream) {
+    if (!state) return fail(UTD_E_ARG, "state is NULL");
+    const utd_forward_state* fs = state;
+    if (!d_tx) return fail(UTD_E_ARG, "d_tx is NULL");
+    if (fs->L.n_cyl && !d_cyl) return fail(UTD_E_ARG, "d_cyl is NULL with n_cyl > 0");
+    if (fs->L.n_sph && !d_sph) return fail(UTD_E_ARG, "d_sph is NULL with n_sph > 0");
+    if (fs->L.n_rx > 0 && !grad_E) return fail(UTD_E_ARG, "grad_E is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const Workspace& w = fs->w;
+    hipError_t e;
+    {
+        ProfScope ps(UTD_K_BACKWARD, s);
+        e = utd::launch_adjoint(fs->L, fs->precision, fs->rx, fs->sph, fs->cyl, w.prep, w.fc, w.mask, w.rec, w.flags,
+                                grad_E, fs->adj, d_sph, d_cyl, d_tx, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return UTD_OK;
+}
+
+utd_status utd_forward_state_release(utd_forward_state* state, void* stream) {
+    if (!state) return UTD_OK;
+    hipError_t e = hipFreeAsync(state->mem, (hipStream_t)stream);
+    delete state;
+    if (e != hipSuccess) return hip_fail(e, "hipFreeAsync");
+    return UTD_OK;
+}
+
 utd_status utd_batched_config(int tile_rx, int blocks_per_cu) {
     if (tile_rx != 64 && tile_rx != 128 && tile_rx != 256) return fail(UTD_E_ARG, "tile_rx must be 64, 128 or 256");
     if (blocks_per_cu < 1 || blocks_per_cu > 16) return fail(UTD_E_ARG, "blocks_per_cu must be in 1..16");
@@ -651,15 +762,27 @@ utd_status utd_smooth_field_batched(const utd_scene* scene, int64_t n_frames, co
     }
     utd::BatchWs w;
     utd::batch_workspace(B, opt->precision, n_blocks, st.ws, &w);
-    auto launch = [&](hipStream_t ls) {
+    auto launch = [&](hipStream_t ls, int part) {
         return utd::launch_batch(B, opt->precision, n_blocks, body_off, rx_off, rx, cyl, freqs, w,
                                  scene ? scene->d_nodes : nullptr, scene ? scene->d_tris : nullptr, E_out, rx_flags,
-                                 ls);
+                                 ls, part);
     };
+    if (g_prof_on && !caller_capturing) {
+        // measurement: the two launches directly, each timed on its own
+        {
+            ProfScope ps(UTD_K_PREP, s);
+            e = launch(s, 1);
+        }
+        if (e == hipSuccess) {
+            ProfScope ps(UTD_K_BATCHED, s);
+            e = launch(s, 2);
+        }
+        return e == hipSuccess ? UTD_OK : hip_fail(e, "kernel launch");
+    }
     if (caller_capturing) {
         // the caller records these launches into its own graph
         ProfScope ps(UTD_K_BATCHED, s);
-        e = launch(s);
+        e = launch(s, 0);
         return e == hipSuccess ? UTD_OK : hip_fail(e, "kernel launch");
     }
     // one graph (prep + persistent kernel) per distinct argument set, replayed
@@ -688,7 +811,7 @@ utd_status utd_smooth_field_batched(const utd_scene* scene, int64_t n_frames, co
         }
         e = hipStreamBeginCapture(st.cap, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-        hipError_t el = launch(st.cap);
+        hipError_t el = launch(st.cap, 0);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(st.cap, &g);
         if (el != hipSuccess || e != hipSuccess) {

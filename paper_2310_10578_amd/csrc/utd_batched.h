@@ -613,18 +613,20 @@ size_t batch_workspace(const BatchParams& B, int precision, int n_blocks, char* 
 hipError_t launch_batch(const BatchParams& B, int precision, int n_blocks, const int64_t* body_off,
                         const int64_t* rx_off, const float* rx, const float* cyl, const double* freqs,
                         const BatchWs& w, const float4* nodes, const float4* tris, void* E, uint8_t* flags,
-                        hipStream_t s) {
-    int64_t nwork = B.n_cyl > B.L.n_f ? B.n_cyl : B.L.n_f;
-    int pb = (int)((nwork + 1023) / 1024);
-    pb = pb < 1 ? 1 : (pb > 1024 ? 1024 : pb);
-    hipLaunchKernelGGL(k_batch_prep, dim3(pb), dim3(1024), 0, s, B, body_off, rx_off, cyl, freqs, w.prep, w.fcs,
-                       w.bo, w.ro, w.tile_off, w.counter);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const int sb = (int)(B.n_frames < 4096 ? B.n_frames : 4096);
-    hipLaunchKernelGGL(k_batch_sort, dim3(sb), dim3(1024), 0, s, B, rx, w.ro, w.key, w.perm);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
+                        hipStream_t s, int part) {
+    if (part != 2) {
+        int64_t nwork = B.n_cyl > B.L.n_f ? B.n_cyl : B.L.n_f;
+        int pb = (int)((nwork + 1023) / 1024);
+        pb = pb < 1 ? 1 : (pb > 1024 ? 1024 : pb);
+        hipLaunchKernelGGL(k_batch_prep, dim3(pb), dim3(1024), 0, s, B, body_off, rx_off, cyl, freqs, w.prep, w.fcs,
+                           w.bo, w.ro, w.tile_off, w.counter);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const int sb = (int)(B.n_frames < 4096 ? B.n_frames : 4096);
+        hipLaunchKernelGGL(k_batch_sort, dim3(sb), dim3(1024), 0, s, B, rx, w.ro, w.key, w.perm);
+        e = hipGetLastError();
+        if (e != hipSuccess || part == 1) return e;
+    }
     if (precision == 0) {
         switch (B.tile) {
             case 64: return launch_batch_tile<float, 64>(B, n_blocks, rx, cyl, w, nodes, tris, E, flags, s);

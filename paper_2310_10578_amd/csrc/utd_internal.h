@@ -56,10 +56,12 @@ struct BatchWs {
     void* ew;                // per block: the tile's field
 };
 size_t batch_workspace(const BatchParams& B, int precision, int n_blocks, char* base, BatchWs* ws);
+// part 0: the whole call; 1: the constants and the receiver order only
+// (k_batch_prep, k_batch_sort); 2: the persistent kernel only.
 hipError_t launch_batch(const BatchParams& B, int precision, int n_blocks, const int64_t* body_off,
                         const int64_t* rx_off, const float* rx, const float* cyl, const double* freqs,
                         const BatchWs& ws, const float4* nodes, const float4* tris, void* E, uint8_t* flags,
-                        hipStream_t s);
+                        hipStream_t s, int part = 0);
 
 // Scratch of the allocation-free entry point: a static device array of
 // kNoAllocScratchBytes; noalloc_scratch gives its address on the current

@@ -338,3 +338,47 @@ def test_random_scenes_vs_oracle(seed):
         e = _err(gg, go)
         _report("random scene %d p%d" % (seed, precision), e)
         assert e <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_saved_forward_state_gives_the_same_field_and_gradients(room_case, precision):
+    """utd_smooth_field_saved returns the field and flags of utd_smooth_field,
+    and utd_smooth_field_backward_saved the gradients of
+    utd_smooth_field_backward, bitwise (the same kernels on the forward's
+    masks and records); the state owns copies of the inputs, so changing the
+    caller's arrays afterwards changes nothing, and it can serve several
+    backward calls."""
+    import torch
+
+    import paper_2310_10578_amd as utd
+    cfg, G, _ = room_case
+    scene = utd.Scene(cfg["scene"].get("tri"))
+    sph, cyl, rxt, ft = _tensors(cfg)
+    tx = cfg["tx"]
+    src = utd.make_source(tx["pos"], tx["dipole"], tx["amplitude"])
+    cdt = torch.complex64 if precision == 0 else torch.complex128
+    gt = torch.from_numpy(np.ascontiguousarray(G)).to(cdt).cuda()
+    E0, f0 = utd.smooth_field(scene, sph, cyl, src, rxt, ft, precision=precision)
+    ref = utd.smooth_field_backward(scene, sph, cyl, src, rxt, ft, gt, precision=precision)
+    E1, f1, st = utd.smooth_field_saved(scene, sph, cyl, src, rxt, ft, precision=precision)
+    torch.cuda.synchronize()
+    assert torch.equal(E0, E1) and torch.equal(f0, f1)
+    # the caller's arrays change after the forward: the state keeps its copies
+    cyl.add_(0.25)
+    rxt.mul_(0.5)
+    for _ in range(2):
+        got = utd.smooth_field_backward_saved(st, gt)
+        torch.cuda.synchronize()
+        for a, b in zip(got, ref):
+            assert torch.equal(a, b)
+    st.release()
+    st.release()
+    with pytest.raises(ValueError):
+        utd.smooth_field_backward_saved(st, gt)
+    # no receivers: the state holds nothing and every gradient is zero
+    E2, _, st2 = utd.smooth_field_saved(scene, sph, cyl, src, rxt[:0], ft, precision=precision)
+    d = utd.smooth_field_backward_saved(st2, torch.zeros((ft.shape[0], 3, 0), dtype=cdt, device="cuda"))
+    torch.cuda.synchronize()
+    assert all(bool(torch.all(x == 0)) for x in d)
+    del st2
+    scene.close()
