@@ -61,9 +61,9 @@ PEAK_FP32_TFLOPS = 78.6
 PEAK_FP32_PUBLISHED_TFLOPS = 157.3
 PEAK_HBM_GBPS = 8000.0
 
-TRAFFIC_PROFILE = {"config2": "profiles/hbm_sphere-plane-64f.md",
-                   "config3": "profiles/hbm_room-512x512-2f.md",
-                   "config4": "profiles/hbm_crowd-256f.md"}
+TRAFFIC_PROFILE = {"config2": "profiles/counters_k_field_sphere-plane-64f.md",
+                   "config3": "profiles/counters_k_vis_room-512x512-2f.md",
+                   "config4": "profiles/counters_k_batch_crowd-256f.md"}
 VIS_KERNELS = ("utd::k_setup", "utd::k_cand<float", "utd::k_vis<float", "utd::k_rec<float", "utd::k_paths<float")
 
 

@@ -226,7 +226,11 @@ utd_status utd_smooth_field_backward(const utd_scene *scene, const utd_bodies *b
  * the classification and visibility pass.  The state is read-only for the
  * backward, which may be called several times; a backward on another stream
  * must be ordered after the forward by the caller.  Release with
- * utd_forward_state_release (frees on `stream`, NULL-safe).  Memory held per
+ * utd_forward_state_release (NULL-safe): the buffer is kept for reuse by the
+ * next saved forward on `stream` (one per device and stream, the largest
+ * seen; a smaller one is freed stream-ordered on `stream`), so steady-state
+ * training steps allocate nothing; the kept buffer lives until the process
+ * ends.  Memory held per
  * state: the forward's workspace, about (80 B FP32 / 120 B FP64)
  * x (2 l_enc + 3) x n_rx x n_bodies for the records plus 64 B per possible
  * path for the adjoint.

@@ -578,14 +578,26 @@ utd_status utd_smooth_field_backward(const utd_scene* scene, const utd_bodies* b
 struct utd_forward_state {
     utd::LaunchParams L;
     int precision = 0;
+    int device = 0;
     hipStream_t stream = nullptr;
     char* mem = nullptr;
+    size_t bytes = 0;
     Workspace w;
     const float* rx = nullptr;
     const float* sph = nullptr;
     const float* cyl = nullptr;
     char* adj = nullptr;
 };
+
+// One released state buffer kept per (device, stream): the next saved
+// forward on that stream reuses it when it is large enough (stream order
+// makes the reuse safe), so a training loop allocates nothing per step.
+struct StateCache {
+    char* p = nullptr;
+    size_t bytes = 0;
+};
+std::mutex g_state_mu;
+std::map<std::pair<int, hipStream_t>, StateCache> g_state_cache;
 
 utd_status utd_smooth_field_saved(const utd_scene* scene, const utd_bodies* bodies, const utd_source* tx,
                                   const float* rx, int64_t n_rx, const double* freqs, int n_f,
@@ -612,10 +624,29 @@ utd_status utd_smooth_field_saved(const utd_scene* scene, const utd_bodies* bodi
     const size_t rx_bytes = up(sizeof(float) * 3 * (size_t)fs->L.n_rx);
     const size_t sph_bytes = up(sizeof(float) * 4 * (size_t)bodies->n_sph);
     const size_t cyl_bytes = up(sizeof(float) * 5 * (size_t)bodies->n_cyl);
-    hipError_t e = hipMallocAsync((void**)&fs->mem, ws_bytes + adj_bytes + rx_bytes + sph_bytes + cyl_bytes, s);
+    const size_t total = ws_bytes + adj_bytes + rx_bytes + sph_bytes + cyl_bytes;
+    hipError_t e = hipGetDevice(&fs->device);
     if (e != hipSuccess) {
         delete fs;
-        return e == hipErrorOutOfMemory ? fail(UTD_E_OOM, "state allocation") : hip_fail(e, "hipMallocAsync");
+        return hip_fail(e, "hipGetDevice");
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_state_mu);
+        StateCache& c = g_state_cache[std::make_pair(fs->device, s)];
+        if (c.p && c.bytes >= total) {
+            fs->mem = c.p;
+            fs->bytes = c.bytes;
+            c.p = nullptr;
+            c.bytes = 0;
+        }
+    }
+    if (!fs->mem) {
+        e = hipMallocAsync((void**)&fs->mem, total, s);
+        if (e != hipSuccess) {
+            delete fs;
+            return e == hipErrorOutOfMemory ? fail(UTD_E_OOM, "state allocation") : hip_fail(e, "hipMallocAsync");
+        }
+        fs->bytes = total;
     }
     fs->w.bind(fs->mem);
     char* p = fs->mem + ws_bytes;
@@ -677,7 +708,19 @@ utd_status utd_smooth_field_backward_saved(const utd_forward_state* state, const
 
 utd_status utd_forward_state_release(utd_forward_state* state, void* stream) {
     if (!state) return UTD_OK;
-    hipError_t e = hipFreeAsync(state->mem, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    char* give_back = state->mem;
+    {
+        // keep the larger of this buffer and the one cached for the stream
+        std::lock_guard<std::mutex> lk(g_state_mu);
+        StateCache& c = g_state_cache[std::make_pair(state->device, s)];
+        if (state->bytes > c.bytes) {
+            give_back = c.p;
+            c.p = state->mem;
+            c.bytes = state->bytes;
+        }
+    }
+    hipError_t e = give_back ? hipFreeAsync(give_back, s) : hipSuccess;
     delete state;
     if (e != hipSuccess) return hip_fail(e, "hipFreeAsync");
     return UTD_OK;
