@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <algorithm>
 #include <atomic>
 #include <mutex>
 #include <new>
@@ -805,10 +806,12 @@ utd_status utd_smooth_field_batched(const utd_scene* scene, int64_t n_frames, co
     }
     utd::BatchWs w;
     utd::batch_workspace(B, opt->precision, n_blocks, st.ws, &w);
+    const int n_main = !scene || !scene->d_nodes ? 0
+                       : (int)(scene->broot >= 0 ? scene->broot : std::min<int64_t>(scene->n_nodes, INT32_MAX));
     auto launch = [&](hipStream_t ls, int part) {
         return utd::launch_batch(B, opt->precision, n_blocks, body_off, rx_off, rx, cyl, freqs, w,
-                                 scene ? scene->d_nodes : nullptr, scene ? scene->d_tris : nullptr, E_out, rx_flags,
-                                 ls, part);
+                                 scene ? scene->d_nodes : nullptr, scene ? scene->d_tris : nullptr, n_main, E_out,
+                                 rx_flags, ls, part);
     };
     if (g_prof_on && !caller_capturing) {
         // measurement: the two launches directly, each timed on its own

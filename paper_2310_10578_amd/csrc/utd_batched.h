@@ -237,6 +237,324 @@ __global__ void __launch_bounds__(1024) k_batch_sort(BatchParams B, const float*
     }
 }
 
+// Visibility profiles of the source-side legs (the incident segments of
+// Eqs. (2) and (4)).  Every creeping path of one (cylinder, side) attaches
+// on the same vertical tangent line (the tangent point of the source's
+// horizontal tangent; only the height depends on the receiver), so the legs
+// from the source to it form a planar fan, and whether a leg is blocked is a
+// function of the attachment height alone: computed once per frame for all
+// receivers (the reuse of diffraction paths across a local area, Sec. III-A).
+//
+// Each occluder cuts the fan in a segment (a triangle) or a rectangle (a
+// cylinder); the rays from the source through the cut reach the tangent
+// line in an interval of heights.  A cut (lo, hi, mlo, mhi) blocks heights
+// in (lo + mlo, hi - mhi) for certain and leaves heights within mlo of lo
+// and mhi of hi undecided.  The margins are the spatial tolerance ds (40
+// FP32 ulps of the scene's largest coordinate) seen from the tangent line
+// (ds / t for a crossing at the leg's parameter t), so outside them the
+// FP32 segment test of the same leg and the exact body tests decide the same
+// way.  A height is blocked if a cut blocks it for certain, else undecided if
+// it lies in a cut's margin, else free; the profile stores that
+// classification of the line's heights as at most kFanRuns runs.  A run
+// boundary, a degenerate cut (a triangle edge in the fan's plane, a
+// cylinder tangent to it), more than kFanCuts cuts or runs, a fan reaching
+// outside the scene box, or a main tree larger than kFanMaxNodes nodes all
+// fall back to testing the leg itself, so the decisions are those of the
+// per-segment tests.
+constexpr int kFanRuns = 16;
+constexpr int kFanCuts = 64;
+constexpr int kFanMaxNodes = 4096;
+constexpr int kFanFree = 0, kFanBlocked = 1, kFanUndecided = 2;
+struct FanProfile {
+    int n;                       // runs; -1: no profile (every leg is tested)
+    float z0;                    // start of the first run
+    float pad[2];
+    float2 run[kFanRuns];        // (end height, status)
+};
+
+// kFanFree: no occluder blocks the leg ending at height z; kFanBlocked;
+// kFanUndecided: test the leg.
+__device__ __forceinline__ int fan_lookup(const FanProfile* __restrict__ F, double z) {
+    const int n = F->n;
+    const float zf = (float)z;
+    if (n <= 0 || !(zf > F->z0 + 1e-6f)) return kFanUndecided;
+    for (int i = 0; i < n; ++i) {
+        const float2 r = F->run[i];
+        if (zf < r.x - 1e-6f) return (int)r.y;
+        if (zf <= r.x + 1e-6f) return kFanUndecided;      // at a run boundary
+    }
+    return kFanUndecided;                                  // above the last run
+}
+
+// Cuts of one fan (source T, horizontal unit direction (dx, dy) towards the
+// tangent line at horizontal distance U), appended to an LDS list.
+struct FanGeo {
+    double tx, ty, tz, dx, dy, U, ds;
+    double zmin, zmax;           // the heights that matter (the line's, widened)
+    __device__ double zline(double u, double w) const { return tz + (w - tz) * U / u; }
+};
+
+// Appends one cut (unless it lies wholly outside the heights that matter);
+// returns false when the list is full.
+__device__ __forceinline__ bool fan_put(const FanGeo& F, float4* cuts, int* ncut, double lo, double hi, double mlo,
+                                        double mhi) {
+    if (hi + mhi < F.zmin || lo - mlo > F.zmax) return true;
+    const int k = atomicAdd(ncut, 1);
+    if (k >= kFanCuts) return false;
+    cuts[k] = make_float4((float)lo, (float)hi, (float)mlo + 1e-6f, (float)mhi + 1e-6f);
+    return true;
+}
+
+// The segment (ua, wa)-(ub, wb) of the fan's plane inside an occluder; with
+// `edge` (a cut along a triangle edge or through a vertex) its whole image
+// is undecided.  Returns false on overflow.
+__device__ __forceinline__ bool fan_segment(const FanGeo& F, float4* cuts, int* ncut, double ua, double wa,
+                                            double ub, double wb, bool edge) {
+    const double e0 = 1e-6 * F.U, e1 = (1.0 - 1e-6) * F.U;  // open leg parameter (kSegEps)
+    double t0 = 0.0, t1 = 1.0;
+    const double du = ub - ua;
+    if (du != 0.0) {
+        double ta = (e0 - ua) / du, tb = (e1 - ua) / du;
+        if (ta > tb) { const double x = ta; ta = tb; tb = x; }
+        t0 = fmax(t0, ta);
+        t1 = fmin(t1, tb);
+    } else if (ua < e0 || ua > e1) {
+        return true;
+    }
+    if (t0 > t1) return true;
+    const double u0 = ua + t0 * du, w0 = wa + t0 * (wb - wa);
+    const double u1 = ua + t1 * du, w1 = wa + t1 * (wb - wa);
+    const double z0 = F.zline(u0, w0), z1 = F.zline(u1, w1);
+    const double m0 = F.ds * F.U / u0, m1 = F.ds * F.U / u1;
+    const double lo = fmin(z0, z1), hi = fmax(z0, z1);
+    const double mlo = z0 <= z1 ? m0 : m1, mhi = z0 <= z1 ? m1 : m0;
+    if (edge) {
+        const double mid = 0.5 * (lo + hi), half = 0.5 * (hi - lo) + fmax(mlo, mhi);
+        return fan_put(F, cuts, ncut, mid, mid, half, half);
+    }
+    return fan_put(F, cuts, ncut, lo, hi, mlo, mhi);
+}
+
+// A scene triangle; returns false on overflow or a degenerate cut.
+__device__ __forceinline__ bool fan_triangle(const FanGeo& F, float4* cuts, int* ncut, float4 a, float4 b, float4 c) {
+    const double vx[3] = {a.x, b.x, c.x}, vy[3] = {a.y, b.y, c.y}, vz[3] = {a.z, b.z, c.z};
+    double sd[3];
+    int on = 0, pos = 0, neg = 0;
+    const double tol = 1e-12 * (1.0 + fabs(F.tx) + fabs(F.ty) + F.U);
+    for (int i = 0; i < 3; ++i) {
+        sd[i] = -F.dy * (vx[i] - F.tx) + F.dx * (vy[i] - F.ty);
+        if (fabs(sd[i]) <= tol) { sd[i] = 0.0; ++on; }
+        else if (sd[i] > 0.0) ++pos;
+        else ++neg;
+    }
+    if (on == 3) return false;                         // in the fan's plane
+    if (on == 0 && (pos == 0 || neg == 0)) return true;
+    double pu[3], pw[3];
+    int np = 0;
+    for (int i = 0; i < 3; ++i) {
+        const int j = i == 2 ? 0 : i + 1;
+        if (sd[i] == 0.0) {
+            pu[np] = F.dx * (vx[i] - F.tx) + F.dy * (vy[i] - F.ty);
+            pw[np] = vz[i];
+            ++np;
+        }
+        if ((sd[i] < 0.0 && sd[j] > 0.0) || (sd[i] > 0.0 && sd[j] < 0.0)) {
+            const double f = sd[i] / (sd[i] - sd[j]);
+            const double x = vx[i] + f * (vx[j] - vx[i]), y = vy[i] + f * (vy[j] - vy[i]);
+            pu[np] = F.dx * (x - F.tx) + F.dy * (y - F.ty);
+            pw[np] = vz[i] + f * (vz[j] - vz[i]);
+            ++np;
+        }
+    }
+    if (np < 2) return np == 1 ? fan_segment(F, cuts, ncut, pu[0], pw[0], pu[0], pw[0], true) : true;
+    return fan_segment(F, cuts, ncut, pu[0], pw[0], pu[1], pw[1], on >= 2);
+}
+
+// Another solid vertical cylinder (cx, cy, z0, h, a); false on overflow or
+// a cylinder tangent to the fan's plane.
+__device__ __forceinline__ bool fan_cylinder(const FanGeo& F, float4* cuts, int* ncut, const float* cq) {
+    const double cx = cq[0], cy = cq[1], cz0 = cq[2], ch = cq[3], ca = cq[4];
+    const double dc = -F.dy * (cx - F.tx) + F.dx * (cy - F.ty);
+    if (fabs(dc) >= ca + F.ds) return true;
+    if (fabs(dc) > ca - F.ds) return false;
+    const double hc = sqrt((ca - dc) * (ca + dc));
+    const double uc = F.dx * (cx - F.tx) + F.dy * (cy - F.ty);
+    const double e0 = 1e-6 * F.U, e1 = (1.0 - 1e-6) * F.U;
+    const double u0 = fmax(uc - hc, e0), u1 = fmin(uc + hc, e1);
+    if (u0 >= u1) return true;
+    const double w0 = cz0, w1 = cz0 + ch;
+    const double za = F.zline(u0, w0), zb = F.zline(u0, w1), zc = F.zline(u1, w0), zd = F.zline(u1, w1);
+    const double lo = fmin(fmin(za, zb), fmin(zc, zd)), hi = fmax(fmax(za, zb), fmax(zc, zd));
+    const double m = F.ds * F.U / u0;                  // the larger of the two columns' margins
+    return fan_put(F, cuts, ncut, lo, hi, m, m);
+}
+
+// One wavefront per (cylinder, side) of the call, four per workgroup: the
+// fan profiles of every frame, from the sanitised body offsets and the body
+// constants of k_batch_prep.  Lanes share the cuts: the main tree's nodes
+// (n_main of them) and the frame's cylinders are strided over the lanes.
+__global__ void __launch_bounds__(256) k_batch_fans(BatchParams B, const float* __restrict__ cyl,
+                                                    const BodyPrep* __restrict__ prep,
+                                                    const int64_t* __restrict__ bo, const float4* __restrict__ nodes,
+                                                    const float4* __restrict__ tris, int n_main,
+                                                    FanProfile* __restrict__ fans) {
+    __shared__ float4 s_cut[4][kFanCuts];
+    __shared__ float s_bp[4][4 * kFanCuts + 2];
+    __shared__ float s_srt[4][4 * kFanCuts + 2];
+    __shared__ int s_st[4][4 * kFanCuts + 2];
+    __shared__ int s_n[4];
+    __shared__ int s_bad[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t k = (int64_t)blockIdx.x * 4 + w;          // (cylinder, side) of this wavefront
+    if (k >= 2 * B.n_cyl) return;                            // wave-uniform
+    FanProfile* out = fans + k;
+    const int64_t g = k >> 1;
+    const int sgn = (k & 1) ? -1 : 1;
+    if (lane == 0) { s_n[w] = 0; s_bad[w] = 0; }
+    __builtin_amdgcn_wave_barrier();
+    // frame of cylinder g: the last f with bo[f] <= g (empty frames skipped)
+    int64_t lo = 0, hi = B.n_frames;
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (bo[mid] <= g) lo = mid; else hi = mid;
+    }
+    const BodyPrep P = prep[g];
+    const LaunchParams& L = B.L;
+    bool ok = B.n_frames > 0 && bo[lo] <= g && g < bo[lo + 1] && P.ok && n_main <= kFanMaxNodes;
+    // the tangent line, as the creeping path computes its attachment point
+    const double a = P.a, idT = grcp(P.dT);
+    const double cgT = a * idT, sgT = P.sI0 * idT;
+    const double c1 = P.eT[0] * cgT - (double)sgn * P.eT[1] * sgT, s1 = P.eT[1] * cgT + (double)sgn * P.eT[0] * sgT;
+    const double xt = P.c[0] + a * c1, yt = P.c[1] + a * s1;
+    const double zl0 = P.z0, zl1 = P.z0 + P.h;
+    FanGeo F;
+    F.tx = L.T[0]; F.ty = L.T[1]; F.tz = L.T[2];
+    const double hx = xt - F.tx, hy = yt - F.ty;
+    F.U = sqrt(hx * hx + hy * hy);
+    ok = ok && F.U > 1e-9 && isfinite(F.U);
+    F.dx = ok ? hx / F.U : 1.0; F.dy = ok ? hy / F.U : 0.0;
+    const double ext = fmax(fmax(fmax(fabs(F.tx), fabs(F.ty)), fmax(fabs(F.tz), fabs(xt))),
+                            fmax(fmax(fabs(yt), fabs(zl0)), fabs(zl1)));
+    F.ds = 4e-6 * (1.0 + ext);
+    F.zmin = zl0 - 1e-3;
+    F.zmax = zl1 + 1e-3;
+    // segments reaching outside the scene box walk the boundary tree too:
+    // those fans are not profiled
+    if (ok && nodes && L.broot >= 0) {
+        auto inb = [&](double x, double y, double z) {
+            const float fx = (float)x, fy = (float)y, fz = (float)z;
+            return fx >= L.blo[0] && fx <= L.bhi[0] && fy >= L.blo[1] && fy <= L.bhi[1] && fz >= L.blo[2] &&
+                   fz <= L.bhi[2];
+        };
+        ok = inb(F.tx, F.ty, F.tz) && inb(xt, yt, zl0) && inb(xt, yt, zl1);
+    }
+    if (!ok) {
+        if (lane == 0) out->n = -1;
+        return;
+    }
+    float4* cuts = s_cut[w];
+    int* ncut = &s_n[w];
+    bool good = true;
+    if (nodes) {
+        // leaves of the main tree whose boxes meet the fan's box, the nodes
+        // strided over the lanes
+        const float pad = (float)F.ds;
+        const float bx0 = (float)fmin(F.tx, xt) - pad, bx1 = (float)fmax(F.tx, xt) + pad;
+        const float by0 = (float)fmin(F.ty, yt) - pad, by1 = (float)fmax(F.ty, yt) + pad;
+        const float bz0 = (float)fmin(F.tz, zl0) - pad, bz1 = (float)fmax(F.tz, zl1) + pad;
+        for (int nd = lane; nd < n_main && good; nd += 64) {
+            const float4 q0 = nodes[4 * nd], q1 = nodes[4 * nd + 1], q2 = nodes[4 * nd + 2];
+            const int4 q3 = *reinterpret_cast<const int4*>(&nodes[4 * nd + 3]);
+            for (int c = 0; c < 2 && good; ++c) {
+                const int first = c ? q3.z : q3.x, cnt = c ? q3.w : q3.y;
+                if (first < 0 || cnt <= 0) continue;           // empty or an inner child
+                const float lx = c ? q1.z : q0.x, ly = c ? q1.w : q0.y, lz = c ? q2.x : q0.z;
+                const float ux = c ? q2.y : q0.w, uy = c ? q2.z : q1.x, uz = c ? q2.w : q1.y;
+                if (!(lx <= bx1 && ux >= bx0 && ly <= by1 && uy >= by0 && lz <= bz1 && uz >= bz0)) continue;
+                for (int t = first; t < first + cnt && good; ++t)
+                    good = fan_triangle(F, cuts, ncut, tris[3 * t], tris[3 * t + 1], tris[3 * t + 2]);
+            }
+        }
+    }
+    if (L.bodies_occlude)
+        for (int64_t j = bo[lo] + lane; j < bo[lo + 1] && good; j += 64)
+            if (j != g) good = fan_cylinder(F, cuts, ncut, cyl + 5 * j);
+    if (!good) atomicOr(&s_bad[w], 1);
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const int nc = s_n[w];
+    if (s_bad[w] || nc > kFanCuts) {
+        if (lane == 0) out->n = -1;
+        return;
+    }
+    // breakpoints: the four margin edges of every cut, within the line's
+    // heights widened by a little
+    const float za = (float)zl0 - 1e-3f, zb = (float)zl1 + 1e-3f;
+    float* bp = s_bp[w];
+    const int nb = 4 * nc + 2;
+    for (int i = lane; i < nb; i += 64) {
+        float v;
+        if (i >= 4 * nc) {
+            v = i == 4 * nc ? za : zb;
+        } else {
+            const float4 q = cuts[i >> 2];
+            const int e = i & 3;
+            v = e == 0 ? q.x - q.z : (e == 1 ? q.x + q.z : (e == 2 ? q.y - q.w : q.y + q.w));
+        }
+        bp[i] = fminf(fmaxf(v, za), zb);
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    // sort by rank (ties broken by index)
+    float* srt = s_srt[w];
+    for (int i = lane; i < nb; i += 64) {
+        const float v = bp[i];
+        int r = 0;
+        for (int j = 0; j < nb; ++j) r += (bp[j] < v || (bp[j] == v && j < i)) ? 1 : 0;
+        srt[r] = v;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    // status of every gap between consecutive breakpoints, at its middle
+    int* st = s_st[w];
+    for (int i = lane; i + 1 < nb; i += 64) {
+        const float z = 0.5f * (srt[i] + srt[i + 1]);
+        bool blk = false, und = false;
+        for (int c = 0; c < nc; ++c) {
+            const float4 q = cuts[c];
+            blk |= z > q.x + q.z && z < q.y - q.w;
+            und |= fabsf(z - q.x) <= q.z || fabsf(z - q.y) <= q.w;
+        }
+        st[i] = blk ? kFanBlocked : (und ? kFanUndecided : kFanFree);
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    if (lane == 0) {
+        // runs: consecutive gaps of one status merged (empty gaps skipped)
+        int nr = 0, cur = -1;
+        float2 run[kFanRuns];
+        bool over = false;
+        for (int i = 0; i + 1 < nb; ++i) {
+            if (!(srt[i + 1] > srt[i])) continue;
+            if (st[i] == cur) {
+                run[nr - 1].x = srt[i + 1];
+            } else if (nr < kFanRuns) {
+                run[nr++] = make_float2(srt[i + 1], (float)st[i]);
+                cur = st[i];
+            } else {
+                over = true;
+            }
+        }
+        if (over || nr == 0) {
+            out->n = -1;
+        } else {
+            out->z0 = srt[0];
+            for (int i = 0; i < nr; ++i) out->run[i] = run[i];
+            out->n = nr;
+        }
+    }
+}
+
 __device__ __forceinline__ int64_t uniform64(int64_t v) {
     uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
     uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
@@ -283,7 +601,8 @@ __global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(3, 8)
                                                 unsigned* __restrict__ counter, const float4* __restrict__ nodes,
                                                 const float4* __restrict__ tris, double* __restrict__ th_scratch,
                                                 const int* __restrict__ perm, R* __restrict__ ew_scratch,
-                                                R* __restrict__ E_out, uint8_t* __restrict__ flags) {
+                                                const FanProfile* __restrict__ fans, R* __restrict__ E_out,
+                                                uint8_t* __restrict__ flags) {
     static_assert(TILE <= 256, "lane index is stored in 8 bits");
     constexpr int QCAP = 8 * TILE;
     __shared__ int stack[kStackDepth * TILE];
@@ -340,6 +659,7 @@ __global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(3, 8)
         const int nbf = L.n_cyl;
         const float* fcyl = cyl + 5 * b0;
         const BodyPrep* fprep = prep + b0;
+        const FanProfile* ffan = fans + 2 * b0;
         R* E = E_out + 2 * 3 * (int64_t)B.L.n_f * r0;
         const int64_t i = r0 + src;
         const float rxx = act ? rx[3 * i] : 0.0f, rxy = act ? rx[3 * i + 1] : 0.0f, rxz = act ? rx[3 * i + 2] : 0.0f;
@@ -412,9 +732,17 @@ __global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(3, 8)
                         cyl_creep<R, double>(P, g, R2, T, L, (bit & 1) ? -1 : 1, bit >> 1,
                                              (PathEval<R>*)nullptr, &pts);
                     }
+                    // a creeping path's source-side leg: the frame's profile of
+                    // its (body, side) decides unless the height is undecided
                     bool vis = true;
+                    int leg = 0;
+                    if (bit != kBitRefl) {
+                        const int fv = fan_lookup(ffan + 2 * b + (bit & 1), pts.P1.z);
+                        vis = fv != 1;
+                        leg = fv == 0 ? 1 : 0;
+                    }
 #pragma unroll 1
-                    for (int leg = 0; leg < 2 && vis; ++leg) {
+                    for (; leg < 2 && vis; ++leg) {
                         d3 a = leg ? pts.P2 : pts.P0, c = leg ? pts.P3 : pts.P1;
                         vis = !seg_blocked(a, c, L, nullptr, fcyl, b, L.bodies_occlude != 0, nodes, tris,
                                            stk, TILE);
@@ -565,7 +893,7 @@ static hipError_t launch_batch_tile(const BatchParams& B, int n_blocks, const fl
                                     const BatchWs& w, const float4* nodes, const float4* tris, void* E,
                                     uint8_t* flags, hipStream_t s) {
     hipLaunchKernelGGL((k_batch<R, TILE>), dim3(n_blocks), dim3(TILE), 0, s, B, rx, cyl, w.prep, w.fcs, w.bo, w.ro,
-                       w.tile_off, w.counter, nodes, tris, w.th, w.perm, (R*)w.ew, (R*)E, flags);
+                       w.tile_off, w.counter, nodes, tris, w.th, w.perm, (R*)w.ew, w.fans, (R*)E, flags);
     return hipGetLastError();
 }
 
@@ -592,6 +920,7 @@ size_t batch_workspace(const BatchParams& B, int precision, int n_blocks, char* 
     const size_t o_key = take(sizeof(uint16_t) * (size_t)B.n_rx);
     const size_t o_perm = take(sizeof(int) * (size_t)B.n_rx);
     const size_t o_th = take(sizeof(double) * (size_t)n_blocks * kBGroup * B.tile);
+    const size_t o_fan = take(sizeof(FanProfile) * 2 * (size_t)(B.n_cyl > 0 ? B.n_cyl : 1));
     const size_t ew_bytes = real * 2 * 3 * (size_t)B.L.n_f * (size_t)n_blocks * B.tile;
     const bool use_ew = ew_bytes <= kBatchFieldScratchMax;
     const size_t o_ew = take(use_ew ? ew_bytes : 0);
@@ -605,6 +934,7 @@ size_t batch_workspace(const BatchParams& B, int precision, int n_blocks, char* 
         ws->key = (uint16_t*)(base + o_key);
         ws->perm = (int*)(base + o_perm);
         ws->th = (double*)(base + o_th);
+        ws->fans = (FanProfile*)(base + o_fan);
         ws->ew = use_ew ? base + o_ew : nullptr;
     }
     return o;
@@ -612,8 +942,8 @@ size_t batch_workspace(const BatchParams& B, int precision, int n_blocks, char* 
 
 hipError_t launch_batch(const BatchParams& B, int precision, int n_blocks, const int64_t* body_off,
                         const int64_t* rx_off, const float* rx, const float* cyl, const double* freqs,
-                        const BatchWs& w, const float4* nodes, const float4* tris, void* E, uint8_t* flags,
-                        hipStream_t s, int part) {
+                        const BatchWs& w, const float4* nodes, const float4* tris, int n_main, void* E,
+                        uint8_t* flags, hipStream_t s, int part) {
     if (part != 2) {
         int64_t nwork = B.n_cyl > B.L.n_f ? B.n_cyl : B.L.n_f;
         int pb = (int)((nwork + 1023) / 1024);
@@ -625,6 +955,13 @@ hipError_t launch_batch(const BatchParams& B, int precision, int n_blocks, const
         const int sb = (int)(B.n_frames < 4096 ? B.n_frames : 4096);
         hipLaunchKernelGGL(k_batch_sort, dim3(sb), dim3(1024), 0, s, B, rx, w.ro, w.key, w.perm);
         e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        if (B.n_cyl > 0) {
+            const unsigned fb = (unsigned)((2 * B.n_cyl + 3) / 4);
+            hipLaunchKernelGGL(k_batch_fans, dim3(fb), dim3(256), 0, s, B, cyl, w.prep, w.bo, nodes, tris,
+                               n_main, w.fans);
+            e = hipGetLastError();
+        }
         if (e != hipSuccess || part == 1) return e;
     }
     if (precision == 0) {

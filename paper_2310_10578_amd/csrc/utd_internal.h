@@ -10,6 +10,7 @@
 
 namespace utd {
 
+struct FanProfile;
 
 // Frames of a batched call (see utd_batched.h).
 struct BatchParams {
@@ -54,14 +55,17 @@ struct BatchWs {
     int* perm;               // per receiver: frame-local index at each sorted position
     double* th;              // per block: reflection angles of a body group
     void* ew;                // per block: the tile's field
+    struct FanProfile* fans; // per (cylinder, side): source-side leg profile
 };
 size_t batch_workspace(const BatchParams& B, int precision, int n_blocks, char* base, BatchWs* ws);
-// part 0: the whole call; 1: the constants and the receiver order only
-// (k_batch_prep, k_batch_sort); 2: the persistent kernel only.
+// part 0: the whole call; 1: the constants, the receiver order and the
+// source-side leg profiles only (k_batch_prep, k_batch_sort, k_batch_fans);
+// 2: the persistent kernel only.  n_main: nodes of the BVH's main
+// (interior-triangle) tree, which come first in `nodes`.
 hipError_t launch_batch(const BatchParams& B, int precision, int n_blocks, const int64_t* body_off,
                         const int64_t* rx_off, const float* rx, const float* cyl, const double* freqs,
-                        const BatchWs& ws, const float4* nodes, const float4* tris, void* E, uint8_t* flags,
-                        hipStream_t s, int part = 0);
+                        const BatchWs& ws, const float4* nodes, const float4* tris, int n_main, void* E,
+                        uint8_t* flags, hipStream_t s, int part = 0);
 
 // Scratch of the allocation-free entry point: a static device array of
 // kNoAllocScratchBytes; noalloc_scratch gives its address on the current

@@ -406,3 +406,48 @@ def test_batched_many_frequencies_accumulate_in_place():
     worst = _compare_frames(cfg, E, fl, scene, 1)
     print("160 frequencies FP64 in place: worst frame %.2e" % worst, flush=True)
     scene.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batched_source_leg_profiles(precision):
+    """The batched kernel decides a creeping path's source-side leg from a
+    per-(frame, cylinder, side) profile of the fan of legs to the tangent
+    line, falling back to the leg's own test where a height is undecided or
+    the profile does not exist.  A dense set of low boxes with the source
+    below the tops of many of them (many cuts per fan: some profiles
+    overflow, many heights sit near cut boundaries), cylinders of random
+    heights and a source at several heights: equal to per-frame calls, which
+    test every leg."""
+    import paper_2310_10578_amd as utd
+    rng = np.random.default_rng(23)
+    Lx, Ly = 10.0, 8.0
+    boxes = []
+    for _ in range(120):
+        sz = rng.uniform([0.1, 0.1, 0.2], [0.6, 0.6, 1.8])
+        x0, y0 = rng.uniform(0, Lx - sz[0]), rng.uniform(0, Ly - sz[1])
+        boxes.append((np.array([x0, y0, 0.0]), np.array([x0 + sz[0], y0 + sz[1], sz[2]])))
+    tri = np.concatenate([W.room_shell(0.5)] + [W.box_triangles(lo, hi) for lo, hi in boxes]).astype(np.float32)
+    cyls, rxs, bo, ro = [], [], [0], [0]
+    for f in range(6):
+        nb = int(rng.integers(8, 40))
+        c = np.stack([rng.uniform(0.5, Lx - 0.5, nb), rng.uniform(0.5, Ly - 0.5, nb), np.zeros(nb),
+                      rng.uniform(0.8, 2.2, nb), rng.uniform(0.12, 0.3, nb)], 1)
+        nr = int(rng.integers(300, 1500))
+        r = np.stack([rng.uniform(0, Lx, nr), rng.uniform(0, Ly, nr), rng.uniform(0.3, 2.0, nr)], 1)
+        cyls.append(c)
+        rxs.append(r)
+        bo.append(bo[-1] + nb)
+        ro.append(ro[-1] + nr)
+    scene = utd.Scene(tri)
+    for tz in (0.6, 1.4, 2.6):
+        cfg = dict(tri=tri, cylinders=np.concatenate(cyls).astype(np.float32), rx=np.concatenate(rxs).astype(np.float32),
+                   body_off=np.array(bo, np.int64), rx_off=np.array(ro, np.int64),
+                   tx=dict(pos=np.array([4.7, 3.3, tz], np.float32), dipole=np.array([0.2, 0.3, 0.9], np.float32),
+                           amplitude=1.0),
+                   freqs=np.array([2.4e9, 5.0e9]))
+        d = _to_dev(cfg)
+        utd.batched_config(256, 3)
+        E, fl = _batched(cfg, precision, scene, d, l_enc=1)
+        worst = _compare_frames(cfg, E, fl, scene, precision, l_enc=1)
+        print("source-leg profiles p%d, source at %.1f m: worst frame %.2e" % (precision, tz, worst), flush=True)
+    scene.close()
