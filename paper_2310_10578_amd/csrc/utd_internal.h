@@ -11,6 +11,7 @@
 namespace utd {
 
 struct FanProfile;
+struct FrameGrid;
 
 // Frames of a batched call (see utd_batched.h).
 struct BatchParams {
@@ -56,6 +57,7 @@ struct BatchWs {
     double* th;              // per block: reflection angles of a body group
     void* ew;                // per block: the tile's field
     struct FanProfile* fans; // per (cylinder, side): source-side leg profile
+    struct FrameGrid* grids; // per frame: grid of the cylinders' footprints
 };
 size_t batch_workspace(const BatchParams& B, int precision, int n_blocks, char* base, BatchWs* ws);
 // part 0: the whole call; 1: the constants, the receiver order and the
