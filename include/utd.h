@@ -268,7 +268,10 @@ utd_status utd_forward_state_release(utd_forward_state *state, void *stream);
  * kernel) as long as its arguments repeat (device data may change), and when
  * the stream is itself being captured it records the two launches into the
  * caller's graph instead (the workspace must then exist from an earlier call
- * of at least this size).  Tile shape: utd_batched_config.  The library keeps
+ * of at least this size).  A caller's graph points into that workspace: once
+ * a call has been captured, a later call that needs a larger workspace
+ * allocates a new one and keeps the old one alive until the process ends, so
+ * captured graphs stay valid.  Tile shape: utd_batched_config.  The library keeps
  * one workspace per device: concurrent batched calls on one device race.
  * Errors as for utd_smooth_field; UTD_E_ARG for n_frames < 0, n_cyl < 0, NULL
  * offsets with n_frames, n_rx, n_f > 0, or a capture without workspace;

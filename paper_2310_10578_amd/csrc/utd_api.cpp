@@ -230,6 +230,10 @@ struct Workspace {
 struct BatchState {
     char* ws = nullptr;
     size_t ws_bytes = 0;
+    // a caller's graph holds raw pointers into ws once it captured a call:
+    // from then on a replaced workspace is kept (retired), never freed
+    bool in_caller_graph = false;
+    std::vector<char*> retired;
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -796,7 +800,10 @@ utd_status utd_smooth_field_batched(const utd_scene* scene, int64_t n_frames, co
                                    "size outside capture first");
         if (st.exec) { (void)hipGraphExecDestroy(st.exec); st.exec = nullptr; }
         if (st.graph) { (void)hipGraphDestroy(st.graph); st.graph = nullptr; }
-        if (st.ws) (void)hipFree(st.ws);
+        if (st.ws) {
+            if (st.in_caller_graph) st.retired.push_back(st.ws);
+            else (void)hipFree(st.ws);
+        }
         st.ws = nullptr;
         st.ws_bytes = 0;
         e = hipMalloc((void**)&st.ws, need);
@@ -827,6 +834,7 @@ utd_status utd_smooth_field_batched(const utd_scene* scene, int64_t n_frames, co
     }
     if (caller_capturing) {
         // the caller records these launches into its own graph
+        st.in_caller_graph = true;
         ProfScope ps(UTD_K_BATCHED, s);
         e = launch(s, 0);
         return e == hipSuccess ? UTD_OK : hip_fail(e, "kernel launch");

@@ -223,6 +223,19 @@ def test_capture_into_caller_graph():
         g.replay()
         torch.cuda.synchronize()
         assert torch.equal(out, ref)
+    # a larger call grows the library's workspace; the captured graph still
+    # points into the old one, which must stay alive
+    big = _crowd(n_frames=12, rx_range=(2000, 4000))
+    db = _to_dev(big)
+    Eb, _ = utd.smooth_field_batched(scene, db["body_off"], db["cyl"], db["rx_off"], db["rx"], src, db["freqs"])
+    torch.cuda.synchronize()
+    for rep in range(2):
+        out.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
+    del Eb
     scene.close()
 
 
