@@ -174,9 +174,10 @@ struct Workspace {
     uint64_t* vis = nullptr;                  // queue positions of the visible paths
     int64_t cap = 0;
     char* extra = nullptr;
+    void* grid = nullptr;                     // grid of the bodies' footprints
     bool with_flags = false, with_extra = false;
     size_t o_prep = 0, o_fc = 0, o_mask = 0, o_rec = 0, o_flag = 0, o_cnt = 0, o_ent = 0, o_th = 0, o_vis = 0,
-           o_extra = 0;
+           o_grid = 0, o_extra = 0;
     // Byte offsets of every part; returns the total size.
     size_t plan(int nb, int64_t n_rx, int n_f, int l_enc, int precision, bool need_flags, size_t extra_bytes = 0) {
         auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
@@ -193,7 +194,8 @@ struct Workspace {
         o_ent = up(o_cnt + 16 * sizeof(unsigned long long));
         o_th = up(o_ent + sizeof(uint64_t) * (size_t)cap);
         o_vis = up(o_th + sizeof(double) * (size_t)cap);
-        o_extra = up(o_vis + sizeof(uint64_t) * (size_t)cap);
+        o_grid = up(o_vis + sizeof(uint64_t) * (size_t)cap);
+        o_extra = up(o_grid + utd::body_grid_bytes());
         with_flags = need_flags;
         with_extra = extra_bytes > 0;
         return o_extra + extra_bytes;
@@ -221,6 +223,7 @@ struct Workspace {
         ent = (uint64_t*)(base + o_ent);
         ent_th = (double*)(base + o_th);
         vis = (uint64_t*)(base + o_vis);
+        grid = base + o_grid;
         extra = extra_bytes ? base + o_extra : nullptr;
     }
 };
@@ -386,7 +389,7 @@ utd_status utd_smooth_field(const utd_scene* scene, const utd_bodies* bodies, co
     {
         ProfScope ps(UTD_K_OCCLUDE, s);
         e = utd::launch_paths(L, opt->precision, rx, bodies->sph, bodies->cyl, freqs, w.prep, w.fc, nodes, tris,
-                              w.mask, w.rec, flags, w.ent, w.ent_th, w.vis, w.counters + 12, w.cap, s);
+                              w.mask, w.rec, flags, w.ent, w.ent_th, w.vis, w.counters + 12, w.cap, s, w.grid);
     }
     int fc = pick_fc(opt->precision, n_rx, n_f);
     if (e == hipSuccess) {
@@ -433,7 +436,7 @@ utd_status utd_smooth_field_noalloc(const utd_scene* scene, const utd_bodies* bo
     {
         ProfScope ps(UTD_K_OCCLUDE, s);
         e = utd::launch_paths(L, opt->precision, rx, bodies->sph, bodies->cyl, freqs, w.prep, w.fc, nodes, tris,
-                              w.mask, w.rec, flags, w.ent, w.ent_th, w.vis, w.counters + 12, w.cap, s);
+                              w.mask, w.rec, flags, w.ent, w.ent_th, w.vis, w.counters + 12, w.cap, s, w.grid);
     }
     if (e == hipSuccess) {
         ProfScope ps(UTD_K_FIELD, s);
@@ -470,7 +473,7 @@ utd_status utd_path_census(const utd_scene* scene, const utd_bodies* bodies, con
     if (e == hipSuccess)
         e = utd::launch_paths(L, 0, rx, bodies->sph, bodies->cyl, nullptr, w.prep, w.fc,
                               scene ? scene->d_nodes : nullptr, scene ? scene->d_tris : nullptr, w.mask, w.rec,
-                              w.flags, w.ent, w.ent_th, w.vis, w.counters + 12, w.cap, s);
+                              w.flags, w.ent, w.ent_th, w.vis, w.counters + 12, w.cap, s, w.grid);
     if (e == hipSuccess) e = utd::launch_census(nb > 0 ? (int64_t)nb * n_rx : 0, w.mask, n_rx, w.flags, w.counters, s);
     if (e == hipSuccess) e = hipMemcpyAsync(host, w.counters, sizeof host, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -498,7 +501,8 @@ utd_status utd_path_masks(const utd_scene* scene, const utd_bodies* bodies, cons
         ProfScope ps(UTD_K_OCCLUDE, s);
         e = utd::launch_paths(L, opt->precision, rx, bodies->sph, bodies->cyl, nullptr, w.prep, w.fc,
                               scene ? scene->d_nodes : nullptr, scene ? scene->d_tris : nullptr, w.mask, w.rec,
-                              rx_flags ? rx_flags : w.flags, w.ent, w.ent_th, w.vis, w.counters + 12, w.cap, s);
+                              rx_flags ? rx_flags : w.flags, w.ent, w.ent_th, w.vis, w.counters + 12, w.cap, s,
+                              w.grid);
     }
     if (e == hipSuccess && nb > 0)
         e = hipMemcpyAsync(mask_out, w.mask, (size_t)nb * (size_t)n_rx, hipMemcpyDeviceToDevice, s);
@@ -522,7 +526,8 @@ utd_status utd_wall_masks(const utd_scene* scene, const utd_bodies* bodies, cons
     hipError_t e = w.alloc((int)nb, n_rx, 0, opt->l_enc, opt->precision, true, s, utd::walls_scratch_bytes(L, n_planes));
     if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(UTD_E_OOM, "workspace allocation") : hip_fail(e, "hipMallocAsync");
     e = utd::launch_paths(L, opt->precision, rx, bodies->sph, bodies->cyl, nullptr, w.prep, w.fc, scene->d_nodes,
-                          scene->d_tris, w.mask, w.rec, w.flags, w.ent, w.ent_th, w.vis, w.counters + 12, w.cap, s);
+                          scene->d_tris, w.mask, w.rec, w.flags, w.ent, w.ent_th, w.vis, w.counters + 12, w.cap, s,
+                          w.grid);
     if (e == hipSuccess)
         e = utd::launch_walls(L, opt->precision, scene->mat, rx, bodies->sph, bodies->cyl, w.prep,
                               (utd::BodyPrep*)w.extra, scene->d_planes, n_planes, scene->d_nodes, scene->d_tris, w.fc,
@@ -566,7 +571,7 @@ utd_status utd_smooth_field_backward(const utd_scene* scene, const utd_bodies* b
     if (work) {
         ProfScope ps(UTD_K_OCCLUDE, s);
         e = utd::launch_paths(L, opt->precision, rx, bodies->sph, bodies->cyl, freqs, w.prep, w.fc, nodes, tris,
-                              w.mask, w.rec, w.flags, w.ent, w.ent_th, w.vis, w.counters + 12, w.cap, s);
+                              w.mask, w.rec, w.flags, w.ent, w.ent_th, w.vis, w.counters + 12, w.cap, s, w.grid);
     }
     if (e == hipSuccess) {
         ProfScope ps(UTD_K_BACKWARD, s);
@@ -673,7 +678,7 @@ utd_status utd_smooth_field_saved(const utd_scene* scene, const utd_bodies* bodi
     if (e == hipSuccess && work) {
         ProfScope ps(UTD_K_OCCLUDE, s);
         e = utd::launch_paths(fs->L, opt->precision, fs->rx, fs->sph, fs->cyl, freqs, w.prep, w.fc, nodes, tris,
-                              w.mask, w.rec, w.flags, w.ent, w.ent_th, w.vis, w.counters + 12, w.cap, s);
+                              w.mask, w.rec, w.flags, w.ent, w.ent_th, w.vis, w.counters + 12, w.cap, s, w.grid);
     }
     if (e == hipSuccess && work) {
         ProfScope ps(UTD_K_FIELD, s);

@@ -555,119 +555,23 @@ __global__ void __launch_bounds__(256) k_batch_fans(BatchParams B, const float* 
     }
 }
 
-// Per-frame grid of the cylinders' footprints: 16 x 16 cells over the box of
-// the frame's cylinders, each with the bit mask of the cylinders whose disc,
-// widened by kGridPad, meets the cell.  A leg then runs the exact body test
-// on the cylinders of the cells its horizontal projection crosses (rows of
-// the grid, the leg's x range within each row widened by kGridPad) instead
-// of every cylinder of the frame: a conservative subset (every cylinder the
-// leg can meet is in it), so the decision is the same.  Frames of more than
-// 64 cylinders keep the plain loop.
-constexpr int kGridN = 16;
-constexpr float kGridPad = 1e-3f;
-struct FrameGrid {
-    float x0, y0, sx, sy;        // origin and cells per metre
-    int ok, pad[3];
-    unsigned long long m[kGridN * kGridN];
-};
-
-// One block of kGridN^2 threads per frame (grid-stride): thread = cell.
+// One block of kGridN^2 threads per frame (grid-stride): the grid of the
+// frame's cylinders (BodyGrid, utd_bvh.h).
 __global__ void __launch_bounds__(kGridN * kGridN) k_batch_grid(BatchParams B, const float* __restrict__ cyl,
                                                                 const int64_t* __restrict__ bo,
-                                                                FrameGrid* __restrict__ grids) {
+                                                                BodyGrid* __restrict__ grids) {
     __shared__ float s_box[4];
-    const int t = threadIdx.x;
     for (int64_t fr = blockIdx.x; fr < B.n_frames; fr += gridDim.x) {
         const int64_t b0 = bo[fr], nb = bo[fr + 1] - b0;
-        FrameGrid* G = grids + fr;
-        if (nb > 64 || nb <= 0) {
-            if (t == 0) G->ok = 0;
-            continue;                                    // block-uniform
-        }
-        if (t == 0) {
-            float x0 = INFINITY, y0 = INFINITY, x1 = -INFINITY, y1 = -INFINITY;
-            for (int64_t j = 0; j < nb; ++j) {
-                const float* c = cyl + 5 * (b0 + j);
-                x0 = fminf(x0, c[0] - c[4]); x1 = fmaxf(x1, c[0] + c[4]);
-                y0 = fminf(y0, c[1] - c[4]); y1 = fmaxf(y1, c[1] + c[4]);
-            }
-            // non-finite bodies (flagged elsewhere) leave the plain loop
-            const bool fin = isfinite(x0) && isfinite(x1) && isfinite(y0) && isfinite(y1);
-            x0 -= kGridPad; y0 -= kGridPad; x1 += kGridPad; y1 += kGridPad;
-            s_box[0] = x0; s_box[1] = y0;
-            s_box[2] = fin ? (float)kGridN / fmaxf(x1 - x0, 1e-6f) : 0.0f;
-            s_box[3] = fin ? (float)kGridN / fmaxf(y1 - y0, 1e-6f) : 0.0f;
-            G->x0 = x0; G->y0 = y0; G->sx = s_box[2]; G->sy = s_box[3];
-            G->ok = fin ? 1 : 0;
-        }
-        __syncthreads();
-        const int ix = t % kGridN, iy = t / kGridN;
-        const float cx0 = s_box[0] + ix / s_box[2], cx1 = s_box[0] + (ix + 1) / s_box[2];
-        const float cy0 = s_box[1] + iy / s_box[3], cy1 = s_box[1] + (iy + 1) / s_box[3];
-        unsigned long long m = 0ull;
-        if (s_box[2] > 0.0f)
-            for (int64_t j = 0; j < nb; ++j) {
-                const float* c = cyl + 5 * (b0 + j);
-                const float qx = fminf(fmaxf(c[0], cx0), cx1), qy = fminf(fmaxf(c[1], cy0), cy1);
-                const float ex = c[0] - qx, ey = c[1] - qy, r = c[4] + 2.0f * kGridPad;
-                if (ex * ex + ey * ey <= r * r) m |= 1ull << j;
-            }
-        G->m[t] = m;
-        __syncthreads();
+        grid_build_block(grids + fr, nullptr, 0, cyl + 5 * b0, nb, s_box);
     }
-}
-
-// Mask of the frame's cylinders a leg P0-P1 may meet (all of them without a grid).
-__device__ __forceinline__ unsigned long long grid_candidates(const FrameGrid* __restrict__ G, int nb, d3 P0, d3 P1) {
-    const unsigned long long all = nb >= 64 ? ~0ull : ((1ull << nb) - 1ull);
-    if (!G->ok) return all;
-    const float x0 = G->x0, y0 = G->y0, sx = G->sx, sy = G->sy;
-    // the leg in cell coordinates
-    const float ax = ((float)P0.x - x0) * sx, ay = ((float)P0.y - y0) * sy;
-    const float bx = ((float)P1.x - x0) * sx, by = ((float)P1.y - y0) * sy;
-    const float px = kGridPad * sx, py = kGridPad * sy;
-    const float ylo = fminf(ay, by) - py, yhi = fmaxf(ay, by) + py;
-    const int r0 = (int)fmaxf(floorf(ylo), 0.0f), r1 = (int)fminf(floorf(yhi), (float)(kGridN - 1));
-    unsigned long long m = 0ull;
-    const float dyb = by - ay;
-    for (int r = r0; r <= r1; ++r) {
-        // the leg's x range within the row's band [r, r + 1] (widened)
-        float t0 = 0.0f, t1 = 1.0f;
-        if (fabsf(dyb) > 1e-12f) {
-            float ta = ((float)r - py - ay) / dyb, tb = ((float)(r + 1) + py - ay) / dyb;
-            if (ta > tb) { const float x = ta; ta = tb; tb = x; }
-            t0 = fmaxf(t0, ta);
-            t1 = fminf(t1, tb);
-        }
-        if (t0 > t1) continue;
-        const float xa = ax + t0 * (bx - ax), xb = ax + t1 * (bx - ax);
-        const int c0 = (int)fmaxf(floorf(fminf(xa, xb) - px), 0.0f);
-        const int c1 = (int)fminf(floorf(fmaxf(xa, xb) + px), (float)(kGridN - 1));
-        for (int c = c0; c <= c1; ++c) m |= G->m[r * kGridN + c];
-    }
-    return m;
 }
 
 // seg_blocked of the batched kernel: the frame's cylinders through its grid.
 __device__ __forceinline__ bool seg_blocked_frame(d3 P0, d3 P1, const LaunchParams& L, const float* cyl, int skip,
-                                                  bool bodies, const FrameGrid* G, const float4* nodes,
+                                                  bool bodies, const BodyGrid* G, const float4* nodes,
                                                   const float4* tris, int* stack, int stride) {
-    if (bodies) {
-        unsigned long long m = grid_candidates(G, L.n_cyl, P0, P1);
-        if (skip >= 0 && skip < 64) m &= ~(1ull << skip);
-        if (L.n_cyl > 64) {
-            const SegF f = make_segf(P0, P1);
-            for (int i = 0; i < L.n_cyl; ++i)
-                if (i != skip && seg_cylinder(P0, P1, f, cyl + 5 * i)) return true;
-        } else if (m) {
-            const SegF f = make_segf(P0, P1);
-            while (m) {
-                const int i = __builtin_ctzll(m);
-                m &= m - 1ull;
-                if (seg_cylinder(P0, P1, f, cyl + 5 * i)) return true;
-            }
-        }
-    }
+    if (bodies && blocked_by_grid(P0, P1, nullptr, 0, cyl, L.n_cyl, skip, G)) return true;
     return seg_blocked(P0, P1, L, nullptr, cyl, skip, false, nodes, tris, stack, stride);
 }
 
@@ -718,7 +622,7 @@ __global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(3, 8)
                                                 const float4* __restrict__ tris, double* __restrict__ th_scratch,
                                                 const int* __restrict__ perm, R* __restrict__ ew_scratch,
                                                 const FanProfile* __restrict__ fans,
-                                                const FrameGrid* __restrict__ grids, R* __restrict__ E_out,
+                                                const BodyGrid* __restrict__ grids, R* __restrict__ E_out,
                                                 uint8_t* __restrict__ flags) {
     static_assert(TILE <= 256, "lane index is stored in 8 bits");
     constexpr int QCAP = 8 * TILE;
@@ -777,7 +681,7 @@ __global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(3, 8)
         const float* fcyl = cyl + 5 * b0;
         const BodyPrep* fprep = prep + b0;
         const FanProfile* ffan = fans + 2 * b0;
-        const FrameGrid* fgrid = grids + fr;
+        const BodyGrid* fgrid = grids + fr;
         R* E = E_out + 2 * 3 * (int64_t)B.L.n_f * r0;
         const int64_t i = r0 + src;
         const float rxx = act ? rx[3 * i] : 0.0f, rxy = act ? rx[3 * i + 1] : 0.0f, rxz = act ? rx[3 * i + 2] : 0.0f;
@@ -1039,7 +943,7 @@ size_t batch_workspace(const BatchParams& B, int precision, int n_blocks, char* 
     const size_t o_perm = take(sizeof(int) * (size_t)B.n_rx);
     const size_t o_th = take(sizeof(double) * (size_t)n_blocks * kBGroup * B.tile);
     const size_t o_fan = take(sizeof(FanProfile) * 2 * (size_t)(B.n_cyl > 0 ? B.n_cyl : 1));
-    const size_t o_grid = take(sizeof(FrameGrid) * (size_t)(B.n_frames > 0 ? B.n_frames : 1));
+    const size_t o_grid = take(sizeof(BodyGrid) * (size_t)(B.n_frames > 0 ? B.n_frames : 1));
     const size_t ew_bytes = real * 2 * 3 * (size_t)B.L.n_f * (size_t)n_blocks * B.tile;
     const bool use_ew = ew_bytes <= kBatchFieldScratchMax;
     const size_t o_ew = take(use_ew ? ew_bytes : 0);
@@ -1054,7 +958,7 @@ size_t batch_workspace(const BatchParams& B, int precision, int n_blocks, char* 
         ws->perm = (int*)(base + o_perm);
         ws->th = (double*)(base + o_th);
         ws->fans = (FanProfile*)(base + o_fan);
-        ws->grids = (FrameGrid*)(base + o_grid);
+        ws->grids = (BodyGrid*)(base + o_grid);
         ws->ew = use_ew ? base + o_ew : nullptr;
     }
     return o;

@@ -210,4 +210,135 @@ __device__ __forceinline__ bool seg_cylinder(d3 P0, d3 P1, const SegF& f, const 
     return fmax(lo, (double)kSegEps) < fmin(hi, 1.0 - kSegEps);
 }
 
+
+// Grid of the bodies' footprints in the horizontal plane: 16 x 16 cells over
+// the box of the bodies' discs (a sphere's and a cylinder's footprint is the
+// disc of its radius about its axis), each cell with the bit mask of the
+// bodies whose disc, widened by 2 kGridPad, meets it (at most 64 bodies,
+// spheres first).  A segment then runs the exact body test only on the
+// bodies of the cells its horizontal projection crosses: the grid's rows,
+// the segment's x range within each row widened by kGridPad (the cell
+// coordinates are FP32, good to about 1e-5 m here).  A body the segment
+// meets has a point of the segment inside its disc, in some crossed cell,
+// so the subset holds every body that can block and the decision is that of
+// the plain loop over all bodies.
+constexpr int kGridN = 16;
+constexpr float kGridPad = 1e-3f;
+struct BodyGrid {
+    float x0, y0, sx, sy;        // origin and cells per metre
+    int ok, pad[3];              // ok = 0: test every body
+    unsigned long long m[kGridN * kGridN];
+};
+
+__device__ __forceinline__ void body_disc(const float* sph, int n_sph, const float* cyl, int j, float* x, float* y,
+                                          float* r) {
+    if (j < n_sph) {
+        const float* q = sph + 4 * j;
+        *x = q[0]; *y = q[1]; *r = q[3];
+    } else {
+        const float* q = cyl + 5 * (j - n_sph);
+        *x = q[0]; *y = q[1]; *r = q[4];
+    }
+}
+
+// The grid of nb = n_sph + n_cyl bodies, built by one block of kGridN^2
+// threads (thread = cell); s_box: 4 floats of LDS.  Contains barriers: all
+// threads of the block call it with the same arguments.
+__device__ __forceinline__ void grid_build_block(BodyGrid* G, const float* sph, int n_sph, const float* cyl,
+                                                 int64_t n_cyl, float* s_box) {
+    const int t = threadIdx.x;
+    const int64_t nb = n_sph + n_cyl;
+    if (nb > 64 || nb <= 0) {
+        if (t == 0) G->ok = 0;
+        return;
+    }
+    if (t == 0) {
+        float x0 = INFINITY, y0 = INFINITY, x1 = -INFINITY, y1 = -INFINITY;
+        for (int j = 0; j < (int)nb; ++j) {
+            float x, y, r;
+            body_disc(sph, n_sph, cyl, j, &x, &y, &r);
+            x0 = fminf(x0, x - r); x1 = fmaxf(x1, x + r);
+            y0 = fminf(y0, y - r); y1 = fmaxf(y1, y + r);
+        }
+        // non-finite bodies (flagged elsewhere) keep the plain loop
+        const bool fin = isfinite(x0) && isfinite(x1) && isfinite(y0) && isfinite(y1);
+        x0 -= kGridPad; y0 -= kGridPad; x1 += kGridPad; y1 += kGridPad;
+        s_box[0] = x0; s_box[1] = y0;
+        s_box[2] = fin ? (float)kGridN / fmaxf(x1 - x0, 1e-6f) : 0.0f;
+        s_box[3] = fin ? (float)kGridN / fmaxf(y1 - y0, 1e-6f) : 0.0f;
+        G->x0 = x0; G->y0 = y0; G->sx = s_box[2]; G->sy = s_box[3];
+        G->ok = fin ? 1 : 0;
+    }
+    __syncthreads();
+    const int ix = t % kGridN, iy = t / kGridN;
+    const float cx0 = s_box[0] + ix / s_box[2], cx1 = s_box[0] + (ix + 1) / s_box[2];
+    const float cy0 = s_box[1] + iy / s_box[3], cy1 = s_box[1] + (iy + 1) / s_box[3];
+    unsigned long long m = 0ull;
+    if (s_box[2] > 0.0f)
+        for (int j = 0; j < (int)nb; ++j) {
+            float x, y, r;
+            body_disc(sph, n_sph, cyl, j, &x, &y, &r);
+            const float qx = fminf(fmaxf(x, cx0), cx1), qy = fminf(fmaxf(y, cy0), cy1);
+            const float ex = x - qx, ey = y - qy, rr = r + 2.0f * kGridPad;
+            if (ex * ex + ey * ey <= rr * rr) m |= 1ull << j;
+        }
+    G->m[t] = m;
+    __syncthreads();
+}
+
+// Mask of the bodies a segment P0-P1 may meet.
+__device__ __forceinline__ unsigned long long grid_candidates(const BodyGrid* __restrict__ G, int nb, d3 P0, d3 P1) {
+    const unsigned long long all = nb >= 64 ? ~0ull : ((1ull << nb) - 1ull);
+    if (!G->ok) return all;
+    const float x0 = G->x0, y0 = G->y0, sx = G->sx, sy = G->sy;
+    const float ax = ((float)P0.x - x0) * sx, ay = ((float)P0.y - y0) * sy;
+    const float bx = ((float)P1.x - x0) * sx, by = ((float)P1.y - y0) * sy;
+    const float px = kGridPad * sx, py = kGridPad * sy;
+    const float ylo = fminf(ay, by) - py, yhi = fmaxf(ay, by) + py;
+    const int r0 = (int)fmaxf(floorf(ylo), 0.0f), r1 = (int)fminf(floorf(yhi), (float)(kGridN - 1));
+    unsigned long long m = 0ull;
+    const float dyb = by - ay;
+    for (int r = r0; r <= r1; ++r) {
+        // the segment's x range within the row's band [r, r + 1] (widened)
+        float t0 = 0.0f, t1 = 1.0f;
+        if (fabsf(dyb) > 1e-12f) {
+            float ta = ((float)r - py - ay) / dyb, tb = ((float)(r + 1) + py - ay) / dyb;
+            if (ta > tb) { const float x = ta; ta = tb; tb = x; }
+            t0 = fmaxf(t0, ta);
+            t1 = fminf(t1, tb);
+        }
+        if (t0 > t1) continue;
+        const float xa = ax + t0 * (bx - ax), xb = ax + t1 * (bx - ax);
+        const int c0 = (int)fmaxf(floorf(fminf(xa, xb) - px), 0.0f);
+        const int c1 = (int)fminf(floorf(fmaxf(xa, xb) + px), (float)(kGridN - 1));
+        for (int c = c0; c <= c1; ++c) m |= G->m[r * kGridN + c];
+    }
+    return m;
+}
+
+// Any body except `skip` crossed strictly inside the segment, through the
+// grid when there is one (G may be NULL) and it holds the bodies.
+__device__ __forceinline__ bool blocked_by_grid(d3 P0, d3 P1, const float* sph, int n_sph, const float* cyl,
+                                                int n_cyl, int skip, const BodyGrid* G) {
+    const int nb = n_sph + n_cyl;
+    const SegF f = make_segf(P0, P1);
+    if (!G || nb > 64) {
+        for (int i = 0; i < nb; ++i) {
+            if (i == skip) continue;
+            if (i < n_sph ? seg_sphere(P0, P1, f, sph + 4 * i) : seg_cylinder(P0, P1, f, cyl + 5 * (i - n_sph)))
+                return true;
+        }
+        return false;
+    }
+    unsigned long long m = grid_candidates(G, nb, P0, P1);
+    if (skip >= 0 && skip < 64) m &= ~(1ull << skip);
+    while (m) {
+        const int i = __builtin_ctzll(m);
+        m &= m - 1ull;
+        if (i < n_sph ? seg_sphere(P0, P1, f, sph + 4 * i) : seg_cylinder(P0, P1, f, cyl + 5 * (i - n_sph)))
+            return true;
+    }
+    return false;
+}
+
 }  // namespace utd

@@ -11,7 +11,7 @@
 namespace utd {
 
 struct FanProfile;
-struct FrameGrid;
+struct BodyGrid;
 
 // Frames of a batched call (see utd_batched.h).
 struct BatchParams {
@@ -27,11 +27,17 @@ struct BatchParams {
 // lengths in counter[0] and counter[1]; without triangles in one pass.  Also
 // stores the body constants (prep) and, when freqs is not NULL, the
 // frequency constants (fcs) for the later kernels of the call.  Record slots
-// per (receiver, body): 2 (l_enc + 1) + 1.
+// per (receiver, body): 2 (l_enc + 1) + 1.  `grid` (body_grid_bytes(), or
+// NULL): scratch for the grid of the bodies' footprints that the visibility
+// tests use.
 hipError_t launch_paths(const LaunchParams& L, int precision, const float* rx, const float* sph, const float* cyl,
                         const double* freqs, BodyPrep* prep, FreqConst* fcs, const float4* nodes, const float4* tris,
                         uint8_t* mask, void* rec, uint8_t* flags, uint64_t* ent, double* ent_th,
-                        uint64_t* vis_list, unsigned long long* counter, int64_t cap, hipStream_t s);
+                        uint64_t* vis_list, unsigned long long* counter, int64_t cap, hipStream_t s,
+                        void* grid = nullptr);
+// Scratch of the body grid that launch_paths builds (scenes with triangles
+// and at most 64 bodies) when given one.
+size_t body_grid_bytes();
 size_t path_record_bytes(int precision);
 hipError_t launch_field(const LaunchParams& L, int precision, int fc, const float* rx, const FreqConst* fcs,
                         const uint8_t* mask, const void* rec, uint8_t* flags, void* E, hipStream_t s);
@@ -57,7 +63,7 @@ struct BatchWs {
     double* th;              // per block: reflection angles of a body group
     void* ew;                // per block: the tile's field
     struct FanProfile* fans; // per (cylinder, side): source-side leg profile
-    struct FrameGrid* grids; // per frame: grid of the cylinders' footprints
+    struct BodyGrid* grids;  // per frame: grid of the cylinders' footprints
 };
 size_t batch_workspace(const BatchParams& B, int precision, int n_blocks, char* base, BatchWs* ws);
 // part 0: the whole call; 1: the constants, the receiver order and the

@@ -126,6 +126,14 @@ __device__ __forceinline__ bool seg_blocked(d3 P0, d3 P1, const LaunchParams& L,
     return bvh_anyhit(nodes, tris, r, stack, stride, L.broot);
 }
 
+// The same with the bodies through their grid (grid may be NULL).
+__device__ __forceinline__ bool seg_blocked_g(d3 P0, d3 P1, const LaunchParams& L, const float* sph,
+                                              const float* cyl, int skip, bool bodies, const BodyGrid* grid,
+                                              const float4* nodes, const float4* tris, int* stack, int stride) {
+    if (bodies && blocked_by_grid(P0, P1, sph, L.n_sph, cyl, L.n_cyl, skip, grid)) return true;
+    return seg_blocked(P0, P1, L, sph, cyl, skip, false, nodes, tris, stack, stride);
+}
+
 // Path records: the frequency-independent constants of one valid path,
 // written by the visibility pass and read by the field kernel.  Slot-major
 // layout rec[(body * S + slot) * n_rx + rx] keeps both passes coalesced;
@@ -356,7 +364,8 @@ __device__ __forceinline__ void vis_body(const LaunchParams& L, const float* __r
                                          const float4* __restrict__ tris, const uint64_t* __restrict__ ent,
                                          const double* __restrict__ ent_th, unsigned long long* __restrict__ counter,
                                          int64_t cap, uint8_t* __restrict__ mask, uint8_t* __restrict__ flags,
-                                         uint64_t* __restrict__ vis_list, int* stack, uint64_t* vbuf) {
+                                         uint64_t* __restrict__ vis_list, const BodyGrid* grid, int* stack,
+                                         uint64_t* vbuf) {
     int* stk = stack + threadIdx.x;
     // Visible paths collect in the wavefront's own LDS buffer (vbuf, 128
     // entries) and go to the global list 64 at a time: one atomic on the
@@ -382,7 +391,7 @@ __device__ __forceinline__ void vis_body(const LaunchParams& L, const float* __r
             const d3 R3 = mk(rx[3 * i], rx[3 * i + 1], rx[3 * i + 2]);
             if (bb == (int64_t)kLosEntry) {
                 // the receiver's only entry of this kind: a plain byte update
-                if (!seg_blocked(T, R3, L, sph, cyl, -1, true, nodes, tris, stk, stride))
+                if (!seg_blocked_g(T, R3, L, sph, cyl, -1, true, grid, nodes, tris, stk, stride))
                     flags[i] = (uint8_t)(flags[i] | kFlagLos);
             } else {
                 const int b = (int)bb;
@@ -401,8 +410,8 @@ __device__ __forceinline__ void vis_body(const LaunchParams& L, const float* __r
                     else
                         cyl_creep<R, double>(P, g, R3, T, L, sgn, ell, (PathEval<R>*)nullptr, &pts);
                 }
-                vis = !seg_blocked(pts.P0, pts.P1, L, sph, cyl, b, bo, nodes, tris, stk, stride);
-                if (vis) vis = !seg_blocked(pts.P2, pts.P3, L, sph, cyl, b, bo, nodes, tris, stk, stride);
+                vis = !seg_blocked_g(pts.P0, pts.P1, L, sph, cyl, b, bo, grid, nodes, tris, stk, stride);
+                if (vis) vis = !seg_blocked_g(pts.P2, pts.P3, L, sph, cyl, b, bo, grid, nodes, tris, stk, stride);
                 if (vis) {
                     // mask bytes of one pair can be set by concurrent lanes: OR into the word
                     const int64_t mb = (int64_t)b * L.n_rx + i;
@@ -445,12 +454,22 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
                                              const double* __restrict__ ent_th,
                                              unsigned long long* __restrict__ counter, int64_t cap,
                                              uint8_t* __restrict__ mask, uint8_t* __restrict__ flags,
-                                             uint64_t* __restrict__ vis_list) {
+                                             uint64_t* __restrict__ vis_list, const BodyGrid* __restrict__ grid) {
     __shared__ int stack[kStackDepth * 256];
     __shared__ uint64_t vbuf[4 * 128];
-    vis_body<R>(L, rx, sph, cyl, prep, nodes, tris, ent, ent_th, counter, cap, mask, flags, vis_list, stack,
+    vis_body<R>(L, rx, sph, cyl, prep, nodes, tris, ent, ent_th, counter, cap, mask, flags, vis_list, grid, stack,
                 vbuf + 128 * (threadIdx.x >> 6));
 }
+
+// The grid of the call's bodies (one block; at most 64 bodies).
+__global__ void __launch_bounds__(kGridN * kGridN) k_body_grid(LaunchParams L, const float* __restrict__ sph,
+                                                               const float* __restrict__ cyl,
+                                                               BodyGrid* __restrict__ grid) {
+    __shared__ float s_box[4];
+    grid_build_block(grid, sph, L.n_sph, cyl, L.n_cyl, s_box);
+}
+
+size_t body_grid_bytes() { return sizeof(BodyGrid); }
 
 // Pass 3: one lane per visible path (grid-stride over the visible list): the
 // frequency-independent constants of the path, packed into its record slot.
@@ -886,7 +905,7 @@ static hipError_t launch_paths_t(const LaunchParams& L, const float* rx, const f
                                  const double* freqs, BodyPrep* prep, FreqConst* fcs, const float4* nodes,
                                  const float4* tris, uint8_t* mask, void* rec, uint8_t* flags, uint64_t* ent,
                                  double* ent_th, uint64_t* vis_list, unsigned long long* counter, int64_t cap,
-                                 hipStream_t s) {
+                                 hipStream_t s, void* grid_mem) {
     int nb = L.n_sph + L.n_cyl;
     if (!nodes) {
         // one wavefront per path kind and 64 receivers
@@ -908,8 +927,14 @@ static hipError_t launch_paths_t(const LaunchParams& L, const float* rx, const f
     // workgroups to fill the chip
     int64_t vgrid = (cap + 255) / 256;
     vgrid = vgrid < 1 ? 1 : (vgrid > 256 * 20 ? 256 * 20 : vgrid);
+    BodyGrid* bgrid = nullptr;
+    if (grid_mem && nb > 0 && nb <= 64) {
+        bgrid = (BodyGrid*)grid_mem;
+        hipLaunchKernelGGL(k_body_grid, dim3(1), dim3(kGridN * kGridN), 0, s, L, sph, cyl, bgrid);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     hipLaunchKernelGGL((k_vis<R>), dim3((unsigned)vgrid), dim3(256), 0, s, L, rx, sph, cyl, prep, nodes, tris, ent,
-                       ent_th, counter, cap, mask, flags, vis_list);
+                       ent_th, counter, cap, mask, flags, vis_list, bgrid);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     int64_t rgrid = vgrid < 256 * 8 ? vgrid : 256 * 8;
     hipLaunchKernelGGL((k_rec<R>), dim3((unsigned)rgrid), dim3(256), 0, s, L, rx, prep, ent, ent_th, counter,
@@ -920,11 +945,12 @@ static hipError_t launch_paths_t(const LaunchParams& L, const float* rx, const f
 hipError_t launch_paths(const LaunchParams& L, int precision, const float* rx, const float* sph, const float* cyl,
                         const double* freqs, BodyPrep* prep, FreqConst* fcs, const float4* nodes, const float4* tris,
                         uint8_t* mask, void* rec, uint8_t* flags, uint64_t* ent, double* ent_th,
-                        uint64_t* vis_list, unsigned long long* counter, int64_t cap, hipStream_t s) {
+                        uint64_t* vis_list, unsigned long long* counter, int64_t cap, hipStream_t s,
+                        void* grid) {
     return precision == 0 ? launch_paths_t<float>(L, rx, sph, cyl, freqs, prep, fcs, nodes, tris, mask, rec, flags,
-                                                  ent, ent_th, vis_list, counter, cap, s)
+                                                  ent, ent_th, vis_list, counter, cap, s, grid)
                           : launch_paths_t<double>(L, rx, sph, cyl, freqs, prep, fcs, nodes, tris, mask, rec, flags,
-                                                   ent, ent_th, vis_list, counter, cap, s);
+                                                   ent, ent_th, vis_list, counter, cap, s, grid);
 }
 
 size_t path_record_bytes(int precision) { return precision == 0 ? sizeof(PathRec<float>) : sizeof(PathRec<double>); }
