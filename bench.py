@@ -101,6 +101,11 @@ def measured_traffic(workload_name, kernel_prefix):
     return val
 
 
+def _progress(msg):
+    """One line on stderr per finished phase (the JSON line stays alone on stdout)."""
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -391,6 +396,10 @@ def _frozen(mask, flags, n_cyl):
     return dict(los=(flags & 4) != 0, inside=(flags & 1) != 0, flags=flags.copy(), paths=paths)
 
 
+def _oracle_frame_k(kt):
+    return kt[0], _oracle_frame(kt[1])
+
+
 def cpu_baseline(d, n_frames, n_rx):
     """The FP64 oracle on a seeded sample of the crowd: n_frames frames with
     cylinders, n_rx receivers of each, all 8 frequencies; one worker process
@@ -425,9 +434,11 @@ def cpu_baseline(d, n_frames, n_rx):
         share = os.cpu_count() or 1
     procs = max(1, min(share, 16, len(tasks)))
     with mp.get_context("fork").Pool(procs) as pool:
-        t0 = time.perf_counter()
-        parts = pool.map(_oracle_frame, tasks, chunksize=1)
-        dt = time.perf_counter() - t0
+        parts = [None] * len(tasks)
+        for k, part in pool.imap_unordered(_oracle_frame_k, list(enumerate(tasks)), chunksize=1):
+            parts[k] = part
+            _progress("oracle frame %d of %d done (%.1f s)" % (sum(p is not None for p in parts), len(tasks),
+                                                               part[2]))
     n_f = len(cfg["freqs"])
     evals = sum(n_rx * (bo[f + 1] - bo[f]) for f in frames) * n_f
     field_s = sum(p[2] for p in parts)
@@ -479,8 +490,11 @@ def main():
     crowd = None
     if args.workload == "config4":
         crowd = crowd_setup()
+        _progress("crowd set up")
         ms, wall, k_ms, per_kernel, tune = crowd_batched(crowd, args.steps, args.warmup)
+        _progress("crowd timed: %.3f ms per step" % ms)
         census = crowd_census(crowd)
+        _progress("crowd path census done")
         cfg = crowd["cfg"]
         n_live = int(cfg["rx"].shape[0]) - census["inside"]
         flops = _path_flops(census, len(cfg["freqs"]), n_live)
@@ -511,13 +525,19 @@ def main():
             p_ms = crowd_per_frame(crowd, 2)
             res["per_frame"] = {"ms_per_step": p_ms, "evals_per_s": crowd["evals"] / (p_ms / 1e3),
                                 "batched_over_per_frame_speedup": p_ms / res["ms_per_step"]}
+            _progress("per-frame crowd timed")
         if args.workload != "config2":
             res["field"] = field_measure("config2", args.secondary_steps, 20)
+            _progress("field workload timed")
         if args.workload != "config3":
             res["occlusion"] = field_measure("config3", max(10, args.secondary_steps // 10), 3)
+            _progress("occlusion workload timed")
         res["adjoint"] = adjoint_measure(5)
+        _progress("adjoint timed")
     if args.cpu_baseline and crowd is not None:
+        _progress("CPU baseline (the oracle) starting")
         res["cpu_baseline"] = cpu_baseline(crowd, args.cpu_frames, args.cpu_rx)
+        _progress("CPU baseline done")
     if crowd is not None:
         crowd["scene"].close()
     print(json.dumps(res))
