@@ -53,6 +53,14 @@ FLOPS_CREEP = 108
 FLOPS_REFL = 140
 FLOPS_LOS = 14
 FLOPS_RX_SCALE = 6
+# Frequency-independent work per candidate path (classification, geodesic or
+# reflection point, path constants: steps a2-a4), the lower end of the
+# algorithmic per-path figure the method's formula set needs (120-180 FP32
+# flops).  The batched kernel does these steps for every (receiver, body)
+# pair and each of its 2 (l_enc + 1) creeping paths and its reflection, so
+# its algorithmic count is pairs x paths per pair x 120 plus the field of
+# the paths that exist and are visible.
+FLOPS_PATH_GEOM = 120
 # MI355X FP32 vector rate: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
 # = 78.6 TFLOP/s for the plain FP32 instructions this library is built with
 # (packed FP32, which doubles it to the published 157.3, is disabled at
@@ -497,7 +505,10 @@ def main():
         _progress("crowd path census done")
         cfg = crowd["cfg"]
         n_live = int(cfg["rx"].shape[0]) - census["inside"]
-        flops = _path_flops(census, len(cfg["freqs"]), n_live)
+        field_flops = _path_flops(census, len(cfg["freqs"]), n_live)
+        pairs = crowd["evals"] // len(cfg["freqs"])
+        geom_flops = pairs * 3 * FLOPS_PATH_GEOM          # l_enc = 0: two creeping paths and the reflection
+        flops = geom_flops + field_flops
         res.update({"value": crowd["evals"] / (ms / 1e3), "ms_per_step": ms, "wall_s": wall,
                     "config": {"workload": cfg["name"], "frames": len(cfg["body_off"]) - 1,
                                "receivers": int(cfg["rx"].shape[0]), "cylinders": int(cfg["cylinders"].shape[0]),
@@ -509,8 +520,13 @@ def main():
                                                "paths": census["creeping"] + census["reflections"],
                                                "creeping": census["creeping"], "reflections": census["reflections"],
                                                "los_receivers": census["los"],
-                                               "note": "fused kernel: classification, BVH visibility and field; "
-                                                       "only the field's FP32 operations are counted"}),
+                                               "pairs": pairs, "geometry_flops": geom_flops,
+                                               "field_flops": field_flops,
+                                               "field_only_achieved": field_flops / (k_ms / 1e3) / 1e12,
+                                               "note": "fused kernel (classification, reflection points, "
+                                                       "visibility, field): 120 flops per candidate path "
+                                                       "(3 per receiver-body pair) plus the field of the "
+                                                       "visible paths"}),
                     "kernels_ms_per_step": per_kernel,
                     "tiles_ms": {"%dx%d" % k: v for k, v in tune["ms"].items()}})
     else:
