@@ -630,7 +630,7 @@ __global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(3, 8)
     __shared__ unsigned int s_mask[kBGroup * TILE / 4];   // bytes [body in group][lane]
     __shared__ uint32_t s_q[QCAP];
     __shared__ uint16_t s_pq[kPGroup * TILE];             // queued (lane, body) pairs
-    __shared__ int s_qn, s_pn;
+    __shared__ int s_qn, s_qr, s_pn;   // creeping / reflection candidates, queued pairs
     __shared__ int64_t s_tile;
     __shared__ float s_rx[3][TILE];                       // the tile's receivers
     const Tabs<R> tb = GlobalTabs<R>::get();
@@ -732,25 +732,29 @@ __global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(3, 8)
         for (int g0 = 0; g0 < nbf; g0 += kBGroup) {
             const int ng = nbf - g0 < kBGroup ? nbf - g0 : kBGroup;
             for (int k = tid; k < kBGroup * TILE / 4; k += TILE) s_mask[k] = 0u;
-            if (tid == 0) s_qn = 0;
+            if (tid == 0) { s_qn = 0; s_qr = 0; }
             __syncthreads();
             // --- 3. visibility: the queued candidates, one per lane (legs
             // against the frame's other bodies and the BVH); visible bits go
             // to the group's LDS masks and the queue is emptied
-            auto drain = [&](int qn) {
-                for (int kq = tid; kq < qn; kq += TILE) {
-                    const uint32_t key = s_q[kq];
+            // Creeping candidates fill the queue from the front, reflections
+            // from the back, so most wavefronts hold one kind (one branch).
+            auto drain = [&](int qn, int qr) {
+                for (int kq = tid; kq < qn + qr; kq += TILE) {
+                    const uint32_t key = s_q[kq < qn ? kq : QCAP - qr + (kq - qn)];
                     const int lane = (int)(key & 0xffu), blk = (int)((key >> 8) & 0x1fu), bit = (int)(key >> 13);
                     const d3 R2 = mk(s_rx[0][lane], s_rx[1][lane], s_rx[2][lane]);
                     const int b = g0 + blk;
                     const BodyPrep P = fprep[b];
-                    RxGeo g = rx_geo<double, Kinds::Cylinders>(P, R2);
                     PathPts pts;
                     if (bit == kBitRefl) {
+                        // a cylinder's reflection point needs only the angle
+                        // (no receiver geometry)
                         d3 Q, n3;
-                        refl_point<double, Kinds::Cylinders>(P, g, R2, T, thb[blk * TILE + lane], &Q, &n3);
+                        refl_point<double, Kinds::Cylinders>(P, RxGeo{}, R2, T, thb[blk * TILE + lane], &Q, &n3);
                         pts.P0 = T; pts.P1 = Q; pts.P2 = Q; pts.P3 = R2;
                     } else {
+                        RxGeo g = rx_geo<double, Kinds::Cylinders>(P, R2);
                         cyl_creep<R, double>(P, g, R2, T, L, (bit & 1) ? -1 : 1, bit >> 1,
                                              (PathEval<R>*)nullptr, &pts);
                     }
@@ -775,7 +779,7 @@ __global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(3, 8)
                     }
                 }
                 __syncthreads();
-                if (tid == 0) s_qn = 0;
+                if (tid == 0) { s_qn = 0; s_qr = 0; }
                 __syncthreads();
             };
             // --- 1. cull: the (receiver, body) pairs whose heights can reach
@@ -816,24 +820,27 @@ __global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(3, 8)
                             cand |= 1u << kBitRefl;
                             thb[bl * TILE + lane] = th;
                         }
-                        if (cand) {
-                            int q = atomicAdd(&s_qn, __builtin_popcount(cand));
-                            for (int bit = 0; bit <= kBitRefl; ++bit)
-                                if ((cand >> bit) & 1u)
-                                    s_q[q++] = (uint32_t)lane | ((uint32_t)bl << 8) | ((uint32_t)bit << 13);
+                        const uint32_t key0 = (uint32_t)lane | ((uint32_t)bl << 8);
+                        const uint32_t creep = cand & ((1u << kBitRefl) - 1u);
+                        if (creep) {
+                            int q = atomicAdd(&s_qn, __builtin_popcount(creep));
+                            for (int bit = 0; bit < kBitRefl; ++bit)
+                                if ((creep >> bit) & 1u) s_q[q++] = key0 | ((uint32_t)bit << 13);
                         }
+                        if ((cand >> kBitRefl) & 1u)
+                            s_q[QCAP - 1 - atomicAdd(&s_qr, 1)] = key0 | ((uint32_t)kBitRefl << 13);
                     }
                     __syncthreads();
                     // every wave reads the count before any wave appends more,
                     // so the drain decision is workgroup-uniform
-                    const int qn = s_qn;
+                    const int qn = s_qn, qr = s_qr;
                     __syncthreads();
-                    if (qn > QCAP - TILE * per_pair) drain(qn);
+                    if (qn + qr > QCAP - TILE * per_pair) drain(qn, qr);
                 }
             }
             // every write of the count was followed by a barrier
-            const int qe = s_qn;
-            if (qe > 0) drain(qe);
+            const int qe = s_qn, qf = s_qr;
+            if (qe + qf > 0) drain(qe, qf);
             // --- 4. field of this group's visible paths ---------------------
             // Each lane walks its own visible paths (creeping paths in
             // (body, bit) order, then the reflections), so a wavefront runs
@@ -859,13 +866,13 @@ __global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(3, 8)
                         const int bit = __builtin_ctz(mrem);
                         mrem &= mrem - 1u;
                         const BodyPrep P = fprep[g0 + bl];
-                        RxGeo g = rx_geo<double, Kinds::Cylinders>(P, R3);
                         PathEval<R> pe;
                         if (pass == 1) {
                             d3 Q, n3;
-                            refl_point<double, Kinds::Cylinders>(P, g, R3, T, thb[bl * TILE + tid], &Q, &n3);
+                            refl_point<double, Kinds::Cylinders>(P, RxGeo{}, R3, T, thb[bl * TILE + tid], &Q, &n3);
                             refl_eval<R, double>(P, Q, n3, R3, T, L, &pe);
                         } else {
+                            RxGeo g = rx_geo<double, Kinds::Cylinders>(P, R3);
                             cyl_creep<R, double>(P, g, R3, T, L, (bit & 1) ? -1 : 1, bit >> 1, &pe, nullptr);
                         }
 #pragma unroll 1
