@@ -875,27 +875,44 @@ __global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(3, 8)
                             RxGeo g = rx_geo<double, Kinds::Cylinders>(P, R3);
                             cyl_creep<R, double>(P, g, R3, T, L, (bit & 1) ? -1 : 1, bit >> 1, &pe, nullptr);
                         }
+                        // Two frequencies per step: both loads first, then
+                        // both evaluations, then both stores, so the memory
+                        // latency of one overlaps the other's work (four per
+                        // step measured slower: registers).  With an odd
+                        // count the last step's second slot repeats the
+                        // first unchanged and is stored before it.
 #pragma unroll 1
-                        for (int j = 0; j < L.n_f; ++j) {
-                            if (!fcs[j].ok) continue;     // an invalid frequency keeps its zero field
-                            R e[6];
+                        for (int j = 0; j < L.n_f; j += 2) {
+                            const bool two = j + 1 < L.n_f;
+                            R e[2][6];
 #pragma unroll
-                            for (int c = 0; c < 3; ++c) {
-                                const int64_t o = (int64_t)(j * 3 + c) * es + ec;
-                                e[2 * c] = Ew[2 * o];
-                                e[2 * c + 1] = Ew[2 * o + 1];
-                            }
-                            FreqC<R> fc(fcs[j]);
-                            if (pass == 0)
-                                add_path<R, kCreep>(pe, tb, fc, e);
-                            else
-                                add_path<R, kRefl>(pe, tb, fc, e);
+                            for (int u = 0; u < 2; ++u)
 #pragma unroll
-                            for (int c = 0; c < 3; ++c) {
-                                const int64_t o = (int64_t)(j * 3 + c) * es + ec;
-                                Ew[2 * o] = e[2 * c];
-                                Ew[2 * o + 1] = e[2 * c + 1];
+                                for (int c = 0; c < 3; ++c) {
+                                    const int64_t o = (int64_t)((j + (two ? u : 0)) * 3 + c) * es + ec;
+                                    e[u][2 * c] = Ew[2 * o];
+                                    e[u][2 * c + 1] = Ew[2 * o + 1];
+                                }
+#pragma unroll
+                            for (int u = 0; u < 2; ++u) {
+                                const int jj = j + (two ? u : 0);
+                                // an invalid frequency keeps its zero field
+                                if ((u == 0 || two) && fcs[jj].ok) {
+                                    FreqC<R> fc(fcs[jj]);
+                                    if (pass == 0)
+                                        add_path<R, kCreep>(pe, tb, fc, e[u]);
+                                    else
+                                        add_path<R, kRefl>(pe, tb, fc, e[u]);
+                                }
                             }
+#pragma unroll
+                            for (int u = 1; u >= 0; --u)
+#pragma unroll
+                                for (int c = 0; c < 3; ++c) {
+                                    const int64_t o = (int64_t)((j + (two ? u : 0)) * 3 + c) * es + ec;
+                                    Ew[2 * o] = e[u][2 * c];
+                                    Ew[2 * o + 1] = e[u][2 * c + 1];
+                                }
                         }
                     }
                 }
