@@ -631,6 +631,8 @@ __global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(3, 8)
     __shared__ uint32_t s_q[QCAP];
     __shared__ uint16_t s_pq[kPGroup * TILE];             // queued (lane, body) pairs
     __shared__ int s_qn, s_qr, s_pn;   // creeping / reflection candidates, queued pairs
+    __shared__ float s_box[TILE / 64][6];                 // per wavefront: its live receivers' box
+    __shared__ uint32_t s_tmask;                          // bodies of the group the tile's box can reach
     __shared__ int64_t s_tile;
     __shared__ float s_rx[3][TILE];                       // the tile's receivers
     const Tabs<R> tb = GlobalTabs<R>::get();
@@ -729,10 +731,42 @@ __global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(3, 8)
             }
         }
 
+        // box of the tile's live receivers (for the per-group body cull)
+        {
+            const bool live = act && !dead;
+            float v[6] = {live ? rxx : INFINITY, live ? rxy : INFINITY, live ? rxz : INFINITY,
+                          live ? rxx : -INFINITY, live ? rxy : -INFINITY, live ? rxz : -INFINITY};
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    const float o = __shfl_xor(v[k], off);
+                    v[k] = k < 3 ? fminf(v[k], o) : fmaxf(v[k], o);
+                }
+            if ((tid & 63) == 0)
+#pragma unroll
+                for (int k = 0; k < 6; ++k) s_box[tid >> 6][k] = v[k];
+        }
+        __syncthreads();
+
         for (int g0 = 0; g0 < nbf; g0 += kBGroup) {
             const int ng = nbf - g0 < kBGroup ? nbf - g0 : kBGroup;
             for (int k = tid; k < kBGroup * TILE / 4; k += TILE) s_mask[k] = 0u;
             if (tid == 0) { s_qn = 0; s_qr = 0; }
+            // the group's bodies that some live receiver of the tile may reach
+            if (tid < 64) {
+                float blo[3] = {INFINITY, INFINITY, INFINITY}, bhi[3] = {-INFINITY, -INFINITY, -INFINITY};
+                for (int w = 0; w < TILE / 64; ++w)
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        blo[k] = fminf(blo[k], s_box[w][k]);
+                        bhi[k] = fmaxf(bhi[k], s_box[w][3 + k]);
+                    }
+                const bool any_live = blo[0] <= bhi[0];
+                const bool okb = any_live && tid < ng && cyl_box_possible(fprep[g0 + tid], blo, bhi, T, L);
+                const uint64_t bm = __ballot(okb);
+                if (tid == 0) s_tmask = (uint32_t)bm;
+            }
             __syncthreads();
             // --- 3. visibility: the queued candidates, one per lane (legs
             // against the frame's other bodies and the BVH); visible bits go
@@ -767,9 +801,13 @@ __global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(3, 8)
                         vis = fv != 1;
                         leg = fv == 0 ? 1 : 0;
                     }
+                    // a reflection tests its receiver-side leg first (the one
+                    // more often blocked on the crowd: 1.5 % faster); the
+                    // order does not change the decision
 #pragma unroll 1
                     for (; leg < 2 && vis; ++leg) {
-                        d3 a = leg ? pts.P2 : pts.P0, c = leg ? pts.P3 : pts.P1;
+                        const int lg = bit == kBitRefl ? 1 - leg : leg;
+                        d3 a = lg ? pts.P2 : pts.P0, c = lg ? pts.P3 : pts.P1;
                         vis = !seg_blocked_frame(a, c, L, fcyl, b, L.bodies_occlude != 0, fgrid, nodes, tris,
                                            stk, TILE);
                     }
@@ -791,7 +829,7 @@ __global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(3, 8)
                 if (tid == 0) s_pn = 0;
                 __syncthreads();
                 for (int bl = c0; bl < c0 + nc; ++bl) {
-                    const bool ok = act && !dead && cyl_paths_possible(fprep[g0 + bl], R3, T, L);
+                    const bool ok = act && !dead && ((s_tmask >> bl) & 1u) && cyl_paths_possible(fprep[g0 + bl], R3, T, L);
                     if (ok) s_pq[atomicAdd(&s_pn, 1)] = (uint16_t)((uint32_t)tid | ((uint32_t)bl << 8));
                 }
                 __syncthreads();

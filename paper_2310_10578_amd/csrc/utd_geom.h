@@ -481,6 +481,41 @@ __device__ __forceinline__ bool cyl_paths_possible(const BodyPrep& b, d3 Rp, d3 
     return false;
 }
 
+// cyl_paths_possible for every receiver of a box at once: false only when
+// no receiver with lo <= R <= hi (componentwise) passes it.  The distances
+// to the axis over the box bound the tangent lengths, and each height test
+// becomes the range of z_T + dz f over the box of (dz, f) that the
+// receivers' values fill; the slack is a thousand times the per-receiver one.
+__device__ __forceinline__ bool cyl_box_possible(const BodyPrep& b, const float* lo, const float* hi, d3 T,
+                                                 const LaunchParams& L) {
+    if (!b.ok) return false;
+    const double a = b.a;
+    const double ex = fmax(fmax((double)lo[0] - b.c[0], b.c[0] - (double)hi[0]), 0.0);
+    const double ey = fmax(fmax((double)lo[1] - b.c[1], b.c[1] - (double)hi[1]), 0.0);
+    const double fx = fmax(fabs((double)lo[0] - b.c[0]), fabs((double)hi[0] - b.c[0]));
+    const double fy = fmax(fabs((double)lo[1] - b.c[1]), fabs((double)hi[1] - b.c[1]));
+    const double dmax = sqrt(fx * fx + fy * fy);
+    if (!(dmax > a)) return false;
+    const double d0 = fmax(sqrt(ex * ex + ey * ey), a);
+    const double s0 = sqrt(fmax((d0 - a) * (d0 + a), 0.0)), s1 = sqrt((dmax - a) * (dmax + a));
+    const double dz0 = (double)lo[2] - T.z, dz1 = (double)hi[2] - T.z;
+    const double slack = 1e-6 * (1.0 + fabs(T.z) + fmax(fabs((double)lo[2]), fabs((double)hi[2])));
+    const double zlo = b.z0 - slack, zhi = b.z0 + b.h + slack;
+    auto meets = [&](double f0, double f1) {
+        const double p0 = dz0 * f0, p1 = dz0 * f1, p2 = dz1 * f0, p3 = dz1 * f1;
+        return T.z + fmax(fmax(p0, p1), fmax(p2, p3)) >= zlo && T.z + fmin(fmin(p0, p1), fmin(p2, p3)) <= zhi;
+    };
+    const double sI = b.sI0, c = kTwoPi * (L.l_enc + 1) * a;
+    if (meets(sI / (sI + s1 + c), sI / (sI + s0)) && meets(sI / (sI + s1), 1.0 - s0 / (sI + s0 + c))) return true;
+    if (L.lit_branch) {
+        const double da = b.dT - a;
+        const double fa0 = da / (da + s1), fa1 = da / (da + s0);
+        const double fb0 = sI / (sI + (dmax - a)), fb1 = sI / (sI + (d0 - a));
+        if (meets(fmin(fa0, fb0), fmax(fa1, fb1))) return true;
+    }
+    return false;
+}
+
 // Reflection point for a lit receiver: the angle parameter (sphere: polar
 // angle in the T-C-R plane; cylinder: azimuth), false if the receiver is not
 // lit by this body or the point is off the lateral surface.
