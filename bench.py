@@ -69,9 +69,9 @@ PEAK_FP32_TFLOPS = 78.6
 PEAK_FP32_PUBLISHED_TFLOPS = 157.3
 PEAK_HBM_GBPS = 8000.0
 
-TRAFFIC_PROFILE = {"config2": "profiles/counters_k_field_sphere-plane-64f.md",
-                   "config3": "profiles/counters_k_vis_room-512x512-2f.md",
-                   "config4": "profiles/counters_k_batch_crowd-256f.md"}
+TRAFFIC_PROFILE = {"sphere_plane": "profiles/counters_k_field_sphere-plane-64f.md",
+                   "room": "profiles/counters_k_vis_room-512x512-2f.md",
+                   "crowd": "profiles/counters_k_batch_crowd-256f.md"}
 VIS_KERNELS = ("utd::k_setup", "utd::k_cand<float", "utd::k_vis<float", "utd::k_rec<float", "utd::k_paths<float")
 
 
@@ -119,7 +119,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10, help="timed steps of the headline workload")
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="config4", choices=["config4", "config2", "config3", "config5"],
+    ap.add_argument("--workload", default="crowd", choices=["crowd", "sphere_plane", "room", "room_adjoint"],
                     help="headline workload (default: the crowd, batched)")
     ap.add_argument("--secondary", type=int, default=1, help="also time the per-frame, field, occlusion and "
                                                              "adjoint measurements")
@@ -197,7 +197,7 @@ def crowd_setup():
 
     import paper_2310_10578_amd as utd
     import workloads as W
-    cfg = W.config4()
+    cfg = W.crowd()
     d = dict(cfg=cfg, scene=utd.Scene(cfg["tri"]), bo=_dev(cfg["body_off"]), ro=_dev(cfg["rx_off"]),
              cyl=_dev(cfg["cylinders"]), rx=_dev(cfg["rx"]), freqs=_dev(np.asarray(cfg["freqs"], np.float64)),
              src=utd.make_source(cfg["tx"]["pos"], cfg["tx"]["dipole"], cfg["tx"]["amplitude"]))
@@ -327,7 +327,7 @@ def adjoint_measure(steps):
     scratch (it repeats classification and visibility) and the backward from
     the state a forward call saved (the autograd path)."""
     import paper_2310_10578_amd as utd
-    d = single_setup("config5")
+    d = single_setup("room_adjoint")
     step = single_step(d)
     step()
     gE = 2 * d["out"]
@@ -441,12 +441,21 @@ def cpu_baseline(d, n_frames, n_rx):
     except AttributeError:
         share = os.cpu_count() or 1
     procs = max(1, min(share, 16, len(tasks)))
-    with mp.get_context("fork").Pool(procs) as pool:
+    # the workers are joined, not terminated: a worker killed by a signal
+    # can hang in a profiler's exit handler when this runs under one
+    pool = mp.get_context("fork").Pool(procs)
+    try:
         parts = [None] * len(tasks)
         for k, part in pool.imap_unordered(_oracle_frame_k, list(enumerate(tasks)), chunksize=1):
             parts[k] = part
             _progress("oracle frame %d of %d done (%.1f s)" % (sum(p is not None for p in parts), len(tasks),
                                                                part[2]))
+    except BaseException:
+        pool.terminate()
+        raise
+    pool.close()
+    pool.join()
+    _progress("oracle workers joined")
     n_f = len(cfg["freqs"])
     evals = sum(n_rx * (bo[f + 1] - bo[f]) for f in frames) * n_f
     field_s = sum(p[2] for p in parts)
@@ -496,7 +505,7 @@ def main():
            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic"}
     crowd = None
-    if args.workload == "config4":
+    if args.workload == "crowd":
         crowd = crowd_setup()
         _progress("crowd set up")
         ms, wall, k_ms, per_kernel, tune = crowd_batched(crowd, args.steps, args.warmup)
@@ -516,7 +525,7 @@ def main():
                                "evals_per_step": crowd["evals"], "tile": list(tune["best"]),
                                "parallelism": "single-gpu"},
                     "roofline": _alu_roofline(flops, k_ms, "k_batch<float,%d>" % tune["best"][0],
-                                              {"traffic": measured_traffic("config4", "utd::k_batch<float"),
+                                              {"traffic": measured_traffic("crowd", "utd::k_batch<float"),
                                                "paths": census["creeping"] + census["reflections"],
                                                "creeping": census["creeping"], "reflections": census["reflections"],
                                                "los_receivers": census["los"],
@@ -542,11 +551,11 @@ def main():
             res["per_frame"] = {"ms_per_step": p_ms, "evals_per_s": crowd["evals"] / (p_ms / 1e3),
                                 "batched_over_per_frame_speedup": p_ms / res["ms_per_step"]}
             _progress("per-frame crowd timed")
-        if args.workload != "config2":
-            res["field"] = field_measure("config2", args.secondary_steps, 20)
+        if args.workload != "sphere_plane":
+            res["field"] = field_measure("sphere_plane", args.secondary_steps, 20)
             _progress("field workload timed")
-        if args.workload != "config3":
-            res["occlusion"] = field_measure("config3", max(10, args.secondary_steps // 10), 3)
+        if args.workload != "room":
+            res["occlusion"] = field_measure("room", max(10, args.secondary_steps // 10), 3)
             _progress("occlusion workload timed")
         res["adjoint"] = adjoint_measure(5)
         _progress("adjoint timed")

@@ -8,15 +8,23 @@
 //   k_batch_sort   per frame, a counting sort of the receivers by spatial
 //                  cell (Morton order of a grid over the frame's receivers),
 //                  so that the receivers of one tile are neighbours
+//   k_batch_grid   per frame, the grid of the cylinders' footprints that
+//                  the visibility tests take their candidate bodies from
+//   k_batch_fans   per (cylinder, side), the visibility profile of the
+//                  source-side legs along the tangent line
 //   k_batch        persistent: each workgroup takes the next (frame, tile of
 //                  TILE receivers in sorted order) from an atomic work queue
-//                  until the queue is empty.  A lane owns one receiver:
-//                  inside / line-of-sight flags, then per body of its frame
-//                  the path geometry, the visibility tests, and for each
-//                  visible path the Fock evaluation of every frequency, added
-//                  in place to the lane's column of the block's field scratch
-//                  (initialised with the direct ray), which is copied to the
-//                  receiver's own place in E when the tile is done.
+//                  until the queue is empty.  A lane owns one receiver: its
+//                  flags and direct ray; then per group of the frame's
+//                  bodies a cull (tile box, then per receiver), the
+//                  classification of the surviving (receiver, body) pairs
+//                  one per lane into an LDS queue of candidate paths, the
+//                  visibility of the candidates one per lane, and the Fock
+//                  evaluation of each lane's visible paths at every
+//                  frequency, added in place to the lane's column of the
+//                  block's field scratch (initialised with the direct ray),
+//                  which is copied to the receiver's own place in E when the
+//                  tile is done.
 //
 // Neighbouring receivers have nearly the same paths: their candidate legs
 // walk the same BVH nodes and meet the same bodies, so a wavefront of
@@ -25,11 +33,11 @@
 // The order changes nothing in any receiver's result: each receiver's field
 // is computed by one lane, whatever lane that is.
 //
-// Fusing visibility and field keeps no per-path records (config-4 sized runs
-// have ~2.7e8 receiver-body pairs); the per-receiver accumulation order is
-// that of the single-frame kernels (direct ray, then bodies in order, paths
-// in (ell, side) order, reflection last), so a frame gives the same field as
-// utd_smooth_field on that frame up to floating-point contraction.
+// Fusing visibility and field keeps no per-path records (a 256-frame crowd
+// has ~2.4e8 receiver-body pairs).  Each receiver's field is the direct ray,
+// then per group of 32 bodies its creeping paths in (body, ell, side) order
+// and its reflections in body order, so a frame gives the field of
+// utd_smooth_field on that frame up to rounding.
 #pragma once
 
 namespace utd {

@@ -104,7 +104,7 @@ def test_small_room_vs_oracle(room_case, precision):
 
 @pytest.fixture(scope="module")
 def sphere_case():
-    cfg = W.config1(n_rx=96, polarisation="hard")
+    cfg = W.sphere_ring(n_rx=96, polarisation="hard")
     cfg["tx"]["dipole"] = np.array([0.6, 0.3, 0.74], np.float32)
     rng = np.random.default_rng(12)
     cfg["rx"] = (cfg["rx"] + rng.normal(0, 0.3, cfg["rx"].shape)).astype(np.float32)
@@ -115,7 +115,7 @@ def sphere_case():
 
 @pytest.mark.parametrize("precision", [1, 0])
 def test_sphere_encircling_vs_oracle(sphere_case, precision):
-    """Config-1 sphere with receivers jittered off the plane, a tilted dipole
+    """The 0.5 m sphere's receiver ring with receivers jittered off the plane, a tilted dipole
     and one extra encirclement per side (l_enc = 1)."""
     cfg, G, go = sphere_case
     gg = gpu_grad(cfg, G, precision, l_enc=1)
@@ -132,7 +132,7 @@ def test_adjoint_full_size_sampled():
     receivers' loss); the oracle differentiates the source and the 6 bodies
     with the most paths to them, and every body with no valid path to them
     must get exactly zero."""
-    cfg = W.config5()
+    cfg = W.room_adjoint()
     n = cfg["rx"].shape[0]
     rng = np.random.default_rng(14)
     idx = np.sort(rng.choice(n, 16, replace=False))
@@ -150,7 +150,7 @@ def test_adjoint_full_size_sampled():
     sel = dict(tx=gg["tx"], sph=gg["sph"], cyl=gg["cyl"][top])
     ref = dict(tx=go["tx"], sph=go["sph"], cyl=go["cyl"][top])
     e = _err(sel, ref)
-    _report("config5 full sampled", e)
+    _report("room_adjoint full sampled", e)
     assert e <= TOL[0]
     none = [b for b in range(cfg["scene"]["cylinders"].shape[0]) if b not in count]
     assert np.all(gg["cyl"][none] == 0)

@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _crowd(n_frames=10, n_pop=16, rx_range=(40, 700)):
-    return W.config4(n_frames=n_frames, n_pop=n_pop, rx_range=rx_range, edge=0.5)
+    return W.crowd(n_frames=n_frames, n_pop=n_pop, rx_range=rx_range, edge=0.5)
 
 
 def _to_dev(cfg):
@@ -277,7 +277,7 @@ def test_batched_second_body_group_and_options(precision, kw):
     scene.close()
 
 
-def test_config4_full_size_sampled_frames():
+def test_crowd_full_size_sampled_frames():
     """Config 4 at full size (256 frames of the 2.0e5-triangle room, 0..64
     cylinders, 1k..64k receivers, 8 frequencies, FP32) in the bench's launch
     configuration (tile 256 x 3): the frames with the most cylinders and the
@@ -286,7 +286,7 @@ def test_config4_full_size_sampled_frames():
     receivers each, evaluated with the per-frame call's decisions."""
     import paper_2310_10578_amd as utd
     from gpu_util import parity
-    cfg = W.config4()
+    cfg = W.crowd()
     scene = utd.Scene(cfg["tri"])
     d = _to_dev(cfg)
     utd.batched_config(256, 3)
@@ -294,7 +294,7 @@ def test_config4_full_size_sampled_frames():
     nb, nr = np.diff(cfg["body_off"]), np.diff(cfg["rx_off"])
     frames = sorted({int(np.argmax(nb)), int(np.argmax(nr)), int(np.argmax(nb * (nr > 30000))), 17})
     worst = _compare_frames(cfg, E, fl, scene, 0, frames=frames)
-    print("config4 full size: frames %s (cylinders %s, receivers %s) vs per-frame: worst %.2e" % (
+    print("crowd full size: frames %s (cylinders %s, receivers %s) vs per-frame: worst %.2e" % (
         frames, nb[frames].tolist(), nr[frames].tolist(), worst), flush=True)
     allf = list(_frames(cfg, E, fl))
     rng = np.random.default_rng(11)
@@ -308,7 +308,7 @@ def test_config4_full_size_sampled_frames():
         mk, _ = utd.path_masks(scene, None, torch.from_numpy(np.ascontiguousarray(cyl)).cuda(), src,
                                torch.from_numpy(np.ascontiguousarray(rx)).cuda())
         torch.cuda.synchronize()
-        parity(one, 0, sample=idx, lib=(blk, flb, mk.cpu().numpy()), name="config4 frame %d (%d cylinders)" % (
+        parity(one, 0, sample=idx, lib=(blk, flb, mk.cpu().numpy()), name="crowd frame %d (%d cylinders)" % (
             f, cyl.shape[0]))
     scene.close()
 

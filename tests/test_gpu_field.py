@@ -28,34 +28,34 @@ R14 = {0: 1e-3, 1: 1e-9}
 
 @pytest.mark.parametrize("precision", [1, 0])
 @pytest.mark.parametrize("pol", ["hard", "soft"])
-def test_config1_sphere_ring(precision, pol):
-    cfg = W.config1(polarisation=pol)
-    parity(cfg, precision, name="config1 %s" % pol, r14_bound=R14[precision], max_mismatch=0)
+def test_sphere_ring(precision, pol):
+    cfg = W.sphere_ring(polarisation=pol)
+    parity(cfg, precision, name="sphere_ring %s" % pol, r14_bound=R14[precision], max_mismatch=0)
 
 
 @pytest.mark.parametrize("precision", [1, 0])
-def test_config2_plane_subsample(precision):
+def test_sphere_plane_subsample(precision):
     """Config 2 geometry: every 8th receiver row/column (32 x 32 = 1024, a
     ragged tail w.r.t. the 256-lane blocks) at 9 of the 64 frequencies, so the
     frequency chunks also end ragged."""
-    cfg = W.config2()
+    cfg = W.sphere_plane()
     rx = cfg["rx"].reshape(256, 256, 3)[3::8, 5::8].reshape(-1, 3)
-    parity(cfg, precision, rx=rx, freqs=cfg["freqs"][::7], name="config2 subsample", r14_bound=R14[precision],
+    parity(cfg, precision, rx=rx, freqs=cfg["freqs"][::7], name="sphere_plane subsample", r14_bound=R14[precision],
            max_mismatch=0)
 
 
 @pytest.mark.parametrize("lit_branch", [True, False])
-def test_config2_full_size_sampled(lit_branch):
+def test_sphere_plane_full_size_sampled(lit_branch):
     """Config 2 at full size in the launch configuration the bench times
     (65536 receivers, 64 frequencies, FP32), with and without the lit branch
     (creeping fields alone: the deep-shadow field, 20-40 dB below the direct
     ray, is compared on its own); 1500 sampled receivers recomputed by the
     oracle one by one."""
-    cfg = W.config2()
+    cfg = W.sphere_plane()
     rng = np.random.default_rng(3)
     idx = np.sort(rng.choice(cfg["rx"].shape[0], 1500, replace=False))
     opts = dict(lit_branch=lit_branch)
-    res = parity(cfg, 0, sample=idx, opts=opts, name="config2 full sampled lit_branch=%s" % lit_branch,
+    res = parity(cfg, 0, sample=idx, opts=opts, name="sphere_plane full sampled lit_branch=%s" % lit_branch,
                  r14_bound=R14[0], max_mismatch=0)
     if not lit_branch:
         # the sample reaches into the shadow, where only creeping paths exist
@@ -77,7 +77,7 @@ def test_encirclements_and_creeping_only(precision):
 
 
 def test_inside_and_degenerate_receivers():
-    cfg = W.config1(n_rx=8)
+    cfg = W.sphere_ring(n_rx=8)
     rx = np.array([[0.1, 0.0, 0.0],        # inside the sphere
                    [-3.0, 0.0, 0.0],       # on the source axis behind the sphere (caustic)
                    [0.0, 2.0, 0.0],
@@ -91,7 +91,7 @@ def test_inside_and_degenerate_receivers():
 
 
 def test_source_inside_body_zeroes_field():
-    cfg = W.config1(n_rx=64)
+    cfg = W.sphere_ring(n_rx=64)
     cfg["tx"] = dict(pos=np.array([0.1, 0.0, 0.0], np.float32), dipole=np.array([0, 0, 1.0], np.float32),
                      amplitude=1.0)
     Eg, fg = run_library(cfg, 0)
@@ -185,7 +185,7 @@ def test_bad_arguments_raise():
         utd.smooth_field(scene, None, None, src, rx, f, precision=3)
 
 
-@pytest.mark.parametrize("cfg_name", ["config3", "config5"])
+@pytest.mark.parametrize("cfg_name", ["room", "room_adjoint"])
 def test_room_full_size_sampled(cfg_name):
     """The indoor room at full size (2.0e5 triangles; 32 cylinders, 512^2
     receivers, 5/28 GHz -- or 64 cylinders, 128^2 receivers, 16 frequencies)
@@ -244,7 +244,7 @@ def test_ragged_receivers_and_frequency_chunks(n_side, n_f, precision):
     (FP32 65025 x 63: four per lane, the last chunk of 3 in rows of two;
     FP32 and FP64 65025 x 17: two per lane, the last chunk of 1 in rows of
     one); sampled receivers against the oracle, including the last ones."""
-    cfg = W.config2(n_side=n_side, n_f=n_f)
+    cfg = W.sphere_plane(n_side=n_side, n_f=n_f)
     n = cfg["rx"].shape[0]
     rng = np.random.default_rng(9)
     idx = np.unique(np.concatenate([rng.choice(n, 300, replace=False), np.arange(n - 64, n)]))
@@ -270,9 +270,9 @@ def _band_case(body):
     n = 256
     d = np.linspace(-1e-3, 1e-3, n)
     if body == "sphere":
-        # config-2 sphere (a = 1, source (4, 0, 0)), receivers on x = -3:
+        # the 1 m sphere of the plane workload (source (4, 0, 0)), receivers on x = -3:
         # r_b = sqrt(49/15), spread azimuths
-        cfg = W.config2(n_side=4, n_f=4)
+        cfg = W.sphere_plane(n_side=4, n_f=4)
         psi = np.arange(n) * 2.399963229728653
         r = np.sqrt(49.0 / 15.0) * (1.0 + d)
         rx = np.stack([np.full(n, -3.0), r * np.cos(psi), r * np.sin(psi)], 1)

@@ -39,7 +39,7 @@ def test_series_conventions_match_closed_forms():
 
 @pytest.mark.parametrize("mode,max_db,rms_db,lit_db", [("soft", 1.9, 0.6, 0.05), ("hard", 1.5, 0.35, 0.35)])
 def test_scalar_sphere_vs_mie(mode, max_db, rms_db, lit_db):
-    """Config-1 geometry (a = 0.5 m, source at 3 m, ring r = 3 m, 1 GHz,
+    """Sphere-ring geometry (a = 0.5 m, source at 3 m, ring r = 3 m, 1 GHz,
     ka = 10.5) against the exact series.  The leading-order UTD neglects
     O(m^-2) ~ 0.33 terms at m = 1.74; excluded: within 10 deg of the source
     and within 3 deg of the axial caustic."""

@@ -37,7 +37,7 @@ def empty_scene():
 # Config 1: sphere a = 0.5 m, source at (3,0,0), 4096 receivers on r = 3 m.
 # ---------------------------------------------------------------------------
 
-def config1(n_rx=4096, polarisation="hard"):
+def sphere_ring(n_rx=4096, polarisation="hard"):
     phi = 2 * np.pi * (np.arange(n_rx) + 0.5) / n_rx
     rx = np.stack([3 * np.cos(phi), 3 * np.sin(phi), np.zeros(n_rx)], 1).astype(np.float32)
     sc = empty_scene()
@@ -55,7 +55,7 @@ def config1(n_rx=4096, polarisation="hard"):
 # 64 frequencies 1..6 GHz.
 # ---------------------------------------------------------------------------
 
-def config2(n_side=256, n_f=64, dipole=(0.0, 0.0, 1.0)):
+def sphere_plane(n_side=256, n_f=64, dipole=(0.0, 0.0, 1.0)):
     c = -4 + 8 * (np.arange(n_side) + 0.5) / n_side
     yy, zz = np.meshgrid(c, c, indexing="ij")
     rx = np.stack([np.full(yy.size, -3.0), yy.ravel(), zz.ravel()], 1).astype(np.float32)
@@ -67,7 +67,7 @@ def config2(n_side=256, n_f=64, dipole=(0.0, 0.0, 1.0)):
 
 
 # ---------------------------------------------------------------------------
-# Indoor room (configs 3-5)
+# Indoor room (the room, its adjoint workload and the crowd)
 # ---------------------------------------------------------------------------
 
 def _quad_grid(origin, u, v, nu, nv):
@@ -171,20 +171,20 @@ def room_tx():
     return dict(pos=np.array(TX_ROOM, np.float32), dipole=np.array([0.0, 0.0, 1.0], np.float32), amplitude=1.0)
 
 
-def config3(n_side=512, edge=0.052):
+def room(n_side=512, edge=0.052):
     sc, boxes = room_scene(32, 0, edge)
     return dict(name="room10x8x3-200ktri-32cyl-512x512-5/28GHz", scene=sc, tx=room_tx(),
                 rx=room_grid(n_side), freqs=np.array([5e9, 28e9]), boxes=boxes)
 
 
-def config5(n_side=128, n_f=16, edge=0.052):
+def room_adjoint(n_side=128, n_f=16, edge=0.052):
     sc, boxes = room_scene(64, 1, edge)
     return dict(name="room10x8x3-200ktri-64cyl-128x128-16f", scene=sc, tx=room_tx(),
                 rx=room_grid(n_side), freqs=np.linspace(3.4e9, 3.8e9, n_f), boxes=boxes)
 
 
-def config4(n_frames=256, n_pop=64, step=0.05, edge=0.052, rx_range=(1000, 64000)):
-    """Dynamic crowd: the config-3 room; 64 cylinders random-walk 0.05 m per
+def crowd(n_frames=256, n_pop=64, step=0.05, edge=0.052, rx_range=(1000, 64000)):
+    """Dynamic crowd: the indoor room; 64 cylinders random-walk 0.05 m per
     frame (a move that would collide is rejected); frame f uses the first
     n_f ~ U{0..64} of them and n_rx ~ U{1000..64000} uniform receivers at 1.2 m."""
     boxes = furniture()
@@ -232,7 +232,7 @@ def to_oracle(scene, tx, rx):
 
 
 def small_room(n_cyl=8, edge=0.5, n_side=24, freqs=(5e9, 28e9), spheres=False):
-    """The config-3 room at a coarse tessellation, fewer cylinders and a
+    """The indoor room at a coarse tessellation, fewer cylinders and a
     small receiver grid: a parity-test case the oracle finishes in seconds."""
     sc, boxes = room_scene(n_cyl, 7, edge)
     if spheres:
