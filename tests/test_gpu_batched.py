@@ -464,3 +464,32 @@ def test_batched_source_leg_profiles(precision):
         worst = _compare_frames(cfg, E, fl, scene, precision, l_enc=1)
         print("source-leg profiles p%d, source at %.1f m: worst frame %.2e" % (precision, tz, worst), flush=True)
     scene.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batched_result_independent_of_tile_shape(precision):
+    """Each receiver's field is summed by one lane in a fixed order (direct
+    ray, then per group of 32 bodies its creeping paths and its
+    reflections), and every visibility decision depends on its own path
+    only, so the tile shape and the workgroups per CU must not change a
+    single bit of the output: frames of up to 64 cylinders (two body
+    groups), l_enc = 0 and 2."""
+    import torch
+
+    import paper_2310_10578_amd as utd
+    cfg = _crowd(n_frames=8, n_pop=64, rx_range=(100, 1500))
+    scene = utd.Scene(cfg["tri"])
+    d = _to_dev(cfg)
+    for l_enc in (0, 2):
+        ref = None
+        for tile, bpc in ((256, 3), (128, 6), (64, 8), (256, 1)):
+            utd.batched_config(tile, bpc)
+            E, fl = _batched(cfg, precision, scene, d, l_enc=l_enc)
+            if ref is None:
+                ref = (E, fl)
+                continue
+            assert np.array_equal(fl, ref[1]), (tile, bpc, l_enc)
+            assert np.array_equal(E, ref[0]), (tile, bpc, l_enc, float(np.max(np.abs(E - ref[0]))))
+    utd.batched_config(256, 3)
+    torch.cuda.synchronize()
+    scene.close()
