@@ -493,3 +493,59 @@ def test_batched_result_independent_of_tile_shape(precision):
     utd.batched_config(256, 3)
     torch.cuda.synchronize()
     scene.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batched_tile_cull_receiver_by_receiver(precision):
+    """The tile-box cull skips a body for a whole tile only when no receiver
+    of the tile could carry one of its paths.  Receivers fill a band of
+    heights around the cylinders' tops, with the source above them, so that
+    many tiles' boxes straddle the heights where a cylinder's paths start or
+    stop existing; every receiver's field must equal that of per-frame calls
+    (which test every pair), receiver by receiver."""
+    import torch
+
+    import paper_2310_10578_amd as utd
+    rng = np.random.default_rng(97)
+    Lx, Ly = 10.0, 8.0
+    tri = np.concatenate([W.room_shell(0.5)] + [W.box_triangles(np.array([x, y, 0.0]), np.array([x + 0.4, y + 0.4, 0.8]))
+                                                for x, y in ((2.0, 2.0), (7.0, 5.0), (4.5, 6.5))]).astype(np.float32)
+    cyls, rxs, bo, ro = [], [], [0], [0]
+    for f in range(4):
+        nb = int(rng.integers(16, 48))
+        c = np.stack([rng.uniform(0.5, Lx - 0.5, nb), rng.uniform(0.5, Ly - 0.5, nb), np.zeros(nb),
+                      rng.uniform(1.0, 1.6, nb), rng.uniform(0.12, 0.3, nb)], 1)
+        nr = int(rng.integers(2000, 5000))
+        r = np.stack([rng.uniform(0, Lx, nr), rng.uniform(0, Ly, nr), rng.uniform(0.9, 1.7, nr)], 1)
+        cyls.append(c)
+        rxs.append(r)
+        bo.append(bo[-1] + nb)
+        ro.append(ro[-1] + nr)
+    cfg = dict(tri=tri, cylinders=np.concatenate(cyls).astype(np.float32), rx=np.concatenate(rxs).astype(np.float32),
+               body_off=np.array(bo, np.int64), rx_off=np.array(ro, np.int64),
+               tx=dict(pos=np.array([5.1, 3.9, 2.1], np.float32), dipole=np.array([0.3, 0.1, 0.9], np.float32),
+                       amplitude=1.0),
+               freqs=np.array([2.4e9, 3.6e9, 5.8e9]))
+    scene = utd.Scene(tri)
+    d = _to_dev(cfg)
+    # the two calls sum each receiver's paths in different orders: rounding
+    # differences, relative to the receiver's field or to 1 % of the frame's
+    # RMS field (a factor of up to 100 for weak receivers) -- about 1e-7
+    # (FP32) and 1e-13 (FP64) before that factor; a dropped or added path
+    # changes a receiver by far more (1e-3 and up)
+    tol = {0: 1e-5, 1: 1e-9}[precision]
+    for kw in (dict(), dict(l_enc=1)):
+        utd.batched_config(256, 3)
+        E, fl = _batched(cfg, precision, scene, d, **kw)
+        worst = 0.0
+        for f, cyl, rx, blk, flb in _frames(cfg, E, fl):
+            Es, fls = _single(cfg, scene, cyl, rx, precision, **kw)
+            np.testing.assert_array_equal(flb, fls)
+            mag = np.sqrt(np.sum(np.abs(Es) ** 2, axis=(0, 1)))
+            diff = np.sqrt(np.sum(np.abs(blk - Es) ** 2, axis=(0, 1)))
+            floor = 1e-2 * np.sqrt(np.mean(mag ** 2))
+            worst = max(worst, float(np.max(diff / np.maximum(mag, floor))))
+        print("tile cull p%d %s: worst receiver %.2e" % (precision, kw, worst), flush=True)
+        assert worst <= tol, worst
+    torch.cuda.synchronize()
+    scene.close()
