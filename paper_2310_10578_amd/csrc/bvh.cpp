@@ -71,8 +71,12 @@ struct Node {
     Child ch[2];
 };
 
-constexpr int kLeaf = 4;
-constexpr int kBins = 16;
+// At most two triangles per leaf and 32 SAH bins: of leaves of 1, 2, 4 and
+// 8 triangles and 16, 32 or 64 bins, the fastest for the batched crowd and
+// the room's visibility pass (the walks are latency-bound, so a node visit
+// that rejects a box costs about what a triangle test does).
+constexpr int kLeaf = 2;
+constexpr int kBins = 32;
 
 Box range_box(const std::vector<Prim>& P, int64_t b, int64_t e) {
     Box bx;
