@@ -1,5 +1,5 @@
 // Host-side BVH builder for the occluder triangles (binned SAH, two children
-// per node, leaves of at most 4 triangles).  The visibility steps U of
+// per node, leaves of at most 2 triangles).  The visibility steps U of
 // Eqs. (1)-(2) are decided by walking these trees on the GPU (utd_bvh.h).
 //
 // Two trees share the output arrays: the first (root node 0) holds the
