@@ -366,7 +366,8 @@ utd_status utd_input_status(uint32_t *bits);
  * (k = UTD_K_*; arrays of UTD_K_COUNT entries, host) and clears the record.
  * utd_profile_enable(0) stops recording.  While recording, a batched call
  * launches its kernels directly instead of replaying its graph, and times
- * its constants and receiver order (UTD_K_PREP) apart from its persistent
+ * its constants, receiver order, body grids, source-side profiles and the
+ * receivers' flags and direct rays (UTD_K_PREP) apart from its persistent
  * kernel (UTD_K_BATCHED).  Not for concurrent use from several host
  * threads.  Errors: UTD_E_ARG for NULL outputs, UTD_E_DEVICE. */
 #define UTD_K_PREP 0

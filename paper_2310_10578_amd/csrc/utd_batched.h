@@ -621,6 +621,52 @@ template <> struct GlobalTabs<double> {
     }
 };
 
+// Receiver flags and the direct rays' visibility of every receiver, in the
+// persistent kernel's tile order (sorted receivers: neighbouring lanes walk
+// the same BVH nodes).  Kept out of k_batch, whose registers are taken by the
+// path stages: here the walks run at six waves per SIMD (measured 1.3 ms
+// less in k_batch for 0.8 ms here on the crowd).  Each lane writes its
+// receiver's flags (inside, source inside, invalid receiver, bad body, bad
+// frequency, line of sight) to fl, which k_batch reads.
+template <int TILE>
+__global__ void __launch_bounds__(TILE) k_batch_los(BatchParams B, const float* __restrict__ rx,
+                                                    const float* __restrict__ cyl, const FreqConst* __restrict__ fcs,
+                                                    const int64_t* __restrict__ bo, const int64_t* __restrict__ ro,
+                                                    const int64_t* __restrict__ tile_off, const int* __restrict__ perm,
+                                                    const BodyGrid* __restrict__ grids,
+                                                    const float4* __restrict__ nodes, const float4* __restrict__ tris,
+                                                    uint8_t* __restrict__ fl) {
+    __shared__ int stack[kStackDepth * TILE];
+    int* stk = stack + threadIdx.x;
+    const int64_t total = tile_off[B.n_frames];
+    const d3 T = mk(B.L.T[0], B.L.T[1], B.L.T[2]);
+    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+        int64_t lo = 0, hi = B.n_frames;
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (tile_off[mid] <= t) lo = mid; else hi = mid;
+        }
+        const int64_t r0 = ro[lo], r1 = ro[lo + 1];
+        const int64_t li = (t - tile_off[lo]) * TILE + threadIdx.x;
+        if (r0 + li >= r1) continue;
+        const int src = perm[r0 + li];
+        if (src < 0 || src >= r1 - r0) continue;
+        const int64_t i = r0 + src;
+        LaunchParams L = B.L;
+        L.n_sph = 0;
+        L.n_cyl = (int)(bo[lo + 1] - bo[lo]);
+        L.n_rx = r1 - r0;
+        const float* fcyl = cyl + 5 * bo[lo];
+        const d3 R3 = mk(rx[3 * i], rx[3 * i + 1], rx[3 * i + 2]);
+        uint8_t f = receiver_flags(L, nullptr, fcyl, R3, T);
+        for (int j = 0; j < L.n_f; ++j)
+            if (!fcs[j].ok) f |= kFlagBadFreq;
+        if (!(f & kFlagDead) && !seg_blocked_frame(T, R3, L, fcyl, -1, true, grids + lo, nodes, tris, stk, TILE))
+            f |= kFlagLos;
+        fl[i] = f;
+    }
+}
+
 template <typename R, int TILE>
 __global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(3, 8))) k_batch(BatchParams B, const float* __restrict__ rx,
                                                 const float* __restrict__ cyl, const BodyPrep* __restrict__ prep,
@@ -630,7 +676,8 @@ __global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(3, 8)
                                                 const float4* __restrict__ tris, double* __restrict__ th_scratch,
                                                 const int* __restrict__ perm, R* __restrict__ ew_scratch,
                                                 const FanProfile* __restrict__ fans,
-                                                const BodyGrid* __restrict__ grids, R* __restrict__ E_out,
+                                                const BodyGrid* __restrict__ grids,
+                                                const uint8_t* __restrict__ flw, R* __restrict__ E_out,
                                                 uint8_t* __restrict__ flags) {
     static_assert(TILE <= 256, "lane index is stored in 8 bits");
     constexpr int QCAP = 8 * TILE;
@@ -703,16 +750,13 @@ __global__ void __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(3, 8)
         R* const Ew = Ews ? Ews : E;
         const int64_t es = Ews ? TILE : L.n_rx, ec = Ews ? tid : src;
 
-        // --- flags, direct ray, E initialisation ---------------------------
+        // --- flags and direct ray (from k_batch_los), E initialisation ------
         bool dead = true;
         uint8_t fl = 0;
         if (act) {
-            fl = receiver_flags(L, nullptr, fcyl, R3, T);
-            for (int j = 0; j < L.n_f; ++j)
-                if (!fcs[j].ok) fl |= kFlagBadFreq;
+            fl = flw[i];
             dead = (fl & kFlagDead) != 0;
-            const bool los = !dead && !seg_blocked_frame(T, R3, L, fcyl, -1, true, fgrid, nodes, tris, stk, TILE);
-            if (los) fl |= kFlagLos;
+            const bool los = (fl & kFlagLos) != 0;
             R e3[3] = {(R)0, (R)0, (R)0};
             double sd = 0.0;
             const bool use_los = los && L.lit_branch;
@@ -985,7 +1029,8 @@ static hipError_t launch_batch_tile(const BatchParams& B, int n_blocks, const fl
                                     const BatchWs& w, const float4* nodes, const float4* tris, void* E,
                                     uint8_t* flags, hipStream_t s) {
     hipLaunchKernelGGL((k_batch<R, TILE>), dim3(n_blocks), dim3(TILE), 0, s, B, rx, cyl, w.prep, w.fcs, w.bo, w.ro,
-                       w.tile_off, w.counter, nodes, tris, w.th, w.perm, (R*)w.ew, w.fans, w.grids, (R*)E, flags);
+                       w.tile_off, w.counter, nodes, tris, w.th, w.perm, (R*)w.ew, w.fans, w.grids, w.flw, (R*)E,
+                       flags);
     return hipGetLastError();
 }
 
@@ -1014,6 +1059,7 @@ size_t batch_workspace(const BatchParams& B, int precision, int n_blocks, char* 
     const size_t o_th = take(sizeof(double) * (size_t)n_blocks * kBGroup * B.tile);
     const size_t o_fan = take(sizeof(FanProfile) * 2 * (size_t)(B.n_cyl > 0 ? B.n_cyl : 1));
     const size_t o_grid = take(sizeof(BodyGrid) * (size_t)(B.n_frames > 0 ? B.n_frames : 1));
+    const size_t o_flw = take((size_t)(B.n_rx > 0 ? B.n_rx : 1));
     const size_t ew_bytes = real * 2 * 3 * (size_t)B.L.n_f * (size_t)n_blocks * B.tile;
     const bool use_ew = ew_bytes <= kBatchFieldScratchMax;
     const size_t o_ew = take(use_ew ? ew_bytes : 0);
@@ -1029,6 +1075,7 @@ size_t batch_workspace(const BatchParams& B, int precision, int n_blocks, char* 
         ws->th = (double*)(base + o_th);
         ws->fans = (FanProfile*)(base + o_fan);
         ws->grids = (BodyGrid*)(base + o_grid);
+        ws->flw = (uint8_t*)(base + o_flw);
         ws->ew = use_ew ? base + o_ew : nullptr;
     }
     return o;
@@ -1059,7 +1106,23 @@ hipError_t launch_batch(const BatchParams& B, int precision, int n_blocks, const
             hipLaunchKernelGGL(k_batch_fans, dim3(fb), dim3(256), 0, s, B, cyl, w.prep, w.bo, nodes, tris,
                                n_main, w.fans);
             e = hipGetLastError();
+            if (e != hipSuccess) return e;
         }
+        const dim3 lg((unsigned)(2 * n_blocks));
+        switch (B.tile) {
+            case 64:
+                hipLaunchKernelGGL(k_batch_los<64>, lg, dim3(64), 0, s, B, rx, cyl, w.fcs, w.bo, w.ro, w.tile_off,
+                                   w.perm, w.grids, nodes, tris, w.flw);
+                break;
+            case 128:
+                hipLaunchKernelGGL(k_batch_los<128>, lg, dim3(128), 0, s, B, rx, cyl, w.fcs, w.bo, w.ro, w.tile_off,
+                                   w.perm, w.grids, nodes, tris, w.flw);
+                break;
+            default:
+                hipLaunchKernelGGL(k_batch_los<256>, lg, dim3(256), 0, s, B, rx, cyl, w.fcs, w.bo, w.ro, w.tile_off,
+                                   w.perm, w.grids, nodes, tris, w.flw);
+        }
+        e = hipGetLastError();
         if (e != hipSuccess || part == 1) return e;
     }
     if (precision == 0) {

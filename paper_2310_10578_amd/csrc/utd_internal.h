@@ -64,12 +64,14 @@ struct BatchWs {
     void* ew;                // per block: the tile's field
     struct FanProfile* fans; // per (cylinder, side): source-side leg profile
     struct BodyGrid* grids;  // per frame: grid of the cylinders' footprints
+    uint8_t* flw;            // per receiver: its flags and line of sight (k_batch_los)
 };
 size_t batch_workspace(const BatchParams& B, int precision, int n_blocks, char* base, BatchWs* ws);
-// part 0: the whole call; 1: the constants, the receiver order and the
-// source-side leg profiles only (k_batch_prep, k_batch_sort, k_batch_fans);
-// 2: the persistent kernel only.  n_main: nodes of the BVH's main
-// (interior-triangle) tree, which come first in `nodes`.
+// part 0: the whole call; 1: the constants, the receiver order, the body
+// grids, the source-side leg profiles and the receivers' flags and direct
+// rays only (k_batch_prep, k_batch_sort, k_batch_grid, k_batch_fans,
+// k_batch_los); 2: the persistent kernel only.  n_main: nodes of the BVH's
+// main (interior-triangle) tree, which come first in `nodes`.
 hipError_t launch_batch(const BatchParams& B, int precision, int n_blocks, const int64_t* body_off,
                         const int64_t* rx_off, const float* rx, const float* cyl, const double* freqs,
                         const BatchWs& ws, const float4* nodes, const float4* tris, int n_main, void* E,
