@@ -1108,7 +1108,10 @@ hipError_t launch_batch(const BatchParams& B, int precision, int n_blocks, const
             e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
-        const dim3 lg((unsigned)(2 * n_blocks));
+        // a block per tile up to 16384 blocks (grid-stride beyond): its own
+        // occupancy, whatever the persistent kernel's workgroups per CU
+        const int64_t ntile = B.n_rx / B.tile + B.n_frames + 1;
+        const dim3 lg((unsigned)(ntile < 16384 ? ntile : 16384));
         switch (B.tile) {
             case 64:
                 hipLaunchKernelGGL(k_batch_los<64>, lg, dim3(64), 0, s, B, rx, cyl, w.fcs, w.bo, w.ro, w.tile_off,
