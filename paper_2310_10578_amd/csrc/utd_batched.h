@@ -12,19 +12,21 @@
 //                  the visibility tests take their candidate bodies from
 //   k_batch_fans   per (cylinder, side), the visibility profile of the
 //                  source-side legs along the tangent line
+//   k_batch_los    per receiver, in the tiles' order, its flags and the
+//                  visibility of its direct ray
 //   k_batch        persistent: each workgroup takes the next (frame, tile of
 //                  TILE receivers in sorted order) from an atomic work queue
 //                  until the queue is empty.  A lane owns one receiver: its
-//                  flags and direct ray; then per group of the frame's
-//                  bodies a cull (tile box, then per receiver), the
-//                  classification of the surviving (receiver, body) pairs
-//                  one per lane into an LDS queue of candidate paths, the
-//                  visibility of the candidates one per lane, and the Fock
-//                  evaluation of each lane's visible paths at every
-//                  frequency, added in place to the lane's column of the
-//                  block's field scratch (initialised with the direct ray),
-//                  which is copied to the receiver's own place in E when the
-//                  tile is done.
+//                  flags and direct ray (from k_batch_los); then per group
+//                  of the frame's bodies a cull (tile box, then per
+//                  receiver), the classification of the surviving
+//                  (receiver, body) pairs one per lane into an LDS queue of
+//                  candidate paths, the visibility of the candidates one per
+//                  lane, and the Fock evaluation of each lane's visible paths
+//                  at every frequency, added in place to the lane's column of
+//                  the block's field scratch (initialised with the direct
+//                  ray), which is copied to the receiver's own place in E
+//                  when the tile is done.
 //
 // Neighbouring receivers have nearly the same paths: their candidate legs
 // walk the same BVH nodes and meet the same bodies, so a wavefront of
