@@ -566,14 +566,36 @@ __global__ void __launch_bounds__(256) k_batch_fans(BatchParams B, const float* 
 }
 
 // One block of kGridN^2 threads per frame (grid-stride): the grid of the
-// frame's cylinders (BodyGrid, utd_bvh.h).
+// frame's cylinders (BodyGrid, utd_bvh.h) and the receiver flags that are the
+// same for the whole frame (source inside a cylinder, an invalid cylinder),
+// with the invalid-body input bit raised for a frame that has receivers.
 __global__ void __launch_bounds__(kGridN * kGridN) k_batch_grid(BatchParams B, const float* __restrict__ cyl,
                                                                 const int64_t* __restrict__ bo,
+                                                                const int64_t* __restrict__ ro,
                                                                 BodyGrid* __restrict__ grids) {
     __shared__ float s_box[4];
+    __shared__ int s_ff;
+    const d3 T = mk(B.L.T[0], B.L.T[1], B.L.T[2]);
     for (int64_t fr = blockIdx.x; fr < B.n_frames; fr += gridDim.x) {
         const int64_t b0 = bo[fr], nb = bo[fr + 1] - b0;
+        if (threadIdx.x == 0) s_ff = 0;
         grid_build_block(grids + fr, nullptr, 0, cyl + 5 * b0, nb, s_box);
+        __syncthreads();
+        LaunchParams L = B.L;
+        L.n_sph = 0;
+        L.n_cyl = (int)nb;
+        int ff = 0;
+        for (int64_t j = threadIdx.x; j < nb; j += blockDim.x) {
+            if (inside_raw(L, nullptr, cyl + 5 * b0, (int)j, T)) ff |= kFlagTxInside;
+            if (body_params_bad(nullptr, 0, cyl + 5 * b0, (int)j)) ff |= kFlagBadBody;
+        }
+        if (ff) atomicOr(&s_ff, ff);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            grids[fr].fflags = s_ff;
+            report_bad((s_ff & kFlagBadBody) && ro[fr + 1] > ro[fr], kBadBody);
+        }
+        __syncthreads();   // s_ff is cleared for the next frame
     }
 }
 
@@ -660,7 +682,27 @@ __global__ void __launch_bounds__(TILE) k_batch_los(BatchParams B, const float* 
         L.n_rx = r1 - r0;
         const float* fcyl = cyl + 5 * bo[lo];
         const d3 R3 = mk(rx[3 * i], rx[3 * i + 1], rx[3 * i + 2]);
-        uint8_t f = receiver_flags(L, nullptr, fcyl, R3, T);
+        // receiver_flags, with the frame-uniform part from k_batch_grid and
+        // the inside test on the cylinders of the receiver's grid cells (all
+        // of them without a grid or with an invalid cylinder in the frame)
+        const BodyGrid* G = grids + lo;
+        uint8_t f = (uint8_t)G->fflags;
+        const bool bad_rx = !finite3(R3);
+        report_bad(bad_rx, kBadRx);
+        bool inside = false;
+        if (!bad_rx) {
+            if (G->ok && !(f & kFlagBadBody) && L.n_cyl <= 64) {
+                uint64_t m = grid_candidates(G, L.n_cyl, R3, R3);
+                while (m && !inside) {
+                    const int b = __builtin_ctzll(m);
+                    m &= m - 1ull;
+                    inside = inside_raw(L, nullptr, fcyl, b, R3);
+                }
+            } else {
+                for (int b = 0; b < L.n_cyl && !inside; ++b) inside = inside_raw(L, nullptr, fcyl, b, R3);
+            }
+        }
+        f |= (inside ? kFlagInside : 0) | (bad_rx ? kFlagInvalidRx : 0);
         for (int j = 0; j < L.n_f; ++j)
             if (!fcs[j].ok) f |= kFlagBadFreq;
         if (!(f & kFlagDead) && !seg_blocked_frame(T, R3, L, fcyl, -1, true, grids + lo, nodes, tris, stk, TILE))
@@ -1100,7 +1142,7 @@ hipError_t launch_batch(const BatchParams& B, int precision, int n_blocks, const
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         const int gb = (int)(B.n_frames < 4096 ? B.n_frames : 4096);
-        hipLaunchKernelGGL(k_batch_grid, dim3(gb), dim3(kGridN * kGridN), 0, s, B, cyl, w.bo, w.grids);
+        hipLaunchKernelGGL(k_batch_grid, dim3(gb), dim3(kGridN * kGridN), 0, s, B, cyl, w.bo, w.ro, w.grids);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         if (B.n_cyl > 0) {

@@ -239,7 +239,9 @@ constexpr int kGridN = 16;
 constexpr float kGridPad = 1e-3f;
 struct BodyGrid {
     float x0, y0, sx, sy;        // origin and cells per metre
-    int ok, pad[3];              // ok = 0: test every body
+    int ok;                      // ok = 0: test every body
+    int fflags;                  // batched frames: the frame's uniform receiver flags (k_batch_grid)
+    int pad[2];
     unsigned long long m[kGridN * kGridN];
 };
 
