@@ -264,10 +264,11 @@ utd_status utd_forward_state_release(utd_forward_state *state, void *stream);
  * Offsets are clamped to [0, n_cyl] / [0, n_rx] and to non-decreasing values
  * on the device, so malformed offsets give empty frames, never out-of-bounds
  * accesses.  One work queue over (frame, tile of receivers) feeds a
- * persistent kernel; the call replays a captured HIP graph (prep + persistent
- * kernel) as long as its arguments repeat (device data may change), and when
- * the stream is itself being captured it records the two launches into the
- * caller's graph instead (the workspace must then exist from an earlier call
+ * persistent kernel; the call replays a captured HIP graph (the constants,
+ * receiver order, body grids, source-side profiles, receiver flags and the
+ * persistent kernel: six launches) as long as its arguments repeat (device
+ * data may change), and when the stream is itself being captured it records
+ * the six launches into the caller's graph instead (the workspace must then exist from an earlier call
  * of at least this size).  A caller's graph points into that workspace: once
  * a call has been captured, a later call that needs a larger workspace
  * allocates a new one and keeps the old one alive until the process ends, so
