@@ -413,7 +413,7 @@ def batched_config(tile_rx, blocks_per_cu):
 
 def smooth_field_batched(scene, body_off, cylinders, rx_off, rx, source, freqs, precision=0, l_enc=0,
                          bodies_occlude=True, lit_branch=True, caustic_guard=1e-6, out=None, flags=None, stream=None):
-    """Fields of many frames in one launch.  body_off, rx_off: int64 GPU tensors
+    """Fields of many frames in one call.  body_off, rx_off: int64 GPU tensors
     [n_frames + 1]; cylinders [n_cyl, 5], rx [n_rx, 3]: float32 GPU tensors.
     Returns (E, flags): E is a flat complex tensor of 3 * n_f * n_rx elements,
     frame f's [n_f, 3, n_rx_f] block starting at 3 * n_f * rx_off[f]."""
