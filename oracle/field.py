@@ -24,13 +24,18 @@ For every receiver R and frequency f (k = 2 pi f / c, time factor e^{+jwt}):
   ``caustic_guard`` of the source axis (|rho_perp| small, the axial caustic
   where the ray field is singular) is dropped and the receiver flagged.
 
+With ``caustic_uniform`` the creeping paths of a sphere that meet on the
+source axis in pairs, both visible, are summed by the uniform formula of
+``oracle/caustic`` instead (finite on the axis); a path left without its
+partner is still dropped within ``caustic_guard`` of the axis.
+
 ``mode='soft'`` or ``'hard'`` replaces the dipole by a scalar point source
 u^i = e^{-jks}/s and keeps only that polarisation; the exact-series checks of
 the oracle use it.
 """
 import numpy as np
 
-from . import fock, geometry, occlusion, walls
+from . import caustic, fock, geometry, occlusion, walls
 
 C0 = 299792458.0
 
@@ -40,7 +45,8 @@ FLAG_LOS = 4
 
 
 def _opts(opts):
-    o = dict(l_enc=0, bodies_occlude=True, lit_branch=True, caustic_guard=1e-6, walls=None)
+    o = dict(l_enc=0, bodies_occlude=True, lit_branch=True, caustic_guard=1e-6, walls=None,
+             caustic_uniform=False)
     if opts:
         o.update(opts)
     return o
@@ -95,6 +101,8 @@ def _classify(scene, T, R, opts, visibility=True):
         los = np.zeros(n, dtype=bool)
     flags |= np.where(los, FLAG_LOS, 0).astype(np.uint8)
     paths = []
+    pairs = []
+    uniform = bool(o["caustic_uniform"])
     bodies = [("s", i, b) for i, b in enumerate(sc["spheres"])] + [("c", i, b) for i, b in enumerate(sc["cylinders"])]
     for kind, i, b in bodies:
         if kind == "s":
@@ -111,10 +119,11 @@ def _classify(scene, T, R, opts, visibility=True):
                 recs.append((("r",), geometry.cylinder_reflection(T, b, R, plan)))
         for key, rec in recs:
             valid = rec["valid"] & ~inside
-            if rec["kind"] == "creep":
+            if rec["kind"] == "creep" and not (uniform and kind == "s"):
                 caus = valid & (np.abs(rec["rho_perp"]) < o["caustic_guard"])
                 flags |= np.where(caus, FLAG_CAUSTIC, 0).astype(np.uint8)
                 valid &= ~caus
+            if rec["kind"] == "creep":
                 segs = [(Tb, rec["Q1"]), (rec["Q2"], R)]
             else:
                 segs = [(Tb, rec["Q"]), (rec["Q"], R)]
@@ -126,6 +135,14 @@ def _classify(scene, T, R, opts, visibility=True):
                     valid[idx[blk]] = False
             rec["valid"] = valid
             paths.append(((kind, i) + key, rec))
+        if uniform and kind == "s":
+            pairs += _pair_up(T, b[:3], b[3], R, dict(recs), o)
+            for key, rec in recs:
+                if rec["kind"] != "creep":
+                    continue
+                caus = rec["valid"] & ~rec["paired"] & (np.abs(rec["rho_perp"]) < o["caustic_guard"])
+                flags |= np.where(caus, FLAG_CAUSTIC, 0).astype(np.uint8)
+                rec["valid"] = rec["valid"] & ~caus
     wall_paths = []
     if o["walls"] is not None:
         # one specular bounce on the scene's planes, alone and feeding the bodies
@@ -133,7 +150,27 @@ def _classify(scene, T, R, opts, visibility=True):
         for key, rec in wall_paths:
             if "caustic" in rec:
                 flags |= np.where(rec["caustic"], FLAG_CAUSTIC, 0).astype(np.uint8)
-    return dict(los=los, inside=inside, flags=flags, paths=paths, walls=wall_paths, n=n)
+    return dict(los=los, inside=inside, flags=flags, paths=paths, walls=wall_paths, n=n, pairs=pairs)
+
+
+def _pair_up(T, C, a, R, recs, o):
+    """The caustic pairs of one sphere whose paths are both visible; their
+    paths are marked ``paired`` (left out of the per-ray sum)."""
+    for key, rec in recs.items():
+        if rec["kind"] == "creep":
+            rec["paired"] = np.zeros(R.shape[0], dtype=bool)
+    rear = caustic.rear_mask(T, C, R)
+    out = []
+    for side_rear in (True, False):
+        for kn, kf in caustic.pair_keys(o["l_enc"], side_rear):
+            near, far = recs[("c",) + kn], recs[("c",) + kf]
+            sel = near["valid"] & far["valid"] & (rear == side_rear)
+            idx = np.nonzero(sel)[0]
+            if idx.size:
+                near["paired"][idx] = True
+                far["paired"][idx] = True
+                out.append((C, a, near, far, idx, side_rear))
+    return out
 
 
 def n_rx_frozen(frozen):
@@ -167,6 +204,8 @@ def field(scene, tx, rx, freqs, opts=None, mode="em", frozen=None, return_info=F
     R = np.asarray(rx, dtype=float).reshape(-1, 3)
     freqs = np.atleast_1d(np.asarray(freqs, dtype=float))
     info = classify(sc, T, R, o, visibility=frozen is None)
+    if frozen is not None and o["caustic_uniform"]:
+        raise ValueError("caustic_uniform takes its pairs from the visibility decisions: no frozen classification")
     if frozen is not None:
         info["los"] = frozen["los"]
         info["inside"] = frozen["inside"]
@@ -196,7 +235,8 @@ def field(scene, tx, rx, freqs, opts=None, mode="em", frozen=None, return_info=F
                     acc[:, idx] += (pp * (np.exp(-1j * k * s) / s)[:, None]).T
                     absum[fi, idx] += np.linalg.norm(pp, axis=1) / s
         for key, rec in info["paths"]:
-            idx = np.nonzero(rec["valid"])[0]
+            use = rec["valid"] & ~rec["paired"] if "paired" in rec else rec["valid"]
+            idx = np.nonzero(use)[0]
             if not idx.size:
                 continue
             part = np.zeros_like(acc) if return_abs else acc
@@ -204,6 +244,12 @@ def field(scene, tx, rx, freqs, opts=None, mode="em", frozen=None, return_info=F
                 _add_creeping(part, rec, idx, T, dip, amp, k, mode)
             else:
                 _add_reflection(part, rec, idx, T, dip, amp, k, mode)
+            if return_abs:
+                acc += part
+                absum[fi] += np.abs(part) if scalar else np.linalg.norm(part, axis=0)
+        for C, a, near, far, idx, rear in info["pairs"]:
+            part = np.zeros_like(acc) if return_abs else acc
+            caustic.add_pair(part, T, C, a, R, near, far, idx, rear, dip, amp, k, mode)
             if return_abs:
                 acc += part
                 absum[fi] += np.abs(part) if scalar else np.linalg.norm(part, axis=0)

@@ -51,8 +51,12 @@ def sphere_frame(T, C, a, R):
     along = v @ eT
     w = v - along[:, None] * eT[None, :]
     wn = _norm(w)
-    eperp = np.where((wn > 1e-300)[:, None], w / np.maximum(wn, 1e-300)[:, None],
-                     _any_perp(np.broadcast_to(eT, v.shape)))
+    # on the axis (the plane of T, C and R undefined; w is rounding noise
+    # below a relative 1e-12) any perpendicular serves
+    on_axis = wn <= 1e-12 * dR
+    eperp = np.where(on_axis[:, None], _any_perp(np.broadcast_to(eT, v.shape)),
+                     w / np.where(on_axis, 1.0, wn)[:, None])
+    wn = np.where(on_axis, 0.0, wn)
     thR = np.arctan2(wn, along)
     return dT, eT, dR, eperp, thR
 
