@@ -37,9 +37,11 @@ finite limit,
     G = T_p |S| sqrt(x/(2 pi)) e^{j pi/4} e^{j pi n_s/2} e^{-j k s_bar} / s^i,
     |S| sqrt(x) = sqrt(a sin(gamma_T) k a eps / (s^d d_R sin eps)),
 
-with T_p the ray's Fock transfer function of Eq. (4) and n_s = floor(theta2/pi)
-its surface caustics (the far ray's crossing of the axis is what the
-Bessel functions supply).  For large x, J_n's leading asymptotic form turns
+with T_p the ray's Fock transfer function of Eq. (4) and n_s the near
+ray's caustic count, floor(theta2_near/pi).  The far ray has exactly one
+caustic more (where it crosses the axis: in space, or on the surface at a
+pole when its Q2 lies beyond one), and that quarter turn is what the Bessel
+functions supply.  For large x, J_n's leading asymptotic form turns
 the result back into the two ray fields of Eq. (4) exactly; on the axis it
 is finite and independent of the direction from which the axis is reached.
 
@@ -100,7 +102,8 @@ def add_pair(acc, T, C, a, R, near, far, idx, rear, dip, amp, k, mode):
     s_bar = 0.5 * (s_n + s_f)
     base = s_x / np.sqrt(2 * np.pi) * np.exp(0.25j * np.pi) * np.exp(-1j * k * s_bar) / sI
     th2 = [gT + rec["phi"][idx] for rec in (near, far)]
-    surf = [np.exp(0.5j * np.pi * np.floor(t2 / np.pi)) for t2 in th2]
+    sn = np.exp(0.5j * np.pi * np.floor(th2[0] / np.pi))
+    surf = [sn, sn]
     J = [jv(n, x) for n in range(4)]
     A0 = 2 * np.pi * J[0]
     A1 = 2j * np.pi * J[1]

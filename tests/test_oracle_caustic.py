@@ -4,7 +4,7 @@ two-ray limit far from it, reciprocity on the axis and continuity onto it."""
 import numpy as np
 import pytest
 
-from oracle import field, mie
+from oracle import caustic, field, mie
 
 C0 = 299792458.0
 A, B = 0.5, 3.0
@@ -54,24 +54,37 @@ def test_em_uniform_field_vs_mie_radial_dipole_on_the_rear_axis():
     np.testing.assert_allclose([worst[0] / worst[1], worst[1] / worst[2]], [3 ** (2 / 3), 2 ** (2 / 3)], rtol=0.4)
 
 
-@pytest.mark.parametrize("l_enc", [0, 1])
+@pytest.mark.parametrize("l_enc", [0, 1, 2])
 def test_uniform_field_tends_to_the_two_rays(l_enc):
-    """Away from the axis the uniform field is the sum of its two rays up to
-    the O(1/x) of the Bessel functions' asymptotic forms (x = k a eps): a
-    swapped Bessel combination, a lost phase or a wrong amplitude would leave
-    an O(1) difference.  A tilted dipole exercises every polarisation term;
-    receivers off the source plane."""
-    a = A
-    th = np.radians(np.linspace(150, 172, 12))
+    """Away from the axis each pair's uniform field is the sum of its two
+    rays up to the O(1/x) of the Bessel functions' asymptotic forms
+    (x = k a eps), measured against the pair's own ray magnitudes: a swapped
+    Bessel combination, a lost phase or quarter turn or a wrong amplitude
+    would leave an O(1) difference.  Rear pairs on both sides of
+    theta_R + gamma_R = pi (the far ray's extra caustic on the surface or in
+    space), front pairs from l_enc 1; a tilted dipole exercises every
+    polarisation term; receivers off the source plane."""
+    th = np.radians(np.concatenate([np.linspace(92, 172, 24), np.linspace(8, 88, 12)]))
     rx = np.stack([2.5 * np.cos(th), 2.5 * np.sin(th) * 0.6, 2.5 * np.sin(th) * 0.8], 1)
-    sc, tx = dict(spheres=[[0, 0, 0, a]]), dict(pos=[B, 0, 0], dipole=[0.3, 0.5, 0.8])
+    T, dip = np.array([B, 0, 0]), np.array([0.3, 0.5, 0.8])
+    sc = dict(spheres=[[0, 0, 0, A]])
+    info = field.classify(sc, T, rx, dict(OPT, l_enc=l_enc))
+    assert sum(len(p[4]) for p in info["pairs"]) >= (4, 40, 76)[l_enc]
     for f in (5e9, 10e9, 20e9):
         k = 2 * np.pi * f / C0
-        Eu = field.field(sc, tx, rx, [f], opts=dict(OPT, l_enc=l_enc))[0]
-        Er, absum = field.field(sc, tx, rx, [f], opts=dict(l_enc=l_enc), return_abs=True)
-        x = k * a * (np.pi - th)
-        rel = np.linalg.norm(Eu - Er, axis=1)[0] / absum[0]
-        assert np.max(rel * x) < 1.0, np.max(rel * x)
+        for C, a, near, far, idx, rear in info["pairs"]:
+            Eu = np.zeros((3, rx.shape[0]), complex)
+            caustic.add_pair(Eu, T, C, a, rx, near, far, idx, rear, dip, 1.0, k, "em")
+            En, Ef = np.zeros_like(Eu), np.zeros_like(Eu)
+            field._add_creeping(En, near, idx, T, dip, 1.0, k, "em")
+            field._add_creeping(Ef, far, idx, T, dip, 1.0, k, "em")
+            x = k * a * np.where(rear, np.pi - th[idx], th[idx])
+            rel = np.linalg.norm(Eu - En - Ef, axis=0)[idx] / (np.linalg.norm(En, axis=0) + np.linalg.norm(Ef, axis=0))[idx]
+            assert np.max(rel * x) < 3.0, (f, rear, np.max(rel * x))
+
+
+def info_pairs(sc, tx, rx, l_enc):
+    return field.classify(sc, tx["pos"], rx, dict(OPT, l_enc=l_enc))["pairs"]
 
 
 def test_uniform_field_on_the_axis():
