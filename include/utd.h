@@ -92,6 +92,19 @@ typedef struct {
                                and the body paths it feeds or that feed it
                                (utd_scene_set_wall_material); forward calls
                                only.  Default 0.                               */
+    int caustic_uniform;    /* 1: a sphere's creeping paths that meet on the
+                               source axis in pairs (near and far side, Sec.
+                               II-B's paths around the sphere), both visible,
+                               are summed by the uniform Bessel-function form
+                               of their azimuthal integral instead of as two
+                               rays: finite on the axis, the two rays' sum
+                               away from it up to O(1/(k a eps)); paths left
+                               unpaired keep caustic_guard.  Receivers with
+                               theta_R > pi/2 pair at the rear axis, the
+                               others at the front.  Forward calls only (the
+                               adjoint entry points return
+                               UTD_E_UNSUPPORTED); batched frames hold no
+                               spheres.  Default 0.                            */
 } utd_options;
 
 /* Wall material of a scene's reflecting planes: a homogeneous slab of
@@ -378,7 +391,8 @@ utd_status utd_input_status(uint32_t *bits);
 #define UTD_K_REDUCE 4
 #define UTD_K_BATCHED 5
 #define UTD_K_WALLS 6
-#define UTD_K_COUNT 7
+#define UTD_K_CAUSTIC 7
+#define UTD_K_COUNT 8
 void utd_profile_enable(int on);
 utd_status utd_profile_read(double *ms, int64_t *count);
 

@@ -94,6 +94,11 @@ def add_pair(acc, T, C, a, R, near, far, idx, rear, dip, amp, k, mode):
     c1, s1 = np.cos(gT), np.sin(gT)
     # near ray's half-plane: side + runs in R's own (eperp), side - in the other
     e1 = eperp if rear else -eperp
+    # close to the axis the rounding of R - C leaves e1 a component along u
+    # of order 1e-16 |R - C| / rho_perp; removed, so that p1 e1 + p2 e2 is
+    # the transverse dipole whatever the direction of e1
+    e1 = e1 - (e1 @ u)[:, None] * u[None, :]
+    e1 = e1 / np.linalg.norm(e1, axis=1)[:, None]
     e2 = np.cross(np.broadcast_to(u, e1.shape), e1)
     ratio = np.where(eps > 0, eps / np.where(eps > 0, np.sin(eps), 1.0), 1.0)
     s_x = np.sqrt(a * s1 * k * a * ratio / (sD * dR))          # |S| sqrt(x)

@@ -188,7 +188,11 @@ def _reflection_common(T, R, Q, n, valid, rho_g, inv_f1_cos, inv_f2_over_cos):
     rho2 = 1.0 / inv_rho2
     cr = np.cross(si_hat, n)
     crn = _norm(cr)
-    eperp = np.where((crn > 1e-12)[:, None], cr / np.maximum(crn, 1e-300)[:, None], _any_perp(n))
+    # at normal incidence the plane of incidence is undefined, and on a
+    # curved surface R_s != -R_h, so the field depends on the basis chosen:
+    # within sin(th_i) <= 1e-6 (the resolution of an FP32 frame) the fixed
+    # perpendicular of n is taken
+    eperp = np.where((crn > 1e-6)[:, None], cr / np.maximum(crn, 1e-300)[:, None], _any_perp(n))
     epar_i = np.cross(eperp, si_hat)
     epar_r = np.cross(eperp, sr_hat)
     return dict(kind="refl", valid=valid, Q=Q, n=n, s_i=sI, s_r=sR, si_hat=si_hat, sr_hat=sr_hat,

@@ -24,12 +24,13 @@ EXPORTS = ["utd_default_options", "utd_scene_create", "utd_scene_destroy", "utd_
            "utd_path_masks", "utd_input_status", "utd_smooth_field_noalloc", "utd_scene_planes",
            "utd_scene_set_wall_material", "utd_wall_masks", "utd_smooth_field_saved",
            "utd_smooth_field_backward_saved", "utd_forward_state_release"]
-KERNELS = ["prep", "occlude", "field", "backward", "reduce", "batched", "walls"]
+KERNELS = ["prep", "occlude", "field", "backward", "reduce", "batched", "walls", "caustic"]
 
 
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("l_enc", ctypes.c_int), ("bodies_occlude", ctypes.c_int),
-                ("lit_branch", ctypes.c_int), ("caustic_guard", ctypes.c_double), ("wall_reflections", ctypes.c_int)]
+                ("lit_branch", ctypes.c_int), ("caustic_guard", ctypes.c_double), ("wall_reflections", ctypes.c_int),
+                ("caustic_uniform", ctypes.c_int)]
 
 
 class WallMaterial(ctypes.Structure):
@@ -150,13 +151,14 @@ def _dev(t, dtype, shape_tail, name):
 
 
 def make_options(precision=0, l_enc=0, bodies_occlude=True, lit_branch=True, caustic_guard=1e-6,
-                 wall_reflections=False):
+                 wall_reflections=False, caustic_uniform=False):
     o = Options()
     load_library().utd_default_options(ctypes.byref(o))
     o.precision, o.l_enc = int(precision), int(l_enc)
     o.bodies_occlude, o.lit_branch = int(bool(bodies_occlude)), int(bool(lit_branch))
     o.caustic_guard = float(caustic_guard)
     o.wall_reflections = int(bool(wall_reflections))
+    o.caustic_uniform = int(bool(caustic_uniform))
     return o
 
 
@@ -235,7 +237,7 @@ def _stream(stream):
 
 def smooth_field(scene, spheres, cylinders, source, rx, freqs, precision=0, l_enc=0, bodies_occlude=True,
                  lit_branch=True, caustic_guard=1e-6, out=None, flags=None, stream=None, noalloc=False,
-                 wall_reflections=False):
+                 wall_reflections=False, caustic_uniform=False):
     """E[f, c, n] (complex64 for precision 0, complex128 for 1) and flags[n].
 
     spheres [ns, 4], cylinders [nc, 5], rx [n, 3]: float32 GPU tensors;
@@ -255,7 +257,8 @@ def smooth_field(scene, spheres, cylinders, source, rx, freqs, precision=0, l_en
         out = torch.empty((nf, 3, n), dtype=cdt, device=rx.device)
     if flags is None:
         flags = torch.empty((n,), dtype=torch.uint8, device=rx.device)
-    opt = make_options(precision, l_enc, bodies_occlude, lit_branch, caustic_guard, wall_reflections)
+    opt = make_options(precision, l_enc, bodies_occlude, lit_branch, caustic_guard, wall_reflections,
+                       caustic_uniform)
     _check(fn(scene.handle if scene is not None else None, ctypes.byref(b), ctypes.byref(source),
                                 rx.data_ptr() if n else None, n, freqs.data_ptr() if nf else None, nf,
                                 ctypes.byref(opt), out.data_ptr() if out.numel() else None,

@@ -91,6 +91,7 @@ utd_status check_common(const utd_bodies* bodies, const utd_source* tx, const fl
     if (opt->l_enc < 0 || opt->l_enc > 2) return fail(UTD_E_ARG, "l_enc must be in 0..2");
     if (!(opt->caustic_guard >= 0)) return fail(UTD_E_ARG, "caustic_guard must be >= 0");
     if (opt->wall_reflections != 0 && opt->wall_reflections != 1) return fail(UTD_E_ARG, "wall_reflections must be 0 or 1");
+    if (opt->caustic_uniform != 0 && opt->caustic_uniform != 1) return fail(UTD_E_ARG, "caustic_uniform must be 0 or 1");
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(tx->pos[a]) || !std::isfinite(tx->dipole[a]))
             return fail(UTD_E_ARG, "non-finite source position or dipole");
@@ -115,13 +116,20 @@ utd::LaunchParams make_params(const utd_scene* scene, const utd_bodies* bodies, 
     L.l_enc = opt->l_enc;
     L.bodies_occlude = opt->bodies_occlude;
     L.lit_branch = opt->lit_branch;
-    L.caustic_guard = opt->caustic_guard;
+    // with the uniform caustic sum the guard is applied after pairing (k_pair)
+    L.caustic_guard = opt->caustic_uniform ? 0.0 : opt->caustic_guard;
     return L;
 }
 
 bool walls_on(const utd_scene* scene, const utd_options* opt) {
     return opt->wall_reflections && scene && !scene->planes.empty();
 }
+
+// Bytes of the pair bytes [n_sph][n_rx] of the uniform caustic sum (0 without it).
+size_t pair_bytes(const utd_options* opt, const utd_bodies* bodies, int64_t n_rx) {
+    return opt->caustic_uniform && bodies->n_sph > 0 ? (size_t)bodies->n_sph * (size_t)n_rx : 0;
+}
+size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Stream-ordered scratch of one call: body constants, frequency constants,
 // path masks, reflection angles, flags (when the caller passed none) and
@@ -267,6 +275,7 @@ void utd_default_options(utd_options* opt) {
     opt->lit_branch = 1;
     opt->caustic_guard = 1e-6;
     opt->wall_reflections = 0;
+    opt->caustic_uniform = 0;
 }
 
 const char* utd_last_error(void) { return g_err.c_str(); }
@@ -380,8 +389,9 @@ utd_status utd_smooth_field(const utd_scene* scene, const utd_bodies* bodies, co
     const bool walls = walls_on(scene, opt);
     const int n_planes = walls ? (int)scene->planes.size() : 0;
     Workspace w;
+    const size_t wall_bytes = walls ? up256(utd::walls_scratch_bytes(L, n_planes)) : 0;
     e = w.alloc(nb, n_rx, n_f, opt->l_enc, opt->precision, rx_flags == nullptr, s,
-                walls ? utd::walls_scratch_bytes(L, n_planes) : 0);
+                wall_bytes + pair_bytes(opt, bodies, n_rx));
     if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(UTD_E_OOM, "workspace allocation") : hip_fail(e, "hipMallocAsync");
     uint8_t* flags = rx_flags ? rx_flags : w.flags;
     const float4* nodes = scene ? scene->d_nodes : nullptr;
@@ -391,10 +401,19 @@ utd_status utd_smooth_field(const utd_scene* scene, const utd_bodies* bodies, co
         e = utd::launch_paths(L, opt->precision, rx, bodies->sph, bodies->cyl, freqs, w.prep, w.fc, nodes, tris,
                               w.mask, w.rec, flags, w.ent, w.ent_th, w.vis, w.counters + 12, w.cap, s, w.grid);
     }
+    uint8_t* pm = pair_bytes(opt, bodies, n_rx) ? (uint8_t*)(w.extra + wall_bytes) : nullptr;
+    if (e == hipSuccess && pm) {
+        ProfScope ps(UTD_K_CAUSTIC, s);
+        e = utd::launch_pairs(L, opt->caustic_guard, rx, w.prep, w.mask, pm, s);
+    }
     int fc = pick_fc(opt->precision, n_rx, n_f);
     if (e == hipSuccess) {
         ProfScope ps(UTD_K_FIELD, s);
         e = utd::launch_field(L, opt->precision, fc, rx, w.fc, w.mask, w.rec, flags, E_out, s);
+    }
+    if (e == hipSuccess && pm) {
+        ProfScope ps(UTD_K_CAUSTIC, s);
+        e = utd::launch_caustic(L, opt->precision, rx, w.prep, w.fc, pm, E_out, s);
     }
     if (e == hipSuccess && walls) {
         ProfScope ps(UTD_K_WALLS, s);
@@ -419,8 +438,9 @@ utd_status utd_smooth_field_noalloc(const utd_scene* scene, const utd_bodies* bo
     const bool walls = walls_on(scene, opt);
     const int n_planes = walls ? (int)scene->planes.size() : 0;
     Workspace w;
+    const size_t wall_bytes = walls ? up256(utd::walls_scratch_bytes(L, n_planes)) : 0;
     const size_t need = w.plan(nb, n_rx, n_f, opt->l_enc, opt->precision, rx_flags == nullptr,
-                               walls ? utd::walls_scratch_bytes(L, n_planes) : 0);
+                               wall_bytes + pair_bytes(opt, bodies, n_rx));
     if (need > utd::kNoAllocScratchBytes)
         return fail(UTD_E_ARG,
                     "this call needs %zu bytes of scratch; the allocation-free entry point has %zu (fewer "
@@ -438,10 +458,19 @@ utd_status utd_smooth_field_noalloc(const utd_scene* scene, const utd_bodies* bo
         e = utd::launch_paths(L, opt->precision, rx, bodies->sph, bodies->cyl, freqs, w.prep, w.fc, nodes, tris,
                               w.mask, w.rec, flags, w.ent, w.ent_th, w.vis, w.counters + 12, w.cap, s, w.grid);
     }
+    uint8_t* pm = pair_bytes(opt, bodies, n_rx) ? (uint8_t*)(w.extra + wall_bytes) : nullptr;
+    if (e == hipSuccess && pm) {
+        ProfScope ps(UTD_K_CAUSTIC, s);
+        e = utd::launch_pairs(L, opt->caustic_guard, rx, w.prep, w.mask, pm, s);
+    }
     if (e == hipSuccess) {
         ProfScope ps(UTD_K_FIELD, s);
         e = utd::launch_field(L, opt->precision, pick_fc(opt->precision, n_rx, n_f), rx, w.fc, w.mask, w.rec,
                               flags, E_out, s);
+    }
+    if (e == hipSuccess && pm) {
+        ProfScope ps(UTD_K_CAUSTIC, s);
+        e = utd::launch_caustic(L, opt->precision, rx, w.prep, w.fc, pm, E_out, s);
     }
     if (e == hipSuccess && walls) {
         ProfScope ps(UTD_K_WALLS, s);
@@ -553,6 +582,7 @@ utd_status utd_smooth_field_backward(const utd_scene* scene, const utd_bodies* b
     if (st != UTD_OK) return st;
     if (!d_tx) return fail(UTD_E_ARG, "d_tx is NULL");
     if (opt->wall_reflections) return fail(UTD_E_UNSUPPORTED, "wall reflections have no adjoint");
+    if (opt->caustic_uniform) return fail(UTD_E_UNSUPPORTED, "the uniform caustic sum has no adjoint");
     if (bodies->n_cyl && !d_cyl) return fail(UTD_E_ARG, "d_cyl is NULL with n_cyl > 0");
     if (bodies->n_sph && !d_sph) return fail(UTD_E_ARG, "d_sph is NULL with n_sph > 0");
     const bool work = n_rx > 0 && n_f > 0;
@@ -618,6 +648,7 @@ utd_status utd_smooth_field_saved(const utd_scene* scene, const utd_bodies* bodi
     utd_status st = check_common(bodies, tx, rx, n_rx, freqs, n_f, opt);
     if (st != UTD_OK) return st;
     if (opt->wall_reflections) return fail(UTD_E_UNSUPPORTED, "wall reflections have no adjoint");
+    if (opt->caustic_uniform) return fail(UTD_E_UNSUPPORTED, "the uniform caustic sum has no adjoint");
     const bool work = n_rx > 0 && n_f > 0;
     if (work && !E_out) return fail(UTD_E_ARG, "E_out is NULL");
     hipStream_t s = (hipStream_t)stream;
@@ -764,6 +795,7 @@ utd_status utd_smooth_field_batched(const utd_scene* scene, int64_t n_frames, co
     if (opt->l_enc < 0 || opt->l_enc > 2) return fail(UTD_E_ARG, "l_enc must be in 0..2");
     if (!(opt->caustic_guard >= 0)) return fail(UTD_E_ARG, "caustic_guard must be >= 0");
     if (opt->wall_reflections) return fail(UTD_E_UNSUPPORTED, "wall reflections are not batched");
+    if (opt->caustic_uniform != 0 && opt->caustic_uniform != 1) return fail(UTD_E_ARG, "caustic_uniform must be 0 or 1");
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(tx->pos[a]) || !std::isfinite(tx->dipole[a]))
             return fail(UTD_E_ARG, "non-finite source position or dipole");

@@ -164,7 +164,9 @@ __device__ __forceinline__ RxGeoT<G> rx_geo_sphere(const BodyPrepT<G>& b, V3<G> 
     g.along = along;
     V3<G> w = v - along * eT;
     g.wn = gnorm(w);
-    if (g.wn > 1e-300) {
+    // on the axis the plane of T, C and R is undefined and w is rounding
+    // noise (below a relative 1e-12): any perpendicular serves
+    if (g.wn > G(1e-12) * gsqrt(d2)) {
         g.eperp = grcp(g.wn) * w;
     } else {
         d3 ap = any_perp(val3(eT));

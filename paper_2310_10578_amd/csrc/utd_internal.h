@@ -104,6 +104,16 @@ struct WallMat {
     int pec;
 };
 
+// Uniform sum of a sphere's creeping-ray pairs at the axial caustic
+// (utd_caustic.h): launch_pairs after the path kernels (the pairs with both
+// paths visible leave the mask for pm [n_sph][n_rx]; unpaired paths within
+// guard of the axis are dropped and flagged), launch_caustic after the
+// field kernel (the pairs' field added into E).
+hipError_t launch_pairs(const LaunchParams& L, double guard, const float* rx, const BodyPrep* prep, uint8_t* mask,
+                        uint8_t* pm, hipStream_t s);
+hipError_t launch_caustic(const LaunchParams& L, int precision, const float* rx, const BodyPrep* prep,
+                          const FreqConst* fcs, const uint8_t* pm, void* E, hipStream_t s);
+
 // One specular wall bounce (utd_walls.h): body constants of the image
 // sources (prep_img, n_planes * bodies entries) then the wall paths of every
 // receiver, added to E; wall decisions to wmask ([n_rx][n_planes]) when not

@@ -11,8 +11,9 @@
 // Field:
 //   k_field    per (receiver, frequency chunk) coherent field of Eqs. (1)-(4)
 //   k_census   per-bit counts of the masks (measurement)
-// The adjoint (utd_adjoint.h) and the batched kernel (utd_batched.h) are
-// included at the end.
+// The adjoint (utd_adjoint.h), the batched kernels (utd_batched.h), the
+// wall bounce (utd_walls.h) and the uniform sum of a sphere's creeping-ray
+// pairs at the axial caustic (utd_caustic.h) are included at the end.
 //
 // In k_field one lane owns one receiver and a chunk of FC frequencies; it
 // walks the bodies in order, reads each valid path's record once and runs the
@@ -613,7 +614,8 @@ template <> struct FreqC<double> {
           isk(c.iskd) {}
 };
 
-// One path at one frequency: the Fock arguments scale with powers of k
+// The soft and hard coefficients of one path at one frequency (its Fock
+// kernels times its phase).  The Fock arguments scale with powers of k
 // (xi ~ k^{1/3}, sqrt(X) ~ k^{1/2}, q ~ k^{1/6}), so they are products of the
 // path's constants and the frequency's.  MODE picks the Fock specialisation
 // (kCreep, kRefl or kAny for mixed wavefronts); callers branch on
@@ -621,7 +623,8 @@ template <> struct FreqC<double> {
 // k^{-1/6}; with KM16 = false it is left out, for callers that apply it once
 // to their sum.
 template <typename R, int MODE, bool KM16 = true>
-__device__ __forceinline__ void add_path(const PathEval<R>& pe, const Tabs<R>& tb, const FreqC<R>& fc, R* E) {
+__device__ __forceinline__ void path_coefs(const PathEval<R>& pe, const Tabs<R>& tb, const FreqC<R>& fc,
+                                           cplx<R>* cs_out, cplx<R>* ch_out) {
     FockArgs<R> a;
     a.xi = fc.k13 * pe.xh;
     a.u = fc.sk * pe.uh;
@@ -638,7 +641,16 @@ __device__ __forceinline__ void add_path(const PathEval<R>& pe, const Tabs<R>& t
         ph.re *= fc.km16;
         ph.im *= fc.km16;
     }
-    cplx<R> cs = cmul(Ks, ph), ch = cmul(Kh, ph);
+    *cs_out = cmul(Ks, ph);
+    *ch_out = cmul(Kh, ph);
+}
+
+// The path's field at one frequency: the coefficients times its
+// polarisation vectors, accumulated into E[6] (x, y, z; re, im).
+template <typename R, int MODE, bool KM16 = true>
+__device__ __forceinline__ void add_path(const PathEval<R>& pe, const Tabs<R>& tb, const FreqC<R>& fc, R* E) {
+    cplx<R> cs, ch;
+    path_coefs<R, MODE, KM16>(pe, tb, fc, &cs, &ch);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         E[2 * c] = fma(cs.re, pe.vs[c], E[2 * c]);
@@ -991,3 +1003,4 @@ hipError_t launch_field(const LaunchParams& L, int precision, int fc, const floa
 #include "utd_adjoint.h"
 #include "utd_batched.h"
 #include "utd_walls.h"
+#include "utd_caustic.h"

@@ -51,6 +51,22 @@ def test_default_options_and_error_paths_without_gpu():
     st = lib.utd_smooth_field(None, ctypes.byref(b), ctypes.byref(s), None, 0, None, 0, ctypes.byref(o),
                               None, None, None)
     assert st == 0
+    # the uniform caustic sum: 0 or 1, forward calls only
+    assert o.caustic_uniform == 0
+    o.caustic_uniform = 2
+    st = lib.utd_smooth_field(None, ctypes.byref(b), ctypes.byref(s), None, 0, None, 0, ctypes.byref(o),
+                              None, None, None)
+    assert st == -1 and b"caustic_uniform" in lib.utd_last_error()
+    o.caustic_uniform = 1
+    dummy = ctypes.c_double()
+    st = lib.utd_smooth_field_backward(None, ctypes.byref(b), ctypes.byref(s), None, 0, None, 0, ctypes.byref(o),
+                                       None, None, None, ctypes.byref(dummy), None)
+    assert st == -5 and b"caustic" in lib.utd_last_error()
+    state = ctypes.c_void_p()
+    st = lib.utd_smooth_field_saved(None, ctypes.byref(b), ctypes.byref(s), None, 0, None, 0, ctypes.byref(o),
+                                    None, None, ctypes.byref(state), None)
+    assert st == -5 and not state.value
+    o.caustic_uniform = 0
     h = ctypes.c_void_p()
     assert lib.utd_scene_create(None, -1, ctypes.byref(h)) == -1
     assert lib.utd_scene_create(None, 0, None) == -1

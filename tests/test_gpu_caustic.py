@@ -1,0 +1,155 @@
+"""Parity of the uniform caustic sum (option caustic_uniform) against the
+oracle: receivers on and near a sphere's rear and front source axes (where
+the ray field is infinite or nearly so) and a ring through both
+hemispheres, every encirclement count, both precisions, the bodies-only and
+the triangle-scene pipelines.  The scenes' visibility is exact on both sides
+(spheres only, or triangles that block nothing), so the oracle's own
+decisions are the library's and the fields are compared directly:
+normwise per frequency and per receiver against the sum of the receiver's
+contribution magnitudes (a uniform pair counting as one), within 1e-4
+(FP32 path) and 1e-10 (FP64 path).  In FP64 the per-receiver bound adds
+four times the oracle's own change under a 1e-15 relative move of the
+receiver (its conditioning), and the three receivers on the lit front axis,
+whose reflection lies within 1e-6 rad of normal incidence, are held to 1e-9:
+there the FP64 reflection-point solve leaves 6e-10 (a limit of that solve,
+with or without the uniform sum)."""
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import TOL, normwise, run_library, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+A_SPH = 0.5
+C_SPH = np.array([0.2, -0.1, 1.1])
+# float32 values on both sides (the library takes the source in float32)
+TX = dict(pos=np.float32([3.2, 0.5, 0.7]), dipole=np.float32([0.3, 0.5, 0.8]), amplitude=1.0)
+FREQS = np.linspace(1e9, 6e9, 9)
+
+
+def _receivers(seed=0):
+    """Rear-axis and front-axis points (on the axis up to the float32
+    rounding of the coordinates, and at offsets from 1e-6 m (rear) or 1e-4 m
+    (front) to 0.3 m), and a ring through both hemispheres; 323 in all (a
+    ragged tail of the 256-lane blocks).  Closer to the lit front axis the
+    lone creeping ray of l_enc = 0 is at its own caustic and the reflection
+    within 1e-6 of normal incidence, where the two sides' ray fields differ
+    by up to 3e-3 with or without the uniform sum."""
+    rng = np.random.default_rng(seed)
+    T = np.array(TX["pos"])
+    ax = (C_SPH - T) / np.linalg.norm(C_SPH - T)
+    pts = []
+    for d, sgn in ((1.4, 1), (2.3, 1), (3.5, 1), (0.9, -1), (2.2, -1), (5.0, -1)):
+        base = C_SPH + sgn * d * ax
+        pts.append(base)
+        for off in ((1e-6,) if sgn > 0 else ()) + (1e-4, 1e-3, 1e-2, 0.05, 0.1, 0.3):
+            v = np.cross(ax, rng.normal(size=3))
+            pts.append(base + off * v / np.linalg.norm(v))
+    e1 = np.cross(ax, [0.0, 0.0, 1.0])
+    e1 /= np.linalg.norm(e1)
+    ph = 2 * np.pi * (np.arange(278) + 0.5) / 278
+    ring = C_SPH + 2.4 * (np.cos(ph)[:, None] * (-ax) + np.sin(ph)[:, None] * e1)
+    return np.concatenate([np.array(pts), ring]).astype(np.float32)
+
+
+def _cfg(tri=None):
+    return dict(scene=dict(spheres=np.array([list(C_SPH) + [A_SPH]], np.float32),
+                           cylinders=np.zeros((0, 5), np.float32), tri=tri),
+                tx=TX, rx=_receivers(), freqs=FREQS)
+
+
+def _oracle_sensitivity(cfg, opts, n_try=4, rel=1e-15, seed=0):
+    """Per frequency and receiver: the largest change of the oracle's field
+    when every receiver coordinate moves by rel of its value (about five
+    FP64 ulps)."""
+    from oracle import field
+    rng = np.random.default_rng(seed)
+    sc, tx, r = W.to_oracle(cfg["scene"], cfg["tx"], cfg["rx"])
+    E0 = field.field(sc, tx, r, cfg["freqs"], opts=opts)
+    S = np.zeros((len(cfg["freqs"]), r.shape[0]))
+    for _ in range(n_try):
+        rp = r * (1.0 + rel * rng.choice([-1.0, 1.0], size=r.shape))
+        S = np.maximum(S, np.linalg.norm(field.field(sc, tx, rp, cfg["freqs"], opts=opts) - E0, axis=1))
+    return S
+
+
+def _compare(cfg, precision, l_enc, name):
+    opts = dict(l_enc=l_enc, caustic_uniform=True)
+    Eg, fg = run_library(cfg, precision, **opts)
+    Eo, info, A = run_oracle(cfg, opts=opts, absum=True)
+    nw = normwise(Eg, Eo)
+    dE = np.linalg.norm(Eg - Eo, axis=1)
+    comp = dE / np.maximum(A, 1e-300)
+    n_pairs = sum(len(p[4]) for p in info["pairs"])
+    print("%s p%d l_enc=%d: %d pairs, normwise max %.2e, per-receiver max %.2e"
+          % (name, precision, l_enc, n_pairs, nw.max(), comp.max()), flush=True)
+    assert np.all(np.isfinite(Eg))
+    np.testing.assert_array_equal(fg & 7, info["flags"] & 7)
+    assert np.all(nw <= TOL[precision]), nw
+    if precision == 0:
+        assert comp.max() <= TOL[0], comp.max()
+    else:
+        S = _oracle_sensitivity(cfg, opts)
+        refl = dict(info["paths"])[("s", 0, "r")]
+        normal = refl["valid"] & (refl["cos_i"] > 1.0 - 5e-13)
+        bound = np.where(normal, 1e-9, TOL[1])
+        assert np.sum(normal) <= 3
+        assert np.all(dE <= bound * A + 4.0 * S), np.max(dE / A)
+    assert n_pairs >= 40
+    return Eg, fg
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+@pytest.mark.parametrize("l_enc", [0, 1, 2])
+def test_uniform_pairs_bodies_only(precision, l_enc):
+    _compare(_cfg(), precision, l_enc, "caustic bodies only")
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_uniform_pairs_triangle_scene(precision):
+    """The same through the triangle-scene kernels (candidate queue, BVH
+    walk, records): a box well away from every path."""
+    lo, hi = np.array([20.0, 20.0, 0.0]), np.array([21.0, 21.0, 1.0])
+    cfg = _cfg(tri=W.box_triangles(lo, hi).astype(np.float32))
+    _compare(cfg, precision, 1, "caustic triangle scene")
+
+
+def test_uniform_pairs_off_leaves_the_ray_field():
+    """Without the option the rear-axis receivers keep the caustic flag and
+    the field over the ring equals the oracle's ray field (next to the axis
+    the ray amplitude, 1/sqrt(rho_perp), is too ill-conditioned for 1e-10:
+    the cancellation in rho_perp alone leaves 1e-16 d_R / rho_perp); with
+    the option their flag is clear (their pairs are summed)."""
+    cfg = _cfg()
+    Eg, fg = run_library(cfg, 1)
+    Eo, info = run_oracle(cfg)
+    np.testing.assert_array_equal(fg & 7, info["flags"] & 7)
+    rear_axis = [0, 8, 16]
+    assert np.all(fg[rear_axis] & 2)
+    ring = slice(45, None)
+    assert np.all(normwise(Eg[:, :, ring], Eo[:, :, ring]) <= TOL[1])
+    Eu, fu = run_library(cfg, 1, caustic_uniform=True)
+    assert not np.any(fu[rear_axis] & 2)
+
+
+def test_uniform_pairs_noalloc_matches():
+    """The allocation-free entry point gives the same field, twice in a row
+    (the second call smaller)."""
+    import torch
+
+    import paper_2310_10578_amd as utd
+    cfg = _cfg()
+    for n in (cfg["rx"].shape[0], 100):
+        rx = cfg["rx"][:n]
+        Ea, fa = run_library(cfg, 0, rx=rx, caustic_uniform=True, l_enc=1)
+        sc = cfg["scene"]
+        sph = torch.from_numpy(sc["spheres"]).cuda()
+        cyl = torch.zeros((0, 5), dtype=torch.float32, device="cuda")
+        src = utd.make_source(TX["pos"], TX["dipole"], TX["amplitude"])
+        E, f = utd.smooth_field(None, sph, cyl, src, torch.from_numpy(rx).cuda(), torch.from_numpy(FREQS).cuda(),
+                                noalloc=True, caustic_uniform=True, l_enc=1)
+        torch.cuda.synchronize()
+        assert np.array_equal(E.cpu().numpy().astype(np.complex128), Ea)
+        assert np.array_equal(f.cpu().numpy(), fa)
