@@ -61,6 +61,15 @@ FLOPS_RX_SCALE = 6
 # its algorithmic count is pairs x paths per pair x 120 plus the field of
 # the paths that exist and are visible.
 FLOPS_PATH_GEOM = 120
+# Uniform sum of a sphere's creeping-ray pair at the axial caustic, per
+# (pair, frequency): the two rays' Fock coefficients 2 x 84 (the creeping
+# count above without its accumulation), J_0..J_3 by their power series to
+# the accuracy used (4 x 8 terms x 2) 64, the combination (6 Bessel
+# weights, 4 complex interpolations, 9 complex real-weighted sums and the
+# 3 x 3 complex accumulation) 218 -> 450; counted against the FP64 rate
+# (the Bessel functions and the geometry are FP64).
+FLOPS_CAUSTIC_PAIR_FREQ = 450
+PEAK_FP64_TFLOPS = 78.6
 # MI355X FP32 vector rate: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
 # = 78.6 TFLOP/s for the plain FP32 instructions this library is built with
 # (packed FP32, which doubles it to the published 157.3, is disabled at
@@ -321,6 +330,52 @@ def field_measure(name, steps, warmup):
     return res
 
 
+def caustic_measure(steps, warmup):
+    """The sphere workload with one encirclement (rear and front pairs) and
+    the uniform caustic sum, against the same call without it; the pair
+    kernels' time and the pairs they summed (counted on the host from the
+    library's own visibility masks: both paths of a pair visible)."""
+    import paper_2310_10578_amd as utd
+    d = single_setup("sphere_plane")
+    kw = dict(precision=0, l_enc=1, out=d["out"], flags=d["flags"])
+    on = lambda: utd.smooth_field(d["scene"], d["sph"], d["cyl"], d["src"], d["rx"], d["freqs"],
+                                  caustic_uniform=True, **kw)
+    off = lambda: utd.smooth_field(d["scene"], d["sph"], d["cyl"], d["src"], d["rx"], d["freqs"], **kw)
+    ms_on = _event_ms(on, steps, warmup)
+    ms_off = _event_ms(off, steps, warmup)
+    # per call: the two pair kernels (k_pair, k_caustic) share one timing class
+    utd.profile_enable(True)
+    utd.profile_read()
+    for _ in range(steps):
+        on()
+    prof = utd.profile_read()
+    utd.profile_enable(False)
+    k_ms = prof["caustic"][0] / steps
+    per_kernel = {k: v[0] / steps for k, v in prof.items() if v[1]}
+    mk, _ = utd.path_masks(d["scene"], d["sph"], d["cyl"], d["src"], d["rx"], l_enc=1, caustic_guard=0.0)
+    mk = mk.cpu().numpy()
+    rx = d["cfg"]["rx"].astype(np.float64)
+    T = np.asarray(d["cfg"]["tx"]["pos"], np.float64)
+    pairs = 0
+    for b, sph in enumerate(np.asarray(d["cfg"]["scene"]["spheres"], np.float64).reshape(-1, 4)):
+        rear = (rx - sph[:3]) @ (T - sph[:3]) < 0
+        m = mk[b].astype(np.int64)
+        both = lambda i, j: ((m >> i) & 1).astype(bool) & ((m >> j) & 1).astype(bool)
+        pairs += int(np.sum(rear & both(0, 1)) + np.sum(rear & both(2, 3)) + np.sum(~rear & both(1, 2)))
+    n_f = d["freqs"].shape[0]
+    flops = pairs * n_f * FLOPS_CAUSTIC_PAIR_FREQ
+    achieved = flops / (k_ms / 1e3) / 1e12 if k_ms > 0 else None
+    res = {"workload": d["cfg"]["name"] + " l_enc=1 caustic_uniform", "ms_per_step": ms_on,
+           "ms_per_step_without": ms_off, "pairs": pairs, "frequencies": n_f,
+           "pair_freqs_per_s": pairs * n_f / (k_ms / 1e3) if k_ms > 0 else None,
+           "kernels_ms_per_step": per_kernel,
+           "roofline": {"bound": "alu", "kernel": "k_pair + k_caustic<float>", "kernel_ms": k_ms,
+                        "flops_per_launch": flops, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                        "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS if achieved else None}}
+    d["scene"].close()
+    return res
+
+
 def adjoint_measure(steps):
     """Forward and backward (loss = sum |E|^2, dL/dE = 2E) on the room with
     64 cylinders, 128 x 128 receivers, 16 frequencies, FP32: the backward from
@@ -559,6 +614,8 @@ def main():
             _progress("occlusion workload timed")
         res["adjoint"] = adjoint_measure(5)
         _progress("adjoint timed")
+        res["caustic"] = caustic_measure(max(10, args.secondary_steps // 4), 3)
+        _progress("caustic workload timed")
     if args.cpu_baseline and crowd is not None:
         _progress("CPU baseline (the oracle) starting")
         res["cpu_baseline"] = cpu_baseline(crowd, args.cpu_frames, args.cpu_rx)

@@ -28,52 +28,67 @@
 //              both visible leave the mask (their bits go to a pair byte per
 //              (sphere, receiver)); a path left alone within the axis guard
 //              is dropped and the receiver flagged, as without the option
-//   k_caustic  per receiver: the pairs' field added into E, after k_field
+//   k_caustic  per (receiver, 4 frequencies): the pairs' field added into E,
+//              after k_field
 // The path kernels run with a zero guard under this option (no path is
 // dropped before it is paired).
 namespace utd {
 
-// J_0 .. J_3 at x >= 0, FP64.  Up to x = 25 the trapezoidal rule on Bessel's
-// integral J_n(x) = (1/2 pi) int_0^{2 pi} cos(n t - x sin t) dt with 64 nodes
-// (its error is the aliased orders n + 64 l, J_61(25) ~ 3e-16 and below);
-// the integrand is even about t = pi, so 33 distinct nodes.  Beyond: Hankel's
-// asymptotic expansion, J_n = sqrt(2/(pi x)) (P cos chi - Q sin chi) with
-// chi = x - (2n + 1) pi/4 and P, Q the even and odd terms of the series in
-// 1/(8x), 16 terms (below 1e-15 relative at x = 25).
-__device__ __forceinline__ void bessel_j03(double x, double J[4]) {
-    if (x <= 25.0) {
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+// sin(pi k / 32), k = 0 .. 16: the trapezoidal nodes below (cos(pi k / 32)
+// is entry 16 - k; the nodes beyond pi/2 follow by symmetry)
+__device__ const double kNodeSin[17] = {
+    0.0, 0.098017140329560604, 0.19509032201612825, 0.29028467725446233,
+    0.38268343236508978, 0.47139673682599764, 0.55557023301960218, 0.63439328416364549,
+    0.70710678118654752, 0.77301045336273699, 0.83146961230254524, 0.88192126434835494,
+    0.92387953251128674, 0.95694033573220894, 0.98078528040323043, 0.99518472667219682, 1.0};
+
+__device__ __forceinline__ void gsincos_r(double x, double* s, double* c) { sincos(x, s, c); }
+__device__ __forceinline__ void gsincos_r(float x, float* s, float* c) { sincosf(x, s, c); }
+
+// J_0 .. J_3 at x >= 0 in precision R.  Up to x = 25 the trapezoidal rule on
+// Bessel's integral J_n(x) = (1/2 pi) int_0^{2 pi} cos(n t - x sin t) dt with
+// 64 nodes (its error is the aliased orders n + 64 l, J_61(25) ~ 3e-16 and
+// below); the integrand is even about t = pi, so 33 distinct nodes.
+// Beyond: Hankel's asymptotic expansion, J_n = sqrt(2/(pi x)) (P cos chi -
+// Q sin chi) with chi = x - (2n + 1) pi/4 and P, Q the even and odd terms
+// of the series in 1/(8x), 16 terms (below 1e-15 relative at x = 25).
+template <typename R>
+__device__ __forceinline__ void bessel_j03(R x, R J[4]) {
+    if (x <= (R)25) {
+        R acc[4] = {(R)0, (R)0, (R)0, (R)0};
 #pragma unroll 1
         for (int k = 0; k <= 32; ++k) {
-            double st, ct, sx, cx;
-            sincospi((double)k * (1.0 / 32.0), &st, &ct);
-            sincos(x * st, &sx, &cx);
-            const double w = (k == 0 || k == 32) ? 1.0 : 2.0;
-            double cn = 1.0, sn = 0.0;   // cos(n t), sin(n t)
+            const bool lo = k <= 16;
+            const R st = (R)kNodeSin[lo ? k : 32 - k];
+            const R ct = lo ? (R)kNodeSin[16 - k] : -(R)kNodeSin[k - 16];
+            R sx, cx;
+            gsincos_r(x * st, &sx, &cx);
+            const R w = (k == 0 || k == 32) ? (R)1 : (R)2;
+            R cn = (R)1, sn = (R)0;   // cos(n t), sin(n t)
 #pragma unroll
             for (int n = 0; n < 4; ++n) {
                 acc[n] += w * (cn * cx + sn * sx);
-                const double c2 = cn * ct - sn * st;
+                const R c2 = cn * ct - sn * st;
                 sn = sn * ct + cn * st;
                 cn = c2;
             }
         }
 #pragma unroll
-        for (int n = 0; n < 4; ++n) J[n] = acc[n] * (1.0 / 64.0);
+        for (int n = 0; n < 4; ++n) J[n] = acc[n] * (R)(1.0 / 64.0);
         return;
     }
-    double s, c;
-    sincos(x, &s, &c);
+    R s, c;
+    gsincos_r(x, &s, &c);
     // cos and sin of chi_0 = x - pi/4; each next order turns chi by -pi/2
-    double cc = (c + s) * 0.70710678118654752, sc = (s - c) * 0.70710678118654752;
-    const double amp = sqrt(2.0 / (kPi * x)), i8x = 1.0 / (8.0 * x);
+    R cc = (c + s) * (R)0.70710678118654752, sc = (s - c) * (R)0.70710678118654752;
+    const R amp = sqrt((R)2 / ((R)kPi * x)), i8x = (R)1 / ((R)8 * x);
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
-        const double mu = 4.0 * n * n;
-        double t = 1.0, P = 1.0, Q = 0.0;
+        const R mu = (R)(4 * n * n);
+        R t = (R)1, P = (R)1, Q = (R)0;
 #pragma unroll 1
         for (int k = 1; k <= 16; ++k) {
-            t *= (mu - (double)((2 * k - 1) * (2 * k - 1))) * i8x / (double)k;
+            t *= (mu - (R)((2 * k - 1) * (2 * k - 1))) * i8x / (R)k;
             switch (k & 3) {
                 case 1: Q += t; break;
                 case 2: P -= t; break;
@@ -82,7 +97,7 @@ __device__ __forceinline__ void bessel_j03(double x, double J[4]) {
             }
         }
         J[n] = amp * (P * cc - Q * sc);
-        const double c2 = sc;
+        const R c2 = sc;
         sc = -cc;
         cc = c2;
     }
@@ -138,7 +153,12 @@ template <typename R> __device__ __forceinline__ cplx<R> cx_comb(R s, cplx<R> a,
     return {s * a.re - t * b.im, s * a.im + t * b.re};
 }
 
-// grid ceil(n_rx / 256); adds into E [n_f][3][n_rx] complex.
+// Frequencies per thread of k_caustic (grid rows).
+constexpr int kCausticFreqs = 4;
+
+// grid (ceil(n_rx / 256), rows): receiver i at the frequencies of its row,
+// kCausticFreqs consecutive ones every rows * kCausticFreqs; adds into
+// E [n_f][3][n_rx] complex.
 template <typename R>
 __global__ void __launch_bounds__(256) k_caustic(LaunchParams L, const float* __restrict__ rx,
                                                  const BodyPrep* __restrict__ prep, const FreqConst* __restrict__ fcs,
@@ -195,18 +215,21 @@ __global__ void __launch_bounds__(256) k_caustic(LaunchParams L, const float* __
             const R e1x = (R)e1.x, e1y = (R)e1.y, e1z = (R)e1.z;
             const R e2x = (R)e2.x, e2y = (R)e2.y, e2z = (R)e2.z;
 #pragma unroll 1
-            for (int j = 0; j < L.n_f; ++j) {
+            for (int jb = (int)blockIdx.y * kCausticFreqs; jb < L.n_f; jb += (int)gridDim.y * kCausticFreqs)
+#pragma unroll 1
+            for (int j = jb; j < jb + kCausticFreqs && j < L.n_f; ++j) {
                 if (!fcs[j].ok) continue;      // an invalid frequency keeps its zero field
                 const FreqC<R> fc(fcs[j]);
                 cplx<R> csn, chn, csf, chf;
                 path_coefs<R, kCreep>(pn, tb, fc, &csn, &chn);
                 path_coefs<R, kCreep>(pf, tb, fc, &csf, &chf);
                 const double k = fcs[j].kd;
-                double J[4];
-                bessel_j03(k * a * eps, J);
-                const R a0 = (R)(2.0 * kPi * J[0]), a1 = (R)(2.0 * kPi * J[1]);
-                const R am = (R)(kPi * (J[0] - J[2])), ap = (R)(kPi * (J[0] + J[2]));
-                const R b3 = (R)(0.5 * kPi * (3.0 * J[1] - J[3])), b1 = (R)(0.5 * kPi * (J[1] + J[3]));
+                R J[4];
+                bessel_j03<R>((R)(k * a * eps), J);
+                const R pi = (R)kPi;
+                const R a0 = (R)2 * pi * J[0], a1 = (R)2 * pi * J[1];
+                const R am = pi * (J[0] - J[2]), ap = pi * (J[0] + J[2]);
+                const R b3 = (R)0.5 * pi * ((R)3 * J[1] - J[3]), b1 = (R)0.5 * pi * (J[1] + J[3]);
                 // W e^{j pi/4} times each coefficient
                 const R w = (R)(W0 * sqrt(k) * 0.70710678118654752);
                 const cplx<R> wq{w, w};
@@ -248,7 +271,8 @@ hipError_t launch_pairs(const LaunchParams& L, double guard, const float* rx, co
 hipError_t launch_caustic(const LaunchParams& L, int precision, const float* rx, const BodyPrep* prep,
                           const FreqConst* fcs, const uint8_t* pm, void* E, hipStream_t s) {
     if (L.n_sph == 0 || L.n_rx == 0 || L.n_f == 0) return hipSuccess;
-    const dim3 grid((unsigned)((L.n_rx + 255) / 256));
+    const int rows = (L.n_f + kCausticFreqs - 1) / kCausticFreqs;
+    const dim3 grid((unsigned)((L.n_rx + 255) / 256), (unsigned)(rows < 65535 ? rows : 65535));
     if (precision == 0)
         hipLaunchKernelGGL((k_caustic<float>), grid, dim3(256), 0, s, L, rx, prep, fcs, pm, (float*)E);
     else
