@@ -327,7 +327,10 @@ utd_status utd_smooth_field_noalloc(const utd_scene *scene, const utd_bodies *bo
  * counts[2*ell + s] creeping paths on side s (0: towards the receiver,
  * 1: far side) with ell encirclements, counts[6] reflections, counts[7]
  * caustic drops -- then counts[8] receivers with a visible direct path and
- * counts[9] receivers inside a body.  Waits for the stream.
+ * counts[9] receivers inside a body.  Waits for the stream.  With
+ * opt->caustic_uniform the census is taken before the pairing: both paths
+ * of a pair count, and no path is dropped at the caustic (the guard applies
+ * after pairing, to paths left alone).
  * Errors as for utd_smooth_field; UTD_E_ARG if counts is NULL. */
 utd_status utd_path_census(const utd_scene *scene, const utd_bodies *bodies, const utd_source *tx,
                            const float *rx, int64_t n_rx, const utd_options *opt, int64_t *counts,
@@ -346,6 +349,8 @@ utd_status utd_path_census(const utd_scene *scene, const utd_bodies *bodies, con
  *   rx_flags  device uint8 [n_rx] or NULL (UTD_FLAG_*, UTD_FLAG_LOS = U_LOS).
  * These are the decisions utd_smooth_field takes for the same inputs; tests
  * feed them to an independent evaluation to compare fields path by path.
+ * With opt->caustic_uniform the masks are those before the pairing (as for
+ * utd_path_census).
  * Asynchronous on `stream`.  Errors as for utd_smooth_field; UTD_E_ARG if
  * mask_out is NULL with bodies and receivers. */
 utd_status utd_path_masks(const utd_scene *scene, const utd_bodies *bodies, const utd_source *tx,
