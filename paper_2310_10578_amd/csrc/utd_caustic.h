@@ -28,7 +28,7 @@
 //              both visible leave the mask (their bits go to a pair byte per
 //              (sphere, receiver)); a path left alone within the axis guard
 //              is dropped and the receiver flagged, as without the option
-//   k_caustic  per (receiver, 4 frequencies): the pairs' field added into E,
+//   k_caustic  per (receiver, 8 frequencies): the pairs' field added into E,
 //              after k_field
 // The path kernels run with a zero guard under this option (no path is
 // dropped before it is paired).
@@ -45,19 +45,23 @@ __device__ const double kNodeSin[17] = {
 __device__ __forceinline__ void gsincos_r(double x, double* s, double* c) { sincos(x, s, c); }
 __device__ __forceinline__ void gsincos_r(float x, float* s, float* c) { sincosf(x, s, c); }
 
-// J_0 .. J_3 at x >= 0 in precision R.  Up to x = 25 the trapezoidal rule on
-// Bessel's integral J_n(x) = (1/2 pi) int_0^{2 pi} cos(n t - x sin t) dt with
-// 64 nodes (its error is the aliased orders n + 64 l, J_61(25) ~ 3e-16 and
-// below); the integrand is even about t = pi, so 33 distinct nodes.
-// Beyond: Hankel's asymptotic expansion, J_n = sqrt(2/(pi x)) (P cos chi -
-// Q sin chi) with chi = x - (2n + 1) pi/4 and P, Q the even and odd terms
-// of the series in 1/(8x), 16 terms (below 1e-15 relative at x = 25).
+// J_0 .. J_3 at x >= 0 in precision R.  Up to x = x_s the trapezoidal rule
+// on Bessel's integral J_n(x) = (1/2 pi) int_0^{2 pi} cos(n t - x sin t) dt
+// with M nodes, whose error is the aliased orders M - n and beyond; the
+// integrand is even about t = pi, so M/2 + 1 distinct nodes.  FP64: M = 64
+// up to x_s = 25 (J_61(25) ~ 3e-16); FP32: M = 32 up to x_s = 12
+// (J_29(12) ~ 5e-8).  Beyond: Hankel's asymptotic expansion,
+// J_n = sqrt(2/(pi x)) (P cos chi - Q sin chi) with chi = x - (2n + 1) pi/4
+// and P, Q the even and odd terms of the series in 1/(8x), 16 terms (below
+// 1e-15 relative at x = 25, 1e-9 at x = 12).
 template <typename R>
 __device__ __forceinline__ void bessel_j03(R x, R J[4]) {
-    if (x <= (R)25) {
+    constexpr bool kF64 = sizeof(R) == 8;
+    constexpr int kStep = kF64 ? 1 : 2;          // every node of the 64, or every other one
+    if (x <= (kF64 ? (R)25 : (R)12)) {
         R acc[4] = {(R)0, (R)0, (R)0, (R)0};
 #pragma unroll 1
-        for (int k = 0; k <= 32; ++k) {
+        for (int k = 0; k <= 32; k += kStep) {
             const bool lo = k <= 16;
             const R st = (R)kNodeSin[lo ? k : 32 - k];
             const R ct = lo ? (R)kNodeSin[16 - k] : -(R)kNodeSin[k - 16];
@@ -74,7 +78,7 @@ __device__ __forceinline__ void bessel_j03(R x, R J[4]) {
             }
         }
 #pragma unroll
-        for (int n = 0; n < 4; ++n) J[n] = acc[n] * (R)(1.0 / 64.0);
+        for (int n = 0; n < 4; ++n) J[n] = acc[n] * (R)(kStep / 64.0);
         return;
     }
     R s, c;
@@ -154,7 +158,7 @@ template <typename R> __device__ __forceinline__ cplx<R> cx_comb(R s, cplx<R> a,
 }
 
 // Frequencies per thread of k_caustic (grid rows).
-constexpr int kCausticFreqs = 4;
+constexpr int kCausticFreqs = 8;
 
 // grid (ceil(n_rx / 256), rows): receiver i at the frequencies of its row,
 // kCausticFreqs consecutive ones every rows * kCausticFreqs; adds into
