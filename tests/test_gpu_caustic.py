@@ -153,3 +153,26 @@ def test_uniform_pairs_noalloc_matches():
         torch.cuda.synchronize()
         assert np.array_equal(E.cpu().numpy().astype(np.complex128), Ea)
         assert np.array_equal(f.cpu().numpy(), fa)
+
+
+def test_uniform_pairs_sphere_plane_full_size_sampled():
+    """Config 2 at full size with one encirclement and the uniform sum, in
+    the launch configuration the bench times (65536 receivers, 64
+    frequencies, FP32); 600 sampled receivers recomputed by the oracle (a
+    sphere alone: both sides' decisions are exact)."""
+    cfg = W.sphere_plane()
+    opts = dict(l_enc=1, caustic_uniform=True)
+    Eg, fg = run_library(cfg, 0, **opts)
+    rng = np.random.default_rng(7)
+    idx = np.sort(rng.choice(cfg["rx"].shape[0], 600, replace=False))
+    Eo, info, A = run_oracle(cfg, rx=cfg["rx"][idx], opts=opts, absum=True)
+    Eg = Eg[:, :, idx]
+    nw = normwise(Eg, Eo)
+    comp = np.linalg.norm(Eg - Eo, axis=1) / np.maximum(A, 1e-300)
+    n_pairs = sum(len(p[4]) for p in info["pairs"])
+    print("caustic sphere_plane full size sampled: %d pairs, normwise max %.2e, per-receiver max %.2e"
+          % (n_pairs, nw.max(), comp.max()), flush=True)
+    np.testing.assert_array_equal(fg[idx] & 7, info["flags"] & 7)
+    assert n_pairs >= 300
+    assert np.all(nw <= TOL[0]), nw
+    assert comp.max() <= TOL[0], comp.max()
