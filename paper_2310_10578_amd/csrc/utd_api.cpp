@@ -417,7 +417,10 @@ utd_status utd_smooth_field(const utd_scene* scene, const utd_bodies* bodies, co
     }
     if (e == hipSuccess && walls) {
         ProfScope ps(UTD_K_WALLS, s);
-        e = utd::launch_walls(L, opt->precision, scene->mat, rx, bodies->sph, bodies->cyl, w.prep,
+        // wall-fed paths are not paired: they keep the caller's guard
+        utd::LaunchParams Lw = L;
+        Lw.caustic_guard = opt->caustic_guard;
+        e = utd::launch_walls(Lw, opt->precision, scene->mat, rx, bodies->sph, bodies->cyl, w.prep,
                               (utd::BodyPrep*)w.extra, scene->d_planes, n_planes, nodes, tris, w.fc, freqs, flags,
                               E_out, nullptr, s);
     }
@@ -474,7 +477,10 @@ utd_status utd_smooth_field_noalloc(const utd_scene* scene, const utd_bodies* bo
     }
     if (e == hipSuccess && walls) {
         ProfScope ps(UTD_K_WALLS, s);
-        e = utd::launch_walls(L, opt->precision, scene->mat, rx, bodies->sph, bodies->cyl, w.prep,
+        // wall-fed paths are not paired: they keep the caller's guard
+        utd::LaunchParams Lw = L;
+        Lw.caustic_guard = opt->caustic_guard;
+        e = utd::launch_walls(Lw, opt->precision, scene->mat, rx, bodies->sph, bodies->cyl, w.prep,
                               (utd::BodyPrep*)w.extra, scene->d_planes, n_planes, nodes, tris, w.fc, freqs, flags,
                               E_out, nullptr, s);
     }
@@ -557,8 +563,10 @@ utd_status utd_wall_masks(const utd_scene* scene, const utd_bodies* bodies, cons
     e = utd::launch_paths(L, opt->precision, rx, bodies->sph, bodies->cyl, nullptr, w.prep, w.fc, scene->d_nodes,
                           scene->d_tris, w.mask, w.rec, w.flags, w.ent, w.ent_th, w.vis, w.counters + 12, w.cap, s,
                           w.grid);
+    utd::LaunchParams Lw = L;   // wall-fed paths keep the caller's guard (as in utd_smooth_field)
+    Lw.caustic_guard = opt->caustic_guard;
     if (e == hipSuccess)
-        e = utd::launch_walls(L, opt->precision, scene->mat, rx, bodies->sph, bodies->cyl, w.prep,
+        e = utd::launch_walls(Lw, opt->precision, scene->mat, rx, bodies->sph, bodies->cyl, w.prep,
                               (utd::BodyPrep*)w.extra, scene->d_planes, n_planes, scene->d_nodes, scene->d_tris, w.fc,
                               nullptr, w.flags, nullptr, mask_out, s);
     if (e != hipSuccess) return hip_fail(e, "wall masks");

@@ -176,3 +176,39 @@ def test_uniform_pairs_sphere_plane_full_size_sampled():
     assert n_pairs >= 300
     assert np.all(nw <= TOL[0]), nw
     assert comp.max() <= TOL[0], comp.max()
+
+
+def test_wall_fed_paths_keep_the_guard():
+    """With the option and wall reflections, a sphere's own pairs are summed
+    but the paths fed by the wall's image source are not paired: on the image
+    source's axis they are dropped within the guard and flagged, as the
+    oracle does (a PEC floor under a sphere).  The wall paths' visibility is
+    not frozen here, so the option's effect is compared: the change the
+    uniform sum makes to each side's field, at 1e-4 of the oracle's."""
+    from oracle import walls as OW
+    big = 20.0
+    tri = np.array([[[-big, -big, 0.0], [big, -big, 0.0], [big, big, 0.0]],
+                    [[-big, -big, 0.0], [big, big, 0.0], [-big, big, 0.0]]], np.float32)
+    C = np.array([0.2, -0.1, 1.5])
+    T = np.float32([3.0, 0.5, 2.0])
+    img = np.array([T[0], T[1], -T[2]], np.float64)
+    ax = (C - img) / np.linalg.norm(C - img)
+    rng = np.random.default_rng(2)
+    pts = []
+    for d in (1.3, 2.1):
+        for off in (0.0, 1e-3, 1e-2, 0.1):
+            v = np.cross(ax, rng.normal(size=3))
+            pts.append(C + d * ax + off * v / np.linalg.norm(v))
+    cfg = dict(scene=dict(spheres=np.array([list(C) + [0.4]], np.float32), cylinders=np.zeros((0, 5), np.float32),
+                          tri=tri),
+               tx=dict(pos=T, dipole=np.float32([0.2, 0.4, 0.9]), amplitude=1.0),
+               rx=np.concatenate([np.array(pts), _receivers()[24:]]).astype(np.float32), freqs=FREQS[::4])
+    Eg, fg = run_library(cfg, 0, walls=OW.PEC, caustic_uniform=True)
+    Eo, info = run_oracle(cfg, opts=dict(caustic_uniform=True, walls=OW.PEC))
+    np.testing.assert_array_equal(fg & 7, info["flags"] & 7)
+    assert np.all(fg[[0, 4]] & 2)           # on the image axis: the wall-fed paths dropped and flagged
+    assert np.all(np.isfinite(Eg)) and len(info["pairs"]) > 0
+    Eg0, _ = run_library(cfg, 0, walls=OW.PEC)
+    Eo0, _ = run_oracle(cfg, opts=dict(walls=OW.PEC))
+    d = np.linalg.norm((Eg - Eg0) - (Eo - Eo0)) / np.linalg.norm(Eo - Eo0)
+    assert d <= TOL[0], d
