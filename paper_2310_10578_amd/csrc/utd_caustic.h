@@ -28,7 +28,7 @@
 //              both visible leave the mask (their bits go to a pair byte per
 //              (sphere, receiver)); a path left alone within the axis guard
 //              is dropped and the receiver flagged, as without the option
-//   k_caustic  per (receiver, 8 frequencies): the pairs' field added into E,
+//   k_caustic  per (receiver, 4 frequencies): the pairs' field added into E,
 //              after k_field
 // The path kernels run with a zero guard under this option (no path is
 // dropped before it is paired).
@@ -157,15 +157,20 @@ template <typename R> __device__ __forceinline__ cplx<R> cx_comb(R s, cplx<R> a,
     return {s * a.re - t * b.im, s * a.im + t * b.re};
 }
 
-// Frequencies per thread of k_caustic (grid rows).
-constexpr int kCausticFreqs = 8;
+// Frequencies per thread of k_caustic (grid rows).  With the four-wave cap
+// below, per call on the sphere workload with one encirclement (FP32 /
+// FP64): 2 per row 0.396 / 1.42 ms, 4 0.402 / 1.38, 8 0.455 / 1.50, 16
+// 0.547 / 1.61 (fewer, longer rows recompute the pair geometry less often
+// but fill the chip less).
+constexpr int kCausticFreqs = 4;
 
 // grid (ceil(n_rx / 256), rows): receiver i at the frequencies of its row,
 // kCausticFreqs consecutive ones every rows * kCausticFreqs; adds into
 // E [n_f][3][n_rx] complex.
-// At most 128 VGPRs (four waves per SIMD): 0.459 against 0.505 ms (FP32)
-// and 1.49 against 1.67 ms (FP64) with the compiler's own choice of 155 and
-// 256; five waves helped FP32 no further and cost FP64 40 %.
+// At most 128 VGPRs (four waves per SIMD; eight frequencies per row): 0.459
+// against 0.505 ms (FP32) and 1.49 against 1.67 ms (FP64) with the
+// compiler's own choice of 155 and 256; five waves helped FP32 no further
+// and cost FP64 40 %.
 template <typename R>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_caustic(LaunchParams L, const float* __restrict__ rx,
                                                  const BodyPrep* __restrict__ prep, const FreqConst* __restrict__ fcs,
