@@ -103,7 +103,10 @@ def sphere_creeping(T, C, a, R, side, ell):
     b = np.cross(t1, n1)
     Q1 = C + a * n1
     Q2 = C + a * n2
-    rho_perp = a * s2 + sD * c2
+    # signed distance of R from the source axis: a sin th2 + s^d cos th2,
+    # whose magnitude is d_R sin theta_R; the sum cancels near the axis
+    # (an absolute error of ~1e-15 m), so only its sign is taken from it
+    rho_perp = np.sign(a * s2 + sD * c2) * (dR * np.sin(thR))
     Nc = np.floor(th2 / np.pi) + (np.sign(rho_perp) != np.sign(s2))
     amp = np.sqrt(a * s1 / (sD * np.abs(rho_perp)))
     S = amp * np.exp(0.5j * np.pi * Nc)

@@ -34,9 +34,9 @@ def _receivers(seed=0):
     rounding of the coordinates, and at offsets from 1e-6 m (rear) or 1e-4 m
     (front) to 0.3 m), and a ring through both hemispheres; 323 in all (a
     ragged tail of the 256-lane blocks).  Closer to the lit front axis the
-    lone creeping ray of l_enc = 0 is at its own caustic and the reflection
-    within 1e-6 of normal incidence, where the two sides' ray fields differ
-    by up to 3e-3 with or without the uniform sum."""
+    lone creeping ray of l_enc = 0 sits at its own caustic, 1e3 times its
+    usual size; at 1e-6 m the two sides' amplitudes of that ray differ by
+    3e-9, with or without the uniform sum, above the FP64 bound."""
     rng = np.random.default_rng(seed)
     T = np.array(TX["pos"])
     ax = (C_SPH - T) / np.linalg.norm(C_SPH - T)
