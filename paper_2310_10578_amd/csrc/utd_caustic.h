@@ -172,9 +172,9 @@ constexpr int kCausticFreqs = 4;
 // compiler's own choice of 155 and 256; five waves helped FP32 no further
 // and cost FP64 40 %.
 template <typename R>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_caustic(LaunchParams L, const float* __restrict__ rx,
-                                                 const BodyPrep* __restrict__ prep, const FreqConst* __restrict__ fcs,
-                                                 const uint8_t* __restrict__ pm, R* __restrict__ E_out) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_caustic(LaunchParams L, const float* __restrict__ rx, const BodyPrep* __restrict__ prep,
+          const FreqConst* __restrict__ fcs, const uint8_t* __restrict__ pm, R* __restrict__ E_out) {
     __shared__ __attribute__((aligned(16))) R s_reg[TableStage<R>::NREG];
     __shared__ __attribute__((aligned(16))) R s_tf[TableStage<R>::NTF];
     const Tabs<R> tb = TableStage<R>::template stage<256>(s_reg, s_tf);
@@ -226,6 +226,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
             const R ux = (R)u.x, uy = (R)u.y, uz = (R)u.z;
             const R e1x = (R)e1.x, e1y = (R)e1.y, e1z = (R)e1.z;
             const R e2x = (R)e2.x, e2y = (R)e2.y, e2z = (R)e2.z;
+            // this row's frequencies: kCausticFreqs consecutive ones, every
+            // gridDim.y * kCausticFreqs
 #pragma unroll 1
             for (int jb = (int)blockIdx.y * kCausticFreqs; jb < L.n_f; jb += (int)gridDim.y * kCausticFreqs)
 #pragma unroll 1
