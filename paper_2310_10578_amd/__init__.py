@@ -415,7 +415,8 @@ def batched_config(tile_rx, blocks_per_cu):
 
 
 def smooth_field_batched(scene, body_off, cylinders, rx_off, rx, source, freqs, precision=0, l_enc=0,
-                         bodies_occlude=True, lit_branch=True, caustic_guard=1e-6, out=None, flags=None, stream=None):
+                         bodies_occlude=True, lit_branch=True, caustic_guard=1e-6, out=None, flags=None, stream=None,
+                         caustic_uniform=False):
     """Fields of many frames in one call.  body_off, rx_off: int64 GPU tensors
     [n_frames + 1]; cylinders [n_cyl, 5], rx [n_rx, 3]: float32 GPU tensors.
     Returns (E, flags): E is a flat complex tensor of 3 * n_f * n_rx elements,
@@ -436,7 +437,8 @@ def smooth_field_batched(scene, body_off, cylinders, rx_off, rx, source, freqs, 
         out = torch.empty((3 * nf * n,), dtype=cdt, device=rx.device)
     if flags is None:
         flags = torch.empty((n,), dtype=torch.uint8, device=rx.device)
-    opt = make_options(precision, l_enc, bodies_occlude, lit_branch, caustic_guard)
+    opt = make_options(precision, l_enc, bodies_occlude, lit_branch, caustic_guard,
+                       caustic_uniform=caustic_uniform)
     _check(lib.utd_smooth_field_batched(
         scene.handle if scene is not None else None, max(n_frames, 0), body_off.data_ptr(),
         cylinders.data_ptr() if nc else None, nc, rx_off.data_ptr(), rx.data_ptr() if n else None, n,

@@ -212,3 +212,30 @@ def test_wall_fed_paths_keep_the_guard():
     Eo0, _ = run_oracle(cfg, opts=dict(walls=OW.PEC))
     d = np.linalg.norm((Eg - Eg0) - (Eo - Eo0)) / np.linalg.norm(Eo - Eo0)
     assert d <= TOL[0], d
+
+
+def test_batched_frames_ignore_the_option():
+    """Batched frames hold cylinders only: the option is accepted and leaves
+    every output bit unchanged (two frames, 3 and 5 cylinders, l_enc 1)."""
+    import torch
+
+    import paper_2310_10578_amd as utd
+    rng = np.random.default_rng(11)
+    cyl = np.concatenate([np.stack([rng.uniform(1, 5, n), rng.uniform(1, 4, n), np.zeros(n), np.full(n, 1.8),
+                                    np.full(n, 0.2)], 1) for n in (3, 5)]).astype(np.float32)
+    rx = np.stack([rng.uniform(0, 6, 300), rng.uniform(0, 5, 300), np.full(300, 1.2)], 1).astype(np.float32)
+    def dev(a, dt=None):
+        if dt is None:
+            return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+        return torch.tensor(a, dtype=dt, device="cuda")
+
+    bo, ro = dev([0, 3, 8], torch.int64), dev([0, 120, 300], torch.int64)
+    src = utd.make_source((3.0, 2.5, 2.5), (0.3, 0.4, 0.8), 1.0)
+    freqs = dev(FREQS[:3], torch.float64)
+    out = []
+    for uni in (False, True):
+        E, fl = utd.smooth_field_batched(None, bo, dev(cyl), ro, dev(rx), src, freqs, l_enc=1, caustic_uniform=uni)
+        torch.cuda.synchronize()
+        out.append((E.cpu().numpy().copy(), fl.cpu().numpy().copy()))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    assert np.count_nonzero(out[0][0]) > 0
